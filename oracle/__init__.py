@@ -1,0 +1,218 @@
+"""FP64 CPU oracle for the Monte Carlo path engine -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package. The product library never loads it and
+shares no code with it.
+
+The arithmetic lives in ``mc_oracle.c`` (plain double precision, one path and
+one step at a time). This module only marshals numpy arrays through ctypes
+and adds the estimator formulas of Eq. (3) and the bias-variance split of
+Sec. V-B, plus the Adam update used to train the learned control variate.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+_u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
+
+GBM_CHANNELS = ("euro", "asian", "geo", "uo", "euro_delta", "euro_vega",
+                "asian_delta", "asian_vega", "disc_ST", "uo_bridge")
+HESTON_CHANNELS = ("euro", "asian", "euro_delta", "euro_dv0", "asian_delta",
+                   "asian_dv0", "disc_ST")
+BASKET_CHANNELS = ("basket", "geo_basket", "delta0")
+MLP_NPARAM = 4545
+
+
+def lib():
+    """Loads liboracle.so (built by oracle/build.py)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"{_LIB_PATH} is missing: run oracle/build.py")
+        L = C.CDLL(_LIB_PATH)
+        L.orc_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+        L.orc_uniform.argtypes = [C.c_uint32]
+        L.orc_uniform.restype = C.c_double
+        L.orc_normal.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64]
+        L.orc_normal.restype = C.c_double
+        L.orc_normals.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64,
+                                  C.c_uint64, _dp]
+        L.orc_words_many.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, _u64p,
+                                     _u64p, _u32p]
+        L.orc_gbm.argtypes = [_dp, C.c_int, C.c_int, C.c_int, C.c_uint64,
+                              C.c_uint32, C.c_uint64, C.c_uint64, _dp]
+        L.orc_heston.argtypes = [_dp, C.c_int, C.c_uint64, C.c_uint32, C.c_uint64,
+                                 C.c_uint64, _dp]
+        L.orc_cholesky.argtypes = [C.c_int, _dp, _dp]
+        L.orc_cholesky.restype = C.c_int
+        L.orc_basket.argtypes = [C.c_int, _dp, _dp, _dp, _dp, C.c_double,
+                                 C.c_double, C.c_double, C.c_int, C.c_uint64,
+                                 C.c_uint32, C.c_uint64, C.c_uint64, _dp]
+        L.orc_heston_cv.argtypes = [_dp, C.c_int, C.c_int, _dp, C.c_uint64,
+                                    C.c_uint32, C.c_uint64, C.c_uint64, _dp]
+        L.orc_mlp_eval.argtypes = [_dp, C.c_uint64, _dp, _dp]
+        L.orc_cv_loss_grad.argtypes = [_dp, C.c_int, C.c_int, _dp, C.c_uint64,
+                                       C.c_uint32, C.c_uint64, C.c_uint64, C.c_void_p]
+        L.orc_cv_loss_grad.restype = C.c_double
+        for f in ("orc_gbm_channels", "orc_heston_channels", "orc_basket_channels",
+                  "orc_mlp_nparam"):
+            getattr(L, f).restype = C.c_int
+        assert L.orc_gbm_channels() == len(GBM_CHANNELS)
+        assert L.orc_heston_channels() == len(HESTON_CHANNELS)
+        assert L.orc_basket_channels() == len(BASKET_CHANNELS)
+        assert L.orc_mlp_nparam() == MLP_NPARAM
+        _lib = L
+    return _lib
+
+
+# --------------------------------------------------------------------------
+# Random numbers (Sec. IV-A): Philox4x32-10 block function, counter layout,
+# open-interval uniform and Box-Muller.
+# --------------------------------------------------------------------------
+def philox(ctr, key):
+    out = np.zeros(4, np.uint32)
+    lib().orc_philox4x32_10(np.ascontiguousarray(ctr, np.uint32),
+                            np.ascontiguousarray(key, np.uint32), out)
+    return out
+
+
+def words(seed: int, tag: int, paths, blocks) -> np.ndarray:
+    paths = np.ascontiguousarray(paths, np.uint64)
+    blocks = np.ascontiguousarray(blocks, np.uint64)
+    out = np.zeros((paths.size, 4), np.uint32)
+    lib().orc_words_many(seed, tag, paths.size, paths, blocks, out)
+    return out
+
+
+def uniform(w: int) -> float:
+    return lib().orc_uniform(int(w))
+
+
+def normal(seed: int, tag: int, path: int, k: int) -> float:
+    return lib().orc_normal(seed, tag, path, k)
+
+
+def normals(seed: int, tag: int, path: int, k0: int, count: int) -> np.ndarray:
+    out = np.zeros(count, np.float64)
+    lib().orc_normals(seed, tag, path, k0, count, out)
+    return out
+
+
+# --------------------------------------------------------------------------
+# Path simulators: per-path channel rows.
+# --------------------------------------------------------------------------
+def gbm(S0, r, sigma, T, K, B, n_steps, n_paths, seed, tag=0, path0=0,
+        scheme=0, coarsen=1) -> np.ndarray:
+    prm = np.array([S0, r, sigma, T, K, B], np.float64)
+    out = np.zeros((n_paths, len(GBM_CHANNELS)), np.float64)
+    lib().orc_gbm(prm, n_steps, scheme, coarsen, seed, tag, path0, n_paths, out)
+    return out
+
+
+def heston(S0, v0, kappa, theta, xi, rho, r, T, K, n_steps, n_paths, seed,
+           tag=0, path0=0) -> np.ndarray:
+    prm = np.array([S0, v0, kappa, theta, xi, rho, r, T, K], np.float64)
+    out = np.zeros((n_paths, len(HESTON_CHANNELS)), np.float64)
+    lib().orc_heston(prm, n_steps, seed, tag, path0, n_paths, out)
+    return out
+
+
+def cholesky(Cm: np.ndarray) -> np.ndarray | None:
+    Cm = np.ascontiguousarray(Cm, np.float64)
+    d = Cm.shape[0]
+    L = np.zeros((d, d), np.float64)
+    st = lib().orc_cholesky(d, Cm, L)
+    return None if st != 0 else L
+
+
+def basket(S0, sigma, L, w, r, T, K, n_steps, n_paths, seed, tag=0,
+           path0=0) -> np.ndarray:
+    S0 = np.ascontiguousarray(S0, np.float64)
+    sigma = np.ascontiguousarray(sigma, np.float64)
+    L = np.ascontiguousarray(L, np.float64)
+    w = np.ascontiguousarray(w, np.float64)
+    d = S0.size
+    out = np.zeros((n_paths, len(BASKET_CHANNELS)), np.float64)
+    lib().orc_basket(d, S0, sigma, L, w, r, T, K, n_steps, seed, tag, path0,
+                     n_paths, out)
+    return out
+
+
+def _heston_prm(h: dict) -> np.ndarray:
+    return np.array([h["S0"], h["v0"], h["kappa"], h["theta"], h["xi"],
+                     h["rho"], h["r"], h["T"], h["K"]], np.float64)
+
+
+def heston_cv(h: dict, n_steps, theta, n_paths, seed, tag=0, path0=0,
+              m_every=1) -> np.ndarray:
+    """Per-path (discounted Asian payoff, hedge P&L H, payoff - H)."""
+    out = np.zeros((n_paths, 3), np.float64)
+    lib().orc_heston_cv(_heston_prm(h), n_steps, m_every,
+                        np.ascontiguousarray(theta, np.float64), seed, tag,
+                        path0, n_paths, out)
+    return out
+
+
+def mlp_eval(theta, phi) -> np.ndarray:
+    phi = np.ascontiguousarray(phi, np.float64).reshape(-1, 4)
+    out = np.zeros(phi.shape[0], np.float64)
+    lib().orc_mlp_eval(np.ascontiguousarray(theta, np.float64), phi.shape[0],
+                       phi, out)
+    return out
+
+
+def cv_loss_grad(h: dict, n_steps, theta, B, seed, tag=2, path0=0,
+                 m_every=1, want_grad=True):
+    grad = np.zeros(MLP_NPARAM, np.float64) if want_grad else None
+    loss = lib().orc_cv_loss_grad(
+        _heston_prm(h), n_steps, m_every,
+        np.ascontiguousarray(theta, np.float64), seed, tag, path0, B,
+        grad.ctypes.data if want_grad else None)
+    return loss, grad
+
+
+# --------------------------------------------------------------------------
+# Estimators (Eq. 3; standard error from the variance term of Sec. V-B,
+# read as Var(f(X))/N).
+# --------------------------------------------------------------------------
+def estimate(y: np.ndarray) -> dict:
+    y = np.asarray(y, np.float64)
+    n = y.size
+    mean = float(np.sum(y) / n)
+    var = float(np.sum((y - mean) ** 2) / (n - 1))
+    return {"price": mean, "variance": var, "std_err": float(np.sqrt(var / n)),
+            "n": n}
+
+
+def cv_beta(a: np.ndarray, g: np.ndarray) -> float:
+    """Least-squares control-variate coefficient cov(a,g)/var(g)."""
+    a = np.asarray(a, np.float64)
+    g = np.asarray(g, np.float64)
+    am, gm = a.mean(), g.mean()
+    return float(np.sum((a - am) * (g - gm)) / np.sum((g - gm) ** 2))
+
+
+def cv_estimate(a: np.ndarray, g: np.ndarray, g_mean: float, beta: float) -> dict:
+    """Estimate of E[a] through Y = a - beta (g - E[g])."""
+    return estimate(np.asarray(a) - beta * (np.asarray(g) - g_mean))
+
+
+# --------------------------------------------------------------------------
+# Adam (Kingma and Ba, 2015), the optimiser of the learned control variate.
+# --------------------------------------------------------------------------
+def adam_step(theta, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One update at step t >= 1; returns new (theta, m, v)."""
+    m = b1 * m + (1.0 - b1) * grad
+    v = b2 * v + (1.0 - b2) * grad * grad
+    mhat = m / (1.0 - b1 ** t)
+    vhat = v / (1.0 - b2 ** t)
+    return theta - lr * mhat / (np.sqrt(vhat) + eps), m, v

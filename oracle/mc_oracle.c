@@ -1,0 +1,613 @@
+/*
+ * mc_oracle.c -- plain, slow, double-precision CPU oracle for the Monte Carlo
+ * path engine ("Tensor Processing Units for Financial Monte Carlo",
+ * Belletti et al., arXiv:1906.02818).
+ *
+ * TEST INFRASTRUCTURE ONLY. It exists to check the HIP library. Only the tests,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it. It
+ * shares no code, header, table or helper with the HIP library; the only thing
+ * the two sides agree on is the published definition of Philox4x32-10 and the
+ * counter layout written down below, which each side implements on its own.
+ *
+ * Style: one path at a time, one time step at a time, every quantity in
+ * double precision, in the order the method states it. No blocking, fusion
+ * or reordering. OpenMP only splits the independent paths across threads;
+ * every path writes its own output row, so the result does not depend on the
+ * thread count.
+ *
+ * Per-path outputs are written row-major: out[p * n_channels + c].
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* 1. Philox4x32-10: the keyed counter-based generator of Salmon, Moraes,    */
+/*    Dror and Shaw (SC'11), which the paper uses on GPUs (Sec. IV-A, Sec.   */
+/*    VI). Ten rounds; each round multiplies counter words 0 and 2 by the    */
+/*    two Philox multipliers as full 32x32->64-bit products and mixes the    */
+/*    halves with words 1, 3 and the key; the key is bumped by the two Weyl  */
+/*    constants between rounds.                                              */
+/* ------------------------------------------------------------------------ */
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2],
+                       uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {            /* key schedule between rounds */
+            k0 += PHILOX_W0;
+            k1 += PHILOX_W1;
+        }
+        uint64_t p0 = (uint64_t)PHILOX_M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)PHILOX_M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 2. Counter layout (the paper leaves it open; this is the reading the     */
+/*    library must follow). Normal number k of path p in stream `tag` comes  */
+/*    from Philox block j = floor(k/4), counter (j, p mod 2^32, p >> 32,    */
+/*    tag), key (seed mod 2^32, seed >> 32), and uses slot k mod 4 of that   */
+/*    block. Per time step i a model with d normals per step uses            */
+/*    k = i*d + a, a = 0..d-1.                                               */
+/* ------------------------------------------------------------------------ */
+void orc_block_words(uint64_t seed, uint32_t tag, uint64_t path, uint64_t j,
+                     uint32_t out[4])
+{
+    uint32_t ctr[4] = {(uint32_t)j, (uint32_t)(path & 0xffffffffu),
+                       (uint32_t)(path >> 32), tag};
+    uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    (void)(j >> 32);            /* blocks beyond 2^32 per path are not used */
+    orc_philox4x32_10(ctr, key, out);
+}
+
+/* 3. Uniform in the open interval (0,1): u = (2*(w >> 9) + 1) / 2^24.
+ *    Odd multiples of 2^-24, so 0 and 1 never occur and u -> 1-u maps the
+ *    set onto itself. */
+double orc_uniform(uint32_t w)
+{
+    return (double)(2u * (w >> 9) + 1u) * 0x1p-24;
+}
+
+/* 4. Box-Muller on one Philox block: slots 0,1 use words (w0 radius, w1
+ *    angle) as r cos, r sin; slots 2,3 use (w2 radius, w3 angle). */
+static void box_muller_block(const uint32_t w[4], double z[4])
+{
+    for (int h = 0; h < 2; ++h) {
+        double u_r = orc_uniform(w[2 * h]);
+        double u_a = orc_uniform(w[2 * h + 1]);
+        double rad = sqrt(-2.0 * log(u_r));
+        double ang = 2.0 * M_PI * u_a;
+        z[2 * h] = rad * cos(ang);
+        z[2 * h + 1] = rad * sin(ang);
+    }
+}
+
+/* Normal number k of path `path`. */
+double orc_normal(uint64_t seed, uint32_t tag, uint64_t path, uint64_t k)
+{
+    uint32_t w[4];
+    double z[4];
+    orc_block_words(seed, tag, path, k / 4, w);
+    box_muller_block(w, z);
+    return z[k % 4];
+}
+
+/* Normals k0 .. k0+count-1 of one path (convenience for the tests). */
+void orc_normals(uint64_t seed, uint32_t tag, uint64_t path, uint64_t k0,
+                 uint64_t count, double *z)
+{
+    for (uint64_t i = 0; i < count; ++i)
+        z[i] = orc_normal(seed, tag, path, k0 + i);
+}
+
+/* Raw words of sampled (path, block) pairs, for the bit-exact tests. */
+void orc_words_many(uint64_t seed, uint32_t tag, uint64_t n,
+                    const uint64_t *paths, const uint64_t *blocks,
+                    uint32_t *out /* n x 4 */)
+{
+    for (uint64_t i = 0; i < n; ++i)
+        orc_block_words(seed, tag, paths[i], blocks[i], out + 4 * i);
+}
+
+/* The normals of one path are drawn block by block in index order. This
+ * small cursor keeps the current block so that a path costs one Philox call
+ * per four normals, exactly like reading orc_normal(k) for k = 0,1,2,... */
+typedef struct {
+    uint64_t seed, path;
+    uint32_t tag;
+    uint64_t next_k;
+    uint64_t block;
+    double z[4];
+} normal_stream;
+
+static void ns_init(normal_stream *s, uint64_t seed, uint32_t tag, uint64_t path)
+{
+    s->seed = seed; s->tag = tag; s->path = path; s->next_k = 0;
+    s->block = UINT64_MAX;
+}
+
+static double ns_next(normal_stream *s)
+{
+    uint64_t k = s->next_k++;
+    uint64_t j = k / 4;
+    if (j != s->block) {
+        uint32_t w[4];
+        orc_block_words(s->seed, s->tag, s->path, j, w);
+        box_muller_block(w, s->z);
+        s->block = j;
+    }
+    return s->z[k % 4];
+}
+
+static double pos(double x) { return x > 0.0 ? x : 0.0; }
+
+/* ------------------------------------------------------------------------ */
+/* 5. One-dimensional GBM under the risk-neutral measure, dS = r S dt +      */
+/*    sigma S dW, discretised by Euler-Maruyama (Eq. 1 with mu = r S,        */
+/*    sigma(S) = sigma S; scheme of Sec. II-A.1). Two schemes:               */
+/*      scheme 0 (log-Euler): x = ln S, x += (r - sigma^2/2) dt              */
+/*                                          + sigma sqrt(dt) Z               */
+/*      scheme 1 (Euler on S): S *= 1 + r dt + sigma sqrt(dt) Z              */
+/*    `coarsen` c >= 1 couples a coarse path to a fine one as in multilevel  */
+/*    Monte Carlo (Sec. V-B): coarse step k uses Z = (sum of the c fine      */
+/*    normals k*c .. k*c+c-1) / sqrt(c); the step count n is the coarse one. */
+/*                                                                           */
+/*    Per-path channels (discount factor e^{-rT} included):                  */
+/*      0 European call (S_n - K)+                                           */
+/*      1 arithmetic-average Asian call (A - K)+, A = mean of S_1..S_n       */
+/*      2 geometric-average Asian call (G - K)+, G = exp(mean of ln S_i)     */
+/*      3 discretely monitored up-and-out call (S_n - K)+ 1{S_i < B all i}   */
+/*      4 pathwise delta of 0     5 pathwise vega (d/dsigma) of 0            */
+/*      6 pathwise delta of 1     7 pathwise vega of 1                       */
+/*      8 e^{-rT} S_n             9 (Brownian-bridge) up-and-out call with   */
+/*                                  continuous monitoring, see below         */
+/*    The pathwise derivatives are forward tangents (Sec. I-A.3 greeks).     */
+/*    Channel 9: between grid values x, y of ln S the maximum of the         */
+/*    Brownian bridge is drawn as m = (x + y + sqrt((x-y)^2                  */
+/*    - 2 dt sigma^2 ln U))/2 with U uniform (Sec. VI-A.1, exotic put);      */
+/*    U is word (i mod 4) of block floor(i/4) of stream tag+5, scheme 0 only.*/
+/* ------------------------------------------------------------------------ */
+#define GBM_CH 10
+
+static void gbm_one_path(const double *prm, int n, int scheme, int coarsen,
+                         uint64_t seed, uint32_t tag, uint64_t path, double *o)
+{
+    const double S0 = prm[0], r = prm[1], sig = prm[2], T = prm[3];
+    const double K = prm[4], B = prm[5];
+    const double dt = T / n;
+    const double sdt = sqrt(dt);
+    const double disc = exp(-r * T);
+    normal_stream ns;
+    ns_init(&ns, seed, tag, path);
+
+    double S = S0, x = log(S0);
+    double dS_dS0 = 1.0, dS_dsig = 0.0;     /* tangents of S_i */
+    double dx_dsig = 0.0;                   /* tangent of x_i (scheme 0) */
+    double sumS = 0.0, sum_lnS = 0.0, sum_dS_dS0 = 0.0, sum_dS_dsig = 0.0;
+    int alive = 1, alive_bb = 1;
+    const double lnB = log(B);
+
+    for (int i = 0; i < n; ++i) {
+        double Z = 0.0;
+        for (int c = 0; c < coarsen; ++c) Z += ns_next(&ns);
+        Z /= sqrt((double)coarsen);
+        double x_prev = x;
+        if (scheme == 0) {
+            x = x + (r - 0.5 * sig * sig) * dt + sig * sdt * Z;
+            dx_dsig = dx_dsig - sig * dt + sdt * Z;
+            S = exp(x);
+            dS_dS0 = S / S0;
+            dS_dsig = S * dx_dsig;
+        } else {
+            double f = 1.0 + r * dt + sig * sdt * Z;
+            dS_dsig = dS_dsig * f + S * sdt * Z;
+            S = S * f;
+            dS_dS0 = dS_dS0 * f;
+            x = log(S);
+        }
+        sumS += S;
+        sum_lnS += log(S);
+        sum_dS_dS0 += dS_dS0;
+        sum_dS_dsig += dS_dsig;
+        if (!(S < B)) alive = 0;
+        if (scheme == 0) {
+            uint32_t w[4];
+            orc_block_words(seed, tag + 5u, path, (uint64_t)i / 4, w);
+            double U = orc_uniform(w[i % 4]);
+            double d = x_prev - x;
+            double m = 0.5 * (x_prev + x + sqrt(d * d - 2.0 * dt * sig * sig * log(U)));
+            if (!(m < lnB)) alive_bb = 0;
+        }
+    }
+    double A = sumS / n;
+    double G = exp(sum_lnS / n);
+    double call = pos(S - K);
+    o[0] = disc * call;
+    o[1] = disc * pos(A - K);
+    o[2] = disc * pos(G - K);
+    o[3] = alive ? disc * call : 0.0;
+    o[4] = S > K ? disc * dS_dS0 : 0.0;
+    o[5] = S > K ? disc * dS_dsig : 0.0;
+    o[6] = A > K ? disc * sum_dS_dS0 / n : 0.0;
+    o[7] = A > K ? disc * sum_dS_dsig / n : 0.0;
+    o[8] = disc * S;
+    o[9] = (scheme == 0 && alive_bb) ? disc * call : 0.0;
+}
+
+int orc_gbm_channels(void) { return GBM_CH; }
+
+/* prm = {S0, r, sigma, T, K, B} */
+void orc_gbm(const double *prm, int n_steps, int scheme, int coarsen,
+             uint64_t seed, uint32_t tag, uint64_t path0, uint64_t n_paths,
+             double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (long long p = 0; p < (long long)n_paths; ++p)
+        gbm_one_path(prm, n_steps, scheme, coarsen, seed, tag,
+                     path0 + (uint64_t)p, out + (uint64_t)p * GBM_CH);
+}
+
+/* ------------------------------------------------------------------------ */
+/* 6. Heston stochastic volatility (stochastic volatility is named in Sec.   */
+/*    I-A.1 and Sec. II-A.1 as the same computation pattern), discretised by */
+/*    full-truncation Euler on (ln S, v):                                    */
+/*      v+ = max(v, 0)                                                       */
+/*      x += (r - v+/2) dt + sqrt(v+ dt) Zs                                  */
+/*      v += kappa (theta - v+) dt + xi sqrt(v+ dt) Z1                       */
+/*      Zs = rho Z1 + sqrt(1 - rho^2) Z2                                     */
+/*    Step i uses normals k = 2i (Z1) and k = 2i+1 (Z2).                     */
+/*    Channels (discounted):                                                 */
+/*      0 European call        1 arithmetic Asian call (mean of S_1..S_n)    */
+/*      2 d/dS0 of 0           3 d/dv0 of 0                                  */
+/*      4 d/dS0 of 1           5 d/dv0 of 1                                  */
+/*      6 e^{-rT} S_n                                                        */
+/*    Tangents in forward mode; the derivative of sqrt(v+) at v <= 0 is 0.   */
+/* ------------------------------------------------------------------------ */
+#define HES_CH 7
+
+static void heston_one_path(const double *prm, int n, uint64_t seed,
+                            uint32_t tag, uint64_t path, double *o)
+{
+    const double S0 = prm[0], v0 = prm[1], kap = prm[2], th = prm[3];
+    const double xi = prm[4], rho = prm[5], r = prm[6], T = prm[7], K = prm[8];
+    const double dt = T / n, disc = exp(-r * T);
+    const double rho_c = sqrt(1.0 - rho * rho);
+    normal_stream ns;
+    ns_init(&ns, seed, tag, path);
+
+    double x = log(S0), v = v0;
+    double dx_dS0 = 1.0 / S0;                /* d x_i / d S0 (constant) */
+    double dx_dv0 = 0.0, dv_dv0 = 1.0;       /* tangents w.r.t. v0 */
+    double S = S0, sumS = 0.0, sum_dS0 = 0.0, sum_dv0 = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double Z1 = ns_next(&ns);
+        double Z2 = ns_next(&ns);
+        double Zs = rho * Z1 + rho_c * Z2;
+        double vp = pos(v);
+        double dvp = v > 0.0 ? dv_dv0 : 0.0;
+        double sq = sqrt(vp * dt);
+        double dsq = vp > 0.0 ? dt * dvp / (2.0 * sq) : 0.0;
+        double x_new = x + (r - 0.5 * vp) * dt + sq * Zs;
+        double v_new = v + kap * (th - vp) * dt + xi * sq * Z1;
+        double dx_new = dx_dv0 - 0.5 * dvp * dt + dsq * Zs;
+        double dv_new = dv_dv0 - kap * dvp * dt + xi * dsq * Z1;
+        x = x_new; v = v_new; dx_dv0 = dx_new; dv_dv0 = dv_new;
+        S = exp(x);
+        sumS += S;
+        sum_dS0 += S * dx_dS0;
+        sum_dv0 += S * dx_dv0;
+    }
+    double A = sumS / n;
+    o[0] = disc * pos(S - K);
+    o[1] = disc * pos(A - K);
+    o[2] = S > K ? disc * S * dx_dS0 : 0.0;
+    o[3] = S > K ? disc * S * dx_dv0 : 0.0;
+    o[4] = A > K ? disc * sum_dS0 / n : 0.0;
+    o[5] = A > K ? disc * sum_dv0 / n : 0.0;
+    o[6] = disc * S;
+}
+
+int orc_heston_channels(void) { return HES_CH; }
+
+/* prm = {S0, v0, kappa, theta, xi, rho, r, T, K} */
+void orc_heston(const double *prm, int n_steps, uint64_t seed, uint32_t tag,
+                uint64_t path0, uint64_t n_paths, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (long long p = 0; p < (long long)n_paths; ++p)
+        heston_one_path(prm, n_steps, seed, tag, path0 + (uint64_t)p,
+                        out + (uint64_t)p * HES_CH);
+}
+
+/* ------------------------------------------------------------------------ */
+/* 7. Cholesky factorisation C = L L^T (lower triangular), the textbook      */
+/*    column-by-column algorithm. Returns 0, or -1 if C is not positive      */
+/*    definite (a pivot <= 0). The paper factors Gram matrices the same way  */
+/*    in its regression workload (Sec. II-A.3) and builds correlated         */
+/*    increments from a volatility matrix (Sec. II-A.2).                     */
+/* ------------------------------------------------------------------------ */
+int orc_cholesky(int d, const double *C, double *L)
+{
+    memset(L, 0, sizeof(double) * (size_t)d * (size_t)d);
+    for (int j = 0; j < d; ++j) {
+        double s = C[(size_t)j * d + j];
+        for (int k = 0; k < j; ++k) s -= L[(size_t)j * d + k] * L[(size_t)j * d + k];
+        if (!(s > 0.0)) return -1;
+        double ljj = sqrt(s);
+        L[(size_t)j * d + j] = ljj;
+        for (int i = j + 1; i < d; ++i) {
+            double t = C[(size_t)i * d + j];
+            for (int k = 0; k < j; ++k) t -= L[(size_t)i * d + k] * L[(size_t)j * d + k];
+            L[(size_t)i * d + j] = t / ljj;
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 8. Basket of d correlated GBM assets (Sec. II-A.2; basket call of         */
+/*    Sec. VI-A.2), log-Euler per asset:                                     */
+/*      x_a += (r - sigma_a^2/2) dt + sigma_a sqrt(dt) (L Z_i)_a             */
+/*    with Z_i the d normals k = i*d + a of the step and L the lower         */
+/*    Cholesky factor of the correlation matrix.                             */
+/*    Channels (discounted):                                                 */
+/*      0 basket call (sum_a w_a S_{n,a} - K)+                               */
+/*      1 geometric basket call (exp(sum_a w_a x_{n,a}) - K)+                */
+/*      2 pathwise d/dS0 of asset 0 of channel 0                             */
+/* ------------------------------------------------------------------------ */
+#define BSK_CH 3
+
+int orc_basket_channels(void) { return BSK_CH; }
+
+void orc_basket(int d, const double *S0, const double *sigma, const double *L,
+                const double *w, double r, double T, double K, int n_steps,
+                uint64_t seed, uint32_t tag, uint64_t path0, uint64_t n_paths,
+                double *out)
+{
+    const double dt = T / n_steps, sdt = sqrt(dt), disc = exp(-r * T);
+#pragma omp parallel
+    {
+        double *x = (double *)malloc(sizeof(double) * (size_t)d);
+        double *Z = (double *)malloc(sizeof(double) * (size_t)d);
+#pragma omp for schedule(static)
+        for (long long p = 0; p < (long long)n_paths; ++p) {
+            normal_stream ns;
+            ns_init(&ns, seed, tag, path0 + (uint64_t)p);
+            for (int a = 0; a < d; ++a) x[a] = log(S0[a]);
+            for (int i = 0; i < n_steps; ++i) {
+                for (int a = 0; a < d; ++a) Z[a] = ns_next(&ns);
+                for (int a = 0; a < d; ++a) {
+                    double dW = 0.0;
+                    for (int b = 0; b <= a; ++b) dW += L[(size_t)a * d + b] * Z[b];
+                    x[a] += (r - 0.5 * sigma[a] * sigma[a]) * dt + sigma[a] * sdt * dW;
+                }
+            }
+            double basket = 0.0, geo = 0.0;
+            for (int a = 0; a < d; ++a) {
+                basket += w[a] * exp(x[a]);
+                geo += w[a] * x[a];
+            }
+            double *o = out + (uint64_t)p * BSK_CH;
+            o[0] = disc * pos(basket - K);
+            o[1] = disc * pos(exp(geo) - K);
+            o[2] = basket > K ? disc * w[0] * exp(x[0]) / S0[0] : 0.0;
+        }
+        free(x);
+        free(Z);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* 9. Learned martingale control variate on the Heston Asian call.           */
+/*    A small network Delta_theta(t, state) is a hedge ratio; the hedge     */
+/*    P&L  H = sum_j Delta(t_j, phi_j) (St_{j+1} - St_j),  St_i = e^{-r t_i}  */
+/*    S_i, has zero mean for any weights because St is a martingale under   */
+/*    the log-Euler step. The estimator averages Y = payoff - H (Eq. 3      */
+/*    applied to Y). With rebalancing every m steps the hedge is held from  */
+/*    step j*m to (j+1)*m.                                                   */
+/*    Network 4 -> 64 -> 64 -> 1, tanh after the two hidden layers.         */
+/*    Parameters, flat: W1[64][4], b1[64], W2[64][64], b2[64], W3[64], b3.   */
+/*    Features phi_i = (t_i/T, ln(S_i/K), v_i/theta, Abar_i/K - 1), Abar_i  */
+/*    the running mean of S_1..S_i (Abar_0 = S0).                            */
+/* ------------------------------------------------------------------------ */
+#define MLP_H 64
+#define MLP_NPARAM (MLP_H * 4 + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1)
+
+int orc_mlp_nparam(void) { return MLP_NPARAM; }
+
+typedef struct {
+    const double *W1, *b1, *W2, *b2, *W3, *b3;
+} mlp_view;
+
+static mlp_view mlp_split(const double *th)
+{
+    mlp_view m;
+    m.W1 = th;
+    m.b1 = m.W1 + MLP_H * 4;
+    m.W2 = m.b1 + MLP_H;
+    m.b2 = m.W2 + MLP_H * MLP_H;
+    m.W3 = m.b2 + MLP_H;
+    m.b3 = m.W3 + MLP_H;
+    return m;
+}
+
+/* Forward pass; keeps the hidden activations for the backward pass. */
+static double mlp_forward(const mlp_view *m, const double phi[4],
+                          double h1[MLP_H], double h2[MLP_H])
+{
+    for (int u = 0; u < MLP_H; ++u) {
+        double s = m->b1[u];
+        for (int f = 0; f < 4; ++f) s += m->W1[u * 4 + f] * phi[f];
+        h1[u] = tanh(s);
+    }
+    for (int u = 0; u < MLP_H; ++u) {
+        double s = m->b2[u];
+        for (int q = 0; q < MLP_H; ++q) s += m->W2[u * MLP_H + q] * h1[q];
+        h2[u] = tanh(s);
+    }
+    double out = m->b3[0];
+    for (int u = 0; u < MLP_H; ++u) out += m->W3[u] * h2[u];
+    return out;
+}
+
+/* Backward pass of g * Delta with respect to every parameter, accumulated
+ * into grad (same flat layout). */
+static void mlp_backward(const mlp_view *m, const double phi[4],
+                         const double h1[MLP_H], const double h2[MLP_H],
+                         double g, double *grad)
+{
+    double *gW1 = grad, *gb1 = gW1 + MLP_H * 4, *gW2 = gb1 + MLP_H;
+    double *gb2 = gW2 + MLP_H * MLP_H, *gW3 = gb2 + MLP_H, *gb3 = gW3 + MLP_H;
+    double d2[MLP_H], d1[MLP_H];
+    gb3[0] += g;
+    for (int u = 0; u < MLP_H; ++u) {
+        gW3[u] += g * h2[u];
+        d2[u] = g * m->W3[u] * (1.0 - h2[u] * h2[u]);
+    }
+    for (int u = 0; u < MLP_H; ++u) {
+        gb2[u] += d2[u];
+        for (int q = 0; q < MLP_H; ++q) gW2[u * MLP_H + q] += d2[u] * h1[q];
+    }
+    for (int q = 0; q < MLP_H; ++q) {
+        double s = 0.0;
+        for (int u = 0; u < MLP_H; ++u) s += m->W2[u * MLP_H + q] * d2[u];
+        d1[q] = s * (1.0 - h1[q] * h1[q]);
+    }
+    for (int u = 0; u < MLP_H; ++u) {
+        gb1[u] += d1[u];
+        for (int f = 0; f < 4; ++f) gW1[u * 4 + f] += d1[u] * phi[f];
+    }
+}
+
+/* Simulates one Heston path and its hedge. Returns the discounted Asian
+ * payoff in *pay and the hedge P&L in *H. When grad != NULL it also adds
+ * g_up * dH/dtheta to grad (g_up is the upstream derivative of the loss
+ * with respect to H of this path). */
+static void heston_cv_path(const double *prm, int n, int m_every,
+                           const mlp_view *net, uint64_t seed, uint32_t tag,
+                           uint64_t path, double *pay, double *H,
+                           double g_up, double *grad)
+{
+    const double S0 = prm[0], v0 = prm[1], kap = prm[2], th = prm[3];
+    const double xi = prm[4], rho = prm[5], r = prm[6], T = prm[7], K = prm[8];
+    const double dt = T / n, disc = exp(-r * T);
+    const double rho_c = sqrt(1.0 - rho * rho);
+    normal_stream ns;
+    ns_init(&ns, seed, tag, path);
+    double x = log(S0), v = v0, S = S0, sumS = 0.0, Abar = S0;
+    double hedge = 0.0, Hsum = 0.0;
+    double St_open = S0;             /* discounted S where the hedge opened */
+    double phi_open[4], h1[MLP_H], h2[MLP_H];
+    for (int i = 0; i < n; ++i) {
+        if (i % m_every == 0) {
+            phi_open[0] = (i * dt) / T;
+            phi_open[1] = log(S / K);
+            phi_open[2] = v / th;
+            phi_open[3] = Abar / K - 1.0;
+            hedge = mlp_forward(net, phi_open, h1, h2);
+            St_open = exp(-r * i * dt) * S;
+        }
+        double Z1 = ns_next(&ns);
+        double Z2 = ns_next(&ns);
+        double Zs = rho * Z1 + rho_c * Z2;
+        double vp = pos(v);
+        double sq = sqrt(vp * dt);
+        x = x + (r - 0.5 * vp) * dt + sq * Zs;
+        v = v + kap * (th - vp) * dt + xi * sq * Z1;
+        S = exp(x);
+        sumS += S;
+        Abar = sumS / (i + 1);
+        if ((i + 1) % m_every == 0 || i + 1 == n) {
+            double dSt = exp(-r * (i + 1) * dt) * S - St_open;
+            Hsum += hedge * dSt;
+            if (grad) mlp_backward(net, phi_open, h1, h2, g_up * dSt, grad);
+        }
+    }
+    *pay = disc * pos(sumS / n - K);
+    *H = Hsum;
+}
+
+/* Per-path (payoff, H, payoff - H). */
+void orc_heston_cv(const double *prm, int n_steps, int m_every,
+                   const double *theta, uint64_t seed, uint32_t tag,
+                   uint64_t path0, uint64_t n_paths, double *out /* n x 3 */)
+{
+    mlp_view net = mlp_split(theta);
+#pragma omp parallel for schedule(static)
+    for (long long p = 0; p < (long long)n_paths; ++p) {
+        double pay, H;
+        heston_cv_path(prm, n_steps, m_every, &net, seed, tag,
+                       path0 + (uint64_t)p, &pay, &H, 0.0, NULL);
+        out[3 * p] = pay;
+        out[3 * p + 1] = H;
+        out[3 * p + 2] = pay - H;
+    }
+}
+
+/* Network output alone, for a list of feature vectors (n x 4). */
+void orc_mlp_eval(const double *theta, uint64_t n, const double *phi,
+                  double *out)
+{
+    mlp_view net = mlp_split(theta);
+    double h1[MLP_H], h2[MLP_H];
+    for (uint64_t i = 0; i < n; ++i) out[i] = mlp_forward(&net, phi + 4 * i, h1, h2);
+}
+
+/* Training loss over a batch of B paths and its gradient:
+ *   L(theta) = (1/B) sum_b (Y_b - Ybar)^2,  Y_b = payoff_b - H_b(theta).
+ *   dL/dtheta = (2/B) sum_b (Y_b - Ybar) dY_b/dtheta
+ *             = sum_b [-(2/B)(Y_b - Ybar)] dH_b/dtheta.
+ * The first pass gets Ybar, the second accumulates the gradient. Paths are
+ * path0 .. path0+B-1 of stream `tag`. */
+double orc_cv_loss_grad(const double *prm, int n_steps, int m_every,
+                        const double *theta, uint64_t seed, uint32_t tag,
+                        uint64_t path0, uint64_t B, double *grad)
+{
+    mlp_view net = mlp_split(theta);
+    double *Y = (double *)malloc(sizeof(double) * B);
+#pragma omp parallel for schedule(static)
+    for (long long b = 0; b < (long long)B; ++b) {
+        double pay, H;
+        heston_cv_path(prm, n_steps, m_every, &net, seed, tag,
+                       path0 + (uint64_t)b, &pay, &H, 0.0, NULL);
+        Y[b] = pay - H;
+    }
+    double Ybar = 0.0;
+    for (uint64_t b = 0; b < B; ++b) Ybar += Y[b];
+    Ybar /= (double)B;
+    double loss = 0.0;
+    for (uint64_t b = 0; b < B; ++b) loss += (Y[b] - Ybar) * (Y[b] - Ybar);
+    loss /= (double)B;
+    if (grad) {
+        memset(grad, 0, sizeof(double) * MLP_NPARAM);
+        /* Serial in b: the gradient is a sum over paths in path order. */
+        for (uint64_t b = 0; b < B; ++b) {
+            double pay, H;
+            double g_up = -(2.0 / (double)B) * (Y[b] - Ybar);
+            heston_cv_path(prm, n_steps, m_every, &net, seed, tag,
+                           path0 + b, &pay, &H, g_up, grad);
+        }
+    }
+    free(Y);
+    return loss;
+}

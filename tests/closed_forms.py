@@ -1,0 +1,122 @@
+"""Closed and semi-closed forms used to pin the oracle.
+
+These are textbook formulas, written independently of the oracle's path
+simulation, so that a mistake in the oracle's dynamics, payoff or random
+numbers shows up as a disagreement with them.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy import integrate
+from scipy.stats import norm
+
+
+# Black-Scholes-Merton (no dividends) -------------------------------------
+def bs_call(S0, K, r, sigma, T):
+    st = sigma * math.sqrt(T)
+    d1 = (math.log(S0 / K) + (r + 0.5 * sigma * sigma) * T) / st
+    d2 = d1 - st
+    return S0 * norm.cdf(d1) - K * math.exp(-r * T) * norm.cdf(d2)
+
+
+def bs_delta(S0, K, r, sigma, T):
+    st = sigma * math.sqrt(T)
+    d1 = (math.log(S0 / K) + (r + 0.5 * sigma * sigma) * T) / st
+    return norm.cdf(d1)
+
+
+def bs_vega(S0, K, r, sigma, T):
+    st = sigma * math.sqrt(T)
+    d1 = (math.log(S0 / K) + (r + 0.5 * sigma * sigma) * T) / st
+    return S0 * norm.pdf(d1) * math.sqrt(T)
+
+
+def lognormal_call(m, s2, K, disc):
+    """disc * E[(e^Y - K)+] for Y ~ N(m, s2)."""
+    s = math.sqrt(s2)
+    d2 = (m - math.log(K)) / s
+    d1 = d2 + s
+    return disc * (math.exp(m + 0.5 * s2) * norm.cdf(d1) - K * norm.cdf(d2))
+
+
+# Discretely sampled geometric-average Asian call (Kemna-Vorst type), average
+# of ln S over the n dates t_i = i T/n, i = 1..n (S0 not included).
+def geo_asian_call(S0, K, r, sigma, T, n):
+    mu = r - 0.5 * sigma * sigma
+    m = math.log(S0) + mu * T * (n + 1) / (2.0 * n)
+    s2 = sigma * sigma * T * (n + 1) * (2 * n + 1) / (6.0 * n * n)
+    return lognormal_call(m, s2, K, math.exp(-r * T))
+
+
+# Continuously monitored up-and-out call, barrier H above the strike
+# (Merton 1973; Reiner-Rubinstein 1991), no rebate.
+def up_out_call(S, K, H, r, sigma, T):
+    if S >= H:
+        return 0.0
+    if K >= H:
+        return 0.0
+    st = sigma * math.sqrt(T)
+    mu = (r - 0.5 * sigma * sigma) / (sigma * sigma)
+    x1 = math.log(S / K) / st + (1 + mu) * st
+    x2 = math.log(S / H) / st + (1 + mu) * st
+    y1 = math.log(H * H / (S * K)) / st + (1 + mu) * st
+    y2 = math.log(H / S) / st + (1 + mu) * st
+    df = math.exp(-r * T)
+    A = S * norm.cdf(x1) - K * df * norm.cdf(x1 - st)
+    Bt = S * norm.cdf(x2) - K * df * norm.cdf(x2 - st)
+    p1 = (H / S) ** (2 * (mu + 1))
+    p0 = (H / S) ** (2 * mu)
+    Ct = S * p1 * norm.cdf(-y1) - K * df * p0 * norm.cdf(-y1 + st)
+    Dt = S * p1 * norm.cdf(-y2) - K * df * p0 * norm.cdf(-y2 + st)
+    return A - Bt + Ct - Dt
+
+
+def bgk_discrete_up_out_call(S, K, H, r, sigma, T, n):
+    """Broadie-Glasserman-Kou continuity correction for n monitoring dates."""
+    beta1 = 0.5825971579390107  # -zeta(1/2)/sqrt(2*pi)
+    return up_out_call(S, K, H * math.exp(beta1 * sigma * math.sqrt(T / n)), r,
+                       sigma, T)
+
+
+# Heston (1993) European call by Gil-Pelaez inversion of the characteristic
+# function of ln S_T, in the rotation-safe form of Albrecher et al. (2007).
+def heston_cf(u, S0, v0, kappa, theta, xi, rho, r, T):
+    iu = 1j * u
+    b = kappa - rho * xi * iu
+    d = np.sqrt(b * b + xi * xi * (iu + u * u))
+    g = (b - d) / (b + d)
+    e = np.exp(-d * T)
+    C = kappa * theta / (xi * xi) * ((b - d) * T - 2.0 * np.log((1 - g * e) / (1 - g)))
+    D = (b - d) / (xi * xi) * (1 - e) / (1 - g * e)
+    return np.exp(iu * (math.log(S0) + r * T) + C + D * v0)
+
+
+def heston_call(S0, v0, kappa, theta, xi, rho, r, T, K):
+    lnK = math.log(K)
+    fwd = S0 * math.exp(r * T)
+
+    def f2(u):
+        return (np.exp(-1j * u * lnK) * heston_cf(u, S0, v0, kappa, theta, xi, rho, r, T)
+                / (1j * u)).real
+
+    def f1(u):
+        return (np.exp(-1j * u * lnK) * heston_cf(u - 1j, S0, v0, kappa, theta, xi, rho, r, T)
+                / (1j * u * fwd)).real
+
+    opts = dict(limit=400, epsabs=1e-13, epsrel=1e-12)
+    P1 = 0.5 + integrate.quad(f1, 1e-12, 200.0, **opts)[0] / math.pi
+    P2 = 0.5 + integrate.quad(f2, 1e-12, 200.0, **opts)[0] / math.pi
+    return S0 * P1 - K * math.exp(-r * T) * P2
+
+
+def geo_basket_call(S0, sigma, corr, w, r, T, K):
+    """disc * E[(exp(sum_a w_a ln S_T,a) - K)+] under correlated GBM."""
+    S0 = np.asarray(S0, float)
+    sigma = np.asarray(sigma, float)
+    w = np.asarray(w, float)
+    m = float(np.sum(w * (np.log(S0) + (r - 0.5 * sigma ** 2) * T)))
+    ws = w * sigma
+    s2 = float(ws @ np.asarray(corr) @ ws) * T
+    return lognormal_call(m, s2, K, math.exp(-r * T))
