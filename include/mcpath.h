@@ -1,0 +1,254 @@
+/*
+ * mcpath.h -- C ABI of the MI355X (gfx950) Monte Carlo path engine.
+ *
+ * The engine estimates E[f(X_{0:T})] for an SDE dX = mu dt + sigma dW
+ * (Eq. 1, Eq. 2) by the empirical mean over N simulated Euler-Maruyama paths
+ * (Eq. 3; scheme of Sec. II-A.1, correlated form of Sec. II-A.2), together
+ * with the estimator's standard error (variance term of the bias-variance
+ * split, Sec. V-B) and pathwise greeks (Sec. I-A.3). Gaussian increments
+ * come from the keyed counter-based Philox4x32-10 generator (Sec. IV-A)
+ * through Box-Muller; every step of the computation runs in hand-written
+ * HIP kernels on one GPU.
+ *
+ * Random-number layout (shared contract with any independent checker):
+ *   normal k of path p in stream `tag` is slot (k mod 4) of the Philox block
+ *   with counter (floor(k/4), p mod 2^32, p >> 32, tag) and key
+ *   (seed mod 2^32, seed >> 32); a block's words (w0,w1,w2,w3) give
+ *   normals r(w0)cos(2 pi u(w1)), r(w0)sin(2 pi u(w1)), r(w2)cos(2 pi u(w3)),
+ *   r(w2)sin(2 pi u(w3)), with u(w) = (2 (w >> 9) + 1) 2^-24 and
+ *   r(w) = sqrt(-2 ln u(w)). A model with d normals per time step uses
+ *   k = i d + a at step i (GBM d = 1; Heston d = 2 with a = 0 the variance
+ *   driver; basket d = number of assets). Tags: 0 main run, 1 pilot run,
+ *   2 learned-hedge training set; tag + 5 carries the Brownian-bridge
+ *   uniforms of the continuously monitored barrier.
+ *
+ * Conventions for every entry point:
+ *   - Returns an mc_status; no exception or signal crosses the ABI.
+ *   - On error nothing is written to the output structs; mc_last_error()
+ *     gives a message.
+ *   - Host pointers are read during the call only; the library keeps no
+ *     pointer to caller memory after it returns.
+ *   - Device pointers (workspace, checkpoint buffers) are owned by the
+ *     caller and must stay valid until the call returns.
+ *   - One context per host thread; calls on one context are serialised by
+ *     the caller.
+ *   - All pricing entry points block until the result is on the host.
+ */
+#ifndef MCPATH_H
+#define MCPATH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MC_OK = 0,
+    MC_ERR_INVALID_ARG = -1,   /* a NULL pointer, non-finite or out-of-range value */
+    MC_ERR_NOT_PD = -2,        /* correlation matrix not positive definite */
+    MC_ERR_NO_DEVICE = -3,     /* no HIP device, or the device index is out of range */
+    MC_ERR_OOM = -4,           /* device allocation failed */
+    MC_ERR_DEVICE = -5,        /* a HIP runtime call or kernel launch failed */
+    MC_ERR_UNSUPPORTED = -6,   /* valid arguments, combination not offered */
+    MC_ERR_WORKSPACE = -7      /* caller workspace smaller than required */
+} mc_status;
+
+typedef enum { MC_GBM = 1, MC_GBM_BASKET = 2, MC_HESTON = 3 } mc_model_kind;
+
+/* GBM discretisation (Sec. II-A.1 applied to dS = r S dt + sigma S dW):
+ * MC_LOG_EULER steps ln S, MC_EULER_S steps S itself. Heston always uses
+ * full-truncation Euler on (ln S, v); the basket always uses log-Euler. */
+typedef enum { MC_LOG_EULER = 0, MC_EULER_S = 1 } mc_scheme;
+
+/* Arithmetic of the path state (Sec. V-A). MC_FP64: the whole path in
+ * double. MC_FP32: single-precision path state and arithmetic, double
+ * precision only for the cross-path sums. For the basket the correlated
+ * increment Z L^T is a matrix product on the matrix cores: MC_FP32 uses
+ * FP32 inputs, MC_BF16_GEMM / MC_FP16_GEMM round Z and L to bfloat16 /
+ * half with FP32 accumulation, MC_BF16X2_GEMM splits L into two bfloat16
+ * terms (hi + lo) to remove the systematic rounding of L. */
+typedef enum {
+    MC_FP64 = 0, MC_FP32 = 1, MC_BF16_GEMM = 2, MC_FP16_GEMM = 3, MC_BF16X2_GEMM = 4
+} mc_precision;
+
+typedef struct {
+    mc_model_kind kind;
+    uint32_t dim;              /* assets: 1 for MC_GBM and MC_HESTON */
+    double r;                  /* risk-free rate (drift under Q) */
+    double T;                  /* maturity in years, > 0 */
+    const double *S0;          /* [dim] initial prices, host, > 0 */
+    const double *sigma;       /* [dim] volatilities, host (GBM, basket), >= 0 */
+    const double *corr;        /* [dim*dim] row-major correlation, host; basket only */
+    double v0, kappa, theta, xi, rho;  /* Heston: v0 >= 0, kappa, theta, xi >= 0, |rho| < 1 */
+    mc_scheme scheme;
+} mc_model;
+
+typedef enum {
+    MC_EURO_CALL = 1,           /* (S_T - K)+ */
+    MC_ASIAN_ARITH_CALL = 2,    /* (A - K)+, A = mean of S_{t_1..t_n} (S0 excluded) */
+    MC_ASIAN_GEO_CALL = 3,      /* (exp(mean of ln S_{t_i}) - K)+ */
+    MC_UO_BARRIER_CALL = 4,     /* (S_T - K)+ 1{S_{t_i} < B for i = 1..n} */
+    MC_BASKET_CALL = 5,         /* (sum_a w_a S_T,a - K)+ */
+    MC_UO_BRIDGE_CALL = 6       /* up-and-out call, continuous monitoring through the
+                                   Brownian-bridge maximum between steps (Sec. VI-A.1) */
+} mc_payoff_kind;
+
+/* Control variates. MC_CV_GEO_ASIAN: Y = P_A - beta (P_G - C_G) with C_G the
+ * discrete geometric-Asian closed form (GBM only). MC_CV_LEARNED: Y = payoff
+ * - H, H the discounted P&L of a learned hedge (Heston Asian only). */
+typedef enum { MC_CV_NONE = 0, MC_CV_GEO_ASIAN = 1, MC_CV_LEARNED = 2 } mc_cv_kind;
+
+typedef struct {
+    mc_payoff_kind kind;
+    double K;                  /* strike, >= 0 */
+    double B;                  /* barrier (barrier payoffs), > S0 */
+    const double *weights;     /* [dim] basket weights, host; NULL = 1/dim each */
+    mc_cv_kind cv;
+} mc_payoff;
+
+#define MC_GREEK_DELTA 1u      /* d price / d S0 (basket: of asset 0) */
+#define MC_GREEK_VEGA 2u       /* GBM: d/d sigma; Heston: d/d v0 */
+
+#define MC_MLP_NPARAM 4545     /* 4-64-64-1 hedge network, FP32 */
+
+typedef struct {
+    mc_precision prec;         /* default MC_FP32 */
+    uint32_t greeks;           /* MC_GREEK_* bits */
+    uint64_t path_offset;      /* first global path index (sharding, resumption) */
+    uint32_t stream_tag;       /* Philox stream tag, default 0 */
+    void *hip_stream;          /* hipStream_t to run on; NULL = the context stream */
+    void *workspace;           /* device scratch; NULL = context-owned */
+    size_t workspace_bytes;
+    const float *cv_weights;   /* [MC_MLP_NPARAM] host, for MC_CV_LEARNED */
+    uint32_t cv_hedge_every;   /* learned hedge rebalanced every m steps (>= 1) */
+    double cv_beta;            /* static-CV coefficient; NaN = estimate on a pilot */
+    uint64_t pilot_paths;      /* pilot size (tag 1) for beta / fallback; 0 = 2^16 */
+    double *path_values;       /* optional host [n_paths * mc_path_channels()]
+                                  per-path values (testing and diagnostics) */
+} mc_options;
+
+typedef struct {
+    double price, std_err, variance;   /* estimator (with the control variate, if any) */
+    double delta, delta_se, vega, vega_se;
+    double plain_price, plain_std_err; /* same paths without the control variate */
+    double cv_beta;                    /* coefficient used (static CV) */
+    double vrf;                        /* variance-reduction factor plain/CV */
+    uint64_t n_paths, n_nonfinite;
+    double kernel_ms;                  /* device time of the path kernel(s) */
+    int cv_fallback;                   /* 1 when the learned CV lost to plain MC on the pilot */
+} mc_result;
+
+typedef struct mc_context mc_context;
+
+/* Opens a context on HIP device `device` with its own stream. */
+mc_status mc_create(mc_context **ctx, int device);
+/* Frees the context, its stream and its device buffers. NULL is allowed. */
+mc_status mc_destroy(mc_context *ctx);
+
+/* Fills opts with defaults (MC_FP32, no greeks, tag 0, beta NaN, m = 1). */
+void mc_options_default(mc_options *opts);
+
+/* Runs every argument check mc_price makes (values, model/payoff/precision
+ * combination, positive definiteness of a basket correlation) without
+ * touching a device. ctx may be NULL (then no message is kept). */
+mc_status mc_validate(mc_context *ctx, const mc_model *model, const mc_payoff *payoff,
+                      uint64_t n_paths, uint32_t n_steps, const mc_options *opts);
+
+/* Bytes of device workspace one mc_price call needs (0 on bad arguments). */
+size_t mc_workspace_bytes(const mc_model *model, const mc_payoff *payoff,
+                          uint64_t n_paths, uint32_t n_steps, const mc_options *opts);
+
+/* Estimates E[f(X_{0:T})] of Eq. (2) by Eq. (3) over n_paths paths of
+ * n_steps Euler-Maruyama steps (Sec. II-A.1 / II-A.2), with standard error
+ * and the requested pathwise greeks (Sec. I-A.3). Path p of the run uses
+ * global index opts->path_offset + p in the counter, so disjoint path
+ * ranges can be merged exactly. Requires n_paths >= 2, n_steps >= 1.
+ * Pathwise greeks of a discontinuous payoff (barriers) are MC_ERR_UNSUPPORTED.
+ * opts may be NULL (defaults). */
+mc_status mc_price(mc_context *ctx, const mc_model *model, const mc_payoff *payoff,
+                   uint64_t n_paths, uint32_t n_steps, uint64_t seed,
+                   const mc_options *opts, mc_result *out);
+
+/* Prices n_payoffs payoffs on the same simulated paths in one pass.
+ * results[i] receives payoff i. GBM only. */
+mc_status mc_price_multi(mc_context *ctx, const mc_model *model,
+                         const mc_payoff *payoffs, uint32_t n_payoffs,
+                         uint64_t n_paths, uint32_t n_steps, uint64_t seed,
+                         const mc_options *opts, mc_result *results);
+
+/* Number of per-path channels written to opts->path_values by mc_price for
+ * this model/payoff/options, and the name of channel i ("euro", "asian",
+ * "geo", "uo", "uo_bridge", "euro_delta", "euro_vega", "asian_delta",
+ * "asian_vega", "basket", "basket_delta0", "hedge_pnl", ...). Every channel
+ * is a discounted per-path value; a row is one path. Returns 0 / NULL on
+ * bad arguments. */
+uint32_t mc_path_channels(const mc_model *model, const mc_payoff *payoff,
+                          const mc_options *opts);
+const char *mc_path_channel_name(const mc_model *model, const mc_payoff *payoff,
+                                 const mc_options *opts, uint32_t i);
+
+/* Pathwise adjoint greeks (Sec. I-A.3, Sec. VI-A.2 basket delta by
+ * back-propagation), Heston European or arithmetic-Asian call. The reverse
+ * sweep restarts from checkpoints of (ln S, v) saved every `ckpt_every`
+ * steps and regenerates the normals from Philox.
+ *   MC_ADJ_FULL: forward + reverse in one launch; fills price, delta, vega
+ *                (d/dv0) and their standard errors. ckpt may be NULL
+ *                (context workspace).
+ *   MC_ADJ_FWD:  forward only: price, and writes the checkpoints to ckpt.
+ *   MC_ADJ_REV:  reverse only from the checkpoints of a previous FWD call
+ *                with identical arguments; fills delta, vega scaled by
+ *                grad_out (the upstream derivative of the loss w.r.t. price).
+ * ckpt is a device buffer of mc_adjoint_ckpt_bytes() bytes, FP32, laid out
+ * [checkpoint][component][path]. */
+typedef enum { MC_ADJ_FULL = 0, MC_ADJ_FWD = 1, MC_ADJ_REV = 2 } mc_adjoint_phase;
+size_t mc_adjoint_ckpt_bytes(uint64_t n_paths, uint32_t n_steps, uint32_t ckpt_every);
+mc_status mc_greeks_adjoint(mc_context *ctx, const mc_model *model,
+                            const mc_payoff *payoff, uint64_t n_paths,
+                            uint32_t n_steps, uint64_t seed, const mc_options *opts,
+                            mc_adjoint_phase phase, uint32_t ckpt_every,
+                            void *ckpt, size_t ckpt_bytes, double grad_out,
+                            mc_result *out);
+
+/* Adam settings for mc_cv_train (Kingma and Ba). */
+typedef struct {
+    double lr, beta1, beta2, eps;
+    uint32_t steps;            /* Adam steps */
+    uint64_t batch;            /* minibatch paths, multiple of 256 */
+    uint32_t hedge_every;      /* rebalancing period m >= 1 */
+    mc_precision prec;         /* MC_FP32 or MC_BF16_GEMM for the 64x64 layer */
+} mc_adam_cfg;
+
+/* Trains the hedge network of the learned control variate on n_train paths
+ * of stream tag 2 (cycled in minibatches) to minimise the batch variance of
+ * Y = payoff - H. weights_inout: host [MC_MLP_NPARAM] FP32, initial weights
+ * in, trained weights out. loss_log: host [steps] or NULL. Heston Asian
+ * call only. */
+mc_status mc_cv_train(mc_context *ctx, const mc_model *model, const mc_payoff *payoff,
+                      uint64_t n_train, uint32_t n_steps, uint64_t seed,
+                      const mc_adam_cfg *cfg, float *weights_inout, float *loss_log);
+
+/* Loss and gradient of the learned CV on one minibatch (paths path0 ..
+ * path0+batch-1 of stream `tag`): grad_out host [MC_MLP_NPARAM] FP32. */
+mc_status mc_cv_loss_grad(mc_context *ctx, const mc_model *model, const mc_payoff *payoff,
+                          uint32_t n_steps, uint64_t seed, uint32_t tag, uint64_t path0,
+                          uint64_t batch, const mc_adam_cfg *cfg, const float *weights,
+                          double *loss_out, float *grad_out);
+
+/* Raw Philox4x32-10 blocks of sampled (path, block) pairs and the normals
+ * of one path, computed by the same device functions the path kernels use
+ * (bit-exact checks of the random-number layout). Host arrays. */
+mc_status mc_philox_words(mc_context *ctx, uint64_t seed, uint32_t tag, uint64_t n,
+                          const uint64_t *paths, const uint64_t *blocks, uint32_t *out4);
+mc_status mc_normals(mc_context *ctx, uint64_t seed, uint32_t tag, uint64_t path,
+                     uint64_t k0, uint64_t count, mc_precision prec, double *out);
+
+const char *mc_status_str(mc_status st);
+const char *mc_last_error(const mc_context *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCPATH_H */

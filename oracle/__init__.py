@@ -25,7 +25,8 @@ _u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
 _u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
 
 GBM_CHANNELS = ("euro", "asian", "geo", "uo", "euro_delta", "euro_vega",
-                "asian_delta", "asian_vega", "disc_ST", "uo_bridge")
+                "asian_delta", "asian_vega", "disc_ST", "uo_bridge", "uo_margin",
+                "uo_bridge_margin")
 HESTON_CHANNELS = ("euro", "asian", "euro_delta", "euro_dv0", "asian_delta",
                    "asian_dv0", "disc_ST")
 BASKET_CHANNELS = ("basket", "geo_basket", "delta0")

@@ -181,13 +181,15 @@ static double pos(double x) { return x > 0.0 ? x : 0.0; }
 /*      6 pathwise delta of 1     7 pathwise vega of 1                       */
 /*      8 e^{-rT} S_n             9 (Brownian-bridge) up-and-out call with   */
 /*                                  continuous monitoring, see below         */
+/*     10 knock-out margin max_i ln(S_i/B) of channel 3                      */
+/*     11 knock-out margin max_i (m_i - ln B) of channel 9                   */
 /*    The pathwise derivatives are forward tangents (Sec. I-A.3 greeks).     */
 /*    Channel 9: between grid values x, y of ln S the maximum of the         */
 /*    Brownian bridge is drawn as m = (x + y + sqrt((x-y)^2                  */
 /*    - 2 dt sigma^2 ln U))/2 with U uniform (Sec. VI-A.1, exotic put);      */
 /*    U is word (i mod 4) of block floor(i/4) of stream tag+5, scheme 0 only.*/
 /* ------------------------------------------------------------------------ */
-#define GBM_CH 10
+#define GBM_CH 12
 
 static void gbm_one_path(const double *prm, int n, int scheme, int coarsen,
                          uint64_t seed, uint32_t tag, uint64_t path, double *o)
@@ -206,6 +208,7 @@ static void gbm_one_path(const double *prm, int n, int scheme, int coarsen,
     double sumS = 0.0, sum_lnS = 0.0, sum_dS_dS0 = 0.0, sum_dS_dsig = 0.0;
     int alive = 1, alive_bb = 1;
     const double lnB = log(B);
+    double margin = -INFINITY, margin_bb = -INFINITY;
 
     for (int i = 0; i < n; ++i) {
         double Z = 0.0;
@@ -230,6 +233,7 @@ static void gbm_one_path(const double *prm, int n, int scheme, int coarsen,
         sum_dS_dS0 += dS_dS0;
         sum_dS_dsig += dS_dsig;
         if (!(S < B)) alive = 0;
+        if (log(S) - lnB > margin) margin = log(S) - lnB;
         if (scheme == 0) {
             uint32_t w[4];
             orc_block_words(seed, tag + 5u, path, (uint64_t)i / 4, w);
@@ -237,6 +241,7 @@ static void gbm_one_path(const double *prm, int n, int scheme, int coarsen,
             double d = x_prev - x;
             double m = 0.5 * (x_prev + x + sqrt(d * d - 2.0 * dt * sig * sig * log(U)));
             if (!(m < lnB)) alive_bb = 0;
+            if (m - lnB > margin_bb) margin_bb = m - lnB;
         }
     }
     double A = sumS / n;
@@ -252,6 +257,8 @@ static void gbm_one_path(const double *prm, int n, int scheme, int coarsen,
     o[7] = A > K ? disc * sum_dS_dsig / n : 0.0;
     o[8] = disc * S;
     o[9] = (scheme == 0 && alive_bb) ? disc * call : 0.0;
+    o[10] = margin;
+    o[11] = margin_bb;
 }
 
 int orc_gbm_channels(void) { return GBM_CH; }

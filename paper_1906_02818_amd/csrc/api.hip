@@ -1,0 +1,802 @@
+// C ABI of the path engine (include/mcpath.h): argument validation, device
+// workspace and stream plumbing, kernel dispatch and the estimator formulas
+// (Eq. 3 and the variance term of Sec. V-B) applied to the block moments
+// the kernels produce. Host code only; every per-path computation runs in
+// the kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mcpath.h"
+#include "host_math.h"
+#include "mc_internal.h"
+
+struct mc_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  double* pinned = nullptr;      // host staging for moments
+  size_t pinned_count = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::string err;
+};
+
+namespace {
+
+using namespace mcp;
+
+mc_status fail(mc_context* ctx, mc_status st, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                                \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? MC_ERR_OOM : MC_ERR_DEVICE, "%s: %s", \
+                  #expr, hipGetErrorString(e_));                                          \
+  } while (0)
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
+
+mc_options defaults() {
+  mc_options o;
+  mc_options_default(&o);
+  return o;
+}
+
+mc_status validate_common(mc_context* ctx, const mc_model* m, const mc_payoff* f,
+                          uint64_t n_paths, uint32_t n_steps) {
+  if (!m || !f) return fail(ctx, MC_ERR_INVALID_ARG, "model and payoff must not be NULL");
+  if (n_paths < 2) return fail(ctx, MC_ERR_INVALID_ARG, "n_paths must be >= 2");
+  if (n_steps == 0) return fail(ctx, MC_ERR_INVALID_ARG, "n_steps must be >= 1");
+  if (n_paths > (1ull << 36)) return fail(ctx, MC_ERR_INVALID_ARG, "n_paths above 2^36");
+  if (!finite_pos(m->T)) return fail(ctx, MC_ERR_INVALID_ARG, "T must be finite and > 0");
+  if (!std::isfinite(m->r)) return fail(ctx, MC_ERR_INVALID_ARG, "r must be finite");
+  if (!finite_nonneg(f->K)) return fail(ctx, MC_ERR_INVALID_ARG, "K must be finite and >= 0");
+  if (m->dim == 0 || !m->S0) return fail(ctx, MC_ERR_INVALID_ARG, "S0 missing");
+  for (uint32_t a = 0; a < m->dim; ++a)
+    if (!finite_pos(m->S0[a])) return fail(ctx, MC_ERR_INVALID_ARG, "S0[%u] must be > 0", a);
+  return MC_OK;
+}
+
+mc_status validate_gbm(mc_context* ctx, const mc_model* m, const mc_payoff* f,
+                       const mc_options& o) {
+  if (m->dim != 1) return fail(ctx, MC_ERR_INVALID_ARG, "MC_GBM needs dim == 1");
+  if (!m->sigma || !finite_nonneg(m->sigma[0]))
+    return fail(ctx, MC_ERR_INVALID_ARG, "sigma must be finite and >= 0");
+  if (m->scheme != MC_LOG_EULER && m->scheme != MC_EULER_S)
+    return fail(ctx, MC_ERR_INVALID_ARG, "unknown scheme");
+  const bool barrier = f->kind == MC_UO_BARRIER_CALL || f->kind == MC_UO_BRIDGE_CALL;
+  if (barrier && !(std::isfinite(f->B) && f->B > m->S0[0]))
+    return fail(ctx, MC_ERR_INVALID_ARG, "barrier must be finite and above S0");
+  if (o.prec != MC_FP32 && o.prec != MC_FP64)
+    return fail(ctx, MC_ERR_UNSUPPORTED, "GBM paths run in MC_FP32 or MC_FP64");
+  return MC_OK;
+}
+
+mc_status validate_heston(mc_context* ctx, const mc_model* m, const mc_options& o) {
+  if (m->dim != 1) return fail(ctx, MC_ERR_INVALID_ARG, "MC_HESTON needs dim == 1");
+  if (!finite_nonneg(m->v0) || !finite_nonneg(m->kappa) || !finite_nonneg(m->theta) ||
+      !finite_nonneg(m->xi))
+    return fail(ctx, MC_ERR_INVALID_ARG, "v0, kappa, theta, xi must be finite and >= 0");
+  if (!(std::isfinite(m->rho) && std::fabs(m->rho) < 1.0))
+    return fail(ctx, MC_ERR_INVALID_ARG, "|rho| must be < 1");
+  if (o.prec != MC_FP32 && o.prec != MC_FP64)
+    return fail(ctx, MC_ERR_UNSUPPORTED, "Heston paths run in MC_FP32 or MC_FP64");
+  return MC_OK;
+}
+
+uint32_t gbm_want_mask(const mc_payoff* f, const mc_options& o, mc_status* st);
+
+// Every check of mc_price, no device access.
+mc_status validate_all(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint64_t n_paths,
+                       uint32_t n_steps, const mc_options& o) {
+  mc_status st = validate_common(ctx, m, f, n_paths, n_steps);
+  if (st != MC_OK) return st;
+  if (o.cv_hedge_every == 0) return fail(ctx, MC_ERR_INVALID_ARG, "cv_hedge_every must be >= 1");
+  if (m->kind == MC_GBM) {
+    st = validate_gbm(ctx, m, f, o);
+    if (st != MC_OK) return st;
+    (void)gbm_want_mask(f, o, &st);
+    if (st != MC_OK) return fail(ctx, st, "pathwise greeks need a continuous payoff");
+    if (f->cv == MC_CV_LEARNED) return fail(ctx, MC_ERR_UNSUPPORTED, "learned CV is Heston-only");
+    if (f->cv == MC_CV_GEO_ASIAN && f->kind != MC_ASIAN_ARITH_CALL)
+      return fail(ctx, MC_ERR_UNSUPPORTED, "geometric CV applies to the arithmetic Asian");
+    if (f->cv == MC_CV_GEO_ASIAN && m->scheme != MC_LOG_EULER)
+      return fail(ctx, MC_ERR_UNSUPPORTED, "geometric-Asian CV needs the log-Euler scheme");
+    if (f->kind == MC_UO_BRIDGE_CALL && m->scheme != MC_LOG_EULER)
+      return fail(ctx, MC_ERR_UNSUPPORTED, "Brownian-bridge barrier needs the log-Euler scheme");
+    return MC_OK;
+  }
+  if (m->kind == MC_HESTON) {
+    st = validate_heston(ctx, m, o);
+    if (st != MC_OK) return st;
+    if (f->kind != MC_EURO_CALL && f->kind != MC_ASIAN_ARITH_CALL)
+      return fail(ctx, MC_ERR_UNSUPPORTED, "Heston offers the European and arithmetic-Asian call");
+    if (f->cv == MC_CV_GEO_ASIAN)
+      return fail(ctx, MC_ERR_UNSUPPORTED, "geometric CV is GBM-only");
+    if (o.greeks && o.prec != MC_FP32)
+      return fail(ctx, MC_ERR_UNSUPPORTED, "adjoint greeks run in MC_FP32");
+    return MC_OK;
+  }
+  if (m->kind == MC_GBM_BASKET) return fail(ctx, MC_ERR_UNSUPPORTED, "basket not built yet");
+  return fail(ctx, MC_ERR_INVALID_ARG, "unknown model kind");
+}
+
+// Device workspace: the caller's, or the context's (grown on demand).
+mc_status get_ws(mc_context* ctx, const mc_options& o, size_t bytes, char** base) {
+  if (o.workspace) {
+    if (o.workspace_bytes < bytes)
+      return fail(ctx, MC_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", o.workspace_bytes,
+                  bytes);
+    *base = (char*)o.workspace;
+    return MC_OK;
+  }
+  if (ctx->ws_bytes < bytes) {
+    if (ctx->ws) {
+      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      HIP_TRY(ctx, hipFree(ctx->ws));
+      ctx->ws = nullptr;
+      ctx->ws_bytes = 0;
+    }
+    size_t want = bytes < (1u << 20) ? (1u << 20) : bytes;
+    HIP_TRY(ctx, hipMalloc(&ctx->ws, want));
+    ctx->ws_bytes = want;
+  }
+  *base = (char*)ctx->ws;
+  return MC_OK;
+}
+
+mc_status get_pinned(mc_context* ctx, size_t count) {
+  if (ctx->pinned_count >= count) return MC_OK;
+  if (ctx->pinned) HIP_TRY(ctx, hipHostFree(ctx->pinned));
+  ctx->pinned = nullptr;
+  ctx->pinned_count = 0;
+  size_t want = count < 4096 ? 4096 : count;
+  HIP_TRY(ctx, hipHostMalloc((void**)&ctx->pinned, want * sizeof(double), hipHostMallocDefault));
+  ctx->pinned_count = want;
+  return MC_OK;
+}
+
+hipStream_t stream_of(mc_context* ctx, const mc_options& o) {
+  return o.hip_stream ? (hipStream_t)o.hip_stream : ctx->stream;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Sizes of one moment run.
+struct RunLayout {
+  uint32_t n_blocks, n_mom, C;
+  size_t off_mom, off_path, bytes;
+};
+
+RunLayout layout_for(uint64_t n_paths, int C, bool want_path) {
+  RunLayout L;
+  L.n_blocks = (uint32_t)((n_paths + kBlock - 1) / kBlock);
+  L.C = (uint32_t)C;
+  L.n_mom = (uint32_t)n_moments(C);
+  L.off_mom = align256((size_t)L.n_mom * L.n_blocks * sizeof(double));
+  L.off_path = L.off_mom + align256((size_t)L.n_mom * sizeof(double));
+  L.bytes = L.off_path + (want_path ? align256((size_t)n_paths * C * sizeof(double)) : 0);
+  return L;
+}
+
+// Result of one moment run: n, means and covariances of C channels.
+struct Moments {
+  int C = 0;
+  double n = 0, nonfinite = 0;
+  std::vector<double> sum, cross;  // cross in upper-triangular row order
+  double mean(int c) const { return sum[c] / n; }
+  double cov(int a, int b) const {
+    if (a > b) std::swap(a, b);
+    int idx = 0;
+    for (int i = 0; i < a; ++i) idx += C - i;
+    idx += b - a;
+    return (cross[idx] - sum[a] * sum[b] / n) / (n - 1.0);
+  }
+};
+
+// Launch wrapper: runs `launch` (which enqueues the path kernel), then the
+// final reduction, and brings the moments to the host.
+template <typename F>
+mc_status run_moments(mc_context* ctx, const mc_options& o, uint64_t n_paths, int C,
+                      double* host_path_values, F&& launch, Moments* out, double* kernel_ms) {
+  const RunLayout L = layout_for(n_paths, C, host_path_values != nullptr);
+  char* base = nullptr;
+  mc_status st = get_ws(ctx, o, L.bytes, &base);
+  if (st != MC_OK) return st;
+  st = get_pinned(ctx, L.n_mom);
+  if (st != MC_OK) return st;
+  hipStream_t s = stream_of(ctx, o);
+  double* partials = (double*)base;
+  double* mom = (double*)(base + L.off_mom);
+  double* path_out = host_path_values ? (double*)(base + L.off_path) : nullptr;
+  HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
+  uint32_t nb = 0;
+  HIP_TRY(ctx, launch(partials, path_out, s, &nb));
+  HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));
+  if (nb != L.n_blocks) return fail(ctx, MC_ERR_DEVICE, "block count mismatch");
+  HIP_TRY(ctx, launch_final_reduce(partials, nb, L.n_mom, mom, s));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, mom, L.n_mom * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (path_out)
+    HIP_TRY(ctx, hipMemcpyAsync(host_path_values, path_out, n_paths * C * sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  float ms = 0.f;
+  HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  if (kernel_ms) *kernel_ms += ms;
+  out->C = C;
+  out->n = ctx->pinned[0];
+  out->nonfinite = ctx->pinned[1];
+  out->sum.assign(ctx->pinned + 2, ctx->pinned + 2 + C);
+  out->cross.assign(ctx->pinned + 2 + C, ctx->pinned + L.n_mom);
+  if (out->n < 2) return fail(ctx, MC_ERR_DEVICE, "fewer than two finite paths");
+  return MC_OK;
+}
+
+void fill_channel(const Moments& m, int c, double* price, double* var, double* se) {
+  *price = m.mean(c);
+  *var = m.cov(c, c);
+  *se = std::sqrt(*var / m.n);
+}
+
+// ---------------------------------------------------------------- GBM ----
+uint32_t gbm_want_mask(const mc_payoff* f, const mc_options& o, mc_status* st) {
+  *st = MC_OK;
+  const bool greeks = o.greeks != 0;
+  switch (f->kind) {
+    case MC_EURO_CALL:
+      return G_EURO | (greeks ? G_EURO_G : 0);
+    case MC_ASIAN_ARITH_CALL:
+      return G_ASIAN | (f->cv == MC_CV_GEO_ASIAN ? G_GEO : 0) | (greeks ? G_ASIAN_G : 0);
+    case MC_ASIAN_GEO_CALL:
+      if (greeks) *st = MC_ERR_UNSUPPORTED;
+      return G_GEO;
+    case MC_UO_BARRIER_CALL:
+      if (greeks) *st = MC_ERR_UNSUPPORTED;
+      return G_UO;
+    case MC_UO_BRIDGE_CALL:
+      if (greeks) *st = MC_ERR_UNSUPPORTED;
+      return G_UOBB;
+    default:
+      *st = MC_ERR_UNSUPPORTED;
+      return 0;
+  }
+}
+
+// Channel index of functional `bit` (and its second greek) inside `mask`.
+int gbm_channel_index(uint32_t mask, uint32_t bit) {
+  int c = 0;
+  for (uint32_t b = 1; b <= G_ASIAN_G; b <<= 1) {
+    if (b == bit) return (mask & b) ? c : -1;
+    if (mask & b) c += (b == G_EURO_G || b == G_ASIAN_G) ? 2 : 1;
+  }
+  return -1;
+}
+
+const char* gbm_channel_name(uint32_t mask, uint32_t i) {
+  static const char* names[] = {"euro",       "asian",     "geo",         "uo",        "uo_bridge",
+                                "euro_delta", "euro_vega", "asian_delta", "asian_vega"};
+  int c = 0, slot = 0;
+  for (uint32_t b = 1; b <= G_ASIAN_G; b <<= 1) {
+    const int w = (b == G_EURO_G || b == G_ASIAN_G) ? 2 : 1;
+    if (mask & b) {
+      if ((uint32_t)c == i) return names[slot];
+      if (w == 2 && (uint32_t)c + 1 == i) return names[slot + 1];
+      c += w;
+    }
+    slot += w;
+  }
+  return nullptr;
+}
+
+GbmParams gbm_params(const mc_model* m, const mc_payoff* f, uint64_t n_paths, uint32_t n_steps,
+                     uint64_t seed, const mc_options& o, bool fp64, uint32_t tag) {
+  GbmParams p{};
+  const double S0 = m->S0[0], sig = m->sigma[0], r = m->r, T = m->T;
+  const double dt = T / n_steps;
+  const double sc = fp64 ? 1.0 : 1.0 / std::log(2.0);   // log domain of the kernel
+  p.n_paths = n_paths;
+  p.path_offset = o.path_offset;
+  p.n_steps = n_steps;
+  p.tag = tag;
+  p.k0 = (uint32_t)seed;
+  p.k1 = (uint32_t)(seed >> 32);
+  p.log_scheme = m->scheme == MC_LOG_EULER;
+  p.S0 = S0;
+  p.K = f->K;
+  p.disc = std::exp(-r * T);
+  p.T = T;
+  p.dt = dt;
+  p.sdt = std::sqrt(dt);
+  p.sigma = sig;
+  p.drift_dom = (r - 0.5 * sig * sig) * dt * sc;
+  p.vol_dom = sig * std::sqrt(dt) * sc;
+  const double B = (std::isfinite(f->B) && f->B > 0) ? f->B : 1e300;
+  p.barrier_dom = std::log(B / S0) * sc;
+  p.bridge_c = 2.0 * dt * sig * sig * (fp64 ? 1.0 : 1.0 / std::log(2.0));
+  p.r_dt = r * dt;
+  p.vol_sdt = sig * std::sqrt(dt);
+  p.barrier_rel = B / S0;
+  return p;
+}
+
+mc_status gbm_run(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint64_t n_paths,
+                  uint32_t n_steps, uint64_t seed, const mc_options& o, uint32_t want,
+                  uint32_t tag, double* path_values, Moments* mom, uint32_t* mask_used,
+                  double* kernel_ms) {
+  const bool fp64 = o.prec == MC_FP64;
+  const bool logs = m->scheme == MC_LOG_EULER;
+  const uint32_t mask = gbm_pick_mask(want, fp64, logs);
+  if (!mask) return fail(ctx, MC_ERR_UNSUPPORTED, "payoff not available for this scheme/precision");
+  *mask_used = mask;
+  GbmParams p = gbm_params(m, f, n_paths, n_steps, seed, o, fp64, tag);
+  return run_moments(ctx, o, n_paths, gbm_channels(mask), path_values,
+                     [&](double* partials, double* path_out, hipStream_t s, uint32_t* nb) {
+                       p.partials = partials;
+                       p.path_out = path_out;
+                       return launch_gbm(p, mask, fp64, s, nb);
+                     },
+                     mom, kernel_ms);
+}
+
+// Fills `out` for one GBM payoff from the moments of a run.
+mc_status gbm_result(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint32_t n_steps,
+                     uint64_t seed, const mc_options& o, uint32_t mask, const Moments& mom,
+                     double kernel_ms, uint64_t n_paths, mc_result* out) {
+  mc_result r{};
+  uint32_t bit = 0, gbit = 0;
+  switch (f->kind) {
+    case MC_EURO_CALL: bit = G_EURO; gbit = G_EURO_G; break;
+    case MC_ASIAN_ARITH_CALL: bit = G_ASIAN; gbit = G_ASIAN_G; break;
+    case MC_ASIAN_GEO_CALL: bit = G_GEO; break;
+    case MC_UO_BARRIER_CALL: bit = G_UO; break;
+    case MC_UO_BRIDGE_CALL: bit = G_UOBB; break;
+    default: return fail(ctx, MC_ERR_UNSUPPORTED, "payoff not offered for GBM");
+  }
+  const int c = gbm_channel_index(mask, bit);
+  fill_channel(mom, c, &r.price, &r.variance, &r.std_err);
+  r.plain_price = r.price;
+  r.plain_std_err = r.std_err;
+  r.cv_beta = 0.0;
+  r.vrf = 1.0;
+  if (o.greeks && gbit) {
+    const int g = gbm_channel_index(mask, gbit);
+    double v;
+    if (o.greeks & MC_GREEK_DELTA) fill_channel(mom, g, &r.delta, &v, &r.delta_se);
+    if (o.greeks & MC_GREEK_VEGA) fill_channel(mom, g + 1, &r.vega, &v, &r.vega_se);
+  }
+  if (f->kind == MC_ASIAN_ARITH_CALL && f->cv == MC_CV_GEO_ASIAN) {
+    if (m->scheme != MC_LOG_EULER)
+      return fail(ctx, MC_ERR_UNSUPPORTED, "geometric-Asian CV needs the log-Euler scheme");
+    const int a = c, gi = gbm_channel_index(mask, G_GEO);
+    double beta = o.cv_beta;
+    if (!std::isfinite(beta)) {
+      // Pilot on stream tag+1 (independent of the main paths).
+      Moments pm;
+      uint32_t pmask;
+      mc_options po = o;
+      po.path_offset = 0;
+      const uint64_t np = o.pilot_paths ? o.pilot_paths : (1ull << 16);
+      mc_status st = gbm_run(ctx, m, f, np, n_steps, seed, po, G_ASIAN | G_GEO, o.stream_tag + 1,
+                             nullptr, &pm, &pmask, nullptr);
+      if (st != MC_OK) return st;
+      const int pa = gbm_channel_index(pmask, G_ASIAN), pg = gbm_channel_index(pmask, G_GEO);
+      beta = pm.cov(pa, pg) / pm.cov(pg, pg);
+    }
+    const double CG = host::geo_asian_call(m->S0[0], f->K, m->r, m->sigma[0], m->T, n_steps);
+    r.price = mom.mean(a) - beta * (mom.mean(gi) - CG);
+    r.variance = mom.cov(a, a) - 2.0 * beta * mom.cov(a, gi) + beta * beta * mom.cov(gi, gi);
+    r.std_err = std::sqrt(r.variance / mom.n);
+    r.cv_beta = beta;
+    r.vrf = mom.cov(a, a) / r.variance;
+  }
+  r.n_paths = (uint64_t)mom.n;
+  r.n_nonfinite = (uint64_t)mom.nonfinite;
+  r.kernel_ms = kernel_ms;
+  (void)seed;
+  (void)n_paths;
+  *out = r;
+  return MC_OK;
+}
+
+// ------------------------------------------------------------- Heston ----
+HestonParams heston_params(const mc_model* m, const mc_payoff* f, uint64_t n_paths,
+                           uint32_t n_steps, uint64_t seed, const mc_options& o, uint32_t tag) {
+  HestonParams p{};
+  p.n_paths = n_paths;
+  p.path_offset = o.path_offset;
+  p.n_steps = n_steps;
+  p.tag = tag;
+  p.k0 = (uint32_t)seed;
+  p.k1 = (uint32_t)(seed >> 32);
+  p.S0 = m->S0[0];
+  p.K = f->K;
+  p.disc = std::exp(-m->r * m->T);
+  p.dt = m->T / n_steps;
+  p.sdt = std::sqrt(p.dt);
+  p.r = m->r;
+  p.v0 = m->v0;
+  p.kappa = m->kappa;
+  p.theta = m->theta;
+  p.xi = m->xi;
+  p.rho = m->rho;
+  p.rho_c = std::sqrt(1.0 - m->rho * m->rho);
+  return p;
+}
+
+mc_status heston_price(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint64_t n_paths,
+                       uint32_t n_steps, uint64_t seed, const mc_options& o, mc_result* out) {
+  if (f->cv != MC_CV_NONE) return fail(ctx, MC_ERR_UNSUPPORTED, "control variate not available");
+  if (o.greeks) {
+    return mc_greeks_adjoint(ctx, m, f, n_paths, n_steps, seed, &o, MC_ADJ_FULL, mcp::kCkpt,
+                             nullptr, 0, 1.0, out);
+  }
+  const bool fp64 = o.prec == MC_FP64;
+  HestonParams p = heston_params(m, f, n_paths, n_steps, seed, o, o.stream_tag);
+  Moments mom;
+  double kms = 0.0;
+  mc_status st = run_moments(ctx, o, n_paths, 2, o.path_values,
+                             [&](double* partials, double* path_out, hipStream_t s, uint32_t* nb) {
+                               p.partials = partials;
+                               p.path_out = path_out;
+                               return launch_heston(p, H_EURO | H_ASIAN, fp64, s, nb);
+                             },
+                             &mom, &kms);
+  if (st != MC_OK) return st;
+  mc_result r{};
+  const int c = f->kind == MC_EURO_CALL ? 0 : 1;
+  fill_channel(mom, c, &r.price, &r.variance, &r.std_err);
+  r.plain_price = r.price;
+  r.plain_std_err = r.std_err;
+  r.vrf = 1.0;
+  r.n_paths = (uint64_t)mom.n;
+  r.n_nonfinite = (uint64_t)mom.nonfinite;
+  r.kernel_ms = kms;
+  *out = r;
+  return MC_OK;
+}
+
+}  // namespace
+
+// ================================================================ C ABI ===
+extern "C" {
+
+void mc_options_default(mc_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->prec = MC_FP32;
+  o->cv_hedge_every = 1;
+  o->cv_beta = std::nan("");
+}
+
+mc_status mc_create(mc_context** out, int device) {
+  if (!out) return MC_ERR_INVALID_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return MC_ERR_NO_DEVICE;
+  if (device < 0 || device >= n) return MC_ERR_NO_DEVICE;
+  mc_context* ctx = new mc_context();
+  ctx->device = device;
+  if (hipSetDevice(device) != hipSuccess || hipStreamCreate(&ctx->stream) != hipSuccess ||
+      hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
+    mc_destroy(ctx);
+    return MC_ERR_DEVICE;
+  }
+  *out = ctx;
+  return MC_OK;
+}
+
+mc_status mc_destroy(mc_context* ctx) {
+  if (!ctx) return MC_OK;
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+  if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return MC_OK;
+}
+
+const char* mc_status_str(mc_status st) {
+  switch (st) {
+    case MC_OK: return "MC_OK";
+    case MC_ERR_INVALID_ARG: return "MC_ERR_INVALID_ARG";
+    case MC_ERR_NOT_PD: return "MC_ERR_NOT_PD";
+    case MC_ERR_NO_DEVICE: return "MC_ERR_NO_DEVICE";
+    case MC_ERR_OOM: return "MC_ERR_OOM";
+    case MC_ERR_DEVICE: return "MC_ERR_DEVICE";
+    case MC_ERR_UNSUPPORTED: return "MC_ERR_UNSUPPORTED";
+    case MC_ERR_WORKSPACE: return "MC_ERR_WORKSPACE";
+  }
+  return "unknown mc_status";
+}
+
+const char* mc_last_error(const mc_context* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+uint32_t mc_path_channels(const mc_model* m, const mc_payoff* f, const mc_options* opts) {
+  if (!m || !f) return 0;
+  const mc_options o = opts ? *opts : defaults();
+  if (m->kind == MC_GBM) {
+    mc_status st;
+    const uint32_t want = gbm_want_mask(f, o, &st);
+    if (st != MC_OK) return 0;
+    const uint32_t mask = gbm_pick_mask(want, o.prec == MC_FP64, m->scheme == MC_LOG_EULER);
+    return mask ? (uint32_t)gbm_channels(mask) : 0;
+  }
+  if (m->kind == MC_HESTON) return o.greeks ? 3u : 2u;
+  return 0;
+}
+
+const char* mc_path_channel_name(const mc_model* m, const mc_payoff* f, const mc_options* opts,
+                                 uint32_t i) {
+  if (!m || !f) return nullptr;
+  const mc_options o = opts ? *opts : defaults();
+  if (m->kind == MC_GBM) {
+    mc_status st;
+    const uint32_t want = gbm_want_mask(f, o, &st);
+    if (st != MC_OK) return nullptr;
+    const uint32_t mask = gbm_pick_mask(want, o.prec == MC_FP64, m->scheme == MC_LOG_EULER);
+    return mask ? gbm_channel_name(mask, i) : nullptr;
+  }
+  if (m->kind == MC_HESTON) {
+    const bool asian = f->kind == MC_ASIAN_ARITH_CALL;
+    if (o.greeks) {
+      static const char* e[] = {"euro", "euro_delta", "euro_dv0"};
+      static const char* a[] = {"asian", "asian_delta", "asian_dv0"};
+      return i < 3 ? (asian ? a[i] : e[i]) : nullptr;
+    }
+    static const char* n[] = {"euro", "asian"};
+    return i < 2 ? n[i] : nullptr;
+  }
+  return nullptr;
+}
+
+size_t mc_workspace_bytes(const mc_model* m, const mc_payoff* f, uint64_t n_paths,
+                          uint32_t n_steps, const mc_options* opts) {
+  (void)n_steps;
+  if (!m || !f || n_paths < 2) return 0;
+  const mc_options o = opts ? *opts : defaults();
+  const uint32_t C = mc_path_channels(m, f, &o);
+  if (C == 0) return 0;
+  size_t bytes = layout_for(n_paths, (int)C, o.path_values != nullptr).bytes;
+  if (m->kind == MC_HESTON && o.greeks)
+    bytes = align256(bytes) + align256(mc_adjoint_ckpt_bytes(n_paths, n_steps, mcp::kCkpt));
+  return bytes;
+}
+
+mc_status mc_validate(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint64_t n_paths,
+                      uint32_t n_steps, const mc_options* opts) {
+  const mc_options o = opts ? *opts : defaults();
+  return validate_all(ctx, m, f, n_paths, n_steps, o);
+}
+
+mc_status mc_price(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint64_t n_paths,
+                   uint32_t n_steps, uint64_t seed, const mc_options* opts, mc_result* out) {
+  if (!ctx) return MC_ERR_INVALID_ARG;
+  const mc_options o = opts ? *opts : defaults();
+  mc_status st = validate_all(ctx, m, f, n_paths, n_steps, o);
+  if (st != MC_OK) return st;
+  if (!out) return fail(ctx, MC_ERR_INVALID_ARG, "out must not be NULL");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, MC_ERR_DEVICE, "hipSetDevice");
+  if (m->kind == MC_GBM) {
+    const uint32_t want = gbm_want_mask(f, o, &st);
+    Moments mom;
+    uint32_t mask = 0;
+    double kms = 0.0;
+    st = gbm_run(ctx, m, f, n_paths, n_steps, seed, o, want, o.stream_tag, o.path_values, &mom,
+                 &mask, &kms);
+    if (st != MC_OK) return st;
+    return gbm_result(ctx, m, f, n_steps, seed, o, mask, mom, kms, n_paths, out);
+  }
+  return heston_price(ctx, m, f, n_paths, n_steps, seed, o, out);
+}
+
+mc_status mc_price_multi(mc_context* ctx, const mc_model* m, const mc_payoff* fs, uint32_t nf,
+                         uint64_t n_paths, uint32_t n_steps, uint64_t seed, const mc_options* opts,
+                         mc_result* results) {
+  if (!ctx) return MC_ERR_INVALID_ARG;
+  if (!fs || nf == 0 || !results) return fail(ctx, MC_ERR_INVALID_ARG, "no payoffs");
+  mc_status st = validate_common(ctx, m, &fs[0], n_paths, n_steps);
+  if (st != MC_OK) return st;
+  const mc_options o = opts ? *opts : defaults();
+  if (m->kind != MC_GBM) return fail(ctx, MC_ERR_UNSUPPORTED, "mc_price_multi is GBM-only");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, MC_ERR_DEVICE, "hipSetDevice");
+  uint32_t want = 0;
+  for (uint32_t i = 0; i < nf; ++i) {
+    st = validate_gbm(ctx, m, &fs[i], o);
+    if (st != MC_OK) return st;
+    if (fs[i].cv == MC_CV_LEARNED) return fail(ctx, MC_ERR_UNSUPPORTED, "learned CV is Heston-only");
+    want |= gbm_want_mask(&fs[i], o, &st);
+    if (st != MC_OK) return fail(ctx, st, "pathwise greeks need a continuous payoff");
+  }
+  // Barrier levels must agree: one kernel monitors one barrier.
+  double B = NAN;
+  for (uint32_t i = 0; i < nf; ++i) {
+    if (fs[i].kind != MC_UO_BARRIER_CALL && fs[i].kind != MC_UO_BRIDGE_CALL) continue;
+    if (std::isnan(B)) B = fs[i].B;
+    else if (B != fs[i].B) return fail(ctx, MC_ERR_UNSUPPORTED, "one barrier level per call");
+  }
+  double Ks = fs[0].K;
+  for (uint32_t i = 1; i < nf; ++i)
+    if (fs[i].K != Ks) return fail(ctx, MC_ERR_UNSUPPORTED, "one strike per call");
+  mc_payoff merged = fs[0];
+  merged.B = std::isnan(B) ? fs[0].B : B;
+  Moments mom;
+  uint32_t mask = 0;
+  double kms = 0.0;
+  st = gbm_run(ctx, m, &merged, n_paths, n_steps, seed, o, want, o.stream_tag, o.path_values,
+               &mom, &mask, &kms);
+  if (st != MC_OK) return st;
+  std::vector<mc_result> tmp(nf);
+  for (uint32_t i = 0; i < nf; ++i) {
+    st = gbm_result(ctx, m, &fs[i], n_steps, seed, o, mask, mom, kms, n_paths, &tmp[i]);
+    if (st != MC_OK) return st;
+  }
+  for (uint32_t i = 0; i < nf; ++i) results[i] = tmp[i];
+  return MC_OK;
+}
+
+size_t mc_adjoint_ckpt_bytes(uint64_t n_paths, uint32_t n_steps, uint32_t ckpt_every) {
+  if (ckpt_every != (uint32_t)mcp::kCkpt || n_steps == 0) return 0;
+  const uint64_t n_ckpt = (n_steps + ckpt_every - 1) / ckpt_every;
+  return (size_t)(2 * n_ckpt + 1) * n_paths * sizeof(float);
+}
+
+mc_status mc_greeks_adjoint(mc_context* ctx, const mc_model* m, const mc_payoff* f,
+                            uint64_t n_paths, uint32_t n_steps, uint64_t seed,
+                            const mc_options* opts, mc_adjoint_phase phase, uint32_t ckpt_every,
+                            void* ckpt, size_t ckpt_bytes, double grad_out, mc_result* out) {
+  if (!ctx) return MC_ERR_INVALID_ARG;
+  mc_status st = validate_common(ctx, m, f, n_paths, n_steps);
+  if (st != MC_OK) return st;
+  if (!out) return fail(ctx, MC_ERR_INVALID_ARG, "out must not be NULL");
+  mc_options o = opts ? *opts : defaults();
+  if (m->kind != MC_HESTON)
+    return fail(ctx, MC_ERR_UNSUPPORTED, "the adjoint kernel covers the Heston model");
+  st = validate_heston(ctx, m, o);
+  if (st != MC_OK) return st;
+  if (f->kind != MC_EURO_CALL && f->kind != MC_ASIAN_ARITH_CALL)
+    return fail(ctx, MC_ERR_UNSUPPORTED, "adjoint for the European or arithmetic-Asian call");
+  if (ckpt_every != (uint32_t)mcp::kCkpt)
+    return fail(ctx, MC_ERR_UNSUPPORTED, "checkpoint period must be %d", mcp::kCkpt);
+  if (phase != MC_ADJ_FULL && phase != MC_ADJ_FWD && phase != MC_ADJ_REV)
+    return fail(ctx, MC_ERR_INVALID_ARG, "unknown phase");
+  if (!std::isfinite(grad_out)) return fail(ctx, MC_ERR_INVALID_ARG, "grad_out must be finite");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, MC_ERR_DEVICE, "hipSetDevice");
+  const size_t need = mc_adjoint_ckpt_bytes(n_paths, n_steps, ckpt_every);
+  const int C = phase == MC_ADJ_FULL ? 3 : phase == MC_ADJ_FWD ? 1 : 2;
+  const RunLayout L = layout_for(n_paths, C, o.path_values != nullptr);
+  float* ck = (float*)ckpt;
+  if (ck) {
+    if (ckpt_bytes < need)
+      return fail(ctx, MC_ERR_WORKSPACE, "checkpoint buffer has %zu bytes, %zu needed", ckpt_bytes,
+                  need);
+  } else {
+    if (phase != MC_ADJ_FULL)
+      return fail(ctx, MC_ERR_INVALID_ARG, "FWD/REV phases need a checkpoint buffer");
+    // Checkpoints after the moment workspace.
+    char* base = nullptr;
+    st = get_ws(ctx, o, align256(L.bytes) + align256(need), &base);
+    if (st != MC_OK) return st;
+    ck = (float*)(base + align256(L.bytes));
+    o.workspace = base;
+    o.workspace_bytes = align256(L.bytes);
+  }
+  AdjointParams a{};
+  a.h = heston_params(m, f, n_paths, n_steps, seed, o, o.stream_tag);
+  a.asian = f->kind == MC_ASIAN_ARITH_CALL;
+  a.phase = (int)phase;
+  a.ckpt = ck;
+  a.n_ckpt = (n_steps + mcp::kCkpt - 1) / mcp::kCkpt;
+  a.grad_out = grad_out;
+  Moments mom;
+  double kms = 0.0;
+  st = run_moments(ctx, o, n_paths, C, o.path_values,
+                   [&](double* partials, double* path_out, hipStream_t s, uint32_t* nb) {
+                     a.h.partials = partials;
+                     a.h.path_out = path_out;
+                     return launch_heston_adjoint(a, s, nb);
+                   },
+                   &mom, &kms);
+  if (st != MC_OK) return st;
+  mc_result r{};
+  double v;
+  if (phase != MC_ADJ_REV) {
+    fill_channel(mom, 0, &r.price, &r.variance, &r.std_err);
+    r.plain_price = r.price;
+    r.plain_std_err = r.std_err;
+  }
+  if (phase != MC_ADJ_FWD) {
+    const int g = phase == MC_ADJ_FULL ? 1 : 0;
+    fill_channel(mom, g, &r.delta, &v, &r.delta_se);
+    fill_channel(mom, g + 1, &r.vega, &v, &r.vega_se);
+    r.delta *= grad_out;
+    r.delta_se *= std::fabs(grad_out);
+    r.vega *= grad_out;
+    r.vega_se *= std::fabs(grad_out);
+  }
+  r.vrf = 1.0;
+  r.n_paths = (uint64_t)mom.n;
+  r.n_nonfinite = (uint64_t)mom.nonfinite;
+  r.kernel_ms = kms;
+  *out = r;
+  return MC_OK;
+}
+
+mc_status mc_cv_train(mc_context* ctx, const mc_model*, const mc_payoff*, uint64_t, uint32_t,
+                      uint64_t, const mc_adam_cfg*, float*, float*) {
+  return fail(ctx, MC_ERR_UNSUPPORTED, "learned control variate not built yet");
+}
+
+mc_status mc_cv_loss_grad(mc_context* ctx, const mc_model*, const mc_payoff*, uint32_t, uint64_t,
+                          uint32_t, uint64_t, uint64_t, const mc_adam_cfg*, const float*, double*,
+                          float*) {
+  return fail(ctx, MC_ERR_UNSUPPORTED, "learned control variate not built yet");
+}
+
+mc_status mc_philox_words(mc_context* ctx, uint64_t seed, uint32_t tag, uint64_t n,
+                          const uint64_t* paths, const uint64_t* blocks, uint32_t* out4) {
+  if (!ctx) return MC_ERR_INVALID_ARG;
+  if (n == 0) return MC_OK;
+  if (!paths || !blocks || !out4) return fail(ctx, MC_ERR_INVALID_ARG, "NULL array");
+  for (uint64_t i = 0; i < n; ++i)
+    if (blocks[i] > 0xffffffffull) return fail(ctx, MC_ERR_INVALID_ARG, "block index above 2^32");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, MC_ERR_DEVICE, "hipSetDevice");
+  mc_options o = defaults();
+  const size_t b_in = align256(n * sizeof(uint64_t));
+  char* base = nullptr;
+  mc_status st = get_ws(ctx, o, 2 * b_in + n * 16, &base);
+  if (st != MC_OK) return st;
+  uint64_t* dp = (uint64_t*)base;
+  uint64_t* db = (uint64_t*)(base + b_in);
+  uint32_t* dout = (uint32_t*)(base + 2 * b_in);
+  hipStream_t s = ctx->stream;
+  HIP_TRY(ctx, hipMemcpyAsync(dp, paths, n * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(ctx, hipMemcpyAsync(db, blocks, n * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(ctx, launch_philox_words((uint32_t)seed, (uint32_t)(seed >> 32), tag, n, dp, db, dout, s));
+  HIP_TRY(ctx, hipMemcpyAsync(out4, dout, n * 16, hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  return MC_OK;
+}
+
+mc_status mc_normals(mc_context* ctx, uint64_t seed, uint32_t tag, uint64_t path, uint64_t k0,
+                     uint64_t count, mc_precision prec, double* out) {
+  if (!ctx) return MC_ERR_INVALID_ARG;
+  if (count == 0) return MC_OK;
+  if (!out) return fail(ctx, MC_ERR_INVALID_ARG, "NULL output");
+  if (prec != MC_FP32 && prec != MC_FP64)
+    return fail(ctx, MC_ERR_UNSUPPORTED, "normals in MC_FP32 or MC_FP64");
+  if ((k0 + count - 1) / 4 > 0xffffffffull)
+    return fail(ctx, MC_ERR_INVALID_ARG, "normal index above 2^34");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, MC_ERR_DEVICE, "hipSetDevice");
+  mc_options o = defaults();
+  char* base = nullptr;
+  mc_status st = get_ws(ctx, o, count * sizeof(double), &base);
+  if (st != MC_OK) return st;
+  hipStream_t s = ctx->stream;
+  HIP_TRY(ctx, launch_normals((uint32_t)seed, (uint32_t)(seed >> 32), tag, path, k0, count,
+                              prec == MC_FP64, (double*)base, s));
+  HIP_TRY(ctx, hipMemcpyAsync(out, base, count * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  return MC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,55 @@
+// Block reduction of per-path values into per-block moment sums, the first
+// stage of the averaging reduction that ends every Monte Carlo estimate
+// (Eq. 3; the variance term of Sec. V-B needs the second moments).
+//
+// Each thread holds the C channel values of its path in double. The block
+// writes, for every moment m, one double to partials[m * n_blocks + block]:
+//   m = 0: number of valid paths, m = 1: number of non-finite paths,
+//   m = 2 .. C+1: sum of y_c, then sum of y_a * y_b for a <= b.
+// Wave sums use a fixed xor butterfly and the 4 wave sums are added in
+// wave order, so the result does not depend on scheduling.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace mcp {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <int C, int BLOCK>
+__device__ __forceinline__ void block_moments(const double (&y)[C], bool valid, bool nonfinite,
+                                              double* __restrict__ partials,
+                                              uint32_t n_blocks) {
+  constexpr int M = 2 + C + C * (C + 1) / 2;
+  constexpr int W = BLOCK / 64;
+  __shared__ double red[M][W];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  int m = 0;
+  auto push = [&](double v) {
+    v = wave_sum(v);
+    if (lane == 0) red[m][wave] = v;
+    ++m;
+  };
+  push(valid ? 1.0 : 0.0);
+  push(nonfinite ? 1.0 : 0.0);
+#pragma unroll
+  for (int a = 0; a < C; ++a) push(valid ? y[a] : 0.0);
+#pragma unroll
+  for (int a = 0; a < C; ++a)
+#pragma unroll
+    for (int b = a; b < C; ++b) push(valid ? y[a] * y[b] : 0.0);
+  __syncthreads();
+  for (int t = threadIdx.x; t < M; t += BLOCK) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) s += red[t][w];
+    partials[(size_t)t * n_blocks + blockIdx.x] = s;
+  }
+}
+
+}  // namespace mcp

@@ -1,0 +1,85 @@
+// Second stage of the averaging reduction (Eq. 3) and the diagnostic kernels
+// that expose the device random numbers for bit-exact checks.
+#include "device/rng.h"
+#include "mc_internal.h"
+
+namespace mcp {
+namespace {
+
+// One workgroup per moment: thread t adds blocks t, t+256, ... in order,
+// then a fixed-shape tree adds the 256 partial sums. Deterministic.
+__global__ __launch_bounds__(256) void final_reduce_kernel(const double* __restrict__ partials,
+                                                           uint32_t n_blocks,
+                                                           double* __restrict__ out) {
+  __shared__ double sh[256];
+  const uint32_t m = blockIdx.x;
+  const double* row = partials + (size_t)m * n_blocks;
+  double s = 0.0;
+  for (uint32_t i = threadIdx.x; i < n_blocks; i += 256) s += row[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[m] = sh[0];
+}
+
+__global__ void philox_words_kernel(uint32_t k0, uint32_t k1, uint32_t tag, uint64_t n,
+                                    const uint64_t* __restrict__ paths,
+                                    const uint64_t* __restrict__ blocks,
+                                    uint32_t* __restrict__ out) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const PathCounter pc = make_counter(paths[i], tag, k0, k1);
+  const Words4 w = philox((uint32_t)blocks[i], pc);
+  out[4 * i + 0] = w.w0;
+  out[4 * i + 1] = w.w1;
+  out[4 * i + 2] = w.w2;
+  out[4 * i + 3] = w.w3;
+}
+
+template <typename R>
+__global__ void normals_kernel(uint32_t k0, uint32_t k1, uint32_t tag, uint64_t path,
+                               uint64_t k_first, uint64_t count, double* __restrict__ out) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const uint64_t k = k_first + i;
+  const PathCounter pc = make_counter(path, tag, k0, k1);
+  const Normals4<R> nz = normals4<R>(philox((uint32_t)(k >> 2), pc));
+  out[i] = (double)nz.z[k & 3];
+}
+
+}  // namespace
+
+hipError_t launch_final_reduce(const double* partials, uint32_t n_blocks, uint32_t n_mom,
+                               double* out, hipStream_t s) {
+  hipLaunchKernelGGL(final_reduce_kernel, dim3(n_mom), dim3(256), 0, s, partials, n_blocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_philox_words(uint32_t k0, uint32_t k1, uint32_t tag, uint64_t n,
+                               const uint64_t* paths, const uint64_t* blocks, uint32_t* out,
+                               hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint32_t nb = (uint32_t)((n + 255) / 256);
+  hipLaunchKernelGGL(philox_words_kernel, dim3(nb), dim3(256), 0, s, k0, k1, tag, n, paths,
+                     blocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_normals(uint32_t k0, uint32_t k1, uint32_t tag, uint64_t path,
+                          uint64_t k_first, uint64_t count, bool fp64, double* out,
+                          hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  const uint32_t nb = (uint32_t)((count + 255) / 256);
+  if (fp64)
+    hipLaunchKernelGGL(normals_kernel<double>, dim3(nb), dim3(256), 0, s, k0, k1, tag, path,
+                       k_first, count, out);
+  else
+    hipLaunchKernelGGL(normals_kernel<float>, dim3(nb), dim3(256), 0, s, k0, k1, tag, path,
+                       k_first, count, out);
+  return hipGetLastError();
+}
+
+}  // namespace mcp

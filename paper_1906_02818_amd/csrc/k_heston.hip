@@ -1,0 +1,263 @@
+// Heston path kernels: full-truncation Euler on (ln S, v), the stochastic-
+// volatility form of the Euler-Maruyama scheme (Sec. I-A.1, Sec. II-A.1):
+//   v+ = max(v, 0)
+//   ln S += (r - v+/2) dt + sqrt(v+ dt) Zs,   Zs = rho Z1 + sqrt(1-rho^2) Z2
+//   v    += kappa (theta - v+) dt + xi sqrt(v+ dt) Z1
+// Step i uses normals 2i (Z1, the variance driver) and 2i+1 (Z2), so one
+// Philox block feeds two steps.
+//
+// Two kernels:
+//  - heston_price_kernel: European and arithmetic-Asian payoffs fused with
+//    the block moments (Eq. 3).
+//  - heston_adjoint_kernel: pathwise delta and d/dv0 by reverse-mode
+//    differentiation of the simulation (greeks by back-propagation,
+//    Sec. I-A.3). The forward sweep stores (ln S, v) every kCkpt steps; the
+//    reverse sweep takes the segments from last to first, recomputes each
+//    from its checkpoint (regenerating the normals from Philox) with the
+//    kCkpt intermediate states in registers, and back-propagates through it.
+#include "device/reduce.h"
+#include "device/rng.h"
+#include "mc_internal.h"
+
+namespace mcp {
+namespace {
+
+template <typename R>
+struct HDom;
+template <>
+struct HDom<float> {
+  static constexpr double kLogScale = 1.4426950408889634;  // ln S -> log2 S
+  static __device__ __forceinline__ float exp_(float z) { return __builtin_amdgcn_exp2f(z); }
+  static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+};
+template <>
+struct HDom<double> {
+  static constexpr double kLogScale = 1.0;
+  static __device__ __forceinline__ double exp_(double z) { return exp(z); }
+  static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+};
+
+// z = log(S/S0) in the kernel's domain, v the variance.
+template <typename R>
+struct HestonStep {
+  R a0, a1, a2, kdt, kthdt, xi, rho, rhoc, dt;
+
+  __device__ __forceinline__ void init(const HestonParams& P) {
+    const double sc = HDom<R>::kLogScale;
+    a0 = (R)(P.r * P.dt * sc);
+    a1 = (R)(-0.5 * P.dt * sc);
+    a2 = (R)sc;
+    kdt = (R)(P.kappa * P.dt);
+    kthdt = (R)(P.kappa * P.theta * P.dt);
+    xi = (R)P.xi;
+    rho = (R)P.rho;
+    rhoc = (R)P.rho_c;
+    dt = (R)P.dt;
+  }
+
+  __device__ __forceinline__ void step(R& z, R& v, R Z1, R Z2, R& Zs) const {
+    const R vp = v > R(0) ? v : R(0);
+    const R sq = HDom<R>::sqrt_(vp * dt);
+    Zs = rho * Z1 + rhoc * Z2;
+    z = z + (a0 + a1 * vp) + a2 * (sq * Zs);
+    v = v + (kthdt - kdt * vp) + xi * (sq * Z1);
+  }
+};
+
+template <typename R>
+__device__ __forceinline__ R posv(R x) {
+  return x > R(0) ? x : R(0);
+}
+
+template <typename R, uint32_t MASK>
+__global__ __launch_bounds__(kBlock) void heston_price_kernel(const HestonParams P) {
+  constexpr int C = popcount_c(MASK);
+  const uint64_t pid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool active = pid < P.n_paths;
+  double y[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) y[c] = 0.0;
+  if (active) {
+    HestonStep<R> hs;
+    hs.init(P);
+    const PathCounter pc = make_counter(P.path_offset + pid, P.tag, P.k0, P.k1);
+    R z = R(0), v = (R)P.v0, sumE = R(0), Zs;
+    const uint32_t n = P.n_steps;
+    for (uint32_t j = 0; 2 * j < n; ++j) {
+      const Normals4<R> nz = normals4<R>(philox(j, pc));
+      hs.step(z, v, nz.z[0], nz.z[1], Zs);
+      if constexpr ((MASK & H_ASIAN) != 0) sumE += HDom<R>::exp_(z);
+      if (2 * j + 1 < n) {
+        hs.step(z, v, nz.z[2], nz.z[3], Zs);
+        if constexpr ((MASK & H_ASIAN) != 0) sumE += HDom<R>::exp_(z);
+      }
+    }
+    const R S0 = (R)P.S0, K = (R)P.K, disc = (R)P.disc;
+    int c = 0;
+    if constexpr ((MASK & H_EURO) != 0) y[c++] = (double)(disc * posv(S0 * HDom<R>::exp_(z) - K));
+    if constexpr ((MASK & H_ASIAN) != 0) y[c++] = (double)(disc * posv(S0 * sumE / (R)n - K));
+  }
+  bool finite = true;
+#pragma unroll
+  for (int c = 0; c < C; ++c) finite = finite && isfinite(y[c]);
+  if (active && P.path_out != nullptr) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) P.path_out[pid * C + c] = y[c];
+  }
+  block_moments<C, kBlock>(y, active && finite, active && !finite, P.partials, gridDim.x);
+}
+
+// Channel sets of the adjoint phases.
+template <int PHASE>
+struct AdjC;
+template <>
+struct AdjC<0> { static constexpr int C = 3; };   // payoff, delta, d/dv0
+template <>
+struct AdjC<1> { static constexpr int C = 1; };   // payoff
+template <>
+struct AdjC<2> { static constexpr int C = 2; };   // delta, d/dv0
+
+// Checkpoint buffer (FP32): rows [2c] = z and [2c+1] = v at step c*kCkpt,
+// then one row with the terminal statistic (A/S0 for the Asian, S_T/S0
+// otherwise). Only the FP32 kernel is built: its state is FP32, so the
+// checkpoints are exact.
+template <typename R, int PHASE, bool ASIAN>
+__global__ __launch_bounds__(kBlock) void heston_adjoint_kernel(const AdjointParams A) {
+  constexpr int C = AdjC<PHASE>::C;
+  const HestonParams& P = A.h;
+  const uint64_t pid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool active = pid < P.n_paths;
+  const uint64_t np = P.n_paths;
+  double y[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) y[c] = 0.0;
+  if (active) {
+    HestonStep<R> hs;
+    hs.init(P);
+    const PathCounter pc = make_counter(P.path_offset + pid, P.tag, P.k0, P.k1);
+    const uint32_t n = P.n_steps;
+    const R S0 = (R)P.S0, K = (R)P.K, disc = (R)P.disc, inv_n = R(1) / (R)n;
+    R term;  // A/S0 (Asian) or S_T/S0
+    if (PHASE != 2) {
+      // Forward sweep with checkpoints.
+      R z = R(0), v = (R)P.v0, sumE = R(0), Zs;
+      for (uint32_t j = 0; 2 * j < n; ++j) {
+        const uint32_t i = 2 * j;
+        if (i % kCkpt == 0) {
+          const uint32_t c = i / kCkpt;
+          A.ckpt[(size_t)(2 * c) * np + pid] = (float)z;
+          A.ckpt[(size_t)(2 * c + 1) * np + pid] = (float)v;
+        }
+        const Normals4<R> nz = normals4<R>(philox(j, pc));
+        hs.step(z, v, nz.z[0], nz.z[1], Zs);
+        if (ASIAN) sumE += HDom<R>::exp_(z);
+        if (i + 1 < n) {
+          hs.step(z, v, nz.z[2], nz.z[3], Zs);
+          if (ASIAN) sumE += HDom<R>::exp_(z);
+        }
+      }
+      term = ASIAN ? sumE * inv_n : HDom<R>::exp_(z);
+      if (PHASE == 1) A.ckpt[(size_t)(2 * A.n_ckpt) * np + pid] = (float)term;
+      const R pay = disc * posv(S0 * term - K);
+      if (PHASE == 0) y[0] = (double)pay;
+      if (PHASE == 1) y[0] = (double)pay;
+    } else {
+      term = (R)A.ckpt[(size_t)(2 * A.n_ckpt) * np + pid];
+    }
+    if (PHASE != 1) {
+      // Reverse sweep. xb = dP/d(ln S_i), vb = dP/dv_i, natural-log units.
+      const bool itm = S0 * term > K;
+      // Asian: dP/d(ln S_i) = disc 1{A>K} S_i / n = abar * (S_i/S0).
+      const R abar = (ASIAN && itm) ? disc * S0 * inv_n : R(0);
+      R xb = (!ASIAN && itm) ? disc * S0 * term : R(0);
+      R vb = R(0);
+      const R dt = hs.dt, half_dt = R(0.5) * hs.dt, kdt = hs.kdt, xi = hs.xi;
+      const uint32_t n_seg = (n + kCkpt - 1) / kCkpt;
+      for (int seg = (int)n_seg - 1; seg >= 0; --seg) {
+        const uint32_t i0 = (uint32_t)seg * kCkpt;
+        const uint32_t len = min((uint32_t)kCkpt, n - i0);
+        // The checkpoint holds the FP32 state exactly, so the recomputed
+        // segment reproduces the forward sweep bit for bit.
+        R z = (R)A.ckpt[(size_t)(2 * seg) * np + pid];
+        R v = (R)A.ckpt[(size_t)(2 * seg + 1) * np + pid];
+        R vs[kCkpt], z1s[kCkpt], zss[kCkpt], Es[kCkpt];
+#pragma unroll
+        for (int q = 0; q < kCkpt; q += 2) {
+          if ((uint32_t)q < len) {
+            const Normals4<R> nz = normals4<R>(philox((i0 + (uint32_t)q) >> 1, pc));
+            vs[q] = v;
+            z1s[q] = nz.z[0];
+            hs.step(z, v, nz.z[0], nz.z[1], zss[q]);
+            Es[q] = HDom<R>::exp_(z);
+            if ((uint32_t)q + 1 < len) {
+              vs[q + 1] = v;
+              z1s[q + 1] = nz.z[2];
+              hs.step(z, v, nz.z[2], nz.z[3], zss[q + 1]);
+              Es[q + 1] = HDom<R>::exp_(z);
+            }
+          }
+        }
+#pragma unroll
+        for (int q = kCkpt - 1; q >= 0; --q) {
+          if ((uint32_t)q < len) {
+            if (ASIAN) xb += abar * Es[q];          // S_{i+1} enters the average
+            const R vq = vs[q];
+            if (vq > R(0)) {
+              const R sq = HDom<R>::sqrt_(vq * dt);
+              const R g = half_dt / sq;               // d sqrt(v dt) / dv
+              const R dxdv = -half_dt + zss[q] * g;
+              const R dvdv = (R(1) - kdt) + xi * z1s[q] * g;
+              vb = xb * dxdv + vb * dvdv;
+            }
+          }
+        }
+      }
+      const int c0 = PHASE == 0 ? 1 : 0;
+      y[c0] = (double)(xb / S0);   // d/dS0 through ln S0
+      y[c0 + 1] = (double)vb;      // d/dv0
+    }
+  }
+  bool finite = true;
+#pragma unroll
+  for (int c = 0; c < C; ++c) finite = finite && isfinite(y[c]);
+  if (active && P.path_out != nullptr) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) P.path_out[pid * C + c] = y[c];
+  }
+  block_moments<C, kBlock>(y, active && finite, active && !finite, P.partials, gridDim.x);
+}
+
+}  // namespace
+
+hipError_t launch_heston(const HestonParams& p, uint32_t mask, bool fp64, hipStream_t s,
+                         uint32_t* n_blocks) {
+  const uint32_t nb = (uint32_t)((p.n_paths + kBlock - 1) / kBlock);
+  *n_blocks = nb;
+  constexpr uint32_t EA = H_EURO | H_ASIAN;
+  if (mask != EA) return hipErrorInvalidValue;
+  if (fp64)
+    hipLaunchKernelGGL((heston_price_kernel<double, EA>), dim3(nb), dim3(kBlock), 0, s, p);
+  else
+    hipLaunchKernelGGL((heston_price_kernel<float, EA>), dim3(nb), dim3(kBlock), 0, s, p);
+  return hipGetLastError();
+}
+
+template <typename R, int PH, bool AS>
+static hipError_t adj_one(const AdjointParams& a, hipStream_t s, uint32_t nb) {
+  hipLaunchKernelGGL((heston_adjoint_kernel<R, PH, AS>), dim3(nb), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_heston_adjoint(const AdjointParams& a, hipStream_t s, uint32_t* n_blocks) {
+  const uint32_t nb = (uint32_t)((a.h.n_paths + kBlock - 1) / kBlock);
+  *n_blocks = nb;
+  const bool as = a.asian != 0;
+  switch (a.phase) {
+    case 0: return as ? adj_one<float, 0, true>(a, s, nb) : adj_one<float, 0, false>(a, s, nb);
+    case 1: return as ? adj_one<float, 1, true>(a, s, nb) : adj_one<float, 1, false>(a, s, nb);
+    case 2: return as ? adj_one<float, 2, true>(a, s, nb) : adj_one<float, 2, false>(a, s, nb);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace mcp

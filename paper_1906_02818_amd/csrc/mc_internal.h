@@ -1,0 +1,90 @@
+// Internal interface between the C ABI (api.hip) and the kernel translation
+// units. Host-side declarations only; no torch types anywhere.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mcp {
+
+constexpr int kBlock = 256;          // threads per path-kernel workgroup (4 waves)
+
+// ---- GBM path functionals (bit mask -> per-path channels, in bit order) ----
+enum : uint32_t {
+  G_EURO = 1u << 0,     // "euro"
+  G_ASIAN = 1u << 1,    // "asian"
+  G_GEO = 1u << 2,      // "geo"
+  G_UO = 1u << 3,       // "uo"
+  G_UOBB = 1u << 4,     // "uo_bridge"
+  G_EURO_G = 1u << 5,   // "euro_delta", "euro_vega"
+  G_ASIAN_G = 1u << 6,  // "asian_delta", "asian_vega"
+  G_ALL = 0x7Fu
+};
+
+__host__ __device__ constexpr int popcount_c(uint32_t m) {
+  return m == 0 ? 0 : (int)(m & 1u) + popcount_c(m >> 1);
+}
+__host__ __device__ constexpr int gbm_channels(uint32_t mask) {
+  return popcount_c(mask & 0x1Fu) + 2 * popcount_c(mask & 0x60u);
+}
+// Moments per block: [n_valid, n_nonfinite, sum y_c (C), sum y_a y_b (a<=b)].
+__host__ __device__ constexpr int n_moments(int C) { return 2 + C + C * (C + 1) / 2; }
+
+struct GbmParams {
+  uint64_t n_paths, path_offset;
+  uint32_t n_steps, tag, k0, k1;
+  int log_scheme;
+  // Model constants, double on the host; kernels round them to their type.
+  double S0, K, disc, T, dt, sdt, sigma;
+  // Log scheme, in the kernel's log domain (log2 for FP32, ln for FP64):
+  double drift_dom, vol_dom, barrier_dom, bridge_c;
+  // Euler on S: increments of S/S0.
+  double r_dt, vol_sdt, barrier_rel;
+  double* partials;   // [n_moments][n_blocks]
+  double* path_out;   // [n_paths][C] or nullptr
+};
+
+// Launches the GBM path kernel for the instantiated mask `mask` (must be one
+// returned by gbm_pick_mask). Returns the number of blocks via *n_blocks.
+hipError_t launch_gbm(const GbmParams& p, uint32_t mask, bool fp64, hipStream_t s,
+                      uint32_t* n_blocks);
+// Smallest instantiated mask containing `want` for this precision/scheme,
+// or 0 when none does.
+uint32_t gbm_pick_mask(uint32_t want, bool fp64, bool log_scheme);
+
+// ---- Heston ----
+enum : uint32_t { H_EURO = 1u << 0, H_ASIAN = 1u << 1 };
+
+struct HestonParams {
+  uint64_t n_paths, path_offset;
+  uint32_t n_steps, tag, k0, k1;
+  double S0, K, disc, dt, sdt, r, v0, kappa, theta, xi, rho, rho_c;
+  double* partials;
+  double* path_out;
+};
+hipError_t launch_heston(const HestonParams& p, uint32_t mask, bool fp64, hipStream_t s,
+                         uint32_t* n_blocks);
+
+// Pathwise adjoint (reverse sweep with checkpoints every kCkpt steps).
+constexpr int kCkpt = 16;
+struct AdjointParams {
+  HestonParams h;
+  int asian;            // 1: arithmetic-Asian call, 0: European call
+  int phase;            // 0 full, 1 forward (write checkpoints), 2 reverse
+  float* ckpt;          // [n_ckpt][3][n_paths]
+  uint32_t n_ckpt;
+  double grad_out;
+};
+hipError_t launch_heston_adjoint(const AdjointParams& p, hipStream_t s, uint32_t* n_blocks);
+
+// ---- reductions and diagnostics ----
+hipError_t launch_final_reduce(const double* partials, uint32_t n_blocks, uint32_t n_mom,
+                               double* out, hipStream_t s);
+hipError_t launch_philox_words(uint32_t k0, uint32_t k1, uint32_t tag, uint64_t n,
+                               const uint64_t* paths, const uint64_t* blocks, uint32_t* out,
+                               hipStream_t s);
+hipError_t launch_normals(uint32_t k0, uint32_t k1, uint32_t tag, uint64_t path,
+                          uint64_t k_first, uint64_t count, bool fp64, double* out,
+                          hipStream_t s);
+
+}  // namespace mcp

@@ -1,0 +1,131 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry
+point include/mcpath.h declares, and rejects bad arguments before touching a
+device. No kernel runs here."""
+import ctypes as C
+import math
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_1906_02818_amd as mc
+from paper_1906_02818_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def built():
+    if not os.path.exists(_abi.LIB_PATH):
+        from paper_1906_02818_amd import build as b
+        b.build()
+
+
+def test_library_exports_every_header_symbol():
+    lib = _abi.load()
+    names = _abi.header_symbols()
+    assert "mc_price" in names and "mc_greeks_adjoint" in names and "mc_cv_train" in names
+    out = subprocess.run(["nm", "-D", "--defined-only", _abi.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if ln.strip()}
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        getattr(lib, n)
+    # ctypes signatures cover the header.
+    assert set(names) == set(_abi.SIGNATURES), set(names) ^ set(_abi.SIGNATURES)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    # Compile a tiny C program against the header and compare sizeof/offsetof.
+    src = str(tmp_path / "abi_layout.c")
+    with open(src, "w") as f:
+        f.write('#include <stdio.h>\n#include <stddef.h>\n#include "mcpath.h"\n'
+                'int main(){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(mc_model), '
+                'sizeof(mc_payoff), sizeof(mc_options), sizeof(mc_result), sizeof(mc_adam_cfg),'
+                ' offsetof(mc_options, path_values), offsetof(mc_result, cv_fallback));}\n')
+    exe = src[:-2]
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+    got = [int(x) for x in subprocess.run([exe], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    want = [C.sizeof(_abi.McModel), C.sizeof(_abi.McPayoff), C.sizeof(_abi.McOptions),
+            C.sizeof(_abi.McResult), C.sizeof(_abi.McAdamCfg),
+            _abi.McOptions.path_values.offset, _abi.McResult.cv_fallback.offset]
+    assert got == want
+
+
+def test_status_strings():
+    assert mc.mc_status_str(0) == "MC_OK"
+    assert mc.mc_status_str(-2) == "MC_ERR_NOT_PD"
+    assert mc.mc_status_str(-7) == "MC_ERR_WORKSPACE"
+
+
+GBM = mc.Model(kind=mc.MC_GBM, S0=100.0, r=0.03, T=1.0, sigma=0.25)
+HES = mc.Model(kind=mc.MC_HESTON, S0=100.0, r=0.02, T=1.0, v0=0.04, kappa=2.0, theta=0.04,
+               xi=0.5, rho=-0.7)
+
+
+@pytest.mark.parametrize("model,payoff,n_paths,n_steps,opts,want", [
+    (GBM, mc.Payoff(mc.MC_EURO_CALL, 100.0), 1 << 10, 64, None, mc.MC_OK),
+    (GBM, mc.Payoff(mc.MC_EURO_CALL, 100.0), 1, 64, None, mc._abi.MC_ERR_INVALID_ARG),
+    (GBM, mc.Payoff(mc.MC_EURO_CALL, 100.0), 16, 0, None, mc._abi.MC_ERR_INVALID_ARG),
+    (mc.Model(kind=mc.MC_GBM, S0=100.0, r=0.03, sigma=math.nan), mc.Payoff(), 16, 4, None,
+     mc._abi.MC_ERR_INVALID_ARG),
+    (mc.Model(kind=mc.MC_GBM, S0=-1.0, r=0.03, sigma=0.2), mc.Payoff(), 16, 4, None,
+     mc._abi.MC_ERR_INVALID_ARG),
+    (mc.Model(kind=mc.MC_GBM, S0=100.0, r=0.03, sigma=0.2, T=0.0), mc.Payoff(), 16, 4, None,
+     mc._abi.MC_ERR_INVALID_ARG),
+    (GBM, mc.Payoff(mc.MC_EURO_CALL, -5.0), 16, 4, None, mc._abi.MC_ERR_INVALID_ARG),
+    (GBM, mc.Payoff(mc.MC_UO_BARRIER_CALL, 100.0, B=90.0), 16, 4, None,
+     mc._abi.MC_ERR_INVALID_ARG),
+    (GBM, mc.Payoff(mc.MC_UO_BARRIER_CALL, 100.0, B=130.0), 16, 4,
+     mc.Options(greeks=mc.MC_GREEK_DELTA), mc._abi.MC_ERR_UNSUPPORTED),
+    (GBM, mc.Payoff(mc.MC_EURO_CALL, 100.0, cv=mc.MC_CV_LEARNED), 16, 4, None,
+     mc._abi.MC_ERR_UNSUPPORTED),
+    (GBM, mc.Payoff(mc.MC_EURO_CALL, 100.0), 16, 4, mc.Options(prec=mc.MC_BF16_GEMM),
+     mc._abi.MC_ERR_UNSUPPORTED),
+    (GBM, mc.Payoff(mc.MC_EURO_CALL, 100.0), 16, 4, mc.Options(cv_hedge_every=0),
+     mc._abi.MC_ERR_INVALID_ARG),
+    (mc.Model(kind=mc.MC_GBM, S0=100.0, r=0.03, sigma=0.2, scheme=mc.MC_EULER_S),
+     mc.Payoff(mc.MC_UO_BRIDGE_CALL, 100.0, B=130.0), 16, 4, None, mc._abi.MC_ERR_UNSUPPORTED),
+    (HES, mc.Payoff(mc.MC_ASIAN_ARITH_CALL, 100.0), 1 << 10, 256, None, mc.MC_OK),
+    (mc.Model(kind=mc.MC_HESTON, S0=100.0, v0=-0.01, kappa=2, theta=0.04, xi=0.5, rho=-0.7),
+     mc.Payoff(), 16, 4, None, mc._abi.MC_ERR_INVALID_ARG),
+    (mc.Model(kind=mc.MC_HESTON, S0=100.0, v0=0.04, kappa=2, theta=0.04, xi=0.5, rho=1.0),
+     mc.Payoff(), 16, 4, None, mc._abi.MC_ERR_INVALID_ARG),
+    (HES, mc.Payoff(mc.MC_UO_BARRIER_CALL, 100.0, B=130.0), 16, 4, None,
+     mc._abi.MC_ERR_UNSUPPORTED),
+    (HES, mc.Payoff(mc.MC_ASIAN_ARITH_CALL, 100.0), 16, 4,
+     mc.Options(greeks=3, prec=mc.MC_FP64), mc._abi.MC_ERR_UNSUPPORTED),
+])
+def test_validation_without_device(model, payoff, n_paths, n_steps, opts, want):
+    assert mc.mc_validate(model, payoff, n_paths, n_steps, opts) == want
+
+
+def test_create_without_device_reports_no_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(mc.McError) as e:
+        mc.mc_create(0)
+    assert e.value.status == mc._abi.MC_ERR_NO_DEVICE
+
+
+def test_channel_names_and_sizes():
+    names = mc.mc_path_channels(GBM, mc.Payoff(mc.MC_ASIAN_ARITH_CALL, 100.0,
+                                               cv=mc.MC_CV_GEO_ASIAN))
+    assert names == ["asian", "geo", "uo"]
+    names = mc.mc_path_channels(GBM, mc.Payoff(mc.MC_EURO_CALL, 100.0),
+                                mc.Options(prec=mc.MC_FP64, greeks=3))
+    assert names == ["euro", "euro_delta", "euro_vega"]
+    names = mc.mc_path_channels(GBM, mc.Payoff(mc.MC_UO_BRIDGE_CALL, 100.0, B=130.0))
+    assert names[4] == "uo_bridge" and len(names) == 9
+    assert mc.mc_path_channels(HES, mc.Payoff(mc.MC_ASIAN_ARITH_CALL, 100.0),
+                               mc.Options(greeks=3)) == ["asian", "asian_delta", "asian_dv0"]
+    # Checkpoints: 16 per 256 steps, (2 per checkpoint + 1) FP32 rows per path.
+    assert mc.mc_adjoint_ckpt_bytes(1000, 256, 16) == (2 * 16 + 1) * 1000 * 4
+    assert mc.mc_adjoint_ckpt_bytes(1000, 250, 16) == (2 * 16 + 1) * 1000 * 4
+    assert mc.mc_adjoint_ckpt_bytes(1000, 256, 8) == 0
+    ws = mc.mc_workspace_bytes(GBM, mc.Payoff(mc.MC_EURO_CALL, 100.0), 1 << 20, 64)
+    assert ws >= (1 << 20) // 256 * 4 * 8     # 4 moments per block for one channel

@@ -1,0 +1,148 @@
+"""GPU parity of the Heston kernels against the FP64 oracle: prices per path,
+the checkpointed pathwise adjoint (delta and d/dv0) against the oracle's
+forward tangents, the FWD/REV split behind torch.autograd, common-random-
+number finite differences and the characteristic-function greeks."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1906_02818_amd as mc
+import synth
+from closed_forms import heston_call
+
+pytestmark = pytest.mark.gpu
+SEED = synth.SEED
+H = {k: synth.HESTON[k] for k in ("S0", "v0", "kappa", "theta", "xi", "rho", "r", "T", "K")}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = mc.mc_create(0)
+    yield c
+    c.close()
+
+
+def model(**over):
+    p = dict(H)
+    p.update(over)
+    return mc.Model(kind=mc.MC_HESTON, S0=p["S0"], r=p["r"], T=p["T"], v0=p["v0"],
+                    kappa=p["kappa"], theta=p["theta"], xi=p["xi"], rho=p["rho"])
+
+
+def orc(n, N, path0=0, **over):
+    p = dict(H)
+    p.update(over)
+    return oracle.heston(p["S0"], p["v0"], p["kappa"], p["theta"], p["xi"], p["rho"], p["r"],
+                         p["T"], p["K"], n, N, SEED, path0=path0)
+
+
+@pytest.mark.parametrize("prec,N,n", [(mc.MC_FP64, 1 << 14, 256), (mc.MC_FP32, 1 << 16, 256),
+                                      (mc.MC_FP32, 1000, 7), (mc.MC_FP64, 333, 1)])
+def test_heston_price_parity(ctx, prec, N, n):
+    say("heston price", prec, N, n)
+    r = mc.mc_price(ctx, model(), mc.Payoff(mc.MC_ASIAN_ARITH_CALL, H["K"]), N, n, SEED,
+                    mc.Options(prec=prec, path_values=True))
+    o = orc(n, N)
+    pv = r["path_values"]
+    rtol = 1e-11 if prec == mc.MC_FP64 else 3e-4
+    np.testing.assert_allclose(pv[:, 0], o[:, 0], rtol=rtol, atol=rtol)
+    np.testing.assert_allclose(pv[:, 1], o[:, 1], rtol=rtol, atol=rtol)
+    e = oracle.estimate(o[:, 1])
+    rel = abs(r["price"] - e["price"]) / e["price"]
+    say("  asian rel err", rel)
+    assert rel < (1e-12 if prec == mc.MC_FP64 else 2e-5)
+
+
+@pytest.mark.parametrize("asian,N,n", [(True, 1 << 16, 256), (False, 1 << 16, 256),
+                                       (True, 1000, 250), (True, 300, 7)])
+def test_adjoint_matches_oracle_tangents(ctx, asian, N, n):
+    say("adjoint", asian, N, n)
+    kind = mc.MC_ASIAN_ARITH_CALL if asian else mc.MC_EURO_CALL
+    r = mc.mc_greeks_adjoint(ctx, model(), mc.Payoff(kind, H["K"]), N, n, SEED,
+                             mc.Options(path_values=True))
+    o = orc(n, N)
+    pay, dS, dv = (1, 4, 5) if asian else (0, 2, 3)
+    pv = r["path_values"]
+    np.testing.assert_allclose(pv[:, 0], o[:, pay], rtol=3e-4, atol=3e-4)
+    away = np.abs(o[:, pay]) > 1e-3           # indicator 1{A>K} not at its jump
+    np.testing.assert_allclose(pv[away, 1], o[away, dS], rtol=3e-4, atol=1e-5)
+    # d/dv0 carries 1/sqrt(v) factors where v is near zero: FP32 rounding of v
+    # is amplified there, so compare with a relative tolerance on most paths
+    # and bound the aggregate.
+    err = np.abs(pv[away, 2] - o[away, dv]) / (1.0 + np.abs(o[away, dv]))
+    say("  dv0 per-path err quantiles", np.quantile(err, [0.5, 0.99, 0.999]), err.max())
+    assert np.quantile(err, 0.999) < 1e-2
+    for col, key, sek in ((dS, "delta", "delta_se"), (dv, "vega", "vega_se")):
+        e = oracle.estimate(o[:, col])
+        say(f"  {key} gpu {r[key]:.6f} oracle {e['price']:.6f} se {e['std_err']:.2e}")
+        assert abs(r[key] - e["price"]) < 0.1 * e["std_err"] + 1e-5 * abs(e["price"])
+
+
+def test_fwd_rev_split_equals_full_and_autograd(ctx):
+    import torch
+    N, n = 1 << 15, 256
+    f = mc.Payoff(mc.MC_ASIAN_ARITH_CALL, H["K"])
+    full = mc.mc_greeks_adjoint(ctx, model(), f, N, n, SEED)
+    nbytes = mc.mc_adjoint_ckpt_bytes(N, n, 16)
+    ck = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    fwd = mc.mc_greeks_adjoint(ctx, model(), f, N, n, SEED, phase=mc.MC_ADJ_FWD,
+                               ckpt_ptr=ck.data_ptr(), ckpt_bytes=nbytes)
+    rev = mc.mc_greeks_adjoint(ctx, model(), f, N, n, SEED, phase=mc.MC_ADJ_REV,
+                               ckpt_ptr=ck.data_ptr(), ckpt_bytes=nbytes, grad_out=2.0)
+    assert fwd["price"] == full["price"]
+    assert rev["delta"] == 2.0 * full["delta"] and rev["vega"] == 2.0 * full["vega"]
+    S0 = torch.tensor(H["S0"], dtype=torch.float64, requires_grad=True)
+    v0 = torch.tensor(H["v0"], dtype=torch.float64, requires_grad=True)
+    price = mc.PathwisePrice.apply(S0, v0, ctx, model(), f, N, n, SEED)
+    (3.0 * price).backward()
+    assert price.item() == full["price"]
+    assert S0.grad.item() == 3.0 * full["delta"]
+    assert v0.grad.item() == 3.0 * full["vega"]
+    # A too-small checkpoint buffer is refused.
+    with pytest.raises(mc.McError):
+        mc.mc_greeks_adjoint(ctx, model(), f, N, n, SEED, phase=mc.MC_ADJ_FWD,
+                             ckpt_ptr=ck.data_ptr(), ckpt_bytes=nbytes - 4)
+
+
+def test_adjoint_against_common_random_number_fd(ctx):
+    # Central differences h = 1e-3 relative on common random numbers (same
+    # seed and tags), path by path, against the adjoint.
+    N, n = 1 << 18, 256
+    f = mc.Payoff(mc.MC_ASIAN_ARITH_CALL, H["K"])
+    adj = mc.mc_greeks_adjoint(ctx, model(), f, N, n, SEED, mc.Options(path_values=True))
+    for key, col, name in (("S0", 1, "delta"), ("v0", 2, "vega")):
+        h = 1e-3 * H[key]
+        up = mc.mc_price(ctx, model(**{key: H[key] + h}), f, N, n, SEED,
+                         mc.Options(path_values=True))
+        dn = mc.mc_price(ctx, model(**{key: H[key] - h}), f, N, n, SEED,
+                         mc.Options(path_values=True))
+        fd = (up["path_values"][:, 1] - dn["path_values"][:, 1]) / (2 * h)
+        d = adj["path_values"][:, col] - fd
+        se = d.std(ddof=1) / math.sqrt(N)
+        say(f"  {name}: adjoint {adj[name]:.5f} fd {fd.mean():.5f} diff {d.mean():.2e} se {se:.2e}")
+        assert abs(d.mean()) < 4 * se + 2e-3 * abs(adj[name])
+
+
+def test_european_greeks_against_characteristic_function(ctx):
+    N, n = 1 << 21, 256
+    r = mc.mc_greeks_adjoint(ctx, model(), mc.Payoff(mc.MC_EURO_CALL, H["K"]), N, n, SEED)
+
+    def cf(**over):
+        p = dict(H)
+        p.update(over)
+        return heston_call(p["S0"], p["v0"], p["kappa"], p["theta"], p["xi"], p["rho"], p["r"],
+                           p["T"], p["K"])
+
+    h = 1e-4
+    d = (cf(S0=H["S0"] * (1 + h)) - cf(S0=H["S0"] * (1 - h))) / (2 * h * H["S0"])
+    v = (cf(v0=H["v0"] * (1 + h)) - cf(v0=H["v0"] * (1 - h))) / (2 * h * H["v0"])
+    say("  price", r["price"], "cf", cf(), "delta", r["delta"], d, "dv0", r["vega"], v)
+    assert abs(r["price"] - cf()) < 4 * r["std_err"] + 0.01
+    assert abs(r["delta"] - d) < 4 * r["delta_se"] + 1e-3
+    assert abs(r["vega"] - v) < 5 * r["vega_se"] + 0.3
