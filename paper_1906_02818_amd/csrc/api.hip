@@ -104,6 +104,40 @@ mc_status validate_heston(mc_context* ctx, const mc_model* m, const mc_options& 
 
 uint32_t gbm_want_mask(const mc_payoff* f, const mc_options& o, mc_status* st);
 
+// Basket checks; on success fills L (d*d, lower Cholesky factor) if given.
+mc_status validate_basket(mc_context* ctx, const mc_model* m, const mc_payoff* f,
+                          uint32_t n_steps, const mc_options& o, std::vector<double>* L) {
+  const uint32_t d = m->dim;
+  if (d == 0 || d > 256 || d % 16 != 0)
+    return fail(ctx, MC_ERR_UNSUPPORTED, "basket dim must be a multiple of 16 up to 256");
+  if (!m->sigma || !m->corr) return fail(ctx, MC_ERR_INVALID_ARG, "basket needs sigma and corr");
+  for (uint32_t a = 0; a < d; ++a)
+    if (!finite_nonneg(m->sigma[a])) return fail(ctx, MC_ERR_INVALID_ARG, "sigma[%u] invalid", a);
+  for (uint32_t i = 0; i < d; ++i)
+    for (uint32_t j = 0; j < d; ++j) {
+      const double c = m->corr[(size_t)i * d + j];
+      if (!std::isfinite(c)) return fail(ctx, MC_ERR_INVALID_ARG, "corr not finite");
+      if (c != m->corr[(size_t)j * d + i]) return fail(ctx, MC_ERR_INVALID_ARG, "corr not symmetric");
+    }
+  if (f->kind != MC_BASKET_CALL) return fail(ctx, MC_ERR_UNSUPPORTED, "basket prices MC_BASKET_CALL");
+  if (f->cv != MC_CV_NONE) return fail(ctx, MC_ERR_UNSUPPORTED, "no control variate for the basket");
+  if (f->weights)
+    for (uint32_t a = 0; a < d; ++a)
+      if (!std::isfinite(f->weights[a])) return fail(ctx, MC_ERR_INVALID_ARG, "weights not finite");
+  if (o.prec == MC_FP64) return fail(ctx, MC_ERR_UNSUPPORTED, "basket runs in FP32/BF16/FP16");
+  if (o.prec != MC_FP32 && o.prec != MC_BF16_GEMM && o.prec != MC_FP16_GEMM &&
+      o.prec != MC_BF16X2_GEMM)
+    return fail(ctx, MC_ERR_INVALID_ARG, "unknown precision");
+  if (o.greeks & MC_GREEK_VEGA) return fail(ctx, MC_ERR_UNSUPPORTED, "basket greeks: delta only");
+  if ((uint64_t)n_steps * d / 4 >= (1ull << 32))
+    return fail(ctx, MC_ERR_INVALID_ARG, "n_steps * dim above 2^34 normals per path");
+  std::vector<double> Lloc((size_t)d * d);
+  if (!host::cholesky((int)d, m->corr, Lloc.data()))
+    return fail(ctx, MC_ERR_NOT_PD, "correlation matrix is not positive definite");
+  if (L) *L = std::move(Lloc);
+  return MC_OK;
+}
+
 // Every check of mc_price, no device access.
 mc_status validate_all(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint64_t n_paths,
                        uint32_t n_steps, const mc_options& o) {
@@ -135,7 +169,7 @@ mc_status validate_all(mc_context* ctx, const mc_model* m, const mc_payoff* f, u
       return fail(ctx, MC_ERR_UNSUPPORTED, "adjoint greeks run in MC_FP32");
     return MC_OK;
   }
-  if (m->kind == MC_GBM_BASKET) return fail(ctx, MC_ERR_UNSUPPORTED, "basket not built yet");
+  if (m->kind == MC_GBM_BASKET) return validate_basket(ctx, m, f, n_steps, o, nullptr);
   return fail(ctx, MC_ERR_INVALID_ARG, "unknown model kind");
 }
 
@@ -473,6 +507,156 @@ mc_status heston_price(mc_context* ctx, const mc_model* m, const mc_payoff* f, u
   return MC_OK;
 }
 
+// ------------------------------------------------------------- Basket ----
+// L' = diag(sigma_a sqrt(dt) / ln 2) L, packed into the kernel's lower-
+// triangular 32x16 blocks (n block nb, k block kb <= 2 nb + 1, block id
+// nb (nb + 1) + kb, element [n][k] row-major), in the requested type.
+template <typename T, typename F>
+void pack_blocks(uint32_t d, uint32_t nd, const std::vector<double>& Ls, F&& conv,
+                 std::vector<T>* out) {
+  out->assign((size_t)nd * (nd + 1) * 512, conv(0.0));
+  for (uint32_t nb = 0; nb < nd; ++nb)
+    for (uint32_t kb = 0; kb <= 2 * nb + 1; ++kb) {
+      const size_t base = (size_t)(nb * (nb + 1) + kb) * 512;
+      for (uint32_t r = 0; r < 32; ++r)
+        for (uint32_t j = 0; j < 16; ++j) {
+          const uint32_t a = 32 * nb + r, b = 16 * kb + j;
+          const double v = (a < d && b < d && b <= a) ? Ls[(size_t)a * d + b] : 0.0;
+          (*out)[base + r * 16 + j] = conv(v);
+        }
+    }
+}
+
+uint16_t to_bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7FFFu + lsb;
+  return (uint16_t)(u >> 16);
+}
+float from_bf16(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+uint16_t to_f16_rne(float f) {
+  _Float16 h = (_Float16)f;   // host conversion rounds to nearest even
+  uint16_t u;
+  std::memcpy(&u, &h, 2);
+  return u;
+}
+
+mc_status basket_price(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint64_t n_paths,
+                       uint32_t n_steps, uint64_t seed, const mc_options& o0, mc_result* out) {
+  std::vector<double> L;
+  mc_status st = validate_basket(ctx, m, f, n_steps, o0, &L);
+  if (st != MC_OK) return st;
+  const uint32_t d = m->dim, nd = basket_blocks_nd(d);
+  const double dt = m->T / n_steps, inv_ln2 = 1.0 / std::log(2.0);
+  std::vector<double> Ls((size_t)d * d);
+  for (uint32_t a = 0; a < d; ++a)
+    for (uint32_t b = 0; b < d; ++b)
+      Ls[(size_t)a * d + b] = m->sigma[a] * std::sqrt(dt) * inv_ln2 * L[(size_t)a * d + b];
+  int prec = BK_FP32;
+  std::vector<float> bf32;
+  std::vector<uint16_t> b16, b16lo;
+  size_t blk_bytes = 0;
+  switch (o0.prec) {
+    case MC_FP32:
+      prec = BK_FP32;
+      pack_blocks<float>(d, nd, Ls, [](double v) { return (float)v; }, &bf32);
+      blk_bytes = bf32.size() * 4;
+      break;
+    case MC_BF16_GEMM:
+      prec = BK_BF16;
+      pack_blocks<uint16_t>(d, nd, Ls, [](double v) { return to_bf16_rne((float)v); }, &b16);
+      blk_bytes = b16.size() * 2;
+      break;
+    case MC_FP16_GEMM:
+      prec = BK_FP16;
+      pack_blocks<uint16_t>(d, nd, Ls, [](double v) { return to_f16_rne((float)v); }, &b16);
+      blk_bytes = b16.size() * 2;
+      break;
+    default:
+      prec = BK_BF16X2;
+      pack_blocks<uint16_t>(d, nd, Ls, [](double v) { return to_bf16_rne((float)v); }, &b16);
+      pack_blocks<uint16_t>(d, nd, Ls, [](double v) {
+        const float hi = from_bf16(to_bf16_rne((float)v));
+        return to_bf16_rne((float)(v - (double)hi));
+      }, &b16lo);
+      blk_bytes = b16.size() * 2;
+      break;
+  }
+  // Per-asset constants: n mu_a in log2 units, w_a S0_a, w_a ln 2.
+  std::vector<float> asset(3 * 256, 0.f);
+  double geo0 = 0.0;
+  for (uint32_t a = 0; a < d; ++a) {
+    const double w = f->weights ? f->weights[a] : 1.0 / d;
+    const double mu = (m->r - 0.5 * m->sigma[a] * m->sigma[a]) * dt * inv_ln2;
+    asset[a] = (float)(n_steps * mu);
+    asset[256 + a] = (float)(w * m->S0[a]);
+    asset[512 + a] = (float)(w * std::log(2.0));
+    geo0 += w * std::log(m->S0[a]);
+  }
+  const RunLayout Lay = layout_for(n_paths, 3, o0.path_values != nullptr);
+  const size_t off_blk = align256(Lay.bytes);
+  const size_t off_lo = off_blk + align256(blk_bytes);
+  const size_t off_asset = off_lo + (prec == BK_BF16X2 ? align256(blk_bytes) : 0);
+  const size_t total = off_asset + align256(asset.size() * 4);
+  char* base = nullptr;
+  st = get_ws(ctx, o0, total, &base);
+  if (st != MC_OK) return st;
+  hipStream_t s = stream_of(ctx, o0);
+  const void* hb = prec == BK_FP32 ? (const void*)bf32.data() : (const void*)b16.data();
+  HIP_TRY(ctx, hipMemcpyAsync(base + off_blk, hb, blk_bytes, hipMemcpyHostToDevice, s));
+  if (prec == BK_BF16X2)
+    HIP_TRY(ctx, hipMemcpyAsync(base + off_lo, b16lo.data(), blk_bytes, hipMemcpyHostToDevice, s));
+  HIP_TRY(ctx, hipMemcpyAsync(base + off_asset, asset.data(), asset.size() * 4,
+                              hipMemcpyHostToDevice, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));   // host vectors go out of scope
+  mc_options o = o0;
+  o.workspace = base;
+  o.workspace_bytes = Lay.bytes;
+  BasketParams p{};
+  p.n_paths = n_paths;
+  p.path_offset = o0.path_offset;
+  p.n_steps = n_steps;
+  p.tag = o0.stream_tag;
+  p.k0 = (uint32_t)seed;
+  p.k1 = (uint32_t)(seed >> 32);
+  p.d = d;
+  p.Lblk = base + off_blk;
+  p.Lblk_lo = prec == BK_BF16X2 ? base + off_lo : nullptr;
+  p.asset = (const float*)(base + off_asset);
+  p.disc = std::exp(-m->r * m->T);
+  p.K = f->K;
+  p.geo0 = geo0;
+  p.w0 = f->weights ? f->weights[0] : 1.0 / d;
+  Moments mom;
+  double kms = 0.0;
+  st = run_moments(ctx, o, n_paths, 3, o0.path_values,
+                   [&](double* partials, double* path_out, hipStream_t ss, uint32_t* nb) {
+                     p.partials = partials;
+                     p.path_out = path_out;
+                     return launch_basket(p, prec, ss, nb);
+                   },
+                   &mom, &kms);
+  if (st != MC_OK) return st;
+  mc_result r{};
+  double v;
+  fill_channel(mom, 0, &r.price, &r.variance, &r.std_err);
+  r.plain_price = r.price;
+  r.plain_std_err = r.std_err;
+  if (o0.greeks & MC_GREEK_DELTA) fill_channel(mom, 2, &r.delta, &v, &r.delta_se);
+  r.vrf = 1.0;
+  r.n_paths = (uint64_t)mom.n;
+  r.n_nonfinite = (uint64_t)mom.nonfinite;
+  r.kernel_ms = kms;
+  *out = r;
+  return MC_OK;
+}
+
 }  // namespace
 
 // ================================================================ C ABI ===
@@ -542,6 +726,7 @@ uint32_t mc_path_channels(const mc_model* m, const mc_payoff* f, const mc_option
     return mask ? (uint32_t)gbm_channels(mask) : 0;
   }
   if (m->kind == MC_HESTON) return o.greeks ? 3u : 2u;
+  if (m->kind == MC_GBM_BASKET) return 3u;
   return 0;
 }
 
@@ -565,6 +750,10 @@ const char* mc_path_channel_name(const mc_model* m, const mc_payoff* f, const mc
     }
     static const char* n[] = {"euro", "asian"};
     return i < 2 ? n[i] : nullptr;
+  }
+  if (m->kind == MC_GBM_BASKET) {
+    static const char* b[] = {"basket", "geo_basket", "basket_delta0"};
+    return i < 3 ? b[i] : nullptr;
   }
   return nullptr;
 }
@@ -606,6 +795,7 @@ mc_status mc_price(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint6
     if (st != MC_OK) return st;
     return gbm_result(ctx, m, f, n_steps, seed, o, mask, mom, kms, n_paths, out);
   }
+  if (m->kind == MC_GBM_BASKET) return basket_price(ctx, m, f, n_paths, n_steps, seed, o, out);
   return heston_price(ctx, m, f, n_paths, n_steps, seed, o, out);
 }
 

@@ -28,5 +28,24 @@ inline double geo_asian_call(double S0, double K, double r, double sigma, double
   return lognormal_call(m, s2, K, disc);
 }
 
+// Lower Cholesky factor of the symmetric matrix C (row-major d x d):
+// C = L L^T. Returns false when a pivot is not positive.
+inline bool cholesky(int d, const double* C, double* L) {
+  for (int i = 0; i < d * d; ++i) L[i] = 0.0;
+  for (int j = 0; j < d; ++j) {
+    double s = C[j * d + j];
+    for (int k = 0; k < j; ++k) s -= L[j * d + k] * L[j * d + k];
+    if (!(s > 0.0)) return false;
+    const double ljj = std::sqrt(s);
+    L[j * d + j] = ljj;
+    for (int i = j + 1; i < d; ++i) {
+      double t = C[i * d + j];
+      for (int k = 0; k < j; ++k) t -= L[i * d + k] * L[j * d + k];
+      L[i * d + j] = t / ljj;
+    }
+  }
+  return true;
+}
+
 }  // namespace host
 }  // namespace mcp

@@ -165,12 +165,15 @@ __global__ __launch_bounds__(kBlock) void heston_adjoint_kernel(const AdjointPar
       term = (R)A.ckpt[(size_t)(2 * A.n_ckpt) * np + pid];
     }
     if (PHASE != 1) {
-      // Reverse sweep. xb = dP/d(ln S_i), vb = dP/dv_i, natural-log units.
+      // Reverse sweep. xb = dP/d(ln S_i), vb = dP/dv_i, natural-log units,
+      // accumulated in FP64: under a violated Feller condition the factor
+      // dv_{i+1}/dv_i = 1 - kappa dt + xi Z1 dt / (2 sqrt(v dt)) can reach
+      // 10^3 near v = 0, and products of such factors overflow FP32.
       const bool itm = S0 * term > K;
       // Asian: dP/d(ln S_i) = disc 1{A>K} S_i / n = abar * (S_i/S0).
-      const R abar = (ASIAN && itm) ? disc * S0 * inv_n : R(0);
-      R xb = (!ASIAN && itm) ? disc * S0 * term : R(0);
-      R vb = R(0);
+      const double abar = (ASIAN && itm) ? (double)(disc * S0 * inv_n) : 0.0;
+      double xb = (!ASIAN && itm) ? (double)(disc * S0 * term) : 0.0;
+      double vb = 0.0;
       const R dt = hs.dt, half_dt = R(0.5) * hs.dt, kdt = hs.kdt, xi = hs.xi;
       const uint32_t n_seg = (n + kCkpt - 1) / kCkpt;
       for (int seg = (int)n_seg - 1; seg >= 0; --seg) {
@@ -200,21 +203,21 @@ __global__ __launch_bounds__(kBlock) void heston_adjoint_kernel(const AdjointPar
 #pragma unroll
         for (int q = kCkpt - 1; q >= 0; --q) {
           if ((uint32_t)q < len) {
-            if (ASIAN) xb += abar * Es[q];          // S_{i+1} enters the average
+            if (ASIAN) xb += abar * (double)Es[q];   // S_{i+1} enters the average
             const R vq = vs[q];
             if (vq > R(0)) {
               const R sq = HDom<R>::sqrt_(vq * dt);
               const R g = half_dt / sq;               // d sqrt(v dt) / dv
-              const R dxdv = -half_dt + zss[q] * g;
-              const R dvdv = (R(1) - kdt) + xi * z1s[q] * g;
+              const double dxdv = (double)(-half_dt + zss[q] * g);
+              const double dvdv = (double)((R(1) - kdt) + xi * z1s[q] * g);
               vb = xb * dxdv + vb * dvdv;
             }
           }
         }
       }
       const int c0 = PHASE == 0 ? 1 : 0;
-      y[c0] = (double)(xb / S0);   // d/dS0 through ln S0
-      y[c0 + 1] = (double)vb;      // d/dv0
+      y[c0] = xb / (double)P.S0;   // d/dS0 through ln S0
+      y[c0 + 1] = vb;              // d/dv0
     }
   }
   bool finite = true;

@@ -71,11 +71,28 @@ struct AdjointParams {
   HestonParams h;
   int asian;            // 1: arithmetic-Asian call, 0: European call
   int phase;            // 0 full, 1 forward (write checkpoints), 2 reverse
-  float* ckpt;          // [n_ckpt][3][n_paths]
+  float* ckpt;          // [2*n_ckpt + 1][n_paths]: (z, v) per checkpoint, then terminal
   uint32_t n_ckpt;
   double grad_out;
 };
 hipError_t launch_heston_adjoint(const AdjointParams& p, hipStream_t s, uint32_t* n_blocks);
+
+// ---- Basket (correlated GBM, MFMA increments) ----
+enum : int { BK_FP32 = 0, BK_BF16 = 1, BK_FP16 = 2, BK_BF16X2 = 3 };
+struct BasketParams {
+  uint64_t n_paths, path_offset;
+  uint32_t n_steps, tag, k0, k1;
+  uint32_t d;             // assets, multiple of 16, <= 256
+  const void* Lblk;       // packed lower-triangular 32x16 blocks of L' (device)
+  const void* Lblk_lo;    // BF16X2: the lo term, same layout
+  const float* asset;     // device [3][256]: n*mu_a (log2), w_a*S0_a, w_a*ln 2
+  double disc, K, geo0, w0;
+  double* partials;
+  double* path_out;       // [n_paths][3] or nullptr
+};
+// Number of 32-wide asset blocks the kernel is instantiated for (1, 2, 4, 8).
+uint32_t basket_blocks_nd(uint32_t d);
+hipError_t launch_basket(const BasketParams& p, int prec, hipStream_t s, uint32_t* n_blocks);
 
 // ---- reductions and diagnostics ----
 hipError_t launch_final_reduce(const double* partials, uint32_t n_blocks, uint32_t n_mom,

@@ -129,3 +129,40 @@ def test_channel_names_and_sizes():
     assert mc.mc_adjoint_ckpt_bytes(1000, 256, 8) == 0
     ws = mc.mc_workspace_bytes(GBM, mc.Payoff(mc.MC_EURO_CALL, 100.0), 1 << 20, 64)
     assert ws >= (1 << 20) // 256 * 4 * 8     # 4 moments per block for one channel
+
+
+def _basket(d=32, corr=None, **kw):
+    import synth
+    sigma, c, _ = synth.basket_market(d)
+    return mc.Model(kind=mc.MC_GBM_BASKET, S0=np.full(d, 100.0), r=0.05, T=1.0, sigma=sigma,
+                    corr=c if corr is None else corr, **kw)
+
+
+def test_basket_validation_without_device():
+    f = mc.Payoff(mc.MC_BASKET_CALL, 100.0)
+    assert mc.mc_validate(_basket(), f, 1024, 100, mc.Options(prec=mc.MC_BF16_GEMM)) == mc.MC_OK
+    assert mc.mc_validate(_basket(256), f, 1024, 100, mc.Options(prec=mc.MC_FP16_GEMM)) == mc.MC_OK
+    # Not positive definite: an off-diagonal above 1.
+    m = _basket()
+    bad = np.array(m.corr)
+    bad[0, 1] = bad[1, 0] = 1.2
+    assert mc.mc_validate(_basket(corr=bad), f, 1024, 10) == mc._abi.MC_ERR_NOT_PD
+    # Singular (two identical assets) is not positive definite either.
+    sing = np.array(m.corr)
+    sing[1, :] = sing[0, :]
+    sing[:, 1] = sing[:, 0]
+    sing[1, 1] = 1.0
+    assert mc.mc_validate(_basket(corr=sing), f, 1024, 10) == mc._abi.MC_ERR_NOT_PD
+    asym = np.array(m.corr)
+    asym[0, 1] += 1e-3
+    assert mc.mc_validate(_basket(corr=asym), f, 1024, 10) == mc._abi.MC_ERR_INVALID_ARG
+    d20 = mc.Model(kind=mc.MC_GBM_BASKET, S0=np.full(20, 100.0), sigma=np.full(20, 0.2),
+                   corr=np.eye(20))
+    assert mc.mc_validate(d20, f, 1024, 10) == mc._abi.MC_ERR_UNSUPPORTED
+    assert mc.mc_validate(_basket(), f, 1024, 10, mc.Options(prec=mc.MC_FP64)) == \
+        mc._abi.MC_ERR_UNSUPPORTED
+    assert mc.mc_validate(_basket(), f, 1024, 10, mc.Options(greeks=mc.MC_GREEK_VEGA)) == \
+        mc._abi.MC_ERR_UNSUPPORTED
+    assert mc.mc_validate(_basket(), mc.Payoff(mc.MC_EURO_CALL, 100.0), 1024, 10) == \
+        mc._abi.MC_ERR_UNSUPPORTED
+    assert mc.mc_path_channels(_basket(), f) == ["basket", "geo_basket", "basket_delta0"]

@@ -66,6 +66,7 @@ def test_adjoint_matches_oracle_tangents(ctx, asian, N, n):
     kind = mc.MC_ASIAN_ARITH_CALL if asian else mc.MC_EURO_CALL
     r = mc.mc_greeks_adjoint(ctx, model(), mc.Payoff(kind, H["K"]), N, n, SEED,
                              mc.Options(path_values=True))
+    assert r["n_nonfinite"] == 0
     o = orc(n, N)
     pay, dS, dv = (1, 4, 5) if asian else (0, 2, 3)
     pv = r["path_values"]
@@ -95,6 +96,7 @@ def test_fwd_rev_split_equals_full_and_autograd(ctx):
                                ckpt_ptr=ck.data_ptr(), ckpt_bytes=nbytes)
     rev = mc.mc_greeks_adjoint(ctx, model(), f, N, n, SEED, phase=mc.MC_ADJ_REV,
                                ckpt_ptr=ck.data_ptr(), ckpt_bytes=nbytes, grad_out=2.0)
+    assert full["n_nonfinite"] == 0 and rev["n_nonfinite"] == 0
     assert fwd["price"] == full["price"]
     assert rev["delta"] == 2.0 * full["delta"] and rev["vega"] == 2.0 * full["vega"]
     S0 = torch.tensor(H["S0"], dtype=torch.float64, requires_grad=True)
