@@ -2,7 +2,8 @@
 
 Every .hip file under csrc/ is compiled with hipcc for gfx950 only and
 linked into one shared library that exports the C ABI of include/mcpath.h.
-Packed FP32 instructions are disabled for the device code.
+Packed FP32 instructions are disabled for the device code; multiply-add
+fusion follows the source expressions (-ffp-contract=on).
 """
 import concurrent.futures as cf
 import glob
@@ -15,7 +16,9 @@ LIB = os.path.join(HERE, "libmcpath.so")
 OBJ_DIR = os.path.join(HERE, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+# -ffp-contract=on: a*b+c is fused only inside one source expression, so the
+# same expression rounds identically in every kernel that contains it.
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 

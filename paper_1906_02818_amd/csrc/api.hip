@@ -547,6 +547,16 @@ uint16_t to_f16_rne(float f) {
   return u;
 }
 
+// Workspace of a basket run: moment layout, L' blocks (twice for the split
+// BF16 form) and the per-asset table.
+size_t basket_ws_bytes(size_t layout_bytes, uint32_t d, mc_precision prec) {
+  const uint32_t nd = basket_blocks_nd(d);
+  const size_t elt = prec == MC_FP32 ? 4 : 2;
+  const size_t blk = align256((size_t)nd * (nd + 1) * 512 * elt);
+  return align256(layout_bytes) + blk * (prec == MC_BF16X2_GEMM ? 2 : 1) +
+         align256(3 * 256 * sizeof(float));
+}
+
 mc_status basket_price(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint64_t n_paths,
                        uint32_t n_steps, uint64_t seed, const mc_options& o0, mc_result* out) {
   std::vector<double> L;
@@ -604,6 +614,8 @@ mc_status basket_price(mc_context* ctx, const mc_model* m, const mc_payoff* f, u
   const size_t off_lo = off_blk + align256(blk_bytes);
   const size_t off_asset = off_lo + (prec == BK_BF16X2 ? align256(blk_bytes) : 0);
   const size_t total = off_asset + align256(asset.size() * 4);
+  if (total != basket_ws_bytes(Lay.bytes, d, o0.prec))
+    return fail(ctx, MC_ERR_DEVICE, "basket workspace layout mismatch");
   char* base = nullptr;
   st = get_ws(ctx, o0, total, &base);
   if (st != MC_OK) return st;
@@ -768,6 +780,7 @@ size_t mc_workspace_bytes(const mc_model* m, const mc_payoff* f, uint64_t n_path
   size_t bytes = layout_for(n_paths, (int)C, o.path_values != nullptr).bytes;
   if (m->kind == MC_HESTON && o.greeks)
     bytes = align256(bytes) + align256(mc_adjoint_ckpt_bytes(n_paths, n_steps, mcp::kCkpt));
+  if (m->kind == MC_GBM_BASKET) bytes = basket_ws_bytes(bytes, m->dim, o.prec);
   return bytes;
 }
 
