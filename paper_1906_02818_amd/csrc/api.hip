@@ -97,8 +97,7 @@ mc_status validate_heston(mc_context* ctx, const mc_model* m, const mc_options& 
     return fail(ctx, MC_ERR_INVALID_ARG, "v0, kappa, theta, xi must be finite and >= 0");
   if (!(std::isfinite(m->rho) && std::fabs(m->rho) < 1.0))
     return fail(ctx, MC_ERR_INVALID_ARG, "|rho| must be < 1");
-  if (o.prec != MC_FP32 && o.prec != MC_FP64)
-    return fail(ctx, MC_ERR_UNSUPPORTED, "Heston paths run in MC_FP32 or MC_FP64");
+  (void)o;
   return MC_OK;
 }
 
@@ -165,6 +164,18 @@ mc_status validate_all(mc_context* ctx, const mc_model* m, const mc_payoff* f, u
       return fail(ctx, MC_ERR_UNSUPPORTED, "Heston offers the European and arithmetic-Asian call");
     if (f->cv == MC_CV_GEO_ASIAN)
       return fail(ctx, MC_ERR_UNSUPPORTED, "geometric CV is GBM-only");
+    if (f->cv == MC_CV_LEARNED) {
+      if (o.greeks) return fail(ctx, MC_ERR_UNSUPPORTED, "greeks with the learned CV");
+      if (f->kind != MC_ASIAN_ARITH_CALL)
+        return fail(ctx, MC_ERR_UNSUPPORTED, "learned CV covers the arithmetic-Asian call");
+      if (!(m->theta > 0.0)) return fail(ctx, MC_ERR_INVALID_ARG, "learned CV needs theta > 0");
+      if (o.prec != MC_FP32 && o.prec != MC_BF16_GEMM)
+        return fail(ctx, MC_ERR_UNSUPPORTED, "learned CV runs in MC_FP32 or MC_BF16_GEMM");
+      if (!o.cv_weights) return fail(ctx, MC_ERR_INVALID_ARG, "MC_CV_LEARNED needs cv_weights");
+      return MC_OK;
+    }
+    if (o.prec != MC_FP32 && o.prec != MC_FP64)
+      return fail(ctx, MC_ERR_UNSUPPORTED, "Heston paths run in MC_FP32 or MC_FP64");
     if (o.greeks && o.prec != MC_FP32)
       return fail(ctx, MC_ERR_UNSUPPORTED, "adjoint greeks run in MC_FP32");
     return MC_OK;
@@ -220,9 +231,9 @@ struct RunLayout {
   size_t off_mom, off_path, bytes;
 };
 
-RunLayout layout_for(uint64_t n_paths, int C, bool want_path) {
+RunLayout layout_for(uint64_t n_paths, int C, bool want_path, uint32_t paths_per_block = kBlock) {
   RunLayout L;
-  L.n_blocks = (uint32_t)((n_paths + kBlock - 1) / kBlock);
+  L.n_blocks = (uint32_t)((n_paths + paths_per_block - 1) / paths_per_block);
   L.C = (uint32_t)C;
   L.n_mom = (uint32_t)n_moments(C);
   L.off_mom = align256((size_t)L.n_mom * L.n_blocks * sizeof(double));
@@ -250,8 +261,9 @@ struct Moments {
 // final reduction, and brings the moments to the host.
 template <typename F>
 mc_status run_moments(mc_context* ctx, const mc_options& o, uint64_t n_paths, int C,
-                      double* host_path_values, F&& launch, Moments* out, double* kernel_ms) {
-  const RunLayout L = layout_for(n_paths, C, host_path_values != nullptr);
+                      double* host_path_values, F&& launch, Moments* out, double* kernel_ms,
+                      uint32_t paths_per_block = kBlock) {
+  const RunLayout L = layout_for(n_paths, C, host_path_values != nullptr, paths_per_block);
   char* base = nullptr;
   mc_status st = get_ws(ctx, o, L.bytes, &base);
   if (st != MC_OK) return st;
@@ -475,8 +487,16 @@ HestonParams heston_params(const mc_model* m, const mc_payoff* f, uint64_t n_pat
   return p;
 }
 
+mc_status heston_cv_price(mc_context* ctx, const mc_model* m, const mc_payoff* f,
+                          uint64_t n_paths, uint32_t n_steps, uint64_t seed, const mc_options& o0,
+                          mc_result* out);
+
 mc_status heston_price(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint64_t n_paths,
                        uint32_t n_steps, uint64_t seed, const mc_options& o, mc_result* out) {
+  if (f->cv == MC_CV_LEARNED) {
+    if (o.greeks) return fail(ctx, MC_ERR_UNSUPPORTED, "greeks with the learned CV");
+    return heston_cv_price(ctx, m, f, n_paths, n_steps, seed, o, out);
+  }
   if (f->cv != MC_CV_NONE) return fail(ctx, MC_ERR_UNSUPPORTED, "control variate not available");
   if (o.greeks) {
     return mc_greeks_adjoint(ctx, m, f, n_paths, n_steps, seed, &o, MC_ADJ_FULL, mcp::kCkpt,
@@ -505,6 +525,232 @@ mc_status heston_price(mc_context* ctx, const mc_model* m, const mc_payoff* f, u
   r.kernel_ms = kms;
   *out = r;
   return MC_OK;
+}
+
+// ------------------------------------------------- Learned control variate --
+// Device buffers of one learned-CV run: weights, their fragments and the
+// undiscounting table, after the moment layout in the workspace.
+struct CvBuffers {
+  float *theta, *w1f, *w2f, *w2tf, *lanec, *dfac;
+};
+
+size_t cv_extra_bytes(uint32_t n_steps) {
+  return align256(kMlpNParam * 4) + align256(kW1fFloats * 4) + 2 * align256(kW2fFloats * 4) +
+         align256(kLanecFloats * 4) + align256((size_t)(n_steps + 1) * 4);
+}
+
+CvBuffers cv_carve(char* p) {
+  CvBuffers b;
+  b.theta = (float*)p;
+  p += align256(kMlpNParam * 4);
+  b.w1f = (float*)p;
+  p += align256(kW1fFloats * 4);
+  b.w2f = (float*)p;
+  p += align256(kW2fFloats * 4);
+  b.w2tf = (float*)p;
+  p += align256(kW2fFloats * 4);
+  b.lanec = (float*)p;
+  p += align256(kLanecFloats * 4);
+  b.dfac = (float*)p;
+  return b;
+}
+
+std::vector<float> dfac_table(const mc_model* m, uint32_t n_steps) {
+  std::vector<float> t(n_steps + 1);
+  for (uint32_t i = 0; i <= n_steps; ++i) t[i] = (float)std::exp(m->r * m->T * i / n_steps);
+  return t;
+}
+
+CvParams cv_params(const mc_model* m, const mc_payoff* f, uint64_t n_paths, uint32_t n_steps,
+                   uint64_t seed, const mc_options& o, uint32_t tag, uint32_t hedge_every,
+                   bool bf16, const CvBuffers& b) {
+  CvParams p{};
+  p.h = heston_params(m, f, n_paths, n_steps, seed, o, tag);
+  p.hedge_every = hedge_every;
+  p.bf16 = bf16 ? 1 : 0;
+  p.theta = b.theta;
+  p.w1f = b.w1f;
+  p.w2f = b.w2f;
+  p.w2tf = b.w2tf;
+  p.lanec = b.lanec;
+  p.dfac = b.dfac;
+  return p;
+}
+
+// Uploads weights and the discount table, builds the fragments.
+mc_status cv_upload(mc_context* ctx, hipStream_t s, const CvBuffers& b, const float* theta_host,
+                    const std::vector<float>& dfac) {
+  if (theta_host)
+    HIP_TRY(ctx, hipMemcpyAsync(b.theta, theta_host, kMlpNParam * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(ctx, hipMemcpyAsync(b.dfac, dfac.data(), dfac.size() * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(ctx, launch_cv_pack(b.theta, b.w1f, b.w2f, b.w2tf, b.lanec, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  return MC_OK;
+}
+
+mc_status cv_validate(mc_context* ctx, const mc_model* m, const mc_payoff* f, mc_precision prec,
+                      uint32_t hedge_every) {
+  if (m->kind != MC_HESTON || f->kind != MC_ASIAN_ARITH_CALL)
+    return fail(ctx, MC_ERR_UNSUPPORTED, "learned CV covers the Heston arithmetic-Asian call");
+  if (!(m->theta > 0.0)) return fail(ctx, MC_ERR_INVALID_ARG, "learned CV needs theta > 0");
+  if (prec != MC_FP32 && prec != MC_BF16_GEMM)
+    return fail(ctx, MC_ERR_UNSUPPORTED, "learned CV runs in MC_FP32 or MC_BF16_GEMM");
+  if (hedge_every == 0) return fail(ctx, MC_ERR_INVALID_ARG, "hedge_every must be >= 1");
+  return MC_OK;
+}
+
+// One evaluation pass of the hedged estimator: channels payoff, H, Y.
+mc_status cv_eval(mc_context* ctx, const mc_options& o, const CvParams& base, uint64_t n_paths,
+                  double* host_path_values, Moments* mom, double* kms) {
+  CvParams p = base;
+  return run_moments(ctx, o, n_paths, 3, host_path_values,
+                     [&](double* partials, double* path_out, hipStream_t s, uint32_t* nb) {
+                       p.partials = partials;
+                       p.path_out = path_out;
+                       return launch_cv_price(p, s, nb);
+                     },
+                     mom, kms, kCvPathsPerBlock);
+}
+
+mc_status heston_cv_price(mc_context* ctx, const mc_model* m, const mc_payoff* f,
+                          uint64_t n_paths, uint32_t n_steps, uint64_t seed, const mc_options& o0,
+                          mc_result* out) {
+  mc_status st = cv_validate(ctx, m, f, o0.prec, o0.cv_hedge_every);
+  if (st != MC_OK) return st;
+  if (!o0.cv_weights) return fail(ctx, MC_ERR_INVALID_ARG, "MC_CV_LEARNED needs cv_weights");
+  for (int i = 0; i < kMlpNParam; ++i)
+    if (!std::isfinite(o0.cv_weights[i])) return fail(ctx, MC_ERR_INVALID_ARG, "cv_weights not finite");
+  const uint64_t n_pilot = o0.pilot_paths ? o0.pilot_paths : (1ull << 16);
+  const uint64_t n_big = n_paths > n_pilot ? n_paths : n_pilot;
+  const RunLayout Lay = layout_for(n_big, 3, o0.path_values != nullptr, kCvPathsPerBlock);
+  const size_t off = align256(Lay.bytes);
+  char* base = nullptr;
+  st = get_ws(ctx, o0, off + cv_extra_bytes(n_steps), &base);
+  if (st != MC_OK) return st;
+  const CvBuffers b = cv_carve(base + off);
+  hipStream_t s = stream_of(ctx, o0);
+  st = cv_upload(ctx, s, b, o0.cv_weights, dfac_table(m, n_steps));
+  if (st != MC_OK) return st;
+  mc_options o = o0;
+  o.workspace = base;
+  o.workspace_bytes = Lay.bytes;
+  const bool bf16 = o0.prec == MC_BF16_GEMM;
+  double kms = 0.0;
+  // Pilot on stream tag+1: plain MC is the fallback when the hedge does not
+  // reduce the variance there.
+  mc_options po = o;
+  po.path_offset = 0;
+  po.path_values = nullptr;
+  Moments pm;
+  st = cv_eval(ctx, po, cv_params(m, f, n_pilot, n_steps, seed, po, o0.stream_tag + 1,
+                                   o0.cv_hedge_every, bf16, b),
+               n_pilot, nullptr, &pm, &kms);
+  if (st != MC_OK) return st;
+  const double pilot_vrf = pm.cov(0, 0) / pm.cov(2, 2);
+  if (!(pilot_vrf > 1.0)) {
+    mc_options plain = o0;
+    plain.path_values = nullptr;
+    mc_payoff fp = *f;
+    fp.cv = MC_CV_NONE;
+    st = heston_price(ctx, m, &fp, n_paths, n_steps, seed, plain, out);
+    if (st != MC_OK) return st;
+    out->cv_fallback = 1;
+    out->vrf = pilot_vrf;
+    out->kernel_ms += kms;
+    return MC_OK;
+  }
+  Moments mom;
+  st = cv_eval(ctx, o, cv_params(m, f, n_paths, n_steps, seed, o, o0.stream_tag, o0.cv_hedge_every,
+                                 bf16, b),
+               n_paths, o0.path_values, &mom, &kms);
+  if (st != MC_OK) return st;
+  mc_result r{};
+  fill_channel(mom, 2, &r.price, &r.variance, &r.std_err);
+  double v;
+  fill_channel(mom, 0, &r.plain_price, &v, &r.plain_std_err);
+  r.vrf = mom.cov(0, 0) / mom.cov(2, 2);
+  r.n_paths = (uint64_t)mom.n;
+  r.n_nonfinite = (uint64_t)mom.nonfinite;
+  r.kernel_ms = kms;
+  *out = r;
+  return MC_OK;
+}
+
+// Forward + backward over one minibatch; leaves the FP64 gradient in
+// grad_dev and returns the moments of the forward pass.
+struct CvTrainWs {
+  char* eval_base;          // moment layout with per-path values
+  size_t eval_bytes;
+  double* grad_partials;    // [kMlpNParam][n_waves]
+  double* grad;             // [kMlpNParam]
+  CvBuffers b;
+  float *m, *v;             // Adam moments
+  double* log;              // [steps][n_mom] forward-pass moments
+};
+
+size_t cv_train_bytes(uint64_t batch, uint32_t n_steps, uint32_t steps, CvTrainWs* w, char* base) {
+  const RunLayout Lay = layout_for(batch, 3, true, kCvPathsPerBlock);
+  const uint64_t n_waves = (uint64_t)Lay.n_blocks * (kCvPathsPerBlock / 32);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base ? base + off : nullptr;
+    off += align256(bytes);
+    return p;
+  };
+  char* e = take(Lay.bytes);
+  char* gp = take((size_t)kMlpNParam * n_waves * 8);
+  char* g = take((size_t)kMlpNParam * 8);
+  char* cv = take(cv_extra_bytes(n_steps));
+  char* mm = take((size_t)kMlpNParam * 4);
+  char* vv = take((size_t)kMlpNParam * 4);
+  char* lg = take((size_t)(steps ? steps : 1) * Lay.n_mom * 8);
+  if (w && base) {
+    w->eval_base = e;
+    w->eval_bytes = Lay.bytes;
+    w->grad_partials = (double*)gp;
+    w->grad = (double*)g;
+    w->b = cv_carve(cv);
+    w->m = (float*)mm;
+    w->v = (float*)vv;
+    w->log = (double*)lg;
+  }
+  return off;
+}
+
+mc_status cv_loss_grad_device(mc_context* ctx, hipStream_t s, const mc_model* m,
+                              const mc_payoff* f, uint32_t n_steps, uint64_t seed, uint32_t tag,
+                              uint64_t path0, uint64_t batch, uint32_t hedge_every, bool bf16,
+                              const CvTrainWs& w, double* log_row) {
+  mc_options o = defaults();
+  o.hip_stream = s;
+  o.path_offset = path0;
+  const RunLayout Lay = layout_for(batch, 3, true, kCvPathsPerBlock);
+  double* partials = (double*)w.eval_base;
+  double* mom = (double*)(w.eval_base + Lay.off_mom);
+  double* ypath = (double*)(w.eval_base + Lay.off_path);
+  CvParams p = cv_params(m, f, batch, n_steps, seed, o, tag, hedge_every, bf16, w.b);
+  p.partials = partials;
+  p.path_out = ypath;
+  uint32_t nb = 0;
+  HIP_TRY(ctx, launch_cv_price(p, s, &nb));
+  HIP_TRY(ctx, launch_final_reduce(partials, nb, Lay.n_mom, mom, s));
+  if (log_row)
+    HIP_TRY(ctx, hipMemcpyAsync(log_row, mom, Lay.n_mom * 8, hipMemcpyDeviceToDevice, s));
+  p.path_out = nullptr;
+  p.ybar_mom = mom;
+  p.y_path = ypath;
+  p.g_scale = -2.0 / (double)batch;
+  p.grad_partials = w.grad_partials;
+  HIP_TRY(ctx, launch_cv_backward(p, s, &nb));
+  const uint32_t n_waves = nb * (kCvPathsPerBlock / 32);
+  HIP_TRY(ctx, launch_final_reduce(w.grad_partials, n_waves, kMlpNParam, w.grad, s));
+  return MC_OK;
+}
+
+double loss_from_moments(const double* mom) {
+  // Channel 2 (Y) of a 3-channel layout: n = mom[0], sum = mom[4], sum sq = mom[10].
+  const double n = mom[0], s1 = mom[4], s2 = mom[10];
+  return (s2 - s1 * s1 / n) / n;
 }
 
 // ------------------------------------------------------------- Basket ----
@@ -737,7 +983,7 @@ uint32_t mc_path_channels(const mc_model* m, const mc_payoff* f, const mc_option
     const uint32_t mask = gbm_pick_mask(want, o.prec == MC_FP64, m->scheme == MC_LOG_EULER);
     return mask ? (uint32_t)gbm_channels(mask) : 0;
   }
-  if (m->kind == MC_HESTON) return o.greeks ? 3u : 2u;
+  if (m->kind == MC_HESTON) return (o.greeks || f->cv == MC_CV_LEARNED) ? 3u : 2u;
   if (m->kind == MC_GBM_BASKET) return 3u;
   return 0;
 }
@@ -755,6 +1001,10 @@ const char* mc_path_channel_name(const mc_model* m, const mc_payoff* f, const mc
   }
   if (m->kind == MC_HESTON) {
     const bool asian = f->kind == MC_ASIAN_ARITH_CALL;
+    if (f->cv == MC_CV_LEARNED) {
+      static const char* c[] = {"asian", "hedge_pnl", "asian_minus_hedge"};
+      return i < 3 ? c[i] : nullptr;
+    }
     if (o.greeks) {
       static const char* e[] = {"euro", "euro_delta", "euro_dv0"};
       static const char* a[] = {"asian", "asian_delta", "asian_dv0"};
@@ -780,6 +1030,12 @@ size_t mc_workspace_bytes(const mc_model* m, const mc_payoff* f, uint64_t n_path
   size_t bytes = layout_for(n_paths, (int)C, o.path_values != nullptr).bytes;
   if (m->kind == MC_HESTON && o.greeks)
     bytes = align256(bytes) + align256(mc_adjoint_ckpt_bytes(n_paths, n_steps, mcp::kCkpt));
+  if (m->kind == MC_HESTON && f->cv == MC_CV_LEARNED) {
+    const uint64_t n_pilot = o.pilot_paths ? o.pilot_paths : (1ull << 16);
+    const uint64_t n_big = n_paths > n_pilot ? n_paths : n_pilot;
+    bytes = align256(layout_for(n_big, 3, o.path_values != nullptr, kCvPathsPerBlock).bytes) +
+            cv_extra_bytes(n_steps);
+  }
   if (m->kind == MC_GBM_BASKET) bytes = basket_ws_bytes(bytes, m->dim, o.prec);
   return bytes;
 }
@@ -944,15 +1200,103 @@ mc_status mc_greeks_adjoint(mc_context* ctx, const mc_model* m, const mc_payoff*
   return MC_OK;
 }
 
-mc_status mc_cv_train(mc_context* ctx, const mc_model*, const mc_payoff*, uint64_t, uint32_t,
-                      uint64_t, const mc_adam_cfg*, float*, float*) {
-  return fail(ctx, MC_ERR_UNSUPPORTED, "learned control variate not built yet");
+mc_status validate_adam(mc_context* ctx, const mc_adam_cfg* cfg, uint64_t n_train) {
+  if (!cfg) return fail(ctx, MC_ERR_INVALID_ARG, "cfg must not be NULL");
+  if (!(std::isfinite(cfg->lr) && cfg->lr > 0 && cfg->beta1 >= 0 && cfg->beta1 < 1 &&
+        cfg->beta2 >= 0 && cfg->beta2 < 1 && cfg->eps > 0))
+    return fail(ctx, MC_ERR_INVALID_ARG, "bad Adam hyper-parameters");
+  if (cfg->batch < 256 || cfg->batch % 256 != 0)
+    return fail(ctx, MC_ERR_INVALID_ARG, "batch must be a positive multiple of 256");
+  if (n_train && (n_train < cfg->batch || n_train % cfg->batch != 0))
+    return fail(ctx, MC_ERR_INVALID_ARG, "n_train must be a multiple of batch");
+  return MC_OK;
 }
 
-mc_status mc_cv_loss_grad(mc_context* ctx, const mc_model*, const mc_payoff*, uint32_t, uint64_t,
-                          uint32_t, uint64_t, uint64_t, const mc_adam_cfg*, const float*, double*,
-                          float*) {
-  return fail(ctx, MC_ERR_UNSUPPORTED, "learned control variate not built yet");
+mc_status mc_cv_loss_grad(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint32_t n_steps,
+                          uint64_t seed, uint32_t tag, uint64_t path0, uint64_t batch,
+                          const mc_adam_cfg* cfg, const float* weights, double* loss_out,
+                          float* grad_out) {
+  if (!ctx) return MC_ERR_INVALID_ARG;
+  mc_status st = validate_common(ctx, m, f, batch, n_steps);
+  if (st != MC_OK) return st;
+  mc_options o = defaults();
+  st = validate_heston(ctx, m, o);
+  if (st != MC_OK) return st;
+  st = validate_adam(ctx, cfg, 0);
+  if (st != MC_OK) return st;
+  st = cv_validate(ctx, m, f, cfg->prec, cfg->hedge_every);
+  if (st != MC_OK) return st;
+  if (!weights || !loss_out || !grad_out) return fail(ctx, MC_ERR_INVALID_ARG, "NULL array");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, MC_ERR_DEVICE, "hipSetDevice");
+  const size_t bytes = cv_train_bytes(batch, n_steps, 1, nullptr, nullptr);
+  char* base = nullptr;
+  st = get_ws(ctx, o, bytes, &base);
+  if (st != MC_OK) return st;
+  CvTrainWs w;
+  cv_train_bytes(batch, n_steps, 1, &w, base);
+  hipStream_t s = ctx->stream;
+  st = cv_upload(ctx, s, w.b, weights, dfac_table(m, n_steps));
+  if (st != MC_OK) return st;
+  st = cv_loss_grad_device(ctx, s, m, f, n_steps, seed, tag, path0, batch, cfg->hedge_every,
+                           cfg->prec == MC_BF16_GEMM, w, w.log);
+  if (st != MC_OK) return st;
+  std::vector<double> g(kMlpNParam), mom(n_moments(3));
+  HIP_TRY(ctx, hipMemcpyAsync(g.data(), w.grad, kMlpNParam * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipMemcpyAsync(mom.data(), w.log, mom.size() * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  for (int i = 0; i < kMlpNParam; ++i) grad_out[i] = (float)g[i];
+  *loss_out = loss_from_moments(mom.data());
+  return MC_OK;
+}
+
+mc_status mc_cv_train(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint64_t n_train,
+                      uint32_t n_steps, uint64_t seed, const mc_adam_cfg* cfg,
+                      float* weights_inout, float* loss_log) {
+  if (!ctx) return MC_ERR_INVALID_ARG;
+  mc_status st = validate_common(ctx, m, f, n_train, n_steps);
+  if (st != MC_OK) return st;
+  mc_options o = defaults();
+  st = validate_heston(ctx, m, o);
+  if (st != MC_OK) return st;
+  st = validate_adam(ctx, cfg, n_train);
+  if (st != MC_OK) return st;
+  st = cv_validate(ctx, m, f, cfg->prec, cfg->hedge_every);
+  if (st != MC_OK) return st;
+  if (!weights_inout) return fail(ctx, MC_ERR_INVALID_ARG, "weights_inout must not be NULL");
+  if (cfg->steps == 0) return MC_OK;
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, MC_ERR_DEVICE, "hipSetDevice");
+  const uint64_t B = cfg->batch;
+  const size_t bytes = cv_train_bytes(B, n_steps, cfg->steps, nullptr, nullptr);
+  char* base = nullptr;
+  st = get_ws(ctx, o, bytes, &base);
+  if (st != MC_OK) return st;
+  CvTrainWs w;
+  cv_train_bytes(B, n_steps, cfg->steps, &w, base);
+  hipStream_t s = ctx->stream;
+  st = cv_upload(ctx, s, w.b, weights_inout, dfac_table(m, n_steps));
+  if (st != MC_OK) return st;
+  HIP_TRY(ctx, hipMemsetAsync(w.m, 0, kMlpNParam * 4, s));
+  HIP_TRY(ctx, hipMemsetAsync(w.v, 0, kMlpNParam * 4, s));
+  const uint64_t n_batches = n_train / B;
+  const uint32_t n_mom = (uint32_t)n_moments(3);
+  const bool bf16 = cfg->prec == MC_BF16_GEMM;
+  for (uint32_t t = 0; t < cfg->steps; ++t) {
+    // Minibatches cycle through the fixed training set (stream tag 2).
+    const uint64_t path0 = (t % n_batches) * B;
+    st = cv_loss_grad_device(ctx, s, m, f, n_steps, seed, 2, path0, B, cfg->hedge_every, bf16, w,
+                             w.log + (size_t)t * n_mom);
+    if (st != MC_OK) return st;
+    HIP_TRY(ctx, launch_adam(w.b.theta, w.m, w.v, w.grad, kMlpNParam, (int)t + 1, cfg->lr,
+                             cfg->beta1, cfg->beta2, cfg->eps, s));
+    HIP_TRY(ctx, launch_cv_pack(w.b.theta, w.b.w1f, w.b.w2f, w.b.w2tf, w.b.lanec, s));
+  }
+  std::vector<double> log((size_t)cfg->steps * n_mom);
+  HIP_TRY(ctx, hipMemcpyAsync(weights_inout, w.b.theta, kMlpNParam * 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipMemcpyAsync(log.data(), w.log, log.size() * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  if (loss_log)
+    for (uint32_t t = 0; t < cfg->steps; ++t) loss_log[t] = (float)loss_from_moments(&log[(size_t)t * n_mom]);
+  return MC_OK;
 }
 
 mc_status mc_philox_words(mc_context* ctx, uint64_t seed, uint32_t tag, uint64_t n,

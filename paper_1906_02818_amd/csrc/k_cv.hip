@@ -1,0 +1,467 @@
+// Learned martingale control variate on the Heston Asian call.
+//
+// A hedge network Delta(t, state), 4 -> 64 -> 64 -> 1 with tanh, is run
+// along every path; its discounted hedging P&L
+//     H = sum_j Delta(phi_{t_j}) (St_{t_{j+1}} - St_{t_j}),  St = e^{-rt} S,
+// has zero mean for any weights (St is a martingale under the log-Euler
+// step), so Y = payoff - H is an unbiased estimator of the price (Eq. 3
+// applied to Y) whose variance the network is trained to minimise.
+//
+// Path state: the discounted log-price z~ = log2(St/S0) (the rate cancels
+// from its drift) and the variance v; S_i/S0 = 2^{z~_i} * dfac[i] feeds the
+// Asian average. Features phi = (t/T, ln(S/K), v/theta, Abar/K - 1).
+//
+// Network on MFMA, one wave = 32 paths, lanes l and l+32 both follow path
+// l mod 32 and each holds half of every hidden layer:
+//   layer 1: D1 = [W1 | b1] (64 x 16) . [phi; 1] (16 x 32 paths)
+//   layer 2: D2 = W2 (64 x 64) . H1^T (64 x 32 paths)
+// An accumulator lane holds units u(mb, r, h) = 32 mb + 8 (r/4) + 4 h +
+// (r mod 4). Layer 2's k-slots are ordered so that its B operand is exactly
+// the lane's layer-1 output (the host permutes W2 to match), so nothing
+// moves between layers. Layer 3 is a per-lane dot product plus one swap of
+// halves. tanh(x) = 2 / (1 + e^{-2x}) - 1 on v_exp_f32 / v_rcp_f32.
+//
+// Training (backward kernel): for each closed hedge segment the upstream
+// derivative dL/dDelta = g_b dSt with g_b = -(2/B)(Y_b - Ybar) is pushed
+// back through the network; dW2 = delta2^T H1 and dW1 = delta1^T [phi; 1]
+// are MFMA products over the wave's 32 paths after a transpose through LDS.
+// Each wave writes its partial gradient in FP64; a fixed-order reduction
+// and the Adam kernel follow.
+#include "device/reduce.h"
+#include "device/rng.h"
+#include "mc_internal.h"
+
+namespace mcp {
+namespace {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+
+constexpr int kCvWaves = 4;
+constexpr int kCvThreads = 64 * kCvWaves;
+constexpr float kNeg2Log2e = -2.88539008177792681472f;   // -2 / ln 2
+
+// acc += A (8 k-slots per lane) x B (8 k-slots per lane) over one 16-wide
+// k block: one BF16 MFMA, or eight FP32 MFMAs with the same k-slot order.
+template <bool BF16>
+__device__ __forceinline__ void mma16(f32x16& acc, const float (&a)[8], const float (&b)[8]) {
+  if constexpr (BF16) {
+    bf16x8 av, bv;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      av[j] = (__bf16)a[j];
+      bv[j] = (__bf16)b[j];
+    }
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[j], b[j], acc, 0, 0, 0);
+  }
+}
+
+// tanh(x + b) with cb = -2 b / ln 2 folded into the exponent.
+__device__ __forceinline__ float tanh_b(float x, float cb) {
+  const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(x, kNeg2Log2e, cb));
+  return __builtin_fmaf(2.0f, __builtin_amdgcn_rcpf(1.0f + e), -1.0f);
+}
+
+__device__ __forceinline__ int unit_of(int mb, int r, int h) {
+  return 32 * mb + 8 * (r >> 2) + 4 * h + (r & 3);
+}
+
+__device__ __forceinline__ void load8(const float* p, float (&x)[8]) {
+  const float4 a = *(const float4*)p;
+  const float4 b = *(const float4*)(p + 4);
+  x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+  x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
+}
+
+constexpr int kFragFloats = 2 * 4 * 64 * 8;   // one set of layer-2 fragments
+constexpr int kLaneFloats = 2 * 64 * 32;      // per-lane b2 (scaled) and W3
+
+// Forward pass of the hedge network for the wave's 32 paths. phi: the
+// lane's B fragment of layer 1 (half 0: features and the constant 1; half
+// 1: zeros). Returns Delta (identical in both halves); keeps h1, h2.
+template <bool BF16>
+__device__ __forceinline__ float mlp_forward(const float (&phi)[8], const float (&w1a)[2][8],
+                                             const float* w2f, const float* lanec, int lane,
+                                             float b3, float (&h1)[32], float (&h2)[32]) {
+  f32x16 d1[2];
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) d1[mb][r] = 0.f;
+    mma16<BF16>(d1[mb], w1a[mb], phi);
+  }
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) h1[mb * 16 + r] = tanh_b(d1[mb][r], 0.f);
+  f32x16 d2[2];
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) d2[mb][r] = 0.f;
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb) {
+    float b[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) b[j] = h1[(kb >> 1) * 16 + 8 * (kb & 1) + j];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+      float a[8];
+      load8(&w2f[((mb * 4 + kb) * 64 + lane) * 8], a);
+      mma16<BF16>(d2[mb], a, b);
+    }
+  }
+  float part = 0.f;
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int idx = mb * 16 + r;
+      const float v = tanh_b(d2[mb][r], lanec[lane * 32 + idx]);
+      h2[idx] = v;
+      part = __builtin_fmaf(lanec[64 * 32 + lane * 32 + idx], v, part);
+    }
+  return part + __shfl_xor(part, 32, 64) + b3;
+}
+
+template <bool BF16, bool TRAIN>
+__global__ __launch_bounds__(kCvThreads) void cv_kernel(const CvParams P) {
+  __shared__ __attribute__((aligned(16))) float s_w2f[kFragFloats];
+  __shared__ __attribute__((aligned(16))) float s_lanec[kLaneFloats];
+  __shared__ __attribute__((aligned(16))) float s_w2tf[TRAIN ? kFragFloats : 4];
+  __shared__ __attribute__((aligned(16))) float tr[TRAIN ? kCvWaves : 1][TRAIN ? (64 * 32 + 8 * 32) : 4];
+  const HestonParams& Hp = P.h;
+  for (int i = threadIdx.x; i < kFragFloats; i += kCvThreads) {
+    s_w2f[i] = P.w2f[i];
+    if constexpr (TRAIN) s_w2tf[i] = P.w2tf[i];
+  }
+  for (int i = threadIdx.x; i < kLaneFloats; i += kCvThreads) s_lanec[i] = P.lanec[i];
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = lane & 31, half = lane >> 5;
+  const uint64_t tile = (uint64_t)blockIdx.x * kCvWaves + wave;
+  const uint64_t pid = tile * 32 + row;
+  const bool active = pid < Hp.n_paths;
+  float w1a[2][8];
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb) load8(&P.w1f[(mb * 64 + lane) * 8], w1a[mb]);
+  const float b3 = P.theta[4544];
+
+  // Heston step on the discounted log2-price (no rate in its drift).
+  const float dt = (float)Hp.dt, kdt = (float)(Hp.kappa * Hp.dt);
+  const float kthdt = (float)(Hp.kappa * Hp.theta * Hp.dt), xi = (float)Hp.xi;
+  const float rho = (float)Hp.rho, rhoc = (float)Hp.rho_c;
+  const float a1 = (float)(-0.5 * Hp.dt * 1.4426950408889634), a2 = 1.4426950408889634f;
+  const float S0 = (float)Hp.S0, K = (float)Hp.K;
+  const float lnS0K = (float)std::log(Hp.S0 / Hp.K), ln2 = 0.69314718055994531f;
+  const float rdt2 = (float)(Hp.r * Hp.dt * 1.4426950408889634);   // log2 e^{r dt}
+  const float inv_theta = (float)(1.0 / Hp.theta);
+  const uint32_t n = Hp.n_steps, m = P.hedge_every;
+  const PathCounter pc = make_counter(Hp.path_offset + pid, Hp.tag, Hp.k0, Hp.k1);
+
+  float g = 0.f;                       // upstream factor of this path (training)
+  if constexpr (TRAIN) {
+    if (active) {
+      const double ybar = P.ybar_mom[2 + 2] / P.ybar_mom[0];
+      g = (float)(P.g_scale * (P.y_path[pid * 3 + 2] - ybar));
+    }
+  }
+  // Training accumulators.
+  f32x16 gw2[2][2], gw1[2];
+  float gw3[32], gb2[32], gb3 = 0.f;
+  if constexpr (TRAIN) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) gw1[a][r] = 0.f;
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) gw2[a][b][r] = 0.f;
+    }
+#pragma unroll
+    for (int q = 0; q < 32; ++q) gw3[q] = gb2[q] = 0.f;
+  }
+
+  float z = 0.f, v = (float)Hp.v0, sumE = 0.f, H = 0.f, delta = 0.f, st_open = 0.f;
+  float Et = 1.f;                      // St_i / S0 = 2^{z~_i}
+  float phi[8], h1[32], h2[32];
+  Normals4<float> nz;
+  for (uint32_t i = 0; i < n; ++i) {
+    if (i % m == 0) {
+      // Features at t_i (F_{t_i}-measurable).
+      const float fi = (float)i;
+      const float Abar = (i == 0) ? 1.0f : sumE / fi;      // running mean of S/S0
+#pragma unroll
+      for (int j = 0; j < 8; ++j) phi[j] = 0.f;
+      if (half == 0) {
+        phi[0] = fi / (float)n;
+        phi[1] = (z + rdt2 * fi) * ln2 + lnS0K;          // ln(S_i / K)
+        phi[2] = v * inv_theta;
+        phi[3] = Abar * S0 / K - 1.0f;
+        phi[4] = 1.0f;
+      }
+      delta = mlp_forward<BF16>(phi, w1a, s_w2f, s_lanec, lane, b3, h1, h2);
+      st_open = Et;
+    }
+    if ((i & 1) == 0) nz = normals4<float>(philox(i >> 1, pc));
+    const float Z1 = (i & 1) ? nz.z[2] : nz.z[0];
+    const float Z2 = (i & 1) ? nz.z[3] : nz.z[1];
+    {
+      const float vp = v > 0.f ? v : 0.f;
+      const float sq = __builtin_amdgcn_sqrtf(vp * dt);
+      const float Zs = rho * Z1 + rhoc * Z2;
+      z = z + a1 * vp + a2 * (sq * Zs);
+      v = v + (kthdt - kdt * vp) + xi * (sq * Z1);
+    }
+    Et = __builtin_amdgcn_exp2f(z);
+    sumE += Et * P.dfac[i + 1];
+    if ((i + 1) % m == 0 || i + 1 == n) {
+      const float dSt = S0 * (Et - st_open);
+      H = __builtin_fmaf(delta, dSt, H);
+      if constexpr (TRAIN) {
+        const float gD = g * dSt;                      // dL/dDelta for this segment
+        if (half == 0) gb3 += gD;
+        float d2v[32], d1v[32];
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+          gw3[q] = __builtin_fmaf(gD, h2[q], gw3[q]);
+          d2v[q] = gD * s_lanec[64 * 32 + lane * 32 + q] * (1.0f - h2[q] * h2[q]);
+          gb2[q] += d2v[q];
+        }
+        // delta1 = (W2^T delta2) (1 - h1^2)
+        f32x16 e1[2];
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) e1[mb][r] = 0.f;
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+          float b[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) b[j] = d2v[(kb >> 1) * 16 + 8 * (kb & 1) + j];
+#pragma unroll
+          for (int mb = 0; mb < 2; ++mb) {
+            float a[8];
+            load8(&s_w2tf[((mb * 4 + kb) * 64 + lane) * 8], a);
+            mma16<BF16>(e1[mb], a, b);
+          }
+        }
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int q = mb * 16 + r;
+            d1v[q] = e1[mb][r] * (1.0f - h1[q] * h1[q]);
+          }
+        // dW2 += delta2^T H1 over the wave's paths (transpose via LDS).
+        float* T = tr[wave];
+        float* TP = T + 64 * 32;
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) T[unit_of(mb, r, half) * 32 + row] = d2v[mb * 16 + r];
+        __syncthreads();
+        float A2[2][2][8];
+#pragma unroll
+        for (int pk = 0; pk < 2; ++pk)
+#pragma unroll
+          for (int mb = 0; mb < 2; ++mb) load8(&T[(32 * mb + row) * 32 + 16 * pk + 8 * half], A2[pk][mb]);
+        __syncthreads();
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) T[unit_of(mb, r, half) * 32 + row] = h1[mb * 16 + r];
+        __syncthreads();
+#pragma unroll
+        for (int pk = 0; pk < 2; ++pk)
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb) {
+            float b[8];
+            load8(&T[(32 * nb + row) * 32 + 16 * pk + 8 * half], b);
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb) mma16<BF16>(gw2[mb][nb], A2[pk][mb], b);
+          }
+        __syncthreads();
+        // dW1ext += delta1^T [phi; 1] over the wave's paths.
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) T[unit_of(mb, r, half) * 32 + row] = d1v[mb * 16 + r];
+        if (half == 0) {
+#pragma unroll
+          for (int f = 0; f < 8; ++f) TP[f * 32 + row] = phi[f];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int pk = 0; pk < 2; ++pk) {
+          float b[8];
+          if (row < 8) {
+            load8(&TP[row * 32 + 16 * pk + 8 * half], b);
+          } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) b[j] = 0.f;
+          }
+#pragma unroll
+          for (int mb = 0; mb < 2; ++mb) {
+            float a[8];
+            load8(&T[(32 * mb + row) * 32 + 16 * pk + 8 * half], a);
+            mma16<BF16>(gw1[mb], a, b);
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+
+  if constexpr (!TRAIN) {
+    double y[3] = {0.0, 0.0, 0.0};
+    const bool report = active && half == 0;
+    if (report) {
+      const double A = (double)S0 * (double)sumE / (double)n;
+      const double pay = Hp.disc * (A > Hp.K ? A - Hp.K : 0.0);
+      y[0] = pay;
+      y[1] = (double)H;
+      y[2] = pay - (double)H;
+    }
+    const bool finite = isfinite(y[0]) && isfinite(y[1]) && isfinite(y[2]);
+    if (report && P.path_out != nullptr) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) P.path_out[pid * 3 + c] = y[c];
+    }
+    block_moments<3, kCvThreads>(y, report && finite, report && !finite, P.partials, gridDim.x);
+  } else {
+    // Per-wave partial gradients in FP64, in the flat parameter layout
+    // W1[64][4], b1[64], W2[64][64], b2[64], W3[64], b3.
+    const uint64_t nw = (uint64_t)gridDim.x * kCvWaves;
+    const uint64_t wg = (uint64_t)blockIdx.x * kCvWaves + wave;
+    double* G = P.grad_partials;
+    auto put = [&](int slot, double val) { G[(uint64_t)slot * nw + wg] = val; };
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int out = unit_of(mb, r, half), in = 32 * nb + row;
+          put(320 + out * 64 + in, (double)gw2[mb][nb][r]);
+        }
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int u = unit_of(mb, r, half);
+        if (row < 4) put(u * 4 + row, (double)gw1[mb][r]);
+        if (row == 4) put(256 + u, (double)gw1[mb][r]);
+      }
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+#pragma unroll
+      for (int off = 16; off > 0; off >>= 1) {
+        gw3[q] += __shfl_xor(gw3[q], off, 64);
+        gb2[q] += __shfl_xor(gb2[q], off, 64);
+      }
+    }
+    if (row == 0) {
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int u = unit_of(mb, r, half);
+          put(4416 + u, (double)gb2[mb * 16 + r]);
+          put(4480 + u, (double)gw3[mb * 16 + r]);
+        }
+    }
+    const double s3 = wave_sum((double)gb3);
+    if (lane == 0) put(4544, s3);
+  }
+}
+
+__global__ void adam_kernel(float* __restrict__ theta, float* __restrict__ m,
+                            float* __restrict__ v, const double* __restrict__ grad, int n,
+                            float lr, float b1, float b2, float eps, float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gr = (float)grad[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gr;
+  const float vi = b2 * v[i] + (1.0f - b2) * gr * gr;
+  m[i] = mi;
+  v[i] = vi;
+  theta[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Builds the per-lane fragments from the flat weights (one thread per
+// output float). Units: u(mb, r, h) as above; layer-2 k-slot (kb, h, j) is
+// the layer-1 unit u(kb/2, 8 (kb mod 2) + j, h).
+__global__ void cv_pack_kernel(const float* __restrict__ th, float* __restrict__ w1f,
+                               float* __restrict__ w2f, float* __restrict__ w2tf,
+                               float* __restrict__ lanec) {
+  const float* W1 = th;
+  const float* b1 = th + 256;
+  const float* W2 = th + 320;
+  const float* b2 = th + 4416;
+  const float* W3 = th + 4480;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < kW1fFloats) {
+    const int j = t & 7, lane = (t >> 3) & 63, mb = t >> 9;
+    const int row = lane & 31, h = lane >> 5, u = 32 * mb + row;
+    w1f[t] = (h == 0 && j < 4) ? W1[u * 4 + j] : (h == 0 && j == 4) ? b1[u] : 0.f;
+  }
+  if (t < kW2fFloats) {
+    const int j = t & 7, lane = (t >> 3) & 63, kb = (t >> 9) & 3, mb = t >> 11;
+    const int row = lane & 31, h = lane >> 5;
+    const int k_unit = unit_of(kb >> 1, 8 * (kb & 1) + j, h);
+    w2f[t] = W2[(32 * mb + row) * 64 + k_unit];
+    w2tf[t] = W2[k_unit * 64 + (32 * mb + row)];
+  }
+  if (t < kLanecFloats / 2) {
+    const int q = t & 31, lane = t >> 5;
+    const int h = lane >> 5, mb = q >> 4, r = q & 15;
+    const int u = unit_of(mb, r, h);
+    lanec[t] = b2[u] * kNeg2Log2e;
+    lanec[kLanecFloats / 2 + t] = W3[u];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_cv_pack(const float* theta, float* w1f, float* w2f, float* w2tf, float* lanec,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(cv_pack_kernel, dim3(kW2fFloats / 256), dim3(256), 0, s, theta, w1f, w2f,
+                     w2tf, lanec);
+  return hipGetLastError();
+}
+
+hipError_t launch_cv_price(const CvParams& p, hipStream_t s, uint32_t* n_blocks) {
+  const uint32_t nb = (uint32_t)((p.h.n_paths + 32 * kCvWaves - 1) / (32 * kCvWaves));
+  *n_blocks = nb;
+  if (p.bf16)
+    hipLaunchKernelGGL((cv_kernel<true, false>), dim3(nb), dim3(kCvThreads), 0, s, p);
+  else
+    hipLaunchKernelGGL((cv_kernel<false, false>), dim3(nb), dim3(kCvThreads), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_cv_backward(const CvParams& p, hipStream_t s, uint32_t* n_blocks) {
+  const uint32_t nb = (uint32_t)((p.h.n_paths + 32 * kCvWaves - 1) / (32 * kCvWaves));
+  *n_blocks = nb;
+  if (p.bf16)
+    hipLaunchKernelGGL((cv_kernel<true, true>), dim3(nb), dim3(kCvThreads), 0, s, p);
+  else
+    hipLaunchKernelGGL((cv_kernel<false, true>), dim3(nb), dim3(kCvThreads), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* theta, float* m, float* v, const double* grad, int n, int t,
+                       double lr, double b1, double b2, double eps, hipStream_t s) {
+  const float c1 = (float)(1.0 - std::pow(b1, t)), c2 = (float)(1.0 - std::pow(b2, t));
+  hipLaunchKernelGGL(adam_kernel, dim3((n + 255) / 256), dim3(256), 0, s, theta, m, v, grad, n,
+                     (float)lr, (float)b1, (float)b2, (float)eps, c1, c2);
+  return hipGetLastError();
+}
+
+}  // namespace mcp

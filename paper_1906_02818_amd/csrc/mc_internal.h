@@ -94,6 +94,39 @@ struct BasketParams {
 uint32_t basket_blocks_nd(uint32_t d);
 hipError_t launch_basket(const BasketParams& p, int prec, hipStream_t s, uint32_t* n_blocks);
 
+// ---- Learned martingale control variate (Heston Asian) ----
+// Hedge network 4 -> 64 -> 64 -> 1 with tanh, run on MFMA for 32 paths per
+// wave. Host-packed per-lane fragments (see api.hip, pack_mlp):
+constexpr int kMlpH = 64;
+constexpr int kMlpNParam = 4545;
+struct CvParams {
+  HestonParams h;
+  uint32_t hedge_every;      // rebalancing period m
+  int bf16;                  // 1: BF16 MFMA operands, 0: FP32 MFMA
+  const float* theta;        // [4545] flat weights (b3 is read from here)
+  const float* w1f;          // [2 mb][64 lane][8]   layer-1 A fragments (W1 | b1 | 0)
+  const float* w2f;          // [2 mb][4 kb][64][8]  layer-2 A fragments (permuted W2)
+  const float* w2tf;         // [2 mb][4 kb][64][8]  W2^T fragments for the backward pass
+  const float* lanec;        // [2][64][32]: per-lane b2 * (-2 / ln 2), W3 of the lane's units
+  const float* dfac;         // [n_steps + 1]: e^{r t_i}
+  // training
+  const double* ybar_mom;    // moments of the forward pass (Ybar = sum y2 / n)
+  const double* y_path;      // per-path values of that pass, [n_paths][3] (Y is channel 2)
+  double g_scale;            // -2 / B
+  double* grad_partials;     // [kMlpNParam][n_waves] FP64
+  double* partials;
+  double* path_out;
+};
+constexpr int kCvPathsPerBlock = 128;   // 4 waves of 32 paths
+// Fragment layout of the weights, built on the device from theta.
+constexpr int kW1fFloats = 2 * 64 * 8, kW2fFloats = 2 * 4 * 64 * 8, kLanecFloats = 2 * 64 * 32;
+hipError_t launch_cv_pack(const float* theta, float* w1f, float* w2f, float* w2tf, float* lanec,
+                          hipStream_t s);
+hipError_t launch_cv_price(const CvParams& p, hipStream_t s, uint32_t* n_blocks);
+hipError_t launch_cv_backward(const CvParams& p, hipStream_t s, uint32_t* n_blocks);
+hipError_t launch_adam(float* theta, float* m, float* v, const double* grad, int n, int t,
+                       double lr, double b1, double b2, double eps, hipStream_t s);
+
 // ---- reductions and diagnostics ----
 hipError_t launch_final_reduce(const double* partials, uint32_t n_blocks, uint32_t n_mom,
                                double* out, hipStream_t s);

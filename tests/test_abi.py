@@ -166,3 +166,22 @@ def test_basket_validation_without_device():
     assert mc.mc_validate(_basket(), mc.Payoff(mc.MC_EURO_CALL, 100.0), 1024, 10) == \
         mc._abi.MC_ERR_UNSUPPORTED
     assert mc.mc_path_channels(_basket(), f) == ["basket", "geo_basket", "basket_delta0"]
+
+
+def test_learned_cv_validation_without_device():
+    w = np.zeros(4545, np.float32)
+    f = mc.Payoff(mc.MC_ASIAN_ARITH_CALL, 100.0, cv=mc.MC_CV_LEARNED)
+    assert mc.mc_validate(HES, f, 1024, 256, mc.Options(cv_weights=w)) == mc.MC_OK
+    assert mc.mc_validate(HES, f, 1024, 256, mc.Options(cv_weights=w, prec=mc.MC_BF16_GEMM)) \
+        == mc.MC_OK
+    assert mc.mc_validate(HES, f, 1024, 256) == mc._abi.MC_ERR_INVALID_ARG          # no weights
+    assert mc.mc_validate(HES, f, 1024, 256, mc.Options(cv_weights=w, prec=mc.MC_FP64)) == \
+        mc._abi.MC_ERR_UNSUPPORTED
+    assert mc.mc_validate(HES, mc.Payoff(mc.MC_EURO_CALL, 100.0, cv=mc.MC_CV_LEARNED), 1024, 256,
+                          mc.Options(cv_weights=w)) == mc._abi.MC_ERR_UNSUPPORTED
+    assert mc.mc_validate(HES, f, 1024, 256, mc.Options(cv_weights=w, greeks=1)) == \
+        mc._abi.MC_ERR_UNSUPPORTED
+    h0 = mc.Model(kind=mc.MC_HESTON, S0=100.0, v0=0.04, kappa=2, theta=0.0, xi=0.5, rho=-0.7)
+    assert mc.mc_validate(h0, f, 1024, 256, mc.Options(cv_weights=w)) == mc._abi.MC_ERR_INVALID_ARG
+    assert mc.mc_path_channels(HES, f, mc.Options(cv_weights=w)) == \
+        ["asian", "hedge_pnl", "asian_minus_hedge"]

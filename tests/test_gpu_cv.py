@@ -1,0 +1,137 @@
+"""GPU parity of the learned martingale control variate against the FP64
+oracle: per-path payoff / hedge P&L / estimator values, the zero mean of the
+hedge for arbitrary weights, the loss gradient of the training kernels
+(FP32 and BF16 matrix products), Adam steps, the variance reduction of a
+trained network on fresh paths, and the fallback to plain Monte Carlo."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1906_02818_amd as mc
+import synth
+
+pytestmark = pytest.mark.gpu
+SEED = synth.SEED
+H = {k: synth.HESTON[k] for k in ("S0", "v0", "kappa", "theta", "xi", "rho", "r", "T", "K")}
+MODEL = mc.Model(kind=mc.MC_HESTON, S0=H["S0"], r=H["r"], T=H["T"], v0=H["v0"],
+                 kappa=H["kappa"], theta=H["theta"], xi=H["xi"], rho=H["rho"])
+PAY = mc.Payoff(mc.MC_ASIAN_ARITH_CALL, H["K"], cv=mc.MC_CV_LEARNED)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = mc.mc_create(0)
+    yield c
+    c.close()
+
+
+def weights(scale=0.3, seed=3):
+    rng = np.random.default_rng(seed)
+    th = synth.glorot_mlp() + rng.normal(0.0, scale, 4545)
+    return th.astype(np.float32).astype(np.float64)     # exactly representable in FP32
+
+
+@pytest.mark.parametrize("m_every,N,n", [(1, 2048, 32), (4, 2000, 33), (3, 512, 7)])
+def test_cv_eval_parity_fp32(ctx, m_every, N, n):
+    say("cv eval", m_every, N, n)
+    th = weights()
+    r = mc.mc_price(ctx, MODEL, PAY, N, n, SEED,
+                    mc.Options(prec=mc.MC_FP32, cv_weights=th, cv_hedge_every=m_every,
+                               path_values=True, pilot_paths=1024))
+    assert r["cv_fallback"] == 0
+    o = oracle.heston_cv(H, n, th, N, SEED, m_every=m_every)
+    pv = r["path_values"]
+    np.testing.assert_allclose(pv[:, 0], o[:, 0], rtol=3e-4, atol=3e-4)
+    err = np.abs(pv[:, 1] - o[:, 1])
+    say("  hedge P&L max abs err", err.max(), "typical |H|", np.abs(o[:, 1]).mean())
+    assert err.max() < 2e-3 * (1 + np.abs(o[:, 1]).max())
+    e = oracle.estimate(o[:, 2])
+    assert abs(r["price"] - e["price"]) < 2e-5 * abs(e["price"]) + 1e-4 * e["std_err"]
+
+
+def test_hedge_has_zero_mean_on_gpu(ctx):
+    th = weights(0.5, seed=8)
+    for prec in (mc.MC_FP32, mc.MC_BF16_GEMM):
+        r = mc.mc_price(ctx, MODEL, PAY, 1 << 18, 64, SEED,
+                        mc.Options(prec=prec, cv_weights=th, path_values=True, pilot_paths=1024))
+        h = r["path_values"][:, 1]
+        se = h.std(ddof=1) / math.sqrt(h.size)
+        say(f"  prec {prec}: mean H {h.mean():.3e} se {se:.3e}; price {r['price']:.5f} "
+            f"plain {r['plain_price']:.5f}")
+        assert abs(h.mean()) < 4 * se
+        assert abs(r["price"] - r["plain_price"]) < 3 * math.hypot(r["std_err"], r["plain_std_err"])
+
+
+@pytest.mark.parametrize("prec,tol", [(mc.MC_FP32, 1e-4), (mc.MC_BF16_GEMM, 2e-2)])
+@pytest.mark.parametrize("m_every,n", [(1, 16), (2, 15)])
+def test_loss_gradient_matches_oracle(ctx, prec, tol, m_every, n):
+    th = weights(0.2, seed=5)
+    B = 512
+    say("grad", prec, m_every, n)
+    loss, g = mc.mc_cv_loss_grad(ctx, MODEL, PAY, n, SEED, 2, 1024, B, th, hedge_every=m_every,
+                                 prec=prec)
+    lo, go = oracle.cv_loss_grad(H, n, th, B, SEED, tag=2, path0=1024, m_every=m_every)
+    rel = np.linalg.norm(g - go) / np.linalg.norm(go)
+    say(f"  loss gpu {loss:.6f} oracle {lo:.6f}; grad rel-L2 {rel:.2e}")
+    assert abs(loss - lo) < (1e-5 if prec == mc.MC_FP32 else 1e-2) * lo
+    assert rel < tol
+    # Each parameter block carries gradient (W1, b1, W2, b2, W3, b3).
+    for a, b in ((0, 256), (256, 320), (320, 4416), (4416, 4480), (4480, 4544), (4544, 4545)):
+        blk = np.linalg.norm(g[a:b] - go[a:b]) / max(np.linalg.norm(go[a:b]), 1e-30)
+        assert blk < 10 * tol, (a, b, blk)
+
+
+def test_adam_steps_match_oracle(ctx):
+    th0 = weights(0.2, seed=6)
+    B, n, steps, lr = 256, 8, 4, 1e-3
+    w, log = mc.mc_cv_train(ctx, MODEL, PAY, 2 * B, n, SEED, th0, lr=lr, steps=steps, batch=B,
+                            hedge_every=1, prec=mc.MC_FP32)
+    th = th0.copy()
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    losses = []
+    for t in range(1, steps + 1):
+        loss, g = oracle.cv_loss_grad(H, n, th, B, SEED, tag=2, path0=((t - 1) % 2) * B)
+        losses.append(loss)
+        th, m, v = oracle.adam_step(th, g, m, v, t, lr=lr)
+    say("  losses gpu", log, "oracle", losses)
+    np.testing.assert_allclose(log, losses, rtol=1e-4)
+    d = np.abs(w - th)
+    say("  weight diff max", d.max(), "frac > 1e-5:", np.mean(d > 1e-5))
+    # A gradient component near zero may flip sign in FP32 and move its
+    # parameter by 2 lr in the first steps; all others agree closely.
+    assert np.mean(d > 1e-5) < 0.01
+    assert d.max() <= 2 * lr * steps + 1e-6
+
+
+def test_trained_hedge_reduces_variance_on_fresh_paths(ctx):
+    n = 64
+    th0 = synth.glorot_mlp()
+    for prec in (mc.MC_FP32, mc.MC_BF16_GEMM):
+        w, log = mc.mc_cv_train(ctx, MODEL, PAY, 1 << 16, n, SEED, th0, lr=3e-3, steps=150,
+                                batch=1 << 13, prec=prec)
+        assert np.all(np.isfinite(w))
+        say(f"  prec {prec}: loss {log[0]:.3f} -> {log[-10:].mean():.3f}")
+        assert log[-10:].mean() < 0.5 * log[0]
+        r = mc.mc_price(ctx, MODEL, PAY, 1 << 20, n, SEED, mc.Options(prec=prec, cv_weights=w))
+        say(f"  fresh paths: price {r['price']:.5f} +- {r['std_err']:.5f}, plain "
+            f"{r['plain_price']:.5f} +- {r['plain_std_err']:.5f}, VRF {r['vrf']:.2f}")
+        assert r["cv_fallback"] == 0 and r["vrf"] > 2.0
+        assert abs(r["price"] - r["plain_price"]) < 3 * r["plain_std_err"]
+
+
+def test_fallback_to_plain_when_hedge_hurts(ctx):
+    # Very large weights make the hedge P&L noise: the pilot sees VRF < 1 and
+    # the call returns the plain Monte Carlo estimate.
+    th = weights(30.0, seed=9)
+    r = mc.mc_price(ctx, MODEL, PAY, 1 << 16, 32, SEED, mc.Options(cv_weights=th))
+    plain = mc.mc_price(ctx, MODEL, mc.Payoff(mc.MC_ASIAN_ARITH_CALL, H["K"]), 1 << 16, 32, SEED)
+    say("  fallback", r["cv_fallback"], "pilot vrf", r["vrf"])
+    assert r["cv_fallback"] == 1 and r["vrf"] < 1.0
+    assert r["price"] == plain["price"] and r["std_err"] == plain["std_err"]
