@@ -123,7 +123,11 @@ typedef struct {
     size_t workspace_bytes;
     const float *cv_weights;   /* [MC_MLP_NPARAM] host, for MC_CV_LEARNED */
     uint32_t cv_hedge_every;   /* learned hedge rebalanced every m steps (>= 1) */
-    double cv_beta;            /* static-CV coefficient; NaN = estimate on a pilot */
+    double cv_beta;            /* control-variate coefficient. Static CV: NaN = estimate
+                                  on a pilot. Learned CV: Y = payoff - cv_beta H; NaN =
+                                  1 with a pilot run deciding between the hedged
+                                  estimator and plain MC (mc_result.cv_fallback);
+                                  on fallback path_values are not written */
     uint64_t pilot_paths;      /* pilot size (tag 1) for beta / fallback; 0 = 2^16 */
     double *path_values;       /* optional host [n_paths * mc_path_channels()]
                                   per-path values (testing and diagnostics) */

@@ -636,28 +636,33 @@ mc_status heston_cv_price(mc_context* ctx, const mc_model* m, const mc_payoff* f
   o.workspace_bytes = Lay.bytes;
   const bool bf16 = o0.prec == MC_BF16_GEMM;
   double kms = 0.0;
-  // Pilot on stream tag+1: plain MC is the fallback when the hedge does not
-  // reduce the variance there.
-  mc_options po = o;
-  po.path_offset = 0;
-  po.path_values = nullptr;
-  Moments pm;
-  st = cv_eval(ctx, po, cv_params(m, f, n_pilot, n_steps, seed, po, o0.stream_tag + 1,
-                                   o0.cv_hedge_every, bf16, b),
-               n_pilot, nullptr, &pm, &kms);
-  if (st != MC_OK) return st;
-  const double pilot_vrf = pm.cov(0, 0) / pm.cov(2, 2);
-  if (!(pilot_vrf > 1.0)) {
-    mc_options plain = o0;
-    plain.path_values = nullptr;
-    mc_payoff fp = *f;
-    fp.cv = MC_CV_NONE;
-    st = heston_price(ctx, m, &fp, n_paths, n_steps, seed, plain, out);
+  // Y = payoff - beta H. A finite cv_beta is the caller's choice; NaN means
+  // beta = 1 (the hedge as trained) with a pilot on stream tag+1 deciding
+  // between the hedged estimator and plain Monte Carlo.
+  const bool fixed = std::isfinite(o0.cv_beta);
+  const double beta = fixed ? o0.cv_beta : 1.0;
+  if (!fixed) {
+    mc_options po = o;
+    po.path_offset = 0;
+    po.path_values = nullptr;
+    Moments pm;
+    st = cv_eval(ctx, po, cv_params(m, f, n_pilot, n_steps, seed, po, o0.stream_tag + 1,
+                                     o0.cv_hedge_every, bf16, b),
+                 n_pilot, nullptr, &pm, &kms);
     if (st != MC_OK) return st;
-    out->cv_fallback = 1;
-    out->vrf = pilot_vrf;
-    out->kernel_ms += kms;
-    return MC_OK;
+    const double pilot_vrf = pm.cov(0, 0) / pm.cov(2, 2);
+    if (!(pilot_vrf > 1.0)) {
+      mc_options plain = o0;
+      plain.path_values = nullptr;
+      mc_payoff fp = *f;
+      fp.cv = MC_CV_NONE;
+      st = heston_price(ctx, m, &fp, n_paths, n_steps, seed, plain, out);
+      if (st != MC_OK) return st;
+      out->cv_fallback = 1;
+      out->vrf = pilot_vrf;
+      out->kernel_ms += kms;
+      return MC_OK;
+    }
   }
   Moments mom;
   st = cv_eval(ctx, o, cv_params(m, f, n_paths, n_steps, seed, o, o0.stream_tag, o0.cv_hedge_every,
@@ -665,10 +670,13 @@ mc_status heston_cv_price(mc_context* ctx, const mc_model* m, const mc_payoff* f
                n_paths, o0.path_values, &mom, &kms);
   if (st != MC_OK) return st;
   mc_result r{};
-  fill_channel(mom, 2, &r.price, &r.variance, &r.std_err);
   double v;
   fill_channel(mom, 0, &r.plain_price, &v, &r.plain_std_err);
-  r.vrf = mom.cov(0, 0) / mom.cov(2, 2);
+  r.price = mom.mean(0) - beta * mom.mean(1);
+  r.variance = mom.cov(0, 0) - 2.0 * beta * mom.cov(0, 1) + beta * beta * mom.cov(1, 1);
+  r.std_err = std::sqrt(r.variance / mom.n);
+  r.cv_beta = beta;
+  r.vrf = mom.cov(0, 0) / r.variance;
   r.n_paths = (uint64_t)mom.n;
   r.n_nonfinite = (uint64_t)mom.nonfinite;
   r.kernel_ms = kms;

@@ -43,8 +43,8 @@ def test_cv_eval_parity_fp32(ctx, m_every, N, n):
     th = weights()
     r = mc.mc_price(ctx, MODEL, PAY, N, n, SEED,
                     mc.Options(prec=mc.MC_FP32, cv_weights=th, cv_hedge_every=m_every,
-                               path_values=True, pilot_paths=1024))
-    assert r["cv_fallback"] == 0
+                               path_values=True, cv_beta=1.0))
+    assert r["cv_fallback"] == 0 and r["cv_beta"] == 1.0
     o = oracle.heston_cv(H, n, th, N, SEED, m_every=m_every)
     pv = r["path_values"]
     np.testing.assert_allclose(pv[:, 0], o[:, 0], rtol=3e-4, atol=3e-4)
@@ -59,7 +59,7 @@ def test_hedge_has_zero_mean_on_gpu(ctx):
     th = weights(0.5, seed=8)
     for prec in (mc.MC_FP32, mc.MC_BF16_GEMM):
         r = mc.mc_price(ctx, MODEL, PAY, 1 << 18, 64, SEED,
-                        mc.Options(prec=prec, cv_weights=th, path_values=True, pilot_paths=1024))
+                        mc.Options(prec=prec, cv_weights=th, path_values=True, cv_beta=1.0))
         h = r["path_values"][:, 1]
         se = h.std(ddof=1) / math.sqrt(h.size)
         say(f"  prec {prec}: mean H {h.mean():.3e} se {se:.3e}; price {r['price']:.5f} "
