@@ -1,12 +1,14 @@
 // Issue-rate microbenchmark for the VALU instructions the path kernels are
-// made of: the 32x32->64 integer multiply of Philox (v_mad_u64_u32), the
-// mul-hi/lo pair, FP32 and FP64 FMA and the transcendental unit
-// (v_exp/log/sin/sqrt_f32). Each thread runs 8 independent dependency chains
-// so that latency is hidden; the result is wave64 instructions per cycle per
-// CU, from which the kernels' ALU roofline is derived. Standalone program:
+// made of: the 32x32->64 integer product of Philox (v_mad_u64_u32, or the
+// v_mul_hi_u32 / v_mul_lo_u32 pair), 32-bit xor, FP32 and FP64 FMA, and the
+// transcendental unit (v_exp/log/sin/sqrt/rcp_f32). Each chain step is ONE
+// instruction of the measured kind (sign and absolute value are free source
+// modifiers), each thread runs 8 independent chains and every SIMD holds 8
+// waves, so latency is hidden. Output: wave64 instructions per clock per CU
+// and the issue cost relative to v_fma_f32 ("slots"), from which the path
+// kernels' ALU roofline is derived.
 //   hipcc --offload-arch=gfx950 -O3 isa_rates.hip -o isa_rates && ./isa_rates
-// Only one store per thread touches memory (to keep the chains alive); the
-// output buffer holds exactly grid*block elements.
+// Memory: one store per thread into a buffer of exactly grid x block words.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -24,7 +26,7 @@
 constexpr int kIters = 2048;
 constexpr int kChains = 8;
 
-enum Op { MAD_U64, MULHI_LO, FMA_F32, EXP_F32, LOG_F32, SIN_F32, SQRT_F32, FMA_F64 };
+enum Op { FMA_F32, MAD_U64, MUL_HI, MUL_LO, XOR, EXP_F32, LOG_F32, SIN_F32, SQRT_F32, RCP_F32, FMA_F64 };
 
 template <int OP>
 __global__ __launch_bounds__(256) void rate_kernel(unsigned* out, unsigned seed) {
@@ -34,28 +36,36 @@ __global__ __launch_bounds__(256) void rate_kernel(unsigned* out, unsigned seed)
   double d[kChains];
 #pragma unroll
   for (int c = 0; c < kChains; ++c) {
-    a[c] = t * 2654435761u + seed + c;
+    a[c] = t * 2654435761u + seed + 977u * c;
     f[c] = 0.5f + 1e-7f * (float)(t & 1023) + 0.01f * c;
     d[c] = (double)f[c];
   }
+  unsigned key = seed * 0x9E3779B9u;
   for (int it = 0; it < kIters; ++it) {
+    key += 0xBB67AE85u;                                  // scalar, keeps the xor chain alive
 #pragma unroll
     for (int c = 0; c < kChains; ++c) {
-      if constexpr (OP == MAD_U64) {
-        const unsigned long long p = (unsigned long long)a[c] * 0xD2511F53ull;
-        a[c] = (unsigned)(p >> 32) ^ (unsigned)p;   // 1 mad + 1 xor
-      } else if constexpr (OP == MULHI_LO) {
-        a[c] = __umulhi(a[c], 0xCD9E8D57u) ^ (a[c] * 0xCD9E8D57u);
-      } else if constexpr (OP == FMA_F32) {
+      if constexpr (OP == FMA_F32) {
         f[c] = __builtin_fmaf(f[c], 0.999f, 1e-3f);
+      } else if constexpr (OP == MAD_U64) {
+        const unsigned long long p = (unsigned long long)a[c] * 0xD2511F53ull;
+        a[c] = (unsigned)(p >> 32) ^ (unsigned)p;        // v_mad_u64_u32 + v_xor_b32
+      } else if constexpr (OP == MUL_HI) {
+        a[c] = __umulhi(a[c], 0xCD9E8D57u);
+      } else if constexpr (OP == MUL_LO) {
+        a[c] = a[c] * 0xCD9E8D57u;
+      } else if constexpr (OP == XOR) {
+        a[c] = a[c] ^ key;
       } else if constexpr (OP == EXP_F32) {
-        f[c] = __builtin_amdgcn_exp2f(f[c]) * -0.5f;
+        f[c] = __builtin_amdgcn_exp2f(-f[c]);            // converges, stays finite
       } else if constexpr (OP == LOG_F32) {
-        f[c] = __builtin_amdgcn_logf(f[c]) * -0.5f + 1.5f;
+        f[c] = __builtin_amdgcn_logf(__builtin_fabsf(f[c]) + 1.0f);   // log + add
       } else if constexpr (OP == SIN_F32) {
         f[c] = __builtin_amdgcn_sinf(f[c]);
       } else if constexpr (OP == SQRT_F32) {
-        f[c] = __builtin_amdgcn_sqrtf(f[c]) + 0.25f;
+        f[c] = __builtin_amdgcn_sqrtf(f[c]);
+      } else if constexpr (OP == RCP_F32) {
+        f[c] = __builtin_amdgcn_rcpf(f[c]);
       } else if constexpr (OP == FMA_F64) {
         d[c] = __builtin_fma(d[c], 0.999, 1e-3);
       }
@@ -96,24 +106,28 @@ int main() {
   CHECK(hipEventCreate(&e0));
   CHECK(hipEventCreate(&e1));
   std::printf("device %s, %d CUs, clock %.3f GHz\n", prop.name, cus, clk_ghz);
-  const double waves = (double)blocks * threads / 64.0;
-  const double steps = waves * kIters * kChains;   // wave64 chain steps
-  struct Row { const char* name; double ms; double insts_per_step; };
+  const double steps = (double)blocks * threads / 64.0 * kIters * kChains;   // wave64 chain steps
+  struct Row { const char* name; double ms; double extra; };   // extra: helper insts per step
   Row rows[] = {
-      {"v_mad_u64_u32 (+1 xor)", run<MAD_U64>(d_out, blocks, threads, e0, e1), 2.0},
-      {"v_mul_hi_u32+v_mul_lo_u32 (+1 xor)", run<MULHI_LO>(d_out, blocks, threads, e0, e1), 3.0},
-      {"v_fma_f32", run<FMA_F32>(d_out, blocks, threads, e0, e1), 1.0},
-      {"v_exp_f32 (+1 mul)", run<EXP_F32>(d_out, blocks, threads, e0, e1), 2.0},
-      {"v_log_f32 (+1 fma)", run<LOG_F32>(d_out, blocks, threads, e0, e1), 2.0},
-      {"v_sin_f32", run<SIN_F32>(d_out, blocks, threads, e0, e1), 1.0},
-      {"v_sqrt_f32 (+1 add)", run<SQRT_F32>(d_out, blocks, threads, e0, e1), 2.0},
-      {"v_fma_f64", run<FMA_F64>(d_out, blocks, threads, e0, e1), 1.0},
+      {"v_fma_f32", run<FMA_F32>(d_out, blocks, threads, e0, e1), 0.0},
+      {"v_mad_u64_u32 (+ v_xor_b32)", run<MAD_U64>(d_out, blocks, threads, e0, e1), 1.0},
+      {"v_mul_hi_u32", run<MUL_HI>(d_out, blocks, threads, e0, e1), 0.0},
+      {"v_mul_lo_u32", run<MUL_LO>(d_out, blocks, threads, e0, e1), 0.0},
+      {"v_xor_b32", run<XOR>(d_out, blocks, threads, e0, e1), 0.0},
+      {"v_exp_f32", run<EXP_F32>(d_out, blocks, threads, e0, e1), 0.0},
+      {"v_log_f32 (+ v_add_f32)", run<LOG_F32>(d_out, blocks, threads, e0, e1), 1.0},
+      {"v_sin_f32", run<SIN_F32>(d_out, blocks, threads, e0, e1), 0.0},
+      {"v_sqrt_f32", run<SQRT_F32>(d_out, blocks, threads, e0, e1), 0.0},
+      {"v_rcp_f32", run<RCP_F32>(d_out, blocks, threads, e0, e1), 0.0},
+      {"v_fma_f64", run<FMA_F64>(d_out, blocks, threads, e0, e1), 0.0},
   };
-  std::printf("%-36s %10s %16s %18s\n", "op", "ms", "chain steps/clk/CU", "wave-insts/clk/CU");
+  const double fma_rate = steps / (rows[0].ms * 1e-3 * clk_ghz * 1e9) / cus;
+  std::printf("%-26s %10s %18s %12s\n", "op", "ms", "wave-insts/clk/CU", "slots");
   for (const Row& r : rows) {
-    const double cycles = r.ms * 1e-3 * clk_ghz * 1e9;
-    const double per_cu = steps / cycles / cus;
-    std::printf("%-36s %10.4f %16.4f %18.4f\n", r.name, r.ms, per_cu, per_cu * r.insts_per_step);
+    const double rate = steps / (r.ms * 1e-3 * clk_ghz * 1e9) / cus;   // chain steps
+    // slots of the measured instruction: step cost minus the helper's (1 slot each)
+    const double slots = fma_rate / rate - r.extra;
+    std::printf("%-26s %10.4f %18.4f %12.3f\n", r.name, r.ms, rate, slots);
   }
   CHECK(hipFree(d_out));
   return 0;
