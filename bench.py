@@ -179,16 +179,17 @@ def main():
                mc.Payoff(mc.MC_UO_BARRIER_CALL, c["K"], B=c["B"]),
                mc.Payoff(mc.MC_ASIAN_GEO_CALL, c["K"])]
     opts = mc.Options(cv_beta=beta)
+    step = mc.PreparedPriceMulti(ctx, model, payoffs, N, n, synth.SEED, opts)
     for _ in range(args.warmup):
-        mc.mc_price_multi(ctx, model, payoffs, N, n, synth.SEED, opts)
+        step()
     torch.cuda.synchronize()
     kernel_ms = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        res = mc.mc_price_multi(ctx, model, payoffs, N, n, synth.SEED, opts)
-        kernel_ms.append(res[0]["kernel_ms"])
+        kernel_ms.append(step()[0].kernel_ms)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    res = step.results()
     ms = (t1 - t0) * 1e3 / args.steps
     path_steps = N * n
     k_ms = sum(kernel_ms) / len(kernel_ms)

@@ -27,7 +27,7 @@ __all__ = [n for n in dir(_abi) if n.startswith("MC_")] + [
     "mc_price", "mc_price_multi", "mc_greeks_adjoint", "mc_cv_train", "mc_cv_loss_grad",
     "mc_philox_words", "mc_normals", "mc_path_channels", "mc_path_channel_name",
     "mc_workspace_bytes", "mc_adjoint_ckpt_bytes", "mc_status_str", "mc_last_error",
-    "PathwisePrice"]
+    "PathwisePrice", "PreparedPriceMulti"]
 
 
 class McError(RuntimeError):
@@ -291,6 +291,30 @@ def mc_price_multi(ctx: Context, model: Model, payoffs: Sequence[Payoff], n_path
                                     n_steps, seed, C.byref(mm.co), res)
     _check(ctx, st)
     return [_result(r) for r in res]
+
+
+class PreparedPriceMulti:
+    """mc_price_multi with its arguments marshalled once: calling it only
+    invokes the C entry point, for tight repeated pricing loops."""
+
+    def __init__(self, ctx: Context, model: Model, payoffs: Sequence[Payoff], n_paths: int,
+                 n_steps: int, seed: int, opts: Options | None = None):
+        self.ctx = ctx
+        self.mm = _Marshal(model, list(payoffs), opts, n_paths)
+        self.args = (n_paths, n_steps, seed)
+        self.res = (_abi.McResult * len(payoffs))()
+        self.fn = _abi.load().mc_price_multi
+        self.cm = C.byref(self.mm.cm)
+        self.co = C.byref(self.mm.co)
+        self.n = len(payoffs)
+
+    def __call__(self):
+        st = self.fn(self.ctx.handle, self.cm, self.mm.cps, self.n, *self.args, self.co, self.res)
+        _check(self.ctx, st)
+        return self.res
+
+    def results(self) -> list[dict]:
+        return [_result(r) for r in self.res]
 
 
 def mc_greeks_adjoint(ctx: Context, model: Model, payoff: Payoff, n_paths: int, n_steps: int,

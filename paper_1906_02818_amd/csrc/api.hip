@@ -277,7 +277,7 @@ mc_status run_moments(mc_context* ctx, const mc_options& o, uint64_t n_paths, in
   uint32_t nb = 0;
   HIP_TRY(ctx, launch(partials, path_out, s, &nb));
   HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));
-  if (nb != L.n_blocks) return fail(ctx, MC_ERR_DEVICE, "block count mismatch");
+  if (nb == 0 || nb > L.n_blocks) return fail(ctx, MC_ERR_DEVICE, "block count mismatch");
   HIP_TRY(ctx, launch_final_reduce(partials, nb, L.n_mom, mom, s));
   HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, mom, L.n_mom * sizeof(double), hipMemcpyDeviceToHost, s));
   if (path_out)
@@ -698,7 +698,8 @@ struct CvTrainWs {
 
 size_t cv_train_bytes(uint64_t batch, uint32_t n_steps, uint32_t steps, CvTrainWs* w, char* base) {
   const RunLayout Lay = layout_for(batch, 3, true, kCvPathsPerBlock);
-  const uint64_t n_waves = (uint64_t)Lay.n_blocks * (kCvPathsPerBlock / 32);
+  const uint64_t n_waves =
+      (batch + kCvTrainPathsPerBlock - 1) / kCvTrainPathsPerBlock * (kCvTrainPathsPerBlock / 32);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     char* p = base ? base + off : nullptr;
@@ -750,7 +751,7 @@ mc_status cv_loss_grad_device(mc_context* ctx, hipStream_t s, const mc_model* m,
   p.g_scale = -2.0 / (double)batch;
   p.grad_partials = w.grad_partials;
   HIP_TRY(ctx, launch_cv_backward(p, s, &nb));
-  const uint32_t n_waves = nb * (kCvPathsPerBlock / 32);
+  const uint32_t n_waves = nb * (kCvTrainPathsPerBlock / 32);
   HIP_TRY(ctx, launch_final_reduce(w.grad_partials, n_waves, kMlpNParam, w.grad, s));
   return MC_OK;
 }

@@ -52,4 +52,47 @@ __device__ __forceinline__ void block_moments(const double (&y)[C], bool valid, 
   }
 }
 
+// Per-thread running moments over several paths (same layout as above):
+// acc[0] valid count, acc[1] non-finite count, acc[2 + c] sum y_c, then
+// sum y_a y_b for a <= b.
+template <int C>
+__device__ __forceinline__ void accumulate_moments(double (&acc)[2 + C + C * (C + 1) / 2],
+                                                   const double (&y)[C], bool valid,
+                                                   bool nonfinite) {
+  if (nonfinite) acc[1] += 1.0;
+  if (!valid) return;
+  acc[0] += 1.0;
+  int m = 2;
+#pragma unroll
+  for (int a = 0; a < C; ++a) acc[m++] += y[a];
+#pragma unroll
+  for (int a = 0; a < C; ++a)
+#pragma unroll
+    for (int b = a; b < C; ++b) acc[m++] += y[a] * y[b];
+}
+
+// Block sum of per-thread moment vectors, written to
+// partials[m * n_blocks + block] (fixed wave-butterfly and wave order).
+template <int M, int BLOCK>
+__device__ __forceinline__ void block_reduce_moments(const double (&acc)[M],
+                                                     double* __restrict__ partials,
+                                                     uint32_t n_blocks) {
+  constexpr int W = BLOCK / 64;
+  __shared__ double red[M][W];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const double v = wave_sum(acc[m]);
+    if (lane == 0) red[m][wave] = v;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < M; t += BLOCK) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) s += red[t][w];
+    partials[(size_t)t * n_blocks + blockIdx.x] = s;
+  }
+}
+
 }  // namespace mcp

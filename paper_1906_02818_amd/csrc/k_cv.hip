@@ -381,6 +381,99 @@ __global__ __launch_bounds__(kCvThreads) void cv_kernel(const CvParams P) {
   }
 }
 
+// Evaluation kernel, 64 paths per wave: lane l follows its own path, and
+// at each rebalancing date the network runs twice, for the sub-tiles of
+// paths 0..31 and 32..63 of the wave. Layer 1 takes its features from half 0
+// of the lanes, so for the second sub-tile half 0 fetches the features of
+// its partner lane (l ^ 32); each lane then keeps Delta of its own sub-tile.
+// A path's network output depends only on its own MFMA column, so it is the
+// same function the training kernel evaluates.
+template <bool BF16>
+__global__ __launch_bounds__(kCvThreads) void cv_eval_kernel(const CvParams P) {
+  __shared__ __attribute__((aligned(16))) float s_w2f[kFragFloats];
+  __shared__ __attribute__((aligned(16))) float s_lanec[kLaneFloats];
+  const HestonParams& Hp = P.h;
+  for (int i = threadIdx.x; i < kFragFloats; i += kCvThreads) s_w2f[i] = P.w2f[i];
+  for (int i = threadIdx.x; i < kLaneFloats; i += kCvThreads) s_lanec[i] = P.lanec[i];
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int half = lane >> 5;
+  const uint64_t pid = ((uint64_t)blockIdx.x * kCvWaves + wave) * 64 + lane;
+  const bool active = pid < Hp.n_paths;
+  float w1a[2][8];
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb) load8(&P.w1f[(mb * 64 + lane) * 8], w1a[mb]);
+  const float b3 = P.theta[4544];
+
+  const float dt = (float)Hp.dt, kdt = (float)(Hp.kappa * Hp.dt);
+  const float kthdt = (float)(Hp.kappa * Hp.theta * Hp.dt), xi = (float)Hp.xi;
+  const float rho = (float)Hp.rho, rhoc = (float)Hp.rho_c;
+  const float a1 = (float)(-0.5 * Hp.dt * 1.4426950408889634), a2 = 1.4426950408889634f;
+  const float S0 = (float)Hp.S0, K = (float)Hp.K;
+  const float lnS0K = (float)std::log(Hp.S0 / Hp.K), ln2 = 0.69314718055994531f;
+  const float rdt2 = (float)(Hp.r * Hp.dt * 1.4426950408889634);
+  const float inv_theta = (float)(1.0 / Hp.theta);
+  const uint32_t n = Hp.n_steps, m = P.hedge_every;
+  const PathCounter pc = make_counter(Hp.path_offset + pid, Hp.tag, Hp.k0, Hp.k1);
+
+  float z = 0.f, v = (float)Hp.v0, sumE = 0.f, H = 0.f, delta = 0.f, st_open = 0.f, Et = 1.f;
+  float h1[32], h2[32];
+  Normals4<float> nz;
+  for (uint32_t i = 0; i < n; ++i) {
+    if (i % m == 0) {
+      const float fi = (float)i;
+      const float Abar = (i == 0) ? 1.0f : sumE / fi;
+      const float own[4] = {fi / (float)n, (z + rdt2 * fi) * ln2 + lnS0K, v * inv_theta,
+                            Abar * S0 / K - 1.0f};
+      float other[4];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) other[f] = __shfl_xor(own[f], 32, 64);
+#pragma unroll 1
+      for (int sub = 0; sub < 2; ++sub) {
+        float phi[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) phi[j] = 0.f;
+        if (half == 0) {
+#pragma unroll
+          for (int f = 0; f < 4; ++f) phi[f] = sub == 0 ? own[f] : other[f];
+          phi[4] = 1.0f;
+        }
+        const float d = mlp_forward<BF16>(phi, w1a, s_w2f, s_lanec, lane, b3, h1, h2);
+        if (sub == half) delta = d;
+      }
+      st_open = Et;
+    }
+    if ((i & 1) == 0) nz = normals4<float>(philox(i >> 1, pc));
+    const float Z1 = (i & 1) ? nz.z[2] : nz.z[0];
+    const float Z2 = (i & 1) ? nz.z[3] : nz.z[1];
+    {
+      const float vp = v > 0.f ? v : 0.f;
+      const float sq = __builtin_amdgcn_sqrtf(vp * dt);
+      const float Zs = rho * Z1 + rhoc * Z2;
+      z = z + a1 * vp + a2 * (sq * Zs);
+      v = v + (kthdt - kdt * vp) + xi * (sq * Z1);
+    }
+    Et = __builtin_amdgcn_exp2f(z);
+    sumE += Et * P.dfac[i + 1];
+    if ((i + 1) % m == 0 || i + 1 == n) H = __builtin_fmaf(delta, S0 * (Et - st_open), H);
+  }
+  double y[3] = {0.0, 0.0, 0.0};
+  if (active) {
+    const double A = (double)S0 * (double)sumE / (double)n;
+    const double pay = Hp.disc * (A > Hp.K ? A - Hp.K : 0.0);
+    y[0] = pay;
+    y[1] = (double)H;
+    y[2] = pay - (double)H;
+  }
+  const bool finite = isfinite(y[0]) && isfinite(y[1]) && isfinite(y[2]);
+  if (active && P.path_out != nullptr) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) P.path_out[pid * 3 + c] = y[c];
+  }
+  block_moments<3, kCvThreads>(y, active && finite, active && !finite, P.partials, gridDim.x);
+}
+
 __global__ void adam_kernel(float* __restrict__ theta, float* __restrict__ m,
                             float* __restrict__ v, const double* __restrict__ grad, int n,
                             float lr, float b1, float b2, float eps, float c1, float c2) {
@@ -437,17 +530,17 @@ hipError_t launch_cv_pack(const float* theta, float* w1f, float* w2f, float* w2t
 }
 
 hipError_t launch_cv_price(const CvParams& p, hipStream_t s, uint32_t* n_blocks) {
-  const uint32_t nb = (uint32_t)((p.h.n_paths + 32 * kCvWaves - 1) / (32 * kCvWaves));
+  const uint32_t nb = (uint32_t)((p.h.n_paths + kCvPathsPerBlock - 1) / kCvPathsPerBlock);
   *n_blocks = nb;
   if (p.bf16)
-    hipLaunchKernelGGL((cv_kernel<true, false>), dim3(nb), dim3(kCvThreads), 0, s, p);
+    hipLaunchKernelGGL((cv_eval_kernel<true>), dim3(nb), dim3(kCvThreads), 0, s, p);
   else
-    hipLaunchKernelGGL((cv_kernel<false, false>), dim3(nb), dim3(kCvThreads), 0, s, p);
+    hipLaunchKernelGGL((cv_eval_kernel<false>), dim3(nb), dim3(kCvThreads), 0, s, p);
   return hipGetLastError();
 }
 
 hipError_t launch_cv_backward(const CvParams& p, hipStream_t s, uint32_t* n_blocks) {
-  const uint32_t nb = (uint32_t)((p.h.n_paths + 32 * kCvWaves - 1) / (32 * kCvWaves));
+  const uint32_t nb = (uint32_t)((p.h.n_paths + kCvTrainPathsPerBlock - 1) / kCvTrainPathsPerBlock);
   *n_blocks = nb;
   if (p.bf16)
     hipLaunchKernelGGL((cv_kernel<true, true>), dim3(nb), dim3(kCvThreads), 0, s, p);

@@ -1,8 +1,9 @@
 // One-dimensional GBM path kernel: Euler-Maruyama (Sec. II-A.1) for
 // dS = r S dt + sigma S dW under the risk-neutral measure, fused with the
 // path functionals, the payoffs and the first stage of the averaging
-// reduction (Eq. 3). One thread owns one path; its state lives in registers
-// and nothing is written to memory per step.
+// reduction (Eq. 3). A thread prices one path at a time, its state in
+// registers, nothing written to memory per step; over a persistent grid it
+// prices several paths and keeps their moments in FP64 registers.
 //
 // Schemes: log-Euler on ln S (exact in law for every step count) and Euler
 // on S (first-order weak error, Sec. V-B). In FP32 the log state is kept in
@@ -164,23 +165,31 @@ __device__ __forceinline__ void simulate(const GbmParams& P, uint64_t path,
   }
 }
 
+// Persistent grid: at most kGbmMaxBlocks workgroups (one wave of blocks at
+// full occupancy); each thread prices paths pid, pid + stride, ... and keeps
+// their moments in FP64 registers, so each block writes one moment vector.
 template <typename R, uint32_t MASK, bool LOGS>
 __global__ __launch_bounds__(kBlock) void gbm_path_kernel(const GbmParams P) {
   constexpr int C = gbm_channels(MASK);
-  const uint64_t pid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool active = pid < P.n_paths;
-  double y[C];
+  constexpr int M = n_moments(C);
+  double acc[M];
 #pragma unroll
-  for (int c = 0; c < C; ++c) y[c] = 0.0;
-  if (active) simulate<R, MASK, LOGS>(P, P.path_offset + pid, y);
-  bool finite = true;
+  for (int m = 0; m < M; ++m) acc[m] = 0.0;
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t pid = (uint64_t)blockIdx.x * kBlock + threadIdx.x; pid < P.n_paths;
+       pid += stride) {
+    double y[C];
+    simulate<R, MASK, LOGS>(P, P.path_offset + pid, y);
+    bool finite = true;
 #pragma unroll
-  for (int c = 0; c < C; ++c) finite = finite && isfinite(y[c]);
-  if (active && P.path_out != nullptr) {
+    for (int c = 0; c < C; ++c) finite = finite && isfinite(y[c]);
+    if (P.path_out != nullptr) {
 #pragma unroll
-    for (int c = 0; c < C; ++c) P.path_out[pid * C + c] = y[c];
+      for (int c = 0; c < C; ++c) P.path_out[pid * C + c] = y[c];
+    }
+    accumulate_moments<C>(acc, y, finite, !finite);
   }
-  block_moments<C, kBlock>(y, active && finite, active && !finite, P.partials, gridDim.x);
+  block_reduce_moments<M, kBlock>(acc, P.partials, gridDim.x);
 }
 
 template <typename R, uint32_t MASK, bool LOGS>
@@ -218,7 +227,8 @@ uint32_t gbm_pick_mask(uint32_t want, bool fp64, bool log_scheme) {
 
 hipError_t launch_gbm(const GbmParams& p, uint32_t mask, bool fp64, hipStream_t s,
                       uint32_t* n_blocks) {
-  const uint32_t nb = (uint32_t)((p.n_paths + kBlock - 1) / kBlock);
+  const uint64_t need = (p.n_paths + kBlock - 1) / kBlock;
+  const uint32_t nb = (uint32_t)(need < kGbmMaxBlocks ? need : kGbmMaxBlocks);
   *n_blocks = nb;
   const bool L = p.log_scheme != 0;
   constexpr uint32_t kMaskS = G_ALL & ~G_UOBB;

@@ -8,6 +8,7 @@
 namespace mcp {
 
 constexpr int kBlock = 256;          // threads per path-kernel workgroup (4 waves)
+constexpr uint32_t kGbmMaxBlocks = 2048;   // GBM grid: 8 workgroups per CU x 256 CUs
 
 // ---- GBM path functionals (bit mask -> per-path channels, in bit order) ----
 enum : uint32_t {
@@ -117,7 +118,8 @@ struct CvParams {
   double* partials;
   double* path_out;
 };
-constexpr int kCvPathsPerBlock = 128;   // 4 waves of 32 paths
+constexpr int kCvPathsPerBlock = 256;       // evaluation: 4 waves of 64 paths
+constexpr int kCvTrainPathsPerBlock = 128;  // backward: 4 waves of 32 paths
 // Fragment layout of the weights, built on the device from theta.
 constexpr int kW1fFloats = 2 * 64 * 8, kW2fFloats = 2 * 4 * 64 * 8, kLanecFloats = 2 * 64 * 32;
 hipError_t launch_cv_pack(const float* theta, float* w1f, float* w2f, float* w2tf, float* lanec,
