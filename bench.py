@@ -39,17 +39,17 @@ ALU_PEAK_SLOTS = N_CU * CLOCK_HZ * FMA_LANES_PER_CLK      # 7.86e13 slots/s
 # paper_1906_02818_amd/isa_rates.hip (profiles/isa_rates.txt).
 COST_MUL64 = 3.7     # 32x32->64-bit product (v_mad_u64_u32)
 COST_TRANS = 4.1     # v_exp / log / sin / cos / sqrt / rcp _f32
-COST_INT = 0.56      # xor, shift, or, compare
+COST_INT = 0.56      # xor, shift, or, compare (gfx950 has no three-input xor)
 COST_FP32 = 1.0      # add, mul, fma
 
 # Algorithmic operations per path-step of the benchmarked workload (one
 # normal per step):
-#   Philox4x32-10: 10 rounds x (2 mul64 + 2 xor3) per 4 normals
+#   Philox4x32-10: 10 rounds x (2 mul64 + 4 xor) per 4 normals
 #   uniform: shift, or, sub per uniform, one uniform per normal
 #   Box-Muller: log, sqrt, sin, cos and 3 mul per 2 normals
 #   step: fma + add; Asian: exp2 + add; geometric: add; barrier: compare
 SLOTS_PER_PATH_STEP = (5.0 * COST_MUL64 + 3.0 * COST_TRANS
-                       + (5.0 + 2.0 + 1.0) * COST_INT
+                       + (10.0 + 2.0 + 1.0) * COST_INT
                        + (1.0 + 1.5 + 2.0 + 1.0 + 1.0) * COST_FP32)
 
 

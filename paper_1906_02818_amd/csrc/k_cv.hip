@@ -102,6 +102,10 @@ __device__ __forceinline__ float mlp_forward(const float (&phi)[8], const float 
   for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
     for (int r = 0; r < 16; ++r) d2[mb][r] = 0.f;
+  // Read the weight fragments from LDS at every use (a compiler barrier
+  // keeps them from being hoisted into registers across the time loop,
+  // which would halve the occupancy).
+  __asm__ volatile("" ::: "memory");
 #pragma unroll
   for (int kb = 0; kb < 4; ++kb) {
     float b[8];

@@ -8,7 +8,11 @@
 namespace mcp {
 
 constexpr int kBlock = 256;          // threads per path-kernel workgroup (4 waves)
-constexpr uint32_t kGbmMaxBlocks = 2048;   // GBM grid: 8 workgroups per CU x 256 CUs
+#ifndef MCP_GBM_MAX_BLOCKS
+#define MCP_GBM_MAX_BLOCKS 8192
+#endif
+// GBM grid cap: the persistent grid gives each thread several paths.
+constexpr uint32_t kGbmMaxBlocks = MCP_GBM_MAX_BLOCKS;
 
 // ---- GBM path functionals (bit mask -> per-path channels, in bit order) ----
 enum : uint32_t {
