@@ -1,21 +1,24 @@
 """Benchmark of the Monte Carlo path engine on one MI355X.
 
-Workload: arithmetic-average Asian call (with the geometric-Asian control
-variate) and discretely monitored up-and-out call (B = 130) priced on the
-same 1-D GBM paths: S0 = K = 100, r = 0.03, sigma = 0.25, T = 1, 252
-log-Euler steps, 2^24 paths, FP32 path state, FP64 cross-path reduction,
-Philox4x32-10 seed 1234. One step of the benchmark is one full pricing pass:
-the path kernel (random numbers, Euler-Maruyama steps, path functionals,
-payoffs, block moments), the fixed-order final reduction and the read-back
-of the moments. Inputs are parameters only, so nothing is staged from the
-host in the timed region.
+Default workload (the metric's configuration): arithmetic-average Asian call
+(with the geometric-Asian control variate) and discretely monitored
+up-and-out call (B = 130) priced on the same 1-D GBM paths: S0 = K = 100,
+r = 0.03, sigma = 0.25, T = 1, 252 log-Euler steps, 2^24 paths, FP32 path
+state, FP64 cross-path reduction, Philox4x32-10 seed 1234. One step of the
+benchmark is one full pricing pass: the path kernel (random numbers,
+Euler-Maruyama steps, path functionals, payoffs, block moments), the
+fixed-order final reduction and the read-back of the moments. Inputs are
+parameters only, so nothing is staged from the host in the timed region.
 
-Prints one JSON line. `roofline` reports the path kernel against the ALU
-issue peak (it reads and writes no HBM per step); `time_to_1bp` compares,
-after the timed region, plain FP32 Monte Carlo with the learned control
-variate (BF16 matrix products) on the Heston Asian call; `cpu_baseline`
-times the FP64 oracle on a bounded sample of the benchmarked workload on the
-host cores.
+Prints one JSON line. `roofline` reports the dominant kernel against the
+ALU issue peak (the path kernels read and write no HBM per step);
+`time_to_1bp` compares, after the timed region, plain FP32 Monte Carlo with
+the learned control variate (BF16 matrix products) on the Heston Asian
+call; `cpu_baseline` times the FP64 oracle on a bounded sample of the same
+workload on the host cores.
+
+Other configurations, for profiling (--workload): european (FP64 with
+pathwise greeks), basket (d = 256, --prec), heston_adjoint, learned_cv.
 """
 from __future__ import annotations
 
@@ -33,6 +36,7 @@ sys.path.insert(0, ROOT)
 # FMA lanes per clock per CU, the unit ("slot") of the ALU roofline.
 N_CU, CLOCK_HZ, FMA_LANES_PER_CLK = 256, 2.4e9, 128
 ALU_PEAK_SLOTS = N_CU * CLOCK_HZ * FMA_LANES_PER_CLK      # 7.86e13 slots/s
+MFMA_PEAK = {"fp32": 157.3e12, "bf16": 2.5e15, "fp16": 2.5e15, "bf16x2": 2.5e15}
 
 # Issue cost of each instruction class in FMA slots on gfx950: 2 wave64
 # FMAs per clock per CU divided by the rate measured for that instruction by
@@ -41,16 +45,39 @@ COST_MUL64 = 3.7     # 32x32->64-bit product (v_mad_u64_u32)
 COST_TRANS = 4.1     # v_exp / log / sin / cos / sqrt / rcp _f32
 COST_INT = 0.56      # xor, shift, or, compare (gfx950 has no three-input xor)
 COST_FP32 = 1.0      # add, mul, fma
+COST_FP64 = 2.2      # v_fma_f64
 
-# Algorithmic operations per path-step of the benchmarked workload (one
-# normal per step):
-#   Philox4x32-10: 10 rounds x (2 mul64 + 4 xor) per 4 normals
-#   uniform: shift, or, sub per uniform, one uniform per normal
-#   Box-Muller: log, sqrt, sin, cos and 3 mul per 2 normals
-#   step: fma + add; Asian: exp2 + add; geometric: add; barrier: compare
-SLOTS_PER_PATH_STEP = (5.0 * COST_MUL64 + 3.0 * COST_TRANS
-                       + (10.0 + 2.0 + 1.0) * COST_INT
-                       + (1.0 + 1.5 + 2.0 + 1.0 + 1.0) * COST_FP32)
+
+def slots(mul64=0.0, trans=0.0, intops=0.0, fp32=0.0, fp64=0.0):
+    return (mul64 * COST_MUL64 + trans * COST_TRANS + intops * COST_INT + fp32 * COST_FP32
+            + fp64 * COST_FP64)
+
+
+# One FP32 normal: a quarter of a Philox4x32-10 block (10 rounds of 2 mul64
+# and 4 xor), the uniform (shift, or, sub) and half of a Box-Muller pair
+# (log, sqrt, sin, cos and 3 mul).
+NORMAL = dict(mul64=5.0, trans=2.0, intops=10.0 + 2.0, fp32=1.0 + 1.5)
+
+
+def _add(*ds):
+    out = {}
+    for d in ds:
+        for k, v in d.items():
+            out[k] = out.get(k, 0.0) + v
+    return out
+
+
+# Algorithmic work per path-step (asset-path-step for the basket).
+SLOTS_ASIAN_BARRIER = slots(**_add(NORMAL, dict(trans=1.0, intops=1.0, fp32=4.0)))
+#   normal; step fma + add; Asian exp2 + add; geometric add; barrier compare
+SLOTS_HESTON = slots(**_add(NORMAL, NORMAL, dict(trans=2.0, fp32=11.0)))
+#   2 normals; v+ max, sqrt(v+ dt), Zs (mul, fma), ln S (fma, add, fma),
+#   v (fma, fma, mul), Asian exp2 + add
+SLOTS_HESTON_REVERSE = slots(trans=2.0, fp32=6.0, fp64=3.0)
+#   per step of the reverse sweep: sqrt, rcp, 6 FP32 ops, 3 FP64 ops
+SLOTS_ASSET_STEP = slots(**_add(NORMAL, dict(intops=0.5)))
+#   per asset-path-step of the basket: one normal and half a 16-bit pack
+SLOTS_TANH = slots(trans=2.0, fp32=3.0)
 
 
 def cpu_baseline(c, budget_s=12.0):
@@ -78,7 +105,21 @@ def _paths_for(se_target, sigma):
     return max(256, (n + 255) // 256 * 256)
 
 
-def time_to_1bp(ctx, mc, synth, hedge_every=8, adam_steps=2000):
+def _heston_model(mc, synth):
+    H = synth.HESTON
+    return mc.Model(kind=mc.MC_HESTON, S0=H["S0"], r=H["r"], T=H["T"], v0=H["v0"],
+                    kappa=H["kappa"], theta=H["theta"], xi=H["xi"], rho=H["rho"])
+
+
+def _timed(torch, fn):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return r, time.perf_counter() - t0
+
+
+def time_to_1bp(ctx, mc, synth, torch, hedge_every=8, adam_steps=2000):
     """Time to a Heston-Asian price whose standard error is 1 bp of the price
     (1e-4 x price), plain FP32 Monte Carlo against the learned control
     variate with BF16 matrix products. Each estimator: a 2^20-path pilot on
@@ -88,43 +129,35 @@ def time_to_1bp(ctx, mc, synth, hedge_every=8, adam_steps=2000):
     training time is reported separately and added in `total_incl_train_s`.
     """
     import numpy as np
-    import torch
     H = synth.HESTON
     cv = synth.LEARNED_CV
     n = H["n_steps"]
-    model = mc.Model(kind=mc.MC_HESTON, S0=H["S0"], r=H["r"], T=H["T"], v0=H["v0"],
-                     kappa=H["kappa"], theta=H["theta"], xi=H["xi"], rho=H["rho"])
+    model = _heston_model(mc, synth)
     plain_f = mc.Payoff(mc.MC_ASIAN_ARITH_CALL, H["K"])
     cv_f = mc.Payoff(mc.MC_ASIAN_ARITH_CALL, H["K"], cv=mc.MC_CV_LEARNED)
     out = {"workload": f"Heston arithmetic-Asian call, {n} steps; target SE = 1e-4 x price",
            "hedge_every": hedge_every}
-
-    def timed(fn):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r = fn()
-        torch.cuda.synchronize()
-        return r, time.perf_counter() - t0
-
-    # Plain FP32.
-    pil, t_pil = timed(lambda: mc.mc_price(ctx, model, plain_f, 1 << 20, n, synth.SEED,
-                                           mc.Options(stream_tag=1)))
-    sig = math.sqrt(pil["variance"])
-    N_plain = _paths_for(1e-4 * pil["price"], sig)
-    run, t_run = timed(lambda: mc.mc_price(ctx, model, plain_f, N_plain, n, synth.SEED))
+    pil, t_pil = _timed(torch, lambda: mc.mc_price(ctx, model, plain_f, 1 << 20, n, synth.SEED,
+                                                   mc.Options(stream_tag=1)))
+    N_plain = _paths_for(1e-4 * pil["price"], math.sqrt(pil["variance"]))
+    run, t_run = _timed(torch, lambda: mc.mc_price(ctx, model, plain_f, N_plain, n, synth.SEED))
     out["plain_fp32"] = {"pilot_s": t_pil, "n_paths": N_plain, "run_s": t_run,
                          "total_s": t_pil + t_run, "price": run["price"],
                          "std_err": run["std_err"], "kernel_ms": run["kernel_ms"]}
-    # Learned CV, BF16.
     th0 = synth.glorot_mlp()
-    (w, log), t_train = timed(lambda: mc.mc_cv_train(
+    (w, log), t_train = _timed(torch, lambda: mc.mc_cv_train(
         ctx, model, cv_f, cv["n_train"], n, synth.SEED, th0, lr=cv["lr"], steps=adam_steps,
         batch=cv["batch"], hedge_every=hedge_every, prec=mc.MC_BF16_GEMM))
-    opts = lambda tag: mc.Options(prec=mc.MC_BF16_GEMM, cv_weights=w, cv_hedge_every=hedge_every,
-                                  cv_beta=1.0, stream_tag=tag)
-    pil, t_pil = timed(lambda: mc.mc_price(ctx, model, cv_f, 1 << 20, n, synth.SEED, opts(1)))
+
+    def opts(tag):
+        return mc.Options(prec=mc.MC_BF16_GEMM, cv_weights=w, cv_hedge_every=hedge_every,
+                          cv_beta=1.0, stream_tag=tag)
+
+    pil, t_pil = _timed(torch, lambda: mc.mc_price(ctx, model, cv_f, 1 << 20, n, synth.SEED,
+                                                   opts(1)))
     N_cv = _paths_for(1e-4 * pil["price"], math.sqrt(pil["variance"]))
-    run, t_run = timed(lambda: mc.mc_price(ctx, model, cv_f, N_cv, n, synth.SEED, opts(0)))
+    run, t_run = _timed(torch, lambda: mc.mc_price(ctx, model, cv_f, N_cv, n, synth.SEED,
+                                                   opts(0)))
     out["learned_cv_bf16"] = {"train_s": t_train, "adam_steps": adam_steps,
                               "loss_first": float(log[0]), "loss_last": float(np.mean(log[-20:])),
                               "pilot_s": t_pil, "pilot_vrf": pil["vrf"], "n_paths": N_cv,
@@ -139,11 +172,165 @@ def time_to_1bp(ctx, mc, synth, hedge_every=8, adam_steps=2000):
     return out
 
 
+def _line(args, metric, value, unit, ms, dtype, config, roofline, **extra):
+    d = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+         "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config,
+         "roofline": roofline}
+    d.update(extra)
+    return d
+
+
+def _alu_roofline(slots_per_unit, units, kernel_ms, kernel):
+    achieved = slots_per_unit * units / (kernel_ms * 1e-3)
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_SLOTS / 1e12,
+            "unit": "Tslot/s", "frac": achieved / ALU_PEAK_SLOTS, "traffic": None,
+            "slots_per_unit": slots_per_unit, "kernel": kernel}
+
+
+def _repeat(args, torch, fn):
+    for _ in range(args.warmup):
+        fn()
+    torch.cuda.synchronize()
+    outs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        outs.append(fn())
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / args.steps, outs
+
+
+def run_asian_barrier(args, ctx, mc, synth, torch):
+    c = synth.ASIAN_BARRIER
+    N, n = c["n_paths"], c["n_steps"]
+    model = mc.Model(kind=mc.MC_GBM, S0=c["S0"], r=c["r"], T=c["T"], sigma=c["sigma"])
+    # The control-variate coefficient comes from a pilot on stream tag 1,
+    # once, before timing (it is an input of the estimator, not of the step).
+    pilot = mc.mc_price(ctx, model, mc.Payoff(mc.MC_ASIAN_ARITH_CALL, c["K"],
+                                              cv=mc.MC_CV_GEO_ASIAN), N, n, synth.SEED,
+                        mc.Options(pilot_paths=1 << 20))
+    beta = pilot["cv_beta"]
+    payoffs = [mc.Payoff(mc.MC_ASIAN_ARITH_CALL, c["K"], cv=mc.MC_CV_GEO_ASIAN),
+               mc.Payoff(mc.MC_UO_BARRIER_CALL, c["K"], B=c["B"]),
+               mc.Payoff(mc.MC_ASIAN_GEO_CALL, c["K"])]
+    step = mc.PreparedPriceMulti(ctx, model, payoffs, N, n, synth.SEED, mc.Options(cv_beta=beta))
+    ms, outs = _repeat(args, torch, lambda: step()[0].kernel_ms)
+    k_ms = sum(outs) / len(outs)
+    res = step.results()
+    line = _line(args, "path-steps/s", N * n / (ms * 1e-3), "path-steps/s", ms, "f32",
+                 {"workload": "GBM arithmetic-Asian (geometric CV) + up-and-out barrier (B=130) "
+                              "+ geometric Asian on the same paths, 2^24 paths x 252 log-Euler "
+                              "steps, FP32 state, FP64 reduction, Philox4x32-10",
+                  "n_paths": N, "n_steps": n},
+                 _alu_roofline(SLOTS_ASIAN_BARRIER, N * n, k_ms,
+                               "gbm_path_kernel<float, asian|geo|uo, log-Euler>"),
+                 kernel_ms=k_ms,
+                 prices={"asian_cv": res[0]["price"], "asian_cv_se": res[0]["std_err"],
+                         "asian_plain": res[0]["plain_price"],
+                         "asian_plain_se": res[0]["plain_std_err"],
+                         "uo": res[1]["price"], "uo_se": res[1]["std_err"],
+                         "geo": res[2]["price"], "geo_se": res[2]["std_err"], "cv_beta": beta,
+                         "vrf": res[0]["vrf"]})
+    if not args.no_time_to_1bp:
+        line["time_to_1bp"] = time_to_1bp(ctx, mc, synth, torch, hedge_every=args.hedge_every)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(c)
+    return line
+
+
+def run_european(args, ctx, mc, synth, torch):
+    c = synth.EURO
+    N, n = c["n_paths"], c["n_steps"]
+    model = mc.Model(kind=mc.MC_GBM, S0=c["S0"], r=c["r"], T=c["T"], sigma=c["sigma"])
+    f = mc.Payoff(mc.MC_EURO_CALL, c["K"])
+    o = mc.Options(prec=mc.MC_FP64, greeks=mc.MC_GREEK_DELTA | mc.MC_GREEK_VEGA)
+    ms, outs = _repeat(args, torch, lambda: mc.mc_price(ctx, model, f, N, n, synth.SEED, o))
+    r = outs[-1]
+    k_ms = sum(x["kernel_ms"] for x in outs) / len(outs)
+    return _line(args, "path-steps/s", N * n / (ms * 1e-3), "path-steps/s", ms, "f64",
+                 {"workload": "European call, GBM log-Euler, 64 steps, 2^18 paths, FP64, "
+                              "pathwise delta and vega", "n_paths": N, "n_steps": n},
+                 {"bound": "alu", "achieved": None, "peak": 78.6, "unit": "TFLOP/s (FP64)",
+                  "frac": None, "traffic": None,
+                  "note": "FP64 transcendentals go through library code; not modelled"},
+                 kernel_ms=k_ms, prices={"price": r["price"], "se": r["std_err"],
+                                         "delta": r["delta"], "vega": r["vega"]})
+
+
+def run_basket(args, ctx, mc, synth, torch):
+    c = synth.BASKET
+    N, n, d = c["n_paths"], c["n_steps"], c["d"]
+    sigma, corr, _ = synth.basket_market(d)
+    model = mc.Model(kind=mc.MC_GBM_BASKET, S0=[c["S0"]] * d, r=c["r"], T=c["T"], sigma=sigma,
+                     corr=corr)
+    prec = {"fp32": mc.MC_FP32, "bf16": mc.MC_BF16_GEMM, "fp16": mc.MC_FP16_GEMM,
+            "bf16x2": mc.MC_BF16X2_GEMM}[args.prec]
+    f = mc.Payoff(mc.MC_BASKET_CALL, c["K"])
+    o = mc.Options(prec=prec, greeks=mc.MC_GREEK_DELTA)
+    ms, outs = _repeat(args, torch, lambda: mc.mc_price(ctx, model, f, N, n, synth.SEED, o))
+    r = outs[-1]
+    k_ms = sum(x["kernel_ms"] for x in outs) / len(outs)
+    # MFMA work issued: lower-triangular 32x16 blocks per 32-path tile.
+    nd = (d + 31) // 32
+    blocks = sum(2 * nb + 2 for nb in range(nd))
+    flops = (N // 32) * n * blocks * 32 * 32 * 16 * 2 * (2 if args.prec == "bf16x2" else 1)
+    roof = _alu_roofline(SLOTS_ASSET_STEP, N * n * d, k_ms, f"basket_kernel<8, {args.prec}>")
+    roof["mfma_tflops"] = flops / (k_ms * 1e-3) / 1e12
+    roof["mfma_frac"] = flops / (k_ms * 1e-3) / MFMA_PEAK[args.prec]
+    return _line(args, "asset-path-steps/s", N * n * d / (ms * 1e-3), "asset-path-steps/s", ms,
+                 args.prec,
+                 {"workload": f"basket call, d = {d} correlated GBM, {n} steps, 2^20 paths, "
+                              f"per-step Z L^T on MFMA ({args.prec})", "n_paths": N,
+                  "n_steps": n, "d": d},
+                 roof, kernel_ms=k_ms,
+                 prices={"price": r["price"], "se": r["std_err"], "delta0": r["delta"]})
+
+
+def run_heston_adjoint(args, ctx, mc, synth, torch):
+    H = synth.HESTON
+    N, n = H["n_paths"], H["n_steps"]
+    model = _heston_model(mc, synth)
+    f = mc.Payoff(mc.MC_ASIAN_ARITH_CALL, H["K"])
+    o = mc.Options(greeks=mc.MC_GREEK_DELTA | mc.MC_GREEK_VEGA)
+    ms, outs = _repeat(args, torch, lambda: mc.mc_price(ctx, model, f, N, n, synth.SEED, o))
+    r = outs[-1]
+    k_ms = sum(x["kernel_ms"] for x in outs) / len(outs)
+    per_step = 2 * SLOTS_HESTON + SLOTS_HESTON_REVERSE   # forward, recompute, reverse
+    return _line(args, "path-steps/s", N * n / (ms * 1e-3), "path-steps/s", ms, "f32",
+                 {"workload": "Heston arithmetic-Asian call, full-truncation Euler, 256 steps, "
+                              "2^22 paths, price + pathwise delta and d/dv0 by the checkpointed "
+                              "adjoint (every 16 steps)", "n_paths": N, "n_steps": n},
+                 _alu_roofline(per_step, N * n, k_ms, "heston_adjoint_kernel<float, full, asian>"),
+                 kernel_ms=k_ms,
+                 prices={"price": r["price"], "se": r["std_err"], "delta": r["delta"],
+                         "delta_se": r["delta_se"], "dv0": r["vega"], "dv0_se": r["vega_se"]})
+
+
+def run_learned_cv(args, ctx, mc, synth, torch):
+    out = time_to_1bp(ctx, mc, synth, torch, hedge_every=args.hedge_every)
+    n = synth.HESTON["n_steps"]
+    cv = out["learned_cv_bf16"]
+    m = args.hedge_every
+    per_step = SLOTS_HESTON + (128 * SLOTS_TANH + slots(fp32=64 + 8)) / m
+    return _line(args, "time to 1bp SE", cv["total_s"], "s", cv["total_s"] * 1e3, "bf16",
+                 {"workload": out["workload"] + f", learned CV rebalanced every {m} steps",
+                  "n_steps": n},
+                 _alu_roofline(per_step, cv["n_paths"] * n, cv["kernel_ms"],
+                               "cv_eval_kernel<bf16>"),
+                 time_to_1bp=out)
+
+
+WORKLOADS = {"asian_barrier": run_asian_barrier, "european": run_european, "basket": run_basket,
+             "heston_adjoint": run_heston_adjoint, "learned_cv": run_learned_cv}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=list(WORKLOADS), default="asian_barrier")
+    ap.add_argument("--prec", choices=["fp32", "bf16", "fp16", "bf16x2"], default="bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-time-to-1bp", action="store_true")
     ap.add_argument("--hedge-every", type=int, default=8)
@@ -159,9 +346,6 @@ def main():
     import paper_1906_02818_amd as mc
     import synth
 
-    c = synth.ASIAN_BARRIER
-    N, n = c["n_paths"], c["n_steps"]
-    model = mc.Model(kind=mc.MC_GBM, S0=c["S0"], r=c["r"], T=c["T"], sigma=c["sigma"])
     ctx = mc.mc_create(0)
     if args.copy_probe:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
@@ -169,57 +353,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    # The control-variate coefficient comes from a pilot on stream tag 1,
-    # once, before timing (it is an input of the estimator, not of the step).
-    pilot = mc.mc_price(ctx, model, mc.Payoff(mc.MC_ASIAN_ARITH_CALL, c["K"],
-                                              cv=mc.MC_CV_GEO_ASIAN), N, n, synth.SEED,
-                        mc.Options(pilot_paths=1 << 20))
-    beta = pilot["cv_beta"]
-    payoffs = [mc.Payoff(mc.MC_ASIAN_ARITH_CALL, c["K"], cv=mc.MC_CV_GEO_ASIAN),
-               mc.Payoff(mc.MC_UO_BARRIER_CALL, c["K"], B=c["B"]),
-               mc.Payoff(mc.MC_ASIAN_GEO_CALL, c["K"])]
-    opts = mc.Options(cv_beta=beta)
-    step = mc.PreparedPriceMulti(ctx, model, payoffs, N, n, synth.SEED, opts)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    kernel_ms = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        kernel_ms.append(step()[0].kernel_ms)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    res = step.results()
-    ms = (t1 - t0) * 1e3 / args.steps
-    path_steps = N * n
-    k_ms = sum(kernel_ms) / len(kernel_ms)
-    achieved = SLOTS_PER_PATH_STEP * path_steps / (k_ms * 1e-3)
-    line = {
-        "metric": "path-steps/s",
-        "value": path_steps / (ms * 1e-3),
-        "unit": "path-steps/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "GBM arithmetic-Asian (geometric CV) + up-and-out barrier "
-                               "(B=130) + geometric Asian on the same paths, 2^24 paths x "
-                               "252 log-Euler steps, FP32 state, FP64 reduction, Philox4x32-10",
-                   "n_paths": N, "n_steps": n},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_SLOTS / 1e12,
-                     "unit": "Tslot/s", "frac": achieved / ALU_PEAK_SLOTS, "traffic": None,
-                     "slots_per_path_step": SLOTS_PER_PATH_STEP,
-                     "kernel": "gbm_path_kernel<float, asian|geo|uo, log-Euler>"},
-        "kernel_ms": k_ms,
-        "prices": {"asian_cv": res[0]["price"], "asian_cv_se": res[0]["std_err"],
-                   "asian_plain": res[0]["plain_price"], "asian_plain_se": res[0]["plain_std_err"],
-                   "uo": res[1]["price"], "uo_se": res[1]["std_err"],
-                   "geo": res[2]["price"], "geo_se": res[2]["std_err"], "cv_beta": beta,
-                   "vrf": res[0]["vrf"]},
-    }
-    if not args.no_time_to_1bp:
-        line["time_to_1bp"] = time_to_1bp(ctx, mc, synth, hedge_every=args.hedge_every)
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(c)
+    line = WORKLOADS[args.workload](args, ctx, mc, synth, torch)
     print(json.dumps(line), flush=True)
     ctx.close()
 
