@@ -38,25 +38,29 @@ N_CU, CLOCK_HZ, FMA_LANES_PER_CLK = 256, 2.4e9, 128
 ALU_PEAK_SLOTS = N_CU * CLOCK_HZ * FMA_LANES_PER_CLK      # 7.86e13 slots/s
 MFMA_PEAK = {"fp32": 157.3e12, "bf16": 2.5e15, "fp16": 2.5e15, "bf16x2": 2.5e15}
 
-# Issue cost of each instruction class in FMA slots on gfx950: 2 wave64
-# FMAs per clock per CU divided by the rate measured for that instruction by
-# paper_1906_02818_amd/isa_rates.hip (profiles/isa_rates.txt).
-COST_MUL64 = 3.7     # 32x32->64-bit product (v_mad_u64_u32)
-COST_TRANS = 4.1     # v_exp / log / sin / cos / sqrt / rcp _f32
+# Issue cost of each instruction class on gfx950 in "slots": wave64 FMA
+# issues at the FP32 vector peak (2 per clock per CU). Each cost is 2 divided
+# by the wave64 issue rate per clock per CU that
+# paper_1906_02818_amd/isa_rates.hip measures for the instruction in
+# isolation (profiles/isa_rates.txt); an FP32 FMA itself issues at 1.78 per
+# clock, so it costs 1.12.
+COST_MUL64 = 3.57    # 32x32->64-bit product (v_mad_u64_u32): 4.13 with its xor, minus 0.56
+COST_TRANS = 4.09    # v_exp / sin / cos / sqrt / rcp _f32
+COST_LOG = 4.90      # v_log_f32: 6.02 with its dependent add, minus 1.12
 COST_INT = 0.56      # xor, shift, or, compare (gfx950 has no three-input xor)
-COST_FP32 = 1.0      # add, mul, fma
-COST_FP64 = 2.2      # v_fma_f64
+COST_FP32 = 1.12     # add, mul, fma
+COST_FP64 = 2.43     # v_fma_f64
 
 
-def slots(mul64=0.0, trans=0.0, intops=0.0, fp32=0.0, fp64=0.0):
-    return (mul64 * COST_MUL64 + trans * COST_TRANS + intops * COST_INT + fp32 * COST_FP32
-            + fp64 * COST_FP64)
+def slots(mul64=0.0, trans=0.0, log=0.0, intops=0.0, fp32=0.0, fp64=0.0):
+    return (mul64 * COST_MUL64 + trans * COST_TRANS + log * COST_LOG + intops * COST_INT
+            + fp32 * COST_FP32 + fp64 * COST_FP64)
 
 
 # One FP32 normal: a quarter of a Philox4x32-10 block (10 rounds of 2 mul64
 # and 4 xor), the uniform (shift, or, sub) and half of a Box-Muller pair
 # (log, sqrt, sin, cos and 3 mul).
-NORMAL = dict(mul64=5.0, trans=2.0, intops=10.0 + 2.0, fp32=1.0 + 1.5)
+NORMAL = dict(mul64=5.0, log=0.5, trans=1.5, intops=10.0 + 2.0, fp32=1.0 + 1.5)
 
 
 def _add(*ds):
@@ -172,9 +176,11 @@ def time_to_1bp(ctx, mc, synth, torch, hedge_every=8, adam_steps=2000):
     return out
 
 
-def _line(args, metric, value, unit, ms, dtype, config, roofline, **extra):
+def _line(args, metric, value, unit, ms, dtype, config, roofline, higher_is_better=True,
+          **extra):
     d = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
-         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": higher_is_better,
+         "scaling": "weak",
          "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config,
          "roofline": roofline}
     d.update(extra)
@@ -232,7 +238,8 @@ def run_asian_barrier(args, ctx, mc, synth, torch):
                          "geo": res[2]["price"], "geo_se": res[2]["std_err"], "cv_beta": beta,
                          "vrf": res[0]["vrf"]})
     if not args.no_time_to_1bp:
-        line["time_to_1bp"] = time_to_1bp(ctx, mc, synth, torch, hedge_every=args.hedge_every)
+        line["time_to_1bp"] = time_to_1bp(ctx, mc, synth, torch, hedge_every=args.hedge_every,
+                                          adam_steps=args.adam_steps)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(c)
     return line
@@ -307,7 +314,8 @@ def run_heston_adjoint(args, ctx, mc, synth, torch):
 
 
 def run_learned_cv(args, ctx, mc, synth, torch):
-    out = time_to_1bp(ctx, mc, synth, torch, hedge_every=args.hedge_every)
+    out = time_to_1bp(ctx, mc, synth, torch, hedge_every=args.hedge_every,
+                      adam_steps=args.adam_steps)
     n = synth.HESTON["n_steps"]
     cv = out["learned_cv_bf16"]
     m = args.hedge_every
@@ -317,7 +325,7 @@ def run_learned_cv(args, ctx, mc, synth, torch):
                   "n_steps": n},
                  _alu_roofline(per_step, cv["n_paths"] * n, cv["kernel_ms"],
                                "cv_eval_kernel<bf16>"),
-                 time_to_1bp=out)
+                 higher_is_better=False, time_to_1bp=out)
 
 
 WORKLOADS = {"asian_barrier": run_asian_barrier, "european": run_european, "basket": run_basket,
@@ -334,6 +342,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-time-to-1bp", action="store_true")
     ap.add_argument("--hedge-every", type=int, default=8)
+    ap.add_argument("--adam-steps", type=int, default=2000,
+                    help="training steps of the hedge network in the time-to-1bp comparison")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()

@@ -5,8 +5,8 @@
 // instruction of the measured kind (sign and absolute value are free source
 // modifiers), each thread runs 8 independent chains and every SIMD holds 8
 // waves, so latency is hidden. Output: wave64 instructions per clock per CU
-// and the issue cost relative to v_fma_f32 ("slots"), from which the path
-// kernels' ALU roofline is derived.
+// and the issue cost in units of a wave64 FMA at the FP32 vector peak
+// ("spec slots"), from which the path kernels' ALU roofline is derived.
 //   hipcc --offload-arch=gfx950 -O3 isa_rates.hip -o isa_rates && ./isa_rates
 // Memory: one store per thread into a buffer of exactly grid x block words.
 #include <hip/hip_runtime.h>
@@ -26,10 +26,10 @@
 constexpr int kIters = 2048;
 constexpr int kChains = 8;
 
-enum Op { FMA_F32, MAD_U64, MUL_HI, MUL_LO, XOR, EXP_F32, LOG_F32, SIN_F32, SQRT_F32, RCP_F32, FMA_F64 };
+enum Op { FMA_F32, FMAC_F32, FMA_INL, MAD_U64, MUL_HI, MUL_LO, XOR, EXP_F32, LOG_F32, SIN_F32, SQRT_F32, RCP_F32, FMA_F64 };
 
 template <int OP>
-__global__ __launch_bounds__(256) void rate_kernel(unsigned* out, unsigned seed) {
+__global__ __launch_bounds__(256) void rate_kernel(unsigned* out, unsigned seed, float kmul) {
   const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
   unsigned a[kChains];
   float f[kChains];
@@ -46,14 +46,18 @@ __global__ __launch_bounds__(256) void rate_kernel(unsigned* out, unsigned seed)
 #pragma unroll
     for (int c = 0; c < kChains; ++c) {
       if constexpr (OP == FMA_F32) {
-        f[c] = __builtin_fmaf(f[c], 0.999f, 1e-3f);
+        f[c] = __builtin_fmaf(f[c], 0.999f, 1e-3f);      // v_fmamk_f32 (32-bit literal)
+      } else if constexpr (OP == FMAC_F32) {
+        f[c] = __builtin_fmaf(kmul, f[(c + 1) % kChains], f[c]);   // v_fmac_f32, 4-byte form
+      } else if constexpr (OP == FMA_INL) {
+        f[c] = __builtin_fmaf(f[c], -0.5f, 2.0f);        // v_fma_f32 with inline constants
       } else if constexpr (OP == MAD_U64) {
         const unsigned long long p = (unsigned long long)a[c] * 0xD2511F53ull;
         a[c] = (unsigned)(p >> 32) ^ (unsigned)p;        // v_mad_u64_u32 + v_xor_b32
       } else if constexpr (OP == MUL_HI) {
         a[c] = __umulhi(a[c], 0xCD9E8D57u);
       } else if constexpr (OP == MUL_LO) {
-        a[c] = a[c] * 0xCD9E8D57u;
+        a[c] = a[c] * (key | 1u);                        // scalar factor: no folding
       } else if constexpr (OP == XOR) {
         a[c] = a[c] ^ key;
       } else if constexpr (OP == EXP_F32) {
@@ -80,12 +84,12 @@ __global__ __launch_bounds__(256) void rate_kernel(unsigned* out, unsigned seed)
 
 template <int OP>
 double run(unsigned* d_out, int blocks, int threads, hipEvent_t e0, hipEvent_t e1) {
-  hipLaunchKernelGGL(rate_kernel<OP>, dim3(blocks), dim3(threads), 0, 0, d_out, 1u);
+  hipLaunchKernelGGL(rate_kernel<OP>, dim3(blocks), dim3(threads), 0, 0, d_out, 1u, 1e-6f);
   CHECK(hipGetLastError());
   CHECK(hipDeviceSynchronize());
   CHECK(hipEventRecord(e0, 0));
   for (int r = 0; r < 5; ++r)
-    hipLaunchKernelGGL(rate_kernel<OP>, dim3(blocks), dim3(threads), 0, 0, d_out, 2u + r);
+    hipLaunchKernelGGL(rate_kernel<OP>, dim3(blocks), dim3(threads), 0, 0, d_out, 2u + r, 1e-6f);
   CHECK(hipEventRecord(e1, 0));
   CHECK(hipEventSynchronize(e1));
   float ms = 0.f;
@@ -109,7 +113,9 @@ int main() {
   const double steps = (double)blocks * threads / 64.0 * kIters * kChains;   // wave64 chain steps
   struct Row { const char* name; double ms; double extra; };   // extra: helper insts per step
   Row rows[] = {
-      {"v_fma_f32", run<FMA_F32>(d_out, blocks, threads, e0, e1), 0.0},
+      {"v_fmamk_f32 (literal)", run<FMA_F32>(d_out, blocks, threads, e0, e1), 0.0},
+      {"v_fmac_f32", run<FMAC_F32>(d_out, blocks, threads, e0, e1), 0.0},
+      {"v_fma_f32 (inline consts)", run<FMA_INL>(d_out, blocks, threads, e0, e1), 0.0},
       {"v_mad_u64_u32 (+ v_xor_b32)", run<MAD_U64>(d_out, blocks, threads, e0, e1), 1.0},
       {"v_mul_hi_u32", run<MUL_HI>(d_out, blocks, threads, e0, e1), 0.0},
       {"v_mul_lo_u32", run<MUL_LO>(d_out, blocks, threads, e0, e1), 0.0},
@@ -121,13 +127,14 @@ int main() {
       {"v_rcp_f32", run<RCP_F32>(d_out, blocks, threads, e0, e1), 0.0},
       {"v_fma_f64", run<FMA_F64>(d_out, blocks, threads, e0, e1), 0.0},
   };
-  const double fma_rate = steps / (rows[0].ms * 1e-3 * clk_ghz * 1e9) / cus;
-  std::printf("%-26s %10s %18s %12s\n", "op", "ms", "wave-insts/clk/CU", "slots");
+  // "spec slots": issue time in units of one wave64 FMA at the FP32 vector
+  // peak (128 FMA lanes per clock per CU = 2 wave64 FMAs per clock per CU).
+  // The helper instruction of a two-instruction chain step is not subtracted
+  // here; its own row gives its cost.
+  std::printf("%-28s %10s %18s %12s\n", "op", "ms", "wave-insts/clk/CU", "spec slots");
   for (const Row& r : rows) {
     const double rate = steps / (r.ms * 1e-3 * clk_ghz * 1e9) / cus;   // chain steps
-    // slots of the measured instruction: step cost minus the helper's (1 slot each)
-    const double slots = fma_rate / rate - r.extra;
-    std::printf("%-26s %10.4f %18.4f %12.3f\n", r.name, r.ms, rate, slots);
+    std::printf("%-28s %10.4f %18.4f %12.3f\n", r.name, r.ms, rate, 2.0 / rate);
   }
   CHECK(hipFree(d_out));
   return 0;
