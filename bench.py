@@ -42,14 +42,14 @@ MFMA_PEAK = {"fp32": 157.3e12, "bf16": 2.5e15, "fp16": 2.5e15, "bf16x2": 2.5e15}
 # issues at the FP32 vector peak (2 per clock per CU). Each cost is 2 divided
 # by the wave64 issue rate per clock per CU that
 # paper_1906_02818_amd/isa_rates.hip measures for the instruction in
-# isolation (profiles/isa_rates.txt); an FP32 FMA itself issues at 1.78 per
-# clock, so it costs 1.12.
-COST_MUL64 = 3.57    # 32x32->64-bit product (v_mad_u64_u32): 4.13 with its xor, minus 0.56
+# isolation (profiles/isa_rates.txt); an FP32 FMA itself issues at 1.80 per
+# clock, so it costs 1.11.
+COST_MUL64 = 3.45    # 32x32->64-bit product (v_mad_u64_u32): 4.00 with its xor, minus 0.55
 COST_TRANS = 4.09    # v_exp / sin / cos / sqrt / rcp _f32
-COST_LOG = 4.90      # v_log_f32: 6.02 with its dependent add, minus 1.12
-COST_INT = 0.56      # xor, shift, or, compare (gfx950 has no three-input xor)
-COST_FP32 = 1.12     # add, mul, fma
-COST_FP64 = 2.43     # v_fma_f64
+COST_LOG = 4.93      # v_log_f32: 6.04 with its dependent add, minus 1.11
+COST_INT = 0.55      # xor, shift, or, compare (gfx950 has no three-input xor)
+COST_FP32 = 1.11     # add, mul, fma
+COST_FP64 = 2.38     # v_fma_f64
 
 
 def slots(mul64=0.0, trans=0.0, log=0.0, intops=0.0, fp32=0.0, fp64=0.0):
@@ -59,8 +59,13 @@ def slots(mul64=0.0, trans=0.0, log=0.0, intops=0.0, fp32=0.0, fp64=0.0):
 
 # One FP32 normal: a quarter of a Philox4x32-10 block (10 rounds of 2 mul64
 # and 4 xor), the uniform (shift, or, sub) and half of a Box-Muller pair
-# (log, sqrt, sin, cos and 3 mul).
-NORMAL = dict(mul64=5.0, log=0.5, trans=1.5, intops=10.0 + 2.0, fp32=1.0 + 1.5)
+# (log, sqrt, sin, cos and 3 mul). Where every lane of a wave draws the same
+# block index at a step (one path per lane), the first product of round 1
+# and the second of round 2 do not depend on the path: 18 of the 20 products
+# are per-path work. The basket's lanes draw two block indices per step, so
+# all 20 are.
+NORMAL = dict(mul64=18 / 4, log=0.5, trans=1.5, intops=10.0 + 2.0, fp32=1.0 + 1.5)
+NORMAL_BASKET = dict(NORMAL, mul64=20 / 4)
 
 
 def _add(*ds):
@@ -79,7 +84,7 @@ SLOTS_HESTON = slots(**_add(NORMAL, NORMAL, dict(trans=2.0, fp32=11.0)))
 #   v (fma, fma, mul), Asian exp2 + add
 SLOTS_HESTON_REVERSE = slots(trans=2.0, fp32=6.0, fp64=3.0)
 #   per step of the reverse sweep: sqrt, rcp, 6 FP32 ops, 3 FP64 ops
-SLOTS_ASSET_STEP = slots(**_add(NORMAL, dict(intops=0.5)))
+SLOTS_ASSET_STEP = slots(**_add(NORMAL_BASKET, dict(intops=0.5)))
 #   per asset-path-step of the basket: one normal and half a 16-bit pack
 SLOTS_TANH = slots(trans=2.0, fp32=3.0)
 
@@ -173,6 +178,11 @@ def time_to_1bp(ctx, mc, synth, torch, hedge_every=8, adam_steps=2000):
     out["speedup_excl_train"] = out["plain_fp32"]["total_s"] / out["learned_cv_bf16"]["total_s"]
     out["speedup_incl_train"] = (out["plain_fp32"]["total_s"]
                                  / out["learned_cv_bf16"]["total_incl_train_s"])
+    # Both estimators' path counts scale as 1 / SE^2 while the training cost
+    # is fixed: the learned CV, training included, is faster for standard
+    # errors below this many basis points of the price.
+    gain = out["plain_fp32"]["total_s"] - out["learned_cv_bf16"]["total_s"]
+    out["break_even_se_bp"] = math.sqrt(gain / t_train) if gain > 0 else None
     return out
 
 
@@ -187,11 +197,23 @@ def _line(args, metric, value, unit, ms, dtype, config, roofline, higher_is_bett
     return d
 
 
+# HBM bytes per launch from rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE x 1 (KiB;
+# the factors are what the counters read for a 1 GiB copy), for the kernels
+# and launch shapes the profiles under profiles/ name; None where a kernel
+# has no such measurement.
+TRAFFIC_BYTES = {
+    "gbm_path_kernel<float, asian|geo|uo, log-Euler>": 2.984e6,   # 2^24 paths x 252 steps
+    "basket_kernel<8, bf16>": 3.363e6,                          # 2^20 paths x 100 steps
+    "heston_adjoint_kernel<float, full, asian>": 9.411e8,       # 2^22 paths x 256 steps
+}
+
+
 def _alu_roofline(slots_per_unit, units, kernel_ms, kernel):
     achieved = slots_per_unit * units / (kernel_ms * 1e-3)
     return {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_SLOTS / 1e12,
-            "unit": "Tslot/s", "frac": achieved / ALU_PEAK_SLOTS, "traffic": None,
-            "slots_per_unit": slots_per_unit, "kernel": kernel}
+            "unit": "Tslot/s", "frac": achieved / ALU_PEAK_SLOTS,
+            "traffic": TRAFFIC_BYTES.get(kernel), "slots_per_unit": slots_per_unit,
+            "kernel": kernel}
 
 
 def _repeat(args, torch, fn):
