@@ -27,6 +27,8 @@
 // are MFMA products over the wave's 32 paths after a transpose through LDS.
 // Each wave writes its partial gradient in FP64; a fixed-order reduction
 // and the Adam kernel follow.
+#include <type_traits>
+
 #include "device/reduce.h"
 #include "device/rng.h"
 #include "mc_internal.h"
@@ -41,21 +43,68 @@ constexpr int kCvWaves = 4;
 constexpr int kCvThreads = 64 * kCvWaves;
 constexpr float kNeg2Log2e = -2.88539008177792681472f;   // -2 / ln 2
 
-// acc += A (8 k-slots per lane) x B (8 k-slots per lane) over one 16-wide
-// k block: one BF16 MFMA, or eight FP32 MFMAs with the same k-slot order.
+// One MFMA operand: 8 k-slots per lane, held as BF16 for the BF16 products
+// (converted with round-to-nearest-even once, where the value is made) or as
+// FP32 for the FP32 form.
 template <bool BF16>
-__device__ __forceinline__ void mma16(f32x16& acc, const float (&a)[8], const float (&b)[8]) {
-  if constexpr (BF16) {
-    bf16x8 av, bv;
+using FragT = std::conditional_t<BF16, __bf16, float>;
+template <bool BF16>
+struct Op8;
+template <>
+struct Op8<true> {
+  bf16x8 v;
+};
+template <>
+struct Op8<false> {
+  float v[8];
+};
+
+template <bool BF16>
+__device__ __forceinline__ Op8<BF16> op_from(const float (&x)[8]) {
+  Op8<BF16> o;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      av[j] = (__bf16)a[j];
-      bv[j] = (__bf16)b[j];
-    }
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+  for (int j = 0; j < 8; ++j) {
+    if constexpr (BF16)
+      o.v[j] = (__bf16)x[j];
+    else
+      o.v[j] = x[j];
+  }
+  return o;
+}
+
+template <bool BF16>
+__device__ __forceinline__ Op8<BF16> op_zero() {
+  Op8<BF16> o;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) o.v[j] = (FragT<BF16>)0.f;
+  return o;
+}
+
+// 8 consecutive elements from LDS (16-byte aligned for BF16, 32 for FP32).
+template <bool BF16>
+__device__ __forceinline__ Op8<BF16> op_lds(const FragT<BF16>* p) {
+  Op8<BF16> o;
+  if constexpr (BF16) {
+    o.v = *(const bf16x8*)p;
+  } else {
+    const float4 a = *(const float4*)p;
+    const float4 b = *(const float4*)(p + 4);
+    o.v[0] = a.x; o.v[1] = a.y; o.v[2] = a.z; o.v[3] = a.w;
+    o.v[4] = b.x; o.v[5] = b.y; o.v[6] = b.z; o.v[7] = b.w;
+  }
+  return o;
+}
+
+// acc += A x B over one 16-wide k block: one BF16 MFMA, or eight FP32
+// MFMAs with the same k-slot order.
+template <bool BF16>
+__device__ __forceinline__ void mma16(f32x16& acc, const Op8<BF16>& a, const Op8<BF16>& b) {
+  if constexpr (BF16) {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, b.v, acc, 0, 0, 0);
   } else {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[j], b[j], acc, 0, 0, 0);
+    for (int j = 0; j < 8; ++j)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.v[j], b.v[j], acc, 0, 0, 0);
   }
 }
 
@@ -76,6 +125,14 @@ __device__ __forceinline__ void load8(const float* p, float (&x)[8]) {
   x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
 }
 
+// Orders one wave's LDS stores before its later loads of the same region
+// (a wave runs in lockstep; no other wave shares the region).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 constexpr int kFragFloats = 2 * 4 * 64 * 8;   // one set of layer-2 fragments
 constexpr int kLaneFloats = 2 * 64 * 32;      // per-lane b2 (scaled) and W3
 
@@ -83,15 +140,16 @@ constexpr int kLaneFloats = 2 * 64 * 32;      // per-lane b2 (scaled) and W3
 // lane's B fragment of layer 1 (half 0: features and the constant 1; half
 // 1: zeros). Returns Delta (identical in both halves); keeps h1, h2.
 template <bool BF16>
-__device__ __forceinline__ float mlp_forward(const float (&phi)[8], const float (&w1a)[2][8],
-                                             const float* w2f, const float* lanec, int lane,
+__device__ __forceinline__ float mlp_forward(const float (&phi)[8], const Op8<BF16> (&w1a)[2],
+                                             const FragT<BF16>* w2f, const float* lanec, int lane,
                                              float b3, float (&h1)[32], float (&h2)[32]) {
   f32x16 d1[2];
+  const Op8<BF16> phio = op_from<BF16>(phi);
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) d1[mb][r] = 0.f;
-    mma16<BF16>(d1[mb], w1a[mb], phi);
+    mma16<BF16>(d1[mb], w1a[mb], phio);
   }
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb)
@@ -108,15 +166,13 @@ __device__ __forceinline__ float mlp_forward(const float (&phi)[8], const float 
   __asm__ volatile("" ::: "memory");
 #pragma unroll
   for (int kb = 0; kb < 4; ++kb) {
-    float b[8];
+    float bf[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) b[j] = h1[(kb >> 1) * 16 + 8 * (kb & 1) + j];
+    for (int j = 0; j < 8; ++j) bf[j] = h1[(kb >> 1) * 16 + 8 * (kb & 1) + j];
+    const Op8<BF16> b = op_from<BF16>(bf);
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb) {
-      float a[8];
-      load8(&w2f[((mb * 4 + kb) * 64 + lane) * 8], a);
-      mma16<BF16>(d2[mb], a, b);
-    }
+    for (int mb = 0; mb < 2; ++mb)
+      mma16<BF16>(d2[mb], op_lds<BF16>(&w2f[((mb * 4 + kb) * 64 + lane) * 8]), b);
   }
   float part = 0.f;
 #pragma unroll
@@ -133,14 +189,15 @@ __device__ __forceinline__ float mlp_forward(const float (&phi)[8], const float 
 
 template <bool BF16, bool TRAIN>
 __global__ __launch_bounds__(kCvThreads) void cv_kernel(const CvParams P) {
-  __shared__ __attribute__((aligned(16))) float s_w2f[kFragFloats];
+  using FT = FragT<BF16>;
+  __shared__ __attribute__((aligned(16))) FT s_w2f[kFragFloats];
   __shared__ __attribute__((aligned(16))) float s_lanec[kLaneFloats];
-  __shared__ __attribute__((aligned(16))) float s_w2tf[TRAIN ? kFragFloats : 4];
-  __shared__ __attribute__((aligned(16))) float tr[TRAIN ? kCvWaves : 1][TRAIN ? (64 * 32 + 8 * 32) : 4];
+  __shared__ __attribute__((aligned(16))) FT s_w2tf[TRAIN ? kFragFloats : 8];
+  __shared__ __attribute__((aligned(16))) FT tr[TRAIN ? kCvWaves : 1][TRAIN ? (64 * 32 + 8 * 32) : 8];
   const HestonParams& Hp = P.h;
   for (int i = threadIdx.x; i < kFragFloats; i += kCvThreads) {
-    s_w2f[i] = P.w2f[i];
-    if constexpr (TRAIN) s_w2tf[i] = P.w2tf[i];
+    s_w2f[i] = (FT)P.w2f[i];
+    if constexpr (TRAIN) s_w2tf[i] = (FT)P.w2tf[i];
   }
   for (int i = threadIdx.x; i < kLaneFloats; i += kCvThreads) s_lanec[i] = P.lanec[i];
   __syncthreads();
@@ -150,9 +207,13 @@ __global__ __launch_bounds__(kCvThreads) void cv_kernel(const CvParams P) {
   const uint64_t tile = (uint64_t)blockIdx.x * kCvWaves + wave;
   const uint64_t pid = tile * 32 + row;
   const bool active = pid < Hp.n_paths;
-  float w1a[2][8];
+  Op8<BF16> w1a[2];
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb) load8(&P.w1f[(mb * 64 + lane) * 8], w1a[mb]);
+  for (int mb = 0; mb < 2; ++mb) {
+    float w[8];
+    load8(&P.w1f[(mb * 64 + lane) * 8], w);
+    w1a[mb] = op_from<BF16>(w);
+  }
   const float b3 = P.theta[4544];
 
   // Heston step on the discounted log2-price (no rate in its drift).
@@ -245,15 +306,13 @@ __global__ __launch_bounds__(kCvThreads) void cv_kernel(const CvParams P) {
           for (int r = 0; r < 16; ++r) e1[mb][r] = 0.f;
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
-          float b[8];
+          float bf[8];
 #pragma unroll
-          for (int j = 0; j < 8; ++j) b[j] = d2v[(kb >> 1) * 16 + 8 * (kb & 1) + j];
+          for (int j = 0; j < 8; ++j) bf[j] = d2v[(kb >> 1) * 16 + 8 * (kb & 1) + j];
+          const Op8<BF16> b = op_from<BF16>(bf);
 #pragma unroll
-          for (int mb = 0; mb < 2; ++mb) {
-            float a[8];
-            load8(&s_w2tf[((mb * 4 + kb) * 64 + lane) * 8], a);
-            mma16<BF16>(e1[mb], a, b);
-          }
+          for (int mb = 0; mb < 2; ++mb)
+            mma16<BF16>(e1[mb], op_lds<BF16>(&s_w2tf[((mb * 4 + kb) * 64 + lane) * 8]), b);
         }
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb)
@@ -262,62 +321,56 @@ __global__ __launch_bounds__(kCvThreads) void cv_kernel(const CvParams P) {
             const int q = mb * 16 + r;
             d1v[q] = e1[mb][r] * (1.0f - h1[q] * h1[q]);
           }
-        // dW2 += delta2^T H1 over the wave's paths (transpose via LDS).
-        float* T = tr[wave];
-        float* TP = T + 64 * 32;
+        // dW2 += delta2^T H1 over the wave's paths (transpose through the
+        // wave's own LDS region; only this wave touches it, so ordering
+        // within the wave is all that is needed).
+        FT* T = tr[wave];
+        FT* TP = T + 64 * 32;
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-          for (int r = 0; r < 16; ++r) T[unit_of(mb, r, half) * 32 + row] = d2v[mb * 16 + r];
-        __syncthreads();
-        float A2[2][2][8];
+          for (int r = 0; r < 16; ++r) T[unit_of(mb, r, half) * 32 + row] = (FT)d2v[mb * 16 + r];
+        wave_lds_sync();
+        Op8<BF16> A2[2][2];
 #pragma unroll
         for (int pk = 0; pk < 2; ++pk)
 #pragma unroll
-          for (int mb = 0; mb < 2; ++mb) load8(&T[(32 * mb + row) * 32 + 16 * pk + 8 * half], A2[pk][mb]);
-        __syncthreads();
+          for (int mb = 0; mb < 2; ++mb)
+            A2[pk][mb] = op_lds<BF16>(&T[(32 * mb + row) * 32 + 16 * pk + 8 * half]);
+        wave_lds_sync();
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-          for (int r = 0; r < 16; ++r) T[unit_of(mb, r, half) * 32 + row] = h1[mb * 16 + r];
-        __syncthreads();
+          for (int r = 0; r < 16; ++r) T[unit_of(mb, r, half) * 32 + row] = (FT)h1[mb * 16 + r];
+        wave_lds_sync();
 #pragma unroll
         for (int pk = 0; pk < 2; ++pk)
 #pragma unroll
           for (int nb = 0; nb < 2; ++nb) {
-            float b[8];
-            load8(&T[(32 * nb + row) * 32 + 16 * pk + 8 * half], b);
+            const Op8<BF16> b = op_lds<BF16>(&T[(32 * nb + row) * 32 + 16 * pk + 8 * half]);
 #pragma unroll
             for (int mb = 0; mb < 2; ++mb) mma16<BF16>(gw2[mb][nb], A2[pk][mb], b);
           }
-        __syncthreads();
+        wave_lds_sync();
         // dW1ext += delta1^T [phi; 1] over the wave's paths.
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-          for (int r = 0; r < 16; ++r) T[unit_of(mb, r, half) * 32 + row] = d1v[mb * 16 + r];
+          for (int r = 0; r < 16; ++r) T[unit_of(mb, r, half) * 32 + row] = (FT)d1v[mb * 16 + r];
         if (half == 0) {
 #pragma unroll
-          for (int f = 0; f < 8; ++f) TP[f * 32 + row] = phi[f];
+          for (int f = 0; f < 8; ++f) TP[f * 32 + row] = (FT)phi[f];
         }
-        __syncthreads();
+        wave_lds_sync();
 #pragma unroll
         for (int pk = 0; pk < 2; ++pk) {
-          float b[8];
-          if (row < 8) {
-            load8(&TP[row * 32 + 16 * pk + 8 * half], b);
-          } else {
+          const Op8<BF16> b =
+              row < 8 ? op_lds<BF16>(&TP[row * 32 + 16 * pk + 8 * half]) : op_zero<BF16>();
 #pragma unroll
-            for (int j = 0; j < 8; ++j) b[j] = 0.f;
-          }
-#pragma unroll
-          for (int mb = 0; mb < 2; ++mb) {
-            float a[8];
-            load8(&T[(32 * mb + row) * 32 + 16 * pk + 8 * half], a);
-            mma16<BF16>(gw1[mb], a, b);
-          }
+          for (int mb = 0; mb < 2; ++mb)
+            mma16<BF16>(gw1[mb], op_lds<BF16>(&T[(32 * mb + row) * 32 + 16 * pk + 8 * half]), b);
         }
-        __syncthreads();
+        wave_lds_sync();
       }
     }
   }
@@ -394,10 +447,11 @@ __global__ __launch_bounds__(kCvThreads) void cv_kernel(const CvParams P) {
 // same function the training kernel evaluates.
 template <bool BF16>
 __global__ __launch_bounds__(kCvThreads) void cv_eval_kernel(const CvParams P) {
-  __shared__ __attribute__((aligned(16))) float s_w2f[kFragFloats];
+  using FT = FragT<BF16>;
+  __shared__ __attribute__((aligned(16))) FT s_w2f[kFragFloats];
   __shared__ __attribute__((aligned(16))) float s_lanec[kLaneFloats];
   const HestonParams& Hp = P.h;
-  for (int i = threadIdx.x; i < kFragFloats; i += kCvThreads) s_w2f[i] = P.w2f[i];
+  for (int i = threadIdx.x; i < kFragFloats; i += kCvThreads) s_w2f[i] = (FT)P.w2f[i];
   for (int i = threadIdx.x; i < kLaneFloats; i += kCvThreads) s_lanec[i] = P.lanec[i];
   __syncthreads();
 
@@ -405,9 +459,13 @@ __global__ __launch_bounds__(kCvThreads) void cv_eval_kernel(const CvParams P) {
   const int half = lane >> 5;
   const uint64_t pid = ((uint64_t)blockIdx.x * kCvWaves + wave) * 64 + lane;
   const bool active = pid < Hp.n_paths;
-  float w1a[2][8];
+  Op8<BF16> w1a[2];
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb) load8(&P.w1f[(mb * 64 + lane) * 8], w1a[mb]);
+  for (int mb = 0; mb < 2; ++mb) {
+    float w[8];
+    load8(&P.w1f[(mb * 64 + lane) * 8], w);
+    w1a[mb] = op_from<BF16>(w);
+  }
   const float b3 = P.theta[4544];
 
   const float dt = (float)Hp.dt, kdt = (float)(Hp.kappa * Hp.dt);
