@@ -697,7 +697,7 @@ struct CvTrainWs {
 };
 
 size_t cv_train_bytes(uint64_t batch, uint32_t n_steps, uint32_t steps, CvTrainWs* w, char* base) {
-  const RunLayout Lay = layout_for(batch, 3, true, kCvPathsPerBlock);
+  const RunLayout Lay = layout_for(batch, 3, true, kCvTrainPathsPerBlock);
   const uint64_t n_waves =
       (batch + kCvTrainPathsPerBlock - 1) / kCvTrainPathsPerBlock * (kCvTrainPathsPerBlock / 32);
   size_t off = 0;
@@ -733,7 +733,7 @@ mc_status cv_loss_grad_device(mc_context* ctx, hipStream_t s, const mc_model* m,
   mc_options o = defaults();
   o.hip_stream = s;
   o.path_offset = path0;
-  const RunLayout Lay = layout_for(batch, 3, true, kCvPathsPerBlock);
+  const RunLayout Lay = layout_for(batch, 3, true, kCvTrainPathsPerBlock);
   double* partials = (double*)w.eval_base;
   double* mom = (double*)(w.eval_base + Lay.off_mom);
   double* ypath = (double*)(w.eval_base + Lay.off_path);
@@ -741,7 +741,7 @@ mc_status cv_loss_grad_device(mc_context* ctx, hipStream_t s, const mc_model* m,
   p.partials = partials;
   p.path_out = ypath;
   uint32_t nb = 0;
-  HIP_TRY(ctx, launch_cv_price(p, s, &nb));
+  HIP_TRY(ctx, launch_cv_forward32(p, s, &nb));
   HIP_TRY(ctx, launch_final_reduce(partials, nb, Lay.n_mom, mom, s));
   if (log_row)
     HIP_TRY(ctx, hipMemcpyAsync(log_row, mom, Lay.n_mom * 8, hipMemcpyDeviceToDevice, s));

@@ -601,6 +601,19 @@ hipError_t launch_cv_price(const CvParams& p, hipStream_t s, uint32_t* n_blocks)
   return hipGetLastError();
 }
 
+// Forward pass with 32 paths per wave (the training kernel's tiling): twice
+// the waves of the evaluation kernel, for minibatches too small to fill the
+// chip with 64-path waves. Same network function per path.
+hipError_t launch_cv_forward32(const CvParams& p, hipStream_t s, uint32_t* n_blocks) {
+  const uint32_t nb = (uint32_t)((p.h.n_paths + kCvTrainPathsPerBlock - 1) / kCvTrainPathsPerBlock);
+  *n_blocks = nb;
+  if (p.bf16)
+    hipLaunchKernelGGL((cv_kernel<true, false>), dim3(nb), dim3(kCvThreads), 0, s, p);
+  else
+    hipLaunchKernelGGL((cv_kernel<false, false>), dim3(nb), dim3(kCvThreads), 0, s, p);
+  return hipGetLastError();
+}
+
 hipError_t launch_cv_backward(const CvParams& p, hipStream_t s, uint32_t* n_blocks) {
   const uint32_t nb = (uint32_t)((p.h.n_paths + kCvTrainPathsPerBlock - 1) / kCvTrainPathsPerBlock);
   *n_blocks = nb;

@@ -129,6 +129,7 @@ constexpr int kW1fFloats = 2 * 64 * 8, kW2fFloats = 2 * 4 * 64 * 8, kLanecFloats
 hipError_t launch_cv_pack(const float* theta, float* w1f, float* w2f, float* w2tf, float* lanec,
                           hipStream_t s);
 hipError_t launch_cv_price(const CvParams& p, hipStream_t s, uint32_t* n_blocks);
+hipError_t launch_cv_forward32(const CvParams& p, hipStream_t s, uint32_t* n_blocks);
 hipError_t launch_cv_backward(const CvParams& p, hipStream_t s, uint32_t* n_blocks);
 hipError_t launch_adam(float* theta, float* m, float* v, const double* grad, int n, int t,
                        double lr, double b1, double b2, double eps, hipStream_t s);
