@@ -19,8 +19,9 @@
  *   r(w) = sqrt(-2 ln u(w)). A model with d normals per time step uses
  *   k = i d + a at step i (GBM d = 1; Heston d = 2 with a = 0 the variance
  *   driver; basket d = number of assets). Tags: 0 main run, 1 pilot run,
- *   2 learned-hedge training set; tag + 5 carries the Brownian-bridge
- *   uniforms of the continuously monitored barrier.
+ *   2 learned-hedge training set, tag + 16 l level l of a multilevel
+ *   estimate; tag + 5 carries the Brownian-bridge uniforms of the
+ *   continuously monitored barrier.
  *
  * Conventions for every entry point:
  *   - Returns an mc_status; no exception or signal crosses the ABI.
@@ -239,6 +240,66 @@ mc_status mc_cv_loss_grad(mc_context *ctx, const mc_model *model, const mc_payof
                           uint32_t n_steps, uint64_t seed, uint32_t tag, uint64_t path0,
                           uint64_t batch, const mc_adam_cfg *cfg, const float *weights,
                           double *loss_out, float *grad_out);
+
+/* Multilevel Monte Carlo (Sec. V-B, Sec. VIII; Giles): the estimate of the
+ * finest level's expectation as a telescoping sum of independent level
+ * estimators,
+ *     E[P_L] = E[P_0] + sum_{l=1..L-1} E[P_l - P_{l-1}],
+ * where level l's correction is simulated with both the level's own
+ * configuration ("fine") and the previous level's ("coarse") on the SAME
+ * paths, so that its variance is small and few paths suffice. Two
+ * couplings between consecutive levels:
+ *   precision: equal n_steps, different prec. Fine and coarse use the same
+ *              normals; this is the low-precision companion estimator whose
+ *              bias a reference-precision level corrects (Sec. V-B). Any
+ *              model.
+ *   time:      equal prec, n_steps(l) = c n_steps(l-1) with c = 2 or 4. The
+ *              coarse step k uses (z_{ck} + ... + z_{ck+c-1}) / sqrt(c) of the
+ *              fine path's normals (the same Brownian path on the coarser
+ *              grid). One-dimensional GBM, every payoff except the
+ *              Brownian-bridge barrier.
+ * Level l draws from stream tag opts->stream_tag + 16 l (paths from
+ * opts->path_offset), so levels are independent. The payoff must have
+ * cv = MC_CV_NONE; opts->greeks and opts->path_values must be 0 / NULL. The
+ * per-path values of a correction level are kept on the device in chunks of
+ * at most 2^20 paths and reduced there (FP64); n_paths per level is
+ * otherwise unlimited. Errors: n_levels outside 1..MC_MLMC_MAX_LEVELS, a
+ * level with n_paths < 2 or n_steps = 0 -> MC_ERR_INVALID_ARG; consecutive
+ * levels that match neither coupling, or a model/payoff/precision that the
+ * single-level mc_price rejects -> that error. */
+#define MC_MLMC_MAX_LEVELS 8
+typedef struct {
+    uint32_t n_steps;          /* time steps of this level */
+    mc_precision prec;         /* arithmetic of this level */
+    uint64_t n_paths;          /* paths of this level's estimator, >= 2 */
+} mc_level;
+
+typedef enum { MC_COUPLE_NONE = 0, MC_COUPLE_PRECISION = 1, MC_COUPLE_TIME = 2 } mc_coupling;
+
+typedef struct {
+    double price;              /* sum of the level means */
+    double std_err;            /* sqrt(sum_l variance[l] / n_paths[l]) */
+    uint32_t n_levels;
+    mc_coupling coupling[MC_MLMC_MAX_LEVELS];    /* level 0: MC_COUPLE_NONE */
+    double mean[MC_MLMC_MAX_LEVELS];       /* Y_0 = P_0, Y_l = P_l - P_{l-1} */
+    double variance[MC_MLMC_MAX_LEVELS];   /* sample variance of Y_l (N_l - 1) */
+    double fine_mean[MC_MLMC_MAX_LEVELS];  /* mean of P_l on level l's paths */
+    double coarse_mean[MC_MLMC_MAX_LEVELS];/* mean of P_{l-1} on the same paths */
+    uint64_t n_paths[MC_MLMC_MAX_LEVELS];
+    double kernel_ms[MC_MLMC_MAX_LEVELS];  /* device time of the level's kernels */
+} mc_mlmc_result;
+
+mc_status mc_price_mlmc(mc_context *ctx, const mc_model *model, const mc_payoff *payoff,
+                        uint32_t n_levels, const mc_level *levels, uint64_t seed,
+                        const mc_options *opts, mc_mlmc_result *out);
+
+/* Path counts that minimise the total cost sum_l N_l cost[l] subject to
+ * sum_l var[l] / N_l = target_se^2 (Lagrange multiplier; Giles):
+ *     N_l = ceil(target_se^-2 sqrt(var[l] / cost[l]) sum_k sqrt(var[k] cost[k])),
+ * at least 2. var and cost: host [n_levels], finite, var >= 0, cost > 0.
+ * Host arithmetic only (no device). Errors: MC_ERR_INVALID_ARG. */
+mc_status mc_mlmc_allocate(uint32_t n_levels, const double *var, const double *cost,
+                           double target_se, uint64_t *n_paths_out);
 
 /* Raw Philox4x32-10 blocks of sampled (path, block) pairs and the normals
  * of one path, computed by the same device functions the path kernels use

@@ -17,9 +17,12 @@ import numpy as np
 
 from . import _abi
 from ._abi import (MC_ADJ_FULL, MC_ADJ_FWD, MC_ADJ_REV, MC_ASIAN_ARITH_CALL, MC_ASIAN_GEO_CALL,
-                   MC_BASKET_CALL, MC_BF16_GEMM, MC_BF16X2_GEMM, MC_CV_GEO_ASIAN, MC_CV_LEARNED,
-                   MC_CV_NONE, MC_EULER_S, MC_EURO_CALL, MC_FP16_GEMM, MC_FP32, MC_FP64, MC_GBM,
-                   MC_GBM_BASKET, MC_GREEK_DELTA, MC_GREEK_VEGA, MC_HESTON, MC_LOG_EULER,
+                   MC_BASKET_CALL, MC_BF16_GEMM, MC_BF16X2_GEMM, MC_COUPLE_NONE,
+                   MC_COUPLE_PRECISION, MC_COUPLE_TIME, MC_CV_GEO_ASIAN, MC_CV_LEARNED,
+                   MC_CV_NONE, MC_ERR_DEVICE, MC_ERR_INVALID_ARG, MC_ERR_NO_DEVICE,
+                   MC_ERR_NOT_PD, MC_ERR_OOM, MC_ERR_UNSUPPORTED, MC_ERR_WORKSPACE, MC_EULER_S,
+                   MC_EURO_CALL, MC_FP16_GEMM, MC_FP32, MC_FP64, MC_GBM, MC_GBM_BASKET,
+                   MC_GREEK_DELTA, MC_GREEK_VEGA, MC_HESTON, MC_LOG_EULER, MC_MLMC_MAX_LEVELS,
                    MC_MLP_NPARAM, MC_OK, MC_UO_BARRIER_CALL, MC_UO_BRIDGE_CALL)
 
 __all__ = [n for n in dir(_abi) if n.startswith("MC_")] + [
@@ -27,7 +30,7 @@ __all__ = [n for n in dir(_abi) if n.startswith("MC_")] + [
     "mc_price", "mc_price_multi", "mc_greeks_adjoint", "mc_cv_train", "mc_cv_loss_grad",
     "mc_philox_words", "mc_normals", "mc_path_channels", "mc_path_channel_name",
     "mc_workspace_bytes", "mc_adjoint_ckpt_bytes", "mc_status_str", "mc_last_error",
-    "PathwisePrice", "PreparedPriceMulti"]
+    "mc_price_mlmc", "mc_mlmc_allocate", "Level", "PathwisePrice", "PreparedPriceMulti"]
 
 
 class McError(RuntimeError):
@@ -291,6 +294,49 @@ def mc_price_multi(ctx: Context, model: Model, payoffs: Sequence[Payoff], n_path
                                     n_steps, seed, C.byref(mm.co), res)
     _check(ctx, st)
     return [_result(r) for r in res]
+
+
+@dataclass
+class Level:
+    """One level of a multilevel estimate (mc_level)."""
+    n_steps: int
+    prec: int
+    n_paths: int
+
+
+def mc_price_mlmc(ctx: Context, model: Model, payoff: Payoff, levels: Sequence[Level], seed: int,
+                  opts: Options | None = None) -> dict:
+    """Multilevel estimate: level 0 plain, level l the correction P_l - P_{l-1}
+    on paths shared by both configurations (mc_price_mlmc)."""
+    mm = _Marshal(model, payoff, opts, max(lv.n_paths for lv in levels))
+    torch = _torch()
+    if torch is not None:
+        mm.co.hip_stream = torch.cuda.current_stream(ctx.device).cuda_stream
+    arr = (_abi.McLevel * len(levels))(
+        *[_abi.McLevel(int(lv.n_steps), int(lv.prec), int(lv.n_paths)) for lv in levels])
+    res = _abi.McMlmcResult()
+    st = _abi.load().mc_price_mlmc(ctx.handle, C.byref(mm.cm), C.byref(mm.cp), len(levels), arr,
+                                   seed, C.byref(mm.co), C.byref(res))
+    _check(ctx, st)
+    n = res.n_levels
+    lv = [{k: getattr(res, k)[i] for k in ("coupling", "mean", "variance", "fine_mean",
+                                           "coarse_mean", "n_paths", "kernel_ms")}
+          for i in range(n)]
+    return {"price": res.price, "std_err": res.std_err, "levels": lv}
+
+
+def mc_mlmc_allocate(var: Sequence[float], cost: Sequence[float], target_se: float) -> list[int]:
+    """Cost-optimal path counts per level for a target standard error."""
+    v = _arr(var)
+    c = _arr(cost)
+    if v.size != c.size:
+        raise ValueError("var and cost differ in length")
+    out = np.zeros(v.size, np.uint64)
+    st = _abi.load().mc_mlmc_allocate(v.size, v.ctypes.data_as(C.POINTER(C.c_double)),
+                                      c.ctypes.data_as(C.POINTER(C.c_double)), float(target_se),
+                                      out.ctypes.data_as(C.POINTER(C.c_uint64)))
+    _check(None, st)
+    return [int(x) for x in out]
 
 
 class PreparedPriceMulti:

@@ -21,6 +21,8 @@ MC_CV_NONE, MC_CV_GEO_ASIAN, MC_CV_LEARNED = 0, 1, 2
 MC_GREEK_DELTA, MC_GREEK_VEGA = 1, 2
 MC_ADJ_FULL, MC_ADJ_FWD, MC_ADJ_REV = 0, 1, 2
 MC_MLP_NPARAM = 4545
+MC_MLMC_MAX_LEVELS = 8
+MC_COUPLE_NONE, MC_COUPLE_PRECISION, MC_COUPLE_TIME = 0, 1, 2
 
 _dp = C.POINTER(C.c_double)
 _fp = C.POINTER(C.c_float)
@@ -57,6 +59,21 @@ class McResult(C.Structure):
                 ("kernel_ms", C.c_double), ("cv_fallback", C.c_int)]
 
 
+class McLevel(C.Structure):
+    _fields_ = [("n_steps", C.c_uint32), ("prec", C.c_int), ("n_paths", C.c_uint64)]
+
+
+_L = MC_MLMC_MAX_LEVELS
+
+
+class McMlmcResult(C.Structure):
+    _fields_ = [("price", C.c_double), ("std_err", C.c_double), ("n_levels", C.c_uint32),
+                ("coupling", C.c_int * _L), ("mean", C.c_double * _L),
+                ("variance", C.c_double * _L), ("fine_mean", C.c_double * _L),
+                ("coarse_mean", C.c_double * _L), ("n_paths", C.c_uint64 * _L),
+                ("kernel_ms", C.c_double * _L)]
+
+
 class McAdamCfg(C.Structure):
     _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
                 ("eps", C.c_double), ("steps", C.c_uint32), ("batch", C.c_uint64),
@@ -91,6 +108,9 @@ SIGNATURES = {
                                   _u32p]),
     "mc_normals": (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64,
                              C.c_uint64, C.c_int, _dp]),
+    "mc_price_mlmc": (C.c_int, [C.c_void_p, _P(McModel), _P(McPayoff), C.c_uint32, _P(McLevel),
+                                C.c_uint64, _P(McOptions), _P(McMlmcResult)]),
+    "mc_mlmc_allocate": (C.c_int, [C.c_uint32, _dp, _dp, C.c_double, _u64p]),
     "mc_status_str": (C.c_char_p, [C.c_int]),
     "mc_last_error": (C.c_char_p, [C.c_void_p]),
 }

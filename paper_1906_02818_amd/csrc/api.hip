@@ -25,6 +25,13 @@ struct mc_context {
   size_t pinned_count = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::string err;
+  // Multilevel runs: when `sink` is set, run_moments writes the per-path
+  // values there (device) instead of returning them to the host; `coarsen`
+  // is the GBM coupling factor of the next run (1 = plain).
+  double* sink = nullptr;
+  uint32_t coarsen = 1;
+  void* mlmc_buf = nullptr;
+  size_t mlmc_bytes = 0;
 };
 
 namespace {
@@ -272,7 +279,8 @@ mc_status run_moments(mc_context* ctx, const mc_options& o, uint64_t n_paths, in
   hipStream_t s = stream_of(ctx, o);
   double* partials = (double*)base;
   double* mom = (double*)(base + L.off_mom);
-  double* path_out = host_path_values ? (double*)(base + L.off_path) : nullptr;
+  double* path_out =
+      ctx->sink ? ctx->sink : (host_path_values ? (double*)(base + L.off_path) : nullptr);
   HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
   uint32_t nb = 0;
   HIP_TRY(ctx, launch(partials, path_out, s, &nb));
@@ -280,7 +288,7 @@ mc_status run_moments(mc_context* ctx, const mc_options& o, uint64_t n_paths, in
   if (nb == 0 || nb > L.n_blocks) return fail(ctx, MC_ERR_DEVICE, "block count mismatch");
   HIP_TRY(ctx, launch_final_reduce(partials, nb, L.n_mom, mom, s));
   HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, mom, L.n_mom * sizeof(double), hipMemcpyDeviceToHost, s));
-  if (path_out)
+  if (host_path_values && !ctx->sink)
     HIP_TRY(ctx, hipMemcpyAsync(host_path_values, path_out, n_paths * C * sizeof(double),
                                 hipMemcpyDeviceToHost, s));
   HIP_TRY(ctx, hipStreamSynchronize(s));
@@ -365,6 +373,7 @@ GbmParams gbm_params(const mc_model* m, const mc_payoff* f, uint64_t n_paths, ui
   p.k0 = (uint32_t)seed;
   p.k1 = (uint32_t)(seed >> 32);
   p.log_scheme = m->scheme == MC_LOG_EULER;
+  p.coarsen = 1;
   p.S0 = S0;
   p.K = f->K;
   p.disc = std::exp(-r * T);
@@ -389,10 +398,11 @@ mc_status gbm_run(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint64
                   double* kernel_ms) {
   const bool fp64 = o.prec == MC_FP64;
   const bool logs = m->scheme == MC_LOG_EULER;
-  const uint32_t mask = gbm_pick_mask(want, fp64, logs);
+  const uint32_t mask = gbm_pick_mask(want, fp64, logs, ctx->coarsen);
   if (!mask) return fail(ctx, MC_ERR_UNSUPPORTED, "payoff not available for this scheme/precision");
   *mask_used = mask;
   GbmParams p = gbm_params(m, f, n_paths, n_steps, seed, o, fp64, tag);
+  p.coarsen = ctx->coarsen;
   return run_moments(ctx, o, n_paths, gbm_channels(mask), path_values,
                      [&](double* partials, double* path_out, hipStream_t s, uint32_t* nb) {
                        p.partials = partials;
@@ -924,6 +934,70 @@ mc_status basket_price(mc_context* ctx, const mc_model* m, const mc_payoff* f, u
   return MC_OK;
 }
 
+// ---- multilevel helpers ----
+
+// Per-path channel count of a plain run of (m, f, o) and the payoff's
+// channel in it (coarsen: GBM coupling factor of the run).
+mc_status payoff_channel(mc_context* ctx, const mc_model* m, const mc_payoff* f,
+                         const mc_options& o, uint32_t coarsen, uint32_t* C, uint32_t* ch) {
+  if (m->kind == MC_GBM) {
+    mc_status st = MC_OK;
+    const uint32_t want = gbm_want_mask(f, o, &st);
+    if (st != MC_OK) return fail(ctx, st, "payoff not offered for GBM");
+    const uint32_t mask =
+        gbm_pick_mask(want, o.prec == MC_FP64, m->scheme == MC_LOG_EULER, coarsen);
+    if (!mask) return fail(ctx, MC_ERR_UNSUPPORTED, "payoff not available for this coupling");
+    uint32_t bit = 0;
+    switch (f->kind) {
+      case MC_EURO_CALL: bit = G_EURO; break;
+      case MC_ASIAN_ARITH_CALL: bit = G_ASIAN; break;
+      case MC_ASIAN_GEO_CALL: bit = G_GEO; break;
+      case MC_UO_BARRIER_CALL: bit = G_UO; break;
+      case MC_UO_BRIDGE_CALL: bit = G_UOBB; break;
+      default: return fail(ctx, MC_ERR_UNSUPPORTED, "payoff not offered for GBM");
+    }
+    const int c = gbm_channel_index(mask, bit);
+    if (c < 0) return fail(ctx, MC_ERR_DEVICE, "channel layout mismatch");
+    *C = (uint32_t)gbm_channels(mask);
+    *ch = (uint32_t)c;
+    return MC_OK;
+  }
+  if (m->kind == MC_HESTON) {
+    *C = 2;
+    *ch = f->kind == MC_EURO_CALL ? 0u : 1u;
+    return MC_OK;
+  }
+  *C = 3;
+  *ch = 0;
+  return MC_OK;
+}
+
+// Restores the context's plain-run state however a level ends.
+struct SinkGuard {
+  mc_context* ctx;
+  ~SinkGuard() {
+    ctx->sink = nullptr;
+    ctx->coarsen = 1;
+  }
+};
+
+mc_status get_mlmc_buf(mc_context* ctx, size_t bytes, char** base) {
+  if (ctx->mlmc_bytes < bytes) {
+    if (ctx->mlmc_buf) {
+      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      HIP_TRY(ctx, hipFree(ctx->mlmc_buf));
+      ctx->mlmc_buf = nullptr;
+      ctx->mlmc_bytes = 0;
+    }
+    HIP_TRY(ctx, hipMalloc(&ctx->mlmc_buf, bytes));
+    ctx->mlmc_bytes = bytes;
+  }
+  *base = (char*)ctx->mlmc_buf;
+  return MC_OK;
+}
+
+constexpr uint64_t kMlmcChunk = 1ull << 20;
+
 }  // namespace
 
 // ================================================================ C ABI ===
@@ -958,6 +1032,7 @@ mc_status mc_destroy(mc_context* ctx) {
   if (!ctx) return MC_OK;
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->mlmc_buf) (void)hipFree(ctx->mlmc_buf);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -1122,6 +1197,166 @@ mc_status mc_price_multi(mc_context* ctx, const mc_model* m, const mc_payoff* fs
   return MC_OK;
 }
 
+// ---------------------------------------------------------- Multilevel ----
+mc_status mc_price_mlmc(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint32_t n_levels,
+                        const mc_level* levels, uint64_t seed, const mc_options* opts,
+                        mc_mlmc_result* out) {
+  if (!ctx) return MC_ERR_INVALID_ARG;
+  if (!m || !f || !levels || !out) return fail(ctx, MC_ERR_INVALID_ARG, "NULL argument");
+  if (n_levels < 1 || n_levels > MC_MLMC_MAX_LEVELS)
+    return fail(ctx, MC_ERR_INVALID_ARG, "n_levels must be in 1..%d", MC_MLMC_MAX_LEVELS);
+  const mc_options o0 = opts ? *opts : defaults();
+  if (f->cv != MC_CV_NONE)
+    return fail(ctx, MC_ERR_UNSUPPORTED, "multilevel estimates take payoffs without a control variate");
+  if (o0.greeks) return fail(ctx, MC_ERR_UNSUPPORTED, "multilevel estimates carry no greeks");
+  if (o0.path_values) return fail(ctx, MC_ERR_UNSUPPORTED, "multilevel estimates return no path values");
+  mc_coupling cpl[MC_MLMC_MAX_LEVELS] = {};
+  uint32_t cfac[MC_MLMC_MAX_LEVELS] = {};
+  for (uint32_t l = 0; l < n_levels; ++l) {
+    const mc_level& lv = levels[l];
+    if (lv.n_paths < 2 || lv.n_steps == 0)
+      return fail(ctx, MC_ERR_INVALID_ARG, "level %u: n_paths >= 2 and n_steps >= 1", l);
+    mc_options ol = o0;
+    ol.prec = lv.prec;
+    mc_status st = validate_all(ctx, m, f, lv.n_paths, lv.n_steps, ol);
+    if (st != MC_OK) return st;
+    if (l == 0) continue;
+    const mc_level& pv = levels[l - 1];
+    if (lv.n_steps == pv.n_steps && lv.prec != pv.prec) {
+      cpl[l] = MC_COUPLE_PRECISION;
+      cfac[l] = 1;
+    } else if (lv.prec == pv.prec && (lv.n_steps == 2 * pv.n_steps || lv.n_steps == 4 * pv.n_steps)) {
+      if (m->kind != MC_GBM)
+        return fail(ctx, MC_ERR_UNSUPPORTED, "time-step coupling is offered for 1-D GBM");
+      if (f->kind == MC_UO_BRIDGE_CALL)
+        return fail(ctx, MC_ERR_UNSUPPORTED, "time-step coupling of the bridge barrier");
+      cpl[l] = MC_COUPLE_TIME;
+      cfac[l] = lv.n_steps / pv.n_steps;
+    } else {
+      return fail(ctx, MC_ERR_UNSUPPORTED,
+                  "levels %u and %u: need equal steps with different precision, or equal "
+                  "precision with 2x / 4x the steps", l - 1, l);
+    }
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, MC_ERR_DEVICE, "hipSetDevice");
+  hipStream_t s = stream_of(ctx, o0);
+  mc_mlmc_result r{};
+  r.n_levels = n_levels;
+  double var_over_n = 0.0;
+  for (uint32_t l = 0; l < n_levels; ++l) {
+    const mc_level& lv = levels[l];
+    mc_options ol = o0;
+    ol.prec = lv.prec;
+    ol.stream_tag = o0.stream_tag + 16u * l;
+    r.coupling[l] = cpl[l];
+    if (l == 0) {
+      mc_result pr{};
+      mc_status st = mc_price(ctx, m, f, lv.n_paths, lv.n_steps, seed, &ol, &pr);
+      if (st != MC_OK) return st;
+      r.mean[0] = r.fine_mean[0] = pr.price;
+      r.variance[0] = pr.variance;
+      r.n_paths[0] = pr.n_paths;
+      r.kernel_ms[0] = pr.kernel_ms;
+      var_over_n += pr.variance / (double)pr.n_paths;
+      continue;
+    }
+    // Correction level: fine = this level, coarse = previous level's
+    // configuration, on the same paths of this level's stream.
+    const mc_level& pv = levels[l - 1];
+    mc_options oc = ol;
+    oc.prec = pv.prec;
+    uint32_t Ca = 0, ca = 0, Cb = 0, cb = 0;
+    mc_status st = payoff_channel(ctx, m, f, ol, 1, &Ca, &ca);
+    if (st != MC_OK) return st;
+    st = payoff_channel(ctx, m, f, oc, cfac[l], &Cb, &cb);
+    if (st != MC_OK) return st;
+    const uint64_t n_chunks = (lv.n_paths + kMlmcChunk - 1) / kMlmcChunk;
+    const uint64_t chunk = (lv.n_paths + n_chunks - 1) / n_chunks;
+    const size_t bytes_a = align256((size_t)chunk * Ca * sizeof(double));
+    const size_t bytes_b = align256((size_t)chunk * Cb * sizeof(double));
+    const uint32_t M = (uint32_t)n_moments(3);
+    const size_t bytes_p = align256((size_t)kDiffMaxBlocks * M * sizeof(double));
+    char* base = nullptr;
+    st = get_mlmc_buf(ctx, bytes_a + bytes_b + bytes_p + align256(M * sizeof(double)), &base);
+    if (st != MC_OK) return st;
+    st = get_pinned(ctx, M);
+    if (st != MC_OK) return st;
+    double* A = (double*)base;
+    double* B = (double*)(base + bytes_a);
+    double* partials = (double*)(base + bytes_a + bytes_b);
+    double* mom = (double*)(base + bytes_a + bytes_b + bytes_p);
+    double acc[n_moments(3)] = {};
+    double kms = 0.0;
+    for (uint64_t p0 = 0; p0 < lv.n_paths; p0 += chunk) {
+      const uint64_t nc = lv.n_paths - p0 < chunk ? lv.n_paths - p0 : chunk;
+      mc_result tmp{};
+      {
+        SinkGuard guard{ctx};
+        mc_options of = ol;
+        of.path_offset = o0.path_offset + p0;
+        ctx->sink = A;
+        ctx->coarsen = 1;
+        st = mc_price(ctx, m, f, nc, lv.n_steps, seed, &of, &tmp);
+        if (st != MC_OK) return st;
+        kms += tmp.kernel_ms;
+        mc_options ocp = oc;
+        ocp.path_offset = o0.path_offset + p0;
+        ctx->sink = B;
+        ctx->coarsen = cfac[l];
+        st = mc_price(ctx, m, f, nc, pv.n_steps, seed, &ocp, &tmp);
+        if (st != MC_OK) return st;
+        kms += tmp.kernel_ms;
+      }
+      uint32_t nb = 0;
+      HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
+      HIP_TRY(ctx, launch_diff_moments(A, Ca, ca, B, Cb, cb, nc, partials, s, &nb));
+      HIP_TRY(ctx, launch_final_reduce(partials, nb, M, mom, s));
+      HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));
+      HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, mom, M * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(ctx, hipStreamSynchronize(s));
+      float ms = 0.f;
+      HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+      kms += ms;
+      for (uint32_t i = 0; i < M; ++i) acc[i] += ctx->pinned[i];
+    }
+    // acc: [n, nonfinite, sum d, sum a, sum b, dd, da, db, aa, ab, bb]
+    const double n = acc[0];
+    if (n < 2) return fail(ctx, MC_ERR_DEVICE, "level %u: fewer than two finite paths", l);
+    r.mean[l] = acc[2] / n;
+    r.variance[l] = (acc[5] - acc[2] * acc[2] / n) / (n - 1.0);
+    r.fine_mean[l] = acc[3] / n;
+    r.coarse_mean[l] = acc[4] / n;
+    r.n_paths[l] = (uint64_t)n;
+    r.kernel_ms[l] = kms;
+    var_over_n += r.variance[l] / n;
+  }
+  for (uint32_t l = 0; l < n_levels; ++l) r.price += r.mean[l];
+  r.std_err = std::sqrt(var_over_n);
+  *out = r;
+  return MC_OK;
+}
+
+mc_status mc_mlmc_allocate(uint32_t n_levels, const double* var, const double* cost,
+                           double target_se, uint64_t* n_paths_out) {
+  if (n_levels < 1 || n_levels > MC_MLMC_MAX_LEVELS || !var || !cost || !n_paths_out)
+    return MC_ERR_INVALID_ARG;
+  if (!(target_se > 0.0) || !std::isfinite(target_se)) return MC_ERR_INVALID_ARG;
+  double sum = 0.0;
+  for (uint32_t l = 0; l < n_levels; ++l) {
+    if (!(var[l] >= 0.0) || !std::isfinite(var[l]) || !(cost[l] > 0.0) || !std::isfinite(cost[l]))
+      return MC_ERR_INVALID_ARG;
+    sum += std::sqrt(var[l] * cost[l]);
+  }
+  uint64_t tmp[MC_MLMC_MAX_LEVELS];
+  for (uint32_t l = 0; l < n_levels; ++l) {
+    const double n = std::ceil(sum * std::sqrt(var[l] / cost[l]) / (target_se * target_se));
+    if (!(n < 0x1p62)) return MC_ERR_INVALID_ARG;
+    tmp[l] = n < 2.0 ? 2u : (uint64_t)n;
+  }
+  for (uint32_t l = 0; l < n_levels; ++l) n_paths_out[l] = tmp[l];
+  return MC_OK;
+}
+
 size_t mc_adjoint_ckpt_bytes(uint64_t n_paths, uint32_t n_steps, uint32_t ckpt_every) {
   if (ckpt_every != (uint32_t)mcp::kCkpt || n_steps == 0) return 0;
   const uint64_t n_ckpt = (n_steps + ckpt_every - 1) / ckpt_every;
@@ -1209,7 +1444,7 @@ mc_status mc_greeks_adjoint(mc_context* ctx, const mc_model* m, const mc_payoff*
   return MC_OK;
 }
 
-mc_status validate_adam(mc_context* ctx, const mc_adam_cfg* cfg, uint64_t n_train) {
+static mc_status validate_adam(mc_context* ctx, const mc_adam_cfg* cfg, uint64_t n_train) {
   if (!cfg) return fail(ctx, MC_ERR_INVALID_ARG, "cfg must not be NULL");
   if (!(std::isfinite(cfg->lr) && cfg->lr > 0 && cfg->beta1 >= 0 && cfg->beta1 < 1 &&
         cfg->beta2 >= 0 && cfg->beta2 < 1 && cfg->eps > 0))

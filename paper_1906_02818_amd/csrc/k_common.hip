@@ -1,5 +1,8 @@
-// Second stage of the averaging reduction (Eq. 3) and the diagnostic kernels
-// that expose the device random numbers for bit-exact checks.
+// Second stage of the averaging reduction (Eq. 3), the reduction of a
+// multilevel correction (difference of two runs on the same paths) and the
+// diagnostic kernels that expose the device random numbers for bit-exact
+// checks.
+#include "device/reduce.h"
 #include "device/rng.h"
 #include "mc_internal.h"
 
@@ -50,7 +53,42 @@ __global__ void normals_kernel(uint32_t k0, uint32_t k1, uint32_t tag, uint64_t 
   out[i] = (double)nz.z[k & 3];
 }
 
+// Moments of y = (a[ca] - b[cb], a[ca], b[cb]) per path, a and b row-major
+// [n][Ca] and [n][Cb] tables of two runs on the same paths. The difference
+// is taken in FP64 from the stored values, so its variance carries no
+// cancellation from the cross moments.
+__global__ __launch_bounds__(kBlock) void diff_moments_kernel(const double* __restrict__ a,
+                                                              uint32_t Ca, uint32_t ca,
+                                                              const double* __restrict__ b,
+                                                              uint32_t Cb, uint32_t cb, uint64_t n,
+                                                              double* __restrict__ partials) {
+  constexpr int M = n_moments(3);
+  double acc[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) acc[m] = 0.0;
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const double fa = a[i * Ca + ca], fb = b[i * Cb + cb];
+    const double y[3] = {fa - fb, fa, fb};
+    const bool finite = isfinite(y[0]) && isfinite(fa) && isfinite(fb);
+    accumulate_moments<3>(acc, y, finite, !finite);
+  }
+  block_reduce_moments<M, kBlock>(acc, partials, gridDim.x);
+}
+
 }  // namespace
+
+hipError_t launch_diff_moments(const double* a, uint32_t Ca, uint32_t ca, const double* b,
+                               uint32_t Cb, uint32_t cb, uint64_t n, double* partials,
+                               hipStream_t s, uint32_t* n_blocks) {
+  const uint64_t need = (n + kBlock - 1) / kBlock;
+  const uint32_t nb = (uint32_t)(need < kDiffMaxBlocks ? need : kDiffMaxBlocks);
+  *n_blocks = nb;
+  if (nb == 0 || ca >= Ca || cb >= Cb) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(diff_moments_kernel, dim3(nb), dim3(kBlock), 0, s, a, Ca, ca, b, Cb, cb, n,
+                     partials);
+  return hipGetLastError();
+}
 
 hipError_t launch_final_reduce(const double* partials, uint32_t n_blocks, uint32_t n_mom,
                                double* out, hipStream_t s) {

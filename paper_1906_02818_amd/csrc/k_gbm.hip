@@ -100,7 +100,7 @@ struct GbmStepper {
   }
 };
 
-template <typename R, uint32_t MASK, bool LOGS>
+template <typename R, uint32_t MASK, bool LOGS, uint32_t CO>
 __device__ __forceinline__ void simulate(const GbmParams& P, uint64_t path,
                                          double (&y)[gbm_channels(MASK)]) {
   GbmStepper<R, MASK, LOGS> st;
@@ -112,7 +112,30 @@ __device__ __forceinline__ void simulate(const GbmParams& P, uint64_t path,
   const PathCounter pc = make_counter(path, P.tag, P.k0, P.k1);
   const PathCounter pcb = make_counter(path, P.tag + 5u, P.k0, P.k1);
   const uint32_t n = P.n_steps;
-  const uint32_t n_full = n >> 2;
+  if constexpr (CO > 1) {
+    // Coupled coarse path: step i takes normals CO i .. CO i + CO - 1 of the
+    // fine path, summed and scaled by 1/sqrt(CO) (same Brownian increment
+    // over the coarse step). CO divides the 4 normals of a Philox block.
+    static_assert(CO == 2 || CO == 4, "coupling factor");
+    const R rsc = CO == 2 ? R(0.70710678118654752440) : R(0.5);
+    constexpr uint32_t SPB = 4 / CO;              // coarse steps per block
+    const uint32_t nb = n / SPB;
+    for (uint32_t j = 0; j < nb; ++j) {
+      const Normals4<R> nz = normals4<R>(philox(j, pc));
+#pragma unroll
+      for (uint32_t q = 0; q < SPB; ++q) {
+        R Z = nz.z[q * CO];
+#pragma unroll
+        for (uint32_t t = 1; t < CO; ++t) Z += nz.z[q * CO + t];
+        st.step(s, Z * rsc, SPB * j + q, R(0));
+      }
+    }
+    if (n % SPB) {                                 // CO = 2, odd n: one step left
+      const Normals4<R> nz = normals4<R>(philox(nb, pc));
+      st.step(s, (nz.z[0] + nz.z[1]) * rsc, n - 1, R(0));
+    }
+  }
+  const uint32_t n_full = CO > 1 ? 0u : n >> 2;
   for (uint32_t j = 0; j < n_full; ++j) {
     const Normals4<R> nz = normals4<R>(philox(j, pc));
     Words4 wb{0, 0, 0, 0};
@@ -124,7 +147,7 @@ __device__ __forceinline__ void simulate(const GbmParams& P, uint64_t path,
       st.step(s, nz.z[q], 4 * j + q, U);
     }
   }
-  const uint32_t rem = n & 3u;
+  const uint32_t rem = CO > 1 ? 0u : n & 3u;
   if (rem) {
     const Normals4<R> nz = normals4<R>(philox(n_full, pc));
     Words4 wb{0, 0, 0, 0};
@@ -168,7 +191,7 @@ __device__ __forceinline__ void simulate(const GbmParams& P, uint64_t path,
 // Persistent grid: at most kGbmMaxBlocks workgroups (one wave of blocks at
 // full occupancy); each thread prices paths pid, pid + stride, ... and keeps
 // their moments in FP64 registers, so each block writes one moment vector.
-template <typename R, uint32_t MASK, bool LOGS>
+template <typename R, uint32_t MASK, bool LOGS, uint32_t CO>
 __global__ __launch_bounds__(kBlock) void gbm_path_kernel(const GbmParams P) {
   constexpr int C = gbm_channels(MASK);
   constexpr int M = n_moments(C);
@@ -179,7 +202,7 @@ __global__ __launch_bounds__(kBlock) void gbm_path_kernel(const GbmParams P) {
   for (uint64_t pid = (uint64_t)blockIdx.x * kBlock + threadIdx.x; pid < P.n_paths;
        pid += stride) {
     double y[C];
-    simulate<R, MASK, LOGS>(P, P.path_offset + pid, y);
+    simulate<R, MASK, LOGS, CO>(P, P.path_offset + pid, y);
     bool finite = true;
 #pragma unroll
     for (int c = 0; c < C; ++c) finite = finite && isfinite(y[c]);
@@ -192,10 +215,19 @@ __global__ __launch_bounds__(kBlock) void gbm_path_kernel(const GbmParams P) {
   block_reduce_moments<M, kBlock>(acc, P.partials, gridDim.x);
 }
 
-template <typename R, uint32_t MASK, bool LOGS>
+template <typename R, uint32_t MASK, bool LOGS, uint32_t CO = 1>
 hipError_t launch_one(const GbmParams& p, hipStream_t s, uint32_t nb) {
-  hipLaunchKernelGGL((gbm_path_kernel<R, MASK, LOGS>), dim3(nb), dim3(kBlock), 0, s, p);
+  hipLaunchKernelGGL((gbm_path_kernel<R, MASK, LOGS, CO>), dim3(nb), dim3(kBlock), 0, s, p);
   return hipGetLastError();
+}
+
+// Coupled coarse paths (multilevel): every channel except the bridge barrier.
+constexpr uint32_t kMaskCoupled = G_ALL & ~G_UOBB;
+
+template <typename R, bool LOGS>
+hipError_t launch_coupled(const GbmParams& p, hipStream_t s, uint32_t nb) {
+  return p.coarsen == 2 ? launch_one<R, kMaskCoupled, LOGS, 2>(p, s, nb)
+                        : launch_one<R, kMaskCoupled, LOGS, 4>(p, s, nb);
 }
 
 constexpr uint32_t kMaskEuro = G_EURO;
@@ -204,7 +236,11 @@ constexpr uint32_t kMaskPath3 = G_ASIAN | G_GEO | G_UO;
 
 }  // namespace
 
-uint32_t gbm_pick_mask(uint32_t want, bool fp64, bool log_scheme) {
+uint32_t gbm_pick_mask(uint32_t want, bool fp64, bool log_scheme, uint32_t coarsen) {
+  if (coarsen != 1) {
+    if (coarsen != 2 && coarsen != 4) return 0;
+    return (want & ~kMaskCoupled) == 0 ? kMaskCoupled : 0;
+  }
   const uint32_t f32_log[] = {kMaskEuro, kMaskEuroG, kMaskPath3, G_ALL};
   const uint32_t f64_log[] = {kMaskEuroG, G_ALL};
   const uint32_t any_s[] = {G_ALL & ~G_UOBB};
@@ -232,6 +268,11 @@ hipError_t launch_gbm(const GbmParams& p, uint32_t mask, bool fp64, hipStream_t 
   *n_blocks = nb;
   const bool L = p.log_scheme != 0;
   constexpr uint32_t kMaskS = G_ALL & ~G_UOBB;
+  if (p.coarsen != 1) {
+    if (mask != kMaskCoupled || (p.coarsen != 2 && p.coarsen != 4)) return hipErrorInvalidValue;
+    if (L) return fp64 ? launch_coupled<double, true>(p, s, nb) : launch_coupled<float, true>(p, s, nb);
+    return fp64 ? launch_coupled<double, false>(p, s, nb) : launch_coupled<float, false>(p, s, nb);
+  }
   if (L && !fp64) {
     switch (mask) {
       case kMaskEuro: return launch_one<float, kMaskEuro, true>(p, s, nb);

@@ -39,6 +39,9 @@ struct GbmParams {
   uint64_t n_paths, path_offset;
   uint32_t n_steps, tag, k0, k1;
   int log_scheme;
+  // Multilevel coupling: step i uses the normalised sum of normals
+  // coarsen*i .. coarsen*i + coarsen - 1 (1, 2 or 4; 1 = plain).
+  uint32_t coarsen;
   // Model constants, double on the host; kernels round them to their type.
   double S0, K, disc, T, dt, sdt, sigma;
   // Log scheme, in the kernel's log domain (log2 for FP32, ln for FP64):
@@ -53,9 +56,17 @@ struct GbmParams {
 // returned by gbm_pick_mask). Returns the number of blocks via *n_blocks.
 hipError_t launch_gbm(const GbmParams& p, uint32_t mask, bool fp64, hipStream_t s,
                       uint32_t* n_blocks);
-// Smallest instantiated mask containing `want` for this precision/scheme,
-// or 0 when none does.
-uint32_t gbm_pick_mask(uint32_t want, bool fp64, bool log_scheme);
+// Smallest instantiated mask containing `want` for this precision/scheme
+// and coupling factor, or 0 when none does.
+uint32_t gbm_pick_mask(uint32_t want, bool fp64, bool log_scheme, uint32_t coarsen = 1);
+
+// Moments of [a[ca] - b[cb], a[ca], b[cb]] over n paths of two per-path
+// tables with Ca and Cb channels (multilevel correction); returns the block
+// count.
+hipError_t launch_diff_moments(const double* a, uint32_t Ca, uint32_t ca, const double* b,
+                               uint32_t Cb, uint32_t cb, uint64_t n, double* partials,
+                               hipStream_t s, uint32_t* n_blocks);
+constexpr uint32_t kDiffMaxBlocks = 1024;
 
 // ---- Heston ----
 enum : uint32_t { H_EURO = 1u << 0, H_ASIAN = 1u << 1 };

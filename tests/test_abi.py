@@ -55,6 +55,55 @@ def test_struct_layout_matches_header(tmp_path):
     assert got == want
 
 
+def test_mlmc_struct_layout_matches_header(tmp_path):
+    src = str(tmp_path / "abi_mlmc.c")
+    with open(src, "w") as f:
+        f.write('#include <stdio.h>\n#include <stddef.h>\n#include "mcpath.h"\n'
+                'int main(){printf("%zu %zu %zu %zu %zu\\n", sizeof(mc_level), '
+                'sizeof(mc_mlmc_result), offsetof(mc_mlmc_result, mean), '
+                'offsetof(mc_mlmc_result, n_paths), offsetof(mc_mlmc_result, kernel_ms));}\n')
+    exe = src[:-2]
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+    got = [int(x) for x in subprocess.run([exe], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    R = _abi.McMlmcResult
+    assert got == [C.sizeof(_abi.McLevel), C.sizeof(R), R.mean.offset, R.n_paths.offset,
+                   R.kernel_ms.offset]
+
+
+def test_mlmc_allocation_is_the_lagrange_optimum():
+    # N_l proportional to sqrt(V_l / C_l), scaled so that sum V_l / N_l hits
+    # the target variance; checked against a direct minimisation.
+    var = np.array([40.0, 0.5, 0.12, 0.03])
+    cost = np.array([1.0, 3.0, 6.0, 12.0])
+    eps = 0.01
+    n = np.array(mc.mc_mlmc_allocate(var, cost, eps), np.float64)
+    lam = np.sum(np.sqrt(var * cost)) / eps ** 2
+    np.testing.assert_array_equal(n, np.ceil(lam * np.sqrt(var / cost)))
+    assert np.sum(var / n) <= eps ** 2 * (1 + 1e-12)
+    # Any other allocation with the same variance costs at least as much.
+    rng = np.random.default_rng(0)
+    for _ in range(200):
+        x = n * np.exp(rng.normal(0, 0.3, n.size))
+        x *= np.sum(var / x) / eps ** 2
+        assert np.sum(x * cost) >= np.sum(n * cost) * (1 - 1e-6)
+    assert mc.mc_mlmc_allocate([0.0, 1.0], [1.0, 1.0], 1.0) == [2, 2]
+
+
+@pytest.mark.parametrize("var,cost,eps", [([1.0], [0.0], 0.1), ([-1.0], [1.0], 0.1),
+                                          ([1.0], [1.0], 0.0), ([np.nan], [1.0], 0.1),
+                                          ([1.0] * 9, [1.0] * 9, 0.1)])
+def test_mlmc_allocation_rejects_bad_input(var, cost, eps):
+    with pytest.raises(mc.McError) as e:
+        mc.mc_mlmc_allocate(var, cost, eps)
+    assert e.value.status == mc._abi.MC_ERR_INVALID_ARG
+
+
+def test_binding_exports_every_name():
+    missing = [n for n in mc.__all__ if not hasattr(mc, n)]
+    assert not missing, missing
+
+
 def test_status_strings():
     assert mc.mc_status_str(0) == "MC_OK"
     assert mc.mc_status_str(-2) == "MC_ERR_NOT_PD"
