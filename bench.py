@@ -315,6 +315,54 @@ def run_basket(args, ctx, mc, synth, torch):
                  prices={"price": r["price"], "se": r["std_err"], "delta0": r["delta"]})
 
 
+def run_mlmc_basket(args, ctx, mc, synth, torch):
+    """Time to a standard error of 1 bp of the price on the d = 256 basket:
+    plain FP32 Monte Carlo against the two-level estimator whose level 0
+    runs the BF16 matrix product and whose level 1 corrects it to FP32 on
+    shared paths (the low-precision companion estimator with a reference-
+    precision correction). Each side: a 2^18-path pilot (stream tag 1, and
+    1 + 16 for the pilot's correction level) sizes the main run (tag 0;
+    the multilevel path counts from mc_mlmc_allocate with the pilot's level
+    variances and measured per-path device times); pilot and run are timed."""
+    c = synth.BASKET
+    n, d = c["n_steps"], c["d"]
+    sigma, corr, _ = synth.basket_market(d)
+    model = mc.Model(kind=mc.MC_GBM_BASKET, S0=[c["S0"]] * d, r=c["r"], T=c["T"], sigma=sigma,
+                     corr=corr)
+    f = mc.Payoff(mc.MC_BASKET_CALL, c["K"])
+    pilot = 1 << 18
+    pil, t_pil = _timed(torch, lambda: mc.mc_price(ctx, model, f, pilot, n, synth.SEED,
+                                                   mc.Options(prec=mc.MC_FP32, stream_tag=1)))
+    N_plain = _paths_for(1e-4 * pil["price"], math.sqrt(pil["variance"]))
+    run, t_run = _timed(torch, lambda: mc.mc_price(ctx, model, f, N_plain, n, synth.SEED,
+                                                   mc.Options(prec=mc.MC_FP32)))
+    plain = {"pilot_s": t_pil, "n_paths": N_plain, "run_s": t_run, "total_s": t_pil + t_run,
+             "price": run["price"], "std_err": run["std_err"], "kernel_ms": run["kernel_ms"]}
+    lp = [mc.Level(n, mc.MC_BF16_GEMM, pilot), mc.Level(n, mc.MC_FP32, pilot)]
+    mp, t_mp = _timed(torch, lambda: mc.mc_price_mlmc(ctx, model, f, lp, synth.SEED,
+                                                      mc.Options(stream_tag=1)))
+    var = [lv["variance"] for lv in mp["levels"]]
+    cost = [lv["kernel_ms"] / lv["n_paths"] for lv in mp["levels"]]
+    N = mc.mc_mlmc_allocate(var, cost, 1e-4 * mp["price"])
+    levels = [mc.Level(n, mc.MC_BF16_GEMM, N[0]), mc.Level(n, mc.MC_FP32, N[1])]
+    mr, t_mr = _timed(torch, lambda: mc.mc_price_mlmc(ctx, model, f, levels, synth.SEED))
+    l0, l1 = mr["levels"]
+    mlmc = {"pilot_s": t_mp, "pilot_var": var, "pilot_cost_ms_per_path": cost, "n_paths": N,
+            "run_s": t_mr, "total_s": t_mp + t_mr, "price": mr["price"],
+            "std_err": mr["std_err"], "level_kernel_ms": [l0["kernel_ms"], l1["kernel_ms"]],
+            "bf16_bias": l1["mean"], "bf16_bias_se": math.sqrt(l1["variance"] / l1["n_paths"]),
+            "level0_price": l0["mean"]}
+    k_ms = l0["kernel_ms"]
+    roof = _alu_roofline(SLOTS_ASSET_STEP, N[0] * n * d, k_ms, "basket_kernel<8, bf16>")
+    return _line(args, "time to 1bp SE", mlmc["total_s"], "s", mlmc["total_s"] * 1e3, "bf16",
+                 {"workload": f"basket call, d = {d} correlated GBM, {n} steps; target SE = "
+                              "1e-4 x price; BF16 level + FP32 correction level vs plain FP32",
+                  "n_steps": n, "d": d},
+                 roof, higher_is_better=False,
+                 time_to_1bp={"plain_fp32": plain, "mlmc_bf16_fp32": mlmc,
+                              "speedup": plain["total_s"] / mlmc["total_s"]})
+
+
 def run_heston_adjoint(args, ctx, mc, synth, torch):
     H = synth.HESTON
     N, n = H["n_paths"], H["n_steps"]
@@ -351,7 +399,8 @@ def run_learned_cv(args, ctx, mc, synth, torch):
 
 
 WORKLOADS = {"asian_barrier": run_asian_barrier, "european": run_european, "basket": run_basket,
-             "heston_adjoint": run_heston_adjoint, "learned_cv": run_learned_cv}
+             "heston_adjoint": run_heston_adjoint, "learned_cv": run_learned_cv,
+             "mlmc_basket": run_mlmc_basket}
 
 
 def main():
