@@ -58,6 +58,14 @@ def lib():
         L.orc_basket.argtypes = [C.c_int, _dp, _dp, _dp, _dp, C.c_double,
                                  C.c_double, C.c_double, C.c_int, C.c_uint64,
                                  C.c_uint32, C.c_uint64, C.c_uint64, _dp]
+        L.orc_bs_call.argtypes = [C.c_double] * 5
+        L.orc_bs_call.restype = C.c_double
+        L.orc_portfolio_premium.argtypes = [C.c_int, _dp, _dp, C.c_int, _dp, _dp,
+                                            C.c_double, C.c_double]
+        L.orc_portfolio_premium.restype = C.c_double
+        L.orc_portfolio_pnl.argtypes = [C.c_int, _dp, _dp, _dp, _dp, C.c_int, _dp, _dp,
+                                        C.c_double, C.c_double, C.c_int, C.c_uint64,
+                                        C.c_uint32, C.c_uint64, C.c_uint64, _dp]
         L.orc_heston_cv.argtypes = [_dp, C.c_int, C.c_int, _dp, C.c_uint64,
                                     C.c_uint32, C.c_uint64, C.c_uint64, _dp]
         L.orc_mlp_eval.argtypes = [_dp, C.c_uint64, _dp, _dp]
@@ -146,6 +154,44 @@ def basket(S0, sigma, L, w, r, T, K, n_steps, n_paths, seed, tag=0,
     lib().orc_basket(d, S0, sigma, L, w, r, T, K, n_steps, seed, tag, path0,
                      n_paths, out)
     return out
+
+
+def portfolio_premium(S0, sigma, m, q, r, T) -> float:
+    """Black-Scholes value at time 0 of q_k calls of strike m_k S0_a on every
+    asset (Sec. VI-B.1 portfolio)."""
+    S0, sigma = _c(S0), _c(sigma)
+    m, q = _c(m), _c(q)
+    return lib().orc_portfolio_premium(S0.size, S0, sigma, m.size, m, q, r, T)
+
+
+def portfolio_pnl(S0, sigma, mu, L, m, q, r, T, n_steps, n_paths, seed, tag=0,
+                  path0=0) -> np.ndarray:
+    """Per-path horizon P&L of the call portfolio on d correlated GBM assets
+    with real-world drifts mu (Sec. VI-B.1)."""
+    S0, sigma, mu, L = _c(S0), _c(sigma), _c(mu), _c(L)
+    m, q = _c(m), _c(q)
+    out = np.zeros(n_paths, np.float64)
+    lib().orc_portfolio_pnl(S0.size, S0, sigma, mu, L, m.size, m, q, r, T, n_steps,
+                            seed, tag, path0, n_paths, out)
+    return out
+
+
+def var_cvar(pnl, alpha):
+    """Empirical Value-at-Risk and Conditional Value-at-Risk of Sec. VI-B.1.
+    VaR_alpha = -inf{x : F_N(x) > 1 - alpha}, the k-th smallest P&L with
+    k = floor(N (1 - alpha)) + 1; CVaR_alpha = -mean{PnL_i : -PnL_i > VaR}.
+    Returns (VaR, CVaR, k, number of tail paths)."""
+    x = np.sort(np.asarray(pnl, np.float64))
+    N = x.size
+    k = int(np.floor(N * (1.0 - alpha))) + 1
+    var = -x[k - 1]
+    tail = x[x < x[k - 1]]
+    cvar = -tail.mean() if tail.size else float("nan")
+    return var, cvar, k, tail.size
+
+
+def _c(a) -> np.ndarray:
+    return np.ascontiguousarray(np.atleast_1d(np.asarray(a, np.float64)))
 
 
 def _heston_prm(h: dict) -> np.ndarray:

@@ -425,6 +425,72 @@ void orc_basket(int d, const double *S0, const double *sigma, const double *L,
 }
 
 /* ------------------------------------------------------------------------ */
+/* 8b. Portfolio profit and loss for the risk metrics of Sec. VI-B.1: the    */
+/*    d correlated GBM assets of section 8 under the real-world measure      */
+/*    (drift mu_a in place of r), log-Euler over the horizon T in n steps.   */
+/*    The portfolio holds q_k European calls of strike m_k S0_a on every     */
+/*    asset a (k = 0..ns-1), expiring at the horizon:                        */
+/*      PnL = sum_a sum_k q_k (S_{T,a} - m_k S0_a)^+  -  V0,                 */
+/*    V0 the Black-Scholes value at time 0 (rate r, volatility sigma_a) of   */
+/*    the same holdings. No discounting of the horizon value.                */
+/* ------------------------------------------------------------------------ */
+double orc_bs_call(double S, double K, double r, double sig, double T)
+{
+    const double sq = sig * sqrt(T);
+    const double d1 = (log(S / K) + (r + 0.5 * sig * sig) * T) / sq;
+    const double d2 = d1 - sq;
+    const double N1 = 0.5 * erfc(-d1 / sqrt(2.0));
+    const double N2 = 0.5 * erfc(-d2 / sqrt(2.0));
+    return S * N1 - K * exp(-r * T) * N2;
+}
+
+double orc_portfolio_premium(int d, const double *S0, const double *sigma, int ns,
+                             const double *m, const double *q, double r, double T)
+{
+    double v = 0.0;
+    for (int a = 0; a < d; ++a)
+        for (int k = 0; k < ns; ++k)
+            v += q[k] * orc_bs_call(S0[a], m[k] * S0[a], r, sigma[a], T);
+    return v;
+}
+
+void orc_portfolio_pnl(int d, const double *S0, const double *sigma, const double *mu,
+                       const double *L, int ns, const double *m, const double *q,
+                       double r, double T, int n_steps, uint64_t seed, uint32_t tag,
+                       uint64_t path0, uint64_t n_paths, double *out)
+{
+    const double dt = T / n_steps, sdt = sqrt(dt);
+    const double V0 = orc_portfolio_premium(d, S0, sigma, ns, m, q, r, T);
+#pragma omp parallel
+    {
+        double *x = (double *)malloc(sizeof(double) * (size_t)d);
+        double *Z = (double *)malloc(sizeof(double) * (size_t)d);
+#pragma omp for schedule(static)
+        for (long long p = 0; p < (long long)n_paths; ++p) {
+            normal_stream ns_;
+            ns_init(&ns_, seed, tag, path0 + (uint64_t)p);
+            for (int a = 0; a < d; ++a) x[a] = log(S0[a]);
+            for (int i = 0; i < n_steps; ++i) {
+                for (int a = 0; a < d; ++a) Z[a] = ns_next(&ns_);
+                for (int a = 0; a < d; ++a) {
+                    double dW = 0.0;
+                    for (int b = 0; b <= a; ++b) dW += L[(size_t)a * d + b] * Z[b];
+                    x[a] += (mu[a] - 0.5 * sigma[a] * sigma[a]) * dt + sigma[a] * sdt * dW;
+                }
+            }
+            double v = 0.0;
+            for (int a = 0; a < d; ++a) {
+                const double S = exp(x[a]);
+                for (int k = 0; k < ns; ++k) v += q[k] * pos(S - m[k] * S0[a]);
+            }
+            out[p] = v - V0;
+        }
+        free(x);
+        free(Z);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* 9. Learned martingale control variate on the Heston Asian call.           */
 /*    A small network Delta_theta(t, state) is a hedge ratio; the hedge     */
 /*    P&L  H = sum_j Delta(t_j, phi_j) (St_{j+1} - St_j),  St_i = e^{-r t_i}  */

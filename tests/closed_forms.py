@@ -120,3 +120,28 @@ def geo_basket_call(S0, sigma, corr, w, r, T, K):
     ws = w * sigma
     s2 = float(ws @ np.asarray(corr) @ ws) * T
     return lognormal_call(m, s2, K, math.exp(-r * T))
+
+
+# Risk metrics of a short-call position on one GBM asset (Sec. VI-B.1) -----
+def short_calls_var_cvar(S0, mu, sigma, T, strikes, qty, premium, alpha):
+    """VaR and CVaR of PnL = sum_k q_k (S_T - K_k)^+ - premium with all q_k < 0
+    and S_T lognormal under drift mu: the P&L falls as S_T rises, so the loss
+    tail is S_T above its alpha-quantile s. Requires s above every strike.
+    Also returns the density of the P&L at its (1 - alpha)-quantile, for the
+    standard error of the empirical quantile."""
+    st = sigma * math.sqrt(T)
+    z = norm.ppf(alpha)
+    s = S0 * math.exp((mu - 0.5 * sigma * sigma) * T + st * z)
+    assert all(q < 0 for q in qty) and s > max(strikes)
+    pnl_s = sum(q * (s - K) for q, K in zip(qty, strikes)) - premium
+    var = -pnl_s
+    # E[S_T 1{S_T > s}] and P(S_T > s) = 1 - alpha
+    d1 = (math.log(S0 / s) + (mu + 0.5 * sigma * sigma) * T) / st
+    es = S0 * math.exp(mu * T) * norm.cdf(d1)
+    tail = 1.0 - alpha
+    cond = sum(q * (es - K * tail) for q, K in zip(qty, strikes)) / tail - premium
+    cvar = -cond
+    # density of S_T at s, mapped through |dPnL/dS| = -sum q_k
+    fs = norm.pdf(z) / (s * st)
+    f_pnl = fs / abs(sum(qty))
+    return var, cvar, f_pnl
