@@ -301,6 +301,56 @@ mc_status mc_price_mlmc(mc_context *ctx, const mc_model *model, const mc_payoff 
 mc_status mc_mlmc_allocate(uint32_t n_levels, const double *var, const double *cost,
                            double target_se, uint64_t *n_paths_out);
 
+/* Portfolio risk over a horizon (Sec. VI-B.1). The basket model's d assets
+ * (dim a multiple of 16 up to 256, correlation, sigma) are simulated by
+ * log-Euler under the real-world measure, with drift mu[a] in place of r,
+ * to the horizon T = model->T in n_steps steps. The portfolio holds, on
+ * every asset a, quantity[k] European calls of strike strike_mult[k] * S0_a
+ * expiring at the horizon (k < n_strikes; negative quantities are short).
+ * Per path
+ *     PnL = sum_a sum_k quantity[k] (S_{T,a} - strike_mult[k] S0_a)^+ - V0,
+ * V0 the Black-Scholes value at time 0 (rate r, volatility sigma_a) of the
+ * holdings; the horizon value is not discounted. With k = floor(N (1 -
+ * alpha)) + 1 and PnL_(k) the k-th smallest of the N path values,
+ *     VaR_alpha  = -PnL_(k)  (the printed infimum read as the (1 - alpha)
+ *                            quantile: -inf{x : P(PnL <= x) > 1 - alpha}),
+ *     CVaR_alpha = -mean{PnL_i : PnL_i < PnL_(k)}  (-E[PnL | -PnL > VaR]).
+ * The order statistic is exact over the simulated values (radix select on
+ * the device). Options: prec MC_FP32, MC_BF16_GEMM or MC_FP16_GEMM;
+ * stream_tag, path_offset, hip_stream; path_values (host [N], the P&L of
+ * each path) optional; greeks must be 0. The per-path P&L is kept in
+ * context-owned device memory (8 bytes per path). Errors: a NULL argument,
+ * n_strikes outside 1..MC_MAX_STRIKES, a non-finite or negative strike,
+ * non-finite quantity or drift, alpha outside (0, 1) or k < 2 (an empty
+ * tail) -> MC_ERR_INVALID_ARG; a model the basket pricer rejects -> that
+ * error. */
+#define MC_MAX_STRIKES 8
+typedef struct {
+    uint32_t n_strikes;                    /* calls per asset, 1..MC_MAX_STRIKES */
+    double strike_mult[MC_MAX_STRIKES];    /* strike of call k on asset a / S0_a */
+    double quantity[MC_MAX_STRIKES];       /* holding of call k on each asset */
+    const double *mu;                      /* [dim] real-world drifts; NULL: model->r */
+    double alpha;                          /* confidence level, 0 < alpha < 1 */
+} mc_portfolio;
+
+typedef struct {
+    double var;                /* VaR_alpha */
+    double cvar;               /* CVaR_alpha */
+    double quantile_pnl;       /* PnL_(k) = -VaR_alpha */
+    double pnl_mean;           /* mean horizon P&L */
+    double pnl_std_err;        /* its standard error */
+    double premium;            /* V0 */
+    uint64_t k;                /* rank of the order statistic */
+    uint64_t n_tail;           /* paths strictly below PnL_(k) */
+    uint64_t n_paths;
+    double kernel_ms;          /* path kernel */
+    double select_ms;          /* order statistic and tail sum */
+} mc_risk_result;
+
+mc_status mc_risk(mc_context *ctx, const mc_model *model, const mc_portfolio *portfolio,
+                  uint64_t n_paths, uint32_t n_steps, uint64_t seed, const mc_options *opts,
+                  mc_risk_result *out);
+
 /* Raw Philox4x32-10 blocks of sampled (path, block) pairs and the normals
  * of one path, computed by the same device functions the path kernels use
  * (bit-exact checks of the random-number layout). Host arrays. */

@@ -23,14 +23,15 @@ from ._abi import (MC_ADJ_FULL, MC_ADJ_FWD, MC_ADJ_REV, MC_ASIAN_ARITH_CALL, MC_
                    MC_ERR_NOT_PD, MC_ERR_OOM, MC_ERR_UNSUPPORTED, MC_ERR_WORKSPACE, MC_EULER_S,
                    MC_EURO_CALL, MC_FP16_GEMM, MC_FP32, MC_FP64, MC_GBM, MC_GBM_BASKET,
                    MC_GREEK_DELTA, MC_GREEK_VEGA, MC_HESTON, MC_LOG_EULER, MC_MLMC_MAX_LEVELS,
-                   MC_MLP_NPARAM, MC_OK, MC_UO_BARRIER_CALL, MC_UO_BRIDGE_CALL)
+                   MC_MAX_STRIKES, MC_MLP_NPARAM, MC_OK, MC_UO_BARRIER_CALL, MC_UO_BRIDGE_CALL)
 
 __all__ = [n for n in dir(_abi) if n.startswith("MC_")] + [
     "McError", "Model", "Payoff", "Options", "mc_create", "mc_destroy", "mc_validate",
     "mc_price", "mc_price_multi", "mc_greeks_adjoint", "mc_cv_train", "mc_cv_loss_grad",
     "mc_philox_words", "mc_normals", "mc_path_channels", "mc_path_channel_name",
     "mc_workspace_bytes", "mc_adjoint_ckpt_bytes", "mc_status_str", "mc_last_error",
-    "mc_price_mlmc", "mc_mlmc_allocate", "Level", "PathwisePrice", "PreparedPriceMulti"]
+    "mc_price_mlmc", "mc_mlmc_allocate", "Level", "mc_risk", "PathwisePrice",
+    "PreparedPriceMulti"]
 
 
 class McError(RuntimeError):
@@ -337,6 +338,42 @@ def mc_mlmc_allocate(var: Sequence[float], cost: Sequence[float], target_se: flo
                                       out.ctypes.data_as(C.POINTER(C.c_uint64)))
     _check(None, st)
     return [int(x) for x in out]
+
+
+def mc_risk(ctx: Context, model: Model, strike_mult: Sequence[float], quantity: Sequence[float],
+            alpha: float, n_paths: int, n_steps: int, seed: int, mu=None,
+            opts: Options | None = None) -> dict:
+    """Horizon P&L of a call portfolio on the basket's assets under drifts mu
+    (None: the model's r); VaR and CVaR at level alpha (mc_risk). With
+    opts.path_values the per-path P&L is returned as "pnl"."""
+    mm = _Marshal(model, Payoff(MC_BASKET_CALL, 0.0), opts, n_paths)
+    torch = _torch()
+    if torch is not None:
+        mm.co.hip_stream = torch.cuda.current_stream(ctx.device).cuda_stream
+    m = _arr(strike_mult)
+    q = _arr(quantity)
+    if m.size != q.size or not 1 <= m.size <= MC_MAX_STRIKES:
+        raise ValueError("strike_mult and quantity: 1..8 entries each, equal lengths")
+    pf = _abi.McPortfolio()
+    pf.n_strikes = m.size
+    for i in range(m.size):
+        pf.strike_mult[i] = m[i]
+        pf.quantity[i] = q[i]
+    if mu is not None:
+        pf.mu = mm._ptr(_arr(mu), C.c_double)
+    pf.alpha = alpha
+    pnl = None
+    if mm.opts.path_values:
+        pnl = np.zeros(n_paths, np.float64)
+        mm.co.path_values = mm._ptr(pnl, C.c_double)
+    res = _abi.McRiskResult()
+    st = _abi.load().mc_risk(ctx.handle, C.byref(mm.cm), C.byref(pf), n_paths, n_steps, seed,
+                             C.byref(mm.co), C.byref(res))
+    _check(ctx, st)
+    out = {name: getattr(res, name) for name, _ in _abi.McRiskResult._fields_}
+    if pnl is not None:
+        out["pnl"] = pnl
+    return out
 
 
 class PreparedPriceMulti:

@@ -22,6 +22,7 @@ MC_GREEK_DELTA, MC_GREEK_VEGA = 1, 2
 MC_ADJ_FULL, MC_ADJ_FWD, MC_ADJ_REV = 0, 1, 2
 MC_MLP_NPARAM = 4545
 MC_MLMC_MAX_LEVELS = 8
+MC_MAX_STRIKES = 8
 MC_COUPLE_NONE, MC_COUPLE_PRECISION, MC_COUPLE_TIME = 0, 1, 2
 
 _dp = C.POINTER(C.c_double)
@@ -74,6 +75,18 @@ class McMlmcResult(C.Structure):
                 ("kernel_ms", C.c_double * _L)]
 
 
+class McPortfolio(C.Structure):
+    _fields_ = [("n_strikes", C.c_uint32), ("strike_mult", C.c_double * MC_MAX_STRIKES),
+                ("quantity", C.c_double * MC_MAX_STRIKES), ("mu", _dp), ("alpha", C.c_double)]
+
+
+class McRiskResult(C.Structure):
+    _fields_ = [("var", C.c_double), ("cvar", C.c_double), ("quantile_pnl", C.c_double),
+                ("pnl_mean", C.c_double), ("pnl_std_err", C.c_double), ("premium", C.c_double),
+                ("k", C.c_uint64), ("n_tail", C.c_uint64), ("n_paths", C.c_uint64),
+                ("kernel_ms", C.c_double), ("select_ms", C.c_double)]
+
+
 class McAdamCfg(C.Structure):
     _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
                 ("eps", C.c_double), ("steps", C.c_uint32), ("batch", C.c_uint64),
@@ -111,6 +124,8 @@ SIGNATURES = {
     "mc_price_mlmc": (C.c_int, [C.c_void_p, _P(McModel), _P(McPayoff), C.c_uint32, _P(McLevel),
                                 C.c_uint64, _P(McOptions), _P(McMlmcResult)]),
     "mc_mlmc_allocate": (C.c_int, [C.c_uint32, _dp, _dp, C.c_double, _u64p]),
+    "mc_risk": (C.c_int, [C.c_void_p, _P(McModel), _P(McPortfolio), C.c_uint64, C.c_uint32,
+                          C.c_uint64, _P(McOptions), _P(McRiskResult)]),
     "mc_status_str": (C.c_char_p, [C.c_int]),
     "mc_last_error": (C.c_char_p, [C.c_void_p]),
 }

@@ -819,11 +819,16 @@ size_t basket_ws_bytes(size_t layout_bytes, uint32_t d, mc_precision prec) {
   const size_t elt = prec == MC_FP32 ? 4 : 2;
   const size_t blk = align256((size_t)nd * (nd + 1) * 512 * elt);
   return align256(layout_bytes) + blk * (prec == MC_BF16X2_GEMM ? 2 : 1) +
-         align256(3 * 256 * sizeof(float));
+         align256(4 * 256 * sizeof(float));
 }
 
+// Basket run. With `port` set it prices the call portfolio of the risk
+// metrics instead: drifts port->mu (or r) and one per-path channel, the
+// horizon P&L (value of the holdings at T minus their Black-Scholes value
+// `premium` at 0); out->price / variance / std_err describe that P&L.
 mc_status basket_price(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint64_t n_paths,
-                       uint32_t n_steps, uint64_t seed, const mc_options& o0, mc_result* out) {
+                       uint32_t n_steps, uint64_t seed, const mc_options& o0, mc_result* out,
+                       const mc_portfolio* port = nullptr, double premium = 0.0) {
   std::vector<double> L;
   mc_status st = validate_basket(ctx, m, f, n_steps, o0, &L);
   if (st != MC_OK) return st;
@@ -863,15 +868,17 @@ mc_status basket_price(mc_context* ctx, const mc_model* m, const mc_payoff* f, u
       blk_bytes = b16.size() * 2;
       break;
   }
-  // Per-asset constants: n mu_a in log2 units, w_a S0_a, w_a ln 2.
-  std::vector<float> asset(3 * 256, 0.f);
+  // Per-asset constants: n mu_a in log2 units, w_a S0_a, w_a ln 2, S0_a.
+  std::vector<float> asset(4 * 256, 0.f);
   double geo0 = 0.0;
   for (uint32_t a = 0; a < d; ++a) {
     const double w = f->weights ? f->weights[a] : 1.0 / d;
-    const double mu = (m->r - 0.5 * m->sigma[a] * m->sigma[a]) * dt * inv_ln2;
+    const double drift = (port && port->mu) ? port->mu[a] : m->r;
+    const double mu = (drift - 0.5 * m->sigma[a] * m->sigma[a]) * dt * inv_ln2;
     asset[a] = (float)(n_steps * mu);
     asset[256 + a] = (float)(w * m->S0[a]);
     asset[512 + a] = (float)(w * std::log(2.0));
+    asset[768 + a] = (float)m->S0[a];
     geo0 += w * std::log(m->S0[a]);
   }
   const RunLayout Lay = layout_for(n_paths, 3, o0.path_values != nullptr);
@@ -910,9 +917,15 @@ mc_status basket_price(mc_context* ctx, const mc_model* m, const mc_payoff* f, u
   p.K = f->K;
   p.geo0 = geo0;
   p.w0 = f->weights ? f->weights[0] : 1.0 / d;
+  p.n_strikes = port ? port->n_strikes : 0u;
+  for (uint32_t k = 0; k < p.n_strikes; ++k) {
+    p.pm[k] = (float)port->strike_mult[k];
+    p.pq[k] = (float)port->quantity[k];
+  }
+  p.premium = premium;
   Moments mom;
   double kms = 0.0;
-  st = run_moments(ctx, o, n_paths, 3, o0.path_values,
+  st = run_moments(ctx, o, n_paths, port ? 1 : 3, o0.path_values,
                    [&](double* partials, double* path_out, hipStream_t ss, uint32_t* nb) {
                      p.partials = partials;
                      p.path_out = path_out;
@@ -925,7 +938,7 @@ mc_status basket_price(mc_context* ctx, const mc_model* m, const mc_payoff* f, u
   fill_channel(mom, 0, &r.price, &r.variance, &r.std_err);
   r.plain_price = r.price;
   r.plain_std_err = r.std_err;
-  if (o0.greeks & MC_GREEK_DELTA) fill_channel(mom, 2, &r.delta, &v, &r.delta_se);
+  if (!port && (o0.greeks & MC_GREEK_DELTA)) fill_channel(mom, 2, &r.delta, &v, &r.delta_se);
   r.vrf = 1.0;
   r.n_paths = (uint64_t)mom.n;
   r.n_nonfinite = (uint64_t)mom.nonfinite;
@@ -1354,6 +1367,107 @@ mc_status mc_mlmc_allocate(uint32_t n_levels, const double* var, const double* c
     tmp[l] = n < 2.0 ? 2u : (uint64_t)n;
   }
   for (uint32_t l = 0; l < n_levels; ++l) n_paths_out[l] = tmp[l];
+  return MC_OK;
+}
+
+// ------------------------------------------------------- Portfolio risk ----
+mc_status mc_risk(mc_context* ctx, const mc_model* m, const mc_portfolio* pf, uint64_t n_paths,
+                  uint32_t n_steps, uint64_t seed, const mc_options* opts, mc_risk_result* out) {
+  if (!ctx) return MC_ERR_INVALID_ARG;
+  if (!m || !pf || !out) return fail(ctx, MC_ERR_INVALID_ARG, "NULL argument");
+  const mc_options o0 = opts ? *opts : defaults();
+  if (m->kind != MC_GBM_BASKET)
+    return fail(ctx, MC_ERR_UNSUPPORTED, "portfolio risk runs on the basket model");
+  if (pf->n_strikes < 1 || pf->n_strikes > MC_MAX_STRIKES)
+    return fail(ctx, MC_ERR_INVALID_ARG, "n_strikes must be in 1..%d", MC_MAX_STRIKES);
+  for (uint32_t k = 0; k < pf->n_strikes; ++k) {
+    if (!finite_nonneg(pf->strike_mult[k]))
+      return fail(ctx, MC_ERR_INVALID_ARG, "strike_mult[%u] invalid", k);
+    if (!std::isfinite(pf->quantity[k]))
+      return fail(ctx, MC_ERR_INVALID_ARG, "quantity[%u] not finite", k);
+  }
+  if (!(pf->alpha > 0.0 && pf->alpha < 1.0))
+    return fail(ctx, MC_ERR_INVALID_ARG, "alpha must lie in (0, 1)");
+  if (o0.greeks) return fail(ctx, MC_ERR_UNSUPPORTED, "portfolio risk carries no greeks");
+  if (o0.prec != MC_FP32 && o0.prec != MC_BF16_GEMM && o0.prec != MC_FP16_GEMM)
+    return fail(ctx, MC_ERR_UNSUPPORTED, "portfolio risk runs in MC_FP32, MC_BF16_GEMM, MC_FP16_GEMM");
+  mc_payoff f{};
+  f.kind = MC_BASKET_CALL;
+  f.K = 0.0;
+  f.B = NAN;
+  f.cv = MC_CV_NONE;
+  mc_options ov = o0;
+  ov.path_values = nullptr;
+  mc_status st = validate_all(ctx, m, &f, n_paths, n_steps, ov);
+  if (st != MC_OK) return st;
+  if (pf->mu)
+    for (uint32_t a = 0; a < m->dim; ++a)
+      if (!std::isfinite(pf->mu[a])) return fail(ctx, MC_ERR_INVALID_ARG, "mu[%u] not finite", a);
+  const double kr = std::floor((double)n_paths * (1.0 - pf->alpha)) + 1.0;
+  const uint64_t k = (uint64_t)kr;
+  if (k < 2 || k > n_paths)
+    return fail(ctx, MC_ERR_INVALID_ARG, "n_paths (1 - alpha) must be at least 1");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, MC_ERR_DEVICE, "hipSetDevice");
+  double V0 = 0.0;
+  for (uint32_t a = 0; a < m->dim; ++a)
+    for (uint32_t j = 0; j < pf->n_strikes; ++j)
+      V0 += pf->quantity[j] *
+            host::bs_call(m->S0[a], pf->strike_mult[j] * m->S0[a], m->r, m->sigma[a], m->T);
+  // Device scratch: per-path P&L, selection state and histogram, tail partials.
+  const size_t bytes_x = align256((size_t)n_paths * sizeof(double));
+  const size_t bytes_st = align256(kSelectStateBytes);
+  const size_t bytes_h = align256(256 * sizeof(uint32_t));
+  const size_t bytes_p = align256((size_t)2 * 1024 * sizeof(double));
+  char* base = nullptr;
+  st = get_mlmc_buf(ctx, bytes_x + bytes_st + bytes_h + bytes_p + align256(2 * sizeof(double)),
+                    &base);
+  if (st != MC_OK) return st;
+  double* x = (double*)base;
+  void* state = base + bytes_x;
+  uint32_t* hist = (uint32_t*)(base + bytes_x + bytes_st);
+  double* partials = (double*)(base + bytes_x + bytes_st + bytes_h);
+  double* tail = (double*)(base + bytes_x + bytes_st + bytes_h + bytes_p);
+  mc_result pr{};
+  {
+    SinkGuard guard{ctx};
+    ctx->sink = x;
+    st = basket_price(ctx, m, &f, n_paths, n_steps, seed, ov, &pr, pf, V0);
+    if (st != MC_OK) return st;
+  }
+  if (pr.n_nonfinite != 0) return fail(ctx, MC_ERR_DEVICE, "non-finite P&L on %llu paths",
+                                       (unsigned long long)pr.n_nonfinite);
+  hipStream_t s = stream_of(ctx, o0);
+  st = get_pinned(ctx, 4);
+  if (st != MC_OK) return st;
+  uint32_t nb = 0;
+  HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
+  HIP_TRY(ctx, launch_select_kth(x, n_paths, k, state, hist, s));
+  HIP_TRY(ctx, launch_tail_sum(x, n_paths, state, partials, s, &nb));
+  HIP_TRY(ctx, launch_final_reduce(partials, nb, 2, tail, s));
+  HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, state, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned + 1, tail, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (o0.path_values)
+    HIP_TRY(ctx, hipMemcpyAsync(o0.path_values, x, n_paths * sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  float ms = 0.f;
+  HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  uint64_t key;
+  std::memcpy(&key, ctx->pinned, sizeof(key));
+  mc_risk_result r{};
+  r.quantile_pnl = select_key_to_value(key);
+  r.var = -r.quantile_pnl;
+  r.n_tail = (uint64_t)ctx->pinned[1];
+  r.cvar = r.n_tail ? -ctx->pinned[2] / ctx->pinned[1] : NAN;
+  r.pnl_mean = pr.price;
+  r.pnl_std_err = pr.std_err;
+  r.premium = V0;
+  r.k = k;
+  r.n_paths = pr.n_paths;
+  r.kernel_ms = pr.kernel_ms;
+  r.select_ms = ms;
+  *out = r;
   return MC_OK;
 }
 

@@ -15,6 +15,14 @@ inline double lognormal_call(double m, double s2, double K, double disc) {
   return disc * (std::exp(m + 0.5 * s2) * norm_cdf(d2 + s) - K * norm_cdf(d2));
 }
 
+// Black-Scholes call (no dividends): S N(d1) - K e^{-rT} N(d2); K = 0 gives S.
+inline double bs_call(double S, double K, double r, double sigma, double T) {
+  if (K <= 0.0) return S;
+  const double st = sigma * std::sqrt(T);
+  const double d1 = (std::log(S / K) + (r + 0.5 * sigma * sigma) * T) / st;
+  return S * norm_cdf(d1) - K * std::exp(-r * T) * norm_cdf(d1 - st);
+}
+
 // Geometric average of S at t_i = i T/n, i = 1..n, under GBM: ln G is normal
 // with mean ln S0 + (r - sigma^2/2) T (n+1)/(2n) and variance
 // sigma^2 T (n+1)(2n+1)/(6 n^2). The mean of the geometric-Asian control

@@ -71,7 +71,7 @@ __device__ __forceinline__ void mfma_block(f32x16& acc, const float (&z)[8],
   }
 }
 
-template <int ND, int PREC>
+template <int ND, int PREC, bool PORT>
 __global__ __launch_bounds__(kThreads) void basket_kernel(const BasketParams P) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   constexpr int NBLK = ND * (ND + 1);                 // packed triangular blocks
@@ -134,13 +134,25 @@ __global__ __launch_bounds__(kThreads) void basket_kernel(const BasketParams P) 
   for (int nb = 0; nb < ND; ++nb) {
     const int a = 32 * nb + row;
     const float nmu = P.asset[a], ca = P.asset[256 + a], ga = P.asset[512 + a];
+    const float s0 = P.asset[768 + a];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const float x = acc[nb][r] + nmu;                 // log2(S_a / S0_a)
       const float E = __builtin_amdgcn_exp2f(x);
-      bsum[r] += ca * E;
-      gsum[r] += ga * x;
-      if (nb == 0) e0[r] = E;
+      if constexpr (PORT) {
+        // Portfolio value of asset a: S0_a sum_k q_k (E - m_k)^+ (zero-padded
+        // assets carry S0 = 0).
+        float v = 0.f;
+        for (uint32_t k = 0; k < P.n_strikes; ++k) {
+          const float itm = E - P.pm[k];
+          v = __builtin_fmaf(P.pq[k], itm > 0.f ? itm : 0.f, v);
+        }
+        bsum[r] = __builtin_fmaf(s0, v, bsum[r]);
+      } else {
+        bsum[r] += ca * E;
+        gsum[r] += ga * x;
+        if (nb == 0) e0[r] = E;
+      }
     }
   }
 #pragma unroll
@@ -148,9 +160,9 @@ __global__ __launch_bounds__(kThreads) void basket_kernel(const BasketParams P) 
 #pragma unroll
     for (int off = 16; off > 0; off >>= 1) {
       bsum[r] += __shfl_xor(bsum[r], off, 64);
-      gsum[r] += __shfl_xor(gsum[r], off, 64);
+      if constexpr (!PORT) gsum[r] += __shfl_xor(gsum[r], off, 64);
     }
-    e0[r] = __shfl(e0[r], lane & 32, 64);               // asset 0 sits in column 0
+    if constexpr (!PORT) e0[r] = __shfl(e0[r], lane & 32, 64);   // asset 0 sits in column 0
   }
   // Lane (half, row < 16) reports path row 8 (row/4) + 4 half + row mod 4.
   float B = 0.f, G = 0.f, E0 = 0.f;
@@ -165,33 +177,48 @@ __global__ __launch_bounds__(kThreads) void basket_kernel(const BasketParams P) 
   const int prow = 8 * (row >> 2) + 4 * half + (row & 3);
   const uint64_t pid = tile * 32 + prow;
   const bool active = row < 16 && pid < P.n_paths;
-  double y[3] = {0.0, 0.0, 0.0};
-  if (active) {
-    const double disc = P.disc, K = P.K;
-    const double basket = (double)B;
-    const double geo = exp(P.geo0 + (double)G);
-    y[0] = disc * (basket > K ? basket - K : 0.0);
-    y[1] = disc * (geo > K ? geo - K : 0.0);
-    y[2] = basket > K ? disc * P.w0 * (double)E0 : 0.0;
-  }
-  bool finite = isfinite(y[0]) && isfinite(y[1]) && isfinite(y[2]);
-  if (active && P.path_out != nullptr) {
+  if constexpr (PORT) {
+    double y[1] = {0.0};
+    if (active) y[0] = (double)B - P.premium;
+    const bool finite = isfinite(y[0]);
+    if (active && P.path_out != nullptr) P.path_out[pid] = y[0];
+    block_moments<1, kThreads>(y, active && finite, active && !finite, P.partials, gridDim.x);
+  } else {
+    double y[3] = {0.0, 0.0, 0.0};
+    if (active) {
+      const double disc = P.disc, K = P.K;
+      const double basket = (double)B;
+      const double geo = exp(P.geo0 + (double)G);
+      y[0] = disc * (basket > K ? basket - K : 0.0);
+      y[1] = disc * (geo > K ? geo - K : 0.0);
+      y[2] = basket > K ? disc * P.w0 * (double)E0 : 0.0;
+    }
+    bool finite = isfinite(y[0]) && isfinite(y[1]) && isfinite(y[2]);
+    if (active && P.path_out != nullptr) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) P.path_out[pid * 3 + c] = y[c];
+      for (int c = 0; c < 3; ++c) P.path_out[pid * 3 + c] = y[c];
+    }
+    block_moments<3, kThreads>(y, active && finite, active && !finite, P.partials, gridDim.x);
   }
-  block_moments<3, kThreads>(y, active && finite, active && !finite, P.partials, gridDim.x);
+}
+
+template <int ND, int PREC, bool PORT>
+hipError_t launch_nd_mode(const BasketParams& p, hipStream_t s, uint32_t nb) {
+  constexpr int NBLK = ND * (ND + 1);
+  constexpr int ELT = sizeof(typename BElt<PREC>::T);
+  const size_t lds = (size_t)NBLK * 512 * ELT * (PREC == BK_BF16X2 ? 2 : 1);
+  hipError_t e = hipFuncSetAttribute((const void*)basket_kernel<ND, PREC, PORT>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((basket_kernel<ND, PREC, PORT>), dim3(nb), dim3(kThreads), lds, s, p);
+  return hipGetLastError();
 }
 
 template <int ND, int PREC>
 hipError_t launch_nd(const BasketParams& p, hipStream_t s, uint32_t nb) {
-  constexpr int NBLK = ND * (ND + 1);
-  constexpr int ELT = sizeof(typename BElt<PREC>::T);
-  const size_t lds = (size_t)NBLK * 512 * ELT * (PREC == BK_BF16X2 ? 2 : 1);
-  hipError_t e = hipFuncSetAttribute((const void*)basket_kernel<ND, PREC>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((basket_kernel<ND, PREC>), dim3(nb), dim3(kThreads), lds, s, p);
-  return hipGetLastError();
+  if (p.n_strikes == 0) return launch_nd_mode<ND, PREC, false>(p, s, nb);
+  if constexpr (PREC == BK_BF16X2) return hipErrorInvalidValue;   // portfolio: one-term L'
+  else return launch_nd_mode<ND, PREC, true>(p, s, nb);
 }
 
 template <int PREC>

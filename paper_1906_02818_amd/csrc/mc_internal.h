@@ -101,14 +101,35 @@ struct BasketParams {
   uint32_t d;             // assets, multiple of 16, <= 256
   const void* Lblk;       // packed lower-triangular 32x16 blocks of L' (device)
   const void* Lblk_lo;    // BF16X2: the lo term, same layout
-  const float* asset;     // device [3][256]: n*mu_a (log2), w_a*S0_a, w_a*ln 2
+  const float* asset;     // device [4][256]: n*mu_a (log2), w_a*S0_a, w_a*ln 2, S0_a
   double disc, K, geo0, w0;
+  // Call portfolio (risk mode): q_k calls of strike m_k S0_a on every asset;
+  // the per-path value is sum_a S0_a sum_k q_k (S_a/S0_a - m_k)^+ - premium.
+  uint32_t n_strikes;     // 0: basket-call mode
+  float pm[8], pq[8];
+  double premium;
   double* partials;
-  double* path_out;       // [n_paths][3] or nullptr
+  double* path_out;       // [n_paths][3] (basket) or [n_paths] (portfolio), or nullptr
 };
+constexpr int kMaxStrikes = 8;
 // Number of 32-wide asset blocks the kernel is instantiated for (1, 2, 4, 8).
 uint32_t basket_blocks_nd(uint32_t d);
 hipError_t launch_basket(const BasketParams& p, int prec, hipStream_t s, uint32_t* n_blocks);
+
+// ---- Order statistic and tail mean of per-path values (risk metrics) ----
+// Exact k-th smallest (1-based) of x[0..n) by an 8-pass radix select on the
+// order-preserving 64-bit keys of the doubles, then the count and sum of the
+// values strictly below it. `state` and `hist` are small device scratch
+// areas (kSelectStateBytes, 256 uint32); partials holds kDiffMaxBlocks x 2
+// doubles. Everything is enqueued on s without host synchronisation.
+constexpr size_t kSelectStateBytes = 64;
+hipError_t launch_select_kth(const double* x, uint64_t n, uint64_t k, void* state, uint32_t* hist,
+                             hipStream_t s);
+hipError_t launch_tail_sum(const double* x, uint64_t n, const void* state, double* partials,
+                           hipStream_t s, uint32_t* n_blocks);
+// Host view of the selection state after the passes: the key of the k-th
+// smallest value and the value itself.
+double select_key_to_value(uint64_t key);
 
 // ---- Learned martingale control variate (Heston Asian) ----
 // Hedge network 4 -> 64 -> 64 -> 1 with tanh, run on MFMA for 32 paths per
