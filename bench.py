@@ -363,6 +363,47 @@ def run_mlmc_basket(args, ctx, mc, synth, torch):
                               "speedup": plain["total_s"] / mlmc["total_s"]})
 
 
+RISK_STRIKES = [0.9, 0.95, 1.0, 1.05, 1.1]
+RISK_QTY = [1.0, -2.0, 1.5, -1.0, 0.5]
+
+
+def run_risk(args, ctx, mc, synth, torch):
+    """VaR_0.95 and CVaR_0.95 of a portfolio of 5 calls on each of the
+    basket's 256 assets (1280 instruments) over a one-year horizon in 100
+    steps, 2^20 scenarios under real-world drifts; the matrix-product
+    precision of --prec, with the FP32 values beside it for the bias."""
+    c = synth.BASKET
+    N, n, d = c["n_paths"], c["n_steps"], c["d"]
+    sigma, corr, _ = synth.basket_market(d)
+    S0 = [c["S0"]] * d
+    mu = [0.02 + 0.08 * a / (d - 1) for a in range(d)]
+    model = mc.Model(kind=mc.MC_GBM_BASKET, S0=S0, r=c["r"], T=c["T"], sigma=sigma, corr=corr)
+    prec = {"fp32": mc.MC_FP32, "bf16": mc.MC_BF16_GEMM, "fp16": mc.MC_FP16_GEMM}.get(
+        args.prec, mc.MC_BF16_GEMM)
+
+    def go(p):
+        return mc.mc_risk(ctx, model, RISK_STRIKES, RISK_QTY, 0.95, N, n, synth.SEED, mu=mu,
+                          opts=mc.Options(prec=p))
+    ms, outs = _repeat(args, torch, lambda: go(prec))
+    r = outs[-1]
+    ref = go(mc.MC_FP32)
+    k_ms = sum(x["kernel_ms"] for x in outs) / len(outs)
+    s_ms = sum(x["select_ms"] for x in outs) / len(outs)
+    roof = _alu_roofline(SLOTS_ASSET_STEP, N * n * d, k_ms, f"basket_kernel<8, {args.prec}, port>")
+    return _line(args, "scenario-asset-steps/s", N * n * d / (ms * 1e-3), "asset-path-steps/s",
+                 ms, args.prec,
+                 {"workload": f"VaR/CVaR 0.95 of 5 calls on each of {d} correlated GBM assets "
+                              f"({5 * d} instruments), 1-year horizon in {n} steps, 2^20 "
+                              f"scenarios, real-world drifts", "n_paths": N, "n_steps": n,
+                  "d": d},
+                 roof, kernel_ms=k_ms, select_ms=s_ms,
+                 risk={"var": r["var"], "cvar": r["cvar"], "pnl_mean": r["pnl_mean"],
+                       "premium": r["premium"], "var_fp32": ref["var"],
+                       "cvar_fp32": ref["cvar"],
+                       "var_rel_diff": r["var"] / ref["var"] - 1.0,
+                       "cvar_rel_diff": r["cvar"] / ref["cvar"] - 1.0})
+
+
 def run_heston_adjoint(args, ctx, mc, synth, torch):
     H = synth.HESTON
     N, n = H["n_paths"], H["n_steps"]
@@ -400,7 +441,7 @@ def run_learned_cv(args, ctx, mc, synth, torch):
 
 WORKLOADS = {"asian_barrier": run_asian_barrier, "european": run_european, "basket": run_basket,
              "heston_adjoint": run_heston_adjoint, "learned_cv": run_learned_cv,
-             "mlmc_basket": run_mlmc_basket}
+             "mlmc_basket": run_mlmc_basket, "risk": run_risk}
 
 
 def main():
