@@ -66,6 +66,16 @@ def lib():
         L.orc_portfolio_pnl.argtypes = [C.c_int, _dp, _dp, _dp, _dp, C.c_int, _dp, _dp,
                                         C.c_double, C.c_double, C.c_int, C.c_uint64,
                                         C.c_uint32, C.c_uint64, C.c_uint64, _dp]
+        L.orc_sobol_polys.argtypes = [C.c_int, np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS"),
+                                      _u32p]
+        L.orc_sobol_polys.restype = C.c_int
+        L.orc_sobol_dirs.argtypes = [C.c_int, _u32p]
+        L.orc_sobol_word.argtypes = [_u32p, C.c_int, C.c_uint64]
+        L.orc_sobol_word.restype = C.c_uint32
+        L.orc_qmc_shifts.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_int, _u32p]
+        L.orc_basket_qmc.argtypes = [C.c_int, _dp, _dp, _dp, _dp, C.c_double, C.c_double,
+                                     C.c_double, C.c_int, C.c_uint64, C.c_uint32, C.c_uint64,
+                                     C.c_uint64, C.c_uint64, _dp]
         L.orc_heston_cv.argtypes = [_dp, C.c_int, C.c_int, _dp, C.c_uint64,
                                     C.c_uint32, C.c_uint64, C.c_uint64, _dp]
         L.orc_mlp_eval.argtypes = [_dp, C.c_uint64, _dp, _dp]
@@ -188,6 +198,48 @@ def var_cvar(pnl, alpha):
     tail = x[x < x[k - 1]]
     cvar = -tail.mean() if tail.size else float("nan")
     return var, cvar, k, tail.size
+
+
+def sobol_polys(n):
+    """First n primitive polynomials over GF(2) (degree, bit pattern)."""
+    deg = np.zeros(n, np.int32)
+    poly = np.zeros(n, np.uint32)
+    k = lib().orc_sobol_polys(n, deg, poly)
+    return deg[:k], poly[:k]
+
+
+def sobol_dirs(n_dims) -> np.ndarray:
+    """Direction words V[dim, bit] of the Sobol' construction (section 11)."""
+    V = np.zeros((n_dims, 32), np.uint32)
+    lib().orc_sobol_dirs(n_dims, V.reshape(-1))
+    return V
+
+
+def sobol_points(V, n_points, point0=0) -> np.ndarray:
+    """Unshifted 32-bit coordinates [n_points, n_dims]."""
+    n_dims = V.shape[0]
+    Vf = np.ascontiguousarray(V.reshape(-1))
+    out = np.zeros((n_points, n_dims), np.uint32)
+    for i in range(n_points):
+        for j in range(n_dims):
+            out[i, j] = lib().orc_sobol_word(Vf, j, point0 + i)
+    return out
+
+
+def qmc_shifts(seed, tag, replicate, n_dims) -> np.ndarray:
+    sh = np.zeros(n_dims, np.uint32)
+    lib().orc_qmc_shifts(seed, tag, replicate, n_dims, sh)
+    return sh
+
+
+def basket_qmc(S0, sigma, L, w, r, T, K, n_steps, n_paths, seed, replicate, tag=6,
+               path0=0) -> np.ndarray:
+    """Basket channels on Sobol' points with the digital shift of `replicate`."""
+    S0, sigma, L, w = _c(S0), _c(sigma), _c(L), _c(w)
+    out = np.zeros((n_paths, len(BASKET_CHANNELS)), np.float64)
+    lib().orc_basket_qmc(S0.size, S0, sigma, L, w, r, T, K, n_steps, seed, tag, replicate,
+                         path0, n_paths, out)
+    return out
 
 
 def _c(a) -> np.ndarray:

@@ -138,12 +138,19 @@ typedef struct {
     uint64_t next_k;
     uint64_t block;
     double z[4];
+    /* Sobol' source (section 11): when V is set, block j's words are the
+     * shifted Sobol' coordinates 4j .. 4j+3 of point `path`. */
+    const uint32_t *V, *shift;
 } normal_stream;
+
+uint32_t orc_sobol_word(const uint32_t *V, int dim, uint64_t point);
 
 static void ns_init(normal_stream *s, uint64_t seed, uint32_t tag, uint64_t path)
 {
     s->seed = seed; s->tag = tag; s->path = path; s->next_k = 0;
     s->block = UINT64_MAX;
+    s->V = NULL;
+    s->shift = NULL;
 }
 
 static double ns_next(normal_stream *s)
@@ -152,7 +159,12 @@ static double ns_next(normal_stream *s)
     uint64_t j = k / 4;
     if (j != s->block) {
         uint32_t w[4];
-        orc_block_words(s->seed, s->tag, s->path, j, w);
+        if (s->V) {
+            for (int t = 0; t < 4; ++t)
+                w[t] = orc_sobol_word(s->V, (int)(4 * j) + t, s->path) ^ s->shift[4 * j + t];
+        } else {
+            orc_block_words(s->seed, s->tag, s->path, j, w);
+        }
         box_muller_block(w, s->z);
         s->block = j;
     }
@@ -386,10 +398,24 @@ int orc_cholesky(int d, const double *C, double *L)
 
 int orc_basket_channels(void) { return BSK_CH; }
 
+static void basket_paths(int d, const double *S0, const double *sigma, const double *L,
+                         const double *w, double r, double T, double K, int n_steps,
+                         uint64_t seed, uint32_t tag, uint64_t path0, uint64_t n_paths,
+                         const uint32_t *V, const uint32_t *shift, double *out);
+
 void orc_basket(int d, const double *S0, const double *sigma, const double *L,
                 const double *w, double r, double T, double K, int n_steps,
                 uint64_t seed, uint32_t tag, uint64_t path0, uint64_t n_paths,
                 double *out)
+{
+    basket_paths(d, S0, sigma, L, w, r, T, K, n_steps, seed, tag, path0, n_paths,
+                 NULL, NULL, out);
+}
+
+static void basket_paths(int d, const double *S0, const double *sigma, const double *L,
+                         const double *w, double r, double T, double K, int n_steps,
+                         uint64_t seed, uint32_t tag, uint64_t path0, uint64_t n_paths,
+                         const uint32_t *V, const uint32_t *shift, double *out)
 {
     const double dt = T / n_steps, sdt = sqrt(dt), disc = exp(-r * T);
 #pragma omp parallel
@@ -400,6 +426,8 @@ void orc_basket(int d, const double *S0, const double *sigma, const double *L,
         for (long long p = 0; p < (long long)n_paths; ++p) {
             normal_stream ns;
             ns_init(&ns, seed, tag, path0 + (uint64_t)p);
+            ns.V = V;
+            ns.shift = shift;
             for (int a = 0; a < d; ++a) x[a] = log(S0[a]);
             for (int i = 0; i < n_steps; ++i) {
                 for (int a = 0; a < d; ++a) Z[a] = ns_next(&ns);
@@ -683,4 +711,150 @@ double orc_cv_loss_grad(const double *prm, int n_steps, int m_every,
     }
     free(Y);
     return loss;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 11. Sobol' low-discrepancy points with a random digital shift (the        */
+/*    quasi-random generator of Sec. IV-B and the Sobol' experiment of       */
+/*    Sec. VI-D), written from Sobol's construction:                         */
+/*    - dimension 0: the van der Corput sequence (direction integers         */
+/*      m_i = 1);                                                            */
+/*    - dimension j >= 1: the j-th primitive polynomial over GF(2),          */
+/*      p = x^s + a_1 x^(s-1) + ... + a_(s-1) x + 1, taken in order of       */
+/*      degree and then of its bit pattern, with initial direction integers  */
+/*      m_i = 2 (h mod 2^(i-1)) + 1 for i = 1..s, h = SplitMix64(64 j + i)   */
+/*      (odd and below 2^i, as the construction requires; the Joe-Kuo       */
+/*      table is not available), and for i > s                              */
+/*        m_i = m_(i-s) xor 2^s m_(i-s) xor sum_k a_k 2^k m_(i-k)             */
+/*    - direction word of bit b of the point index: V_b = m_(b+1) 2^(31-b);  */
+/*    - coordinate of point p in dimension j: the xor of V_b over the set    */
+/*      bits b of p, a 32-bit fraction.                                      */
+/*    Randomisation: word j of a point is xored with shift_j, word (j mod 4) */
+/*    of Philox block (floor(j/4), replicate, tag) -- a random digital shift */
+/*    per replicate; the shifted words then go through the same uniform and  */
+/*    Box-Muller map as Philox words (normal k uses dimension k).            */
+/* ------------------------------------------------------------------------ */
+static uint64_t smix64(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* a * b mod p in GF(2)[x], deg p = s, deg a, b < s. */
+static uint32_t gf2_mulmod(uint32_t a, uint32_t b, uint32_t p, int s)
+{
+    uint32_t r = 0;
+    while (b) {
+        if (b & 1u) r ^= a;
+        b >>= 1;
+        a <<= 1;
+        if (a & (1u << s)) a ^= p;
+    }
+    return r;
+}
+
+static uint32_t gf2_powx(uint64_t e, uint32_t p, int s)
+{
+    uint32_t result = 1u, base = (s == 1) ? (2u ^ p) : 2u;   /* x mod p */
+    while (e) {
+        if (e & 1u) result = gf2_mulmod(result, base, p, s);
+        base = gf2_mulmod(base, base, p, s);
+        e >>= 1;
+    }
+    return result;
+}
+
+/* p (degree s, constant term 1) is primitive when x has order 2^s - 1. */
+static int gf2_primitive(uint32_t p, int s)
+{
+    const uint64_t order = (1ull << s) - 1;
+    if (gf2_powx(order, p, s) != 1u) return 0;
+    uint64_t n = order;
+    for (uint64_t q = 2; q * q <= n; ++q) {
+        if (n % q) continue;
+        while (n % q == 0) n /= q;
+        if (gf2_powx(order / q, p, s) == 1u) return 0;
+    }
+    if (n > 1 && gf2_powx(order / n, p, s) == 1u) return 0;
+    return 1;
+}
+
+/* First n primitive polynomials (bit patterns including x^s and 1) and their
+ * degrees. Returns n, or the number found up to degree 24. */
+int orc_sobol_polys(int n, int *deg, uint32_t *poly)
+{
+    int found = 0;
+    for (int s = 1; s <= 24 && found < n; ++s)
+        for (uint32_t c = (1u << s) | 1u; c < (2u << s) && found < n; c += 2)
+            if (gf2_primitive(c, s)) {
+                deg[found] = s;
+                poly[found] = c;
+                ++found;
+            }
+    return found;
+}
+
+void orc_sobol_dirs(int n_dims, uint32_t *V)
+{
+    int *deg = (int *)malloc(sizeof(int) * (size_t)(n_dims > 1 ? n_dims : 1));
+    uint32_t *poly = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n_dims > 1 ? n_dims : 1));
+    if (n_dims > 1) orc_sobol_polys(n_dims - 1, deg, poly);
+    for (int j = 0; j < n_dims; ++j) {
+        uint64_t m[33];
+        if (j == 0) {
+            for (int i = 1; i <= 32; ++i) m[i] = 1;
+        } else {
+            const int s = deg[j - 1];
+            const uint32_t p = poly[j - 1];
+            for (int i = 1; i <= s && i <= 32; ++i) {
+                const uint64_t h = smix64(64ull * (uint64_t)j + (uint64_t)i);
+                m[i] = 2 * (h % (1ull << (i - 1))) + 1;
+            }
+            for (int i = s + 1; i <= 32; ++i) {
+                uint64_t v = m[i - s] ^ (m[i - s] << s);
+                for (int k = 1; k < s; ++k)
+                    if ((p >> (s - k)) & 1u) v ^= m[i - k] << k;
+                m[i] = v;
+            }
+        }
+        for (int b = 0; b < 32; ++b) V[(size_t)j * 32 + b] = (uint32_t)(m[b + 1] << (31 - b));
+    }
+    free(deg);
+    free(poly);
+}
+
+uint32_t orc_sobol_word(const uint32_t *V, int dim, uint64_t point)
+{
+    uint32_t x = 0;
+    for (int b = 0; b < 32; ++b)
+        if ((point >> b) & 1u) x ^= V[(size_t)dim * 32 + b];
+    return x;
+}
+
+void orc_qmc_shifts(uint64_t seed, uint32_t tag, uint64_t replicate, int n_dims,
+                    uint32_t *shift)
+{
+    for (int j = 0; j < n_dims; j += 4) {
+        uint32_t w[4];
+        orc_block_words(seed, tag, replicate, (uint64_t)(j / 4), w);
+        for (int t = 0; t < 4 && j + t < n_dims; ++t) shift[j + t] = w[t];
+    }
+}
+
+/* The basket of section 8 on shifted Sobol' points: point index = path. */
+void orc_basket_qmc(int d, const double *S0, const double *sigma, const double *L,
+                    const double *w, double r, double T, double K, int n_steps,
+                    uint64_t seed, uint32_t tag, uint64_t replicate, uint64_t path0,
+                    uint64_t n_paths, double *out)
+{
+    const int n_dims = ((n_steps * d + 3) / 4) * 4;
+    uint32_t *V = (uint32_t *)malloc(sizeof(uint32_t) * 32 * (size_t)n_dims);
+    uint32_t *sh = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n_dims);
+    orc_sobol_dirs(n_dims, V);
+    orc_qmc_shifts(seed, tag, replicate, n_dims, sh);
+    basket_paths(d, S0, sigma, L, w, r, T, K, n_steps, seed, tag, path0, n_paths, V, sh, out);
+    free(V);
+    free(sh);
 }
