@@ -21,7 +21,8 @@
  *   driver; basket d = number of assets). Tags: 0 main run, 1 pilot run,
  *   2 learned-hedge training set, tag + 16 l level l of a multilevel
  *   estimate; tag + 5 carries the Brownian-bridge uniforms of the
- *   continuously monitored barrier.
+ *   continuously monitored barrier, tag + 6 the digital shifts of the
+ *   randomised quasi-Monte Carlo replicates.
  *
  * Conventions for every entry point:
  *   - Returns an mc_status; no exception or signal crosses the ABI.
@@ -350,6 +351,42 @@ typedef struct {
 mc_status mc_risk(mc_context *ctx, const mc_model *model, const mc_portfolio *portfolio,
                   uint64_t n_paths, uint32_t n_steps, uint64_t seed, const mc_options *opts,
                   mc_risk_result *out);
+
+/* Randomised quasi-Monte Carlo for the basket (quasi-random numbers of
+ * Sec. IV-B; the Sobol' experiment of Sec. VI-D). Path p is Sobol' point p
+ * (path_offset + i, below 2^32) in n_steps * dim dimensions; normal k uses
+ * dimension k. Sobol' construction: dimension 0 van der Corput; dimension
+ * j >= 1 the j-th primitive polynomial over GF(2) (by degree, then bit
+ * pattern) with initial direction integers m_i = 2 (h mod 2^(i-1)) + 1,
+ * h = SplitMix64(64 j + i), then the Bratley-Fox recursion; direction word
+ * of bit b: m_(b+1) << (31 - b). Replicate r xors dimension j's word with
+ * word (j mod 4) of the Philox block (floor(j/4), r, stream_tag + 6) (a
+ * random digital shift); the shifted words pass through the same uniform
+ * and Box-Muller maps as Philox words. Each replicate's estimate is the
+ * mean over its n_points paths; price and std_err are the mean of the
+ * n_replicates estimates and their standard deviation / sqrt(n_replicates)
+ * (NaN for one replicate). Model MC_GBM_BASKET, payoff MC_BASKET_CALL,
+ * prec MC_FP32 / MC_BF16_GEMM / MC_FP16_GEMM, greeks 0; path_values (host
+ * [n_points][3], the channels of mc_price) only with one replicate.
+ * Errors: n_replicates outside 1..MC_QMC_MAX_REPLICATES, point indices
+ * reaching 2^32, or n_steps * dim above 2^16 dimensions ->
+ * MC_ERR_INVALID_ARG; otherwise the errors of mc_price. */
+#define MC_QMC_MAX_REPLICATES 64
+typedef struct {
+    double price;              /* basket call: mean of the replicate estimates */
+    double std_err;
+    double geo_price;          /* geometric basket call on the same points */
+    double geo_std_err;
+    uint32_t n_replicates;
+    uint64_t n_points;
+    double replicate_price[MC_QMC_MAX_REPLICATES];
+    double replicate_geo[MC_QMC_MAX_REPLICATES];
+    double kernel_ms;          /* path kernels of all replicates */
+} mc_qmc_result;
+
+mc_status mc_price_qmc(mc_context *ctx, const mc_model *model, const mc_payoff *payoff,
+                       uint64_t n_points, uint32_t n_steps, uint64_t seed,
+                       uint32_t n_replicates, const mc_options *opts, mc_qmc_result *out);
 
 /* Raw Philox4x32-10 blocks of sampled (path, block) pairs and the normals
  * of one path, computed by the same device functions the path kernels use

@@ -23,14 +23,15 @@ from ._abi import (MC_ADJ_FULL, MC_ADJ_FWD, MC_ADJ_REV, MC_ASIAN_ARITH_CALL, MC_
                    MC_ERR_NOT_PD, MC_ERR_OOM, MC_ERR_UNSUPPORTED, MC_ERR_WORKSPACE, MC_EULER_S,
                    MC_EURO_CALL, MC_FP16_GEMM, MC_FP32, MC_FP64, MC_GBM, MC_GBM_BASKET,
                    MC_GREEK_DELTA, MC_GREEK_VEGA, MC_HESTON, MC_LOG_EULER, MC_MLMC_MAX_LEVELS,
-                   MC_MAX_STRIKES, MC_MLP_NPARAM, MC_OK, MC_UO_BARRIER_CALL, MC_UO_BRIDGE_CALL)
+                   MC_MAX_STRIKES, MC_MLP_NPARAM, MC_OK, MC_QMC_MAX_REPLICATES,
+                   MC_UO_BARRIER_CALL, MC_UO_BRIDGE_CALL)
 
 __all__ = [n for n in dir(_abi) if n.startswith("MC_")] + [
     "McError", "Model", "Payoff", "Options", "mc_create", "mc_destroy", "mc_validate",
     "mc_price", "mc_price_multi", "mc_greeks_adjoint", "mc_cv_train", "mc_cv_loss_grad",
     "mc_philox_words", "mc_normals", "mc_path_channels", "mc_path_channel_name",
     "mc_workspace_bytes", "mc_adjoint_ckpt_bytes", "mc_status_str", "mc_last_error",
-    "mc_price_mlmc", "mc_mlmc_allocate", "Level", "mc_risk", "PathwisePrice",
+    "mc_price_mlmc", "mc_mlmc_allocate", "Level", "mc_risk", "mc_price_qmc", "PathwisePrice",
     "PreparedPriceMulti"]
 
 
@@ -373,6 +374,31 @@ def mc_risk(ctx: Context, model: Model, strike_mult: Sequence[float], quantity: 
     out = {name: getattr(res, name) for name, _ in _abi.McRiskResult._fields_}
     if pnl is not None:
         out["pnl"] = pnl
+    return out
+
+
+def mc_price_qmc(ctx: Context, model: Model, payoff: Payoff, n_points: int, n_steps: int,
+                 seed: int, n_replicates: int, opts: Options | None = None) -> dict:
+    """Randomised Sobol' quasi-Monte Carlo basket price over n_replicates
+    digital shifts (mc_price_qmc); with opts.path_values and one replicate
+    the per-path channels come back as "path_values"."""
+    mm = _Marshal(model, payoff, opts, n_points)
+    torch = _torch()
+    if torch is not None:
+        mm.co.hip_stream = torch.cuda.current_stream(ctx.device).cuda_stream
+    if mm.opts.path_values:
+        mm.want_path_values(n_points, 3)
+    res = _abi.McQmcResult()
+    st = _abi.load().mc_price_qmc(ctx.handle, C.byref(mm.cm), C.byref(mm.cp), n_points, n_steps,
+                                  seed, n_replicates, C.byref(mm.co), C.byref(res))
+    _check(ctx, st)
+    R = res.n_replicates
+    out = {"price": res.price, "std_err": res.std_err, "geo_price": res.geo_price,
+           "geo_std_err": res.geo_std_err, "n_replicates": R, "n_points": res.n_points,
+           "replicate_price": list(res.replicate_price[:R]),
+           "replicate_geo": list(res.replicate_geo[:R]), "kernel_ms": res.kernel_ms}
+    if mm.path_buf is not None:
+        out["path_values"] = mm.path_buf
     return out
 
 

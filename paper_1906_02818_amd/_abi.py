@@ -23,6 +23,7 @@ MC_ADJ_FULL, MC_ADJ_FWD, MC_ADJ_REV = 0, 1, 2
 MC_MLP_NPARAM = 4545
 MC_MLMC_MAX_LEVELS = 8
 MC_MAX_STRIKES = 8
+MC_QMC_MAX_REPLICATES = 64
 MC_COUPLE_NONE, MC_COUPLE_PRECISION, MC_COUPLE_TIME = 0, 1, 2
 
 _dp = C.POINTER(C.c_double)
@@ -87,6 +88,15 @@ class McRiskResult(C.Structure):
                 ("kernel_ms", C.c_double), ("select_ms", C.c_double)]
 
 
+class McQmcResult(C.Structure):
+    _fields_ = [("price", C.c_double), ("std_err", C.c_double), ("geo_price", C.c_double),
+                ("geo_std_err", C.c_double), ("n_replicates", C.c_uint32),
+                ("n_points", C.c_uint64),
+                ("replicate_price", C.c_double * MC_QMC_MAX_REPLICATES),
+                ("replicate_geo", C.c_double * MC_QMC_MAX_REPLICATES),
+                ("kernel_ms", C.c_double)]
+
+
 class McAdamCfg(C.Structure):
     _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
                 ("eps", C.c_double), ("steps", C.c_uint32), ("batch", C.c_uint64),
@@ -126,6 +136,8 @@ SIGNATURES = {
     "mc_mlmc_allocate": (C.c_int, [C.c_uint32, _dp, _dp, C.c_double, _u64p]),
     "mc_risk": (C.c_int, [C.c_void_p, _P(McModel), _P(McPortfolio), C.c_uint64, C.c_uint32,
                           C.c_uint64, _P(McOptions), _P(McRiskResult)]),
+    "mc_price_qmc": (C.c_int, [C.c_void_p, _P(McModel), _P(McPayoff), C.c_uint64, C.c_uint32,
+                               C.c_uint64, C.c_uint32, _P(McOptions), _P(McQmcResult)]),
     "mc_status_str": (C.c_char_p, [C.c_int]),
     "mc_last_error": (C.c_char_p, [C.c_void_p]),
 }

@@ -14,6 +14,7 @@
 
 #include "../../include/mcpath.h"
 #include "host_math.h"
+#include "host_sobol.h"
 #include "mc_internal.h"
 
 struct mc_context {
@@ -32,6 +33,10 @@ struct mc_context {
   uint32_t coarsen = 1;
   void* mlmc_buf = nullptr;
   size_t mlmc_bytes = 0;
+  // Sobol' direction words of the last quasi-Monte Carlo call (device,
+  // [qmc_dims][32]) followed by one replicate's shifts [qmc_dims].
+  uint32_t* qmc_buf = nullptr;
+  uint32_t qmc_dims = 0;
 };
 
 namespace {
@@ -826,9 +831,18 @@ size_t basket_ws_bytes(size_t layout_bytes, uint32_t d, mc_precision prec) {
 // metrics instead: drifts port->mu (or r) and one per-path channel, the
 // horizon P&L (value of the holdings at T minus their Black-Scholes value
 // `premium` at 0); out->price / variance / std_err describe that P&L.
+// Quasi-Monte Carlo inputs of a basket run (device direction words and
+// shifts) and the run's geometric-basket mean, returned to the caller.
+struct BasketQmc {
+  const uint32_t* V;
+  const uint32_t* shift;
+  double geo_mean;
+};
+
 mc_status basket_price(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint64_t n_paths,
                        uint32_t n_steps, uint64_t seed, const mc_options& o0, mc_result* out,
-                       const mc_portfolio* port = nullptr, double premium = 0.0) {
+                       const mc_portfolio* port = nullptr, double premium = 0.0,
+                       BasketQmc* qmc = nullptr) {
   std::vector<double> L;
   mc_status st = validate_basket(ctx, m, f, n_steps, o0, &L);
   if (st != MC_OK) return st;
@@ -923,6 +937,8 @@ mc_status basket_price(mc_context* ctx, const mc_model* m, const mc_payoff* f, u
     p.pq[k] = (float)port->quantity[k];
   }
   p.premium = premium;
+  p.qV = qmc ? qmc->V : nullptr;
+  p.qshift = qmc ? qmc->shift : nullptr;
   Moments mom;
   double kms = 0.0;
   st = run_moments(ctx, o, n_paths, port ? 1 : 3, o0.path_values,
@@ -939,6 +955,7 @@ mc_status basket_price(mc_context* ctx, const mc_model* m, const mc_payoff* f, u
   r.plain_price = r.price;
   r.plain_std_err = r.std_err;
   if (!port && (o0.greeks & MC_GREEK_DELTA)) fill_channel(mom, 2, &r.delta, &v, &r.delta_se);
+  if (qmc) qmc->geo_mean = mom.mean(1);
   r.vrf = 1.0;
   r.n_paths = (uint64_t)mom.n;
   r.n_nonfinite = (uint64_t)mom.nonfinite;
@@ -1046,6 +1063,7 @@ mc_status mc_destroy(mc_context* ctx) {
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->mlmc_buf) (void)hipFree(ctx->mlmc_buf);
+  if (ctx->qmc_buf) (void)hipFree(ctx->qmc_buf);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -1367,6 +1385,80 @@ mc_status mc_mlmc_allocate(uint32_t n_levels, const double* var, const double* c
     tmp[l] = n < 2.0 ? 2u : (uint64_t)n;
   }
   for (uint32_t l = 0; l < n_levels; ++l) n_paths_out[l] = tmp[l];
+  return MC_OK;
+}
+
+// ------------------------------------------- Randomised quasi-Monte Carlo ----
+mc_status mc_price_qmc(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint64_t n_points,
+                       uint32_t n_steps, uint64_t seed, uint32_t n_replicates,
+                       const mc_options* opts, mc_qmc_result* out) {
+  if (!ctx) return MC_ERR_INVALID_ARG;
+  if (!m || !f || !out) return fail(ctx, MC_ERR_INVALID_ARG, "NULL argument");
+  const mc_options o0 = opts ? *opts : defaults();
+  if (m->kind != MC_GBM_BASKET)
+    return fail(ctx, MC_ERR_UNSUPPORTED, "quasi-Monte Carlo runs on the basket model");
+  if (n_replicates < 1 || n_replicates > MC_QMC_MAX_REPLICATES)
+    return fail(ctx, MC_ERR_INVALID_ARG, "n_replicates must be in 1..%d", MC_QMC_MAX_REPLICATES);
+  if (o0.greeks) return fail(ctx, MC_ERR_UNSUPPORTED, "quasi-Monte Carlo carries no greeks");
+  if (o0.prec != MC_FP32 && o0.prec != MC_BF16_GEMM && o0.prec != MC_FP16_GEMM)
+    return fail(ctx, MC_ERR_UNSUPPORTED, "quasi-Monte Carlo runs in MC_FP32, MC_BF16_GEMM, MC_FP16_GEMM");
+  if (o0.path_values && n_replicates != 1)
+    return fail(ctx, MC_ERR_UNSUPPORTED, "path_values need a single replicate");
+  mc_status st = validate_all(ctx, m, f, n_points, n_steps, o0);
+  if (st != MC_OK) return st;
+  if (o0.path_offset + n_points > (1ull << 32))
+    return fail(ctx, MC_ERR_INVALID_ARG, "Sobol' point indices must stay below 2^32");
+  const uint64_t dims64 = (uint64_t)n_steps * m->dim;
+  if (dims64 > (1u << 16))
+    return fail(ctx, MC_ERR_INVALID_ARG, "n_steps * dim above 2^16 Sobol' dimensions");
+  const uint32_t dims = (uint32_t)dims64;
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, MC_ERR_DEVICE, "hipSetDevice");
+  hipStream_t s = stream_of(ctx, o0);
+  if (ctx->qmc_dims != dims) {
+    std::vector<uint32_t> V;
+    if (!host::sobol_directions(dims, &V))
+      return fail(ctx, MC_ERR_INVALID_ARG, "too many Sobol' dimensions");
+    if (ctx->qmc_buf) {
+      HIP_TRY(ctx, hipStreamSynchronize(s));
+      HIP_TRY(ctx, hipFree(ctx->qmc_buf));
+      ctx->qmc_buf = nullptr;
+      ctx->qmc_dims = 0;
+    }
+    HIP_TRY(ctx, hipMalloc((void**)&ctx->qmc_buf, (size_t)dims * 33 * sizeof(uint32_t)));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->qmc_buf, V.data(), V.size() * sizeof(uint32_t),
+                                hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));     // V goes out of scope
+    ctx->qmc_dims = dims;
+  }
+  BasketQmc q{ctx->qmc_buf, ctx->qmc_buf + (size_t)dims * 32, 0.0};
+  mc_qmc_result r{};
+  r.n_replicates = n_replicates;
+  r.n_points = n_points;
+  for (uint32_t rep = 0; rep < n_replicates; ++rep) {
+    HIP_TRY(ctx, launch_qmc_shifts((uint32_t)seed, (uint32_t)(seed >> 32), o0.stream_tag + 6u,
+                                   rep, dims, (uint32_t*)q.shift, s));
+    mc_result pr{};
+    st = basket_price(ctx, m, f, n_points, n_steps, seed, o0, &pr, nullptr, 0.0, &q);
+    if (st != MC_OK) return st;
+    r.replicate_price[rep] = pr.price;
+    r.replicate_geo[rep] = q.geo_mean;
+    r.kernel_ms += pr.kernel_ms;
+  }
+  auto mean_se = [n_replicates](const double* x, double* mean, double* se) {
+    double s1 = 0.0;
+    for (uint32_t i = 0; i < n_replicates; ++i) s1 += x[i];
+    *mean = s1 / n_replicates;
+    if (n_replicates < 2) {
+      *se = NAN;
+      return;
+    }
+    double s2 = 0.0;
+    for (uint32_t i = 0; i < n_replicates; ++i) s2 += (x[i] - *mean) * (x[i] - *mean);
+    *se = std::sqrt(s2 / (n_replicates - 1.0) / n_replicates);
+  };
+  mean_se(r.replicate_price, &r.price, &r.std_err);
+  mean_se(r.replicate_geo, &r.geo_price, &r.geo_std_err);
+  *out = r;
   return MC_OK;
 }
 

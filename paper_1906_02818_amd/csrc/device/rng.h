@@ -124,6 +124,33 @@ __device__ __forceinline__ Normals4<double> normals4<double>(const Words4& w) {
   return n;
 }
 
+// Sobol' coordinate of point `point` in dimension `dim`: the xor of the
+// direction words V[dim][b] over the set bits b of the point index (point
+// indices below 2^32), as a 32-bit fraction. V is [dims][32] in device
+// memory.
+__device__ __forceinline__ uint32_t sobol_word(const uint32_t* __restrict__ V, uint32_t dim,
+                                               uint32_t point) {
+  const uint32_t* v = V + (size_t)dim * 32u;
+  uint32_t x = 0u;
+  while (point) {
+    x ^= v[__builtin_ctz(point)];
+    point &= point - 1u;
+  }
+  return x;
+}
+
+// Block j of a randomised Sobol' point: dimensions 4j .. 4j+3, each xored
+// with its digital shift; these words replace a Philox block and go through
+// the same uniform and Box-Muller maps.
+__device__ __forceinline__ Words4 sobol_block(const uint32_t* __restrict__ V,
+                                              const uint32_t* __restrict__ shift, uint32_t j,
+                                              uint32_t point) {
+  const uint32_t d = 4u * j;
+  return Words4{sobol_word(V, d, point) ^ shift[d], sobol_word(V, d + 1, point) ^ shift[d + 1],
+                sobol_word(V, d + 2, point) ^ shift[d + 2],
+                sobol_word(V, d + 3, point) ^ shift[d + 3]};
+}
+
 __device__ __forceinline__ uint32_t word_at(const Words4& w, uint32_t s) {
   return s == 0 ? w.w0 : s == 1 ? w.w1 : s == 2 ? w.w2 : w.w3;
 }

@@ -71,7 +71,7 @@ __device__ __forceinline__ void mfma_block(f32x16& acc, const float (&z)[8],
   }
 }
 
-template <int ND, int PREC, bool PORT>
+template <int ND, int PREC, bool PORT, bool QMC>
 __global__ __launch_bounds__(kThreads) void basket_kernel(const BasketParams P) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   constexpr int NBLK = ND * (ND + 1);                 // packed triangular blocks
@@ -112,8 +112,17 @@ __global__ __launch_bounds__(kThreads) void basket_kernel(const BasketParams P) 
     for (int kb = 0; kb < 2 * ND; ++kb) {
       if (kb < nkb) {
         const uint32_t j0 = (uint32_t)((kbase + 16u * kb + 8u * half) >> 2);
-        const Normals4<float> za = normals4<float>(philox(j0, pc));
-        const Normals4<float> zb = normals4<float>(philox(j0 + 1, pc));
+        Words4 wa, wb;
+        if constexpr (QMC) {
+          const uint32_t point = (uint32_t)(P.path_offset + zpath);
+          wa = sobol_block(P.qV, P.qshift, j0, point);
+          wb = sobol_block(P.qV, P.qshift, j0 + 1, point);
+        } else {
+          wa = philox(j0, pc);
+          wb = philox(j0 + 1, pc);
+        }
+        const Normals4<float> za = normals4<float>(wa);
+        const Normals4<float> zb = normals4<float>(wb);
         const float z[8] = {za.z[0], za.z[1], za.z[2], za.z[3],
                             zb.z[0], zb.z[1], zb.z[2], zb.z[3]};
 #pragma unroll
@@ -202,23 +211,31 @@ __global__ __launch_bounds__(kThreads) void basket_kernel(const BasketParams P) 
   }
 }
 
-template <int ND, int PREC, bool PORT>
+template <int ND, int PREC, bool PORT, bool QMC>
 hipError_t launch_nd_mode(const BasketParams& p, hipStream_t s, uint32_t nb) {
   constexpr int NBLK = ND * (ND + 1);
   constexpr int ELT = sizeof(typename BElt<PREC>::T);
   const size_t lds = (size_t)NBLK * 512 * ELT * (PREC == BK_BF16X2 ? 2 : 1);
-  hipError_t e = hipFuncSetAttribute((const void*)basket_kernel<ND, PREC, PORT>,
+  hipError_t e = hipFuncSetAttribute((const void*)basket_kernel<ND, PREC, PORT, QMC>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((basket_kernel<ND, PREC, PORT>), dim3(nb), dim3(kThreads), lds, s, p);
+  hipLaunchKernelGGL((basket_kernel<ND, PREC, PORT, QMC>), dim3(nb), dim3(kThreads), lds, s, p);
   return hipGetLastError();
 }
 
 template <int ND, int PREC>
 hipError_t launch_nd(const BasketParams& p, hipStream_t s, uint32_t nb) {
-  if (p.n_strikes == 0) return launch_nd_mode<ND, PREC, false>(p, s, nb);
-  if constexpr (PREC == BK_BF16X2) return hipErrorInvalidValue;   // portfolio: one-term L'
-  else return launch_nd_mode<ND, PREC, true>(p, s, nb);
+  if constexpr (PREC == BK_BF16X2) {   // basket call with Philox normals only
+    if (p.n_strikes != 0 || p.qV != nullptr) return hipErrorInvalidValue;
+    return launch_nd_mode<ND, PREC, false, false>(p, s, nb);
+  } else {
+    if (p.qV != nullptr) {
+      if (p.n_strikes != 0) return hipErrorInvalidValue;
+      return launch_nd_mode<ND, PREC, false, true>(p, s, nb);
+    }
+    if (p.n_strikes == 0) return launch_nd_mode<ND, PREC, false, false>(p, s, nb);
+    return launch_nd_mode<ND, PREC, true, false>(p, s, nb);
+  }
 }
 
 template <int PREC>

@@ -76,7 +76,25 @@ __global__ __launch_bounds__(kBlock) void diff_moments_kernel(const double* __re
   block_reduce_moments<M, kBlock>(acc, partials, gridDim.x);
 }
 
+__global__ void qmc_shift_kernel(uint32_t k0, uint32_t k1, uint32_t tag, uint64_t replicate,
+                                 uint32_t n_dims, uint32_t* __restrict__ shift) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;   // block index
+  if (4u * j >= n_dims) return;
+  const PathCounter pc = make_counter(replicate, tag, k0, k1);
+  const Words4 w = philox(j, pc);
+  for (uint32_t t = 0; t < 4u && 4u * j + t < n_dims; ++t) shift[4u * j + t] = word_at(w, t);
+}
+
 }  // namespace
+
+hipError_t launch_qmc_shifts(uint32_t k0, uint32_t k1, uint32_t tag, uint64_t replicate,
+                             uint32_t n_dims, uint32_t* shift, hipStream_t s) {
+  const uint32_t blocks = (n_dims + 3u) / 4u;
+  if (blocks == 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(qmc_shift_kernel, dim3((blocks + 255) / 256), dim3(256), 0, s, k0, k1, tag,
+                     replicate, n_dims, shift);
+  return hipGetLastError();
+}
 
 hipError_t launch_diff_moments(const double* a, uint32_t Ca, uint32_t ca, const double* b,
                                uint32_t Cb, uint32_t cb, uint64_t n, double* partials,

@@ -108,6 +108,10 @@ struct BasketParams {
   uint32_t n_strikes;     // 0: basket-call mode
   float pm[8], pq[8];
   double premium;
+  // Randomised quasi-Monte Carlo: when qV is set, normal block j of path p
+  // comes from Sobol' point p (dimensions 4j..4j+3) shifted by qshift.
+  const uint32_t* qV;     // [dims][32] direction words
+  const uint32_t* qshift; // [dims]
   double* partials;
   double* path_out;       // [n_paths][3] (basket) or [n_paths] (portfolio), or nullptr
 };
@@ -115,6 +119,11 @@ constexpr int kMaxStrikes = 8;
 // Number of 32-wide asset blocks the kernel is instantiated for (1, 2, 4, 8).
 uint32_t basket_blocks_nd(uint32_t d);
 hipError_t launch_basket(const BasketParams& p, int prec, hipStream_t s, uint32_t* n_blocks);
+
+// Digital shifts of one randomised-QMC replicate: shift[j] = word (j mod 4)
+// of Philox block (floor(j/4), replicate, tag) under key (k0, k1).
+hipError_t launch_qmc_shifts(uint32_t k0, uint32_t k1, uint32_t tag, uint64_t replicate,
+                             uint32_t n_dims, uint32_t* shift, hipStream_t s);
 
 // ---- Order statistic and tail mean of per-path values (risk metrics) ----
 // Exact k-th smallest (1-based) of x[0..n) by an 8-pass radix select on the

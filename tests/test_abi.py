@@ -86,6 +86,20 @@ def test_risk_struct_layout_matches_header(tmp_path):
     assert got == [C.sizeof(P), C.sizeof(R), P.mu.offset, P.alpha.offset, R.select_ms.offset]
 
 
+def test_qmc_struct_layout_matches_header(tmp_path):
+    src = str(tmp_path / "abi_qmc.c")
+    with open(src, "w") as f:
+        f.write('#include <stdio.h>\n#include <stddef.h>\n#include "mcpath.h"\n'
+                'int main(){printf("%zu %zu %zu\\n", sizeof(mc_qmc_result), '
+                'offsetof(mc_qmc_result, replicate_geo), offsetof(mc_qmc_result, kernel_ms));}\n')
+    exe = src[:-2]
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+    got = [int(x) for x in subprocess.run([exe], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    R = _abi.McQmcResult
+    assert got == [C.sizeof(R), R.replicate_geo.offset, R.kernel_ms.offset]
+
+
 def test_mlmc_allocation_is_the_lagrange_optimum():
     # N_l proportional to sqrt(V_l / C_l), scaled so that sum V_l / N_l hits
     # the target variance; checked against a direct minimisation.
