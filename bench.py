@@ -363,6 +363,38 @@ def run_mlmc_basket(args, ctx, mc, synth, torch):
                               "speedup": plain["total_s"] / mlmc["total_s"]})
 
 
+def run_qmc_basket(args, ctx, mc, synth, torch):
+    """Sobol' randomised QMC against Philox Monte Carlo on a 16-asset basket
+    call in one step (the setting of the Sobol' experiment): 16 replicates of
+    2^16 points against one Monte Carlo run of 2^20 paths; standard errors,
+    device times and the efficiency gain (SE^2 x time ratio)."""
+    d = 16
+    sigma, corr, _ = synth.basket_market(d)
+    model = mc.Model(kind=mc.MC_GBM_BASKET, S0=[100.0] * d, r=0.05, T=1.0, sigma=sigma,
+                     corr=corr)
+    f = mc.Payoff(mc.MC_BASKET_CALL, 100.0)
+    prec = {"fp32": mc.MC_FP32, "bf16": mc.MC_BF16_GEMM, "fp16": mc.MC_FP16_GEMM}.get(
+        args.prec, mc.MC_FP32)
+    R, NQ = 16, 1 << 16
+    ms, outs = _repeat(args, torch, lambda: mc.mc_price_qmc(ctx, model, f, NQ, 1, synth.SEED, R,
+                                                             mc.Options(prec=prec)))
+    q = outs[-1]
+    mcr = mc.mc_price(ctx, model, f, R * NQ, 1, synth.SEED, mc.Options(prec=prec))
+    gain = (mcr["std_err"] ** 2 * mcr["kernel_ms"]) / (q["std_err"] ** 2 * q["kernel_ms"])
+    k_ms = q["kernel_ms"] / R
+    roof = _alu_roofline(SLOTS_ASSET_STEP, NQ * d, k_ms, f"basket_kernel<1, {args.prec}, qmc>")
+    return _line(args, "paths/s", R * NQ / (ms * 1e-3), "paths/s", ms, args.prec,
+                 {"workload": "basket call, d = 16, one step, randomised Sobol' QMC "
+                              "(16 digital shifts x 2^16 points) vs Philox MC (2^20 paths)",
+                  "n_points": NQ, "replicates": R, "d": d},
+                 roof, kernel_ms=q["kernel_ms"],
+                 qmc={"price": q["price"], "std_err": q["std_err"],
+                      "geo_price": q["geo_price"], "geo_std_err": q["geo_std_err"],
+                      "mc_price": mcr["price"], "mc_std_err": mcr["std_err"],
+                      "mc_kernel_ms": mcr["kernel_ms"], "variance_ratio":
+                      (mcr["std_err"] / q["std_err"]) ** 2, "efficiency_gain": gain})
+
+
 RISK_STRIKES = [0.9, 0.95, 1.0, 1.05, 1.1]
 RISK_QTY = [1.0, -2.0, 1.5, -1.0, 0.5]
 
@@ -441,7 +473,7 @@ def run_learned_cv(args, ctx, mc, synth, torch):
 
 WORKLOADS = {"asian_barrier": run_asian_barrier, "european": run_european, "basket": run_basket,
              "heston_adjoint": run_heston_adjoint, "learned_cv": run_learned_cv,
-             "mlmc_basket": run_mlmc_basket, "risk": run_risk}
+             "mlmc_basket": run_mlmc_basket, "risk": run_risk, "qmc_basket": run_qmc_basket}
 
 
 def main():
