@@ -128,7 +128,7 @@ def _timed(torch, fn):
     return r, time.perf_counter() - t0
 
 
-def time_to_1bp(ctx, mc, synth, torch, hedge_every=8, adam_steps=2000):
+def time_to_1bp(ctx, mc, synth, torch, hedge_every=16, adam_steps=2000):
     """Time to a Heston-Asian price whose standard error is 1 bp of the price
     (1e-4 x price), plain FP32 Monte Carlo against the learned control
     variate with BF16 matrix products. Each estimator: a 2^20-path pilot on
@@ -485,7 +485,7 @@ def main():
     ap.add_argument("--prec", choices=["fp32", "bf16", "fp16", "bf16x2"], default="bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-time-to-1bp", action="store_true")
-    ap.add_argument("--hedge-every", type=int, default=8)
+    ap.add_argument("--hedge-every", type=int, default=16)
     ap.add_argument("--adam-steps", type=int, default=2000,
                     help="training steps of the hedge network in the time-to-1bp comparison")
     ap.add_argument("--copy-probe", action="store_true",
