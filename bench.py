@@ -47,24 +47,25 @@ MFMA_PEAK = {"fp32": 157.3e12, "bf16": 2.5e15, "fp16": 2.5e15, "bf16x2": 2.5e15}
 COST_MUL64 = 3.45    # 32x32->64-bit product (v_mad_u64_u32): 4.00 with its xor, minus 0.55
 COST_TRANS = 4.09    # v_exp / sin / cos / sqrt / rcp _f32
 COST_LOG = 4.93      # v_log_f32: 6.04 with its dependent add, minus 1.11
-COST_INT = 0.55      # xor, shift, or, compare (gfx950 has no three-input xor)
+COST_INT = 0.55      # xor, shift, or, compare
+COST_BITOP3 = 0.55   # v_bitop3_b32 (three-input xor); taken equal to v_xor_b32 until measured
 COST_FP32 = 1.11     # add, mul, fma
 COST_FP64 = 2.38     # v_fma_f64
 
 
-def slots(mul64=0.0, trans=0.0, log=0.0, intops=0.0, fp32=0.0, fp64=0.0):
+def slots(mul64=0.0, trans=0.0, log=0.0, intops=0.0, fp32=0.0, fp64=0.0, bitop3=0.0):
     return (mul64 * COST_MUL64 + trans * COST_TRANS + log * COST_LOG + intops * COST_INT
-            + fp32 * COST_FP32 + fp64 * COST_FP64)
+            + fp32 * COST_FP32 + fp64 * COST_FP64 + bitop3 * COST_BITOP3)
 
 
 # One FP32 normal: a quarter of a Philox4x32-10 block (10 rounds of 2 mul64
-# and 4 xor), the uniform (shift, or, sub) and half of a Box-Muller pair
-# (log, sqrt, sin, cos and 3 mul). Where every lane of a wave draws the same
+# and 2 three-input xors), the uniform (shift, or, sub) and half of a
+# Box-Muller pair (log, sqrt, sin, cos and 3 mul). Where every lane of a wave draws the same
 # block index at a step (one path per lane), the first product of round 1
 # and the second of round 2 do not depend on the path: 18 of the 20 products
 # are per-path work. The basket's lanes draw two block indices per step, so
 # all 20 are.
-NORMAL = dict(mul64=18 / 4, log=0.5, trans=1.5, intops=10.0 + 2.0, fp32=1.0 + 1.5)
+NORMAL = dict(mul64=18 / 4, log=0.5, trans=1.5, bitop3=5.0, intops=2.0, fp32=1.0 + 1.5)
 NORMAL_BASKET = dict(NORMAL, mul64=20 / 4)
 
 
@@ -201,11 +202,7 @@ def _line(args, metric, value, unit, ms, dtype, config, roofline, higher_is_bett
 # the factors are what the counters read for a 1 GiB copy), for the kernels
 # and launch shapes the profiles under profiles/ name; None where a kernel
 # has no such measurement.
-TRAFFIC_BYTES = {
-    "gbm_path_kernel<float, asian|geo|uo, log-Euler>": 2.984e6,   # 2^24 paths x 252 steps
-    "basket_kernel<8, bf16>": 3.363e6,                          # 2^20 paths x 100 steps
-    "heston_adjoint_kernel<float, full, asian>": 9.411e8,       # 2^22 paths x 256 steps
-}
+TRAFFIC_BYTES = {}
 
 
 def _alu_roofline(slots_per_unit, units, kernel_ms, kernel):

@@ -56,8 +56,9 @@ __device__ __forceinline__ Words4 philox(uint32_t j, const PathCounter& pc) {
     uint32_t hi0, lo0, hi1, lo1;
     mul_hi_lo(kPhiloxM0, c0, hi0, lo0);
     mul_hi_lo(kPhiloxM1, c2, hi1, lo1);
-    const uint32_t n0 = hi1 ^ c1 ^ k0;
-    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    // Three-input xors: one v_bitop3_b32 each (truth table 0x96 = a^b^c).
+    const uint32_t n0 = __builtin_amdgcn_bitop3_b32(hi1, c1, k0, 0x96);
+    const uint32_t n2 = __builtin_amdgcn_bitop3_b32(hi0, c3, k1, 0x96);
     c0 = n0;
     c1 = lo1;
     c2 = n2;

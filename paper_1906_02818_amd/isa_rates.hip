@@ -26,7 +26,7 @@
 constexpr int kIters = 2048;
 constexpr int kChains = 8;
 
-enum Op { FMA_F32, FMAC_F32, FMA_INL, MAD_U64, MUL_HI, MUL_LO, XOR, EXP_F32, LOG_F32, SIN_F32, SQRT_F32, RCP_F32, FMA_F64 };
+enum Op { FMA_F32, FMAC_F32, FMA_INL, BITOP3, MAD_U64, MUL_HI, MUL_LO, XOR, EXP_F32, LOG_F32, SIN_F32, SQRT_F32, RCP_F32, FMA_F64 };
 
 template <int OP>
 __global__ __launch_bounds__(256) void rate_kernel(unsigned* out, unsigned seed, float kmul) {
@@ -41,6 +41,9 @@ __global__ __launch_bounds__(256) void rate_kernel(unsigned* out, unsigned seed,
     d[c] = (double)f[c];
   }
   unsigned key = seed * 0x9E3779B9u;
+  unsigned f_bits[kChains];             // per-chain third operand (VGPR, loop invariant)
+#pragma unroll
+  for (int c = 0; c < kChains; ++c) f_bits[c] = t * 0x85EBCA6Bu + 31u * c;
   for (int it = 0; it < kIters; ++it) {
     key += 0xBB67AE85u;                                  // scalar, keeps the xor chain alive
 #pragma unroll
@@ -60,6 +63,8 @@ __global__ __launch_bounds__(256) void rate_kernel(unsigned* out, unsigned seed,
         a[c] = a[c] * (key | 1u);                        // scalar factor: no folding
       } else if constexpr (OP == XOR) {
         a[c] = a[c] ^ key;
+      } else if constexpr (OP == BITOP3) {
+        a[c] = __builtin_amdgcn_bitop3_b32(a[c], key, f_bits[c], 0x96);   // a ^ key ^ const
       } else if constexpr (OP == EXP_F32) {
         f[c] = __builtin_amdgcn_exp2f(-f[c]);            // converges, stays finite
       } else if constexpr (OP == LOG_F32) {
@@ -120,6 +125,7 @@ int main() {
       {"v_mul_hi_u32", run<MUL_HI>(d_out, blocks, threads, e0, e1), 0.0},
       {"v_mul_lo_u32", run<MUL_LO>(d_out, blocks, threads, e0, e1), 0.0},
       {"v_xor_b32", run<XOR>(d_out, blocks, threads, e0, e1), 0.0},
+      {"v_bitop3_b32 (xor3)", run<BITOP3>(d_out, blocks, threads, e0, e1), 0.0},
       {"v_exp_f32", run<EXP_F32>(d_out, blocks, threads, e0, e1), 0.0},
       {"v_log_f32 (+ v_add_f32)", run<LOG_F32>(d_out, blocks, threads, e0, e1), 1.0},
       {"v_sin_f32", run<SIN_F32>(d_out, blocks, threads, e0, e1), 0.0},
