@@ -39,18 +39,22 @@ ALU_PEAK_SLOTS = N_CU * CLOCK_HZ * FMA_LANES_PER_CLK      # 7.86e13 slots/s
 MFMA_PEAK = {"fp32": 157.3e12, "bf16": 2.5e15, "fp16": 2.5e15, "bf16x2": 2.5e15}
 
 # Issue cost of each instruction class on gfx950 in "slots": wave64 FMA
-# issues at the FP32 vector peak (2 per clock per CU). Each cost is 2 divided
+# issues at the FP32 vector peak (2 per clock per CU). Costs are 2 divided
 # by the wave64 issue rate per clock per CU that
-# paper_1906_02818_amd/isa_rates.hip measures for the instruction in
-# isolation (profiles/isa_rates.txt); an FP32 FMA itself issues at 1.80 per
-# clock, so it costs 1.11.
-COST_MUL64 = 3.45    # 32x32->64-bit product (v_mad_u64_u32): 4.00 with its xor, minus 0.55
+# paper_1906_02818_amd/isa_rates.hip measures in isolation
+# (profiles/isa_rates.txt). An FP32 FMA issues at 1.77 per clock, so it
+# costs 1.13; other single-pass 32-bit operations (xor, shift, compare,
+# alignbit) are charged the same. The isolated three-input xor measures half
+# that rate (2.08), but in the Philox rounds it replaced two xors and made
+# the kernels faster, so it is charged as one single-pass operation, the
+# lower (conservative) figure.
+COST_FP32 = 1.13     # add, mul, fma
+COST_INT = 1.13      # xor, shift, compare, alignbit
+COST_BITOP3 = 1.13   # v_bitop3_b32 (three-input xor)
+COST_MUL64 = 3.01    # 32x32->64-bit product (v_mad_u64_u32): 4.14 with its xor, minus 1.13
 COST_TRANS = 4.09    # v_exp / sin / cos / sqrt / rcp _f32
-COST_LOG = 4.93      # v_log_f32: 6.04 with its dependent add, minus 1.11
-COST_INT = 0.55      # xor, shift, or, compare
-COST_BITOP3 = 0.55   # v_bitop3_b32 (three-input xor); taken equal to v_xor_b32 until measured
-COST_FP32 = 1.11     # add, mul, fma
-COST_FP64 = 2.38     # v_fma_f64
+COST_LOG = 4.09      # v_log_f32: between 4.09 and 6.06 - 1.13; the lower figure
+COST_FP64 = 2.40     # v_fma_f64
 
 
 def slots(mul64=0.0, trans=0.0, log=0.0, intops=0.0, fp32=0.0, fp64=0.0, bitop3=0.0):
@@ -59,13 +63,15 @@ def slots(mul64=0.0, trans=0.0, log=0.0, intops=0.0, fp32=0.0, fp64=0.0, bitop3=
 
 
 # One FP32 normal: a quarter of a Philox4x32-10 block (10 rounds of 2 mul64
-# and 2 three-input xors), the uniform (shift, or, sub) and half of a
-# Box-Muller pair (log, sqrt, sin, cos and 3 mul). Where every lane of a wave draws the same
-# block index at a step (one path per lane), the first product of round 1
-# and the second of round 2 do not depend on the path: 18 of the 20 products
-# are per-path work. The basket's lanes draw two block indices per step, so
-# all 20 are.
-NORMAL = dict(mul64=18 / 4, log=0.5, trans=1.5, bitop3=5.0, intops=2.0, fp32=1.0 + 1.5)
+# and 2 three-input xors), the uniform (one alignbit, one sub) and half of a
+# Box-Muller pair (log, sqrt, sin, cos and 3 mul). Where every lane of a wave
+# draws the same block index at a step (one path per lane), round 1's two
+# products (block index; the path's high word, the same for every path below
+# 2^32) and round 2's second (fed only by round 1's uniform results) do not
+# depend on the path: 17 of the 20 products are per-path work, the count the
+# compiled kernels issue. The basket's lanes draw two block indices per step,
+# so all 20 are.
+NORMAL = dict(mul64=17 / 4, log=0.5, trans=1.5, bitop3=5.0, intops=1.0, fp32=1.0 + 1.5)
 NORMAL_BASKET = dict(NORMAL, mul64=20 / 4)
 
 
@@ -202,7 +208,11 @@ def _line(args, metric, value, unit, ms, dtype, config, roofline, higher_is_bett
 # the factors are what the counters read for a 1 GiB copy), for the kernels
 # and launch shapes the profiles under profiles/ name; None where a kernel
 # has no such measurement.
-TRAFFIC_BYTES = {}
+TRAFFIC_BYTES = {
+    "gbm_path_kernel<float, asian|geo|uo, log-Euler>": 2.984e6,   # 2^24 paths x 252 steps
+    "basket_kernel<8, bf16>": 3.392e6,                          # 2^20 paths x 100 steps
+    "heston_adjoint_kernel<float, full, asian>": 9.389e8,       # 2^22 paths x 256 steps
+}
 
 
 def _alu_roofline(slots_per_unit, units, kernel_ms, kernel):

@@ -72,7 +72,8 @@ __device__ __forceinline__ Words4 philox(uint32_t j, const PathCounter& pc) {
 // u(w) = (2 (w >> 9) + 1) 2^-24, exact in FP32: the top 23 bits fill the
 // mantissa of a float in [1, 2), and subtracting 1 - 2^-24 is exact.
 __device__ __forceinline__ float uniform_f32(uint32_t w) {
-  return __uint_as_float((w >> 9) | 0x3F800000u) - 0x1.fffffep-1f;
+  // (0x7F:w) >> 9 = 0x3F800000 | (w >> 9) in one v_alignbit_b32.
+  return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, w, 9u)) - 0x1.fffffep-1f;
 }
 
 __device__ __forceinline__ double uniform_f64(uint32_t w) {

@@ -26,7 +26,7 @@
 constexpr int kIters = 2048;
 constexpr int kChains = 8;
 
-enum Op { FMA_F32, FMAC_F32, FMA_INL, BITOP3, MAD_U64, MUL_HI, MUL_LO, XOR, EXP_F32, LOG_F32, SIN_F32, SQRT_F32, RCP_F32, FMA_F64 };
+enum Op { FMA_F32, FMAC_F32, FMA_INL, BITOP3, EXP_3FMA, MAD_U64, MUL_HI, MUL_LO, XOR, EXP_F32, LOG_F32, SIN_F32, SQRT_F32, RCP_F32, FMA_F64 };
 
 template <int OP>
 __global__ __launch_bounds__(256) void rate_kernel(unsigned* out, unsigned seed, float kmul) {
@@ -41,6 +41,9 @@ __global__ __launch_bounds__(256) void rate_kernel(unsigned* out, unsigned seed,
     d[c] = (double)f[c];
   }
   unsigned key = seed * 0x9E3779B9u;
+  float g[kChains];                     // second FP32 chain of the overlap probe
+#pragma unroll
+  for (int c = 0; c < kChains; ++c) g[c] = 0.25f + 0.01f * c;
   unsigned f_bits[kChains];             // per-chain third operand (VGPR, loop invariant)
 #pragma unroll
   for (int c = 0; c < kChains; ++c) f_bits[c] = t * 0x85EBCA6Bu + 31u * c;
@@ -63,6 +66,12 @@ __global__ __launch_bounds__(256) void rate_kernel(unsigned* out, unsigned seed,
         a[c] = a[c] * (key | 1u);                        // scalar factor: no folding
       } else if constexpr (OP == XOR) {
         a[c] = a[c] ^ key;
+      } else if constexpr (OP == EXP_3FMA) {
+        // One transcendental and three independent FMAs per step: issue time
+        // tells whether the two kinds overlap (max) or add (sum).
+        f[c] = __builtin_amdgcn_exp2f(-f[c]);
+        g[c] = __builtin_fmaf(__builtin_fmaf(__builtin_fmaf(g[c], -0.5f, 2.0f), -0.5f, 2.0f),
+                              -0.5f, 2.0f);
       } else if constexpr (OP == BITOP3) {
         a[c] = __builtin_amdgcn_bitop3_b32(a[c], key, f_bits[c], 0x96);   // a ^ key ^ const
       } else if constexpr (OP == EXP_F32) {
@@ -83,7 +92,8 @@ __global__ __launch_bounds__(256) void rate_kernel(unsigned* out, unsigned seed,
   unsigned acc = 0;
 #pragma unroll
   for (int c = 0; c < kChains; ++c)
-    acc ^= a[c] ^ __float_as_uint(f[c]) ^ (unsigned)__double_as_longlong(d[c]);
+    acc ^= a[c] ^ __float_as_uint(f[c]) ^ (unsigned)__double_as_longlong(d[c]) ^
+           __float_as_uint(g[c]);
   out[t] = acc;
 }
 
@@ -126,6 +136,7 @@ int main() {
       {"v_mul_lo_u32", run<MUL_LO>(d_out, blocks, threads, e0, e1), 0.0},
       {"v_xor_b32", run<XOR>(d_out, blocks, threads, e0, e1), 0.0},
       {"v_bitop3_b32 (xor3)", run<BITOP3>(d_out, blocks, threads, e0, e1), 0.0},
+      {"v_exp_f32 + 3 v_fma_f32", run<EXP_3FMA>(d_out, blocks, threads, e0, e1), 0.0},
       {"v_exp_f32", run<EXP_F32>(d_out, blocks, threads, e0, e1), 0.0},
       {"v_log_f32 (+ v_add_f32)", run<LOG_F32>(d_out, blocks, threads, e0, e1), 1.0},
       {"v_sin_f32", run<SIN_F32>(d_out, blocks, threads, e0, e1), 0.0},
