@@ -76,6 +76,22 @@ def lib():
         L.orc_basket_qmc.argtypes = [C.c_int, _dp, _dp, _dp, _dp, C.c_double, C.c_double,
                                      C.c_double, C.c_int, C.c_uint64, C.c_uint32, C.c_uint64,
                                      C.c_uint64, C.c_uint64, _dp]
+        _i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+        L.orc_lsm_n_features.argtypes = [C.c_int, C.c_int, C.c_int]
+        L.orc_lsm_n_features.restype = C.c_int
+        L.orc_lsm.argtypes = [C.c_int, _dp, _dp, _dp, C.c_double, C.c_double, C.c_double,
+                              C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, C.c_uint64,
+                              C.c_uint32, C.c_uint64, C.c_uint64, _dp, _dp, _i64p,
+                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_lsm.restype = C.c_int
+        L.orc_lsm_oos.argtypes = [C.c_int, _dp, _dp, _dp, C.c_double, C.c_double, C.c_double,
+                                  C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, _dp,
+                                  C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64, _dp,
+                                  C.c_void_p, C.c_void_p]
+        L.orc_lsm_oos.restype = C.c_int
+        L.orc_lsm_lattice.argtypes = [C.c_int, _dp, _dp, C.c_double, C.c_double, C.c_double,
+                                      C.c_int, C.c_double, C.c_int, C.c_int]
+        L.orc_lsm_lattice.restype = C.c_double
         L.orc_heston_cv.argtypes = [_dp, C.c_int, C.c_int, _dp, C.c_uint64,
                                     C.c_uint32, C.c_uint64, C.c_uint64, _dp]
         L.orc_mlp_eval.argtypes = [_dp, C.c_uint64, _dp, _dp]
@@ -240,6 +256,68 @@ def basket_qmc(S0, sigma, L, w, r, T, K, n_steps, n_paths, seed, replicate, tag=
     lib().orc_basket_qmc(S0.size, S0, sigma, L, w, r, T, K, n_steps, seed, tag, replicate,
                          path0, n_paths, out)
     return out
+
+
+# --------------------------------------------------------------------------
+# Longstaff-Schwartz regression for Bermudan options (Sec. II-A.3, VI-C) and
+# the binomial lattice that gives the value it estimates.
+# --------------------------------------------------------------------------
+LSM_MAX_CALL, LSM_BASKET_PUT, LSM_BASKET_CALL = 1, 2, 3
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def lsm_n_features(d, degree, kind) -> int:
+    return lib().orc_lsm_n_features(d, degree, kind)
+
+
+def lsm(S0, sigma, L, r, q, T, kind, K, n_dates, steps_per_date, degree, n_paths, seed,
+        tag=0, path0=0, want_paths=False) -> dict:
+    """In-sample Longstaff-Schwartz estimate and everything it decided."""
+    S0, sigma, L = _c(S0), _c(sigma), _c(L)
+    d, M, n = S0.size, n_dates, n_paths
+    nf = lsm_n_features(d, degree, kind)
+    res = np.zeros(4)
+    beta = np.zeros((M, nf))
+    n_itm = np.zeros(M, np.int64)
+    Cf = np.zeros(n)
+    ex = np.zeros(n, np.int32)
+    cont = np.zeros((n, M))
+    y = np.zeros((n, M, d)) if want_paths else None
+    got = lib().orc_lsm(d, S0, sigma, L, r, q, T, kind, K, M, steps_per_date, degree, seed,
+                        tag, path0, n, res, beta, n_itm, _ptr(Cf), _ptr(ex), _ptr(cont), _ptr(y))
+    if got != nf:
+        raise ValueError("orc_lsm rejected its arguments")
+    out = {"price": res[0], "std_err": res[1], "european": res[2], "european_se": res[3],
+           "beta": beta, "n_itm": n_itm, "C": Cf, "ex": ex, "cont": cont, "n_features": nf}
+    if want_paths:
+        out["y"] = y
+    return out
+
+
+def lsm_oos(S0, sigma, L, r, q, T, kind, K, n_dates, steps_per_date, degree, beta, n_paths,
+            seed, tag=7, path0=0) -> dict:
+    """Out-of-sample estimate: the exercise rule of `beta` on fresh paths."""
+    S0, sigma, L = _c(S0), _c(sigma), _c(L)
+    res = np.zeros(2)
+    Y = np.zeros(n_paths)
+    ex = np.zeros(n_paths, np.int32)
+    got = lib().orc_lsm_oos(S0.size, S0, sigma, L, r, q, T, kind, K, n_dates, steps_per_date,
+                            degree, _c(beta), seed, tag, path0, n_paths, res, _ptr(Y), _ptr(ex))
+    if got < 0:
+        raise ValueError("orc_lsm_oos rejected its arguments")
+    return {"price": res[0], "std_err": res[1], "Y": Y, "ex": ex}
+
+
+def lsm_lattice(S0, sigma, r, q, T, kind, K, n_dates, tree_steps_per_date) -> float:
+    S0, sigma = _c(S0), _c(sigma)
+    v = lib().orc_lsm_lattice(S0.size, S0, sigma, r, q, T, kind, K, n_dates,
+                              tree_steps_per_date)
+    if v < 0:
+        raise ValueError("orc_lsm_lattice rejected its arguments")
+    return v
 
 
 def _c(a) -> np.ndarray:

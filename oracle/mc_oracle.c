@@ -858,3 +858,337 @@ void orc_basket_qmc(int d, const double *S0, const double *sigma, const double *
     free(V);
     free(sh);
 }
+
+/* ------------------------------------------------------------------------ */
+/* 12. Longstaff-Schwartz regression for callable (Bermudan) options        */
+/*    (Sec. II-A.3; the American max-option experiment of Sec. VI-C).       */
+/*    Model: d <= 4 correlated GBM assets with continuous dividend yield q,   */
+/*    log-Euler per asset as in section 8 with drift r - q:                   */
+/*      x_a += (r - q - sigma_a^2/2) dt + sigma_a sqrt(dt) (L Z_i)_a          */
+/*    Exercise dates t_j = j T / M (j = 1..M), `spd` Euler steps between     */
+/*    consecutive dates (dt = T / (M spd)); step i uses normals i*d + a.      */
+/*    State y_a = S_a / K. Payoffs f (equal weights 1/d):                   */
+/*      1 max-call    (max_a S_a - K)+                                        */
+/*      2 basket put  (K - mean_a S_a)+                                       */
+/*      3 basket call (mean_a S_a - K)+                                       */
+/*    Dynamic programming on realised cash flows: every path carries its      */
+/*    discounted cash flow C (at first e^{-rT} f(t_M)). For j = M-1 .. 1 the  */
+/*    cash flows of the paths in the money at t_j (f > 0) are projected on    */
+/*    the features psi(y(t_j)) by least squares, solving the normal          */
+/*    equations (sum psi psi^T) beta = sum psi C through a Cholesky          */
+/*    factorisation of the Gram matrix; an in-the-money path whose           */
+/*    discounted exercise value e^{-r t_j} f is at least the fitted           */
+/*    continuation psi . beta exercises: C = e^{-r t_j} f. The price is the   */
+/*    mean of C over all paths (an averaging reduction, as the paper ends    */
+/*    the method); t = 0 is not an exercise date.                            */
+/*    Features: every monomial of y_1..y_d of total degree <= deg, by degree, */
+/*    then by the nondecreasing index tuple; for the max-call with d >= 2    */
+/*    the payoff f / K is appended (on the in-the-money set the basket       */
+/*    payoffs are affine in y, so there it would duplicate degree 1).        */
+/*    A date with fewer in-the-money paths than features, or whose Gram      */
+/*    matrix has a Cholesky pivot <= 1e-12 times its diagonal entry, gets no */
+/*    regression and no exercise (beta row NaN).                             */
+/* ------------------------------------------------------------------------ */
+#define LSM_MAXB 12
+
+static double lsm_payoff(int kind, int d, const double *y)
+{
+    double m = y[0], s = 0.0;
+    for (int a = 0; a < d; ++a) {
+        if (y[a] > m) m = y[a];
+        s += y[a];
+    }
+    s /= d;
+    if (kind == 1) return pos(m - 1.0);
+    if (kind == 2) return pos(1.0 - s);
+    return pos(s - 1.0);
+}
+
+/* Number of features, and their index triples (index d stands for 1,
+ * index d+1 for f/K). */
+static int lsm_features(int d, int deg, int kind, int idx[][3])
+{
+    int n = 0;
+    idx[n][0] = d; idx[n][1] = d; idx[n][2] = d; ++n;
+    if (deg >= 1)
+        for (int a = 0; a < d; ++a) { idx[n][0] = a; idx[n][1] = d; idx[n][2] = d; ++n; }
+    if (deg >= 2)
+        for (int a = 0; a < d; ++a)
+            for (int b = a; b < d; ++b) { idx[n][0] = a; idx[n][1] = b; idx[n][2] = d; ++n; }
+    if (deg >= 3)
+        for (int a = 0; a < d; ++a)
+            for (int b = a; b < d; ++b)
+                for (int c = b; c < d; ++c) { idx[n][0] = a; idx[n][1] = b; idx[n][2] = c; ++n; }
+    if (kind == 1 && d >= 2) { idx[n][0] = d + 1; idx[n][1] = d; idx[n][2] = d; ++n; }
+    return n;
+}
+
+int orc_lsm_n_features(int d, int deg, int kind)
+{
+    int idx[64][3];
+    if (d < 1 || d > 4 || deg < 0 || deg > 3) return -1;
+    return lsm_features(d, deg, kind, idx);
+}
+
+static void lsm_psi(int d, int nf, int idx[][3], const double *y, double fK, double *psi)
+{
+    double v[6];
+    for (int a = 0; a < d; ++a) v[a] = y[a];
+    v[d] = 1.0;
+    v[d + 1] = fK;
+    for (int k = 0; k < nf; ++k) psi[k] = v[idx[k][0]] * v[idx[k][1]] * v[idx[k][2]];
+}
+
+/* Solves G x = b (G symmetric positive definite, n x n) by Cholesky; -1 when a
+ * pivot is <= 1e-12 times the diagonal entry it comes from. */
+static int lsm_solve(int n, const double *G, const double *b, double *x)
+{
+    double Lc[LSM_MAXB * LSM_MAXB], y[LSM_MAXB];
+    for (int j = 0; j < n; ++j) {
+        double s = G[j * n + j];
+        for (int k = 0; k < j; ++k) s -= Lc[j * n + k] * Lc[j * n + k];
+        if (!(s > 1e-12 * G[j * n + j])) return -1;
+        Lc[j * n + j] = sqrt(s);
+        for (int i = j + 1; i < n; ++i) {
+            double t = G[i * n + j];
+            for (int k = 0; k < j; ++k) t -= Lc[i * n + k] * Lc[j * n + k];
+            Lc[i * n + j] = t / Lc[j * n + j];
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        double t = b[i];
+        for (int k = 0; k < i; ++k) t -= Lc[i * n + k] * y[k];
+        y[i] = t / Lc[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double t = y[i];
+        for (int k = i + 1; k < n; ++k) t -= Lc[k * n + i] * x[k];
+        x[i] = t / Lc[i * n + i];
+    }
+    return 0;
+}
+
+/* y[(p * M + (j-1)) * d + a] = S_a(t_j) / K for paths path0 .. path0+n-1. */
+static void lsm_paths(int d, const double *S0, const double *sigma, const double *L,
+                      double r, double q, double T, double K, int M, int spd,
+                      uint64_t seed, uint32_t tag, uint64_t path0, uint64_t n, double *y)
+{
+    const double dt = T / ((double)M * spd), sdt = sqrt(dt);
+#pragma omp parallel for schedule(static)
+    for (long long p = 0; p < (long long)n; ++p) {
+        double x[4], Z[4];
+        normal_stream ns;
+        ns_init(&ns, seed, tag, path0 + (uint64_t)p);
+        for (int a = 0; a < d; ++a) x[a] = log(S0[a] / K);
+        for (int j = 1; j <= M; ++j) {
+            for (int s = 0; s < spd; ++s) {
+                for (int a = 0; a < d; ++a) Z[a] = ns_next(&ns);
+                for (int a = 0; a < d; ++a) {
+                    double dW = 0.0;
+                    for (int b = 0; b <= a; ++b) dW += L[a * d + b] * Z[b];
+                    x[a] += (r - q - 0.5 * sigma[a] * sigma[a]) * dt + sigma[a] * sdt * dW;
+                }
+            }
+            for (int a = 0; a < d; ++a) y[((uint64_t)p * M + (j - 1)) * d + a] = exp(x[a]);
+        }
+    }
+}
+
+static void mean_se(const double *v, uint64_t n, double *out)
+{
+    double s = 0.0;
+    for (uint64_t i = 0; i < n; ++i) s += v[i];
+    const double m = s / (double)n;
+    double ss = 0.0;
+    for (uint64_t i = 0; i < n; ++i) ss += (v[i] - m) * (v[i] - m);
+    out[0] = m;
+    out[1] = n > 1 ? sqrt(ss / (double)(n - 1) / (double)n) : NAN;
+}
+
+/* In-sample Longstaff-Schwartz. res = {price, std_err, european, european_se}
+ * (european: exercise at t_M only, same paths). beta [M][nf], row j-1 for date
+ * j (row M-1 and rows without regression NaN); n_itm [M]. Optional (NULL):
+ * C [n] discounted cash flows, ex [n] exercise date (0 = never), cont [n][M]
+ * fitted continuation (NaN where not evaluated), yout [n][M][d]. Returns nf,
+ * or -1 on bad arguments. */
+int orc_lsm(int d, const double *S0, const double *sigma, const double *L, double r,
+            double q, double T, int kind, double K, int M, int spd, int deg,
+            uint64_t seed, uint32_t tag, uint64_t path0, uint64_t n, double *res,
+            double *beta, int64_t *n_itm, double *C, int32_t *ex, double *cont, double *yout)
+{
+    int idx[64][3];
+    if (d < 1 || d > 4 || M < 1 || spd < 1 || n < 1 || kind < 1 || kind > 3) return -1;
+    const int nf = lsm_features(d, deg, kind, idx);
+    if (nf > LSM_MAXB - 1) return -1;
+    double *y = yout ? yout : (double *)malloc(sizeof(double) * n * (size_t)M * d);
+    double *c = (double *)malloc(sizeof(double) * n);
+    int32_t *e = (int32_t *)malloc(sizeof(int32_t) * n);
+    lsm_paths(d, S0, sigma, L, r, q, T, K, M, spd, seed, tag, path0, n, y);
+    if (cont)
+        for (uint64_t i = 0; i < n * (uint64_t)M; ++i) cont[i] = NAN;
+    for (int i = 0; i < M * nf; ++i) beta[i] = NAN;
+    for (int j = 0; j < M; ++j) n_itm[j] = 0;
+    const double discT = exp(-r * T);
+    for (uint64_t p = 0; p < n; ++p) {
+        const double f = K * lsm_payoff(kind, d, y + (p * M + (M - 1)) * d);
+        c[p] = discT * f;
+        e[p] = f > 0.0 ? M : 0;
+        if (f > 0.0) n_itm[M - 1]++;
+    }
+    mean_se(c, n, res + 2);
+    for (int j = M - 1; j >= 1; --j) {
+        const double dj = exp(-r * T * j / M);
+        double G[LSM_MAXB * LSM_MAXB] = {0}, b[LSM_MAXB] = {0}, psi[LSM_MAXB], bj[LSM_MAXB];
+        int64_t m = 0;
+        for (uint64_t p = 0; p < n; ++p) {
+            const double *yp = y + (p * M + (j - 1)) * d;
+            const double f = lsm_payoff(kind, d, yp);
+            if (!(f > 0.0)) continue;
+            ++m;
+            lsm_psi(d, nf, idx, yp, f, psi);
+            for (int u = 0; u < nf; ++u) {
+                for (int v = 0; v < nf; ++v) G[u * nf + v] += psi[u] * psi[v];
+                b[u] += psi[u] * c[p];
+            }
+        }
+        n_itm[j - 1] = m;
+        if (m < nf || lsm_solve(nf, G, b, bj) != 0) continue;
+        for (int u = 0; u < nf; ++u) beta[(j - 1) * nf + u] = bj[u];
+        for (uint64_t p = 0; p < n; ++p) {
+            const double *yp = y + (p * M + (j - 1)) * d;
+            const double f = lsm_payoff(kind, d, yp);
+            if (!(f > 0.0)) continue;
+            lsm_psi(d, nf, idx, yp, f, psi);
+            double h = 0.0;
+            for (int u = 0; u < nf; ++u) h += psi[u] * bj[u];
+            if (cont) cont[p * M + (j - 1)] = h;
+            if (dj * K * f >= h) {
+                c[p] = dj * K * f;
+                e[p] = j;
+            }
+        }
+    }
+    mean_se(c, n, res);
+    if (C) memcpy(C, c, sizeof(double) * n);
+    if (ex) memcpy(ex, e, sizeof(int32_t) * n);
+    if (!yout) free(y);
+    free(c);
+    free(e);
+    return nf;
+}
+
+/* Out-of-sample estimate: the exercise rule of a fitted beta [M][nf] applied
+ * to independent paths (stream `tag`): each path exercises at the first date
+ * j < M where it is in the money, the row of beta is not NaN and
+ * e^{-r t_j} f >= psi . beta_j, else at t_M when in the money. res = {price,
+ * std_err}; Y [n] and ex [n] optional. */
+int orc_lsm_oos(int d, const double *S0, const double *sigma, const double *L, double r,
+                double q, double T, int kind, double K, int M, int spd, int deg,
+                const double *beta, uint64_t seed, uint32_t tag, uint64_t path0, uint64_t n,
+                double *res, double *Y, int32_t *ex)
+{
+    int idx[64][3];
+    if (d < 1 || d > 4 || M < 1 || spd < 1 || n < 1 || kind < 1 || kind > 3) return -1;
+    const int nf = lsm_features(d, deg, kind, idx);
+    if (nf > LSM_MAXB - 1) return -1;
+    double *y = (double *)malloc(sizeof(double) * n * (size_t)M * d);
+    double *v = (double *)malloc(sizeof(double) * n);
+    lsm_paths(d, S0, sigma, L, r, q, T, K, M, spd, seed, tag, path0, n, y);
+    for (uint64_t p = 0; p < n; ++p) {
+        int e = 0;
+        double val = 0.0;
+        for (int j = 1; j <= M; ++j) {
+            const double *yp = y + (p * M + (j - 1)) * d;
+            const double f = lsm_payoff(kind, d, yp);
+            if (!(f > 0.0)) continue;
+            const double dj = exp(-r * T * j / M);
+            if (j == M) {
+                e = M;
+                val = dj * K * f;
+                break;
+            }
+            if (isnan(beta[(j - 1) * nf])) continue;
+            double psi[LSM_MAXB], h = 0.0;
+            lsm_psi(d, nf, idx, yp, f, psi);
+            for (int u = 0; u < nf; ++u) h += psi[u] * beta[(j - 1) * nf + u];
+            if (dj * K * f >= h) {
+                e = j;
+                val = dj * K * f;
+                break;
+            }
+        }
+        v[p] = val;
+        if (ex) ex[p] = e;
+    }
+    mean_se(v, n, res);
+    if (Y) memcpy(Y, v, sizeof(double) * n);
+    free(y);
+    free(v);
+    return nf;
+}
+
+/* Bermudan price on a binomial lattice (Cox-Ross-Rubinstein), an independent
+ * route to the value LSM estimates: per asset u = e^{sigma sqrt(h)}, 1/u, up
+ * probability (e^{(r-q)h} - 1/u) / (u - 1/u), h = T / (M nt); for d = 2 the
+ * two assets are independent and the lattice is the product of their trees.
+ * Backward induction discounts by e^{-rh} per step and takes the maximum
+ * with the payoff at the steps j nt (j = 1..M). d = 1 or 2; -1 otherwise. */
+double orc_lsm_lattice(int d, const double *S0, const double *sigma, double r, double q,
+                       double T, int kind, double K, int M, int nt)
+{
+    if (d < 1 || d > 2 || M < 1 || nt < 1 || kind < 1 || kind > 3) return -1.0;
+    const int N = M * nt;
+    const double h = T / N, disc = exp(-r * h);
+    double u[2], pu[2];
+    for (int a = 0; a < d; ++a) {
+        u[a] = exp(sigma[a] * sqrt(h));
+        pu[a] = (exp((r - q) * h) - 1.0 / u[a]) / (u[a] - 1.0 / u[a]);
+    }
+    const size_t W = (size_t)N + 1;
+    double *V = (double *)malloc(sizeof(double) * (d == 2 ? W * W : W));
+    double y[2];
+    /* node (i1, i2) at step n: S_a = S0_a u_a^(2 i_a - n) */
+    for (size_t i1 = 0; i1 <= (size_t)N; ++i1) {
+        y[0] = S0[0] / K * pow(u[0], 2.0 * (double)i1 - N);
+        if (d == 1) {
+            V[i1] = K * lsm_payoff(kind, 1, y);
+            continue;
+        }
+        for (size_t i2 = 0; i2 <= (size_t)N; ++i2) {
+            y[1] = S0[1] / K * pow(u[1], 2.0 * (double)i2 - N);
+            V[i1 * W + i2] = K * lsm_payoff(kind, 2, y);
+        }
+    }
+    for (int n = N - 1; n >= 0; --n) {
+        const int ex_step = (n > 0 && n % nt == 0);
+        for (int i1 = 0; i1 <= n; ++i1) {
+            if (d == 1) {
+                double v = disc * (pu[0] * V[i1 + 1] + (1.0 - pu[0]) * V[i1]);
+                if (ex_step) {
+                    y[0] = S0[0] / K * pow(u[0], 2.0 * i1 - n);
+                    const double f = K * lsm_payoff(kind, 1, y);
+                    if (f > v) v = f;
+                }
+                V[i1] = v;
+                continue;
+            }
+            for (int i2 = 0; i2 <= n; ++i2) {
+                const double up = pu[0] * (pu[1] * V[(i1 + 1) * W + i2 + 1]
+                                           + (1.0 - pu[1]) * V[(i1 + 1) * W + i2]);
+                const double dn = (1.0 - pu[0]) * (pu[1] * V[i1 * W + i2 + 1]
+                                                   + (1.0 - pu[1]) * V[i1 * W + i2]);
+                double v = disc * (up + dn);
+                if (ex_step) {
+                    y[0] = S0[0] / K * pow(u[0], 2.0 * i1 - n);
+                    y[1] = S0[1] / K * pow(u[1], 2.0 * i2 - n);
+                    const double f = K * lsm_payoff(kind, 2, y);
+                    if (f > v) v = f;
+                }
+                V[i1 * W + i2] = v;
+            }
+        }
+    }
+    const double out = V[0];
+    free(V);
+    return out;
+}

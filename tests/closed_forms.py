@@ -145,3 +145,27 @@ def short_calls_var_cvar(S0, mu, sigma, T, strikes, qty, premium, alpha):
     fs = norm.pdf(z) / (s * st)
     f_pnl = fs / abs(sum(qty))
     return var, cvar, f_pnl
+
+
+# European options with a continuous dividend yield q (Merton) -------------
+def bs_call_div(S0, K, r, q, sigma, T):
+    """Call on a stock paying dividend yield q: ln S_T ~ N(ln S0 + (r - q -
+    sigma^2/2) T, sigma^2 T) under the pricing measure."""
+    return lognormal_call(math.log(S0) + (r - q - 0.5 * sigma * sigma) * T, sigma * sigma * T,
+                          K, math.exp(-r * T))
+
+
+def bs_put_div(S0, K, r, q, sigma, T):
+    """Put by put-call parity: P = C - S0 e^{-qT} + K e^{-rT}."""
+    return bs_call_div(S0, K, r, q, sigma, T) - S0 * math.exp(-q * T) + K * math.exp(-r * T)
+
+
+def max_call_independent(S0, sigma, r, q, T, K):
+    """e^{-rT} E[(max(S_1, S_2) - K)+] for two independent lognormal assets
+    with dividend yield q: E[(M - K)+] = int_K^inf P(M > x) dx and
+    P(M > x) = 1 - F_1(x) F_2(x)."""
+    def F(x, a):
+        m = math.log(S0[a]) + (r - q - 0.5 * sigma[a] ** 2) * T
+        return norm.cdf((math.log(x) - m) / (sigma[a] * math.sqrt(T)))
+    v, _ = integrate.quad(lambda x: 1.0 - F(x, 0) * F(x, 1), K, np.inf, limit=400)
+    return math.exp(-r * T) * v
