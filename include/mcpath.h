@@ -22,7 +22,8 @@
  *   2 learned-hedge training set, tag + 16 l level l of a multilevel
  *   estimate; tag + 5 carries the Brownian-bridge uniforms of the
  *   continuously monitored barrier, tag + 6 the digital shifts of the
- *   randomised quasi-Monte Carlo replicates.
+ *   randomised quasi-Monte Carlo replicates, tag + 7 the fresh paths of
+ *   the out-of-sample Longstaff-Schwartz estimate.
  *
  * Conventions for every entry point:
  *   - Returns an mc_status; no exception or signal crosses the ABI.
@@ -387,6 +388,85 @@ typedef struct {
 mc_status mc_price_qmc(mc_context *ctx, const mc_model *model, const mc_payoff *payoff,
                        uint64_t n_points, uint32_t n_steps, uint64_t seed,
                        uint32_t n_replicates, const mc_options *opts, mc_qmc_result *out);
+
+/* Longstaff-Schwartz pricing of a Bermudan option (chained least-squares
+ * regressions for callable options, Sec. II-A.3; the American max-option
+ * experiment of Sec. VI-C). Model MC_GBM (dim 1) or MC_GBM_BASKET with dim
+ * 1..4 (S0, sigma, corr); every asset pays the continuous dividend yield
+ * spec->dividend, so it drifts at r - q under the pricing measure. Paths are
+ * simulated by log-Euler (steps_per_date steps between consecutive dates;
+ * step i uses normals i dim + a) and may be exercised at the n_dates dates
+ * t_j = j T / n_dates, j = 1..n_dates. Payoff f, with y_a = S_a / K and
+ * equal weights 1/dim:
+ *     MC_LSM_MAX_CALL    (max_a S_a - K)+
+ *     MC_LSM_BASKET_PUT  (K - mean_a S_a)+
+ *     MC_LSM_BASKET_CALL (mean_a S_a - K)+
+ * Every path carries a discounted cash flow C, first e^{-rT} f(t_M). For
+ * j = M-1 .. 1 the cash flows of the paths in the money at t_j are
+ * regressed on the features of y(t_j) by least squares (Cholesky
+ * factorisation of the FP64 Gram matrix); a path in the money whose
+ * discounted exercise value e^{-r t_j} f is at least the fitted
+ * continuation exercises, C = e^{-r t_j} f. price = mean of C (t = 0 is not
+ * an exercise date). Features: all monomials of y_1..y_dim of total degree
+ * <= spec->degree (1..3), by degree, then by the nondecreasing index tuple,
+ * and f / K last for the max-call with dim >= 2; at most
+ * MC_LSM_MAX_FEATURES. A date with fewer in-the-money paths than features,
+ * or a Cholesky pivot <= 1e-12 times its diagonal entry, gets no regression
+ * and no exercise (its beta row is NaN, beta_valid 0). The out-of-sample
+ * estimate applies the fitted rule to n_paths_oos independent paths of
+ * stream opts->stream_tag + 7 (a stopping rule, so its expectation is a
+ * lower bound on the option's value).
+ * Arithmetic: FP32 path state, stored exercise-date states and cash flows
+ * (device memory: n_dates * dim * n_paths * 4 + 5 n_paths bytes, owned by
+ * the context); FP64 features, Gram matrices, solves and decisions.
+ * Options: prec MC_FP32 only; stream_tag, path_offset, hip_stream; greeks
+ * 0. diag (optional) receives per-path results on the host.
+ * Errors: NULL model/spec/out, dim outside 1..4, unknown payoff, K or
+ * dividend not finite, K <= 0, n_dates outside 1..MC_LSM_MAX_DATES,
+ * steps_per_date 0, degree outside 1..3, n_paths < 2 ->
+ * MC_ERR_INVALID_ARG; more than MC_LSM_MAX_FEATURES features, another
+ * precision, greeks -> MC_ERR_UNSUPPORTED; a correlation that is not
+ * positive definite -> MC_ERR_NOT_PD. */
+#define MC_LSM_MAX_DATES 64
+#define MC_LSM_MAX_FEATURES 11
+typedef enum {
+    MC_LSM_MAX_CALL = 1, MC_LSM_BASKET_PUT = 2, MC_LSM_BASKET_CALL = 3
+} mc_lsm_payoff;
+
+typedef struct {
+    mc_lsm_payoff payoff;
+    double K;                  /* strike, > 0 */
+    double dividend;           /* continuous dividend yield q of every asset */
+    uint32_t n_dates;          /* exercise dates M, 1..MC_LSM_MAX_DATES */
+    uint32_t steps_per_date;   /* Euler steps between consecutive dates, >= 1 */
+    uint32_t degree;           /* total degree of the monomial features, 1..3 */
+    uint64_t n_paths_oos;      /* fresh paths for the out-of-sample estimate; 0 = none */
+} mc_lsm_spec;
+
+typedef struct {
+    double price, std_err;             /* in-sample estimate (mean of C) */
+    double price_oos, std_err_oos;     /* out-of-sample estimate; NaN when not run */
+    double european, european_se;      /* exercise at t_M only, same paths */
+    uint32_t n_features;
+    double beta[MC_LSM_MAX_DATES][MC_LSM_MAX_FEATURES];  /* row j-1: date j */
+    int beta_valid[MC_LSM_MAX_DATES];
+    uint64_t n_itm[MC_LSM_MAX_DATES];  /* paths in the money at date j (row j-1) */
+    uint64_t n_paths, n_paths_oos;
+    double sim_ms;                     /* path simulation and storage */
+    double regress_ms;                 /* backward pass: solves and updates */
+    double oos_ms;                     /* out-of-sample paths */
+} mc_lsm_result;
+
+typedef struct {
+    double *cash_flow;          /* host [n_paths]: C of each in-sample path */
+    int32_t *exercise_date;     /* host [n_paths]: j of the exercise, 0 = never */
+    double *oos_value;          /* host [n_paths_oos]: discounted value of each fresh path */
+    int32_t *oos_exercise_date; /* host [n_paths_oos] */
+} mc_lsm_paths;
+
+mc_status mc_price_lsm(mc_context *ctx, const mc_model *model, const mc_lsm_spec *spec,
+                       uint64_t n_paths, uint64_t seed, const mc_options *opts,
+                       mc_lsm_result *out, const mc_lsm_paths *diag);
 
 /* Raw Philox4x32-10 blocks of sampled (path, block) pairs and the normals
  * of one path, computed by the same device functions the path kernels use

@@ -22,7 +22,9 @@ from ._abi import (MC_ADJ_FULL, MC_ADJ_FWD, MC_ADJ_REV, MC_ASIAN_ARITH_CALL, MC_
                    MC_CV_NONE, MC_ERR_DEVICE, MC_ERR_INVALID_ARG, MC_ERR_NO_DEVICE,
                    MC_ERR_NOT_PD, MC_ERR_OOM, MC_ERR_UNSUPPORTED, MC_ERR_WORKSPACE, MC_EULER_S,
                    MC_EURO_CALL, MC_FP16_GEMM, MC_FP32, MC_FP64, MC_GBM, MC_GBM_BASKET,
-                   MC_GREEK_DELTA, MC_GREEK_VEGA, MC_HESTON, MC_LOG_EULER, MC_MLMC_MAX_LEVELS,
+                   MC_GREEK_DELTA, MC_GREEK_VEGA, MC_HESTON, MC_LOG_EULER, MC_LSM_BASKET_CALL,
+                   MC_LSM_BASKET_PUT, MC_LSM_MAX_CALL, MC_LSM_MAX_DATES, MC_LSM_MAX_FEATURES,
+                   MC_MLMC_MAX_LEVELS,
                    MC_MAX_STRIKES, MC_MLP_NPARAM, MC_OK, MC_QMC_MAX_REPLICATES,
                    MC_UO_BARRIER_CALL, MC_UO_BRIDGE_CALL)
 
@@ -32,6 +34,7 @@ __all__ = [n for n in dir(_abi) if n.startswith("MC_")] + [
     "mc_philox_words", "mc_normals", "mc_path_channels", "mc_path_channel_name",
     "mc_workspace_bytes", "mc_adjoint_ckpt_bytes", "mc_status_str", "mc_last_error",
     "mc_price_mlmc", "mc_mlmc_allocate", "Level", "mc_risk", "mc_price_qmc", "PathwisePrice",
+    "LsmSpec", "mc_price_lsm",
     "PreparedPriceMulti"]
 
 
@@ -399,6 +402,60 @@ def mc_price_qmc(ctx: Context, model: Model, payoff: Payoff, n_points: int, n_st
            "replicate_geo": list(res.replicate_geo[:R]), "kernel_ms": res.kernel_ms}
     if mm.path_buf is not None:
         out["path_values"] = mm.path_buf
+    return out
+
+
+@dataclass
+class LsmSpec:
+    """Bermudan contract and regression of mc_price_lsm."""
+    payoff: int = MC_LSM_MAX_CALL
+    K: float = 100.0
+    dividend: float = 0.0
+    n_dates: int = 9
+    steps_per_date: int = 1
+    degree: int = 2
+    n_paths_oos: int = 0
+
+
+def mc_price_lsm(ctx: Context, model: Model, spec: LsmSpec, n_paths: int, seed: int,
+                 opts: Options | None = None, want_paths: bool = False) -> dict:
+    """Longstaff-Schwartz price of a Bermudan option (mc_price_lsm): the
+    in-sample and out-of-sample estimates, the regression coefficients of
+    every date and, with want_paths, per-path cash flows and exercise dates."""
+    payoff = Payoff(kind=MC_EURO_CALL, K=spec.K)
+    mm = _Marshal(model, payoff, opts, n_paths)
+    torch = _torch()
+    if torch is not None:
+        mm.co.hip_stream = torch.cuda.current_stream(ctx.device).cuda_stream
+    cs = _abi.McLsmSpec(spec.payoff, spec.K, spec.dividend, spec.n_dates, spec.steps_per_date,
+                        spec.degree, spec.n_paths_oos)
+    res = _abi.McLsmResult()
+    diag = None
+    bufs = {}
+    if want_paths:
+        bufs = {"cash_flow": np.zeros(n_paths), "exercise_date": np.zeros(n_paths, np.int32),
+                "oos_value": np.zeros(spec.n_paths_oos),
+                "oos_exercise_date": np.zeros(spec.n_paths_oos, np.int32)}
+        diag = _abi.McLsmPaths(
+            bufs["cash_flow"].ctypes.data_as(C.POINTER(C.c_double)),
+            bufs["exercise_date"].ctypes.data_as(C.POINTER(C.c_int32)),
+            bufs["oos_value"].ctypes.data_as(C.POINTER(C.c_double)) if spec.n_paths_oos else None,
+            bufs["oos_exercise_date"].ctypes.data_as(C.POINTER(C.c_int32))
+            if spec.n_paths_oos else None)
+    st = _abi.load().mc_price_lsm(ctx.handle, C.byref(mm.cm), C.byref(cs), n_paths, seed,
+                                  C.byref(mm.co), C.byref(res),
+                                  C.byref(diag) if diag is not None else None)
+    _check(ctx, st)
+    nf, M = res.n_features, spec.n_dates
+    out = {"price": res.price, "std_err": res.std_err, "price_oos": res.price_oos,
+           "std_err_oos": res.std_err_oos, "european": res.european,
+           "european_se": res.european_se, "n_features": nf,
+           "beta": np.array([[res.beta[j][k] for k in range(nf)] for j in range(M)]),
+           "beta_valid": np.array(res.beta_valid[:M], np.int32),
+           "n_itm": np.array(res.n_itm[:M], np.int64), "n_paths": res.n_paths,
+           "n_paths_oos": res.n_paths_oos, "sim_ms": res.sim_ms, "regress_ms": res.regress_ms,
+           "oos_ms": res.oos_ms}
+    out.update(bufs)
     return out
 
 

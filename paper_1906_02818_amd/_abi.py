@@ -25,6 +25,9 @@ MC_MLMC_MAX_LEVELS = 8
 MC_MAX_STRIKES = 8
 MC_QMC_MAX_REPLICATES = 64
 MC_COUPLE_NONE, MC_COUPLE_PRECISION, MC_COUPLE_TIME = 0, 1, 2
+MC_LSM_MAX_DATES = 64
+MC_LSM_MAX_FEATURES = 11
+MC_LSM_MAX_CALL, MC_LSM_BASKET_PUT, MC_LSM_BASKET_CALL = 1, 2, 3
 
 _dp = C.POINTER(C.c_double)
 _fp = C.POINTER(C.c_float)
@@ -97,6 +100,29 @@ class McQmcResult(C.Structure):
                 ("kernel_ms", C.c_double)]
 
 
+class McLsmSpec(C.Structure):
+    _fields_ = [("payoff", C.c_int), ("K", C.c_double), ("dividend", C.c_double),
+                ("n_dates", C.c_uint32), ("steps_per_date", C.c_uint32), ("degree", C.c_uint32),
+                ("n_paths_oos", C.c_uint64)]
+
+
+class McLsmResult(C.Structure):
+    _fields_ = [("price", C.c_double), ("std_err", C.c_double), ("price_oos", C.c_double),
+                ("std_err_oos", C.c_double), ("european", C.c_double),
+                ("european_se", C.c_double), ("n_features", C.c_uint32),
+                ("beta", (C.c_double * MC_LSM_MAX_FEATURES) * MC_LSM_MAX_DATES),
+                ("beta_valid", C.c_int * MC_LSM_MAX_DATES),
+                ("n_itm", C.c_uint64 * MC_LSM_MAX_DATES),
+                ("n_paths", C.c_uint64), ("n_paths_oos", C.c_uint64), ("sim_ms", C.c_double),
+                ("regress_ms", C.c_double), ("oos_ms", C.c_double)]
+
+
+class McLsmPaths(C.Structure):
+    _fields_ = [("cash_flow", C.POINTER(C.c_double)), ("exercise_date", C.POINTER(C.c_int32)),
+                ("oos_value", C.POINTER(C.c_double)),
+                ("oos_exercise_date", C.POINTER(C.c_int32))]
+
+
 class McAdamCfg(C.Structure):
     _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
                 ("eps", C.c_double), ("steps", C.c_uint32), ("batch", C.c_uint64),
@@ -138,6 +164,8 @@ SIGNATURES = {
                           C.c_uint64, _P(McOptions), _P(McRiskResult)]),
     "mc_price_qmc": (C.c_int, [C.c_void_p, _P(McModel), _P(McPayoff), C.c_uint64, C.c_uint32,
                                C.c_uint64, C.c_uint32, _P(McOptions), _P(McQmcResult)]),
+    "mc_price_lsm": (C.c_int, [C.c_void_p, _P(McModel), _P(McLsmSpec), C.c_uint64, C.c_uint64,
+                               _P(McOptions), _P(McLsmResult), _P(McLsmPaths)]),
     "mc_status_str": (C.c_char_p, [C.c_int]),
     "mc_last_error": (C.c_char_p, [C.c_void_p]),
 }

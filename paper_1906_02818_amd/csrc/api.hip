@@ -5,6 +5,7 @@
 // the kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -37,6 +38,11 @@ struct mc_context {
   // [qmc_dims][32]) followed by one replicate's shifts [qmc_dims].
   uint32_t* qmc_buf = nullptr;
   uint32_t qmc_dims = 0;
+  // Longstaff-Schwartz: stored exercise-date states, cash flows and the
+  // regression workspace of the last call (device, grown on demand).
+  void* lsm_buf = nullptr;
+  size_t lsm_bytes = 0;
+  hipEvent_t ev2 = nullptr, ev3 = nullptr;
 };
 
 namespace {
@@ -1026,6 +1032,28 @@ mc_status get_mlmc_buf(mc_context* ctx, size_t bytes, char** base) {
   return MC_OK;
 }
 
+mc_status get_lsm_buf(mc_context* ctx, size_t bytes, char** base) {
+  if (ctx->lsm_bytes < bytes) {
+    if (ctx->lsm_buf) {
+      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      HIP_TRY(ctx, hipFree(ctx->lsm_buf));
+      ctx->lsm_buf = nullptr;
+      ctx->lsm_bytes = 0;
+    }
+    HIP_TRY(ctx, hipMalloc(&ctx->lsm_buf, bytes));
+    ctx->lsm_bytes = bytes;
+  }
+  *base = (char*)ctx->lsm_buf;
+  return MC_OK;
+}
+
+// Mean and standard error from (n, sum, sum of squares).
+void moments_mean_se(double n, double s1, double s2, double* mean, double* se) {
+  *mean = s1 / n;
+  const double v = n > 1 ? std::max(s2 - s1 * s1 / n, 0.0) / (n - 1) : NAN;
+  *se = std::sqrt(v / n);
+}
+
 constexpr uint64_t kMlmcChunk = 1ull << 20;
 
 }  // namespace
@@ -1050,7 +1078,8 @@ mc_status mc_create(mc_context** out, int device) {
   mc_context* ctx = new mc_context();
   ctx->device = device;
   if (hipSetDevice(device) != hipSuccess || hipStreamCreate(&ctx->stream) != hipSuccess ||
-      hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
+      hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess ||
+      hipEventCreate(&ctx->ev2) != hipSuccess || hipEventCreate(&ctx->ev3) != hipSuccess) {
     mc_destroy(ctx);
     return MC_ERR_DEVICE;
   }
@@ -1067,6 +1096,9 @@ mc_status mc_destroy(mc_context* ctx) {
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  if (ctx->ev2) (void)hipEventDestroy(ctx->ev2);
+  if (ctx->ev3) (void)hipEventDestroy(ctx->ev3);
+  if (ctx->lsm_buf) (void)hipFree(ctx->lsm_buf);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return MC_OK;
@@ -1746,6 +1778,211 @@ mc_status mc_cv_train(mc_context* ctx, const mc_model* m, const mc_payoff* f, ui
   HIP_TRY(ctx, hipStreamSynchronize(s));
   if (loss_log)
     for (uint32_t t = 0; t < cfg->steps; ++t) loss_log[t] = (float)loss_from_moments(&log[(size_t)t * n_mom]);
+  return MC_OK;
+}
+
+mc_status mc_price_lsm(mc_context* ctx, const mc_model* m, const mc_lsm_spec* sp,
+                       uint64_t n_paths, uint64_t seed, const mc_options* opts,
+                       mc_lsm_result* out, const mc_lsm_paths* diag) {
+  if (!ctx) return MC_ERR_INVALID_ARG;
+  if (!m || !sp || !out) return fail(ctx, MC_ERR_INVALID_ARG, "NULL argument");
+  const mc_options o = opts ? *opts : defaults();
+  if (m->kind != MC_GBM && m->kind != MC_GBM_BASKET)
+    return fail(ctx, MC_ERR_UNSUPPORTED, "Longstaff-Schwartz runs on GBM assets");
+  const uint32_t d = m->dim;
+  if (d < 1 || d > (uint32_t)kLsmMaxD || (m->kind == MC_GBM && d != 1))
+    return fail(ctx, MC_ERR_INVALID_ARG, "dim must be 1..%d (1 for MC_GBM)", kLsmMaxD);
+  if (n_paths < 2 || n_paths > (1ull << 32))
+    return fail(ctx, MC_ERR_INVALID_ARG, "n_paths must be in 2..2^32");
+  if (!finite_pos(m->T)) return fail(ctx, MC_ERR_INVALID_ARG, "T must be finite and > 0");
+  if (!std::isfinite(m->r)) return fail(ctx, MC_ERR_INVALID_ARG, "r must be finite");
+  if (!m->S0 || !m->sigma) return fail(ctx, MC_ERR_INVALID_ARG, "S0 and sigma are required");
+  for (uint32_t a = 0; a < d; ++a) {
+    if (!finite_pos(m->S0[a])) return fail(ctx, MC_ERR_INVALID_ARG, "S0[%u] must be > 0", a);
+    if (!finite_nonneg(m->sigma[a])) return fail(ctx, MC_ERR_INVALID_ARG, "sigma[%u] invalid", a);
+  }
+  if (sp->payoff != MC_LSM_MAX_CALL && sp->payoff != MC_LSM_BASKET_PUT &&
+      sp->payoff != MC_LSM_BASKET_CALL)
+    return fail(ctx, MC_ERR_INVALID_ARG, "unknown payoff");
+  if (!finite_pos(sp->K)) return fail(ctx, MC_ERR_INVALID_ARG, "K must be finite and > 0");
+  if (!std::isfinite(sp->dividend)) return fail(ctx, MC_ERR_INVALID_ARG, "dividend not finite");
+  const uint32_t M = sp->n_dates, spd = sp->steps_per_date;
+  if (M < 1 || M > (uint32_t)kLsmMaxDates)
+    return fail(ctx, MC_ERR_INVALID_ARG, "n_dates must be in 1..%d", kLsmMaxDates);
+  if (spd < 1) return fail(ctx, MC_ERR_INVALID_ARG, "steps_per_date must be >= 1");
+  if ((uint64_t)M * spd * d / 4 >= (1ull << 32))
+    return fail(ctx, MC_ERR_INVALID_ARG, "more than 2^34 normals per path");
+  if (sp->degree < 1 || sp->degree > 3)
+    return fail(ctx, MC_ERR_INVALID_ARG, "degree must be in 1..3");
+  if (sp->n_paths_oos == 1 || sp->n_paths_oos > (1ull << 36))
+    return fail(ctx, MC_ERR_INVALID_ARG, "n_paths_oos must be 0 or in 2..2^36");
+  const uint32_t pay_feat = sp->payoff == MC_LSM_MAX_CALL && d >= 2 ? 1u : 0u;
+  const uint32_t nf = lsm_n_features(d, sp->degree, pay_feat);
+  if (nf == 0 || nf > (uint32_t)kLsmMaxFeat)
+    return fail(ctx, MC_ERR_UNSUPPORTED, "%u features; at most %d", nf, kLsmMaxFeat);
+  if (o.prec != MC_FP32) return fail(ctx, MC_ERR_UNSUPPORTED, "Longstaff-Schwartz runs in MC_FP32");
+  if (o.greeks) return fail(ctx, MC_ERR_UNSUPPORTED, "Longstaff-Schwartz carries no greeks");
+  std::vector<double> L((size_t)d * d, 0.0);
+  if (d == 1) {
+    L[0] = 1.0;
+  } else {
+    if (!m->corr) return fail(ctx, MC_ERR_INVALID_ARG, "dim > 1 needs corr");
+    for (uint32_t i = 0; i < d; ++i)
+      for (uint32_t j = 0; j < d; ++j) {
+        const double c = m->corr[(size_t)i * d + j];
+        if (!std::isfinite(c)) return fail(ctx, MC_ERR_INVALID_ARG, "corr not finite");
+        if (c != m->corr[(size_t)j * d + i])
+          return fail(ctx, MC_ERR_INVALID_ARG, "corr not symmetric");
+      }
+    if (!host::cholesky((int)d, m->corr, L.data()))
+      return fail(ctx, MC_ERR_NOT_PD, "correlation matrix is not positive definite");
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, MC_ERR_DEVICE, "hipSetDevice");
+
+  LsmParams p{};
+  p.n_paths = n_paths;
+  p.path_offset = o.path_offset;
+  p.tag = o.stream_tag;
+  p.k0 = (uint32_t)seed;
+  p.k1 = (uint32_t)(seed >> 32);
+  p.d = d;
+  p.degree = sp->degree;
+  p.pay_feat = pay_feat;
+  p.kind = (uint32_t)sp->payoff;
+  p.n_dates = M;
+  p.spd = spd;
+  p.nf = nf;
+  const double dt = m->T / ((double)M * spd), sdt = std::sqrt(dt), il2 = 1.0 / std::log(2.0);
+  for (uint32_t a = 0; a < d; ++a) {
+    const double sg = m->sigma[a];
+    p.x0[a] = (float)std::log2(m->S0[a] / sp->K);
+    p.drift[a] = (float)((m->r - sp->dividend - 0.5 * sg * sg) * dt * il2);
+    for (uint32_t b = 0; b <= a; ++b) p.vol[a][b] = (float)(sg * sdt * L[(size_t)a * d + b] * il2);
+  }
+  for (uint32_t j = 0; j <= M; ++j) p.discK[j] = sp->K * std::exp(-m->r * m->T * j / M);
+
+  // Device memory: states [M][d][N], cash flows, exercise dates, block
+  // partials, one row of reduced moments per stage (simulation, M-1
+  // updates, out-of-sample), coefficients and their flags.
+  const uint64_t Noos = sp->n_paths_oos;
+  const bool want_cf = diag && diag->cash_flow, want_ex = diag && diag->exercise_date;
+  const bool want_ov = diag && diag->oos_value, want_oe = diag && diag->oos_exercise_date;
+  const size_t b_y = align256((size_t)M * d * n_paths * sizeof(float));
+  const size_t b_c = align256((size_t)n_paths * sizeof(float));
+  const size_t b_e = want_ex ? align256((size_t)n_paths) : 0;
+  const size_t b_p = align256((size_t)kLsmMaxMom * kLsmMaxBlocks * sizeof(double));
+  const size_t b_s = align256((size_t)(M + 1) * kLsmMaxMom * sizeof(double));
+  const size_t b_b = align256((size_t)M * kLsmMaxFeat * sizeof(double));
+  const size_t b_v = align256((size_t)M * sizeof(int));
+  const size_t b_ov = want_ov ? align256((size_t)Noos * sizeof(double)) : 0;
+  const size_t b_oe = want_oe ? align256((size_t)Noos) : 0;
+  char* base = nullptr;
+  mc_status st = get_lsm_buf(ctx, b_y + b_c + b_e + b_p + b_s + b_b + b_v + b_ov + b_oe, &base);
+  if (st != MC_OK) return st;
+  char* q = base;
+  p.y = (float*)q;                 q += b_y;
+  p.C = (float*)q;                 q += b_c;
+  p.ex = want_ex ? (uint8_t*)q : nullptr;  q += b_e;
+  p.partials = (double*)q;         q += b_p;
+  double* sums = (double*)q;       q += b_s;
+  double* beta = (double*)q;       q += b_b;
+  int* valid = (int*)q;            q += b_v;
+  double* oval = want_ov ? (double*)q : nullptr;  q += b_ov;
+  uint8_t* oex = want_oe ? (uint8_t*)q : nullptr;
+  p.beta = beta;
+  p.valid = valid;
+
+  hipStream_t s = stream_of(ctx, o);
+  const uint32_t nmom = lsm_n_moments(nf);
+  uint32_t nb = 0;
+  HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
+  HIP_TRY(ctx, launch_lsm_sim(p, s, &nb));
+  HIP_TRY(ctx, launch_final_reduce(p.partials, nb, nmom, sums, s));
+  HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));
+  // Stage t (1..M-1) solves date M-t from row t-1 and updates it; its moments
+  // (the Gram matrix of date M-t-1, or the price at t = M-1) go to row t.
+  for (uint32_t t = 1; t < M; ++t) {
+    const uint32_t j = M - t;
+    HIP_TRY(ctx, launch_lsm_solve(sums + (size_t)(t - 1) * kLsmMaxMom, nf, j, beta, valid, s));
+    HIP_TRY(ctx, launch_lsm_update(p, j, s, &nb));
+    HIP_TRY(ctx, launch_final_reduce(p.partials, nb, nmom, sums + (size_t)t * kLsmMaxMom, s));
+  }
+  HIP_TRY(ctx, hipEventRecord(ctx->ev2, s));
+  if (Noos) {
+    LsmParams po = p;
+    po.n_paths = Noos;
+    po.tag = o.stream_tag + 7;
+    po.y = nullptr;
+    po.C = nullptr;
+    po.ex = oex;
+    po.path_value = oval;
+    HIP_TRY(ctx, launch_lsm_oos(po, s, &nb));
+    HIP_TRY(ctx, launch_final_reduce(p.partials, nb, 2, sums + (size_t)M * kLsmMaxMom, s));
+  }
+  HIP_TRY(ctx, hipEventRecord(ctx->ev3, s));
+  std::vector<double> h_sums((size_t)(M + 1) * kLsmMaxMom), h_beta((size_t)M * kLsmMaxFeat);
+  std::vector<int> h_valid(M);
+  HIP_TRY(ctx, hipMemcpyAsync(h_sums.data(), sums, h_sums.size() * 8, hipMemcpyDeviceToHost, s));
+  if (M > 1) {
+    HIP_TRY(ctx, hipMemcpyAsync(h_beta.data(), beta, (size_t)(M - 1) * kLsmMaxFeat * 8,
+                                hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(h_valid.data(), valid, (size_t)(M - 1) * sizeof(int),
+                                hipMemcpyDeviceToHost, s));
+  }
+  std::vector<float> h_c(want_cf ? n_paths : 0);
+  std::vector<uint8_t> h_e(want_ex ? n_paths : 0), h_oe(want_oe ? Noos : 0);
+  if (want_cf)
+    HIP_TRY(ctx, hipMemcpyAsync(h_c.data(), p.C, n_paths * 4, hipMemcpyDeviceToHost, s));
+  if (want_ex) HIP_TRY(ctx, hipMemcpyAsync(h_e.data(), p.ex, n_paths, hipMemcpyDeviceToHost, s));
+  if (want_ov)
+    HIP_TRY(ctx, hipMemcpyAsync(diag->oos_value, oval, Noos * 8, hipMemcpyDeviceToHost, s));
+  if (want_oe) HIP_TRY(ctx, hipMemcpyAsync(h_oe.data(), oex, Noos, hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  float ms_sim = 0.f, ms_reg = 0.f, ms_oos = 0.f;
+  HIP_TRY(ctx, hipEventElapsedTime(&ms_sim, ctx->ev0, ctx->ev1));
+  HIP_TRY(ctx, hipEventElapsedTime(&ms_reg, ctx->ev1, ctx->ev2));
+  HIP_TRY(ctx, hipEventElapsedTime(&ms_oos, ctx->ev2, ctx->ev3));
+
+  mc_lsm_result r{};
+  const uint32_t ng = (nf + 1) * (nf + 2) / 2;
+  const double n = (double)n_paths;
+  const double* row0 = h_sums.data();
+  moments_mean_se(n, row0[ng], row0[ng + 1], &r.european, &r.european_se);
+  const double* last = h_sums.data() + (size_t)(M - 1) * kLsmMaxMom;
+  if (M == 1)
+    moments_mean_se(n, row0[ng], row0[ng + 1], &r.price, &r.std_err);
+  else
+    moments_mean_se(n, last[ng], last[ng + 1], &r.price, &r.std_err);
+  if (Noos) {
+    const double* ro = h_sums.data() + (size_t)M * kLsmMaxMom;
+    moments_mean_se((double)Noos, ro[0], ro[1], &r.price_oos, &r.std_err_oos);
+  } else {
+    r.price_oos = NAN;
+    r.std_err_oos = NAN;
+  }
+  r.n_features = nf;
+  for (uint32_t j = 0; j < (uint32_t)MC_LSM_MAX_DATES; ++j)
+    for (uint32_t k = 0; k < (uint32_t)MC_LSM_MAX_FEATURES; ++k) r.beta[j][k] = NAN;
+  for (uint32_t j = 1; j < M; ++j) {
+    r.beta_valid[j - 1] = h_valid[j - 1];
+    if (h_valid[j - 1])
+      for (uint32_t k = 0; k < nf; ++k) r.beta[j - 1][k] = h_beta[(size_t)(j - 1) * kLsmMaxFeat + k];
+    // The Gram matrix of date j was reduced into row M-1-j; entry 0 counts.
+    r.n_itm[j - 1] = (uint64_t)h_sums[(size_t)(M - 1 - j) * kLsmMaxMom];
+  }
+  r.n_itm[M - 1] = (uint64_t)row0[ng + 2];
+  r.n_paths = n_paths;
+  r.n_paths_oos = Noos;
+  r.sim_ms = ms_sim;
+  r.regress_ms = ms_reg;
+  r.oos_ms = ms_oos;
+  if (want_cf)
+    for (uint64_t i = 0; i < n_paths; ++i) diag->cash_flow[i] = h_c[i];
+  if (want_ex)
+    for (uint64_t i = 0; i < n_paths; ++i) diag->exercise_date[i] = h_e[i];
+  if (want_oe)
+    for (uint64_t i = 0; i < Noos; ++i) diag->oos_exercise_date[i] = h_oe[i];
+  *out = r;
   return MC_OK;
 }
 

@@ -140,6 +140,48 @@ hipError_t launch_tail_sum(const double* x, uint64_t n, const void* state, doubl
 // smallest value and the value itself.
 double select_key_to_value(uint64_t key);
 
+// ---- Longstaff-Schwartz regression (Bermudan options) ----
+// d <= 4 correlated GBM assets with dividend yield, log-Euler in the log2
+// domain: x_a = log2(S_a / K), so that y_a = S_a / K = exp2(x_a).
+constexpr int kLsmMaxD = 4, kLsmMaxDates = 64, kLsmMaxFeat = 11;
+// Moments per block: the upper triangle of u u^T, u = (features, cash flow),
+// then the sum and the sum of squares of the cash flow and the number of
+// paths in the money at the last date.
+constexpr int kLsmMaxMom = (kLsmMaxFeat + 1) * (kLsmMaxFeat + 2) / 2 + 3;
+constexpr uint32_t kLsmMaxBlocks = 2048;
+enum : uint32_t { LSM_MAX_CALL = 1, LSM_BASKET_PUT = 2, LSM_BASKET_CALL = 3 };
+struct LsmParams {
+  uint64_t n_paths, path_offset;
+  uint32_t tag, k0, k1;
+  uint32_t d, degree, pay_feat;  // pay_feat: f/K appended to the features
+  uint32_t kind, n_dates, spd;   // payoff, exercise dates, Euler steps per date
+  uint32_t nf;                   // number of features
+  float x0[kLsmMaxD];            // log2(S0_a / K)
+  float drift[kLsmMaxD];         // (r - q - sigma_a^2 / 2) dt / ln 2
+  float vol[kLsmMaxD][kLsmMaxD]; // sigma_a sqrt(dt) L_ab / ln 2 (lower triangle)
+  double discK[kLsmMaxDates + 1];// K e^{-r t_j}, j = 0..n_dates
+  float* y;                      // [n_dates][d][n_paths]: S_a(t_j) / K
+  float* C;                      // [n_paths] discounted cash flow
+  uint8_t* ex;                   // [n_paths] exercise date (0 = never), or nullptr
+  const double* beta;            // [n_dates][kLsmMaxFeat]
+  const int* valid;              // [n_dates]: 1 when date j has a regression
+  double* partials;              // [n_mom][n_blocks]
+  double* path_value;            // out-of-sample: [n_paths] values, or nullptr
+};
+// Moments the kernels of this feature set write (see kLsmMaxMom).
+uint32_t lsm_n_moments(uint32_t nf);
+uint32_t lsm_n_features(uint32_t d, uint32_t degree, uint32_t pay_feat);
+// Simulation of the stored paths (cash flows at t_M, Gram matrix of date
+// n_dates - 1 and the exercise-at-maturity moments), the update of date j
+// (exercise rule of date j, then the Gram matrix of date j - 1, or the
+// price moments when j = 1), the Cholesky solve of date j from the reduced
+// moments `sums`, and the out-of-sample estimate on fresh paths.
+hipError_t launch_lsm_sim(const LsmParams& p, hipStream_t s, uint32_t* n_blocks);
+hipError_t launch_lsm_update(const LsmParams& p, uint32_t j, hipStream_t s, uint32_t* n_blocks);
+hipError_t launch_lsm_solve(const double* sums, uint32_t nf, uint32_t j, double* beta, int* valid,
+                            hipStream_t s);
+hipError_t launch_lsm_oos(const LsmParams& p, hipStream_t s, uint32_t* n_blocks);
+
 // ---- Learned martingale control variate (Heston Asian) ----
 // Hedge network 4 -> 64 -> 64 -> 1 with tanh, run on MFMA for 32 paths per
 // wave. Host-packed per-lane fragments (see api.hip, pack_mlp):

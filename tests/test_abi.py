@@ -100,6 +100,24 @@ def test_qmc_struct_layout_matches_header(tmp_path):
     assert got == [C.sizeof(R), R.replicate_geo.offset, R.kernel_ms.offset]
 
 
+def test_lsm_struct_layout_matches_header(tmp_path):
+    src = str(tmp_path / "abi_lsm.c")
+    with open(src, "w") as f:
+        f.write('#include <stdio.h>\n#include <stddef.h>\n#include "mcpath.h"\n'
+                'int main(){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(mc_lsm_spec), '
+                'offsetof(mc_lsm_spec, n_paths_oos), sizeof(mc_lsm_result), '
+                'offsetof(mc_lsm_result, beta), offsetof(mc_lsm_result, n_itm), '
+                'offsetof(mc_lsm_result, oos_ms), sizeof(mc_lsm_paths), '
+                'offsetof(mc_lsm_paths, oos_exercise_date));}\n')
+    exe = src[:-2]
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+    got = [int(x) for x in subprocess.run([exe], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    S, R, P = _abi.McLsmSpec, _abi.McLsmResult, _abi.McLsmPaths
+    assert got == [C.sizeof(S), S.n_paths_oos.offset, C.sizeof(R), R.beta.offset,
+                   R.n_itm.offset, R.oos_ms.offset, C.sizeof(P), P.oos_exercise_date.offset]
+
+
 def test_mlmc_allocation_is_the_lagrange_optimum():
     # N_l proportional to sqrt(V_l / C_l), scaled so that sum V_l / N_l hits
     # the target variance; checked against a direct minimisation.

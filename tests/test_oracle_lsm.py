@@ -23,6 +23,7 @@ import pytest
 import oracle
 import synth
 from closed_forms import bs_call_div, bs_put_div, max_call_independent
+from lsm_basis import features as _feat, payoff as _payoff
 
 SEED = synth.SEED
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -72,29 +73,6 @@ def test_lattice_reproduces_the_papers_max_call_value():
 
 
 # ---- the estimator -----------------------------------------------------------
-def _features(y, f, d, degree, with_payoff):
-    """Monomials of total degree <= degree by degree, then by the
-    nondecreasing index tuple, and f/K for the max-call (numpy, per row)."""
-    cols = [np.ones(len(y))]
-    if degree >= 1:
-        cols += [y[:, a] for a in range(d)]
-    if degree >= 2:
-        cols += [y[:, a] * y[:, b] for a in range(d) for b in range(a, d)]
-    if degree >= 3:
-        cols += [y[:, a] * y[:, b] * y[:, c] for a in range(d) for b in range(a, d)
-                 for c in range(b, d)]
-    if with_payoff:
-        cols.append(f)
-    return np.stack(cols, 1)
-
-
-def _payoff(kind, y):
-    if kind == MAXC:
-        return np.maximum(y.max(1) - 1.0, 0.0)
-    m = y.mean(1)
-    return np.maximum(1.0 - m, 0.0) if kind == PUT else np.maximum(m - 1.0, 0.0)
-
-
 @pytest.mark.parametrize("kind,d,degree", [(MAXC, 2, 2), (PUT, 1, 3), (MAXC, 3, 1)])
 def test_each_regression_is_least_squares_on_the_in_the_money_paths(kind, d, degree):
     S0 = np.array([100.0, 105.0, 95.0][:d])
@@ -104,14 +82,13 @@ def test_each_regression_is_least_squares_on_the_in_the_money_paths(kind, d, deg
     r, q, T, K, M = 0.05, 0.08, 2.0, 100.0, 5
     o = oracle.lsm(S0, sig, L, r, q, T, kind, K, M, 2, degree, 4096, SEED, want_paths=True)
     y, beta = o["y"], o["beta"]
-    with_payoff = kind == MAXC and d >= 2
-    assert o["n_features"] == _features(y[:, 0], y[:, 0, 0], d, degree, with_payoff).shape[1]
+    assert o["n_features"] == _feat(y[:, 0], y[:, 0, 0], degree, kind).shape[1]
     # Rebuild the cash flows date by date from the oracle's own betas.
     c = math.exp(-r * T) * K * _payoff(kind, y[:, M - 1])
     for j in range(M - 1, 0, -1):
         f = _payoff(kind, y[:, j - 1])
         itm = f > 0
-        X = _features(y[itm, j - 1], f[itm], d, degree, with_payoff)
+        X = _feat(y[itm, j - 1], f[itm], degree, kind)
         want, *_ = np.linalg.lstsq(X, c[itm], rcond=None)
         assert np.allclose(beta[j - 1], want, rtol=1e-7, atol=1e-7 * np.abs(want).max())
         assert o["n_itm"][j - 1] == itm.sum()
