@@ -37,6 +37,7 @@ sys.path.insert(0, ROOT)
 N_CU, CLOCK_HZ, FMA_LANES_PER_CLK = 256, 2.4e9, 128
 ALU_PEAK_SLOTS = N_CU * CLOCK_HZ * FMA_LANES_PER_CLK      # 7.86e13 slots/s
 MFMA_PEAK = {"fp32": 157.3e12, "bf16": 2.5e15, "fp16": 2.5e15, "bf16x2": 2.5e15}
+HBM_PEAK = 8.0e12                                           # bytes/s
 
 # Issue cost of each instruction class on gfx950 in "slots": wave64 FMA
 # issues at the FP32 vector peak (2 per clock per CU). Costs are 2 divided
@@ -212,6 +213,7 @@ TRAFFIC_BYTES = {
     "gbm_path_kernel<float, asian|geo|uo, log-Euler>": 2.984e6,   # 2^24 paths x 252 steps
     "basket_kernel<8, bf16>": 3.392e6,                          # 2^20 paths x 100 steps
     "heston_adjoint_kernel<float, full, asian>": 9.389e8,       # 2^22 paths x 256 steps
+    "lsm_update_kernel<2, 2, 1>": 3.673e8,                      # 2^24 paths, mean of 8 dates
 }
 
 
@@ -478,9 +480,81 @@ def run_learned_cv(args, ctx, mc, synth, torch):
                  higher_is_better=False, time_to_1bp=out)
 
 
+# Bermudan call on the maximum of two assets (the LSM experiment of Sec. VI-C):
+# independent assets S0 = 100, sigma = 0.2, dividend yield 0.1, r = 0.05,
+# K = 100, T = 3, 9 exercise dates; 2^24 in-sample and 2^24 fresh paths.
+LSM = dict(S0=[100.0, 100.0], sigma=[0.2, 0.2], r=0.05, q=0.10, T=3.0, K=100.0, n_dates=9,
+           degree=2, n_paths=1 << 24, n_oos=1 << 24)
+PAPER_LSM_PRICE = 13.90   # the true price the paper quotes for this option
+
+
+def _lsm_update_bytes(N, M, d):
+    """Algorithmic HBM bytes of the M-1 update kernels: every date reads the
+    states of its own date and of the previous one (FP32, d assets) and the
+    cash flow; date 1 reads only its own states. Cash-flow writes (only the
+    exercising paths) are not counted."""
+    return N * ((M - 2) * (8 * d + 4) + (4 * d + 4))
+
+
+def lsm_cpu_baseline(c, n_paths=1 << 20):
+    """The FP64 oracle's Longstaff-Schwartz (in-sample regression and the
+    out-of-sample estimate on as many fresh paths) on a sample of the paths."""
+    import numpy as np
+    import oracle
+    t0 = time.perf_counter()
+    o = oracle.lsm(c["S0"], c["sigma"], np.eye(2), c["r"], c["q"], c["T"], 1, c["K"],
+                   c["n_dates"], 1, c["degree"], n_paths, 1234)
+    oracle.lsm_oos(c["S0"], c["sigma"], np.eye(2), c["r"], c["q"], c["T"], 1, c["K"],
+                   c["n_dates"], 1, c["degree"], o["beta"], n_paths, 1234, tag=7)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n_paths / dt, "unit": "paths/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_paths} of {c['n_paths']} in-sample paths plus {n_paths} fresh paths "
+                      f"(FP64 oracle), {dt:.1f} s"}
+
+
+def run_lsm(args, ctx, mc, synth, torch):
+    """Longstaff-Schwartz price of the two-asset Bermudan max-call: path
+    simulation with stored exercise-date states, 8 chained FP64 regressions
+    and the out-of-sample estimate, one mc_price_lsm call per step."""
+    import numpy as np
+    c = LSM
+    N, M, d = c["n_paths"], c["n_dates"], 2
+    model = mc.Model(kind=mc.MC_GBM_BASKET, S0=c["S0"], r=c["r"], T=c["T"], sigma=c["sigma"],
+                     corr=np.eye(2))
+    spec = mc.LsmSpec(payoff=mc.MC_LSM_MAX_CALL, K=c["K"], dividend=c["q"], n_dates=M,
+                      steps_per_date=1, degree=c["degree"], n_paths_oos=c["n_oos"])
+    ms, outs = _repeat(args, torch, lambda: mc.mc_price_lsm(ctx, model, spec, N, synth.SEED))
+    r = outs[-1]
+
+    def avg(k):
+        return sum(x[k] for x in outs) / len(outs)
+    upd = avg("update_ms")
+    kernel = "lsm_update_kernel<2, 2, 1>"
+    achieved = _lsm_update_bytes(N, M, d) / (upd * 1e-3)
+    roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK, "traffic": TRAFFIC_BYTES.get(kernel), "kernel": kernel,
+            "bytes_per_launch": _lsm_update_bytes(N, M, d) / (M - 1), "launches": M - 1}
+    line = _line(args, "paths/s", N / (ms * 1e-3), "paths/s", ms, "f32",
+                 {"workload": "Bermudan call on the max of two independent GBM assets (S0 100, "
+                              "sigma 0.2, dividend yield 0.1, r 0.05, K 100, T 3, 9 dates), "
+                              "Longstaff-Schwartz with degree-2 monomials and the payoff, "
+                              "2^24 in-sample + 2^24 out-of-sample paths", "n_paths": N,
+                  "n_paths_oos": c["n_oos"], "n_dates": M, "d": d},
+                 roof, sim_ms=avg("sim_ms"), regress_ms=avg("regress_ms"), update_ms=upd,
+                 oos_ms=avg("oos_ms"),
+                 lsm={"price": r["price"], "std_err": r["std_err"], "price_oos": r["price_oos"],
+                      "std_err_oos": r["std_err_oos"], "european": r["european"],
+                      "european_se": r["european_se"], "paper_true_price": PAPER_LSM_PRICE})
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = lsm_cpu_baseline(c)
+    return line
+
+
 WORKLOADS = {"asian_barrier": run_asian_barrier, "european": run_european, "basket": run_basket,
              "heston_adjoint": run_heston_adjoint, "learned_cv": run_learned_cv,
-             "mlmc_basket": run_mlmc_basket, "risk": run_risk, "qmc_basket": run_qmc_basket}
+             "mlmc_basket": run_mlmc_basket, "risk": run_risk, "qmc_basket": run_qmc_basket,
+             "lsm": run_lsm}
 
 
 def main():

@@ -417,8 +417,9 @@ mc_status mc_price_qmc(mc_context *ctx, const mc_model *model, const mc_payoff *
  * stream opts->stream_tag + 7 (a stopping rule, so its expectation is a
  * lower bound on the option's value).
  * Arithmetic: FP32 path state, stored exercise-date states and cash flows
- * (device memory: n_dates * dim * n_paths * 4 + 5 n_paths bytes, owned by
- * the context); FP64 features, Gram matrices, solves and decisions.
+ * (device memory: (n_dates - 1) * dim * n_paths * 4 + 5 n_paths bytes,
+ * owned by the context); FP64 features, Gram matrices, solves and
+ * decisions.
  * Options: prec MC_FP32 only; stream_tag, path_offset, hip_stream; greeks
  * 0. diag (optional) receives per-path results on the host.
  * Errors: NULL model/spec/out, dim outside 1..4, unknown payoff, K or
@@ -455,6 +456,7 @@ typedef struct {
     double sim_ms;                     /* path simulation and storage */
     double regress_ms;                 /* backward pass: solves and updates */
     double oos_ms;                     /* out-of-sample paths */
+    double update_ms;                  /* the n_dates - 1 update kernels alone */
 } mc_lsm_result;
 
 typedef struct {

@@ -454,7 +454,7 @@ def mc_price_lsm(ctx: Context, model: Model, spec: LsmSpec, n_paths: int, seed: 
            "beta_valid": np.array(res.beta_valid[:M], np.int32),
            "n_itm": np.array(res.n_itm[:M], np.int64), "n_paths": res.n_paths,
            "n_paths_oos": res.n_paths_oos, "sim_ms": res.sim_ms, "regress_ms": res.regress_ms,
-           "oos_ms": res.oos_ms}
+           "oos_ms": res.oos_ms, "update_ms": res.update_ms}
     out.update(bufs)
     return out
 

@@ -114,7 +114,7 @@ class McLsmResult(C.Structure):
                 ("beta_valid", C.c_int * MC_LSM_MAX_DATES),
                 ("n_itm", C.c_uint64 * MC_LSM_MAX_DATES),
                 ("n_paths", C.c_uint64), ("n_paths_oos", C.c_uint64), ("sim_ms", C.c_double),
-                ("regress_ms", C.c_double), ("oos_ms", C.c_double)]
+                ("regress_ms", C.c_double), ("oos_ms", C.c_double), ("update_ms", C.c_double)]
 
 
 class McLsmPaths(C.Structure):

@@ -43,6 +43,8 @@ struct mc_context {
   void* lsm_buf = nullptr;
   size_t lsm_bytes = 0;
   hipEvent_t ev2 = nullptr, ev3 = nullptr;
+  // Event pairs around each date's update kernel (created on first use).
+  std::vector<hipEvent_t> lsm_ev;
 };
 
 namespace {
@@ -1099,6 +1101,7 @@ mc_status mc_destroy(mc_context* ctx) {
   if (ctx->ev2) (void)hipEventDestroy(ctx->ev2);
   if (ctx->ev3) (void)hipEventDestroy(ctx->ev3);
   if (ctx->lsm_buf) (void)hipFree(ctx->lsm_buf);
+  for (hipEvent_t e : ctx->lsm_ev) (void)hipEventDestroy(e);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return MC_OK;
@@ -1861,14 +1864,16 @@ mc_status mc_price_lsm(mc_context* ctx, const mc_model* m, const mc_lsm_spec* sp
   }
   for (uint32_t j = 0; j <= M; ++j) p.discK[j] = sp->K * std::exp(-m->r * m->T * j / M);
 
-  // Device memory: states [M][d][N], cash flows, exercise dates, block
+  // Device memory: states [M-1][d][N] (t_M is used inside the simulation
+  // only), cash flows, exercise dates, block
   // partials, one row of reduced moments per stage (simulation, M-1
   // updates, out-of-sample), coefficients and their flags.
   const uint64_t Noos = sp->n_paths_oos;
   const bool want_cf = diag && diag->cash_flow, want_ex = diag && diag->exercise_date;
   const bool want_ov = diag && diag->oos_value, want_oe = diag && diag->oos_exercise_date;
-  const size_t b_y = align256((size_t)M * d * n_paths * sizeof(float));
-  const size_t b_c = align256((size_t)n_paths * sizeof(float));
+  p.ystride = (n_paths + 63) / 64 * 64;
+  const size_t b_y = align256((size_t)(M - 1) * d * p.ystride * sizeof(float));
+  const size_t b_c = align256((size_t)p.ystride * sizeof(float));
   const size_t b_e = want_ex ? align256((size_t)n_paths) : 0;
   const size_t b_p = align256((size_t)kLsmMaxMom * kLsmMaxBlocks * sizeof(double));
   const size_t b_s = align256((size_t)(M + 1) * kLsmMaxMom * sizeof(double));
@@ -1893,19 +1898,28 @@ mc_status mc_price_lsm(mc_context* ctx, const mc_model* m, const mc_lsm_spec* sp
   p.valid = valid;
 
   hipStream_t s = stream_of(ctx, o);
+  while (ctx->lsm_ev.size() < 2 * (size_t)kLsmMaxDates) {
+    hipEvent_t e = nullptr;
+    HIP_TRY(ctx, hipEventCreate(&e));
+    ctx->lsm_ev.push_back(e);
+  }
   const uint32_t nmom = lsm_n_moments(nf);
   uint32_t nb = 0;
   HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
   HIP_TRY(ctx, launch_lsm_sim(p, s, &nb));
-  HIP_TRY(ctx, launch_final_reduce(p.partials, nb, nmom, sums, s));
+  // Row 0: the simulation's moments; the Gram matrix in them is date M-1's.
+  HIP_TRY(ctx, launch_lsm_reduce_solve(p.partials, nb, nmom, sums, nf, M - 1, beta, valid, s));
   HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));
-  // Stage t (1..M-1) solves date M-t from row t-1 and updates it; its moments
-  // (the Gram matrix of date M-t-1, or the price at t = M-1) go to row t.
+  // Stage t (1..M-1) updates date j = M-t with the coefficients solved at
+  // stage t-1; its moments (the Gram matrix of date j-1, solved here, or the
+  // price at j = 1) go to row t.
   for (uint32_t t = 1; t < M; ++t) {
     const uint32_t j = M - t;
-    HIP_TRY(ctx, launch_lsm_solve(sums + (size_t)(t - 1) * kLsmMaxMom, nf, j, beta, valid, s));
+    HIP_TRY(ctx, hipEventRecord(ctx->lsm_ev[2 * t], s));
     HIP_TRY(ctx, launch_lsm_update(p, j, s, &nb));
-    HIP_TRY(ctx, launch_final_reduce(p.partials, nb, nmom, sums + (size_t)t * kLsmMaxMom, s));
+    HIP_TRY(ctx, hipEventRecord(ctx->lsm_ev[2 * t + 1], s));
+    HIP_TRY(ctx, launch_lsm_reduce_solve(p.partials, nb, nmom, sums + (size_t)t * kLsmMaxMom, nf,
+                                         j - 1, beta, valid, s));
   }
   HIP_TRY(ctx, hipEventRecord(ctx->ev2, s));
   if (Noos) {
@@ -1942,6 +1956,12 @@ mc_status mc_price_lsm(mc_context* ctx, const mc_model* m, const mc_lsm_spec* sp
   HIP_TRY(ctx, hipEventElapsedTime(&ms_sim, ctx->ev0, ctx->ev1));
   HIP_TRY(ctx, hipEventElapsedTime(&ms_reg, ctx->ev1, ctx->ev2));
   HIP_TRY(ctx, hipEventElapsedTime(&ms_oos, ctx->ev2, ctx->ev3));
+  double ms_upd = 0.0;
+  for (uint32_t t = 1; t < M; ++t) {
+    float e = 0.f;
+    HIP_TRY(ctx, hipEventElapsedTime(&e, ctx->lsm_ev[2 * t], ctx->lsm_ev[2 * t + 1]));
+    ms_upd += e;
+  }
 
   mc_lsm_result r{};
   const uint32_t ng = (nf + 1) * (nf + 2) / 2;
@@ -1976,6 +1996,7 @@ mc_status mc_price_lsm(mc_context* ctx, const mc_model* m, const mc_lsm_spec* sp
   r.sim_ms = ms_sim;
   r.regress_ms = ms_reg;
   r.oos_ms = ms_oos;
+  r.update_ms = ms_upd;
   if (want_cf)
     for (uint64_t i = 0; i < n_paths; ++i) diag->cash_flow[i] = h_c[i];
   if (want_ex)

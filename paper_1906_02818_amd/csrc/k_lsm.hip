@@ -4,13 +4,14 @@
 //
 // Data flow, all on one stream with no host round trip:
 //  1. lsm_sim_kernel simulates every path once (log-Euler per asset, one
-//     lane per path), stores S_a(t_j)/K at each exercise date in HBM as
-//     [date][asset][path] FP32 (coalesced across lanes), sets the cash flow
+//     lane per path), stores S_a(t_j)/K at each exercise date before t_M in
+//     HBM as [date][asset][path] FP32 (coalesced across lanes), sets the cash flow
 //     C = K e^{-rT} f(t_M)/K, and accumulates in FP64 the Gram matrix of date
 //     M-1: the upper triangle of u u^T, u = (features, C), over the paths in
 //     the money there, plus the moments of C (exercise at maturity only).
-//  2. For j = M-1 .. 1: lsm_solve_kernel factors date j's Gram matrix
-//     (Cholesky, FP64, one thread) into the regression coefficients; then
+//  2. For j = M-1 .. 1: the fixed-order reduction of date j's Gram matrix
+//     and lsm_solve_kernel (Cholesky, FP64, one thread's registers) give the
+//     regression coefficients; then
 //     lsm_update_kernel applies date j's exercise rule to every path and, in
 //     the same pass, accumulates the Gram matrix of date j-1 with the updated
 //     cash flows (or, at j = 1, the moments of the price). One read of the
@@ -148,7 +149,7 @@ __global__ __launch_bounds__(256) void lsm_sim_kernel(LsmParams p) {
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         y[a] = __builtin_amdgcn_exp2f(x[a]);
-        p.y[((size_t)(j - 1) * D + a) * N + i] = y[a];
+        if (j < M) p.y[((size_t)(j - 1) * D + a) * p.ystride + i] = y[a];  // t_M is not read back
       }
       if (j + 1 == M) {
 #pragma unroll
@@ -180,109 +181,140 @@ __global__ __launch_bounds__(256) void lsm_sim_kernel(LsmParams p) {
   block_reduce_moments<F::NMOM, 256>(acc, p.partials, gridDim.x);
 }
 
+__device__ __forceinline__ float lane_of(const float4& v, int u) {
+  return u == 0 ? v.x : u == 1 ? v.y : u == 2 ? v.z : v.w;
+}
+
+// Four consecutive paths per lane: 16-byte loads of each state row and of
+// the cash flows (rows are padded to a multiple of 64 floats).
 template <int D, int DEG, int PF>
 __global__ __launch_bounds__(256) void lsm_update_kernel(LsmParams p, uint32_t j) {
   using F = Feat<D, DEG, PF>;
   double acc[F::NMOM];
 #pragma unroll
   for (int m = 0; m < F::NMOM; ++m) acc[m] = 0.0;
-  const uint64_t N = p.n_paths;
+  const uint64_t N = p.n_paths, S = p.ystride;
   const bool valid = p.valid[j - 1] != 0;
   double beta[F::NF];
 #pragma unroll
   for (int k = 0; k < F::NF; ++k) beta[k] = p.beta[(size_t)(j - 1) * kLsmMaxFeat + k];
   const double dK = p.discK[j];
-  const float* yj = p.y + (size_t)(j - 1) * D * N;
-  const float* yq = p.y + (size_t)(j >= 2 ? j - 2 : 0) * D * N;
+  const float* yj = p.y + (size_t)(j - 1) * D * S;
+  const float* yq = p.y + (size_t)(j >= 2 ? j - 2 : 0) * D * S;
+  const uint64_t nq = (N + 3) / 4;
   const uint64_t stride = (uint64_t)gridDim.x * 256;
-  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += stride) {
-    double y[D], yp[D];
+  for (uint64_t q = (uint64_t)blockIdx.x * 256 + threadIdx.x; q < nq; q += stride) {
+    float4 v[D], vp[D];
 #pragma unroll
-    for (int a = 0; a < D; ++a) y[a] = yj[(size_t)a * N + i];
+    for (int a = 0; a < D; ++a) v[a] = *(const float4*)(yj + (size_t)a * S + 4 * q);
     if (j >= 2) {
 #pragma unroll
-      for (int a = 0; a < D; ++a) yp[a] = yq[(size_t)a * N + i];
+      for (int a = 0; a < D; ++a) vp[a] = *(const float4*)(yq + (size_t)a * S + 4 * q);
     }
-    double c = p.C[i];
-    const double f = payoff_over_K<D>(p.kind, y);
-    if (valid && f > 0.0) {
-      double psi[F::NF];
-      F::eval(y, f, psi);
-      double h = 0.0;
+    const float4 cv = *(const float4*)(p.C + 4 * q);
+    float cq[4] = {cv.x, cv.y, cv.z, cv.w};
+    bool changed = false;
 #pragma unroll
-      for (int k = 0; k < F::NF; ++k) h = fma(psi[k], beta[k], h);
-      const double e = dK * f;
-      if (e >= h) {
-        const float ef = (float)e;
-        c = ef;
-        p.C[i] = ef;
-        if (p.ex) p.ex[i] = (uint8_t)j;
-      }
-    }
-    if (j >= 2) {
-      const double fp = payoff_over_K<D>(p.kind, yp);
-      if (fp > 0.0) {
+    for (int u = 0; u < 4; ++u) {
+      const uint64_t i = 4 * q + u;
+      if (i >= N) continue;
+      double y[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) y[a] = lane_of(v[a], u);
+      const double f = payoff_over_K<D>(p.kind, y);
+      if (valid && f > 0.0) {
         double psi[F::NF];
-        F::eval(yp, fp, psi);
-        F::gram_add(acc, psi, c);
+        F::eval(y, f, psi);
+        double h = 0.0;
+#pragma unroll
+        for (int k = 0; k < F::NF; ++k) h = fma(psi[k], beta[k], h);
+        const double e = dK * f;
+        if (e >= h) {
+          cq[u] = (float)e;
+          changed = true;
+          if (p.ex) p.ex[i] = (uint8_t)j;
+        }
       }
-    } else {
-      acc[F::NG] += c;
-      acc[F::NG + 1] = fma(c, c, acc[F::NG + 1]);
+      const double c = cq[u];
+      if (j >= 2) {
+        double yp[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) yp[a] = lane_of(vp[a], u);
+        const double fp = payoff_over_K<D>(p.kind, yp);
+        if (fp > 0.0) {
+          // FP64 products: the normal equations square the conditioning of
+          // the features, so FP32 Gram entries would move the fit far more
+          // than the FP32 states do.
+          double psi[F::NF];
+          F::eval(yp, fp, psi);
+          F::gram_add(acc, psi, c);
+        }
+      } else {
+        acc[F::NG] += c;
+        acc[F::NG + 1] = fma(c, c, acc[F::NG + 1]);
+      }
     }
+    // The quad's cash flows go back as one 16-byte store: nearly every
+    // 32-byte sector holds an exercising path at some date anyway.
+    if (changed) *(float4*)(p.C + 4 * q) = make_float4(cq[0], cq[1], cq[2], cq[3]);
   }
   block_reduce_moments<F::NMOM, 256>(acc, p.partials, gridDim.x);
 }
 
-// One thread: normal equations of date j from the reduced moments (upper
-// triangle of u u^T, u = (psi, C), row-major), Cholesky factorisation, two
-// triangular solves. No regression when fewer paths than features are in the
-// money or a pivot is <= 1e-12 times its diagonal entry.
-__global__ void lsm_solve_kernel(const double* __restrict__ sums, uint32_t nf, uint32_t j,
-                                 double* __restrict__ beta, int* __restrict__ valid) {
-  __shared__ double G[kLsmMaxFeat][kLsmMaxFeat], Lc[kLsmMaxFeat][kLsmMaxFeat];
-  __shared__ double b[kLsmMaxFeat], t[kLsmMaxFeat], x[kLsmMaxFeat];
+// Solves the normal equations of date j from one stage's reduced moments
+// (upper triangle of u u^T, u = (psi, C), row-major) in one thread's
+// registers: Cholesky factorisation and two triangular solves. No
+// regression when fewer paths than features are in the money or a pivot is
+// <= 1e-12 times its diagonal entry.
+template <int NF>
+__global__ __launch_bounds__(64) void lsm_solve_kernel(const double* __restrict__ sh, uint32_t j,
+                                                       double* __restrict__ beta,
+                                                       int* __restrict__ valid) {
   if (threadIdx.x != 0) return;
-  const uint32_t nu = nf + 1;
-  uint32_t m = 0;
-  for (uint32_t a = 0; a < nu; ++a)
-    for (uint32_t c = a; c < nu; ++c, ++m) {
-      if (c < nf) {
-        G[a][c] = sums[m];
-        G[c][a] = sums[m];
-      } else if (a < nf) {
-        b[a] = sums[m];
-      }
+  constexpr int NU = NF + 1;
+  double G[NF][NF], b[NF], Lc[NF][NF], t[NF], x[NF];
+  int m = 0;
+#pragma unroll
+  for (int a = 0; a < NU; ++a)
+#pragma unroll
+    for (int c = a; c < NU; ++c, ++m) {
+      if (c < NF) G[c][a] = sh[m];
+      else if (a < NF) b[a] = sh[m];
     }
-  double* row = beta + (size_t)(j - 1) * kLsmMaxFeat;
-  bool ok = G[0][0] >= (double)nf;  // G[0][0] counts the in-the-money paths
-  for (uint32_t c = 0; c < nf && ok; ++c) {
+  bool ok = G[0][0] >= (double)NF;  // G[0][0] counts the in-the-money paths
+#pragma unroll
+  for (int c = 0; c < NF; ++c) {
     double s = G[c][c];
-    for (uint32_t k = 0; k < c; ++k) s -= Lc[c][k] * Lc[c][k];
-    if (!(s > 1e-12 * G[c][c])) {
-      ok = false;
-      break;
-    }
-    Lc[c][c] = sqrt(s);
-    for (uint32_t i = c + 1; i < nf; ++i) {
+#pragma unroll
+    for (int k = 0; k < c; ++k) s -= Lc[c][k] * Lc[c][k];
+    ok = ok && s > 1e-12 * G[c][c];
+    const double l = sqrt(ok ? s : 1.0);
+    Lc[c][c] = l;
+#pragma unroll
+    for (int i = c + 1; i < NF; ++i) {
       double v = G[i][c];
-      for (uint32_t k = 0; k < c; ++k) v -= Lc[i][k] * Lc[c][k];
-      Lc[i][c] = v / Lc[c][c];
+#pragma unroll
+      for (int k = 0; k < c; ++k) v -= Lc[i][k] * Lc[c][k];
+      Lc[i][c] = v / l;
     }
   }
-  if (ok) {
-    for (uint32_t i = 0; i < nf; ++i) {
-      double v = b[i];
-      for (uint32_t k = 0; k < i; ++k) v -= Lc[i][k] * t[k];
-      t[i] = v / Lc[i][i];
-    }
-    for (int i = (int)nf - 1; i >= 0; --i) {
-      double v = t[i];
-      for (uint32_t k = (uint32_t)i + 1; k < nf; ++k) v -= Lc[k][i] * x[k];
-      x[i] = v / Lc[i][i];
-    }
+#pragma unroll
+  for (int i = 0; i < NF; ++i) {
+    double v = b[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) v -= Lc[i][k] * t[k];
+    t[i] = v / Lc[i][i];
   }
-  for (uint32_t k = 0; k < (uint32_t)kLsmMaxFeat; ++k) row[k] = ok && k < nf ? x[k] : __builtin_nan("");
+#pragma unroll
+  for (int i = NF - 1; i >= 0; --i) {
+    double v = t[i];
+#pragma unroll
+    for (int k = i + 1; k < NF; ++k) v -= Lc[k][i] * x[k];
+    x[i] = v / Lc[i][i];
+  }
+  double* row = beta + (size_t)(j - 1) * kLsmMaxFeat;
+#pragma unroll
+  for (int k = 0; k < kLsmMaxFeat; ++k) row[k] = (ok && k < NF) ? x[k < NF ? k : 0] : __builtin_nan("");
   valid[j - 1] = ok ? 1 : 0;
 }
 
@@ -396,16 +428,28 @@ hipError_t launch_lsm_sim(const LsmParams& p, hipStream_t s, uint32_t* n_blocks)
 }
 
 hipError_t launch_lsm_update(const LsmParams& p, uint32_t j, hipStream_t s, uint32_t* n_blocks) {
-  const uint32_t nb = grid_for(p.n_paths);
+  const uint32_t nb = grid_for((p.n_paths + 3) / 4);   // four paths per lane
   *n_blocks = nb;
   if (nb == 0 || j < 1 || j >= p.n_dates) return hipErrorInvalidValue;
   return dispatch(p, Stage::Update, j, s, nb);
 }
 
-hipError_t launch_lsm_solve(const double* sums, uint32_t nf, uint32_t j, double* beta, int* valid,
-                            hipStream_t s) {
-  if (nf < 1 || nf > (uint32_t)kLsmMaxFeat || j < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(lsm_solve_kernel, dim3(1), dim3(64), 0, s, sums, nf, j, beta, valid);
+hipError_t launch_lsm_reduce_solve(const double* partials, uint32_t nb, uint32_t nmom,
+                                  double* out, uint32_t nf, uint32_t j, double* beta, int* valid,
+                                  hipStream_t s) {
+  if (nmom > (uint32_t)kLsmMaxMom || nb == 0) return hipErrorInvalidValue;
+  hipError_t e = launch_final_reduce(partials, nb, nmom, out, s);
+  if (e != hipSuccess || j == 0) return e;
+#define MCP_LSM_SOLVE(NF)                                                                    \
+  case NF:                                                                                   \
+    hipLaunchKernelGGL(lsm_solve_kernel<NF>, dim3(1), dim3(64), 0, s, out, j, beta, valid); \
+    break;
+  switch (nf) {
+    MCP_LSM_SOLVE(2) MCP_LSM_SOLVE(3) MCP_LSM_SOLVE(4) MCP_LSM_SOLVE(5) MCP_LSM_SOLVE(6)
+    MCP_LSM_SOLVE(7) MCP_LSM_SOLVE(8) MCP_LSM_SOLVE(9) MCP_LSM_SOLVE(10) MCP_LSM_SOLVE(11)
+    default: return hipErrorInvalidValue;
+  }
+#undef MCP_LSM_SOLVE
   return hipGetLastError();
 }
 

@@ -160,8 +160,9 @@ struct LsmParams {
   float drift[kLsmMaxD];         // (r - q - sigma_a^2 / 2) dt / ln 2
   float vol[kLsmMaxD][kLsmMaxD]; // sigma_a sqrt(dt) L_ab / ln 2 (lower triangle)
   double discK[kLsmMaxDates + 1];// K e^{-r t_j}, j = 0..n_dates
-  float* y;                      // [n_dates][d][n_paths]: S_a(t_j) / K
-  float* C;                      // [n_paths] discounted cash flow
+  uint64_t ystride;               // row stride of y and length of C: n_paths rounded up to 64
+  float* y;                      // [n_dates][d][ystride]: S_a(t_j) / K
+  float* C;                      // [ystride] discounted cash flow
   uint8_t* ex;                   // [n_paths] exercise date (0 = never), or nullptr
   const double* beta;            // [n_dates][kLsmMaxFeat]
   const int* valid;              // [n_dates]: 1 when date j has a regression
@@ -174,12 +175,14 @@ uint32_t lsm_n_features(uint32_t d, uint32_t degree, uint32_t pay_feat);
 // Simulation of the stored paths (cash flows at t_M, Gram matrix of date
 // n_dates - 1 and the exercise-at-maturity moments), the update of date j
 // (exercise rule of date j, then the Gram matrix of date j - 1, or the
-// price moments when j = 1), the Cholesky solve of date j from the reduced
-// moments `sums`, and the out-of-sample estimate on fresh paths.
+// price moments when j = 1), the reduction of a stage's block partials into
+// `out` followed by the Cholesky solve of date j (none when j = 0), and the
+// out-of-sample estimate on fresh paths.
 hipError_t launch_lsm_sim(const LsmParams& p, hipStream_t s, uint32_t* n_blocks);
 hipError_t launch_lsm_update(const LsmParams& p, uint32_t j, hipStream_t s, uint32_t* n_blocks);
-hipError_t launch_lsm_solve(const double* sums, uint32_t nf, uint32_t j, double* beta, int* valid,
-                            hipStream_t s);
+hipError_t launch_lsm_reduce_solve(const double* partials, uint32_t nb, uint32_t nmom,
+                                  double* out, uint32_t nf, uint32_t j, double* beta, int* valid,
+                                  hipStream_t s);
 hipError_t launch_lsm_oos(const LsmParams& p, hipStream_t s, uint32_t* n_blocks);
 
 // ---- Learned martingale control variate (Heston Asian) ----

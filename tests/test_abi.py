@@ -107,7 +107,7 @@ def test_lsm_struct_layout_matches_header(tmp_path):
                 'int main(){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(mc_lsm_spec), '
                 'offsetof(mc_lsm_spec, n_paths_oos), sizeof(mc_lsm_result), '
                 'offsetof(mc_lsm_result, beta), offsetof(mc_lsm_result, n_itm), '
-                'offsetof(mc_lsm_result, oos_ms), sizeof(mc_lsm_paths), '
+                'offsetof(mc_lsm_result, update_ms), sizeof(mc_lsm_paths), '
                 'offsetof(mc_lsm_paths, oos_exercise_date));}\n')
     exe = src[:-2]
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
@@ -115,7 +115,7 @@ def test_lsm_struct_layout_matches_header(tmp_path):
                                           check=True).stdout.split()]
     S, R, P = _abi.McLsmSpec, _abi.McLsmResult, _abi.McLsmPaths
     assert got == [C.sizeof(S), S.n_paths_oos.offset, C.sizeof(R), R.beta.offset,
-                   R.n_itm.offset, R.oos_ms.offset, C.sizeof(P), P.oos_exercise_date.offset]
+                   R.n_itm.offset, R.update_ms.offset, C.sizeof(P), P.oos_exercise_date.offset]
 
 
 def test_mlmc_allocation_is_the_lagrange_optimum():
