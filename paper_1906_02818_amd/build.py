@@ -18,8 +18,12 @@ OBJ_DIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # -ffp-contract=on: a*b+c is fused only inside one source expression, so the
 # same expression rounds identically in every kernel that contains it.
+# -amdgpu-mfma-vgpr-form: matrix-core results land in ordinary VGPRs, so the
+# VALU code that consumes them (tanh of the hedge network's layers) reads
+# them without v_accvgpr_read copies and with fewer hazard wait states.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 
 

@@ -221,10 +221,11 @@ __global__ __launch_bounds__(kCvThreads) void cv_kernel(const CvParams P) {
   const float kthdt = (float)(Hp.kappa * Hp.theta * Hp.dt), xi = (float)Hp.xi;
   const float rho = (float)Hp.rho, rhoc = (float)Hp.rho_c;
   const float a1 = (float)(-0.5 * Hp.dt * 1.4426950408889634), a2 = 1.4426950408889634f;
-  const float S0 = (float)Hp.S0, K = (float)Hp.K;
+  const float S0 = (float)Hp.S0;
   const float lnS0K = (float)std::log(Hp.S0 / Hp.K), ln2 = 0.69314718055994531f;
   const float rdt2 = (float)(Hp.r * Hp.dt * 1.4426950408889634);   // log2 e^{r dt}
   const float inv_theta = (float)(1.0 / Hp.theta);
+  const float inv_n = (float)(1.0 / Hp.n_steps), S0K = (float)(Hp.S0 / Hp.K);
   const uint32_t n = Hp.n_steps, m = P.hedge_every;
   const PathCounter pc = make_counter(Hp.path_offset + pid, Hp.tag, Hp.k0, Hp.k1);
 
@@ -260,14 +261,14 @@ __global__ __launch_bounds__(kCvThreads) void cv_kernel(const CvParams P) {
     if (i % m == 0) {
       // Features at t_i (F_{t_i}-measurable).
       const float fi = (float)i;
-      const float Abar = (i == 0) ? 1.0f : sumE / fi;      // running mean of S/S0
+      const float Abar = (i == 0) ? 1.0f : sumE * __builtin_amdgcn_rcpf(fi);      // running mean of S/S0
 #pragma unroll
       for (int j = 0; j < 8; ++j) phi[j] = 0.f;
       if (half == 0) {
-        phi[0] = fi / (float)n;
+        phi[0] = fi * inv_n;
         phi[1] = (z + rdt2 * fi) * ln2 + lnS0K;          // ln(S_i / K)
         phi[2] = v * inv_theta;
-        phi[3] = Abar * S0 / K - 1.0f;
+        phi[3] = Abar * S0K - 1.0f;
         phi[4] = 1.0f;
       }
       delta = mlp_forward<BF16>(phi, w1a, s_w2f, s_lanec, lane, b3, h1, h2);
@@ -472,10 +473,11 @@ __global__ __launch_bounds__(kCvThreads) void cv_eval_kernel(const CvParams P) {
   const float kthdt = (float)(Hp.kappa * Hp.theta * Hp.dt), xi = (float)Hp.xi;
   const float rho = (float)Hp.rho, rhoc = (float)Hp.rho_c;
   const float a1 = (float)(-0.5 * Hp.dt * 1.4426950408889634), a2 = 1.4426950408889634f;
-  const float S0 = (float)Hp.S0, K = (float)Hp.K;
+  const float S0 = (float)Hp.S0;
   const float lnS0K = (float)std::log(Hp.S0 / Hp.K), ln2 = 0.69314718055994531f;
   const float rdt2 = (float)(Hp.r * Hp.dt * 1.4426950408889634);
   const float inv_theta = (float)(1.0 / Hp.theta);
+  const float inv_n = (float)(1.0 / Hp.n_steps), S0K = (float)(Hp.S0 / Hp.K);
   const uint32_t n = Hp.n_steps, m = P.hedge_every;
   const PathCounter pc = make_counter(Hp.path_offset + pid, Hp.tag, Hp.k0, Hp.k1);
 
@@ -485,9 +487,9 @@ __global__ __launch_bounds__(kCvThreads) void cv_eval_kernel(const CvParams P) {
   for (uint32_t i = 0; i < n; ++i) {
     if (i % m == 0) {
       const float fi = (float)i;
-      const float Abar = (i == 0) ? 1.0f : sumE / fi;
-      const float own[4] = {fi / (float)n, (z + rdt2 * fi) * ln2 + lnS0K, v * inv_theta,
-                            Abar * S0 / K - 1.0f};
+      const float Abar = (i == 0) ? 1.0f : sumE * __builtin_amdgcn_rcpf(fi);
+      const float own[4] = {fi * inv_n, (z + rdt2 * fi) * ln2 + lnS0K, v * inv_theta,
+                            Abar * S0K - 1.0f};
       float other[4];
 #pragma unroll
       for (int f = 0; f < 4; ++f) other[f] = __shfl_xor(own[f], 32, 64);
