@@ -93,8 +93,10 @@ def lib():
                                       C.c_int, C.c_double, C.c_int, C.c_int]
         L.orc_lsm_lattice.restype = C.c_double
         L.orc_heston_cv.argtypes = [_dp, C.c_int, C.c_int, _dp, C.c_uint64,
-                                    C.c_uint32, C.c_uint64, C.c_uint64, _dp]
-        L.orc_mlp_eval.argtypes = [_dp, C.c_uint64, _dp, _dp]
+                                    C.c_uint32, C.c_uint64, C.c_uint64, C.c_int, _dp]
+        L.orc_mlp_eval.argtypes = [_dp, C.c_uint64, _dp, C.c_int, _dp]
+        L.orc_bf16_round.argtypes = [C.c_double]
+        L.orc_bf16_round.restype = C.c_double
         L.orc_cv_loss_grad.argtypes = [_dp, C.c_int, C.c_int, _dp, C.c_uint64,
                                        C.c_uint32, C.c_uint64, C.c_uint64, C.c_void_p]
         L.orc_cv_loss_grad.restype = C.c_double
@@ -330,21 +332,26 @@ def _heston_prm(h: dict) -> np.ndarray:
 
 
 def heston_cv(h: dict, n_steps, theta, n_paths, seed, tag=0, path0=0,
-              m_every=1) -> np.ndarray:
-    """Per-path (discounted Asian payoff, hedge P&L H, payoff - H)."""
+              m_every=1, bf16=False) -> np.ndarray:
+    """Per-path (discounted Asian payoff, hedge P&L H, payoff - H); bf16
+    rounds the operands of the network's two matrix products to bfloat16."""
     out = np.zeros((n_paths, 3), np.float64)
     lib().orc_heston_cv(_heston_prm(h), n_steps, m_every,
                         np.ascontiguousarray(theta, np.float64), seed, tag,
-                        path0, n_paths, out)
+                        path0, n_paths, int(bf16), out)
     return out
 
 
-def mlp_eval(theta, phi) -> np.ndarray:
+def mlp_eval(theta, phi, bf16=False) -> np.ndarray:
     phi = np.ascontiguousarray(phi, np.float64).reshape(-1, 4)
     out = np.zeros(phi.shape[0], np.float64)
     lib().orc_mlp_eval(np.ascontiguousarray(theta, np.float64), phi.shape[0],
-                       phi, out)
+                       phi, int(bf16), out)
     return out
+
+
+def bf16_round(x: float) -> float:
+    return lib().orc_bf16_round(float(x))
 
 
 def cv_loss_grad(h: dict, n_steps, theta, B, seed, tag=2, path0=0,

@@ -538,7 +538,23 @@ int orc_mlp_nparam(void) { return MLP_NPARAM; }
 
 typedef struct {
     const double *W1, *b1, *W2, *b2, *W3, *b3;
+    int bf16;    /* round the operands of the two matrix products to bfloat16 */
 } mlp_view;
+
+/* The mixed-precision matrix product of the paper's matrix units (Sec. III,
+ * Sec. V-A): operands in bfloat16, products accumulated in higher
+ * precision. A value is rounded to single precision and then to its top 16
+ * bits, to nearest with ties to even. */
+static double bf16_round(double x)
+{
+    float f = (float)x;
+    uint32_t u;
+    memcpy(&u, &f, sizeof(u));
+    if ((u & 0x7f800000u) == 0x7f800000u) return x;     /* inf, nan */
+    u = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+    memcpy(&f, &u, sizeof(f));
+    return f;
+}
 
 static mlp_view mlp_split(const double *th)
 {
@@ -549,6 +565,7 @@ static mlp_view mlp_split(const double *th)
     m.b2 = m.W2 + MLP_H * MLP_H;
     m.W3 = m.b2 + MLP_H;
     m.b3 = m.W3 + MLP_H;
+    m.bf16 = 0;
     return m;
 }
 
@@ -556,14 +573,19 @@ static mlp_view mlp_split(const double *th)
 static double mlp_forward(const mlp_view *m, const double phi[4],
                           double h1[MLP_H], double h2[MLP_H])
 {
+    const int r = m->bf16;
+    double x[4], a1[MLP_H];
+    for (int f = 0; f < 4; ++f) x[f] = r ? bf16_round(phi[f]) : phi[f];
     for (int u = 0; u < MLP_H; ++u) {
-        double s = m->b1[u];
-        for (int f = 0; f < 4; ++f) s += m->W1[u * 4 + f] * phi[f];
+        double s = r ? bf16_round(m->b1[u]) : m->b1[u];
+        for (int f = 0; f < 4; ++f) s += (r ? bf16_round(m->W1[u * 4 + f]) : m->W1[u * 4 + f]) * x[f];
         h1[u] = tanh(s);
+        a1[u] = r ? bf16_round(h1[u]) : h1[u];
     }
     for (int u = 0; u < MLP_H; ++u) {
         double s = m->b2[u];
-        for (int q = 0; q < MLP_H; ++q) s += m->W2[u * MLP_H + q] * h1[q];
+        for (int q = 0; q < MLP_H; ++q)
+            s += (r ? bf16_round(m->W2[u * MLP_H + q]) : m->W2[u * MLP_H + q]) * a1[q];
         h2[u] = tanh(s);
     }
     double out = m->b3[0];
@@ -648,12 +670,14 @@ static void heston_cv_path(const double *prm, int n, int m_every,
     *H = Hsum;
 }
 
-/* Per-path (payoff, H, payoff - H). */
+/* Per-path (payoff, H, payoff - H); bf16 = 1 evaluates the network with
+ * bfloat16 matrix-product operands. */
 void orc_heston_cv(const double *prm, int n_steps, int m_every,
                    const double *theta, uint64_t seed, uint32_t tag,
-                   uint64_t path0, uint64_t n_paths, double *out /* n x 3 */)
+                   uint64_t path0, uint64_t n_paths, int bf16, double *out /* n x 3 */)
 {
     mlp_view net = mlp_split(theta);
+    net.bf16 = bf16;
 #pragma omp parallel for schedule(static)
     for (long long p = 0; p < (long long)n_paths; ++p) {
         double pay, H;
@@ -665,11 +689,14 @@ void orc_heston_cv(const double *prm, int n_steps, int m_every,
     }
 }
 
+double orc_bf16_round(double x) { return bf16_round(x); }
+
 /* Network output alone, for a list of feature vectors (n x 4). */
-void orc_mlp_eval(const double *theta, uint64_t n, const double *phi,
+void orc_mlp_eval(const double *theta, uint64_t n, const double *phi, int bf16,
                   double *out)
 {
     mlp_view net = mlp_split(theta);
+    net.bf16 = bf16;
     double h1[MLP_H], h2[MLP_H];
     for (uint64_t i = 0; i < n; ++i) out[i] = mlp_forward(&net, phi + 4 * i, h1, h2);
 }

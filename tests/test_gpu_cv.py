@@ -55,6 +55,63 @@ def test_cv_eval_parity_fp32(ctx, m_every, N, n):
     assert abs(r["price"] - e["price"]) < 2e-5 * abs(e["price"]) + 1e-4 * e["std_err"]
 
 
+def _bf16_compare(pv, ob, o64):
+    """Per-path hedge P&L of the BF16 kernel against the oracle evaluated
+    with the same bfloat16 operands. What remains are the operands whose
+    FP32 value sits within FP32 rounding of a bfloat16 tie: each moves one
+    operand by one bfloat16 step (2^-8 relative, ~1e-3 of H), a few per
+    path at most."""
+    err = np.abs(pv[:, 1] - ob[:, 1])
+    scale = 1.0 + np.abs(ob[:, 1]).max()
+    rel_bf = np.linalg.norm(pv[:, 1] - ob[:, 1]) / np.linalg.norm(ob[:, 1])
+    rel_64 = np.linalg.norm(pv[:, 1] - o64[:, 1]) / np.linalg.norm(o64[:, 1])
+    say(f"  H err q99 {np.quantile(err, 0.99):.2e} max {err.max():.2e} (scale {scale:.2f}); "
+        f"rel-L2 vs bf16 oracle {rel_bf:.2e}, vs FP64 oracle {rel_64:.2e}")
+    np.testing.assert_allclose(pv[:, 0], ob[:, 0], rtol=3e-4, atol=3e-4)
+    assert np.quantile(err, 0.99) < 2e-3 * scale
+    assert err.max() < 2e-2 * scale
+    # The emulated rounding accounts for almost all of the BF16 error: what
+    # is left is a few operand steps of ~1e-3 of H on some paths.
+    assert rel_bf < 5e-4 and rel_bf < 0.5 * rel_64
+    return err
+
+
+@pytest.mark.parametrize("m_every,N,n", [(16, 2048, 256), (16, 3001, 64), (4, 1000, 33)])
+def test_cv_eval_parity_bf16(ctx, m_every, N, n):
+    say("cv eval bf16", m_every, N, n)
+    th = weights()
+    r = mc.mc_price(ctx, MODEL, PAY, N, n, SEED,
+                    mc.Options(prec=mc.MC_BF16_GEMM, cv_weights=th, cv_hedge_every=m_every,
+                               path_values=True, cv_beta=1.0))
+    ob = oracle.heston_cv(H, n, th, N, SEED, m_every=m_every, bf16=True)
+    o64 = oracle.heston_cv(H, n, th, N, SEED, m_every=m_every)
+    pv = r["path_values"]
+    err = _bf16_compare(pv, ob, o64)
+    assert abs(r["price"] - ob[:, 2].mean()) <= err.mean() + 2e-5 * abs(ob[:, 2].mean())
+
+
+def test_cv_eval_bf16_full_size_sampled(ctx):
+    # The evaluation launch of the benchmark (BF16 products, rebalanced every
+    # 16 steps, 256 steps) at 2^24 paths; 256 sampled paths against the
+    # oracle path by path, the estimator against the per-path values.
+    N, n, m_every = 1 << 24, 256, 16
+    say("cv eval bf16 full size")
+    th = weights()
+    r = mc.mc_price(ctx, MODEL, PAY, N, n, SEED,
+                    mc.Options(prec=mc.MC_BF16_GEMM, cv_weights=th, cv_hedge_every=m_every,
+                               path_values=True, cv_beta=1.0))
+    pv = r["path_values"]
+    assert r["n_nonfinite"] == 0
+    rng = np.random.default_rng(21)
+    idx = np.unique(np.concatenate([[0, 1, N // 2, N - 1], rng.integers(0, N, 252)]))
+    ob = np.concatenate([oracle.heston_cv(H, n, th, 1, SEED, path0=int(i), m_every=m_every,
+                                          bf16=True) for i in idx])
+    o64 = np.concatenate([oracle.heston_cv(H, n, th, 1, SEED, path0=int(i), m_every=m_every)
+                          for i in idx])
+    _bf16_compare(pv[idx], ob, o64)
+    assert r["price"] == pytest.approx(pv[:, 2].mean(), rel=1e-9)
+
+
 def test_hedge_has_zero_mean_on_gpu(ctx):
     th = weights(0.5, seed=8)
     for prec in (mc.MC_FP32, mc.MC_BF16_GEMM):

@@ -85,6 +85,43 @@ def test_adjoint_matches_oracle_tangents(ctx, asian, N, n):
         assert abs(r[key] - e["price"]) < 0.1 * e["std_err"] + 1e-5 * abs(e["price"])
 
 
+def test_adjoint_full_size_sampled_paths(ctx):
+    # The launch the benchmark times: 2^22 paths x 256 steps, price, delta
+    # and d/dv0 in one kernel; 256 sampled paths against the oracle's
+    # forward tangents, path by path.
+    N, n = 1 << 22, 256
+    say("adjoint full size")
+    r = mc.mc_greeks_adjoint(ctx, model(), mc.Payoff(mc.MC_ASIAN_ARITH_CALL, H["K"]), N, n, SEED,
+                             mc.Options(path_values=True))
+    assert r["n_nonfinite"] == 0
+    pv = r["path_values"]
+    rng = np.random.default_rng(22)
+    idx = np.unique(np.concatenate([[0, N - 1], rng.integers(0, N, 254)]))
+    o = np.concatenate([orc(n, 1, path0=int(i)) for i in idx])
+    np.testing.assert_allclose(pv[idx, 0], o[:, 1], rtol=3e-4, atol=3e-4)
+    away = np.abs(o[:, 1]) > 1e-3
+    np.testing.assert_allclose(pv[idx, 1][away], o[away, 4], rtol=3e-4, atol=1e-5)
+    err = np.abs(pv[idx, 2][away] - o[away, 5]) / (1.0 + np.abs(o[away, 5]))
+    assert np.quantile(err, 0.99) < 1e-2
+    assert r["price"] == pytest.approx(pv[:, 0].mean(), rel=1e-9)
+    assert r["delta"] == pytest.approx(pv[:, 1].mean(), rel=1e-9)
+
+
+def test_plain_heston_full_size_sampled_paths(ctx):
+    # The plain FP32 estimator the time-to-1bp comparison runs, at 2^24 paths.
+    N, n = 1 << 24, 256
+    say("heston plain full size")
+    r = mc.mc_price(ctx, model(), mc.Payoff(mc.MC_ASIAN_ARITH_CALL, H["K"]), N, n, SEED,
+                    mc.Options(prec=mc.MC_FP32, path_values=True))
+    pv = r["path_values"]
+    rng = np.random.default_rng(23)
+    idx = np.unique(np.concatenate([[0, N - 1], rng.integers(0, N, 254)]))
+    o = np.concatenate([orc(n, 1, path0=int(i)) for i in idx])
+    np.testing.assert_allclose(pv[idx, 0], o[:, 0], rtol=3e-4, atol=3e-4)
+    np.testing.assert_allclose(pv[idx, 1], o[:, 1], rtol=3e-4, atol=3e-4)
+    assert r["price"] == pytest.approx(pv[:, 1].mean(), rel=1e-9)
+
+
 def test_fwd_rev_split_equals_full_and_autograd(ctx):
     import torch
     N, n = 1 << 15, 256

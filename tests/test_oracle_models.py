@@ -297,6 +297,46 @@ def test_mlp_backprop_matches_finite_differences():
     assert loss > 0
 
 
+def test_bf16_rounding_matches_torch():
+    # Round to nearest, ties to even, on the top 16 bits of the FP32 value:
+    # random magnitudes, exact ties with even and odd kept bits, subnormals.
+    import torch
+    rng = np.random.default_rng(11)
+    x = np.concatenate([rng.normal(0, 1, 2000), rng.normal(0, 1, 500) * 10.0 ** rng.integers(
+        -40, 38, 500), [0.0, -0.0, 1.0, -1.0, 3.0e38, 1e-40, -1e-41]])
+    ties = np.array([0x3F808000, 0x3F818000, 0xBF808000, 0x00018000, 0x40490FDB],
+                    np.uint32).view(np.float32).astype(np.float64)
+    x = np.concatenate([x, ties])
+    want = torch.tensor(x, dtype=torch.float64).to(torch.float32).to(torch.bfloat16).double()
+    got = np.array([oracle.bf16_round(v) for v in x])
+    np.testing.assert_array_equal(got, want.numpy())
+
+
+def test_mlp_bf16_operands_match_rounded_forward():
+    # The bfloat16 network: operands of both matrix products rounded to
+    # bfloat16, everything else in double precision.
+    import torch
+
+    def bf(a):
+        return torch.tensor(np.asarray(a, np.float64)).to(torch.float32).to(
+            torch.bfloat16).double().numpy()
+    rng = np.random.default_rng(12)
+    theta = synth.glorot_mlp() + rng.normal(0, 0.2, oracle.MLP_NPARAM)
+    phi = rng.normal(0, 0.7, (300, 4))
+    W1, b1 = theta[:256].reshape(64, 4), theta[256:320]
+    W2, b2 = theta[320:4416].reshape(64, 64), theta[4416:4480]
+    W3, b3 = theta[4480:4544], theta[4544]
+    h1 = np.tanh(bf(phi) @ bf(W1).T + bf(b1))
+    h2 = np.tanh(bf(h1) @ bf(W2).T + b2)
+    want = h2 @ W3 + b3
+    got = oracle.mlp_eval(theta, phi, bf16=True)
+    np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-12)
+    exact = np.tanh(np.tanh(phi @ W1.T + b1) @ W2.T + b2) @ W3 + b3
+    np.testing.assert_allclose(oracle.mlp_eval(theta, phi), exact, rtol=1e-12, atol=1e-12)
+    d = np.abs(got - exact)
+    assert 0 < d.max() < 3e-2 * np.abs(exact).max()
+
+
 def test_adam_matches_definition_on_a_quadratic():
     # Adam's first step moves every coordinate by lr * sign(grad).
     th = np.array([1.0, -2.0, 3.0])
