@@ -29,12 +29,14 @@ struct HDom<float> {
   static constexpr double kLogScale = 1.4426950408889634;  // ln S -> log2 S
   static __device__ __forceinline__ float exp_(float z) { return __builtin_amdgcn_exp2f(z); }
   static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+  static __device__ __forceinline__ float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
 };
 template <>
 struct HDom<double> {
   static constexpr double kLogScale = 1.0;
   static __device__ __forceinline__ double exp_(double z) { return exp(z); }
   static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+  static __device__ __forceinline__ double rsqrt_(double x) { return 1.0 / sqrt(x); }
 };
 
 // z = log(S/S0) in the kernel's domain, v the variance.
@@ -206,8 +208,7 @@ __global__ __launch_bounds__(kBlock) void heston_adjoint_kernel(const AdjointPar
             if (ASIAN) xb += abar * (double)Es[q];   // S_{i+1} enters the average
             const R vq = vs[q];
             if (vq > R(0)) {
-              const R sq = HDom<R>::sqrt_(vq * dt);
-              const R g = half_dt / sq;               // d sqrt(v dt) / dv
+              const R g = half_dt * HDom<R>::rsqrt_(vq * dt);   // d sqrt(v dt) / dv
               const double dxdv = (double)(-half_dt + zss[q] * g);
               const double dvdv = (double)((R(1) - kdt) + xi * z1s[q] * g);
               vb = xb * dxdv + vb * dvdv;
