@@ -97,6 +97,16 @@ SLOTS_ASSET_STEP = slots(**_add(NORMAL_BASKET, dict(intops=0.5)))
 SLOTS_TANH = slots(trans=2.0, fp32=3.0)
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(c, budget_s=12.0):
     """FP64 oracle on the host cores over a bounded sample of the workload."""
     import oracle
@@ -112,7 +122,7 @@ def cpu_baseline(c, budget_s=12.0):
     dt = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": n_paths * n / dt, "unit": "path-steps/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": _cpu_model(),
             "sample": f"{n_paths} of {c['n_paths']} paths x {n} steps, all channels of the "
                       f"GBM oracle (FP64), {dt:.1f} s"}
 
@@ -509,6 +519,7 @@ def lsm_cpu_baseline(c, n_paths=1 << 20):
     dt = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": n_paths / dt, "unit": "paths/s", "cores": threads, "kind": "oracle",
+            "cpu_model": _cpu_model(),
             "sample": f"{n_paths} of {c['n_paths']} in-sample paths plus {n_paths} fresh paths "
                       f"(FP64 oracle), {dt:.1f} s"}
 
