@@ -55,19 +55,20 @@ def setup(d, rho, sig0=0.2):
     return S0, sigma, corr, kind
 
 
-def run_both(ctx, d, rho, kind, K, q, T, M, spd, degree, N, r=0.05, n_oos=0, tag=0):
+def run_both(ctx, d, rho, kind, K, q, T, M, spd, degree, N, r=0.05, n_oos=0, tag=0, offset=0):
     S0, sigma, corr, mk = setup(d, rho)
     model = mc.Model(kind=mk, S0=S0, r=r, T=T, sigma=sigma, corr=corr if d > 1 else None)
     spec = mc.LsmSpec(payoff=kind, K=K, dividend=q, n_dates=M, steps_per_date=spd,
                       degree=degree, n_paths_oos=n_oos)
-    g = mc.mc_price_lsm(ctx, model, spec, N, SEED, mc.Options(stream_tag=tag), want_paths=True)
+    g = mc.mc_price_lsm(ctx, model, spec, N, SEED, mc.Options(stream_tag=tag, path_offset=offset),
+                        want_paths=True)
     L = np.linalg.cholesky(corr)
     o = oracle.lsm(S0, sigma, L, r, q, T, kind, K, M, spd, degree, N, SEED, tag=tag,
-                   want_paths=True)
+                   path0=offset, want_paths=True)
     oo = None
     if n_oos:
         oo = oracle.lsm_oos(S0, sigma, L, r, q, T, kind, K, M, spd, degree, o["beta"], n_oos,
-                            SEED, tag=tag + 7)
+                            SEED, tag=tag + 7, path0=offset)
     return g, o, oo
 
 
@@ -80,20 +81,22 @@ def first_difference(eg, eo, M):
 
 
 CASES = [
-    # d, rho, payoff, K, q, T, M, steps/date, degree, N  (features)
-    (2, 0.3, MAXC, 100.0, 0.10, 3.0, 9, 1, 2, (1 << 16) + 77),   # 7
-    (1, 0.0, PUT, 100.0, 0.00, 1.0, 10, 4, 3, 50_000),           # 4
-    (3, 0.2, MAXC, 100.0, 0.05, 1.0, 6, 2, 2, 40_000),           # 11
-    (4, 0.4, PUT, 100.0, 0.00, 1.0, 8, 1, 1, 30_000),            # 5
-    (2, 0.0, CALL, 95.0, 0.06, 2.0, 5, 3, 3, 30_011),            # 10
+    # d, rho, payoff, K, q, T, M, steps/date, degree, N, first path, tag  (features)
+    (2, 0.3, MAXC, 100.0, 0.10, 3.0, 9, 1, 2, (1 << 16) + 77, 0, 0),     # 7
+    (1, 0.0, PUT, 100.0, 0.00, 1.0, 10, 4, 3, 50_000, 0, 0),             # 4
+    (3, 0.2, MAXC, 100.0, 0.05, 1.0, 6, 2, 2, 40_000, 0, 0),             # 11
+    (4, 0.4, PUT, 100.0, 0.00, 1.0, 8, 1, 1, 30_000, 0, 0),              # 5
+    (2, 0.0, CALL, 95.0, 0.06, 2.0, 5, 3, 3, 30_011, 0, 0),              # 10
+    (2, 0.3, MAXC, 100.0, 0.10, 3.0, 9, 1, 2, 20_000, (1 << 33) + 5, 3),  # offset and tag
 ]
 
 
-@pytest.mark.parametrize("d,rho,kind,K,q,T,M,spd,degree,N", CASES)
-def test_lsm_matches_oracle(ctx, d, rho, kind, K, q, T, M, spd, degree, N):
-    say("lsm parity", d, rho, kind, K, q, T, M, spd, degree, N)
+@pytest.mark.parametrize("d,rho,kind,K,q,T,M,spd,degree,N,offset,tag", CASES)
+def test_lsm_matches_oracle(ctx, d, rho, kind, K, q, T, M, spd, degree, N, offset, tag):
+    say("lsm parity", d, rho, kind, K, q, T, M, spd, degree, N, offset, tag)
     r = 0.05
-    g, o, oo = run_both(ctx, d, rho, kind, K, q, T, M, spd, degree, N, r=r, n_oos=N)
+    g, o, oo = run_both(ctx, d, rho, kind, K, q, T, M, spd, degree, N, r=r, n_oos=N, tag=tag,
+                        offset=offset)
     nf = o["n_features"]
     assert g["n_features"] == nf
     y = o["y"]
