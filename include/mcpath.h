@@ -114,6 +114,20 @@ typedef struct {
 #define MC_GREEK_DELTA 1u      /* d price / d S0 (basket: of asset 0) */
 #define MC_GREEK_VEGA 2u       /* GBM: d/d sigma; Heston: d/d v0 */
 
+/* How mc_price computes the requested greeks (Sec. I-A.3).
+ *   MC_GREEKS_PATHWISE: derivatives of each path's payoff (forward tangents;
+ *     the adjoint for Heston); refused for discontinuous payoffs (barriers).
+ *   MC_GREEKS_FD_CRN: central finite differences on common random numbers:
+ *     the run is repeated with the parameter bumped up and down by the
+ *     relative step fd_rel_step on the same paths (same seed, tag and path
+ *     indices), and the greek is the mean of the per-path differences over
+ *     2 h theta, with its standard error. Any GBM or Heston payoff, and the
+ *     basket delta (S0 of asset 0). The greeks are those of the payoff
+ *     without control variate. The bumped GBM and Heston runs use FP64
+ *     paths whatever prec is (the price keeps prec): a difference over a
+ *     relative bump h loses about -log10(h) digits. */
+typedef enum { MC_GREEKS_PATHWISE = 0, MC_GREEKS_FD_CRN = 1 } mc_greeks_method;
+
 #define MC_MLP_NPARAM 4545     /* 4-64-64-1 hedge network, FP32 */
 
 typedef struct {
@@ -134,6 +148,8 @@ typedef struct {
     uint64_t pilot_paths;      /* pilot size (tag 1) for beta / fallback; 0 = 2^16 */
     double *path_values;       /* optional host [n_paths * mc_path_channels()]
                                   per-path values (testing and diagnostics) */
+    uint32_t greeks_method;    /* mc_greeks_method, default MC_GREEKS_PATHWISE */
+    double fd_rel_step;        /* MC_GREEKS_FD_CRN relative bump h, 0 < h < 0.5; default 1e-3 */
 } mc_options;
 
 typedef struct {
@@ -145,6 +161,7 @@ typedef struct {
     uint64_t n_paths, n_nonfinite;
     double kernel_ms;                  /* device time of the path kernel(s) */
     int cv_fallback;                   /* 1 when the learned CV lost to plain MC on the pilot */
+    int greeks_method;                 /* mc_greeks_method that produced delta and vega */
 } mc_result;
 
 typedef struct mc_context mc_context;
@@ -154,7 +171,8 @@ mc_status mc_create(mc_context **ctx, int device);
 /* Frees the context, its stream and its device buffers. NULL is allowed. */
 mc_status mc_destroy(mc_context *ctx);
 
-/* Fills opts with defaults (MC_FP32, no greeks, tag 0, beta NaN, m = 1). */
+/* Fills opts with defaults (MC_FP32, no greeks, tag 0, beta NaN, m = 1,
+ * pathwise greeks, finite-difference step 1e-3). */
 void mc_options_default(mc_options *opts);
 
 /* Runs every argument check mc_price makes (values, model/payoff/precision

@@ -17,16 +17,15 @@ import numpy as np
 
 from . import _abi
 from ._abi import (MC_ADJ_FULL, MC_ADJ_FWD, MC_ADJ_REV, MC_ASIAN_ARITH_CALL, MC_ASIAN_GEO_CALL,
-                   MC_BASKET_CALL, MC_BF16_GEMM, MC_BF16X2_GEMM, MC_COUPLE_NONE,
+                   MC_BASKET_CALL, MC_BF16X2_GEMM, MC_BF16_GEMM, MC_COUPLE_NONE,
                    MC_COUPLE_PRECISION, MC_COUPLE_TIME, MC_CV_GEO_ASIAN, MC_CV_LEARNED,
-                   MC_CV_NONE, MC_ERR_DEVICE, MC_ERR_INVALID_ARG, MC_ERR_NO_DEVICE,
-                   MC_ERR_NOT_PD, MC_ERR_OOM, MC_ERR_UNSUPPORTED, MC_ERR_WORKSPACE, MC_EULER_S,
-                   MC_EURO_CALL, MC_FP16_GEMM, MC_FP32, MC_FP64, MC_GBM, MC_GBM_BASKET,
-                   MC_GREEK_DELTA, MC_GREEK_VEGA, MC_HESTON, MC_LOG_EULER, MC_LSM_BASKET_CALL,
-                   MC_LSM_BASKET_PUT, MC_LSM_MAX_CALL, MC_LSM_MAX_DATES, MC_LSM_MAX_FEATURES,
-                   MC_MLMC_MAX_LEVELS,
-                   MC_MAX_STRIKES, MC_MLP_NPARAM, MC_OK, MC_QMC_MAX_REPLICATES,
-                   MC_UO_BARRIER_CALL, MC_UO_BRIDGE_CALL)
+                   MC_CV_NONE, MC_ERR_DEVICE, MC_ERR_INVALID_ARG, MC_ERR_NOT_PD, MC_ERR_NO_DEVICE,
+                   MC_ERR_OOM, MC_ERR_UNSUPPORTED, MC_ERR_WORKSPACE, MC_EULER_S, MC_EURO_CALL,
+                   MC_FP16_GEMM, MC_FP32, MC_FP64, MC_GBM, MC_GBM_BASKET, MC_GREEKS_FD_CRN,
+                   MC_GREEKS_PATHWISE, MC_GREEK_DELTA, MC_GREEK_VEGA, MC_HESTON, MC_LOG_EULER,
+                   MC_LSM_BASKET_CALL, MC_LSM_BASKET_PUT, MC_LSM_MAX_CALL, MC_LSM_MAX_DATES,
+                   MC_LSM_MAX_FEATURES, MC_MAX_STRIKES, MC_MLMC_MAX_LEVELS, MC_MLP_NPARAM, MC_OK,
+                   MC_QMC_MAX_REPLICATES, MC_UO_BARRIER_CALL, MC_UO_BRIDGE_CALL)
 
 __all__ = [n for n in dir(_abi) if n.startswith("MC_")] + [
     "McError", "Model", "Payoff", "Options", "mc_create", "mc_destroy", "mc_validate",
@@ -80,6 +79,8 @@ class Options:
     cv_beta: float = math.nan
     pilot_paths: int = 0
     path_values: bool = False      # also return per-path channel values
+    greeks_method: int = MC_GREEKS_PATHWISE
+    fd_rel_step: float = 1e-3
 
 
 def _arr(x, dtype=np.float64):
@@ -148,6 +149,8 @@ class _Marshal:
         co.cv_hedge_every = o.cv_hedge_every
         co.cv_beta = o.cv_beta
         co.pilot_paths = o.pilot_paths
+        co.greeks_method = o.greeks_method
+        co.fd_rel_step = o.fd_rel_step
         return co
 
     def want_path_values(self, n_paths: int, n_channels: int):

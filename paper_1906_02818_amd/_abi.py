@@ -20,6 +20,7 @@ MC_UO_BARRIER_CALL, MC_BASKET_CALL, MC_UO_BRIDGE_CALL = 4, 5, 6
 MC_CV_NONE, MC_CV_GEO_ASIAN, MC_CV_LEARNED = 0, 1, 2
 MC_GREEK_DELTA, MC_GREEK_VEGA = 1, 2
 MC_ADJ_FULL, MC_ADJ_FWD, MC_ADJ_REV = 0, 1, 2
+MC_GREEKS_PATHWISE, MC_GREEKS_FD_CRN = 0, 1
 MC_MLP_NPARAM = 4545
 MC_MLMC_MAX_LEVELS = 8
 MC_MAX_STRIKES = 8
@@ -52,7 +53,8 @@ class McOptions(C.Structure):
                 ("stream_tag", C.c_uint32), ("hip_stream", C.c_void_p),
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
                 ("cv_weights", _fp), ("cv_hedge_every", C.c_uint32), ("cv_beta", C.c_double),
-                ("pilot_paths", C.c_uint64), ("path_values", _dp)]
+                ("pilot_paths", C.c_uint64), ("path_values", _dp),
+                ("greeks_method", C.c_uint32), ("fd_rel_step", C.c_double)]
 
 
 class McResult(C.Structure):
@@ -61,7 +63,7 @@ class McResult(C.Structure):
                 ("vega_se", C.c_double), ("plain_price", C.c_double),
                 ("plain_std_err", C.c_double), ("cv_beta", C.c_double), ("vrf", C.c_double),
                 ("n_paths", C.c_uint64), ("n_nonfinite", C.c_uint64),
-                ("kernel_ms", C.c_double), ("cv_fallback", C.c_int)]
+                ("kernel_ms", C.c_double), ("cv_fallback", C.c_int), ("greeks_method", C.c_int)]
 
 
 class McLevel(C.Structure):

@@ -157,9 +157,43 @@ mc_status validate_basket(mc_context* ctx, const mc_model* m, const mc_payoff* f
   return MC_OK;
 }
 
-// Every check of mc_price, no device access.
+mc_status validate_model_payoff(mc_context* ctx, const mc_model* m, const mc_payoff* f,
+                                uint64_t n_paths, uint32_t n_steps, const mc_options& o);
+
+// Every check of mc_price, no device access. Finite-difference greeks are
+// checked here and the rest as for a run without greeks (the bumped runs
+// price the payoff alone).
 mc_status validate_all(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint64_t n_paths,
                        uint32_t n_steps, const mc_options& o) {
+  if (o.greeks_method != MC_GREEKS_PATHWISE && o.greeks_method != MC_GREEKS_FD_CRN)
+    return fail(ctx, MC_ERR_INVALID_ARG, "unknown greeks_method");
+  if (o.greeks == 0 || o.greeks_method == MC_GREEKS_PATHWISE)
+    return validate_model_payoff(ctx, m, f, n_paths, n_steps, o);
+  if (!(std::isfinite(o.fd_rel_step) && o.fd_rel_step > 0.0 && o.fd_rel_step < 0.5))
+    return fail(ctx, MC_ERR_INVALID_ARG, "fd_rel_step must lie in (0, 0.5)");
+  if (o.greeks & ~(MC_GREEK_DELTA | MC_GREEK_VEGA))
+    return fail(ctx, MC_ERR_INVALID_ARG, "unknown greek bits");
+  mc_options ob = o;
+  ob.greeks = 0;
+  ob.greeks_method = MC_GREEKS_PATHWISE;
+  mc_status st = validate_model_payoff(ctx, m, f, n_paths, n_steps, ob);
+  if (st != MC_OK) return st;
+  if (f->cv == MC_CV_LEARNED) return fail(ctx, MC_ERR_UNSUPPORTED, "greeks with the learned CV");
+  if (m->kind == MC_GBM_BASKET && (o.greeks & MC_GREEK_VEGA))
+    return fail(ctx, MC_ERR_UNSUPPORTED, "basket greeks: delta only");
+  if ((o.greeks & MC_GREEK_DELTA) && !(m->S0[0] > 0.0))
+    return fail(ctx, MC_ERR_INVALID_ARG, "finite differences need S0 > 0");
+  if (o.greeks & MC_GREEK_VEGA) {
+    const double th = m->kind == MC_HESTON ? m->v0 : m->sigma[0];
+    if (!(th > 0.0))
+      return fail(ctx, MC_ERR_INVALID_ARG, "relative finite differences need a positive %s",
+                  m->kind == MC_HESTON ? "v0" : "sigma");
+  }
+  return MC_OK;
+}
+
+mc_status validate_model_payoff(mc_context* ctx, const mc_model* m, const mc_payoff* f,
+                                uint64_t n_paths, uint32_t n_steps, const mc_options& o) {
   mc_status st = validate_common(ctx, m, f, n_paths, n_steps);
   if (st != MC_OK) return st;
   if (o.cv_hedge_every == 0) return fail(ctx, MC_ERR_INVALID_ARG, "cv_hedge_every must be >= 1");
@@ -1019,6 +1053,10 @@ struct SinkGuard {
   }
 };
 
+// Per-path values of paired runs (multilevel corrections, finite
+// differences) are kept on the device in chunks of at most this many paths.
+constexpr uint64_t kMlmcChunk = 1ull << 20;
+
 mc_status get_mlmc_buf(mc_context* ctx, size_t bytes, char** base) {
   if (ctx->mlmc_bytes < bytes) {
     if (ctx->mlmc_buf) {
@@ -1049,6 +1087,123 @@ mc_status get_lsm_buf(mc_context* ctx, size_t bytes, char** base) {
   return MC_OK;
 }
 
+mc_status mc_price_impl(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint64_t n_paths,
+                        uint32_t n_steps, uint64_t seed, const mc_options& o, mc_result* out);
+
+// Central finite difference on common random numbers (Sec. I-A.3 greeks by
+// bumping): the payoff of the models with the parameter theta scaled by
+// 1 + h and 1 - h, priced on the same paths (same seed, tag and path
+// indices) into device sinks in chunks of at most 2^20 paths; the greek is
+// the mean of the per-path differences over 2 h theta, reduced in FP64.
+mc_status fd_greek(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint64_t n_paths,
+                   uint32_t n_steps, uint64_t seed, const mc_options& o, uint32_t which,
+                   double* g, double* se, double* kms) {
+  const double h = o.fd_rel_step;
+  const uint32_t d = m->dim;
+  std::vector<double> s0u(m->S0, m->S0 + d), s0d = s0u, sgu, sgd;
+  mc_model mu = *m, md = *m;
+  double theta;
+  if (which == MC_GREEK_DELTA) {
+    theta = m->S0[0];
+    s0u[0] = theta * (1.0 + h);
+    s0d[0] = theta * (1.0 - h);
+    mu.S0 = s0u.data();
+    md.S0 = s0d.data();
+  } else if (m->kind == MC_HESTON) {
+    theta = m->v0;
+    mu.v0 = theta * (1.0 + h);
+    md.v0 = theta * (1.0 - h);
+  } else {
+    sgu.assign(m->sigma, m->sigma + d);
+    sgd = sgu;
+    theta = m->sigma[0];
+    sgu[0] = theta * (1.0 + h);
+    sgd[0] = theta * (1.0 - h);
+    mu.sigma = sgu.data();
+    md.sigma = sgd.data();
+  }
+  mc_payoff fp = *f;
+  fp.cv = MC_CV_NONE;
+  mc_options ob = o;
+  ob.greeks = 0;
+  ob.greeks_method = MC_GREEKS_PATHWISE;
+  ob.path_values = nullptr;
+  ob.cv_beta = std::nan("");
+  // A relative bump h leaves about -log10(h) fewer significant digits in the
+  // difference: FP32 paths (about 1e-7 relative error per path) would carry
+  // errors of order 1e-7 / h into the greek, systematic ones included, so the
+  // bumped pairs run in FP64. The basket has no FP64 path; its only bump
+  // (S0 of asset 0) scales the terminal values and loses nothing.
+  if (m->kind != MC_GBM_BASKET) ob.prec = MC_FP64;
+  uint32_t C = 0, ch = 0;
+  mc_status st = payoff_channel(ctx, m, &fp, ob, 1, &C, &ch);
+  if (st != MC_OK) return st;
+  hipStream_t s = stream_of(ctx, o);
+  const uint64_t n_chunks = (n_paths + kMlmcChunk - 1) / kMlmcChunk;
+  const uint64_t chunk = (n_paths + n_chunks - 1) / n_chunks;
+  const size_t bytes_a = align256((size_t)chunk * C * sizeof(double));
+  const uint32_t M = (uint32_t)n_moments(3);
+  const size_t bytes_p = align256((size_t)kDiffMaxBlocks * M * sizeof(double));
+  char* base = nullptr;
+  st = get_mlmc_buf(ctx, 2 * bytes_a + bytes_p + align256(M * sizeof(double)), &base);
+  if (st != MC_OK) return st;
+  st = get_pinned(ctx, M);
+  if (st != MC_OK) return st;
+  double* A = (double*)base;
+  double* B = (double*)(base + bytes_a);
+  double* partials = (double*)(base + 2 * bytes_a);
+  double* mom = (double*)(base + 2 * bytes_a + bytes_p);
+  double acc[n_moments(3)] = {};
+  for (uint64_t p0 = 0; p0 < n_paths; p0 += chunk) {
+    const uint64_t nc = n_paths - p0 < chunk ? n_paths - p0 : chunk;
+    mc_options oc = ob;
+    oc.path_offset = o.path_offset + p0;
+    mc_result tmp{};
+    {
+      SinkGuard guard{ctx};
+      ctx->sink = A;
+      st = mc_price_impl(ctx, &mu, &fp, nc, n_steps, seed, oc, &tmp);
+      if (st != MC_OK) return st;
+      *kms += tmp.kernel_ms;
+      ctx->sink = B;
+      st = mc_price_impl(ctx, &md, &fp, nc, n_steps, seed, oc, &tmp);
+      if (st != MC_OK) return st;
+      *kms += tmp.kernel_ms;
+    }
+    uint32_t nb = 0;
+    HIP_TRY(ctx, launch_diff_moments(A, C, ch, B, C, ch, nc, partials, s, &nb));
+    HIP_TRY(ctx, launch_final_reduce(partials, nb, M, mom, s));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, mom, M * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    for (uint32_t i = 0; i < M; ++i) acc[i] += ctx->pinned[i];
+  }
+  // acc: [n, nonfinite, sum d, sum a, sum b, dd, ...]
+  const double n = acc[0];
+  if (n < 2) return fail(ctx, MC_ERR_DEVICE, "fewer than two finite paths in a bumped run");
+  const double var = std::max(acc[5] - acc[2] * acc[2] / n, 0.0) / (n - 1.0);
+  *g = acc[2] / n / (2.0 * h * theta);
+  *se = std::sqrt(var / n) / (2.0 * h * theta);
+  return MC_OK;
+}
+
+// One pricing run of mc_price with the arguments already checked.
+mc_status mc_price_impl(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint64_t n_paths,
+                        uint32_t n_steps, uint64_t seed, const mc_options& o, mc_result* out) {
+  mc_status st = MC_OK;
+  if (m->kind == MC_GBM) {
+    const uint32_t want = gbm_want_mask(f, o, &st);
+    Moments mom;
+    uint32_t mask = 0;
+    double kms = 0.0;
+    st = gbm_run(ctx, m, f, n_paths, n_steps, seed, o, want, o.stream_tag, o.path_values, &mom,
+                 &mask, &kms);
+    if (st != MC_OK) return st;
+    return gbm_result(ctx, m, f, n_steps, seed, o, mask, mom, kms, n_paths, out);
+  }
+  if (m->kind == MC_GBM_BASKET) return basket_price(ctx, m, f, n_paths, n_steps, seed, o, out);
+  return heston_price(ctx, m, f, n_paths, n_steps, seed, o, out);
+}
+
 // Mean and standard error from (n, sum, sum of squares).
 void moments_mean_se(double n, double s1, double s2, double* mean, double* se) {
   *mean = s1 / n;
@@ -1056,7 +1211,6 @@ void moments_mean_se(double n, double s1, double s2, double* mean, double* se) {
   *se = std::sqrt(v / n);
 }
 
-constexpr uint64_t kMlmcChunk = 1ull << 20;
 
 }  // namespace
 
@@ -1069,6 +1223,8 @@ void mc_options_default(mc_options* o) {
   o->prec = MC_FP32;
   o->cv_hedge_every = 1;
   o->cv_beta = std::nan("");
+  o->greeks_method = MC_GREEKS_PATHWISE;
+  o->fd_rel_step = 1e-3;
 }
 
 mc_status mc_create(mc_context** out, int device) {
@@ -1204,18 +1360,30 @@ mc_status mc_price(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint6
   if (st != MC_OK) return st;
   if (!out) return fail(ctx, MC_ERR_INVALID_ARG, "out must not be NULL");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, MC_ERR_DEVICE, "hipSetDevice");
-  if (m->kind == MC_GBM) {
-    const uint32_t want = gbm_want_mask(f, o, &st);
-    Moments mom;
-    uint32_t mask = 0;
-    double kms = 0.0;
-    st = gbm_run(ctx, m, f, n_paths, n_steps, seed, o, want, o.stream_tag, o.path_values, &mom,
-                 &mask, &kms);
+  if (o.greeks == 0 || o.greeks_method == MC_GREEKS_PATHWISE)
+    return mc_price_impl(ctx, m, f, n_paths, n_steps, seed, o, out);
+  // Finite differences on common random numbers: the price run, then one
+  // pair of bumped runs per requested greek.
+  mc_options ob = o;
+  ob.greeks = 0;
+  ob.greeks_method = MC_GREEKS_PATHWISE;
+  mc_result r{};
+  st = mc_price_impl(ctx, m, f, n_paths, n_steps, seed, ob, &r);
+  if (st != MC_OK) return st;
+  double kms = r.kernel_ms;
+  if (o.greeks & MC_GREEK_DELTA) {
+    st = fd_greek(ctx, m, f, n_paths, n_steps, seed, o, MC_GREEK_DELTA, &r.delta, &r.delta_se,
+                  &kms);
     if (st != MC_OK) return st;
-    return gbm_result(ctx, m, f, n_steps, seed, o, mask, mom, kms, n_paths, out);
   }
-  if (m->kind == MC_GBM_BASKET) return basket_price(ctx, m, f, n_paths, n_steps, seed, o, out);
-  return heston_price(ctx, m, f, n_paths, n_steps, seed, o, out);
+  if (o.greeks & MC_GREEK_VEGA) {
+    st = fd_greek(ctx, m, f, n_paths, n_steps, seed, o, MC_GREEK_VEGA, &r.vega, &r.vega_se, &kms);
+    if (st != MC_OK) return st;
+  }
+  r.kernel_ms = kms;
+  r.greeks_method = MC_GREEKS_FD_CRN;
+  *out = r;
+  return MC_OK;
 }
 
 mc_status mc_price_multi(mc_context* ctx, const mc_model* m, const mc_payoff* fs, uint32_t nf,
