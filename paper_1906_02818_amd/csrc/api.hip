@@ -881,10 +881,14 @@ struct BasketQmc {
   double geo_mean;
 };
 
-mc_status basket_price(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint64_t n_paths,
-                       uint32_t n_steps, uint64_t seed, const mc_options& o0, mc_result* out,
-                       const mc_portfolio* port = nullptr, double premium = 0.0,
-                       BasketQmc* qmc = nullptr) {
+// Host part of a basket run: checks, Cholesky factor, packed L' and the
+// per-asset constants uploaded to the workspace (after the moment area of
+// run_moments), and the kernel parameters. *o_run is o0 with the workspace
+// narrowed to the moment area.
+mc_status basket_setup(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint64_t n_paths,
+                       uint32_t n_steps, uint64_t seed, const mc_options& o0,
+                       const mc_portfolio* port, double premium, const BasketQmc* qmc,
+                       BasketParams* p_out, int* prec_out, mc_options* o_run) {
   std::vector<double> L;
   mc_status st = validate_basket(ctx, m, f, n_steps, o0, &L);
   if (st != MC_OK) return st;
@@ -981,6 +985,22 @@ mc_status basket_price(mc_context* ctx, const mc_model* m, const mc_payoff* f, u
   p.premium = premium;
   p.qV = qmc ? qmc->V : nullptr;
   p.qshift = qmc ? qmc->shift : nullptr;
+  *p_out = p;
+  *prec_out = prec;
+  *o_run = o;
+  return MC_OK;
+}
+
+mc_status basket_price(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint64_t n_paths,
+                       uint32_t n_steps, uint64_t seed, const mc_options& o0, mc_result* out,
+                       const mc_portfolio* port = nullptr, double premium = 0.0,
+                       BasketQmc* qmc = nullptr) {
+  BasketParams p{};
+  int prec = BK_FP32;
+  mc_options o;
+  mc_status st = basket_setup(ctx, m, f, n_paths, n_steps, seed, o0, port, premium, qmc, &p, &prec,
+                              &o);
+  if (st != MC_OK) return st;
   Moments mom;
   double kms = 0.0;
   st = run_moments(ctx, o, n_paths, port ? 1 : 3, o0.path_values,
@@ -1633,19 +1653,68 @@ mc_status mc_price_qmc(mc_context* ctx, const mc_model* m, const mc_payoff* f, u
     HIP_TRY(ctx, hipStreamSynchronize(s));     // V goes out of scope
     ctx->qmc_dims = dims;
   }
-  BasketQmc q{ctx->qmc_buf, ctx->qmc_buf + (size_t)dims * 32, 0.0};
   mc_qmc_result r{};
   r.n_replicates = n_replicates;
   r.n_points = n_points;
-  for (uint32_t rep = 0; rep < n_replicates; ++rep) {
-    HIP_TRY(ctx, launch_qmc_shifts((uint32_t)seed, (uint32_t)(seed >> 32), o0.stream_tag + 6u,
-                                   rep, dims, (uint32_t*)q.shift, s));
+  if (o0.path_values) {
+    // One replicate with per-path values: the plain basket run.
+    BasketQmc q{ctx->qmc_buf, ctx->qmc_buf + (size_t)dims * 32, 0.0};
+    HIP_TRY(ctx, launch_qmc_shifts((uint32_t)seed, (uint32_t)(seed >> 32), o0.stream_tag + 6u, 0,
+                                   dims, (uint32_t*)q.shift, s));
     mc_result pr{};
     st = basket_price(ctx, m, f, n_points, n_steps, seed, o0, &pr, nullptr, 0.0, &q);
     if (st != MC_OK) return st;
-    r.replicate_price[rep] = pr.price;
-    r.replicate_geo[rep] = q.geo_mean;
-    r.kernel_ms += pr.kernel_ms;
+    r.replicate_price[0] = pr.price;
+    r.replicate_geo[0] = q.geo_mean;
+    r.kernel_ms = pr.kernel_ms;
+  } else {
+    // All replicates back to back on the stream: their digital shifts, path
+    // kernels and fixed-order reductions, one synchronisation at the end.
+    const BasketQmc q0{ctx->qmc_buf, ctx->qmc_buf + (size_t)dims * 32, 0.0};
+    BasketParams p{};
+    int prec = BK_FP32;
+    mc_options orun;
+    st = basket_setup(ctx, m, f, n_points, n_steps, seed, o0, nullptr, 0.0, &q0, &p, &prec, &orun);
+    if (st != MC_OK) return st;
+    const RunLayout Lay = layout_for(n_points, 3, false);
+    const size_t b_shift = align256((size_t)n_replicates * dims * sizeof(uint32_t));
+    const size_t b_part = align256((size_t)Lay.n_mom * Lay.n_blocks * sizeof(double));
+    const size_t b_mom = align256((size_t)n_replicates * Lay.n_mom * sizeof(double));
+    char* base = nullptr;
+    st = get_mlmc_buf(ctx, b_shift + (size_t)n_replicates * b_part + b_mom, &base);
+    if (st != MC_OK) return st;
+    st = get_pinned(ctx, (size_t)n_replicates * Lay.n_mom);
+    if (st != MC_OK) return st;
+    uint32_t* shifts = (uint32_t*)base;
+    double* moms = (double*)(base + b_shift + (size_t)n_replicates * b_part);
+    HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
+    for (uint32_t rep = 0; rep < n_replicates; ++rep) {
+      uint32_t* sh = shifts + (size_t)rep * dims;
+      HIP_TRY(ctx, launch_qmc_shifts((uint32_t)seed, (uint32_t)(seed >> 32), o0.stream_tag + 6u,
+                                     rep, dims, sh, s));
+      p.qshift = sh;
+      p.partials = (double*)(base + b_shift + (size_t)rep * b_part);
+      p.path_out = nullptr;
+      uint32_t nb = 0;
+      HIP_TRY(ctx, launch_basket(p, prec, s, &nb));
+      if (nb == 0 || nb > Lay.n_blocks) return fail(ctx, MC_ERR_DEVICE, "block count mismatch");
+      HIP_TRY(ctx, launch_final_reduce(p.partials, nb, Lay.n_mom, moms + (size_t)rep * Lay.n_mom,
+                                       s));
+    }
+    HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, moms, (size_t)n_replicates * Lay.n_mom * 8,
+                                hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    float ms = 0.f;
+    HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    r.kernel_ms = ms;
+    for (uint32_t rep = 0; rep < n_replicates; ++rep) {
+      // Moments: [n_valid, n_nonfinite, sum basket, sum geometric, ...].
+      const double* mr = ctx->pinned + (size_t)rep * Lay.n_mom;
+      if (mr[0] < 2) return fail(ctx, MC_ERR_DEVICE, "replicate %u: fewer than two finite paths", rep);
+      r.replicate_price[rep] = mr[2] / mr[0];
+      r.replicate_geo[rep] = mr[3] / mr[0];
+    }
   }
   auto mean_se = [n_replicates](const double* x, double* mean, double* se) {
     double s1 = 0.0;
