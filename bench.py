@@ -127,6 +127,32 @@ def cpu_baseline(c, budget_s=12.0):
                       f"GBM oracle (FP64), {dt:.1f} s"}
 
 
+def _oracle_sample(fn, probe, n_max, budget_s=8.0):
+    """Runs fn(n) on a probe of n units, then once more on a power-of-two
+    count sized to about budget_s seconds (at most n_max); returns (n, s)."""
+    t0 = time.perf_counter()
+    fn(probe)
+    dt = time.perf_counter() - t0
+    n = int(max(probe, min(n_max, probe * budget_s / max(dt, 1e-6))))
+    n = 1 << int(math.log2(n))
+    t0 = time.perf_counter()
+    fn(n)
+    return n, time.perf_counter() - t0
+
+
+def _cpu_entry(value, unit, sample, **extra):
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict({"value": value, "unit": unit, "cores": threads, "kind": "oracle",
+                 "cpu_model": _cpu_model(), "sample": sample}, **extra)
+
+
+def _basket_oracle_inputs(synth, d):
+    import numpy as np
+    import oracle
+    sigma, corr, _ = synth.basket_market(d)
+    return sigma, oracle.cholesky(corr), np.full(d, 1.0 / d)
+
+
 def _paths_for(se_target, sigma):
     n = int(math.ceil((sigma / se_target) ** 2))
     return max(256, (n + 255) // 256 * 256)
@@ -568,6 +594,131 @@ WORKLOADS = {"asian_barrier": run_asian_barrier, "european": run_european, "bask
              "lsm": run_lsm}
 
 
+# ---- the oracle beside each workload (bounded samples on the host cores) ----
+def _cpu_european(line, synth):
+    import oracle
+    c = synth.EURO
+    n = c["n_steps"]
+    N, dt = _oracle_sample(lambda k: oracle.gbm(c["S0"], c["r"], c["sigma"], c["T"], c["K"],
+                                                1e300, n, k, 1234), 1 << 12, c["n_paths"])
+    return _cpu_entry(N * n / dt, "path-steps/s",
+                      f"{N} of {c['n_paths']} paths x {n} steps, FP64 GBM oracle (price and "
+                      f"pathwise tangents among its channels), {dt:.1f} s")
+
+
+def _basket_rate(synth, c, probe=1 << 8):
+    import numpy as np
+    import oracle
+    n, d = c["n_steps"], c["d"]
+    sigma, L, w = _basket_oracle_inputs(synth, d)
+    S0 = np.full(d, c["S0"])
+    N, dt = _oracle_sample(lambda k: oracle.basket(S0, sigma, L, w, c["r"], c["T"], c["K"], n,
+                                                   k, 1234), probe, c["n_paths"])
+    return N, dt
+
+
+def _cpu_basket(line, synth):
+    c = synth.BASKET
+    n, d = c["n_steps"], c["d"]
+    N, dt = _basket_rate(synth, c)
+    return _cpu_entry(N * n * d / dt, "asset-path-steps/s",
+                      f"{N} of {c['n_paths']} paths x {n} steps x {d} assets, FP64 basket "
+                      f"oracle (Z L^T as a plain triangular product), {dt:.1f} s")
+
+
+def _cpu_mlmc_basket(line, synth):
+    c = synth.BASKET
+    n, d = c["n_steps"], c["d"]
+    N, dt = _basket_rate(synth, c)
+    n_plain = line["time_to_1bp"]["plain_fp32"]["n_paths"]
+    return _cpu_entry(n_plain * dt / N, "s",
+                      f"{N} basket paths ({n} steps x {d} assets, FP64 oracle) in {dt:.1f} s, "
+                      f"projected to the {n_plain} paths of the plain estimator at SE = 1 bp",
+                      sample_s=dt)
+
+
+def _cpu_risk(line, synth):
+    import numpy as np
+    import oracle
+    c = synth.BASKET
+    n, d = c["n_steps"], c["d"]
+    sigma, L, _ = _basket_oracle_inputs(synth, d)
+    S0 = np.full(d, c["S0"])
+    mu = [0.02 + 0.08 * a / (d - 1) for a in range(d)]
+
+    def run(k):
+        pnl = oracle.portfolio_pnl(S0, sigma, mu, L, RISK_STRIKES, RISK_QTY, c["r"], c["T"], n,
+                                   k, 1234)
+        oracle.var_cvar(pnl, 0.95)
+    N, dt = _oracle_sample(run, 1 << 8, c["n_paths"])
+    return _cpu_entry(N * n * d / dt, "asset-path-steps/s",
+                      f"{N} of {c['n_paths']} scenarios x {n} steps x {d} assets, FP64 "
+                      f"portfolio oracle and a sorted VaR/CVaR, {dt:.1f} s")
+
+
+def _cpu_heston_adjoint(line, synth):
+    import oracle
+    H = synth.HESTON
+    n = H["n_steps"]
+    N, dt = _oracle_sample(lambda k: oracle.heston(
+        H["S0"], H["v0"], H["kappa"], H["theta"], H["xi"], H["rho"], H["r"], H["T"], H["K"], n,
+        k, 1234), 1 << 10, H["n_paths"])
+    return _cpu_entry(N * n / dt, "path-steps/s",
+                      f"{N} of {H['n_paths']} paths x {n} steps, FP64 Heston oracle (price "
+                      f"and forward-mode pathwise delta and d/dv0), {dt:.1f} s")
+
+
+def _cpu_learned_cv(line, synth):
+    import oracle
+    H = synth.HESTON
+    n = H["n_steps"]
+    t1 = line["time_to_1bp"]
+    N, dt = _oracle_sample(lambda k: oracle.heston(
+        H["S0"], H["v0"], H["kappa"], H["theta"], H["xi"], H["rho"], H["r"], H["T"], H["K"], n,
+        k, 1234), 1 << 10, 1 << 20, budget_s=6.0)
+    m = t1["hedge_every"]
+    th = synth.glorot_mlp()
+    Nc, dtc = _oracle_sample(lambda k: oracle.heston_cv(H, n, th, k, 1234, m_every=m),
+                             1 << 8, 1 << 20, budget_s=6.0)
+    n_plain, n_cv = t1["plain_fp32"]["n_paths"], t1["learned_cv_bf16"]["n_paths"]
+    return _cpu_entry(n_plain * dt / N, "s",
+                      f"{N} Heston paths ({n} steps, FP64 oracle) in {dt:.1f} s, projected "
+                      f"to the {n_plain} paths of the plain estimator at SE = 1 bp",
+                      learned_cv_eval_s=n_cv * dtc / Nc,
+                      learned_cv_sample=f"{Nc} paths of the FP64 hedge-network oracle "
+                                        f"(rebalanced every {m} steps) in {dtc:.1f} s, "
+                                        f"projected to the {n_cv} paths of the learned-CV "
+                                        f"estimator; training excluded")
+
+
+def _cpu_qmc_basket(line, synth):
+    import numpy as np
+    import oracle
+    d = 16
+    sigma, L, w = _basket_oracle_inputs(synth, d)
+    S0 = np.full(d, 100.0)
+    NQ, R = line["config"]["n_points"], line["config"]["replicates"]
+
+    def run(k):
+        for rep in range(R):
+            oracle.basket_qmc(S0, sigma, L, w, 0.05, 1.0, 100.0, 1, k, 1234, rep)
+    N, dt = _oracle_sample(run, NQ, NQ)
+    return _cpu_entry(R * N / dt, "paths/s",
+                      f"{N} of the {NQ} points of each of the {R} replicates (16-asset basket, "
+                      f"one step, FP64 Sobol' oracle), {dt:.1f} s")
+
+
+CPU_BASELINES = {
+    "european": _cpu_european,
+    "basket": _cpu_basket,
+    "mlmc_basket": _cpu_mlmc_basket,
+    "risk": _cpu_risk,
+    "heston_adjoint": _cpu_heston_adjoint,
+    "learned_cv": _cpu_learned_cv,
+    "qmc_basket": _cpu_qmc_basket,
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -600,6 +751,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     line = WORKLOADS[args.workload](args, ctx, mc, synth, torch)
+    if (not args.no_cpu_baseline and "cpu_baseline" not in line
+            and args.workload in CPU_BASELINES):
+        line["cpu_baseline"] = CPU_BASELINES[args.workload](line, synth)
     print(json.dumps(line), flush=True)
     ctx.close()
 
