@@ -135,18 +135,17 @@ __global__ __launch_bounds__(kThreads) void basket_kernel(const BasketParams P) 
   }
 
   // Terminal values. Lane holds asset a = 32 nb + row for path rows
-  // 8 (r/4) + 4 half + (r mod 4), r = 0..15.
-  float bsum[16], gsum[16], e0[16];
+  // 8 (r/4) + 4 half + (r mod 4), r = 0..15. One row r at a time: the sum
+  // over the lane's assets, then over the 32 lanes of its half (few live
+  // registers beside the accumulators).
+  float B = 0.f, G = 0.f, E0 = 0.f;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) bsum[r] = gsum[r] = e0[r] = 0.f;
+  for (int r = 0; r < 16; ++r) {
+    float bs = 0.f, gs = 0.f, e0 = 0.f;
 #pragma unroll
-  for (int nb = 0; nb < ND; ++nb) {
-    const int a = 32 * nb + row;
-    const float nmu = P.asset[a], ca = P.asset[256 + a], ga = P.asset[512 + a];
-    const float s0 = P.asset[768 + a];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const float x = acc[nb][r] + nmu;                 // log2(S_a / S0_a)
+    for (int nb = 0; nb < ND; ++nb) {
+      const int a = 32 * nb + row;
+      const float x = acc[nb][r] + P.asset[a];          // log2(S_a / S0_a)
       const float E = __builtin_amdgcn_exp2f(x);
       if constexpr (PORT) {
         // Portfolio value of asset a: S0_a sum_k q_k (E - m_k)^+ (zero-padded
@@ -156,31 +155,24 @@ __global__ __launch_bounds__(kThreads) void basket_kernel(const BasketParams P) 
           const float itm = E - P.pm[k];
           v = __builtin_fmaf(P.pq[k], itm > 0.f ? itm : 0.f, v);
         }
-        bsum[r] = __builtin_fmaf(s0, v, bsum[r]);
+        bs = __builtin_fmaf(P.asset[768 + a], v, bs);
       } else {
-        bsum[r] += ca * E;
-        gsum[r] += ga * x;
-        if (nb == 0) e0[r] = E;
+        bs += P.asset[256 + a] * E;
+        gs += P.asset[512 + a] * x;
+        if (nb == 0) e0 = E;
       }
     }
-  }
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
 #pragma unroll
     for (int off = 16; off > 0; off >>= 1) {
-      bsum[r] += __shfl_xor(bsum[r], off, 64);
-      if constexpr (!PORT) gsum[r] += __shfl_xor(gsum[r], off, 64);
+      bs += __shfl_xor(bs, off, 64);
+      if constexpr (!PORT) gs += __shfl_xor(gs, off, 64);
     }
-    if constexpr (!PORT) e0[r] = __shfl(e0[r], lane & 32, 64);   // asset 0 sits in column 0
-  }
-  // Lane (half, row < 16) reports path row 8 (row/4) + 4 half + row mod 4.
-  float B = 0.f, G = 0.f, E0 = 0.f;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
+    if constexpr (!PORT) e0 = __shfl(e0, lane & 32, 64);   // asset 0 sits in column 0
+    // Lane (half, row < 16) reports path row 8 (row/4) + 4 half + row mod 4.
     if (r == row) {
-      B = bsum[r];
-      G = gsum[r];
-      E0 = e0[r];
+      B = bs;
+      G = gs;
+      E0 = e0;
     }
   }
   const int prow = 8 * (row >> 2) + 4 * half + (row & 3);
