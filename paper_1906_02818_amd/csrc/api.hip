@@ -741,8 +741,9 @@ mc_status heston_cv_price(mc_context* ctx, const mc_model* m, const mc_payoff* f
   return MC_OK;
 }
 
-// Forward + backward over one minibatch; leaves the FP64 gradient in
-// grad_dev and returns the moments of the forward pass.
+// Training workspace: moments and per-path values of the minibatch, the
+// gradient partials, the weights and their fragments, Adam's moments, the
+// per-step loss moments and the feature cache of the training paths.
 struct CvTrainWs {
   char* eval_base;          // moment layout with per-path values
   size_t eval_bytes;
@@ -751,9 +752,16 @@ struct CvTrainWs {
   CvBuffers b;
   float *m, *v;             // Adam moments
   double* log;              // [steps][n_mom] forward-pass moments
+  float *c_phi, *c_dst, *c_delta;
+  double* c_pay;
 };
 
-size_t cv_train_bytes(uint64_t batch, uint32_t n_steps, uint32_t steps, CvTrainWs* w, char* base) {
+uint32_t cv_segments(uint32_t n_steps, uint32_t hedge_every) {
+  return (n_steps + hedge_every - 1) / hedge_every;
+}
+
+size_t cv_train_bytes(uint64_t batch, uint32_t n_steps, uint32_t steps, uint64_t n_cache,
+                      uint32_t n_seg, CvTrainWs* w, char* base) {
   const RunLayout Lay = layout_for(batch, 3, true, kCvTrainPathsPerBlock);
   const uint64_t n_waves =
       (batch + kCvTrainPathsPerBlock - 1) / kCvTrainPathsPerBlock * (kCvTrainPathsPerBlock / 32);
@@ -770,6 +778,10 @@ size_t cv_train_bytes(uint64_t batch, uint32_t n_steps, uint32_t steps, CvTrainW
   char* mm = take((size_t)kMlpNParam * 4);
   char* vv = take((size_t)kMlpNParam * 4);
   char* lg = take((size_t)(steps ? steps : 1) * Lay.n_mom * 8);
+  char* cphi = take((size_t)n_seg * 4 * n_cache * 4);
+  char* cdst = take((size_t)n_seg * n_cache * 4);
+  char* cpay = take((size_t)n_cache * 8);
+  char* cdel = take((size_t)n_seg * batch * 4);
   if (w && base) {
     w->eval_base = e;
     w->eval_bytes = Lay.bytes;
@@ -779,26 +791,62 @@ size_t cv_train_bytes(uint64_t batch, uint32_t n_steps, uint32_t steps, CvTrainW
     w->m = (float*)mm;
     w->v = (float*)vv;
     w->log = (double*)lg;
+    w->c_phi = (float*)cphi;
+    w->c_dst = (float*)cdst;
+    w->c_pay = (double*)cpay;
+    w->c_delta = (float*)cdel;
   }
   return off;
 }
 
-mc_status cv_loss_grad_device(mc_context* ctx, hipStream_t s, const mc_model* m,
-                              const mc_payoff* f, uint32_t n_steps, uint64_t seed, uint32_t tag,
-                              uint64_t path0, uint64_t batch, uint32_t hedge_every, bool bf16,
-                              const CvTrainWs& w, double* log_row) {
+CvParams cv_cache_params(const CvParams& base, const CvTrainWs& w, uint64_t n_cache,
+                         uint32_t n_seg) {
+  CvParams p = base;
+  p.c_phi = w.c_phi;
+  p.c_dst = w.c_dst;
+  p.c_pay = w.c_pay;
+  p.c_delta = w.c_delta;
+  p.c_stride = n_cache;
+  p.n_seg = n_seg;
+  return p;
+}
+
+// Simulates n_cache training paths (from global path path0 on stream tag
+// `tag`) into the feature cache.
+mc_status cv_fill_cache(mc_context* ctx, hipStream_t s, const mc_model* m, const mc_payoff* f,
+                        uint32_t n_steps, uint64_t seed, uint32_t tag, uint64_t path0,
+                        uint64_t n_cache, uint32_t hedge_every, bool bf16, const CvTrainWs& w) {
   mc_options o = defaults();
   o.hip_stream = s;
   o.path_offset = path0;
+  const uint32_t n_seg = cv_segments(n_steps, hedge_every);
+  CvParams p = cv_cache_params(
+      cv_params(m, f, n_cache, n_steps, seed, o, tag, hedge_every, bf16, w.b), w, n_cache, n_seg);
+  HIP_TRY(ctx, launch_cv_cache(p, s));
+  return MC_OK;
+}
+
+// Forward + backward over the minibatch of `batch` cached paths from cache
+// path `first`; leaves the FP64 gradient in w.grad and the forward pass's
+// moments in log_row.
+mc_status cv_loss_grad_device(mc_context* ctx, hipStream_t s, const mc_model* m,
+                              const mc_payoff* f, uint32_t n_steps, uint64_t first,
+                              uint64_t n_cache, uint64_t batch, uint32_t hedge_every, bool bf16,
+                              const CvTrainWs& w, double* log_row) {
+  mc_options o = defaults();
+  o.hip_stream = s;
   const RunLayout Lay = layout_for(batch, 3, true, kCvTrainPathsPerBlock);
   double* partials = (double*)w.eval_base;
   double* mom = (double*)(w.eval_base + Lay.off_mom);
   double* ypath = (double*)(w.eval_base + Lay.off_path);
-  CvParams p = cv_params(m, f, batch, n_steps, seed, o, tag, hedge_every, bf16, w.b);
+  CvParams p = cv_cache_params(cv_params(m, f, batch, n_steps, 0, o, 0, hedge_every, bf16, w.b),
+                               w, n_cache, cv_segments(n_steps, hedge_every));
+  p.c_first = first;
   p.partials = partials;
   p.path_out = ypath;
   uint32_t nb = 0;
-  HIP_TRY(ctx, launch_cv_forward32(p, s, &nb));
+  HIP_TRY(ctx, launch_cv_forward(p, s));
+  HIP_TRY(ctx, launch_cv_values(p, s, &nb));
   HIP_TRY(ctx, launch_final_reduce(partials, nb, Lay.n_mom, mom, s));
   if (log_row)
     HIP_TRY(ctx, hipMemcpyAsync(log_row, mom, Lay.n_mom * 8, hipMemcpyDeviceToDevice, s));
@@ -1950,17 +1998,21 @@ mc_status mc_cv_loss_grad(mc_context* ctx, const mc_model* m, const mc_payoff* f
   if (st != MC_OK) return st;
   if (!weights || !loss_out || !grad_out) return fail(ctx, MC_ERR_INVALID_ARG, "NULL array");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, MC_ERR_DEVICE, "hipSetDevice");
-  const size_t bytes = cv_train_bytes(batch, n_steps, 1, nullptr, nullptr);
+  const uint32_t n_seg = cv_segments(n_steps, cfg->hedge_every);
+  const size_t bytes = cv_train_bytes(batch, n_steps, 1, batch, n_seg, nullptr, nullptr);
   char* base = nullptr;
   st = get_ws(ctx, o, bytes, &base);
   if (st != MC_OK) return st;
   CvTrainWs w;
-  cv_train_bytes(batch, n_steps, 1, &w, base);
+  cv_train_bytes(batch, n_steps, 1, batch, n_seg, &w, base);
   hipStream_t s = ctx->stream;
   st = cv_upload(ctx, s, w.b, weights, dfac_table(m, n_steps));
   if (st != MC_OK) return st;
-  st = cv_loss_grad_device(ctx, s, m, f, n_steps, seed, tag, path0, batch, cfg->hedge_every,
-                           cfg->prec == MC_BF16_GEMM, w, w.log);
+  const bool bf16 = cfg->prec == MC_BF16_GEMM;
+  st = cv_fill_cache(ctx, s, m, f, n_steps, seed, tag, path0, batch, cfg->hedge_every, bf16, w);
+  if (st != MC_OK) return st;
+  st = cv_loss_grad_device(ctx, s, m, f, n_steps, 0, batch, batch, cfg->hedge_every, bf16, w,
+                           w.log);
   if (st != MC_OK) return st;
   std::vector<double> g(kMlpNParam), mom(n_moments(3));
   HIP_TRY(ctx, hipMemcpyAsync(g.data(), w.grad, kMlpNParam * 8, hipMemcpyDeviceToHost, s));
@@ -1988,12 +2040,13 @@ mc_status mc_cv_train(mc_context* ctx, const mc_model* m, const mc_payoff* f, ui
   if (cfg->steps == 0) return MC_OK;
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, MC_ERR_DEVICE, "hipSetDevice");
   const uint64_t B = cfg->batch;
-  const size_t bytes = cv_train_bytes(B, n_steps, cfg->steps, nullptr, nullptr);
+  const uint32_t n_seg = cv_segments(n_steps, cfg->hedge_every);
+  const size_t bytes = cv_train_bytes(B, n_steps, cfg->steps, n_train, n_seg, nullptr, nullptr);
   char* base = nullptr;
   st = get_ws(ctx, o, bytes, &base);
   if (st != MC_OK) return st;
   CvTrainWs w;
-  cv_train_bytes(B, n_steps, cfg->steps, &w, base);
+  cv_train_bytes(B, n_steps, cfg->steps, n_train, n_seg, &w, base);
   hipStream_t s = ctx->stream;
   st = cv_upload(ctx, s, w.b, weights_inout, dfac_table(m, n_steps));
   if (st != MC_OK) return st;
@@ -2002,10 +2055,13 @@ mc_status mc_cv_train(mc_context* ctx, const mc_model* m, const mc_payoff* f, ui
   const uint64_t n_batches = n_train / B;
   const uint32_t n_mom = (uint32_t)n_moments(3);
   const bool bf16 = cfg->prec == MC_BF16_GEMM;
+  // The fixed training set (stream tag 2), simulated once.
+  st = cv_fill_cache(ctx, s, m, f, n_steps, seed, 2, 0, n_train, cfg->hedge_every, bf16, w);
+  if (st != MC_OK) return st;
   for (uint32_t t = 0; t < cfg->steps; ++t) {
-    // Minibatches cycle through the fixed training set (stream tag 2).
-    const uint64_t path0 = (t % n_batches) * B;
-    st = cv_loss_grad_device(ctx, s, m, f, n_steps, seed, 2, path0, B, cfg->hedge_every, bf16, w,
+    // Minibatches cycle through the training set.
+    const uint64_t first = (t % n_batches) * B;
+    st = cv_loss_grad_device(ctx, s, m, f, n_steps, first, n_train, B, cfg->hedge_every, bf16, w,
                              w.log + (size_t)t * n_mom);
     if (st != MC_OK) return st;
     HIP_TRY(ctx, launch_adam(w.b.theta, w.m, w.v, w.grad, kMlpNParam, (int)t + 1, cfg->lr,

@@ -21,7 +21,12 @@
 // moves between layers. Layer 3 is a per-lane dot product plus one swap of
 // halves. tanh(x) = 2 / (1 + e^{-2x}) - 1 on v_exp_f32 / v_rcp_f32.
 //
-// Training (backward kernel): for each closed hedge segment the upstream
+// Training. The network's inputs (the features at each segment's opening
+// date) and the segment's price change do not depend on the weights, so
+// the training paths are simulated once into a feature cache; an Adam step
+// then runs only the network: a forward pass over every (segment, 32-path
+// tile) of the minibatch, the per-path hedged values and their moments,
+// and the backward pass. There, for each hedge segment the upstream
 // derivative dL/dDelta = g_b dSt with g_b = -(2/B)(Y_b - Ybar) is pushed
 // back through the network; dW2 = delta2^T H1 and dW1 = delta1^T [phi; 1]
 // are MFMA products over the wave's 32 paths after a transpose through LDS.
@@ -187,17 +192,176 @@ __device__ __forceinline__ float mlp_forward(const float (&phi)[8], const Op8<BF
   return part + __shfl_xor(part, 32, 64) + b3;
 }
 
-template <bool BF16, bool TRAIN>
-__global__ __launch_bounds__(kCvThreads) void cv_kernel(const CvParams P) {
+// Constants of the Heston step on the discounted log2-price (no rate in
+// its drift) and of the features, in FP32.
+struct HestonF {
+  float dt, kdt, kthdt, xi, rho, rhoc, a1, a2, S0, lnS0K, ln2, rdt2, inv_theta, inv_n, S0K;
+  __device__ explicit HestonF(const HestonParams& Hp)
+      : dt((float)Hp.dt),
+        kdt((float)(Hp.kappa * Hp.dt)),
+        kthdt((float)(Hp.kappa * Hp.theta * Hp.dt)),
+        xi((float)Hp.xi),
+        rho((float)Hp.rho),
+        rhoc((float)Hp.rho_c),
+        a1((float)(-0.5 * Hp.dt * 1.4426950408889634)),
+        a2(1.4426950408889634f),
+        S0((float)Hp.S0),
+        lnS0K((float)std::log(Hp.S0 / Hp.K)),
+        ln2(0.69314718055994531f),
+        rdt2((float)(Hp.r * Hp.dt * 1.4426950408889634)),   // log2 e^{r dt}
+        inv_theta((float)(1.0 / Hp.theta)),
+        inv_n((float)(1.0 / Hp.n_steps)),
+        S0K((float)(Hp.S0 / Hp.K)) {}
+
+  // Features at t_i (F_{t_i}-measurable): t/T, ln(S/K), v/theta, Abar/K - 1.
+  __device__ __forceinline__ void features(uint32_t i, float z, float v, float sumE,
+                                           float (&f)[4]) const {
+    const float fi = (float)i;
+    const float Abar = (i == 0) ? 1.0f : sumE * __builtin_amdgcn_rcpf(fi);   // running mean of S/S0
+    f[0] = fi * inv_n;
+    f[1] = (z + rdt2 * fi) * ln2 + lnS0K;          // ln(S_i / K)
+    f[2] = v * inv_theta;
+    f[3] = Abar * S0K - 1.0f;
+  }
+
+  // One full-truncation Euler step of (z~, v).
+  __device__ __forceinline__ void step(float& z, float& v, float Z1, float Z2) const {
+    const float vp = v > 0.f ? v : 0.f;
+    const float sq = __builtin_amdgcn_sqrtf(vp * dt);
+    const float Zs = rho * Z1 + rhoc * Z2;
+    z = z + a1 * vp + a2 * (sq * Zs);
+    v = v + (kthdt - kdt * vp) + xi * (sq * Z1);
+  }
+};
+
+// Fills the feature cache: one lane per path (h.n_paths paths from global
+// path h.path_offset, stream tag h.tag), the features at every segment's
+// opening date, the discounted price change over the segment and the
+// discounted Asian payoff.
+__global__ __launch_bounds__(kCvThreads) void cv_cache_kernel(const CvParams P) {
+  const HestonParams& Hp = P.h;
+  const uint64_t pid = (uint64_t)blockIdx.x * kCvThreads + threadIdx.x;
+  if (pid >= Hp.n_paths) return;       // no block-level synchronisation follows
+  const HestonF c(Hp);
+  const uint32_t n = Hp.n_steps, m = P.hedge_every;
+  const uint64_t S = P.c_stride;
+  const PathCounter pc = make_counter(Hp.path_offset + pid, Hp.tag, Hp.k0, Hp.k1);
+  float z = 0.f, v = (float)Hp.v0, sumE = 0.f, st_open = 0.f, Et = 1.f;
+  uint32_t k = 0;
+  Normals4<float> nz;
+  for (uint32_t i = 0; i < n; ++i) {
+    if (i % m == 0) {
+      float f[4];
+      c.features(i, z, v, sumE, f);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) P.c_phi[((size_t)k * 4 + q) * S + pid] = f[q];
+      st_open = Et;
+    }
+    if ((i & 1) == 0) nz = normals4<float>(philox(i >> 1, pc));
+    const float Z1 = (i & 1) ? nz.z[2] : nz.z[0];
+    const float Z2 = (i & 1) ? nz.z[3] : nz.z[1];
+    c.step(z, v, Z1, Z2);
+    Et = __builtin_amdgcn_exp2f(z);
+    sumE += Et * P.dfac[i + 1];
+    if ((i + 1) % m == 0 || i + 1 == n) {
+      P.c_dst[(size_t)k * S + pid] = c.S0 * (Et - st_open);
+      ++k;
+    }
+  }
+  const double A = (double)c.S0 * (double)sumE / (double)n;
+  P.c_pay[pid] = Hp.disc * (A > Hp.K ? A - Hp.K : 0.0);
+}
+
+// Layer-1 B fragment of a cached path (half 0: its features and the
+// constant 1; half 1: zeros).
+__device__ __forceinline__ void cached_phi(const CvParams& P, uint32_t k, uint64_t p, int half,
+                                           bool active, float (&phi)[8]) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) phi[j] = 0.f;
+  if (half == 0 && active) {
+    const uint64_t S = P.c_stride, c = P.c_first + p;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) phi[q] = P.c_phi[((size_t)k * 4 + q) * S + c];
+    phi[4] = 1.0f;
+  }
+}
+
+// Network forward pass over every (segment, 32-path tile) of the minibatch
+// (h.n_paths paths from cache path c_first): Delta to c_delta. Waves step
+// through the items, so a launch needs only enough of them to fill the chip.
+template <bool BF16>
+__global__ __launch_bounds__(kCvThreads) void cv_fwd_kernel(const CvParams P) {
   using FT = FragT<BF16>;
   __shared__ __attribute__((aligned(16))) FT s_w2f[kFragFloats];
   __shared__ __attribute__((aligned(16))) float s_lanec[kLaneFloats];
-  __shared__ __attribute__((aligned(16))) FT s_w2tf[TRAIN ? kFragFloats : 8];
-  __shared__ __attribute__((aligned(16))) FT tr[TRAIN ? kCvWaves : 1][TRAIN ? (64 * 32 + 8 * 32) : 8];
-  const HestonParams& Hp = P.h;
+  for (int i = threadIdx.x; i < kFragFloats; i += kCvThreads) s_w2f[i] = (FT)P.w2f[i];
+  for (int i = threadIdx.x; i < kLaneFloats; i += kCvThreads) s_lanec[i] = P.lanec[i];
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = lane & 31, half = lane >> 5;
+  Op8<BF16> w1a[2];
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb) {
+    float w[8];
+    load8(&P.w1f[(mb * 64 + lane) * 8], w);
+    w1a[mb] = op_from<BF16>(w);
+  }
+  const float b3 = P.theta[4544];
+  const uint64_t n = P.h.n_paths, ntiles = (n + 31) / 32;
+  const uint64_t items = ntiles * P.n_seg;
+  const uint64_t nw = (uint64_t)gridDim.x * kCvWaves;
+  for (uint64_t it = (uint64_t)blockIdx.x * kCvWaves + wave; it < items; it += nw) {
+    const uint32_t k = (uint32_t)(it / ntiles);
+    const uint64_t p = (it % ntiles) * 32 + row;
+    const bool active = p < n;
+    float phi[8], h1[32], h2[32];
+    cached_phi(P, k, p, half, active, phi);
+    const float d = mlp_forward<BF16>(phi, w1a, s_w2f, s_lanec, lane, b3, h1, h2);
+    if (half == 0 && active) P.c_delta[(size_t)k * n + p] = d;
+  }
+}
+
+// Hedged values of the minibatch's paths, H = sum_k Delta_k dSt_k in
+// segment order, and their moments (channels payoff, H, Y = payoff - H);
+// 32 paths per wave, as in the backward pass.
+__global__ __launch_bounds__(kCvThreads) void cv_values_kernel(const CvParams P) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = lane & 31, half = lane >> 5;
+  const uint64_t n = P.h.n_paths;
+  const uint64_t pid = ((uint64_t)blockIdx.x * kCvWaves + wave) * 32 + row;
+  const bool report = pid < n && half == 0;
+  double y[3] = {0.0, 0.0, 0.0};
+  if (report) {
+    const uint64_t S = P.c_stride, c = P.c_first + pid;
+    float H = 0.f;
+    for (uint32_t k = 0; k < P.n_seg; ++k)
+      H = __builtin_fmaf(P.c_delta[(size_t)k * n + pid], P.c_dst[(size_t)k * S + c], H);
+    const double pay = P.c_pay[c];
+    y[0] = pay;
+    y[1] = (double)H;
+    y[2] = pay - (double)H;
+  }
+  const bool finite = isfinite(y[0]) && isfinite(y[1]) && isfinite(y[2]);
+  if (report && P.path_out != nullptr) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) P.path_out[pid * 3 + q] = y[q];
+  }
+  block_moments<3, kCvThreads>(y, report && finite, report && !finite, P.partials, gridDim.x);
+}
+
+// Backward pass: a wave takes 32 paths of the minibatch through every hedge
+// segment, re-running the forward pass from the cached features.
+template <bool BF16>
+__global__ __launch_bounds__(kCvThreads) void cv_bwd_kernel(const CvParams P) {
+  using FT = FragT<BF16>;
+  __shared__ __attribute__((aligned(16))) FT s_w2f[kFragFloats];
+  __shared__ __attribute__((aligned(16))) float s_lanec[kLaneFloats];
+  __shared__ __attribute__((aligned(16))) FT s_w2tf[kFragFloats];
+  __shared__ __attribute__((aligned(16))) FT tr[kCvWaves][64 * 32 + 8 * 32];
   for (int i = threadIdx.x; i < kFragFloats; i += kCvThreads) {
     s_w2f[i] = (FT)P.w2f[i];
-    if constexpr (TRAIN) s_w2tf[i] = (FT)P.w2tf[i];
+    s_w2tf[i] = (FT)P.w2tf[i];
   }
   for (int i = threadIdx.x; i < kLaneFloats; i += kCvThreads) s_lanec[i] = P.lanec[i];
   __syncthreads();
@@ -206,7 +370,7 @@ __global__ __launch_bounds__(kCvThreads) void cv_kernel(const CvParams P) {
   const int row = lane & 31, half = lane >> 5;
   const uint64_t tile = (uint64_t)blockIdx.x * kCvWaves + wave;
   const uint64_t pid = tile * 32 + row;
-  const bool active = pid < Hp.n_paths;
+  const bool active = pid < P.h.n_paths;
   Op8<BF16> w1a[2];
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb) {
@@ -216,227 +380,157 @@ __global__ __launch_bounds__(kCvThreads) void cv_kernel(const CvParams P) {
   }
   const float b3 = P.theta[4544];
 
-  // Heston step on the discounted log2-price (no rate in its drift).
-  const float dt = (float)Hp.dt, kdt = (float)(Hp.kappa * Hp.dt);
-  const float kthdt = (float)(Hp.kappa * Hp.theta * Hp.dt), xi = (float)Hp.xi;
-  const float rho = (float)Hp.rho, rhoc = (float)Hp.rho_c;
-  const float a1 = (float)(-0.5 * Hp.dt * 1.4426950408889634), a2 = 1.4426950408889634f;
-  const float S0 = (float)Hp.S0;
-  const float lnS0K = (float)std::log(Hp.S0 / Hp.K), ln2 = 0.69314718055994531f;
-  const float rdt2 = (float)(Hp.r * Hp.dt * 1.4426950408889634);   // log2 e^{r dt}
-  const float inv_theta = (float)(1.0 / Hp.theta);
-  const float inv_n = (float)(1.0 / Hp.n_steps), S0K = (float)(Hp.S0 / Hp.K);
-  const uint32_t n = Hp.n_steps, m = P.hedge_every;
-  const PathCounter pc = make_counter(Hp.path_offset + pid, Hp.tag, Hp.k0, Hp.k1);
-
-  float g = 0.f;                       // upstream factor of this path (training)
-  if constexpr (TRAIN) {
-    if (active) {
-      const double ybar = P.ybar_mom[2 + 2] / P.ybar_mom[0];
-      g = (float)(P.g_scale * (P.y_path[pid * 3 + 2] - ybar));
-    }
+  float g = 0.f;                       // upstream factor of this path
+  if (active) {
+    const double ybar = P.ybar_mom[2 + 2] / P.ybar_mom[0];
+    g = (float)(P.g_scale * (P.y_path[pid * 3 + 2] - ybar));
   }
-  // Training accumulators.
   f32x16 gw2[2][2], gw1[2];
   float gw3[32], gb2[32], gb3 = 0.f;
-  if constexpr (TRAIN) {
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
+  for (int a = 0; a < 2; ++a) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) gw1[a][r] = 0.f;
+    for (int r = 0; r < 16; ++r) gw1[a][r] = 0.f;
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) gw2[a][b][r] = 0.f;
-    }
-#pragma unroll
-    for (int q = 0; q < 32; ++q) gw3[q] = gb2[q] = 0.f;
+      for (int r = 0; r < 16; ++r) gw2[a][b][r] = 0.f;
   }
+#pragma unroll
+  for (int q = 0; q < 32; ++q) gw3[q] = gb2[q] = 0.f;
 
-  float z = 0.f, v = (float)Hp.v0, sumE = 0.f, H = 0.f, delta = 0.f, st_open = 0.f;
-  float Et = 1.f;                      // St_i / S0 = 2^{z~_i}
-  float phi[8], h1[32], h2[32];
-  Normals4<float> nz;
-  for (uint32_t i = 0; i < n; ++i) {
-    if (i % m == 0) {
-      // Features at t_i (F_{t_i}-measurable).
-      const float fi = (float)i;
-      const float Abar = (i == 0) ? 1.0f : sumE * __builtin_amdgcn_rcpf(fi);      // running mean of S/S0
+  for (uint32_t k = 0; k < P.n_seg; ++k) {
+    float phi[8], h1[32], h2[32];
+    cached_phi(P, k, pid, half, active, phi);
+    mlp_forward<BF16>(phi, w1a, s_w2f, s_lanec, lane, b3, h1, h2);
+    const float dSt = active ? P.c_dst[(size_t)k * P.c_stride + P.c_first + pid] : 0.f;
+    const float gD = g * dSt;                      // dL/dDelta for this segment
+    if (half == 0) gb3 += gD;
+    float d2v[32], d1v[32];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) phi[j] = 0.f;
-      if (half == 0) {
-        phi[0] = fi * inv_n;
-        phi[1] = (z + rdt2 * fi) * ln2 + lnS0K;          // ln(S_i / K)
-        phi[2] = v * inv_theta;
-        phi[3] = Abar * S0K - 1.0f;
-        phi[4] = 1.0f;
-      }
-      delta = mlp_forward<BF16>(phi, w1a, s_w2f, s_lanec, lane, b3, h1, h2);
-      st_open = Et;
+    for (int q = 0; q < 32; ++q) {
+      gw3[q] = __builtin_fmaf(gD, h2[q], gw3[q]);
+      d2v[q] = gD * s_lanec[64 * 32 + lane * 32 + q] * (1.0f - h2[q] * h2[q]);
+      gb2[q] += d2v[q];
     }
-    if ((i & 1) == 0) nz = normals4<float>(philox(i >> 1, pc));
-    const float Z1 = (i & 1) ? nz.z[2] : nz.z[0];
-    const float Z2 = (i & 1) ? nz.z[3] : nz.z[1];
-    {
-      const float vp = v > 0.f ? v : 0.f;
-      const float sq = __builtin_amdgcn_sqrtf(vp * dt);
-      const float Zs = rho * Z1 + rhoc * Z2;
-      z = z + a1 * vp + a2 * (sq * Zs);
-      v = v + (kthdt - kdt * vp) + xi * (sq * Z1);
-    }
-    Et = __builtin_amdgcn_exp2f(z);
-    sumE += Et * P.dfac[i + 1];
-    if ((i + 1) % m == 0 || i + 1 == n) {
-      const float dSt = S0 * (Et - st_open);
-      H = __builtin_fmaf(delta, dSt, H);
-      if constexpr (TRAIN) {
-        const float gD = g * dSt;                      // dL/dDelta for this segment
-        if (half == 0) gb3 += gD;
-        float d2v[32], d1v[32];
-#pragma unroll
-        for (int q = 0; q < 32; ++q) {
-          gw3[q] = __builtin_fmaf(gD, h2[q], gw3[q]);
-          d2v[q] = gD * s_lanec[64 * 32 + lane * 32 + q] * (1.0f - h2[q] * h2[q]);
-          gb2[q] += d2v[q];
-        }
-        // delta1 = (W2^T delta2) (1 - h1^2)
-        f32x16 e1[2];
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-          for (int r = 0; r < 16; ++r) e1[mb][r] = 0.f;
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb) {
-          float bf[8];
-#pragma unroll
-          for (int j = 0; j < 8; ++j) bf[j] = d2v[(kb >> 1) * 16 + 8 * (kb & 1) + j];
-          const Op8<BF16> b = op_from<BF16>(bf);
-#pragma unroll
-          for (int mb = 0; mb < 2; ++mb)
-            mma16<BF16>(e1[mb], op_lds<BF16>(&s_w2tf[((mb * 4 + kb) * 64 + lane) * 8]), b);
-        }
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int q = mb * 16 + r;
-            d1v[q] = e1[mb][r] * (1.0f - h1[q] * h1[q]);
-          }
-        // dW2 += delta2^T H1 over the wave's paths (transpose through the
-        // wave's own LDS region; only this wave touches it, so ordering
-        // within the wave is all that is needed).
-        FT* T = tr[wave];
-        FT* TP = T + 64 * 32;
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-          for (int r = 0; r < 16; ++r) T[unit_of(mb, r, half) * 32 + row] = (FT)d2v[mb * 16 + r];
-        wave_lds_sync();
-        Op8<BF16> A2[2][2];
-#pragma unroll
-        for (int pk = 0; pk < 2; ++pk)
-#pragma unroll
-          for (int mb = 0; mb < 2; ++mb)
-            A2[pk][mb] = op_lds<BF16>(&T[(32 * mb + row) * 32 + 16 * pk + 8 * half]);
-        wave_lds_sync();
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-          for (int r = 0; r < 16; ++r) T[unit_of(mb, r, half) * 32 + row] = (FT)h1[mb * 16 + r];
-        wave_lds_sync();
-#pragma unroll
-        for (int pk = 0; pk < 2; ++pk)
-#pragma unroll
-          for (int nb = 0; nb < 2; ++nb) {
-            const Op8<BF16> b = op_lds<BF16>(&T[(32 * nb + row) * 32 + 16 * pk + 8 * half]);
-#pragma unroll
-            for (int mb = 0; mb < 2; ++mb) mma16<BF16>(gw2[mb][nb], A2[pk][mb], b);
-          }
-        wave_lds_sync();
-        // dW1ext += delta1^T [phi; 1] over the wave's paths.
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-          for (int r = 0; r < 16; ++r) T[unit_of(mb, r, half) * 32 + row] = (FT)d1v[mb * 16 + r];
-        if (half == 0) {
-#pragma unroll
-          for (int f = 0; f < 8; ++f) TP[f * 32 + row] = (FT)phi[f];
-        }
-        wave_lds_sync();
-#pragma unroll
-        for (int pk = 0; pk < 2; ++pk) {
-          const Op8<BF16> b =
-              row < 8 ? op_lds<BF16>(&TP[row * 32 + 16 * pk + 8 * half]) : op_zero<BF16>();
-#pragma unroll
-          for (int mb = 0; mb < 2; ++mb)
-            mma16<BF16>(gw1[mb], op_lds<BF16>(&T[(32 * mb + row) * 32 + 16 * pk + 8 * half]), b);
-        }
-        wave_lds_sync();
-      }
-    }
-  }
-
-  if constexpr (!TRAIN) {
-    double y[3] = {0.0, 0.0, 0.0};
-    const bool report = active && half == 0;
-    if (report) {
-      const double A = (double)S0 * (double)sumE / (double)n;
-      const double pay = Hp.disc * (A > Hp.K ? A - Hp.K : 0.0);
-      y[0] = pay;
-      y[1] = (double)H;
-      y[2] = pay - (double)H;
-    }
-    const bool finite = isfinite(y[0]) && isfinite(y[1]) && isfinite(y[2]);
-    if (report && P.path_out != nullptr) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) P.path_out[pid * 3 + c] = y[c];
-    }
-    block_moments<3, kCvThreads>(y, report && finite, report && !finite, P.partials, gridDim.x);
-  } else {
-    // Per-wave partial gradients in FP64, in the flat parameter layout
-    // W1[64][4], b1[64], W2[64][64], b2[64], W3[64], b3.
-    const uint64_t nw = (uint64_t)gridDim.x * kCvWaves;
-    const uint64_t wg = (uint64_t)blockIdx.x * kCvWaves + wave;
-    double* G = P.grad_partials;
-    auto put = [&](int slot, double val) { G[(uint64_t)slot * nw + wg] = val; };
+    // delta1 = (W2^T delta2) (1 - h1^2)
+    f32x16 e1[2];
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-      for (int nb = 0; nb < 2; ++nb)
+      for (int r = 0; r < 16; ++r) e1[mb][r] = 0.f;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int out = unit_of(mb, r, half), in = 32 * nb + row;
-          put(320 + out * 64 + in, (double)gw2[mb][nb][r]);
-        }
+    for (int kb = 0; kb < 4; ++kb) {
+      float bf[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) bf[j] = d2v[(kb >> 1) * 16 + 8 * (kb & 1) + j];
+      const Op8<BF16> b = op_from<BF16>(bf);
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+        mma16<BF16>(e1[mb], op_lds<BF16>(&s_w2tf[((mb * 4 + kb) * 64 + lane) * 8]), b);
+    }
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int q = mb * 16 + r;
+        d1v[q] = e1[mb][r] * (1.0f - h1[q] * h1[q]);
+      }
+    // dW2 += delta2^T H1 over the wave's paths (transpose through the
+    // wave's own LDS region; only this wave touches it, so ordering within
+    // the wave is all that is needed).
+    FT* T = tr[wave];
+    FT* TP = T + 64 * 32;
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) T[unit_of(mb, r, half) * 32 + row] = (FT)d2v[mb * 16 + r];
+    wave_lds_sync();
+    Op8<BF16> A2[2][2];
+#pragma unroll
+    for (int pk = 0; pk < 2; ++pk)
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+        A2[pk][mb] = op_lds<BF16>(&T[(32 * mb + row) * 32 + 16 * pk + 8 * half]);
+    wave_lds_sync();
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) T[unit_of(mb, r, half) * 32 + row] = (FT)h1[mb * 16 + r];
+    wave_lds_sync();
+#pragma unroll
+    for (int pk = 0; pk < 2; ++pk)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        const Op8<BF16> b = op_lds<BF16>(&T[(32 * nb + row) * 32 + 16 * pk + 8 * half]);
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) mma16<BF16>(gw2[mb][nb], A2[pk][mb], b);
+      }
+    wave_lds_sync();
+    // dW1ext += delta1^T [phi; 1] over the wave's paths.
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) T[unit_of(mb, r, half) * 32 + row] = (FT)d1v[mb * 16 + r];
+    if (half == 0) {
+#pragma unroll
+      for (int f = 0; f < 8; ++f) TP[f * 32 + row] = (FT)phi[f];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int pk = 0; pk < 2; ++pk) {
+      const Op8<BF16> b =
+          row < 8 ? op_lds<BF16>(&TP[row * 32 + 16 * pk + 8 * half]) : op_zero<BF16>();
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+        mma16<BF16>(gw1[mb], op_lds<BF16>(&T[(32 * mb + row) * 32 + 16 * pk + 8 * half]), b);
+    }
+    wave_lds_sync();
+  }
+
+  // Per-wave partial gradients in FP64, in the flat parameter layout
+  // W1[64][4], b1[64], W2[64][64], b2[64], W3[64], b3.
+  const uint64_t nw = (uint64_t)gridDim.x * kCvWaves;
+  const uint64_t wg = (uint64_t)blockIdx.x * kCvWaves + wave;
+  double* G = P.grad_partials;
+  auto put = [&](int slot, double val) { G[(uint64_t)slot * nw + wg] = val; };
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int out = unit_of(mb, r, half), in = 32 * nb + row;
+        put(320 + out * 64 + in, (double)gw2[mb][nb][r]);
+      }
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int u = unit_of(mb, r, half);
+      if (row < 4) put(u * 4 + row, (double)gw1[mb][r]);
+      if (row == 4) put(256 + u, (double)gw1[mb][r]);
+    }
+#pragma unroll
+  for (int q = 0; q < 32; ++q) {
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) {
+      gw3[q] += __shfl_xor(gw3[q], off, 64);
+      gb2[q] += __shfl_xor(gb2[q], off, 64);
+    }
+  }
+  if (row == 0) {
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int u = unit_of(mb, r, half);
-        if (row < 4) put(u * 4 + row, (double)gw1[mb][r]);
-        if (row == 4) put(256 + u, (double)gw1[mb][r]);
+        put(4416 + u, (double)gb2[mb * 16 + r]);
+        put(4480 + u, (double)gw3[mb * 16 + r]);
       }
-#pragma unroll
-    for (int q = 0; q < 32; ++q) {
-#pragma unroll
-      for (int off = 16; off > 0; off >>= 1) {
-        gw3[q] += __shfl_xor(gw3[q], off, 64);
-        gb2[q] += __shfl_xor(gb2[q], off, 64);
-      }
-    }
-    if (row == 0) {
-#pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int u = unit_of(mb, r, half);
-          put(4416 + u, (double)gb2[mb * 16 + r]);
-          put(4480 + u, (double)gw3[mb * 16 + r]);
-        }
-    }
-    const double s3 = wave_sum((double)gb3);
-    if (lane == 0) put(4544, s3);
   }
+  const double s3 = wave_sum((double)gb3);
+  if (lane == 0) put(4544, s3);
 }
 
 // Evaluation kernel, 64 paths per wave: lane l follows its own path, and
@@ -603,26 +697,43 @@ hipError_t launch_cv_price(const CvParams& p, hipStream_t s, uint32_t* n_blocks)
   return hipGetLastError();
 }
 
-// Forward pass with 32 paths per wave (the training kernel's tiling): twice
-// the waves of the evaluation kernel, for minibatches too small to fill the
-// chip with 64-path waves. Same network function per path.
-hipError_t launch_cv_forward32(const CvParams& p, hipStream_t s, uint32_t* n_blocks) {
+hipError_t launch_cv_cache(const CvParams& p, hipStream_t s) {
+  const uint32_t nb = (uint32_t)((p.h.n_paths + kCvThreads - 1) / kCvThreads);
+  if (nb == 0 || p.n_seg == 0 || p.h.n_paths > p.c_stride) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(cv_cache_kernel, dim3(nb), dim3(kCvThreads), 0, s, p);
+  return hipGetLastError();
+}
+
+// Enough waves to fill the chip at the kernel's occupancy; each steps
+// through the (segment, tile) items.
+hipError_t launch_cv_forward(const CvParams& p, hipStream_t s) {
+  const uint64_t items = (p.h.n_paths + 31) / 32 * p.n_seg;
+  const uint64_t need = (items + kCvWaves - 1) / kCvWaves;
+  const uint32_t nb = (uint32_t)(need < 2048 ? need : 2048);
+  if (nb == 0 || p.c_first + p.h.n_paths > p.c_stride) return hipErrorInvalidValue;
+  if (p.bf16)
+    hipLaunchKernelGGL((cv_fwd_kernel<true>), dim3(nb), dim3(kCvThreads), 0, s, p);
+  else
+    hipLaunchKernelGGL((cv_fwd_kernel<false>), dim3(nb), dim3(kCvThreads), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_cv_values(const CvParams& p, hipStream_t s, uint32_t* n_blocks) {
   const uint32_t nb = (uint32_t)((p.h.n_paths + kCvTrainPathsPerBlock - 1) / kCvTrainPathsPerBlock);
   *n_blocks = nb;
-  if (p.bf16)
-    hipLaunchKernelGGL((cv_kernel<true, false>), dim3(nb), dim3(kCvThreads), 0, s, p);
-  else
-    hipLaunchKernelGGL((cv_kernel<false, false>), dim3(nb), dim3(kCvThreads), 0, s, p);
+  if (nb == 0 || p.c_first + p.h.n_paths > p.c_stride) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(cv_values_kernel, dim3(nb), dim3(kCvThreads), 0, s, p);
   return hipGetLastError();
 }
 
 hipError_t launch_cv_backward(const CvParams& p, hipStream_t s, uint32_t* n_blocks) {
   const uint32_t nb = (uint32_t)((p.h.n_paths + kCvTrainPathsPerBlock - 1) / kCvTrainPathsPerBlock);
   *n_blocks = nb;
+  if (nb == 0 || p.c_first + p.h.n_paths > p.c_stride) return hipErrorInvalidValue;
   if (p.bf16)
-    hipLaunchKernelGGL((cv_kernel<true, true>), dim3(nb), dim3(kCvThreads), 0, s, p);
+    hipLaunchKernelGGL((cv_bwd_kernel<true>), dim3(nb), dim3(kCvThreads), 0, s, p);
   else
-    hipLaunchKernelGGL((cv_kernel<false, true>), dim3(nb), dim3(kCvThreads), 0, s, p);
+    hipLaunchKernelGGL((cv_bwd_kernel<false>), dim3(nb), dim3(kCvThreads), 0, s, p);
   return hipGetLastError();
 }
 

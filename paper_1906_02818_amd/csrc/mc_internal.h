@@ -207,15 +207,30 @@ struct CvParams {
   double* grad_partials;     // [kMlpNParam][n_waves] FP64
   double* partials;
   double* path_out;
+  // Feature cache of the training paths, one entry per hedge segment k (the
+  // network's inputs do not depend on its weights, so each training path is
+  // simulated once per training run, not once per Adam step).
+  float* c_phi;              // [n_seg][4][c_stride] features at the segment's opening date
+  float* c_dst;              // [n_seg][c_stride] discounted price change over the segment
+  double* c_pay;             // [c_stride] discounted payoff
+  float* c_delta;            // [n_seg][n_paths] network output on the minibatch
+  uint64_t c_stride;         // paths held by the cache
+  uint64_t c_first;          // the minibatch's first path within the cache
+  uint32_t n_seg;            // ceil(n_steps / hedge_every)
 };
 constexpr int kCvPathsPerBlock = 256;       // evaluation: 4 waves of 64 paths
-constexpr int kCvTrainPathsPerBlock = 128;  // backward: 4 waves of 32 paths
+constexpr int kCvTrainPathsPerBlock = 128;  // training: 4 waves of 32 paths
 // Fragment layout of the weights, built on the device from theta.
 constexpr int kW1fFloats = 2 * 64 * 8, kW2fFloats = 2 * 4 * 64 * 8, kLanecFloats = 2 * 64 * 32;
 hipError_t launch_cv_pack(const float* theta, float* w1f, float* w2f, float* w2tf, float* lanec,
                           hipStream_t s);
 hipError_t launch_cv_price(const CvParams& p, hipStream_t s, uint32_t* n_blocks);
-hipError_t launch_cv_forward32(const CvParams& p, hipStream_t s, uint32_t* n_blocks);
+// Training on the feature cache: fill it (h.n_paths paths from h.path_offset),
+// the network on every (segment, 32-path tile) of the minibatch, the per-path
+// hedged values and their moments, and the gradient partials.
+hipError_t launch_cv_cache(const CvParams& p, hipStream_t s);
+hipError_t launch_cv_forward(const CvParams& p, hipStream_t s);
+hipError_t launch_cv_values(const CvParams& p, hipStream_t s, uint32_t* n_blocks);
 hipError_t launch_cv_backward(const CvParams& p, hipStream_t s, uint32_t* n_blocks);
 hipError_t launch_adam(float* theta, float* m, float* v, const double* grad, int n, int t,
                        double lr, double b1, double b2, double eps, hipStream_t s);
