@@ -249,7 +249,9 @@ typedef struct {
  * of stream tag 2 (cycled in minibatches) to minimise the batch variance of
  * Y = payoff - H. weights_inout: host [MC_MLP_NPARAM] FP32, initial weights
  * in, trained weights out. loss_log: host [steps] or NULL. Heston Asian
- * call only. */
+ * call only. The training paths are simulated once into a device cache of
+ * the network's inputs, n_train * ceil(n_steps / hedge_every) * 20 bytes
+ * plus 8 bytes per path (MC_ERR_OOM if it cannot be allocated). */
 mc_status mc_cv_train(mc_context *ctx, const mc_model *model, const mc_payoff *payoff,
                       uint64_t n_train, uint32_t n_steps, uint64_t seed,
                       const mc_adam_cfg *cfg, float *weights_inout, float *loss_log);

@@ -747,7 +747,7 @@ mc_status heston_cv_price(mc_context* ctx, const mc_model* m, const mc_payoff* f
 struct CvTrainWs {
   char* eval_base;          // moment layout with per-path values
   size_t eval_bytes;
-  double* grad_partials;    // [kMlpNParam][n_waves]
+  double* grad_partials;    // [kMlpNParam][n_blocks]
   double* grad;             // [kMlpNParam]
   CvBuffers b;
   float *m, *v;             // Adam moments
@@ -763,8 +763,7 @@ uint32_t cv_segments(uint32_t n_steps, uint32_t hedge_every) {
 size_t cv_train_bytes(uint64_t batch, uint32_t n_steps, uint32_t steps, uint64_t n_cache,
                       uint32_t n_seg, CvTrainWs* w, char* base) {
   const RunLayout Lay = layout_for(batch, 3, true, kCvTrainPathsPerBlock);
-  const uint64_t n_waves =
-      (batch + kCvTrainPathsPerBlock - 1) / kCvTrainPathsPerBlock * (kCvTrainPathsPerBlock / 32);
+  const uint64_t n_blocks = (batch + kCvTrainPathsPerBlock - 1) / kCvTrainPathsPerBlock;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     char* p = base ? base + off : nullptr;
@@ -772,7 +771,7 @@ size_t cv_train_bytes(uint64_t batch, uint32_t n_steps, uint32_t steps, uint64_t
     return p;
   };
   char* e = take(Lay.bytes);
-  char* gp = take((size_t)kMlpNParam * n_waves * 8);
+  char* gp = take((size_t)kMlpNParam * n_blocks * 8);
   char* g = take((size_t)kMlpNParam * 8);
   char* cv = take(cv_extra_bytes(n_steps));
   char* mm = take((size_t)kMlpNParam * 4);
@@ -837,7 +836,7 @@ mc_status cv_loss_grad_device(mc_context* ctx, hipStream_t s, const mc_model* m,
   o.hip_stream = s;
   const RunLayout Lay = layout_for(batch, 3, true, kCvTrainPathsPerBlock);
   double* partials = (double*)w.eval_base;
-  double* mom = (double*)(w.eval_base + Lay.off_mom);
+  double* mom = log_row ? log_row : (double*)(w.eval_base + Lay.off_mom);
   double* ypath = (double*)(w.eval_base + Lay.off_path);
   CvParams p = cv_cache_params(cv_params(m, f, batch, n_steps, 0, o, 0, hedge_every, bf16, w.b),
                                w, n_cache, cv_segments(n_steps, hedge_every));
@@ -848,16 +847,13 @@ mc_status cv_loss_grad_device(mc_context* ctx, hipStream_t s, const mc_model* m,
   HIP_TRY(ctx, launch_cv_forward(p, s));
   HIP_TRY(ctx, launch_cv_values(p, s, &nb));
   HIP_TRY(ctx, launch_final_reduce(partials, nb, Lay.n_mom, mom, s));
-  if (log_row)
-    HIP_TRY(ctx, hipMemcpyAsync(log_row, mom, Lay.n_mom * 8, hipMemcpyDeviceToDevice, s));
   p.path_out = nullptr;
   p.ybar_mom = mom;
   p.y_path = ypath;
   p.g_scale = -2.0 / (double)batch;
   p.grad_partials = w.grad_partials;
-  HIP_TRY(ctx, launch_cv_backward(p, s, &nb));
-  const uint32_t n_waves = nb * (kCvTrainPathsPerBlock / 32);
-  HIP_TRY(ctx, launch_final_reduce(w.grad_partials, n_waves, kMlpNParam, w.grad, s));
+  HIP_TRY(ctx, launch_cv_backward(p, s, &nb));   // one partial per block
+  HIP_TRY(ctx, launch_final_reduce(w.grad_partials, nb, kMlpNParam, w.grad, s));
   return MC_OK;
 }
 

@@ -352,13 +352,29 @@ __global__ __launch_bounds__(kCvThreads) void cv_values_kernel(const CvParams P)
 
 // Backward pass: a wave takes 32 paths of the minibatch through every hedge
 // segment, re-running the forward pass from the cached features.
+//
+// Every weight gradient is a product over the wave's 32 paths on the
+// matrix cores, accumulated in two register sets:
+//   gw2 = delta2^T H1 (64 x 64);
+//   gx  = 64 units x 32 columns holding, by column, db2 = delta2^T 1,
+//         dW3 = H2^T gD, dW1 = delta1^T phi (4 columns) and db1 = delta1^T 1,
+//         each product with a B operand that is zero outside its columns.
+// A path-major operand (delta2, H2, H1, delta1) passes through the wave's
+// LDS region to become unit-major; the column operands (gD, phi, 1) are one
+// row each of a small second region.
 template <bool BF16>
-__global__ __launch_bounds__(kCvThreads) void cv_bwd_kernel(const CvParams P) {
+__device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
   using FT = FragT<BF16>;
-  __shared__ __attribute__((aligned(16))) FT s_w2f[kFragFloats];
-  __shared__ __attribute__((aligned(16))) float s_lanec[kLaneFloats];
-  __shared__ __attribute__((aligned(16))) FT s_w2tf[kFragFloats];
-  __shared__ __attribute__((aligned(16))) FT tr[kCvWaves][64 * 32 + 8 * 32];
+  // One LDS area: the weight fragments and the waves' transpose regions,
+  // reused after the segment loop for the block's gradient sum.
+  constexpr int kTr = 64 * 32 + 8 * 32;
+  constexpr size_t kLds = 2 * kFragFloats * sizeof(FT) + kLaneFloats * 4 + kCvWaves * kTr * sizeof(FT);
+  static_assert(kLds >= kMlpNParam * sizeof(double), "LDS too small for the gradient sum");
+  __shared__ __attribute__((aligned(16))) unsigned char lds[kLds];
+  FT* s_w2f = (FT*)lds;
+  FT* s_w2tf = s_w2f + kFragFloats;
+  float* s_lanec = (float*)(lds + 2 * kFragFloats * sizeof(FT));
+  FT* tr = (FT*)(lds + 2 * kFragFloats * sizeof(FT) + kLaneFloats * 4);
   for (int i = threadIdx.x; i < kFragFloats; i += kCvThreads) {
     s_w2f[i] = (FT)P.w2f[i];
     s_w2tf[i] = (FT)P.w2tf[i];
@@ -379,84 +395,85 @@ __global__ __launch_bounds__(kCvThreads) void cv_bwd_kernel(const CvParams P) {
     w1a[mb] = op_from<BF16>(w);
   }
   const float b3 = P.theta[4544];
+  const float col0 = row == 0 ? 1.0f : 0.0f;   // B operand entry: ones in column 0
 
   float g = 0.f;                       // upstream factor of this path
   if (active) {
     const double ybar = P.ybar_mom[2 + 2] / P.ybar_mom[0];
     g = (float)(P.g_scale * (P.y_path[pid * 3 + 2] - ybar));
   }
-  f32x16 gw2[2][2], gw1[2];
-  float gw3[32], gb2[32], gb3 = 0.f;
+  f32x16 gw2[2][2], gx[2];
+  float gb3 = 0.f;
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) gw1[a][r] = 0.f;
+    for (int r = 0; r < 16; ++r) gx[a][r] = 0.f;
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) gw2[a][b][r] = 0.f;
   }
+  FT* T = tr + wave * kTr;   // [64 units][32 paths]
+  FT* TP = T + 64 * 32;      // [8 columns][32 paths]
+  // Unit-major A fragments of the region T (32 units of block mb x 8 paths).
+  auto a_frag = [&](int pk, int mb) {
+    return op_lds<BF16>(&T[(32 * mb + row) * 32 + 16 * pk + 8 * half]);
+  };
+  auto to_T = [&](const float (&x)[32]) {
 #pragma unroll
-  for (int q = 0; q < 32; ++q) gw3[q] = gb2[q] = 0.f;
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) T[unit_of(mb, r, half) * 32 + row] = (FT)x[mb * 16 + r];
+  };
 
+  // The steps are ordered so that few path-major vectors are live at once.
   for (uint32_t k = 0; k < P.n_seg; ++k) {
-    float phi[8], h1[32], h2[32];
-    cached_phi(P, k, pid, half, active, phi);
-    mlp_forward<BF16>(phi, w1a, s_w2f, s_lanec, lane, b3, h1, h2);
+    float h1[32], h2[32];
+    {
+      float phi[8];
+      cached_phi(P, k, pid, half, active, phi);
+      mlp_forward<BF16>(phi, w1a, s_w2f, s_lanec, lane, b3, h1, h2);
+    }
     const float dSt = active ? P.c_dst[(size_t)k * P.c_stride + P.c_first + pid] : 0.f;
     const float gD = g * dSt;                      // dL/dDelta for this segment
     if (half == 0) gb3 += gD;
-    float d2v[32], d1v[32];
+    // dW3 (column 1 of gx) += H2^T gD.
+    to_T(h2);
+    if (half == 0) TP[1 * 32 + row] = (FT)gD;
+    wave_lds_sync();
 #pragma unroll
-    for (int q = 0; q < 32; ++q) {
-      gw3[q] = __builtin_fmaf(gD, h2[q], gw3[q]);
+    for (int pk = 0; pk < 2; ++pk) {
+      const Op8<BF16> b = row == 1 ? op_lds<BF16>(&TP[1 * 32 + 16 * pk + 8 * half])
+                                   : op_zero<BF16>();
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb) mma16<BF16>(gx[mb], a_frag(pk, mb), b);
+    }
+    wave_lds_sync();
+    // delta2 = gD W3 (1 - h2^2), into unit-major A fragments;
+    // db2 (column 0 of gx) += delta2^T 1.
+    float d2v[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q)
       d2v[q] = gD * s_lanec[64 * 32 + lane * 32 + q] * (1.0f - h2[q] * h2[q]);
-      gb2[q] += d2v[q];
-    }
-    // delta1 = (W2^T delta2) (1 - h1^2)
-    f32x16 e1[2];
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) e1[mb][r] = 0.f;
-#pragma unroll
-    for (int kb = 0; kb < 4; ++kb) {
-      float bf[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) bf[j] = d2v[(kb >> 1) * 16 + 8 * (kb & 1) + j];
-      const Op8<BF16> b = op_from<BF16>(bf);
-#pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
-        mma16<BF16>(e1[mb], op_lds<BF16>(&s_w2tf[((mb * 4 + kb) * 64 + lane) * 8]), b);
-    }
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int q = mb * 16 + r;
-        d1v[q] = e1[mb][r] * (1.0f - h1[q] * h1[q]);
-      }
-    // dW2 += delta2^T H1 over the wave's paths (transpose through the
-    // wave's own LDS region; only this wave touches it, so ordering within
-    // the wave is all that is needed).
-    FT* T = tr[wave];
-    FT* TP = T + 64 * 32;
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) T[unit_of(mb, r, half) * 32 + row] = (FT)d2v[mb * 16 + r];
+    to_T(d2v);
     wave_lds_sync();
     Op8<BF16> A2[2][2];
+    {
+      float ones[8];
 #pragma unroll
-    for (int pk = 0; pk < 2; ++pk)
+      for (int j = 0; j < 8; ++j) ones[j] = col0;
+      const Op8<BF16> b = op_from<BF16>(ones);
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
-        A2[pk][mb] = op_lds<BF16>(&T[(32 * mb + row) * 32 + 16 * pk + 8 * half]);
+      for (int pk = 0; pk < 2; ++pk)
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+          A2[pk][mb] = a_frag(pk, mb);
+          mma16<BF16>(gx[mb], A2[pk][mb], b);
+        }
+    }
     wave_lds_sync();
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) T[unit_of(mb, r, half) * 32 + row] = (FT)h1[mb * 16 + r];
+    // dW2 += delta2^T H1.
+    to_T(h1);
     wave_lds_sync();
 #pragma unroll
     for (int pk = 0; pk < 2; ++pk)
@@ -467,70 +484,101 @@ __global__ __launch_bounds__(kCvThreads) void cv_bwd_kernel(const CvParams P) {
         for (int mb = 0; mb < 2; ++mb) mma16<BF16>(gw2[mb][nb], A2[pk][mb], b);
       }
     wave_lds_sync();
-    // dW1ext += delta1^T [phi; 1] over the wave's paths.
+    // delta1 = (W2^T delta2) (1 - h1^2)
+    float d1v[32];
+    {
+      f32x16 e1[2];
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
+      for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) T[unit_of(mb, r, half) * 32 + row] = (FT)d1v[mb * 16 + r];
+        for (int r = 0; r < 16; ++r) e1[mb][r] = 0.f;
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb) {
+        float bf[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) bf[j] = d2v[(kb >> 1) * 16 + 8 * (kb & 1) + j];
+        const Op8<BF16> b = op_from<BF16>(bf);
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+          mma16<BF16>(e1[mb], op_lds<BF16>(&s_w2tf[((mb * 4 + kb) * 64 + lane) * 8]), b);
+      }
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int q = mb * 16 + r;
+          d1v[q] = e1[mb][r] * (1.0f - h1[q] * h1[q]);
+        }
+    }
+    // dW1 and db1 (columns 2..6 of gx) += delta1^T [phi, 1].
+    to_T(d1v);
     if (half == 0) {
+      const uint64_t S = P.c_stride, c = P.c_first + pid;
 #pragma unroll
-      for (int f = 0; f < 8; ++f) TP[f * 32 + row] = (FT)phi[f];
+      for (int q = 0; q < 4; ++q)
+        TP[(2 + q) * 32 + row] = active ? (FT)P.c_phi[((size_t)k * 4 + q) * S + c] : (FT)0.f;
+      TP[6 * 32 + row] = active ? (FT)1.0f : (FT)0.f;
     }
     wave_lds_sync();
 #pragma unroll
     for (int pk = 0; pk < 2; ++pk) {
-      const Op8<BF16> b =
-          row < 8 ? op_lds<BF16>(&TP[row * 32 + 16 * pk + 8 * half]) : op_zero<BF16>();
+      const Op8<BF16> b = (row >= 2 && row <= 6)
+                              ? op_lds<BF16>(&TP[row * 32 + 16 * pk + 8 * half])
+                              : op_zero<BF16>();
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
-        mma16<BF16>(gw1[mb], op_lds<BF16>(&T[(32 * mb + row) * 32 + 16 * pk + 8 * half]), b);
+      for (int mb = 0; mb < 2; ++mb) mma16<BF16>(gx[mb], a_frag(pk, mb), b);
     }
     wave_lds_sync();
   }
 
-  // Per-wave partial gradients in FP64, in the flat parameter layout
-  // W1[64][4], b1[64], W2[64][64], b2[64], W3[64], b3.
-  const uint64_t nw = (uint64_t)gridDim.x * kCvWaves;
-  const uint64_t wg = (uint64_t)blockIdx.x * kCvWaves + wave;
-  double* G = P.grad_partials;
-  auto put = [&](int slot, double val) { G[(uint64_t)slot * nw + wg] = val; };
+  // The block's gradient in FP64, in the flat parameter layout W1[64][4],
+  // b1[64], W2[64][64], b2[64], W3[64], b3: the waves add theirs in wave
+  // order into LDS (each slot has one writer per wave), then the block
+  // writes one partial per parameter.
+  double* red = (double*)lds;
+  __syncthreads();                     // every wave has left the segment loop
+  for (int w = 0; w < kCvWaves; ++w) {
+    if (wave == w) {
+      auto put = [&](int slot, double val) { red[slot] = (w == 0 ? 0.0 : red[slot]) + val; };
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb)
+      for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb)
+        for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int out = unit_of(mb, r, half), in = 32 * nb + row;
-        put(320 + out * 64 + in, (double)gw2[mb][nb][r]);
-      }
+          for (int r = 0; r < 16; ++r) {
+            const int out = unit_of(mb, r, half), in = 32 * nb + row;
+            put(320 + out * 64 + in, (double)gw2[mb][nb][r]);
+          }
+      // gx: lane column `row`, unit u(mb, r, half).
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb)
+      for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int u = unit_of(mb, r, half);
-      if (row < 4) put(u * 4 + row, (double)gw1[mb][r]);
-      if (row == 4) put(256 + u, (double)gw1[mb][r]);
+        for (int r = 0; r < 16; ++r) {
+          const int u = unit_of(mb, r, half);
+          const double x = (double)gx[mb][r];
+          if (row == 0) put(4416 + u, x);                      // b2
+          else if (row == 1) put(4480 + u, x);                 // W3
+          else if (row <= 5) put(u * 4 + (row - 2), x);        // W1
+          else if (row == 6) put(256 + u, x);                  // b1
+        }
+      const double s3 = wave_sum((double)gb3);
+      if (lane == 0) put(4544, s3);
     }
-#pragma unroll
-  for (int q = 0; q < 32; ++q) {
-#pragma unroll
-    for (int off = 16; off > 0; off >>= 1) {
-      gw3[q] += __shfl_xor(gw3[q], off, 64);
-      gb2[q] += __shfl_xor(gb2[q], off, 64);
-    }
+    __syncthreads();
   }
-  if (row == 0) {
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int u = unit_of(mb, r, half);
-        put(4416 + u, (double)gb2[mb * 16 + r]);
-        put(4480 + u, (double)gw3[mb * 16 + r]);
-      }
-  }
-  const double s3 = wave_sum((double)gb3);
-  if (lane == 0) put(4544, s3);
+  for (int i = threadIdx.x; i < kMlpNParam; i += kCvThreads)
+    P.grad_partials[(uint64_t)i * gridDim.x + blockIdx.x] = red[i];
+}
+
+// The BF16 form fits two waves per SIMD (256 VGPRs, LDS for three
+// workgroups); the FP32 form's LDS allows one workgroup per CU.
+__global__ __launch_bounds__(kCvThreads) __attribute__((amdgpu_waves_per_eu(2))) void
+cv_bwd_kernel_bf16(const CvParams P) {
+  cv_bwd_body<true>(P);
+}
+
+__global__ __launch_bounds__(kCvThreads) void cv_bwd_kernel_fp32(const CvParams P) {
+  cv_bwd_body<false>(P);
 }
 
 // Evaluation kernel, 64 paths per wave: lane l follows its own path, and
@@ -731,9 +779,9 @@ hipError_t launch_cv_backward(const CvParams& p, hipStream_t s, uint32_t* n_bloc
   *n_blocks = nb;
   if (nb == 0 || p.c_first + p.h.n_paths > p.c_stride) return hipErrorInvalidValue;
   if (p.bf16)
-    hipLaunchKernelGGL((cv_bwd_kernel<true>), dim3(nb), dim3(kCvThreads), 0, s, p);
+    hipLaunchKernelGGL(cv_bwd_kernel_bf16, dim3(nb), dim3(kCvThreads), 0, s, p);
   else
-    hipLaunchKernelGGL((cv_bwd_kernel<false>), dim3(nb), dim3(kCvThreads), 0, s, p);
+    hipLaunchKernelGGL(cv_bwd_kernel_fp32, dim3(nb), dim3(kCvThreads), 0, s, p);
   return hipGetLastError();
 }
 

@@ -204,7 +204,7 @@ struct CvParams {
   const double* ybar_mom;    // moments of the forward pass (Ybar = sum y2 / n)
   const double* y_path;      // per-path values of that pass, [n_paths][3] (Y is channel 2)
   double g_scale;            // -2 / B
-  double* grad_partials;     // [kMlpNParam][n_waves] FP64
+  double* grad_partials;     // [kMlpNParam][n_blocks] FP64
   double* partials;
   double* path_out;
   // Feature cache of the training paths, one entry per hedge segment k (the

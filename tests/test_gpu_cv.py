@@ -167,6 +167,27 @@ def test_adam_steps_match_oracle(ctx):
     assert d.max() <= 2 * lr * steps + 1e-6
 
 
+@pytest.mark.parametrize("prec", [mc.MC_FP32, mc.MC_BF16_GEMM])
+def test_training_minibatches_are_the_cached_training_paths(ctx, prec):
+    # mc_cv_train simulates its training set (stream tag 2) once and takes
+    # minibatch t from paths (t mod n_batches) B onwards; its loss at step t
+    # must equal the loss of mc_cv_loss_grad on those paths at the step's
+    # weights, bit for bit (same kernels, same arithmetic). Ragged last
+    # hedge segment: n = 10, m = 3.
+    th0 = weights(0.2, seed=8)
+    B, n, m = 256, 10, 3
+    w1, log1 = mc.mc_cv_train(ctx, MODEL, PAY, 3 * B, n, SEED, th0, steps=1, batch=B,
+                              hedge_every=m, prec=prec)
+    w2, log2 = mc.mc_cv_train(ctx, MODEL, PAY, 3 * B, n, SEED, th0, steps=2, batch=B,
+                              hedge_every=m, prec=prec)
+    l0, _ = mc.mc_cv_loss_grad(ctx, MODEL, PAY, n, SEED, 2, 0, B, th0, hedge_every=m, prec=prec)
+    l1, _ = mc.mc_cv_loss_grad(ctx, MODEL, PAY, n, SEED, 2, B, B, w1, hedge_every=m, prec=prec)
+    say(f"  losses train {log2} loss_grad {l0:.6f} {l1:.6f}")
+    assert log1[0] == np.float32(l0) and log2[0] == np.float32(l0)
+    assert log2[1] == np.float32(l1)
+    assert not np.array_equal(w1, w2)
+
+
 def test_trained_hedge_reduces_variance_on_fresh_paths(ctx):
     n = 64
     th0 = synth.glorot_mlp()
