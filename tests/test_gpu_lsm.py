@@ -88,6 +88,8 @@ CASES = [
     (4, 0.4, PUT, 100.0, 0.00, 1.0, 8, 1, 1, 30_000, 0, 0),              # 5
     (2, 0.0, CALL, 95.0, 0.06, 2.0, 5, 3, 3, 30_011, 0, 0),              # 10
     (2, 0.3, MAXC, 100.0, 0.10, 3.0, 9, 1, 2, 20_000, (1 << 33) + 5, 3),  # offset and tag
+    (1, 0.0, PUT, 100.0, 0.00, 1.0, 7, 1, 3, 40_000, 0, 0),              # 4, dates in 4s
+    (3, 0.2, MAXC, 100.0, 0.05, 1.0, 6, 1, 2, 30_000, 0, 0),             # 11, dates in 4s
 ]
 
 
