@@ -1704,7 +1704,7 @@ mc_status mc_price_qmc(mc_context* ctx, const mc_model* m, const mc_payoff* f, u
     // One replicate with per-path values: the plain basket run.
     BasketQmc q{ctx->qmc_buf, ctx->qmc_buf + (size_t)dims * 32, 0.0};
     HIP_TRY(ctx, launch_qmc_shifts((uint32_t)seed, (uint32_t)(seed >> 32), o0.stream_tag + 6u, 0,
-                                   dims, (uint32_t*)q.shift, s));
+                                   1, dims, (uint32_t*)q.shift, s));
     mc_result pr{};
     st = basket_price(ctx, m, f, n_points, n_steps, seed, o0, &pr, nullptr, 0.0, &q);
     if (st != MC_OK) return st;
@@ -1712,8 +1712,8 @@ mc_status mc_price_qmc(mc_context* ctx, const mc_model* m, const mc_payoff* f, u
     r.replicate_geo[0] = q.geo_mean;
     r.kernel_ms = pr.kernel_ms;
   } else {
-    // All replicates back to back on the stream: their digital shifts, path
-    // kernels and fixed-order reductions, one synchronisation at the end.
+    // All replicates in one launch each of the shift, path and reduction
+    // kernels, one synchronisation at the end.
     const BasketQmc q0{ctx->qmc_buf, ctx->qmc_buf + (size_t)dims * 32, 0.0};
     BasketParams p{};
     int prec = BK_FP32;
@@ -1722,29 +1722,27 @@ mc_status mc_price_qmc(mc_context* ctx, const mc_model* m, const mc_payoff* f, u
     if (st != MC_OK) return st;
     const RunLayout Lay = layout_for(n_points, 3, false);
     const size_t b_shift = align256((size_t)n_replicates * dims * sizeof(uint32_t));
-    const size_t b_part = align256((size_t)Lay.n_mom * Lay.n_blocks * sizeof(double));
+    const size_t b_part = align256((size_t)n_replicates * Lay.n_mom * Lay.n_blocks * sizeof(double));
     const size_t b_mom = align256((size_t)n_replicates * Lay.n_mom * sizeof(double));
     char* base = nullptr;
-    st = get_mlmc_buf(ctx, b_shift + (size_t)n_replicates * b_part + b_mom, &base);
+    st = get_mlmc_buf(ctx, b_shift + b_part + b_mom, &base);
     if (st != MC_OK) return st;
     st = get_pinned(ctx, (size_t)n_replicates * Lay.n_mom);
     if (st != MC_OK) return st;
     uint32_t* shifts = (uint32_t*)base;
-    double* moms = (double*)(base + b_shift + (size_t)n_replicates * b_part);
+    double* parts = (double*)(base + b_shift);
+    double* moms = (double*)(base + b_shift + b_part);
     HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
-    for (uint32_t rep = 0; rep < n_replicates; ++rep) {
-      uint32_t* sh = shifts + (size_t)rep * dims;
-      HIP_TRY(ctx, launch_qmc_shifts((uint32_t)seed, (uint32_t)(seed >> 32), o0.stream_tag + 6u,
-                                     rep, dims, sh, s));
-      p.qshift = sh;
-      p.partials = (double*)(base + b_shift + (size_t)rep * b_part);
-      p.path_out = nullptr;
-      uint32_t nb = 0;
-      HIP_TRY(ctx, launch_basket(p, prec, s, &nb));
-      if (nb == 0 || nb > Lay.n_blocks) return fail(ctx, MC_ERR_DEVICE, "block count mismatch");
-      HIP_TRY(ctx, launch_final_reduce(p.partials, nb, Lay.n_mom, moms + (size_t)rep * Lay.n_mom,
-                                       s));
-    }
+    HIP_TRY(ctx, launch_qmc_shifts((uint32_t)seed, (uint32_t)(seed >> 32), o0.stream_tag + 6u, 0,
+                                   n_replicates, dims, shifts, s));
+    p.qshift = shifts;
+    p.q_dims = dims;
+    p.partials = parts;
+    p.path_out = nullptr;
+    uint32_t nb = 0;
+    HIP_TRY(ctx, launch_basket_qmc_batch(p, prec, n_replicates, s, &nb));
+    if (nb == 0 || nb > Lay.n_blocks) return fail(ctx, MC_ERR_DEVICE, "block count mismatch");
+    HIP_TRY(ctx, launch_final_reduce_batch(parts, nb, Lay.n_mom, n_replicates, moms, s));
     HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, moms, (size_t)n_replicates * Lay.n_mom * 8,
                                 hipMemcpyDeviceToHost, s));

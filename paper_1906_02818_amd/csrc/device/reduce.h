@@ -23,7 +23,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 template <int C, int BLOCK>
 __device__ __forceinline__ void block_moments(const double (&y)[C], bool valid, bool nonfinite,
                                               double* __restrict__ partials,
-                                              uint32_t n_blocks) {
+                                              uint32_t n_blocks, uint32_t block = ~0u) {
+  if (block == ~0u) block = blockIdx.x;
   constexpr int M = 2 + C + C * (C + 1) / 2;
   constexpr int W = BLOCK / 64;
   __shared__ double red[M][W];
@@ -48,7 +49,7 @@ __device__ __forceinline__ void block_moments(const double (&y)[C], bool valid, 
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < W; ++w) s += red[t][w];
-    partials[(size_t)t * n_blocks + blockIdx.x] = s;
+    partials[(size_t)t * n_blocks + block] = s;
   }
 }
 

@@ -94,7 +94,20 @@ __global__ __launch_bounds__(kThreads) void basket_kernel(const BasketParams P) 
   const int wave = threadIdx.x >> 6;
   const int row = lane & 31;          // A row / B and D column
   const int half = lane >> 5;
-  const uint64_t tile = (uint64_t)blockIdx.x * kWaves + wave;
+  // Block blk of the launch, or of its replicate when replicates share it.
+  uint32_t blk = blockIdx.x, n_part = gridDim.x;
+  const uint32_t* qshift = P.qshift;
+  double* partials = P.partials;
+  if constexpr (QMC) {
+    if (P.q_rep_blocks != 0) {
+      const uint32_t rep = blockIdx.x / P.q_rep_blocks;
+      blk = blockIdx.x - rep * P.q_rep_blocks;
+      n_part = P.q_rep_blocks;
+      qshift += (size_t)rep * P.q_dims;
+      partials += (size_t)rep * n_moments(PORT ? 1 : 3) * P.q_rep_blocks;
+    }
+  }
+  const uint64_t tile = (uint64_t)blk * kWaves + wave;
   const uint64_t zpath = tile * 32 + row;             // path this lane draws normals for
   const PathCounter pc = make_counter(P.path_offset + zpath, P.tag, P.k0, P.k1);
   const uint32_t d = P.d;
@@ -115,8 +128,8 @@ __global__ __launch_bounds__(kThreads) void basket_kernel(const BasketParams P) 
         Words4 wa, wb;
         if constexpr (QMC) {
           const uint32_t point = (uint32_t)(P.path_offset + zpath);
-          wa = sobol_block(P.qV, P.qshift, j0, point);
-          wb = sobol_block(P.qV, P.qshift, j0 + 1, point);
+          wa = sobol_block(P.qV, qshift, j0, point);
+          wb = sobol_block(P.qV, qshift, j0 + 1, point);
         } else {
           wa = philox(j0, pc);
           wb = philox(j0 + 1, pc);
@@ -183,7 +196,7 @@ __global__ __launch_bounds__(kThreads) void basket_kernel(const BasketParams P) 
     if (active) y[0] = (double)B - P.premium;
     const bool finite = isfinite(y[0]);
     if (active && P.path_out != nullptr) P.path_out[pid] = y[0];
-    block_moments<1, kThreads>(y, active && finite, active && !finite, P.partials, gridDim.x);
+    block_moments<1, kThreads>(y, active && finite, active && !finite, partials, n_part, blk);
   } else {
     double y[3] = {0.0, 0.0, 0.0};
     if (active) {
@@ -199,7 +212,7 @@ __global__ __launch_bounds__(kThreads) void basket_kernel(const BasketParams P) 
 #pragma unroll
       for (int c = 0; c < 3; ++c) P.path_out[pid * 3 + c] = y[c];
     }
-    block_moments<3, kThreads>(y, active && finite, active && !finite, P.partials, gridDim.x);
+    block_moments<3, kThreads>(y, active && finite, active && !finite, partials, n_part, blk);
   }
 }
 
@@ -244,6 +257,24 @@ hipError_t launch_prec(const BasketParams& p, hipStream_t s, uint32_t nb) {
 uint32_t basket_blocks_nd(uint32_t d) {
   const uint32_t nd = (d + 31) / 32;
   return nd <= 1 ? 1 : nd <= 2 ? 2 : nd <= 4 ? 4 : 8;
+}
+
+hipError_t launch_basket_qmc_batch(BasketParams p, int prec, uint32_t n_rep, hipStream_t s,
+                                   uint32_t* blocks_per_rep) {
+  const uint32_t paths_per_wg = 32 * kWaves;
+  const uint64_t nb = (p.n_paths + paths_per_wg - 1) / paths_per_wg;
+  *blocks_per_rep = (uint32_t)nb;
+  if (p.qV == nullptr || p.n_strikes != 0 || p.path_out != nullptr || n_rep == 0 || nb == 0 ||
+      nb * n_rep > 0x7fffffffull || prec == BK_BF16X2)
+    return hipErrorInvalidValue;
+  p.q_rep_blocks = (uint32_t)nb;
+  const uint32_t total = (uint32_t)(nb * n_rep);
+  switch (prec) {
+    case BK_FP32: return launch_prec<BK_FP32>(p, s, total);
+    case BK_BF16: return launch_prec<BK_BF16>(p, s, total);
+    case BK_FP16: return launch_prec<BK_FP16>(p, s, total);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_basket(const BasketParams& p, int prec, hipStream_t s, uint32_t* n_blocks) {

@@ -11,11 +11,15 @@ namespace {
 
 // One workgroup per moment: thread t adds blocks t, t+256, ... in order,
 // then a fixed-shape tree adds the 256 partial sums. Deterministic.
+// Moment m = blockIdx.x of batch b = blockIdx.y: partials [b][m][n_blocks],
+// out [b][n_mom].
 __global__ __launch_bounds__(256) void final_reduce_kernel(const double* __restrict__ partials,
                                                            uint32_t n_blocks,
                                                            double* __restrict__ out) {
   __shared__ double sh[256];
   const uint32_t m = blockIdx.x;
+  partials += (size_t)blockIdx.y * gridDim.x * n_blocks;
+  out += (size_t)blockIdx.y * gridDim.x;
   const double* row = partials + (size_t)m * n_blocks;
   double s = 0.0;
   for (uint32_t i = threadIdx.x; i < n_blocks; i += 256) s += row[i];
@@ -76,23 +80,25 @@ __global__ __launch_bounds__(kBlock) void diff_moments_kernel(const double* __re
   block_reduce_moments<M, kBlock>(acc, partials, gridDim.x);
 }
 
-__global__ void qmc_shift_kernel(uint32_t k0, uint32_t k1, uint32_t tag, uint64_t replicate,
+// Shift row of replicate replicate0 + blockIdx.y: [blockIdx.y][n_dims].
+__global__ void qmc_shift_kernel(uint32_t k0, uint32_t k1, uint32_t tag, uint64_t replicate0,
                                  uint32_t n_dims, uint32_t* __restrict__ shift) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;   // block index
   if (4u * j >= n_dims) return;
-  const PathCounter pc = make_counter(replicate, tag, k0, k1);
+  shift += (size_t)blockIdx.y * n_dims;
+  const PathCounter pc = make_counter(replicate0 + blockIdx.y, tag, k0, k1);
   const Words4 w = philox(j, pc);
   for (uint32_t t = 0; t < 4u && 4u * j + t < n_dims; ++t) shift[4u * j + t] = word_at(w, t);
 }
 
 }  // namespace
 
-hipError_t launch_qmc_shifts(uint32_t k0, uint32_t k1, uint32_t tag, uint64_t replicate,
-                             uint32_t n_dims, uint32_t* shift, hipStream_t s) {
+hipError_t launch_qmc_shifts(uint32_t k0, uint32_t k1, uint32_t tag, uint64_t replicate0,
+                             uint32_t n_rep, uint32_t n_dims, uint32_t* shift, hipStream_t s) {
   const uint32_t blocks = (n_dims + 3u) / 4u;
-  if (blocks == 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(qmc_shift_kernel, dim3((blocks + 255) / 256), dim3(256), 0, s, k0, k1, tag,
-                     replicate, n_dims, shift);
+  if (blocks == 0 || n_rep == 0 || n_rep > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(qmc_shift_kernel, dim3((blocks + 255) / 256, n_rep), dim3(256), 0, s, k0, k1,
+                     tag, replicate0, n_dims, shift);
   return hipGetLastError();
 }
 
@@ -111,6 +117,14 @@ hipError_t launch_diff_moments(const double* a, uint32_t Ca, uint32_t ca, const 
 hipError_t launch_final_reduce(const double* partials, uint32_t n_blocks, uint32_t n_mom,
                                double* out, hipStream_t s) {
   hipLaunchKernelGGL(final_reduce_kernel, dim3(n_mom), dim3(256), 0, s, partials, n_blocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_final_reduce_batch(const double* partials, uint32_t n_blocks, uint32_t n_mom,
+                                     uint32_t n_batch, double* out, hipStream_t s) {
+  if (n_blocks == 0 || n_mom == 0 || n_batch == 0 || n_batch > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(final_reduce_kernel, dim3(n_mom, n_batch), dim3(256), 0, s, partials,
+                     n_blocks, out);
   return hipGetLastError();
 }
 

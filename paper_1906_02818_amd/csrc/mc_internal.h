@@ -111,7 +111,11 @@ struct BasketParams {
   // Randomised quasi-Monte Carlo: when qV is set, normal block j of path p
   // comes from Sobol' point p (dimensions 4j..4j+3) shifted by qshift.
   const uint32_t* qV;     // [dims][32] direction words
-  const uint32_t* qshift; // [dims]
+  const uint32_t* qshift; // [dims], or [replicates][dims] with q_rep_blocks
+  // Replicates in one launch: block b runs replicate b / q_rep_blocks with
+  // shift row q_dims * replicate, and writes its moments to that
+  // replicate's own [moment][q_rep_blocks] partials.
+  uint32_t q_rep_blocks, q_dims;
   double* partials;
   double* path_out;       // [n_paths][3] (basket) or [n_paths] (portfolio), or nullptr
 };
@@ -119,11 +123,17 @@ constexpr int kMaxStrikes = 8;
 // Number of 32-wide asset blocks the kernel is instantiated for (1, 2, 4, 8).
 uint32_t basket_blocks_nd(uint32_t d);
 hipError_t launch_basket(const BasketParams& p, int prec, hipStream_t s, uint32_t* n_blocks);
+// All n_rep randomised-QMC replicates of p in one launch (p.qshift holds
+// n_rep rows of p.q_dims shifts); *blocks_per_rep = one replicate's blocks.
+hipError_t launch_basket_qmc_batch(BasketParams p, int prec, uint32_t n_rep, hipStream_t s,
+                                   uint32_t* blocks_per_rep);
 
 // Digital shifts of one randomised-QMC replicate: shift[j] = word (j mod 4)
 // of Philox block (floor(j/4), replicate, tag) under key (k0, k1).
-hipError_t launch_qmc_shifts(uint32_t k0, uint32_t k1, uint32_t tag, uint64_t replicate,
-                             uint32_t n_dims, uint32_t* shift, hipStream_t s);
+// Digital shifts of replicates replicate0 .. replicate0 + n_rep - 1:
+// shift [n_rep][n_dims].
+hipError_t launch_qmc_shifts(uint32_t k0, uint32_t k1, uint32_t tag, uint64_t replicate0,
+                             uint32_t n_rep, uint32_t n_dims, uint32_t* shift, hipStream_t s);
 
 // ---- Order statistic and tail mean of per-path values (risk metrics) ----
 // Exact k-th smallest (1-based) of x[0..n) by an 8-pass radix select on the
@@ -238,6 +248,10 @@ hipError_t launch_adam(float* theta, float* m, float* v, const double* grad, int
 // ---- reductions and diagnostics ----
 hipError_t launch_final_reduce(const double* partials, uint32_t n_blocks, uint32_t n_mom,
                                double* out, hipStream_t s);
+// n_batch independent reductions: partials [batch][n_mom][n_blocks] ->
+// out [batch][n_mom].
+hipError_t launch_final_reduce_batch(const double* partials, uint32_t n_blocks, uint32_t n_mom,
+                                     uint32_t n_batch, double* out, hipStream_t s);
 hipError_t launch_philox_words(uint32_t k0, uint32_t k1, uint32_t tag, uint64_t n,
                                const uint64_t* paths, const uint64_t* blocks, uint32_t* out,
                                hipStream_t s);
