@@ -324,17 +324,16 @@ __global__ __launch_bounds__(kCvThreads) void cv_fwd_kernel(const CvParams P) {
 
 // Hedged values of the minibatch's paths, H = sum_k Delta_k dSt_k in
 // segment order, and their moments (channels payoff, H, Y = payoff - H);
-// 32 paths per wave, as in the backward pass.
+// one path per lane.
 __global__ __launch_bounds__(kCvThreads) void cv_values_kernel(const CvParams P) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int row = lane & 31, half = lane >> 5;
   const uint64_t n = P.h.n_paths;
-  const uint64_t pid = ((uint64_t)blockIdx.x * kCvWaves + wave) * 32 + row;
-  const bool report = pid < n && half == 0;
+  const uint64_t pid = (uint64_t)blockIdx.x * kCvThreads + threadIdx.x;
+  const bool active = pid < n;
   double y[3] = {0.0, 0.0, 0.0};
-  if (report) {
+  if (active) {
     const uint64_t S = P.c_stride, c = P.c_first + pid;
     float H = 0.f;
+#pragma unroll 4
     for (uint32_t k = 0; k < P.n_seg; ++k)
       H = __builtin_fmaf(P.c_delta[(size_t)k * n + pid], P.c_dst[(size_t)k * S + c], H);
     const double pay = P.c_pay[c];
@@ -343,11 +342,11 @@ __global__ __launch_bounds__(kCvThreads) void cv_values_kernel(const CvParams P)
     y[2] = pay - (double)H;
   }
   const bool finite = isfinite(y[0]) && isfinite(y[1]) && isfinite(y[2]);
-  if (report && P.path_out != nullptr) {
+  if (active && P.path_out != nullptr) {
 #pragma unroll
     for (int q = 0; q < 3; ++q) P.path_out[pid * 3 + q] = y[q];
   }
-  block_moments<3, kCvThreads>(y, report && finite, report && !finite, P.partials, gridDim.x);
+  block_moments<3, kCvThreads>(y, active && finite, active && !finite, P.partials, gridDim.x);
 }
 
 // Backward pass: a wave takes 32 paths of the minibatch through every hedge
@@ -611,15 +610,8 @@ __global__ __launch_bounds__(kCvThreads) void cv_eval_kernel(const CvParams P) {
   }
   const float b3 = P.theta[4544];
 
-  const float dt = (float)Hp.dt, kdt = (float)(Hp.kappa * Hp.dt);
-  const float kthdt = (float)(Hp.kappa * Hp.theta * Hp.dt), xi = (float)Hp.xi;
-  const float rho = (float)Hp.rho, rhoc = (float)Hp.rho_c;
-  const float a1 = (float)(-0.5 * Hp.dt * 1.4426950408889634), a2 = 1.4426950408889634f;
-  const float S0 = (float)Hp.S0;
-  const float lnS0K = (float)std::log(Hp.S0 / Hp.K), ln2 = 0.69314718055994531f;
-  const float rdt2 = (float)(Hp.r * Hp.dt * 1.4426950408889634);
-  const float inv_theta = (float)(1.0 / Hp.theta);
-  const float inv_n = (float)(1.0 / Hp.n_steps), S0K = (float)(Hp.S0 / Hp.K);
+  const HestonF c(Hp);
+  const float S0 = c.S0;
   const uint32_t n = Hp.n_steps, m = P.hedge_every;
   const PathCounter pc = make_counter(Hp.path_offset + pid, Hp.tag, Hp.k0, Hp.k1);
 
@@ -628,10 +620,8 @@ __global__ __launch_bounds__(kCvThreads) void cv_eval_kernel(const CvParams P) {
   Normals4<float> nz;
   for (uint32_t i = 0; i < n; ++i) {
     if (i % m == 0) {
-      const float fi = (float)i;
-      const float Abar = (i == 0) ? 1.0f : sumE * __builtin_amdgcn_rcpf(fi);
-      const float own[4] = {fi * inv_n, (z + rdt2 * fi) * ln2 + lnS0K, v * inv_theta,
-                            Abar * S0K - 1.0f};
+      float own[4];
+      c.features(i, z, v, sumE, own);
       float other[4];
 #pragma unroll
       for (int f = 0; f < 4; ++f) other[f] = __shfl_xor(own[f], 32, 64);
@@ -653,13 +643,7 @@ __global__ __launch_bounds__(kCvThreads) void cv_eval_kernel(const CvParams P) {
     if ((i & 1) == 0) nz = normals4<float>(philox(i >> 1, pc));
     const float Z1 = (i & 1) ? nz.z[2] : nz.z[0];
     const float Z2 = (i & 1) ? nz.z[3] : nz.z[1];
-    {
-      const float vp = v > 0.f ? v : 0.f;
-      const float sq = __builtin_amdgcn_sqrtf(vp * dt);
-      const float Zs = rho * Z1 + rhoc * Z2;
-      z = z + a1 * vp + a2 * (sq * Zs);
-      v = v + (kthdt - kdt * vp) + xi * (sq * Z1);
-    }
+    c.step(z, v, Z1, Z2);
     Et = __builtin_amdgcn_exp2f(z);
     sumE += Et * P.dfac[i + 1];
     if ((i + 1) % m == 0 || i + 1 == n) H = __builtin_fmaf(delta, S0 * (Et - st_open), H);
@@ -767,7 +751,7 @@ hipError_t launch_cv_forward(const CvParams& p, hipStream_t s) {
 }
 
 hipError_t launch_cv_values(const CvParams& p, hipStream_t s, uint32_t* n_blocks) {
-  const uint32_t nb = (uint32_t)((p.h.n_paths + kCvTrainPathsPerBlock - 1) / kCvTrainPathsPerBlock);
+  const uint32_t nb = (uint32_t)((p.h.n_paths + kCvThreads - 1) / kCvThreads);
   *n_blocks = nb;
   if (nb == 0 || p.c_first + p.h.n_paths > p.c_stride) return hipErrorInvalidValue;
   hipLaunchKernelGGL(cv_values_kernel, dim3(nb), dim3(kCvThreads), 0, s, p);
