@@ -96,4 +96,48 @@ __device__ __forceinline__ void block_reduce_moments(const double (&acc)[M],
   }
 }
 
+// Block sum for long moment vectors (fixed order, like the above): per
+// pass, each wave stores 16 moments of its 64 lanes in LDS; lane l adds the
+// 16 values of moment l / 4 from lanes 16 (l mod 4) .. 16 (l mod 4) + 15,
+// and two butterfly steps combine the four quarters. About a quarter of the
+// instructions of a 6-step butterfly per moment.
+template <int M, int BLOCK>
+__device__ __forceinline__ void block_reduce_moments_wide(const double (&acc)[M],
+                                                          double* __restrict__ partials,
+                                                          uint32_t n_blocks) {
+  constexpr int W = BLOCK / 64, CH = 16;
+  __shared__ double buf[W][CH][64 + 1];
+  __shared__ double red[M][W];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int c = lane >> 2, q = lane & 3;
+  // Orders the wave's own LDS stores before its loads (lockstep wave).
+  auto wave_sync = [] {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+#pragma unroll
+  for (int m0 = 0; m0 < M; m0 += CH) {
+#pragma unroll
+    for (int j = 0; j < CH; ++j)
+      if (m0 + j < M) buf[wave][j][lane] = acc[m0 + j];
+    wave_sync();
+    double s = 0.0;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) s += buf[wave][c][16 * q + t];
+    s += __shfl_xor(s, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    if (q == 0 && m0 + c < M) red[m0 + c][wave] = s;
+    wave_sync();
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < M; t += BLOCK) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) s += red[t][w];
+    partials[(size_t)t * n_blocks + blockIdx.x] = s;
+  }
+}
+
 }  // namespace mcp
