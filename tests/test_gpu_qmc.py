@@ -58,13 +58,17 @@ def test_qmc_paths_match_oracle(ctx, d, N, n, offset, prec):
     np.testing.assert_allclose(r["price"], pv[:, 0].mean(), rtol=1e-12)
 
 
-def test_qmc_replicates_match_oracle(ctx):
-    say("qmc replicates")
-    d, N, n, R = 16, 2048, 1, 6
+@pytest.mark.parametrize("d,N,n,R,offset", [(16, 2048, 1, 6, 0), (48, 2000, 2, 3, 777)])
+def test_qmc_replicates_match_oracle(ctx, d, N, n, R, offset):
+    # All replicates run in one launch; the second case has a ragged last
+    # block in every replicate, two asset blocks and a point offset.
+    say("qmc replicates", d, N, n, R, offset)
     model, S0, sigma, corr, L, w = market(d)
-    r = mc.mc_price_qmc(ctx, model, mc.Payoff(mc.MC_BASKET_CALL, 100.0), N, n, SEED, R)
+    r = mc.mc_price_qmc(ctx, model, mc.Payoff(mc.MC_BASKET_CALL, 100.0), N, n, SEED, R,
+                        mc.Options(path_offset=offset))
     for rep in range(R):
-        o = oracle.basket_qmc(S0, sigma, L, w, 0.05, 1.0, 100.0, n, N, SEED, rep, tag=6)
+        o = oracle.basket_qmc(S0, sigma, L, w, 0.05, 1.0, 100.0, n, N, SEED, rep, tag=6,
+                              path0=offset)
         assert abs(r["replicate_price"][rep] - o[:, 0].mean()) < 2e-5 * o[:, 0].mean()
         assert abs(r["replicate_geo"][rep] - o[:, 1].mean()) < 2e-5 * o[:, 1].mean()
     est = np.array(r["replicate_price"])
