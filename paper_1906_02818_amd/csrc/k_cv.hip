@@ -234,6 +234,53 @@ struct HestonF {
   }
 };
 
+// The same forward pass when only Delta is needed (evaluation): layer 1's
+// activations go straight into layer 2's B operands, so they are held in
+// the operand type (BF16 pairs) rather than as FP32 values. Same arithmetic
+// as mlp_forward.
+template <bool BF16>
+__device__ __forceinline__ float mlp_delta(const float (&phi)[8], const Op8<BF16> (&w1a)[2],
+                                           const FragT<BF16>* w2f, const float* lanec, int lane,
+                                           float b3) {
+  f32x16 d1[2];
+  const Op8<BF16> phio = op_from<BF16>(phi);
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) d1[mb][r] = 0.f;
+    mma16<BF16>(d1[mb], w1a[mb], phio);
+  }
+  Op8<BF16> b[4];
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb) {
+    float bf[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) bf[j] = tanh_b(d1[kb >> 1][8 * (kb & 1) + j], 0.f);
+    b[kb] = op_from<BF16>(bf);
+  }
+  f32x16 d2[2];
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) d2[mb][r] = 0.f;
+  __asm__ volatile("" ::: "memory");   // weight fragments are read from LDS at every use
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+      mma16<BF16>(d2[mb], op_lds<BF16>(&w2f[((mb * 4 + kb) * 64 + lane) * 8]), b[kb]);
+  float part = 0.f;
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int idx = mb * 16 + r;
+      const float v = tanh_b(d2[mb][r], lanec[lane * 32 + idx]);
+      part = __builtin_fmaf(lanec[64 * 32 + lane * 32 + idx], v, part);
+    }
+  return part + __shfl_xor(part, 32, 64) + b3;
+}
+
 // Fills the feature cache: one lane per path (h.n_paths paths from global
 // path h.path_offset, stream tag h.tag), the features at every segment's
 // opening date, the discounted price change over the segment and the
@@ -616,7 +663,6 @@ __global__ __launch_bounds__(kCvThreads) void cv_eval_kernel(const CvParams P) {
   const PathCounter pc = make_counter(Hp.path_offset + pid, Hp.tag, Hp.k0, Hp.k1);
 
   float z = 0.f, v = (float)Hp.v0, sumE = 0.f, H = 0.f, delta = 0.f, st_open = 0.f, Et = 1.f;
-  float h1[32], h2[32];
   Normals4<float> nz;
   for (uint32_t i = 0; i < n; ++i) {
     if (i % m == 0) {
@@ -635,7 +681,7 @@ __global__ __launch_bounds__(kCvThreads) void cv_eval_kernel(const CvParams P) {
           for (int f = 0; f < 4; ++f) phi[f] = sub == 0 ? own[f] : other[f];
           phi[4] = 1.0f;
         }
-        const float d = mlp_forward<BF16>(phi, w1a, s_w2f, s_lanec, lane, b3, h1, h2);
+        const float d = mlp_delta<BF16>(phi, w1a, s_w2f, s_lanec, lane, b3);
         if (sub == half) delta = d;
       }
       st_open = Et;
