@@ -228,6 +228,9 @@ def time_to_1bp(ctx, mc, synth, torch, hedge_every=16, adam_steps=2000):
     # errors below this many basis points of the price.
     gain = out["plain_fp32"]["total_s"] - out["learned_cv_bf16"]["total_s"]
     out["break_even_se_bp"] = math.sqrt(gain / t_train) if gain > 0 else None
+    # A trained network serves every later pricing of the same product: the
+    # number of 1 bp pricings whose time saving pays for the training.
+    out["break_even_pricings_1bp"] = t_train / gain if gain > 0 else None
     return out
 
 
