@@ -76,6 +76,39 @@ def test_qmc_replicates_match_oracle(ctx, d, N, n, R, offset):
     np.testing.assert_allclose(r["std_err"], est.std(ddof=1) / math.sqrt(R), rtol=1e-10)
 
 
+def test_qmc_benchmarked_launch_matches_oracle(ctx):
+    # The launch the benchmark times: 16 digital shifts of 2^16 points of the
+    # 16-asset basket in one step, all replicates in one launch; the oracle
+    # prices every replicate in full.
+    d, N, n, R = 16, 1 << 16, 1, 16
+    say("qmc benchmarked launch", d, N, R)
+    model, S0, sigma, corr, L, w = market(d)
+    r = mc.mc_price_qmc(ctx, model, mc.Payoff(mc.MC_BASKET_CALL, 100.0), N, n, SEED, R,
+                        mc.Options(prec=mc.MC_BF16_GEMM))
+    h = mc.mc_price_qmc(ctx, model, mc.Payoff(mc.MC_BASKET_CALL, 100.0), N, n, SEED, R,
+                        mc.Options(prec=mc.MC_FP16_GEMM))
+    ref = mc.mc_price_qmc(ctx, model, mc.Payoff(mc.MC_BASKET_CALL, 100.0), N, n, SEED, R)
+    om = np.array([oracle.basket_qmc(S0, sigma, L, w, 0.05, 1.0, 100.0, n, N, SEED, rep,
+                                      tag=6)[:, 0].mean() for rep in range(R)])
+    g32 = np.array(ref["replicate_price"][:R])
+    g16 = np.array(r["replicate_price"][:R])
+    # The reduced-precision errors against FP64, in QMC standard errors: the
+    # bench line for this workload runs FP32 products.
+    se = ref["std_err"]
+    say(f"  oracle {om.mean():.8f}, FP32 {ref['price']:.8f} +- {se:.2e}; max rel FP32 "
+        f"{np.abs(g32 / om - 1).max():.2e}; BF16 {r['price']:.8f} "
+        f"({(r['price'] - om.mean()) / se:+.2f} SE), FP16 {h['price']:.8f} "
+        f"({(h['price'] - om.mean()) / se:+.2f} SE)")
+    # FP32 products: each replicate within 2e-5 of the oracle, and the
+    # estimate within 0.1 standard errors of the oracle's.
+    assert np.abs(g32 / om - 1).max() < 2e-5
+    assert abs(ref["price"] - om.mean()) < 0.1 * se
+    # FP16 products (L' to 11 bits) stay within 0.1 standard errors; BF16 (8
+    # bits) moves this 16-asset price by about 4 of them, so it is not used
+    # for QMC at this size.
+    assert abs(h["price"] - om.mean()) < 0.1 * se
+
+
 def test_qmc_geometric_closed_form_and_rate(ctx):
     # Unbiased for the closed form; RMSE over replicates well below the Monte
     # Carlo standard error at every size and falling faster than N^(-1/2).
