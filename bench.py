@@ -277,6 +277,32 @@ def _repeat(args, torch, fn):
     return (time.perf_counter() - t0) * 1e3 / args.steps, outs
 
 
+def gbm_time_to_1bp(ctx, mc, synth, torch):
+    """Time to a standard error of 1 bp of the price for the estimators of the
+    default workload's payoffs: the arithmetic Asian with and without the
+    geometric-Asian control variate, and the up-and-out barrier. Each: a
+    2^20-path pilot on stream tag 1 sizes N* = (s / (1e-4 p))^2, then one
+    run of N* paths on tag 0; both are timed (the control variate's own
+    coefficient pilot is part of its run)."""
+    c = synth.ASIAN_BARRIER
+    n = c["n_steps"]
+    model = mc.Model(kind=mc.MC_GBM, S0=c["S0"], r=c["r"], T=c["T"], sigma=c["sigma"])
+    out = {"workload": f"GBM, {n} steps; target SE = 1e-4 x price"}
+    for name, f in (("asian_geo_cv", mc.Payoff(mc.MC_ASIAN_ARITH_CALL, c["K"],
+                                               cv=mc.MC_CV_GEO_ASIAN)),
+                    ("asian_plain", mc.Payoff(mc.MC_ASIAN_ARITH_CALL, c["K"])),
+                    ("uo_barrier", mc.Payoff(mc.MC_UO_BARRIER_CALL, c["K"], B=c["B"]))):
+        pil, t_pil = _timed(torch, lambda: mc.mc_price(ctx, model, f, 1 << 20, n, synth.SEED,
+                                                       mc.Options(stream_tag=1)))
+        N = _paths_for(1e-4 * pil["price"], math.sqrt(pil["variance"]))
+        run, t_run = _timed(torch, lambda: mc.mc_price(ctx, model, f, N, n, synth.SEED))
+        out[name] = {"pilot_s": t_pil, "n_paths": N, "run_s": t_run, "total_s": t_pil + t_run,
+                     "price": run["price"], "std_err": run["std_err"],
+                     "kernel_ms": run["kernel_ms"]}
+    out["cv_speedup"] = out["asian_plain"]["total_s"] / out["asian_geo_cv"]["total_s"]
+    return out
+
+
 def run_asian_barrier(args, ctx, mc, synth, torch):
     c = synth.ASIAN_BARRIER
     N, n = c["n_paths"], c["n_steps"]
@@ -311,6 +337,7 @@ def run_asian_barrier(args, ctx, mc, synth, torch):
     if not args.no_time_to_1bp:
         line["time_to_1bp"] = time_to_1bp(ctx, mc, synth, torch, hedge_every=args.hedge_every,
                                           adam_steps=args.adam_steps)
+        line["gbm_time_to_1bp"] = gbm_time_to_1bp(ctx, mc, synth, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(c)
     return line
