@@ -546,14 +546,29 @@ def run_heston_adjoint(args, ctx, mc, synth, torch):
     r = outs[-1]
     k_ms = sum(x["kernel_ms"] for x in outs) / len(outs)
     per_step = 2 * SLOTS_HESTON + SLOTS_HESTON_REVERSE   # forward, recompute, reverse
+    # Beside it: the price alone (forward kernel only) on the same paths, and
+    # central differences on common random numbers (h = 1e-3 relative, FP64
+    # bumped pairs) on 2^20 of them as the independent check of the greeks.
+    fwd = [mc.mc_price(ctx, model, f, N, n, synth.SEED)["kernel_ms"] for _ in range(3)]
+    fd = mc.mc_price(ctx, model, f, 1 << 20, n, synth.SEED,
+                     mc.Options(greeks=mc.MC_GREEK_DELTA | mc.MC_GREEK_VEGA,
+                                greeks_method=mc.MC_GREEKS_FD_CRN))
+
+    def z(a, sa, b, sb):
+        return (a - b) / math.hypot(sa, sb)
     return _line(args, "path-steps/s", N * n / (ms * 1e-3), "path-steps/s", ms, "f32",
                  {"workload": "Heston arithmetic-Asian call, full-truncation Euler, 256 steps, "
                               "2^22 paths, price + pathwise delta and d/dv0 by the checkpointed "
                               "adjoint (every 16 steps)", "n_paths": N, "n_steps": n},
                  _alu_roofline(per_step, N * n, k_ms, "heston_adjoint_kernel<float, full, asian>"),
                  kernel_ms=k_ms,
+                 forward_only={"kernel_ms": min(fwd), "path_steps_per_s": N * n / (min(fwd) * 1e-3)},
                  prices={"price": r["price"], "se": r["std_err"], "delta": r["delta"],
-                         "delta_se": r["delta_se"], "dv0": r["vega"], "dv0_se": r["vega_se"]})
+                         "delta_se": r["delta_se"], "dv0": r["vega"], "dv0_se": r["vega_se"]},
+                 fd_check={"n_paths": 1 << 20, "delta": fd["delta"], "delta_se": fd["delta_se"],
+                           "dv0": fd["vega"], "dv0_se": fd["vega_se"],
+                           "delta_z": z(r["delta"], r["delta_se"], fd["delta"], fd["delta_se"]),
+                           "dv0_z": z(r["vega"], r["vega_se"], fd["vega"], fd["vega_se"])})
 
 
 def run_learned_cv(args, ctx, mc, synth, torch):
