@@ -359,7 +359,25 @@ def run_european(args, ctx, mc, synth, torch):
                   "frac": None, "traffic": None,
                   "note": "FP64 transcendentals go through library code; not modelled"},
                  kernel_ms=k_ms, prices={"price": r["price"], "se": r["std_err"],
-                                         "delta": r["delta"], "vega": r["vega"]})
+                                         "delta": r["delta"], "vega": r["vega"]},
+                 black_scholes=_bs_check(c, r))
+
+
+def _bs_check(c, r):
+    """Black-Scholes price, delta and vega of the European call and the
+    estimates' distance from them in standard errors (log-Euler is exact in
+    law, so only Monte Carlo error separates them)."""
+    S, K, rr, s, T = c["S0"], c["K"], c["r"], c["sigma"], c["T"]
+    d1 = (math.log(S / K) + (rr + 0.5 * s * s) * T) / (s * math.sqrt(T))
+    d2 = d1 - s * math.sqrt(T)
+    N = lambda x: 0.5 * (1.0 + math.erf(x / math.sqrt(2.0)))  # noqa: E731
+    price = S * N(d1) - K * math.exp(-rr * T) * N(d2)
+    delta = N(d1)
+    vega = S * math.sqrt(T) * math.exp(-0.5 * d1 * d1) / math.sqrt(2.0 * math.pi)
+    return {"price": price, "delta": delta, "vega": vega,
+            "price_z": (r["price"] - price) / r["std_err"],
+            "delta_z": (r["delta"] - delta) / r["delta_se"],
+            "vega_z": (r["vega"] - vega) / r["vega_se"]}
 
 
 def run_basket(args, ctx, mc, synth, torch):

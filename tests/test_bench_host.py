@@ -76,3 +76,14 @@ def test_cpu_baselines_state_what_they_measured():
         assert line["kind"] == "oracle" and line["unit"] == unit
         assert line["value"] > 0 and line["cores"] >= 1 and line["sample"]
         assert math.isfinite(line["value"])
+
+
+def test_black_scholes_check_of_the_european_line():
+    # Black-Scholes call S0 = K = 100, r = 0.05, sigma = 0.2, T = 1.
+    r = {"price": 10.45, "std_err": 0.03, "delta": 0.637, "delta_se": 0.001, "vega": 37.5,
+         "vega_se": 0.1}
+    b = bench._bs_check(synth.EURO, r)
+    assert b["price"] == pytest.approx(10.450583572185565, rel=1e-13)
+    assert b["delta"] == pytest.approx(0.6368306511756191, rel=1e-13)
+    assert b["vega"] == pytest.approx(37.52403469169379, rel=1e-13)
+    assert b["price_z"] == pytest.approx((10.45 - b["price"]) / 0.03)
