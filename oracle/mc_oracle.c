@@ -16,6 +16,11 @@
  * thread count.
  *
  * Per-path outputs are written row-major: out[p * n_channels + c].
+ *
+ * Parity unpinned: the arithmetic-Asian call price (GBM channel "asian",
+ * Heston channel "asian") has no closed form. Its K = 0 mean (exact), its
+ * ordering against the geometric Asian and its pathwise tangents are
+ * pinned; the price at K > 0 itself is not.
  */
 #include <math.h>
 #include <stdint.h>
