@@ -364,3 +364,21 @@ def test_arithmetic_average_mean_is_exact_at_zero_strike():
     oh = _heston(n, 1 << 20, 17, K=0.0, r=r)
     e = oracle.estimate(oh[:, 1])
     assert within(e, exact) and not within(e, wrong)
+
+
+@pytest.mark.parametrize("K", [95.0, 101.0, 120.0])
+def test_asian_price_at_zero_volatility_is_the_deterministic_payoff(K):
+    # sigma = 0: every path is S_{t_i} = S0 e^{r t_i}, so the Asian channel is
+    # e^{-rT} (A - K)^+ with A the mean of the n fixings, exactly, on every
+    # path: this pins the strike, the positive part and the discounting of
+    # the K > 0 payoff, which the K = 0 mean above cannot see.
+    S0, r, T, n = 100.0, 0.03, 1.0, 12
+    A = S0 / n * sum(math.exp(r * i * T / n) for i in range(1, n + 1))
+    want = math.exp(-r * T) * max(A - K, 0.0)
+    o = oracle.gbm(S0, r, 0.0, T, K, 1e30, n, 64, 17)
+    # Absolute tolerance: A - K cancels, and the path's log-price carries the
+    # rounding of n accumulated steps (~1e-14 of S0).
+    np.testing.assert_allclose(o[:, 1], want, rtol=0, atol=1e-11)
+    geo = math.exp(-r * T) * max(math.exp(sum(math.log(S0) + r * i * T / n
+                                               for i in range(1, n + 1)) / n) - K, 0.0)
+    np.testing.assert_allclose(o[:, 2], geo, rtol=0, atol=1e-11)
