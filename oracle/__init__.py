@@ -9,9 +9,10 @@ one step at a time). This module only marshals numpy arrays through ctypes
 and adds the estimator formulas of Eq. (3) and the bias-variance split of
 Sec. V-B, plus the Adam update used to train the learned control variate.
 
-Parity unpinned: the arithmetic-Asian call price (no closed form); its K = 0
-mean, its ordering against the geometric Asian and its pathwise tangents are
-pinned by the tests.
+Parity unpinned: the arithmetic-Asian call price with volatility (no closed
+form); its K = 0 mean, its zero-volatility value at any K, its ordering
+against the geometric Asian and its pathwise tangents are pinned by the
+tests.
 """
 from __future__ import annotations
 

@@ -19,8 +19,9 @@
  *
  * Parity unpinned: the arithmetic-Asian call price (GBM channel "asian",
  * Heston channel "asian") has no closed form. Its K = 0 mean (exact), its
- * ordering against the geometric Asian and its pathwise tangents are
- * pinned; the price at K > 0 itself is not.
+ * zero-volatility value at any K (exact), its ordering against the
+ * geometric Asian and its pathwise tangents are pinned; the price at K > 0
+ * with volatility is not.
  */
 #include <math.h>
 #include <stdint.h>
