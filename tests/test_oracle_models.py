@@ -382,3 +382,17 @@ def test_asian_price_at_zero_volatility_is_the_deterministic_payoff(K):
     geo = math.exp(-r * T) * max(math.exp(sum(math.log(S0) + r * i * T / n
                                                for i in range(1, n + 1)) / n) - K, 0.0)
     np.testing.assert_allclose(o[:, 2], geo, rtol=0, atol=1e-11)
+
+
+def test_heston_without_vol_of_vol_is_black_scholes():
+    # xi = 0 and v0 = theta: the variance stays at theta on every path, so the
+    # full-truncation scheme is log-Euler GBM with sigma = sqrt(theta), exact
+    # in law: the European channel is Black-Scholes within Monte Carlo error,
+    # and its pathwise delta is the Black-Scholes delta.
+    th = 0.04
+    o = _heston(32, 1 << 18, 29, xi=0.0, v0=th, theta=th, rho=-0.7)
+    S0, K, r, T = H["S0"], H["K"], H["r"], H["T"]
+    e = oracle.estimate(o[:, 0])
+    assert within(e, bs_call(S0, K, r, math.sqrt(th), T), 4.0)
+    d = oracle.estimate(o[:, 2])
+    assert within(d, bs_delta(S0, K, r, math.sqrt(th), T), 4.0)
