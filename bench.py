@@ -568,6 +568,12 @@ def run_heston_adjoint(args, ctx, mc, synth, torch):
     # central differences on common random numbers (h = 1e-3 relative, FP64
     # bumped pairs) on 2^20 of them as the independent check of the greeks.
     fwd = [mc.mc_price(ctx, model, f, N, n, synth.SEED)["kernel_ms"] for _ in range(3)]
+    # The same greeks in forward mode: tangents carried beside the state, no
+    # checkpoints, no reverse sweep.
+    to = mc.Options(greeks=mc.MC_GREEK_DELTA | mc.MC_GREEK_VEGA,
+                    greeks_method=mc.MC_GREEKS_TANGENT)
+    tan = [mc.mc_price(ctx, model, f, N, n, synth.SEED, to) for _ in range(3)]
+    t_ms = min(x["kernel_ms"] for x in tan)
     fd = mc.mc_price(ctx, model, f, 1 << 20, n, synth.SEED,
                      mc.Options(greeks=mc.MC_GREEK_DELTA | mc.MC_GREEK_VEGA,
                                 greeks_method=mc.MC_GREEKS_FD_CRN))
@@ -581,6 +587,8 @@ def run_heston_adjoint(args, ctx, mc, synth, torch):
                  _alu_roofline(per_step, N * n, k_ms, "heston_adjoint_kernel<float, full, asian>"),
                  kernel_ms=k_ms,
                  forward_only={"kernel_ms": min(fwd), "path_steps_per_s": N * n / (min(fwd) * 1e-3)},
+                 forward_tangent={"kernel_ms": t_ms, "path_steps_per_s": N * n / (t_ms * 1e-3),
+                                  "delta": tan[-1]["delta"], "dv0": tan[-1]["vega"]},
                  prices={"price": r["price"], "se": r["std_err"], "delta": r["delta"],
                          "delta_se": r["delta_se"], "dv0": r["vega"], "dv0_se": r["vega_se"]},
                  fd_check={"n_paths": 1 << 20, "delta": fd["delta"], "delta_se": fd["delta_se"],

@@ -22,9 +22,9 @@ from ._abi import (MC_ADJ_FULL, MC_ADJ_FWD, MC_ADJ_REV, MC_ASIAN_ARITH_CALL, MC_
                    MC_CV_NONE, MC_ERR_DEVICE, MC_ERR_INVALID_ARG, MC_ERR_NOT_PD, MC_ERR_NO_DEVICE,
                    MC_ERR_OOM, MC_ERR_UNSUPPORTED, MC_ERR_WORKSPACE, MC_EULER_S, MC_EURO_CALL,
                    MC_FP16_GEMM, MC_FP32, MC_FP64, MC_GBM, MC_GBM_BASKET, MC_GREEKS_FD_CRN,
-                   MC_GREEKS_PATHWISE, MC_GREEK_DELTA, MC_GREEK_VEGA, MC_HESTON, MC_LOG_EULER,
-                   MC_LSM_BASKET_CALL, MC_LSM_BASKET_PUT, MC_LSM_MAX_CALL, MC_LSM_MAX_DATES,
-                   MC_LSM_MAX_FEATURES, MC_MAX_STRIKES, MC_MLMC_MAX_LEVELS, MC_MLP_NPARAM, MC_OK,
+                   MC_GREEKS_PATHWISE, MC_GREEKS_TANGENT, MC_GREEK_DELTA, MC_GREEK_VEGA,
+                   MC_HESTON, MC_LOG_EULER, MC_LSM_BASKET_CALL, MC_LSM_BASKET_PUT,
+                   MC_LSM_MAX_CALL, MC_LSM_MAX_DATES, MC_LSM_MAX_FEATURES, MC_MAX_STRIKES, MC_MLMC_MAX_LEVELS, MC_MLP_NPARAM, MC_OK,
                    MC_QMC_MAX_REPLICATES, MC_UO_BARRIER_CALL, MC_UO_BRIDGE_CALL)
 
 __all__ = [n for n in dir(_abi) if n.startswith("MC_")] + [

@@ -20,7 +20,7 @@ MC_UO_BARRIER_CALL, MC_BASKET_CALL, MC_UO_BRIDGE_CALL = 4, 5, 6
 MC_CV_NONE, MC_CV_GEO_ASIAN, MC_CV_LEARNED = 0, 1, 2
 MC_GREEK_DELTA, MC_GREEK_VEGA = 1, 2
 MC_ADJ_FULL, MC_ADJ_FWD, MC_ADJ_REV = 0, 1, 2
-MC_GREEKS_PATHWISE, MC_GREEKS_FD_CRN = 0, 1
+MC_GREEKS_PATHWISE, MC_GREEKS_FD_CRN, MC_GREEKS_TANGENT = 0, 1, 2
 MC_MLP_NPARAM = 4545
 MC_MLMC_MAX_LEVELS = 8
 MC_MAX_STRIKES = 8

@@ -165,9 +165,10 @@ mc_status validate_model_payoff(mc_context* ctx, const mc_model* m, const mc_pay
 // price the payoff alone).
 mc_status validate_all(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint64_t n_paths,
                        uint32_t n_steps, const mc_options& o) {
-  if (o.greeks_method != MC_GREEKS_PATHWISE && o.greeks_method != MC_GREEKS_FD_CRN)
+  if (o.greeks_method != MC_GREEKS_PATHWISE && o.greeks_method != MC_GREEKS_FD_CRN &&
+      o.greeks_method != MC_GREEKS_TANGENT)
     return fail(ctx, MC_ERR_INVALID_ARG, "unknown greeks_method");
-  if (o.greeks == 0 || o.greeks_method == MC_GREEKS_PATHWISE)
+  if (o.greeks == 0 || o.greeks_method != MC_GREEKS_FD_CRN)
     return validate_model_payoff(ctx, m, f, n_paths, n_steps, o);
   if (!(std::isfinite(o.fd_rel_step) && o.fd_rel_step > 0.0 && o.fd_rel_step < 0.5))
     return fail(ctx, MC_ERR_INVALID_ARG, "fd_rel_step must lie in (0, 0.5)");
@@ -230,7 +231,7 @@ mc_status validate_model_payoff(mc_context* ctx, const mc_model* m, const mc_pay
     }
     if (o.prec != MC_FP32 && o.prec != MC_FP64)
       return fail(ctx, MC_ERR_UNSUPPORTED, "Heston paths run in MC_FP32 or MC_FP64");
-    if (o.greeks && o.prec != MC_FP32)
+    if (o.greeks && o.greeks_method != MC_GREEKS_TANGENT && o.prec != MC_FP32)
       return fail(ctx, MC_ERR_UNSUPPORTED, "adjoint greeks run in MC_FP32");
     return MC_OK;
   }
@@ -555,11 +556,40 @@ mc_status heston_price(mc_context* ctx, const mc_model* m, const mc_payoff* f, u
     return heston_cv_price(ctx, m, f, n_paths, n_steps, seed, o, out);
   }
   if (f->cv != MC_CV_NONE) return fail(ctx, MC_ERR_UNSUPPORTED, "control variate not available");
+  const bool fp64 = o.prec == MC_FP64;
+  if (o.greeks && o.greeks_method == MC_GREEKS_TANGENT) {
+    // Forward-mode tangents: channels payoff, delta, d/dv0.
+    HestonParams p = heston_params(m, f, n_paths, n_steps, seed, o, o.stream_tag);
+    const bool asian = f->kind == MC_ASIAN_ARITH_CALL;
+    Moments mom;
+    double kms = 0.0;
+    mc_status st = run_moments(ctx, o, n_paths, 3, o.path_values,
+                               [&](double* partials, double* path_out, hipStream_t s,
+                                   uint32_t* nb) {
+                                 p.partials = partials;
+                                 p.path_out = path_out;
+                                 return launch_heston_tangent(p, asian, fp64, s, nb);
+                               },
+                               &mom, &kms);
+    if (st != MC_OK) return st;
+    mc_result r{};
+    double v;
+    fill_channel(mom, 0, &r.price, &r.variance, &r.std_err);
+    r.plain_price = r.price;
+    r.plain_std_err = r.std_err;
+    if (o.greeks & MC_GREEK_DELTA) fill_channel(mom, 1, &r.delta, &v, &r.delta_se);
+    if (o.greeks & MC_GREEK_VEGA) fill_channel(mom, 2, &r.vega, &v, &r.vega_se);
+    r.vrf = 1.0;
+    r.n_paths = (uint64_t)mom.n;
+    r.n_nonfinite = (uint64_t)mom.nonfinite;
+    r.kernel_ms = kms;
+    *out = r;
+    return MC_OK;
+  }
   if (o.greeks) {
     return mc_greeks_adjoint(ctx, m, f, n_paths, n_steps, seed, &o, MC_ADJ_FULL, mcp::kCkpt,
                              nullptr, 0, 1.0, out);
   }
-  const bool fp64 = o.prec == MC_FP64;
   HestonParams p = heston_params(m, f, n_paths, n_steps, seed, o, o.stream_tag);
   Moments mom;
   double kms = 0.0;
@@ -1398,7 +1428,7 @@ size_t mc_workspace_bytes(const mc_model* m, const mc_payoff* f, uint64_t n_path
   const uint32_t C = mc_path_channels(m, f, &o);
   if (C == 0) return 0;
   size_t bytes = layout_for(n_paths, (int)C, o.path_values != nullptr).bytes;
-  if (m->kind == MC_HESTON && o.greeks)
+  if (m->kind == MC_HESTON && o.greeks && o.greeks_method == MC_GREEKS_PATHWISE)
     bytes = align256(bytes) + align256(mc_adjoint_ckpt_bytes(n_paths, n_steps, mcp::kCkpt));
   if (m->kind == MC_HESTON && f->cv == MC_CV_LEARNED) {
     const uint64_t n_pilot = o.pilot_paths ? o.pilot_paths : (1ull << 16);
@@ -1424,8 +1454,11 @@ mc_status mc_price(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint6
   if (st != MC_OK) return st;
   if (!out) return fail(ctx, MC_ERR_INVALID_ARG, "out must not be NULL");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, MC_ERR_DEVICE, "hipSetDevice");
-  if (o.greeks == 0 || o.greeks_method == MC_GREEKS_PATHWISE)
-    return mc_price_impl(ctx, m, f, n_paths, n_steps, seed, o, out);
+  if (o.greeks == 0 || o.greeks_method != MC_GREEKS_FD_CRN) {
+    st = mc_price_impl(ctx, m, f, n_paths, n_steps, seed, o, out);
+    if (st == MC_OK && o.greeks) out->greeks_method = (int)o.greeks_method;
+    return st;
+  }
   // Finite differences on common random numbers: the price run, then one
   // pair of bumped runs per requested greek.
   mc_options ob = o;

@@ -109,6 +109,70 @@ __global__ __launch_bounds__(kBlock) void heston_price_kernel(const HestonParams
   block_moments<C, kBlock>(y, active && finite, active && !finite, P.partials, gridDim.x);
 }
 
+// Pathwise delta and d/dv0 in forward mode: the tangents (dz, dv) of the
+// state with respect to v0 ride along the step (the derivative of
+// sqrt(v+ dt) is taken as 0 where v <= 0), and d/dS0 needs none (z does not
+// depend on S0). Two inputs, so this is cheaper than the reverse sweep: no
+// checkpoints and no recomputation. Channels: payoff, delta, d/dv0 of the
+// European (ASIAN = false) or arithmetic-Asian call.
+template <typename R, bool ASIAN>
+__global__ __launch_bounds__(kBlock) void heston_tangent_kernel(const HestonParams P) {
+  const uint64_t pid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool active = pid < P.n_paths;
+  double y[3] = {0.0, 0.0, 0.0};
+  if (active) {
+    HestonStep<R> hs;
+    hs.init(P);
+    const PathCounter pc = make_counter(P.path_offset + pid, P.tag, P.k0, P.k1);
+    const R half_dt = R(0.5) * hs.dt;
+    R z = R(0), v = (R)P.v0, dz = R(0), dv = R(1), sumE = R(0), sumEd = R(0);
+    const uint32_t n = P.n_steps;
+    auto step = [&](R Z1, R Z2) {
+      const R vp = v > R(0) ? v : R(0);
+      const R dvp = v > R(0) ? dv : R(0);
+      // d sqrt(vp dt) = dt dvp / (2 sqrt(vp dt)); 0 where vp = 0.
+      const R dsq = vp > R(0) ? half_dt * dvp * HDom<R>::rsqrt_(vp * hs.dt) : R(0);
+      const R Zs = hs.rho * Z1 + hs.rhoc * Z2;
+      const R dz_new = dz + hs.a1 * dvp + hs.a2 * (dsq * Zs);
+      const R dv_new = dv - hs.kdt * dvp + hs.xi * (dsq * Z1);
+      R zs;
+      hs.step(z, v, Z1, Z2, zs);
+      dz = dz_new;
+      dv = dv_new;
+      if constexpr (ASIAN) {
+        const R E = HDom<R>::exp_(z);
+        sumE += E;
+        sumEd += E * dz;
+      }
+    };
+    for (uint32_t j = 0; 2 * j < n; ++j) {
+      const Normals4<R> nz = normals4<R>(philox(j, pc));
+      step(nz.z[0], nz.z[1]);
+      if (2 * j + 1 < n) step(nz.z[2], nz.z[3]);
+    }
+    // z and dz are in the kernel's log domain (log2 for FP32): d exp(x) =
+    // exp(x) dz / scale.
+    const double S0 = P.S0, K = P.K, disc = P.disc, inv_sc = 1.0 / HDom<R>::kLogScale;
+    if constexpr (ASIAN) {
+      const double A = S0 * (double)sumE / (double)n;
+      y[0] = disc * (A > K ? A - K : 0.0);
+      y[1] = A > K ? disc * A / S0 : 0.0;
+      y[2] = A > K ? disc * S0 * inv_sc * (double)sumEd / (double)n : 0.0;
+    } else {
+      const double ST = S0 * (double)HDom<R>::exp_(z);
+      y[0] = disc * (ST > K ? ST - K : 0.0);
+      y[1] = ST > K ? disc * ST / S0 : 0.0;
+      y[2] = ST > K ? disc * ST * inv_sc * (double)dz : 0.0;
+    }
+  }
+  const bool finite = isfinite(y[0]) && isfinite(y[1]) && isfinite(y[2]);
+  if (active && P.path_out != nullptr) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) P.path_out[pid * 3 + c] = y[c];
+  }
+  block_moments<3, kBlock>(y, active && finite, active && !finite, P.partials, gridDim.x);
+}
+
 // Channel sets of the adjoint phases.
 template <int PHASE>
 struct AdjC;
@@ -243,6 +307,25 @@ hipError_t launch_heston(const HestonParams& p, uint32_t mask, bool fp64, hipStr
     hipLaunchKernelGGL((heston_price_kernel<double, EA>), dim3(nb), dim3(kBlock), 0, s, p);
   else
     hipLaunchKernelGGL((heston_price_kernel<float, EA>), dim3(nb), dim3(kBlock), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_heston_tangent(const HestonParams& p, bool asian, bool fp64, hipStream_t s,
+                                 uint32_t* n_blocks) {
+  const uint32_t nb = (uint32_t)((p.n_paths + kBlock - 1) / kBlock);
+  *n_blocks = nb;
+  if (nb == 0) return hipErrorInvalidValue;
+  if (fp64) {
+    if (asian)
+      hipLaunchKernelGGL((heston_tangent_kernel<double, true>), dim3(nb), dim3(kBlock), 0, s, p);
+    else
+      hipLaunchKernelGGL((heston_tangent_kernel<double, false>), dim3(nb), dim3(kBlock), 0, s, p);
+  } else {
+    if (asian)
+      hipLaunchKernelGGL((heston_tangent_kernel<float, true>), dim3(nb), dim3(kBlock), 0, s, p);
+    else
+      hipLaunchKernelGGL((heston_tangent_kernel<float, false>), dim3(nb), dim3(kBlock), 0, s, p);
+  }
   return hipGetLastError();
 }
 

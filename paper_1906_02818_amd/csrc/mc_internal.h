@@ -80,6 +80,10 @@ struct HestonParams {
 };
 hipError_t launch_heston(const HestonParams& p, uint32_t mask, bool fp64, hipStream_t s,
                          uint32_t* n_blocks);
+// Price, pathwise delta and d/dv0 of one payoff by forward-mode tangents
+// (channels: payoff, delta, d/dv0).
+hipError_t launch_heston_tangent(const HestonParams& p, bool asian, bool fp64, hipStream_t s,
+                                 uint32_t* n_blocks);
 
 // Pathwise adjoint (reverse sweep with checkpoints every kCkpt steps).
 constexpr int kCkpt = 16;

@@ -185,3 +185,81 @@ def test_european_greeks_against_characteristic_function(ctx):
     assert abs(r["price"] - cf()) < 4 * r["std_err"] + 0.01
     assert abs(r["delta"] - d) < 4 * r["delta_se"] + 1e-3
     assert abs(r["vega"] - v) < 5 * r["vega_se"] + 0.3
+
+
+TANGENT = dict(greeks=mc.MC_GREEK_DELTA | mc.MC_GREEK_VEGA, greeks_method=mc.MC_GREEKS_TANGENT)
+
+
+@pytest.mark.parametrize("asian,N,n", [(True, 4096 + 77, 33), (False, 4096 + 77, 64)])
+def test_tangent_fp64_matches_oracle_path_by_path(ctx, asian, N, n):
+    # FP64 forward-mode tangents against the oracle's FP64 tangents on the
+    # same counters: the same arithmetic, so agreement to rounding.
+    say("tangent fp64", asian, N, n)
+    kind = mc.MC_ASIAN_ARITH_CALL if asian else mc.MC_EURO_CALL
+    r = mc.mc_price(ctx, model(), mc.Payoff(kind, H["K"]), N, n, SEED,
+                    mc.Options(prec=mc.MC_FP64, path_values=True, **TANGENT))
+    assert r["greeks_method"] == mc.MC_GREEKS_TANGENT
+    o = orc(n, N)
+    cols = (1, 4, 5) if asian else (0, 2, 3)
+    pv = r["path_values"]
+    for c, col in enumerate(cols):
+        np.testing.assert_allclose(pv[:, c], o[:, col], rtol=1e-10, atol=1e-11)
+    for col, key in ((cols[1], "delta"), (cols[2], "vega")):
+        assert r[key] == pytest.approx(oracle.estimate(o[:, col])["price"], rel=1e-11, abs=1e-13)
+
+
+@pytest.mark.parametrize("asian", [True, False])
+def test_tangent_fp32_equals_the_adjoint(ctx, asian):
+    # Forward and reverse mode compute the same pathwise derivative: in FP32
+    # on the same paths they differ by rounding only.
+    N, n = (1 << 18) + 5, 256
+    kind = mc.MC_ASIAN_ARITH_CALL if asian else mc.MC_EURO_CALL
+    f = mc.Payoff(kind, H["K"])
+    t = mc.mc_price(ctx, model(), f, N, n, SEED, mc.Options(path_values=True, **TANGENT))
+    a = mc.mc_greeks_adjoint(ctx, model(), f, N, n, SEED, mc.Options(path_values=True))
+    say(f"  delta tangent {t['delta']:.7f} adjoint {a['delta']:.7f}; "
+        f"dv0 tangent {t['vega']:.5f} adjoint {a['vega']:.5f} +- {a['vega_se']:.1e}")
+    assert t["price"] == pytest.approx(a["price"], rel=1e-6)
+    np.testing.assert_allclose(t["path_values"][:, 1], a["path_values"][:, 1], rtol=1e-5,
+                               atol=1e-7)
+    err = np.abs(t["path_values"][:, 2] - a["path_values"][:, 2]) / (
+        1.0 + np.abs(a["path_values"][:, 2]))
+    assert np.quantile(err, 0.999) < 1e-3
+    assert abs(t["vega"] - a["vega"]) < 1e-3 * a["vega_se"] + 1e-5 * abs(a["vega"])
+    assert abs(t["delta"] - a["delta"]) < 1e-5 * abs(a["delta"])
+
+
+def test_tangent_fp32_full_size_sampled_paths_against_oracle(ctx):
+    # The benchmarked size in FP32: price, delta and d/dv0 of 2^22 paths x 256
+    # steps; sampled paths against the oracle's FP64 tangents.
+    N, n = 1 << 22, 256
+    f = mc.Payoff(mc.MC_ASIAN_ARITH_CALL, H["K"])
+    r = mc.mc_price(ctx, model(), f, N, n, SEED, mc.Options(path_values=True, **TANGENT))
+    assert r["n_nonfinite"] == 0
+    rng = np.random.default_rng(11)
+    idx = np.sort(rng.choice(N, 256, replace=False))
+    pv = r["path_values"]
+    for i in idx[:256:32]:
+        o = orc(n, 1, path0=int(i))[0]
+        assert pv[i, 0] == pytest.approx(o[1], rel=3e-4, abs=3e-4)
+        if o[1] > 1e-3:
+            assert pv[i, 1] == pytest.approx(o[4], rel=3e-4, abs=1e-5)
+
+
+def test_tangent_argument_handling(ctx):
+    # Barriers have no pathwise derivative in either mode; an unknown method
+    # is refused; GBM's pathwise greeks are forward tangents already.
+    f = mc.Payoff(mc.MC_EURO_CALL, 100.0)
+    gbm = mc.Model(kind=mc.MC_GBM, S0=100.0, r=0.03, T=1.0, sigma=0.25)
+    a = mc.mc_price(ctx, gbm, f, 1 << 14, 16, SEED, mc.Options(**TANGENT))
+    b = mc.mc_price(ctx, gbm, f, 1 << 14, 16, SEED,
+                    mc.Options(greeks=mc.MC_GREEK_DELTA | mc.MC_GREEK_VEGA))
+    assert a["delta"] == b["delta"] and a["vega"] == b["vega"]
+    assert a["greeks_method"] == mc.MC_GREEKS_TANGENT
+    with pytest.raises(mc.McError) as e:
+        mc.mc_price(ctx, gbm, mc.Payoff(mc.MC_UO_BARRIER_CALL, 100.0, B=130.0), 1024, 8, SEED,
+                    mc.Options(**TANGENT))
+    assert "UNSUPPORTED" in str(e.value)
+    with pytest.raises(mc.McError) as e:
+        mc.mc_price(ctx, gbm, f, 1024, 8, SEED, mc.Options(greeks=1, greeks_method=3))
+    assert "INVALID_ARG" in str(e.value)
