@@ -861,7 +861,8 @@ mc_status cv_fill_cache(mc_context* ctx, hipStream_t s, const mc_model* m, const
 mc_status cv_loss_grad_device(mc_context* ctx, hipStream_t s, const mc_model* m,
                               const mc_payoff* f, uint32_t n_steps, uint64_t first,
                               uint64_t n_cache, uint64_t batch, uint32_t hedge_every, bool bf16,
-                              const CvTrainWs& w, double* log_row) {
+                              const CvTrainWs& w, double* log_row,
+                              uint32_t* grad_blocks = nullptr) {
   mc_options o = defaults();
   o.hip_stream = s;
   const RunLayout Lay = layout_for(batch, 3, true, kCvTrainPathsPerBlock);
@@ -883,7 +884,12 @@ mc_status cv_loss_grad_device(mc_context* ctx, hipStream_t s, const mc_model* m,
   p.g_scale = -2.0 / (double)batch;
   p.grad_partials = w.grad_partials;
   HIP_TRY(ctx, launch_cv_backward(p, s, &nb));   // one partial per block
-  HIP_TRY(ctx, launch_final_reduce(w.grad_partials, nb, kMlpNParam, w.grad, s));
+  // With grad_blocks the caller reduces the partials itself (the training
+  // loop does it inside its Adam step).
+  if (grad_blocks)
+    *grad_blocks = nb;
+  else
+    HIP_TRY(ctx, launch_final_reduce(w.grad_partials, nb, kMlpNParam, w.grad, s));
   return MC_OK;
 }
 
@@ -2088,12 +2094,13 @@ mc_status mc_cv_train(mc_context* ctx, const mc_model* m, const mc_payoff* f, ui
   for (uint32_t t = 0; t < cfg->steps; ++t) {
     // Minibatches cycle through the training set.
     const uint64_t first = (t % n_batches) * B;
+    uint32_t nb = 0;
     st = cv_loss_grad_device(ctx, s, m, f, n_steps, first, n_train, B, cfg->hedge_every, bf16, w,
-                             w.log + (size_t)t * n_mom);
+                             w.log + (size_t)t * n_mom, &nb);
     if (st != MC_OK) return st;
-    HIP_TRY(ctx, launch_adam(w.b.theta, w.m, w.v, w.grad, kMlpNParam, (int)t + 1, cfg->lr,
-                             cfg->beta1, cfg->beta2, cfg->eps, s));
-    HIP_TRY(ctx, launch_cv_pack(w.b.theta, w.b.w1f, w.b.w2f, w.b.w2tf, w.b.lanec, s));
+    HIP_TRY(ctx, launch_adam_pack(w.grad_partials, nb, w.grad, w.b.theta, w.m, w.v, (int)t + 1,
+                                  cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, w.b.w1f, w.b.w2f,
+                                  w.b.w2tf, w.b.lanec, s));
   }
   std::vector<double> log((size_t)cfg->steps * n_mom);
   HIP_TRY(ctx, hipMemcpyAsync(weights_inout, w.b.theta, kMlpNParam * 4, hipMemcpyDeviceToHost, s));

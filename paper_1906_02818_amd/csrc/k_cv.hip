@@ -710,19 +710,6 @@ __global__ __launch_bounds__(kCvThreads) void cv_eval_kernel(const CvParams P) {
   block_moments<3, kCvThreads>(y, active && finite, active && !finite, P.partials, gridDim.x);
 }
 
-__global__ void adam_kernel(float* __restrict__ theta, float* __restrict__ m,
-                            float* __restrict__ v, const double* __restrict__ grad, int n,
-                            float lr, float b1, float b2, float eps, float c1, float c2) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float gr = (float)grad[i];
-  const float mi = b1 * m[i] + (1.0f - b1) * gr;
-  const float vi = b2 * v[i] + (1.0f - b2) * gr * gr;
-  m[i] = mi;
-  v[i] = vi;
-  theta[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-}
-
 // Builds the per-lane fragments from the flat weights (one thread per
 // output float). Units: u(mb, r, h) as above; layer-2 k-slot (kb, h, j) is
 // the layer-1 unit u(kb/2, 8 (kb mod 2) + j, h).
@@ -753,6 +740,84 @@ __global__ void cv_pack_kernel(const float* __restrict__ th, float* __restrict__
     const int u = unit_of(mb, r, h);
     lanec[t] = b2[u] * kNeg2Log2e;
     lanec[kLanecFloats / 2 + t] = W3[u];
+  }
+}
+
+// Inverse of unit_of: the fragment slot (mb, r, h) that holds hidden unit u.
+__device__ __forceinline__ void slot_of(int u, int& mb, int& r, int& h) {
+  mb = u >> 5;
+  const int q = u & 31;
+  h = (q >> 2) & 1;
+  r = 4 * (q >> 3) + (q & 3);
+}
+
+// One Adam step with the gradient reduction in front and the fragment update
+// behind, one block per parameter. The block sums its parameter's per-block
+// partials in the order of final_reduce_kernel, takes Adam's step on
+// (theta, m, v) with the bias corrections c1 = 1 - b1^t, c2 = 1 - b2^t, and
+// writes the new value into each fragment slot that cv_pack_kernel gives the
+// parameter (W1, b1: one; W2: one in each of the two layouts; b2, W3: the 32
+// lanes of a half-wave). Padding slots keep the zeros of the first pack; b3
+// lives in theta only.
+__global__ __launch_bounds__(256) void adam_pack_kernel(
+    const double* __restrict__ partials, uint32_t n_blocks, double* __restrict__ grad,
+    float* __restrict__ theta, float* __restrict__ m, float* __restrict__ v, float lr, float b1,
+    float b2, float eps, float c1, float c2, float* __restrict__ w1f, float* __restrict__ w2f,
+    float* __restrict__ w2tf, float* __restrict__ lanec) {
+  __shared__ double sh[256];
+  __shared__ float th_new;
+  const int i = blockIdx.x;
+  const double* row = partials + (size_t)i * n_blocks;
+  double s = 0.0;
+  for (uint32_t k = threadIdx.x; k < n_blocks; k += 256) s += row[k];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double g = sh[0];
+    grad[i] = g;
+    const float gr = (float)g;
+    const float mi = b1 * m[i] + (1.0f - b1) * gr;
+    const float vi = b2 * v[i] + (1.0f - b2) * gr * gr;
+    m[i] = mi;
+    v[i] = vi;
+    const float t = theta[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    theta[i] = t;
+    th_new = t;
+  }
+  __syncthreads();
+  const float t = th_new;
+  const int L = threadIdx.x;
+  if (i < 320) {                       // W1 [64][4] and b1 [64]: lane = unit row, h = 0
+    if (L == 0) {
+      const int u = i < 256 ? i >> 2 : i - 256, j = i < 256 ? (i & 3) : 4;
+      w1f[(u >> 5) * 512 + (u & 31) * 8 + j] = t;
+    }
+  } else if (i < 4416) {               // W2 [64 out][64 in]
+    if (L < 2) {
+      const int e = i - 320;
+      const int a = L == 0 ? e >> 6 : e & 63;   // fragment row
+      const int k = L == 0 ? e & 63 : e >> 6;   // k-slot unit
+      int mb, r, h;
+      slot_of(k, mb, r, h);
+      const int dst = (a >> 5) * 2048 + (2 * mb + (r >> 3)) * 512 + ((a & 31) + 32 * h) * 8 + (r & 7);
+      (L == 0 ? w2f : w2tf)[dst] = t;
+    }
+  } else if (i < 4544) {               // b2 [64] (scaled) and W3 [64]
+    if (L < 32) {
+      const bool is_b2 = i < 4480;
+      const int u = is_b2 ? i - 4416 : i - 4480;
+      int mb, r, h;
+      slot_of(u, mb, r, h);
+      const int dst = (32 * h + L) * 32 + 16 * mb + r;
+      if (is_b2)
+        lanec[dst] = t * kNeg2Log2e;
+      else
+        lanec[kLanecFloats / 2 + dst] = t;
+    }
   }
 }
 
@@ -815,11 +880,15 @@ hipError_t launch_cv_backward(const CvParams& p, hipStream_t s, uint32_t* n_bloc
   return hipGetLastError();
 }
 
-hipError_t launch_adam(float* theta, float* m, float* v, const double* grad, int n, int t,
-                       double lr, double b1, double b2, double eps, hipStream_t s) {
+hipError_t launch_adam_pack(const double* partials, uint32_t n_blocks, double* grad, float* theta,
+                            float* m, float* v, int t, double lr, double b1, double b2,
+                            double eps, float* w1f, float* w2f, float* w2tf, float* lanec,
+                            hipStream_t s) {
+  if (n_blocks == 0) return hipErrorInvalidValue;
   const float c1 = (float)(1.0 - std::pow(b1, t)), c2 = (float)(1.0 - std::pow(b2, t));
-  hipLaunchKernelGGL(adam_kernel, dim3((n + 255) / 256), dim3(256), 0, s, theta, m, v, grad, n,
-                     (float)lr, (float)b1, (float)b2, (float)eps, c1, c2);
+  hipLaunchKernelGGL(adam_pack_kernel, dim3(kMlpNParam), dim3(256), 0, s, partials, n_blocks,
+                     grad, theta, m, v, (float)lr, (float)b1, (float)b2, (float)eps, c1, c2, w1f,
+                     w2f, w2tf, lanec);
   return hipGetLastError();
 }
 

@@ -246,8 +246,12 @@ hipError_t launch_cv_cache(const CvParams& p, hipStream_t s);
 hipError_t launch_cv_forward(const CvParams& p, hipStream_t s);
 hipError_t launch_cv_values(const CvParams& p, hipStream_t s, uint32_t* n_blocks);
 hipError_t launch_cv_backward(const CvParams& p, hipStream_t s, uint32_t* n_blocks);
-hipError_t launch_adam(float* theta, float* m, float* v, const double* grad, int n, int t,
-                       double lr, double b1, double b2, double eps, hipStream_t s);
+// Reduces the per-block gradient partials [kMlpNParam][n_blocks], takes one
+// Adam step and refreshes the packed fragments, in one launch.
+hipError_t launch_adam_pack(const double* partials, uint32_t n_blocks, double* grad, float* theta,
+                            float* m, float* v, int t, double lr, double b1, double b2,
+                            double eps, float* w1f, float* w2f, float* w2tf, float* lanec,
+                            hipStream_t s);
 
 // ---- reductions and diagnostics ----
 hipError_t launch_final_reduce(const double* partials, uint32_t n_blocks, uint32_t n_mom,
