@@ -10,7 +10,7 @@ from __future__ import annotations
 
 import ctypes as C
 import math
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 from typing import Sequence
 
 import numpy as np
@@ -32,7 +32,7 @@ __all__ = [n for n in dir(_abi) if n.startswith("MC_")] + [
     "mc_price", "mc_price_multi", "mc_greeks_adjoint", "mc_cv_train", "mc_cv_loss_grad",
     "mc_philox_words", "mc_normals", "mc_path_channels", "mc_path_channel_name",
     "mc_workspace_bytes", "mc_adjoint_ckpt_bytes", "mc_status_str", "mc_last_error",
-    "mc_price_mlmc", "mc_mlmc_allocate", "Level", "mc_risk", "mc_price_qmc", "PathwisePrice",
+    "mc_price_mlmc", "mc_mlmc_allocate", "Level", "mc_risk", "mc_price_qmc", "PathwisePrice", "TangentPrice",
     "LsmSpec", "mc_price_lsm",
     "PreparedPriceMulti"]
 
@@ -591,7 +591,35 @@ def _make_pathwise_price():
             return (g(r["delta"], dtype=torch.float64), g(r["vega"], dtype=torch.float64),
                     None, None, None, None, None, None, None)
 
-    return PathwisePrice
+    class TangentPrice(torch.autograd.Function):
+        """Heston price as a differentiable function of (S0, v0), in forward
+        mode.
+
+        forward prices with the tangents of (ln S, v) with respect to S0 and
+        v0 carried beside the state (mc_price, MC_GREEKS_TANGENT) and keeps
+        the two derivatives; backward returns grad_out times them. One kernel
+        and no checkpoint buffer; the derivatives are the adjoint's.
+        """
+
+        @staticmethod
+        def forward(actx, S0, v0, ctx: Context, model: Model, payoff: Payoff, n_paths: int,
+                    n_steps: int, seed: int, opts: Options | None = None):
+            m = Model(**{**model.__dict__, "S0": float(S0), "v0": float(v0)})
+            o = replace(opts if opts is not None else Options(),
+                        greeks=MC_GREEK_DELTA | MC_GREEK_VEGA, greeks_method=MC_GREEKS_TANGENT)
+            r = mc_price(ctx, m, payoff, n_paths, n_steps, seed, o)
+            actx.saved = (r["delta"], r["vega"])
+            return torch.tensor(r["price"], dtype=torch.float64)
+
+        @staticmethod
+        def backward(actx, grad_out):
+            delta, dv0 = actx.saved
+            g = float(grad_out)
+            return (torch.tensor(g * delta, dtype=torch.float64),
+                    torch.tensor(g * dv0, dtype=torch.float64),
+                    None, None, None, None, None, None, None)
+
+    return PathwisePrice, TangentPrice
 
 
-PathwisePrice = _make_pathwise_price()
+PathwisePrice, TangentPrice = _make_pathwise_price() or (None, None)

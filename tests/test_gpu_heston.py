@@ -263,3 +263,30 @@ def test_tangent_argument_handling(ctx):
     with pytest.raises(mc.McError) as e:
         mc.mc_price(ctx, gbm, f, 1024, 8, SEED, mc.Options(greeks=1, greeks_method=3))
     assert "INVALID_ARG" in str(e.value)
+
+
+def test_tangent_autograd_equals_the_adjoint_autograd(ctx):
+    # The forward-mode autograd node returns the adjoint node's gradients:
+    # same price and same (dP/dS0, dP/dv0) scaled by the upstream gradient.
+    import torch
+    N, n = 1 << 15, 256
+    f = mc.Payoff(mc.MC_ASIAN_ARITH_CALL, H["K"])
+    grads = []
+    for fn in (mc.PathwisePrice, mc.TangentPrice):
+        S0 = torch.tensor(H["S0"], dtype=torch.float64, requires_grad=True)
+        v0 = torch.tensor(H["v0"], dtype=torch.float64, requires_grad=True)
+        price = fn.apply(S0, v0, ctx, model(), f, N, n, SEED)
+        (3.0 * price + price ** 2).backward()
+        grads.append((price.item(), S0.grad.item(), v0.grad.item()))
+    (pa, da, va), (pt, dt_, vt) = grads
+    print(f"  adjoint {pa:.7f} {da:.7f} {va:.5f}; tangent {pt:.7f} {dt_:.7f} {vt:.5f}")
+    assert pt == pytest.approx(pa, rel=1e-6)
+    assert dt_ == pytest.approx(da, rel=1e-5)
+    assert vt == pytest.approx(va, rel=1e-4)
+    # The node leaves the caller's options alone.
+    o = mc.Options()
+    S0 = torch.tensor(H["S0"], dtype=torch.float64, requires_grad=True)
+    mc.TangentPrice.apply(S0, torch.tensor(H["v0"], dtype=torch.float64), ctx, model(), f, 1024,
+                          8, SEED, o).backward()
+    assert o.greeks == 0 and o.greeks_method == mc.MC_GREEKS_PATHWISE
+    assert math.isfinite(S0.grad.item())
