@@ -400,13 +400,26 @@ def run_basket(args, ctx, mc, synth, torch):
     roof = _alu_roofline(SLOTS_ASSET_STEP, N * n * d, k_ms, f"basket_kernel<8, {args.prec}>")
     roof["mfma_tflops"] = flops / (k_ms * 1e-3) / 1e12
     roof["mfma_frac"] = flops / (k_ms * 1e-3) / MFMA_PEAK[args.prec]
+    extra = {}
+    if prec != mc.MC_FP32:
+        # The rounding of the reduced-precision product at the full size: the
+        # same paths with FP32 products (within 2e-5 of the FP64 oracle),
+        # outside the timed region.
+        ref = mc.mc_price(ctx, model, f, N, n, synth.SEED,
+                          mc.Options(prec=mc.MC_FP32, greeks=mc.MC_GREEK_DELTA))
+        extra["precision_check"] = {
+            "fp32_price": ref["price"], "fp32_delta0": ref["delta"],
+            "price_diff_se": (r["price"] - ref["price"]) / ref["std_err"],
+            "delta0_diff_se": (r["delta"] - ref["delta"]) / ref["delta_se"],
+            "price_rel_diff": r["price"] / ref["price"] - 1.0}
     return _line(args, "asset-path-steps/s", N * n * d / (ms * 1e-3), "asset-path-steps/s", ms,
                  args.prec,
                  {"workload": f"basket call, d = {d} correlated GBM, {n} steps, 2^20 paths, "
                               f"per-step Z L^T on MFMA ({args.prec})", "n_paths": N,
                   "n_steps": n, "d": d},
                  roof, kernel_ms=k_ms,
-                 prices={"price": r["price"], "se": r["std_err"], "delta0": r["delta"]})
+                 prices={"price": r["price"], "se": r["std_err"], "delta0": r["delta"],
+                         "delta0_se": r["delta_se"]}, **extra)
 
 
 def run_mlmc_basket(args, ctx, mc, synth, torch):
