@@ -334,6 +334,21 @@ def run_asian_barrier(args, ctx, mc, synth, torch):
                          "uo": res[1]["price"], "uo_se": res[1]["std_err"],
                          "geo": res[2]["price"], "geo_se": res[2]["std_err"], "cv_beta": beta,
                          "vrf": res[0]["vrf"]})
+    # Outside the timed region: the same paths with FP64 state, each FP32
+    # price's distance from it in standard errors, and the geometric Asian
+    # against its closed form.
+    r64 = mc.mc_price_multi(ctx, model, payoffs, N, n, synth.SEED,
+                            mc.Options(prec=mc.MC_FP64, cv_beta=beta))
+    pairs = (("asian_cv", res[0]["price"], r64[0]["price"], r64[0]["std_err"]),
+             ("asian_plain", res[0]["plain_price"], r64[0]["plain_price"],
+              r64[0]["plain_std_err"]),
+             ("uo", res[1]["price"], r64[1]["price"], r64[1]["std_err"]),
+             ("geo", res[2]["price"], r64[2]["price"], r64[2]["std_err"]))
+    line["precision_check"] = {"fp64": {k: b for k, _, b, _ in pairs},
+                               "diff_se": {k: (a - b) / se for k, a, b, se in pairs},
+                               "rel_diff": {k: a / b - 1.0 for k, a, b, _ in pairs}}
+    cg = _geo_asian_closed_form(c, n)
+    line["closed_form"] = {"geo": cg, "geo_z": (res[2]["price"] - cg) / res[2]["std_err"]}
     if not args.no_time_to_1bp:
         line["time_to_1bp"] = time_to_1bp(ctx, mc, synth, torch, hedge_every=args.hedge_every,
                                           adam_steps=args.adam_steps)
@@ -361,6 +376,20 @@ def run_european(args, ctx, mc, synth, torch):
                  kernel_ms=k_ms, prices={"price": r["price"], "se": r["std_err"],
                                          "delta": r["delta"], "vega": r["vega"]},
                  black_scholes=_bs_check(c, r))
+
+
+def _geo_asian_closed_form(c, n):
+    """Discrete geometric-Asian call on the fixings t_i = i T / n, i = 1..n.
+    Under GBM ln G is normal with mean ln S0 + (r - s^2/2) T (n + 1) / (2 n)
+    and variance s^2 T (n + 1)(2 n + 1) / (6 n^2), so the price is a
+    lognormal call on G."""
+    S, K, rr, s, T = c["S0"], c["K"], c["r"], c["sigma"], c["T"]
+    m = math.log(S) + (rr - 0.5 * s * s) * T * (n + 1) / (2.0 * n)
+    v = s * s * T * (n + 1) * (2 * n + 1) / (6.0 * n * n)
+    d2 = (m - math.log(K)) / math.sqrt(v)
+    d1 = d2 + math.sqrt(v)
+    N = lambda x: 0.5 * (1.0 + math.erf(x / math.sqrt(2.0)))  # noqa: E731
+    return math.exp(-rr * T) * (math.exp(m + 0.5 * v) * N(d1) - K * N(d2))
 
 
 def _bs_check(c, r):

@@ -87,3 +87,17 @@ def test_black_scholes_check_of_the_european_line():
     assert b["delta"] == pytest.approx(0.6368306511756191, rel=1e-13)
     assert b["vega"] == pytest.approx(37.52403469169379, rel=1e-13)
     assert b["price_z"] == pytest.approx((10.45 - b["price"]) / 0.03)
+
+
+def test_geometric_asian_closed_form_of_the_default_line():
+    # bench.py's own closed form against the tests' (written separately).
+    from closed_forms import geo_asian_call
+    c = synth.ASIAN_BARRIER
+    for n in (1, 12, 252):
+        want = geo_asian_call(c["S0"], c["K"], c["r"], c["sigma"], c["T"], n)
+        assert bench._geo_asian_closed_form(c, n) == pytest.approx(want, rel=1e-12)
+    # n = 1 is the European call on S_T.
+    e = dict(c)
+    b = bench._bs_check(e, {"price": 0.0, "std_err": 1.0, "delta": 0.0, "delta_se": 1.0,
+                            "vega": 0.0, "vega_se": 1.0})
+    assert bench._geo_asian_closed_form(c, 1) == pytest.approx(b["price"], rel=1e-12)
