@@ -616,6 +616,11 @@ def run_heston_adjoint(args, ctx, mc, synth, torch):
                     greeks_method=mc.MC_GREEKS_TANGENT)
     tan = [mc.mc_price(ctx, model, f, N, n, synth.SEED, to) for _ in range(3)]
     t_ms = min(x["kernel_ms"] for x in tan)
+    # The same paths with FP64 state (forward tangents in FP64): the FP32
+    # adjoint's price and greeks against them, in standard errors.
+    r64 = mc.mc_price(ctx, model, f, N, n, synth.SEED,
+                      mc.Options(prec=mc.MC_FP64, greeks=mc.MC_GREEK_DELTA | mc.MC_GREEK_VEGA,
+                                 greeks_method=mc.MC_GREEKS_TANGENT))
     fd = mc.mc_price(ctx, model, f, 1 << 20, n, synth.SEED,
                      mc.Options(greeks=mc.MC_GREEK_DELTA | mc.MC_GREEK_VEGA,
                                 greeks_method=mc.MC_GREEKS_FD_CRN))
@@ -633,6 +638,14 @@ def run_heston_adjoint(args, ctx, mc, synth, torch):
                                   "delta": tan[-1]["delta"], "dv0": tan[-1]["vega"]},
                  prices={"price": r["price"], "se": r["std_err"], "delta": r["delta"],
                          "delta_se": r["delta_se"], "dv0": r["vega"], "dv0_se": r["vega_se"]},
+                 precision_check={
+                     "fp64": {"price": r64["price"], "delta": r64["delta"], "dv0": r64["vega"]},
+                     "diff_se": {"price": (r["price"] - r64["price"]) / r64["std_err"],
+                                 "delta": (r["delta"] - r64["delta"]) / r64["delta_se"],
+                                 "dv0": (r["vega"] - r64["vega"]) / r64["vega_se"]},
+                     "rel_diff": {"price": r["price"] / r64["price"] - 1.0,
+                                  "delta": r["delta"] / r64["delta"] - 1.0,
+                                  "dv0": r["vega"] / r64["vega"] - 1.0}},
                  fd_check={"n_paths": 1 << 20, "delta": fd["delta"], "delta_se": fd["delta_se"],
                            "dv0": fd["vega"], "dv0_se": fd["vega_se"],
                            "delta_z": z(r["delta"], r["delta_se"], fd["delta"], fd["delta_se"]),
