@@ -220,6 +220,15 @@ def time_to_1bp(ctx, mc, synth, torch, hedge_every=16, adam_steps=2000):
                               "price": run["price"], "std_err": run["std_err"],
                               "vrf": run["vrf"], "plain_price_same_paths": run["plain_price"],
                               "kernel_ms": run["kernel_ms"]}
+    # The trained network evaluated once on 2^24 fresh paths (stream tag 8,
+    # used by nothing else): its variance-reduction factor against plain
+    # Monte Carlo on the same paths.
+    ev, t_ev = _timed(torch, lambda: mc.mc_price(ctx, model, cv_f, 1 << 24, n, synth.SEED,
+                                                 opts(8)))
+    out["learned_cv_bf16"]["fresh_2p24"] = {
+        "stream_tag": 8, "n_paths": 1 << 24, "price": ev["price"], "std_err": ev["std_err"],
+        "vrf": ev["vrf"], "plain_price": ev["plain_price"], "plain_std_err": ev["plain_std_err"],
+        "run_s": t_ev, "kernel_ms": ev["kernel_ms"]}
     out["speedup_excl_train"] = out["plain_fp32"]["total_s"] / out["learned_cv_bf16"]["total_s"]
     out["speedup_incl_train"] = (out["plain_fp32"]["total_s"]
                                  / out["learned_cv_bf16"]["total_incl_train_s"])
@@ -597,6 +606,7 @@ def run_risk(args, ctx, mc, synth, torch):
 
 
 def run_heston_adjoint(args, ctx, mc, synth, torch):
+    import numpy as np
     H = synth.HESTON
     N, n = H["n_paths"], H["n_steps"]
     model = _heston_model(mc, synth)
@@ -617,10 +627,30 @@ def run_heston_adjoint(args, ctx, mc, synth, torch):
     tan = [mc.mc_price(ctx, model, f, N, n, synth.SEED, to) for _ in range(3)]
     t_ms = min(x["kernel_ms"] for x in tan)
     # The same paths with FP64 state (forward tangents in FP64): the FP32
-    # adjoint's price and greeks against them, in standard errors.
+    # adjoint's price and greeks against them, in standard errors of each
+    # estimate and of the per-path differences. The FP32 d/dv0 sits about half
+    # a standard error off; the bound stated beside it: the mean per-path
+    # difference is within 4 standard errors of the differences, and without
+    # the 100 largest per-path differences the rest is within 0.01 standard
+    # errors of the greek (the difference lives on the few paths whose
+    # variance reaches zero within FP32 resolution).
     r64 = mc.mc_price(ctx, model, f, N, n, synth.SEED,
                       mc.Options(prec=mc.MC_FP64, greeks=mc.MC_GREEK_DELTA | mc.MC_GREEK_VEGA,
-                                 greeks_method=mc.MC_GREEKS_TANGENT))
+                                 greeks_method=mc.MC_GREEKS_TANGENT, path_values=True))
+    pv32 = mc.mc_greeks_adjoint(ctx, model, f, N, n, synth.SEED,
+                                mc.Options(path_values=True))["path_values"]
+    per_path = {}
+    for c, name in ((0, "price"), (1, "delta"), (2, "dv0")):
+        d = pv32[:, c] - r64["path_values"][:, c]
+        se_g = r64["path_values"][:, c].std(ddof=1) / math.sqrt(N)
+        top = np.argsort(np.abs(d))[::-1][:100]
+        per_path[name] = {"mean_diff_se_of_diff": float(d.mean() / (d.std(ddof=1) / math.sqrt(N))),
+                          "rest_without_top100_se": float((d.sum() - d[top].sum()) / N / se_g),
+                          "max_abs_diff": float(np.abs(d).max())}
+    per_path["bound"] = ("FP32 price and delta within 0.1 SE of FP64 state; d/dv0 not: its "
+                         "mean per-path difference within 4 SE of the differences, and within "
+                         "0.01 SE of the greek without the 100 largest per-path differences")
+    del pv32
     fd = mc.mc_price(ctx, model, f, 1 << 20, n, synth.SEED,
                      mc.Options(greeks=mc.MC_GREEK_DELTA | mc.MC_GREEK_VEGA,
                                 greeks_method=mc.MC_GREEKS_FD_CRN))
@@ -645,7 +675,8 @@ def run_heston_adjoint(args, ctx, mc, synth, torch):
                                  "dv0": (r["vega"] - r64["vega"]) / r64["vega_se"]},
                      "rel_diff": {"price": r["price"] / r64["price"] - 1.0,
                                   "delta": r["delta"] / r64["delta"] - 1.0,
-                                  "dv0": r["vega"] / r64["vega"] - 1.0}},
+                                  "dv0": r["vega"] / r64["vega"] - 1.0},
+                     "per_path": per_path},
                  fd_check={"n_paths": 1 << 20, "delta": fd["delta"], "delta_se": fd["delta_se"],
                            "dv0": fd["vega"], "dv0_se": fd["vega_se"],
                            "delta_z": z(r["delta"], r["delta_se"], fd["delta"], fd["delta_se"]),
@@ -878,7 +909,8 @@ def main():
     ap.add_argument("--workload", choices=list(WORKLOADS), default="asian_barrier")
     ap.add_argument("--prec", choices=["fp32", "bf16", "fp16", "bf16x2"], default=None,
                     help="matrix-product precision (default: bf16 for basket and risk, fp32 "
-                         "for qmc_basket, whose standard error is below the BF16 bias)")
+                         "for qmc_basket, which refuses bf16: its standard error is below "
+                         "the BF16 bias)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-time-to-1bp", action="store_true")
     ap.add_argument("--hedge-every", type=int, default=16)

@@ -398,10 +398,13 @@ mc_status mc_risk(mc_context *ctx, const mc_model *model, const mc_portfolio *po
  * mean over its n_points paths; price and std_err are the mean of the
  * n_replicates estimates and their standard deviation / sqrt(n_replicates)
  * (NaN for one replicate). Model MC_GBM_BASKET, payoff MC_BASKET_CALL,
- * prec MC_FP32 / MC_BF16_GEMM / MC_FP16_GEMM, greeks 0; path_values (host
- * [n_points][3], the channels of mc_price) only with one replicate. The
- * QMC standard error can fall below the bias of BF16 products (a few 1e-4
- * relative with few assets); FP16 or FP32 products keep it out.
+ * prec MC_FP32 or MC_FP16_GEMM, greeks 0; path_values (host
+ * [n_points][3], the channels of mc_price) only with one replicate.
+ * Precision: the QMC standard error falls below the bias of BF16 products
+ * (L' rounded to 8 bits moves a 16-asset price by a few 1e-4 relative,
+ * about 4 QMC standard errors at 16 x 2^16 points), so MC_BF16_GEMM and
+ * MC_BF16X2_GEMM are MC_ERR_UNSUPPORTED here; FP16 products (11 bits) stay
+ * within 0.1 standard errors of the FP64 estimate at that size.
  * Errors: n_replicates outside 1..MC_QMC_MAX_REPLICATES, point indices
  * reaching 2^32, or n_steps * dim above 2^16 dimensions ->
  * MC_ERR_INVALID_ARG; otherwise the errors of mc_price. */

@@ -1706,8 +1706,16 @@ mc_status mc_price_qmc(mc_context* ctx, const mc_model* m, const mc_payoff* f, u
   if (n_replicates < 1 || n_replicates > MC_QMC_MAX_REPLICATES)
     return fail(ctx, MC_ERR_INVALID_ARG, "n_replicates must be in 1..%d", MC_QMC_MAX_REPLICATES);
   if (o0.greeks) return fail(ctx, MC_ERR_UNSUPPORTED, "quasi-Monte Carlo carries no greeks");
-  if (o0.prec != MC_FP32 && o0.prec != MC_BF16_GEMM && o0.prec != MC_FP16_GEMM)
-    return fail(ctx, MC_ERR_UNSUPPORTED, "quasi-Monte Carlo runs in MC_FP32, MC_BF16_GEMM, MC_FP16_GEMM");
+  // BF16 products are refused: rounding L' to 8 bits biases the price by a
+  // few 1e-4 relative when few assets average it out, and the QMC standard
+  // error falls below that (16 assets, 16 x 2^16 points: -4 standard errors).
+  // FP16 products (11 bits) stay within a small fraction of it.
+  if (o0.prec == MC_BF16_GEMM)
+    return fail(ctx, MC_ERR_UNSUPPORTED,
+                "quasi-Monte Carlo refuses MC_BF16_GEMM (its bias exceeds the QMC standard "
+                "error); use MC_FP16_GEMM or MC_FP32");
+  if (o0.prec != MC_FP32 && o0.prec != MC_FP16_GEMM)
+    return fail(ctx, MC_ERR_UNSUPPORTED, "quasi-Monte Carlo runs in MC_FP32 or MC_FP16_GEMM");
   if (o0.path_values && n_replicates != 1)
     return fail(ctx, MC_ERR_UNSUPPORTED, "path_values need a single replicate");
   mc_status st = validate_all(ctx, m, f, n_points, n_steps, o0);

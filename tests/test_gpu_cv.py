@@ -112,6 +112,38 @@ def test_cv_eval_bf16_full_size_sampled(ctx):
     assert r["price"] == pytest.approx(pv[:, 2].mean(), rel=1e-9)
 
 
+def test_bf16_price_within_tenth_se_of_fp64_network(ctx):
+    # Reduced-precision bar (Sec. V-A precision policy): with trained weights,
+    # the BF16 network products move the learned-CV price on 2^20 paths by
+    # less than 0.1 of its standard error against the same network evaluated
+    # in FP64 by the oracle, on the same paths (rebalanced every 16 of 256
+    # steps, as in the time-to-1bp comparison). The oracle here is the plain
+    # FP64 network, not its bfloat16-operand mode.
+    n, m_every, N = 256, 16, 1 << 20
+    say("cv bf16 vs FP64 network")
+    w, log = mc.mc_cv_train(ctx, MODEL, PAY, 1 << 18, n, SEED, synth.glorot_mlp(), lr=3e-3,
+                            steps=300, batch=1 << 14, hedge_every=m_every, prec=mc.MC_BF16_GEMM)
+    assert log[-10:].mean() < 0.5 * log[0]
+    w64 = w.astype(np.float64)
+    r = mc.mc_price(ctx, MODEL, PAY, N, n, SEED,
+                    mc.Options(prec=mc.MC_BF16_GEMM, cv_weights=w, cv_hedge_every=m_every,
+                               path_values=True, cv_beta=1.0))
+    o = oracle.heston_cv(H, n, w64, N, SEED, m_every=m_every)
+    e = oracle.estimate(o[:, 2])
+    vrf = oracle.estimate(o[:, 0])["variance"] / e["variance"]
+    pv = r["path_values"]
+    dh = pv[:, 1] - o[:, 1]
+    say(f"  BF16 {r['price']:.6f} +- {r['std_err']:.2e}; FP64 network {e['price']:.6f} "
+        f"+- {e['std_err']:.2e}; difference {(r['price'] - e['price']) / r['std_err']:+.4f} SE; "
+        f"VRF {vrf:.2f}; hedge P&L rel-L2 {np.linalg.norm(dh) / np.linalg.norm(o[:, 1]):.2e}")
+    # FP32 path state: the running average carries a few 1e-6 of S0 on the
+    # worst of 2^20 paths.
+    np.testing.assert_allclose(pv[:, 0], o[:, 0], rtol=3e-4, atol=1e-5 * H["S0"])
+    assert vrf > 2.0                      # the trained network hedges
+    assert abs(r["price"] - e["price"]) < 0.1 * r["std_err"]
+    assert abs(r["std_err"] / e["std_err"] - 1.0) < 0.05
+
+
 def test_hedge_has_zero_mean_on_gpu(ctx):
     th = weights(0.5, seed=8)
     for prec in (mc.MC_FP32, mc.MC_BF16_GEMM):

@@ -1,8 +1,9 @@
 """GPU parity of randomised Sobol' quasi-Monte Carlo on the basket kernel
 (Sec. IV-B, Sec. VI-D): per-path channels against the FP64 oracle on the
-same shifted points (one and several steps, point offsets, BF16), replicate
+same shifted points (one and several steps, point offsets, FP16), replicate
 estimates against the oracle's, the geometric-basket closed form with an
-RMSE that falls faster than N^(-1/2), and argument errors."""
+RMSE that falls faster than N^(-1/2), and argument errors (BF16 products,
+whose bias exceeds the QMC standard error, are refused)."""
 import math
 
 import numpy as np
@@ -38,7 +39,7 @@ def market(d, r=0.05):
 
 @pytest.mark.parametrize("d,N,n,offset,prec", [(16, 4096, 1, 0, mc.MC_FP32),
                                                (32, 3000, 3, 1000, mc.MC_FP32),
-                                               (16, 2048, 2, 0, mc.MC_BF16_GEMM)])
+                                               (16, 2048, 2, 0, mc.MC_FP16_GEMM)])
 def test_qmc_paths_match_oracle(ctx, d, N, n, offset, prec):
     say("qmc paths", d, N, n, offset, prec)
     model, S0, sigma, corr, L, w = market(d)
@@ -50,11 +51,11 @@ def test_qmc_paths_match_oracle(ctx, d, N, n, offset, prec):
         np.testing.assert_allclose(pv[:, 0], o[:, 0], rtol=1e-4, atol=1e-4)
         np.testing.assert_allclose(pv[:, 1], o[:, 1], rtol=1e-4, atol=1e-4)
     else:
-        # BF16 increments: per-path error of the 8-bit-mantissa rounding of
+        # FP16 increments: per-path error of the 11-bit-mantissa rounding of
         # Z and L (largest for the extreme normals of boundary points).
         diff = np.abs(pv[:, 0] - o[:, 0])
-        assert diff.max() < 1e-2 * o[:, 0].max()
-        assert diff.mean() < 2e-3 * o[:, 0].mean()
+        assert diff.max() < 2e-3 * o[:, 0].max()
+        assert diff.mean() < 3e-4 * o[:, 0].mean()
     np.testing.assert_allclose(r["price"], pv[:, 0].mean(), rtol=1e-12)
 
 
@@ -83,30 +84,30 @@ def test_qmc_benchmarked_launch_matches_oracle(ctx):
     d, N, n, R = 16, 1 << 16, 1, 16
     say("qmc benchmarked launch", d, N, R)
     model, S0, sigma, corr, L, w = market(d)
-    r = mc.mc_price_qmc(ctx, model, mc.Payoff(mc.MC_BASKET_CALL, 100.0), N, n, SEED, R,
-                        mc.Options(prec=mc.MC_BF16_GEMM))
     h = mc.mc_price_qmc(ctx, model, mc.Payoff(mc.MC_BASKET_CALL, 100.0), N, n, SEED, R,
                         mc.Options(prec=mc.MC_FP16_GEMM))
     ref = mc.mc_price_qmc(ctx, model, mc.Payoff(mc.MC_BASKET_CALL, 100.0), N, n, SEED, R)
     om = np.array([oracle.basket_qmc(S0, sigma, L, w, 0.05, 1.0, 100.0, n, N, SEED, rep,
                                       tag=6)[:, 0].mean() for rep in range(R)])
     g32 = np.array(ref["replicate_price"][:R])
-    g16 = np.array(r["replicate_price"][:R])
     # The reduced-precision errors against FP64, in QMC standard errors: the
     # bench line for this workload runs FP32 products.
     se = ref["std_err"]
     say(f"  oracle {om.mean():.8f}, FP32 {ref['price']:.8f} +- {se:.2e}; max rel FP32 "
-        f"{np.abs(g32 / om - 1).max():.2e}; BF16 {r['price']:.8f} "
-        f"({(r['price'] - om.mean()) / se:+.2f} SE), FP16 {h['price']:.8f} "
+        f"{np.abs(g32 / om - 1).max():.2e}; FP16 {h['price']:.8f} "
         f"({(h['price'] - om.mean()) / se:+.2f} SE)")
     # FP32 products: each replicate within 2e-5 of the oracle, and the
     # estimate within 0.1 standard errors of the oracle's.
     assert np.abs(g32 / om - 1).max() < 2e-5
     assert abs(ref["price"] - om.mean()) < 0.1 * se
-    # FP16 products (L' to 11 bits) stay within 0.1 standard errors; BF16 (8
-    # bits) moves this 16-asset price by about 4 of them, so it is not used
-    # for QMC at this size.
+    # FP16 products (L' to 11 bits) stay within 0.1 standard errors. BF16 (8
+    # bits) moved this 16-asset price by about 4 of them, so the entry point
+    # refuses it.
     assert abs(h["price"] - om.mean()) < 0.1 * se
+    with pytest.raises(mc.McError) as e:
+        mc.mc_price_qmc(ctx, model, mc.Payoff(mc.MC_BASKET_CALL, 100.0), N, n, SEED, R,
+                        mc.Options(prec=mc.MC_BF16_GEMM))
+    assert e.value.status == mc.MC_ERR_UNSUPPORTED
 
 
 def test_qmc_geometric_closed_form_and_rate(ctx):
@@ -140,6 +141,8 @@ def test_qmc_geometric_closed_form_and_rate(ctx):
     (dict(n=4097), mc.MC_ERR_INVALID_ARG),
     (dict(R=2, pv=True), mc.MC_ERR_UNSUPPORTED),
     (dict(prec=mc.MC_BF16X2_GEMM), mc.MC_ERR_UNSUPPORTED),
+    (dict(prec=mc.MC_BF16_GEMM), mc.MC_ERR_UNSUPPORTED),
+    (dict(prec=mc.MC_BF16_GEMM, R=1, pv=True), mc.MC_ERR_UNSUPPORTED),
 ])
 def test_qmc_argument_errors(ctx, kw, status):
     model, *_ = market(16)
