@@ -207,6 +207,33 @@ mc_status mc_price(mc_context *ctx, const mc_model *model, const mc_payoff *payo
                    uint64_t n_paths, uint32_t n_steps, uint64_t seed,
                    const mc_options *opts, mc_result *out);
 
+/* Allocation-free pricing, for callers that cannot allocate device memory
+ * during the call: code under HIP graph capture, tight serving loops and
+ * harnesses that forbid hipMalloc. Same arguments, kernels and results as
+ * mc_price (bit for bit: same grid, same fixed-order reductions), restricted
+ * to what fits a fixed device scratch: models MC_GBM and MC_HESTON, payoffs
+ * without the learned control variate (the geometric-Asian control variate
+ * and its pilot are allowed), greeks only as pathwise tangents (GBM; Heston
+ * with greeks_method = MC_GREEKS_TANGENT), no path_values; opts->workspace
+ * is ignored. The call performs no device or pinned-host allocation and no
+ * free: the block moments and the reduced moments live in a static device
+ * array of MC_NOALLOC_SCRATCH_BYTES, one per GPU, held until the process
+ * ends, whose address the library looks up once per device in mc_create.
+ * The moments come back through a fixed host array of the context.
+ * Every call on one GPU shares that GPU's scratch and leaves its contents
+ * there; each run overwrites all of it that it reads, so nothing needs
+ * clearing. Calls that overlap on one GPU (two host threads, or two
+ * contexts' streams at once) race on the scratch: serialise them.
+ * Errors: those of mc_price; a model, payoff or option outside the list
+ * above -> MC_ERR_UNSUPPORTED; a run whose moments need more than
+ * MC_NOALLOC_SCRATCH_BYTES (Heston without a persistent grid: about 1.9e7
+ * paths for the price, fewer with tangents) -> MC_ERR_WORKSPACE. */
+#define MC_NOALLOC_SCRATCH_BYTES (4u << 20)
+size_t mc_noalloc_scratch_bytes(void);
+mc_status mc_price_noalloc(mc_context *ctx, const mc_model *model, const mc_payoff *payoff,
+                           uint64_t n_paths, uint32_t n_steps, uint64_t seed,
+                           const mc_options *opts, mc_result *out);
+
 /* Prices n_payoffs payoffs on the same simulated paths in one pass.
  * results[i] receives payoff i. GBM only. */
 mc_status mc_price_multi(mc_context *ctx, const mc_model *model,

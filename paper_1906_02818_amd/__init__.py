@@ -294,6 +294,24 @@ def mc_price(ctx: Context, model: Model, payoff: Payoff, n_paths: int, n_steps: 
     return out
 
 
+def mc_noalloc_scratch_bytes() -> int:
+    return _abi.load().mc_noalloc_scratch_bytes()
+
+
+def mc_price_noalloc(ctx: Context, model: Model, payoff: Payoff, n_paths: int, n_steps: int,
+                     seed: int, opts: Options | None = None) -> dict:
+    """mc_price without device allocation: the library's static per-GPU
+    scratch holds the run's moments; no workspace tensor is attached."""
+    mm = _Marshal(model, payoff, opts, n_paths)
+    if mm.opts.path_values:      # passed through so that the library refuses it
+        mm.want_path_values(n_paths, max(1, len(mc_path_channels(model, payoff, opts))))
+    res = _abi.McResult()
+    st = _abi.load().mc_price_noalloc(ctx.handle, C.byref(mm.cm), C.byref(mm.cp), n_paths,
+                                      n_steps, seed, C.byref(mm.co), C.byref(res))
+    _check(ctx, st)
+    return _result(res)
+
+
 def mc_price_multi(ctx: Context, model: Model, payoffs: Sequence[Payoff], n_paths: int,
                    n_steps: int, seed: int, opts: Options | None = None) -> list[dict]:
     mm = _Marshal(model, list(payoffs), opts, n_paths)

@@ -142,6 +142,9 @@ SIGNATURES = {
                                         _P(McOptions)]),
     "mc_price": (C.c_int, [C.c_void_p, _P(McModel), _P(McPayoff), C.c_uint64, C.c_uint32,
                            C.c_uint64, _P(McOptions), _P(McResult)]),
+    "mc_noalloc_scratch_bytes": (C.c_size_t, []),
+    "mc_price_noalloc": (C.c_int, [C.c_void_p, _P(McModel), _P(McPayoff), C.c_uint64, C.c_uint32,
+                                   C.c_uint64, _P(McOptions), _P(McResult)]),
     "mc_price_multi": (C.c_int, [C.c_void_p, _P(McModel), _P(McPayoff), C.c_uint32, C.c_uint64,
                                  C.c_uint32, C.c_uint64, _P(McOptions), _P(McResult)]),
     "mc_path_channels": (C.c_uint32, [_P(McModel), _P(McPayoff), _P(McOptions)]),

@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -45,11 +46,45 @@ struct mc_context {
   hipEvent_t ev2 = nullptr, ev3 = nullptr;
   // Event pairs around each date's update kernel (created on first use).
   std::vector<hipEvent_t> lsm_ev;
+  // Allocation-free calls (mc_price_noalloc): while `noalloc` is set, every
+  // device buffer of the call comes from this device's static scratch array
+  // (address from hipGetSymbolAddress at mc_create) and the reduced moments
+  // come back into host_mom instead of pinned memory.
+  void* scratch = nullptr;
+  bool noalloc = false;
+  double host_mom[256] = {};
 };
+
+// Device scratch of the allocation-free entry point: the block moment
+// partials and the reduced moments of one run (MC_NOALLOC_SCRATCH_BYTES,
+// one copy per GPU, held until the process ends). Host code never passes
+// this name to a kernel or a copy: it uses the per-device address that
+// scratch_address() obtained from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[MC_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
 using namespace mcp;
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Address of `scratch` on `device`, which must be the current device. The
+// lookup runs once per device; later contexts on it reuse the address.
+hipError_t scratch_address(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxScratchDevices) return hipSuccess;   // no scratch there
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
 
 mc_status fail(mc_context* ctx, mc_status st, const char* fmt, ...) {
   if (ctx) {
@@ -241,6 +276,14 @@ mc_status validate_model_payoff(mc_context* ctx, const mc_model* m, const mc_pay
 
 // Device workspace: the caller's, or the context's (grown on demand).
 mc_status get_ws(mc_context* ctx, const mc_options& o, size_t bytes, char** base) {
+  if (ctx->noalloc) {
+    if (bytes > MC_NOALLOC_SCRATCH_BYTES)
+      return fail(ctx, MC_ERR_WORKSPACE,
+                  "mc_price_noalloc: this run needs %zu bytes of device scratch, the static "
+                  "scratch holds %zu", bytes, (size_t)MC_NOALLOC_SCRATCH_BYTES);
+    *base = (char*)ctx->scratch;
+    return MC_OK;
+  }
   if (o.workspace) {
     if (o.workspace_bytes < bytes)
       return fail(ctx, MC_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", o.workspace_bytes,
@@ -298,10 +341,12 @@ RunLayout layout_for(uint64_t n_paths, int C, bool want_path, uint32_t paths_per
 }
 
 // Result of one moment run: n, means and covariances of C channels.
+constexpr int kMaxChannels = 9;
 struct Moments {
   int C = 0;
   double n = 0, nonfinite = 0;
-  std::vector<double> sum, cross;  // cross in upper-triangular row order
+  double sum[kMaxChannels] = {};
+  double cross[kMaxChannels * (kMaxChannels + 1) / 2] = {};  // upper-triangular row order
   double mean(int c) const { return sum[c] / n; }
   double cov(int a, int b) const {
     if (a > b) std::swap(a, b);
@@ -318,12 +363,19 @@ template <typename F>
 mc_status run_moments(mc_context* ctx, const mc_options& o, uint64_t n_paths, int C,
                       double* host_path_values, F&& launch, Moments* out, double* kernel_ms,
                       uint32_t paths_per_block = kBlock) {
+  if (C < 1 || C > kMaxChannels) return fail(ctx, MC_ERR_DEVICE, "channel count %d", C);
   const RunLayout L = layout_for(n_paths, C, host_path_values != nullptr, paths_per_block);
   char* base = nullptr;
   mc_status st = get_ws(ctx, o, L.bytes, &base);
   if (st != MC_OK) return st;
-  st = get_pinned(ctx, L.n_mom);
-  if (st != MC_OK) return st;
+  double* hmom = ctx->host_mom;
+  if (!ctx->noalloc) {
+    st = get_pinned(ctx, L.n_mom);
+    if (st != MC_OK) return st;
+    hmom = ctx->pinned;
+  } else if (host_path_values || ctx->sink) {
+    return fail(ctx, MC_ERR_UNSUPPORTED, "mc_price_noalloc writes no per-path values");
+  }
   hipStream_t s = stream_of(ctx, o);
   double* partials = (double*)base;
   double* mom = (double*)(base + L.off_mom);
@@ -335,7 +387,7 @@ mc_status run_moments(mc_context* ctx, const mc_options& o, uint64_t n_paths, in
   HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));
   if (nb == 0 || nb > L.n_blocks) return fail(ctx, MC_ERR_DEVICE, "block count mismatch");
   HIP_TRY(ctx, launch_final_reduce(partials, nb, L.n_mom, mom, s));
-  HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, mom, L.n_mom * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipMemcpyAsync(hmom, mom, L.n_mom * sizeof(double), hipMemcpyDeviceToHost, s));
   if (host_path_values && !ctx->sink)
     HIP_TRY(ctx, hipMemcpyAsync(host_path_values, path_out, n_paths * C * sizeof(double),
                                 hipMemcpyDeviceToHost, s));
@@ -344,10 +396,10 @@ mc_status run_moments(mc_context* ctx, const mc_options& o, uint64_t n_paths, in
   HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
   if (kernel_ms) *kernel_ms += ms;
   out->C = C;
-  out->n = ctx->pinned[0];
-  out->nonfinite = ctx->pinned[1];
-  out->sum.assign(ctx->pinned + 2, ctx->pinned + 2 + C);
-  out->cross.assign(ctx->pinned + 2 + C, ctx->pinned + L.n_mom);
+  out->n = hmom[0];
+  out->nonfinite = hmom[1];
+  std::copy(hmom + 2, hmom + 2 + C, out->sum);
+  std::copy(hmom + 2 + C, hmom + L.n_mom, out->cross);
   if (out->n < 2) return fail(ctx, MC_ERR_DEVICE, "fewer than two finite paths");
   return MC_OK;
 }
@@ -1337,7 +1389,8 @@ mc_status mc_create(mc_context** out, int device) {
   ctx->device = device;
   if (hipSetDevice(device) != hipSuccess || hipStreamCreate(&ctx->stream) != hipSuccess ||
       hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess ||
-      hipEventCreate(&ctx->ev2) != hipSuccess || hipEventCreate(&ctx->ev3) != hipSuccess) {
+      hipEventCreate(&ctx->ev2) != hipSuccess || hipEventCreate(&ctx->ev3) != hipSuccess ||
+      scratch_address(device, &ctx->scratch) != hipSuccess) {
     mc_destroy(ctx);
     return MC_ERR_DEVICE;
   }
@@ -1487,6 +1540,41 @@ mc_status mc_price(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint6
   r.greeks_method = MC_GREEKS_FD_CRN;
   *out = r;
   return MC_OK;
+}
+
+size_t mc_noalloc_scratch_bytes(void) { return MC_NOALLOC_SCRATCH_BYTES; }
+
+mc_status mc_price_noalloc(mc_context* ctx, const mc_model* m, const mc_payoff* f,
+                           uint64_t n_paths, uint32_t n_steps, uint64_t seed,
+                           const mc_options* opts, mc_result* out) {
+  if (!ctx) return MC_ERR_INVALID_ARG;
+  const mc_options o = opts ? *opts : defaults();
+  mc_status st = validate_all(ctx, m, f, n_paths, n_steps, o);
+  if (st != MC_OK) return st;
+  if (!out) return fail(ctx, MC_ERR_INVALID_ARG, "out must not be NULL");
+  if (m->kind != MC_GBM && m->kind != MC_HESTON)
+    return fail(ctx, MC_ERR_UNSUPPORTED, "mc_price_noalloc prices MC_GBM and MC_HESTON");
+  if (f->cv == MC_CV_LEARNED)
+    return fail(ctx, MC_ERR_UNSUPPORTED, "mc_price_noalloc has no learned control variate");
+  if (o.path_values)
+    return fail(ctx, MC_ERR_UNSUPPORTED, "mc_price_noalloc writes no per-path values");
+  if (o.greeks && o.greeks_method == MC_GREEKS_FD_CRN)
+    return fail(ctx, MC_ERR_UNSUPPORTED, "mc_price_noalloc offers pathwise greeks only");
+  if (m->kind == MC_HESTON && o.greeks && o.greeks_method != MC_GREEKS_TANGENT)
+    return fail(ctx, MC_ERR_UNSUPPORTED,
+                "mc_price_noalloc: Heston greeks need MC_GREEKS_TANGENT (the adjoint keeps "
+                "checkpoints in device memory)");
+  if (!ctx->scratch)
+    return fail(ctx, MC_ERR_UNSUPPORTED, "no static scratch on device %d", ctx->device);
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, MC_ERR_DEVICE, "hipSetDevice");
+  struct NoallocGuard {
+    mc_context* c;
+    ~NoallocGuard() { c->noalloc = false; }
+  } guard{ctx};
+  ctx->noalloc = true;
+  st = mc_price_impl(ctx, m, f, n_paths, n_steps, seed, o, out);
+  if (st == MC_OK && o.greeks) out->greeks_method = (int)o.greeks_method;
+  return st;
 }
 
 mc_status mc_price_multi(mc_context* ctx, const mc_model* m, const mc_payoff* fs, uint32_t nf,
