@@ -261,7 +261,6 @@ def _line(args, metric, value, unit, ms, dtype, config, roofline, higher_is_bett
 TRAFFIC_BYTES = {
     "gbm_path_kernel<float, asian|geo|uo, log-Euler>": 2.984e6,   # 2^24 paths x 252 steps
     "basket_kernel<8, bf16>": 3.395e6,                          # 2^20 paths x 100 steps
-    "heston_adjoint_kernel<float, full, asian>": 9.219e8,       # 2^22 paths x 256 steps
     "lsm_update_kernel<2, 2, 1>": 3.660e8,                      # 2^24 paths, mean of 8 dates
 }
 

@@ -213,9 +213,9 @@ mc_status mc_price(mc_context *ctx, const mc_model *model, const mc_payoff *payo
  * mc_price (bit for bit: same grid, same fixed-order reductions), restricted
  * to what fits a fixed device scratch: models MC_GBM and MC_HESTON, payoffs
  * without the learned control variate (the geometric-Asian control variate
- * and its pilot are allowed), greeks only as pathwise tangents (GBM; Heston
- * with greeks_method = MC_GREEKS_TANGENT), no path_values; opts->workspace
- * is ignored. The call performs no device or pinned-host allocation and no
+ * and its pilot are allowed), pathwise greeks only (GBM tangents; Heston
+ * forward tangents, or the adjoint while its checkpoints fit on chip, i.e.
+ * n_steps <= 256), no path_values; opts->workspace is ignored. The call performs no device or pinned-host allocation and no
  * free: the block moments and the reduced moments live in a static device
  * array of MC_NOALLOC_SCRATCH_BYTES, one per GPU, held until the process
  * ends, whose address the library looks up once per device in mc_create.
@@ -255,16 +255,21 @@ const char *mc_path_channel_name(const mc_model *model, const mc_payoff *payoff,
 /* Pathwise adjoint greeks (Sec. I-A.3, Sec. VI-A.2 basket delta by
  * back-propagation), Heston European or arithmetic-Asian call. The reverse
  * sweep restarts from checkpoints of (ln S, v) saved every `ckpt_every`
- * steps and regenerates the normals from Philox.
+ * steps (even, 2..16) and regenerates the normals from Philox.
  *   MC_ADJ_FULL: forward + reverse in one launch; fills price, delta, vega
- *                (d/dv0) and their standard errors. ckpt may be NULL
- *                (context workspace).
+ *                (d/dv0) and their standard errors. With at most 16
+ *                checkpoints (n_steps <= 16 ckpt_every) they stay in on-chip
+ *                memory (LDS) and ckpt is ignored; above that ckpt is used,
+ *                or the context workspace when ckpt is NULL.
  *   MC_ADJ_FWD:  forward only: price, and writes the checkpoints to ckpt.
  *   MC_ADJ_REV:  reverse only from the checkpoints of a previous FWD call
  *                with identical arguments; fills delta, vega scaled by
  *                grad_out (the upstream derivative of the loss w.r.t. price).
  * ckpt is a device buffer of mc_adjoint_ckpt_bytes() bytes, FP32, laid out
- * [checkpoint][component][path]. */
+ * [checkpoint][component][path], then one row of the terminal statistic.
+ * mc_adjoint_ckpt_bytes returns 0 for a period that is not even in 2..16.
+ * Errors: another period -> MC_ERR_UNSUPPORTED; FWD/REV without ckpt ->
+ * MC_ERR_INVALID_ARG; ckpt_bytes too small -> MC_ERR_WORKSPACE. */
 typedef enum { MC_ADJ_FULL = 0, MC_ADJ_FWD = 1, MC_ADJ_REV = 2 } mc_adjoint_phase;
 size_t mc_adjoint_ckpt_bytes(uint64_t n_paths, uint32_t n_steps, uint32_t ckpt_every);
 mc_status mc_greeks_adjoint(mc_context *ctx, const mc_model *model,

@@ -1487,7 +1487,8 @@ size_t mc_workspace_bytes(const mc_model* m, const mc_payoff* f, uint64_t n_path
   const uint32_t C = mc_path_channels(m, f, &o);
   if (C == 0) return 0;
   size_t bytes = layout_for(n_paths, (int)C, o.path_values != nullptr).bytes;
-  if (m->kind == MC_HESTON && o.greeks && o.greeks_method == MC_GREEKS_PATHWISE)
+  if (m->kind == MC_HESTON && o.greeks && o.greeks_method == MC_GREEKS_PATHWISE &&
+      (n_steps + mcp::kCkpt - 1) / mcp::kCkpt > (uint32_t)mcp::kLdsCkpt)
     bytes = align256(bytes) + align256(mc_adjoint_ckpt_bytes(n_paths, n_steps, mcp::kCkpt));
   if (m->kind == MC_HESTON && f->cv == MC_CV_LEARNED) {
     const uint64_t n_pilot = o.pilot_paths ? o.pilot_paths : (1ull << 16);
@@ -1560,10 +1561,12 @@ mc_status mc_price_noalloc(mc_context* ctx, const mc_model* m, const mc_payoff* 
     return fail(ctx, MC_ERR_UNSUPPORTED, "mc_price_noalloc writes no per-path values");
   if (o.greeks && o.greeks_method == MC_GREEKS_FD_CRN)
     return fail(ctx, MC_ERR_UNSUPPORTED, "mc_price_noalloc offers pathwise greeks only");
-  if (m->kind == MC_HESTON && o.greeks && o.greeks_method != MC_GREEKS_TANGENT)
+  if (m->kind == MC_HESTON && o.greeks && o.greeks_method != MC_GREEKS_TANGENT &&
+      (n_steps + mcp::kCkpt - 1) / mcp::kCkpt > (uint32_t)mcp::kLdsCkpt)
     return fail(ctx, MC_ERR_UNSUPPORTED,
-                "mc_price_noalloc: Heston greeks need MC_GREEKS_TANGENT (the adjoint keeps "
-                "checkpoints in device memory)");
+                "mc_price_noalloc: the Heston adjoint keeps more than %d checkpoints in device "
+                "memory above %d steps; use MC_GREEKS_TANGENT", mcp::kLdsCkpt,
+                mcp::kLdsCkpt * mcp::kCkpt);
   if (!ctx->scratch)
     return fail(ctx, MC_ERR_UNSUPPORTED, "no static scratch on device %d", ctx->device);
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, MC_ERR_DEVICE, "hipSetDevice");
@@ -2013,7 +2016,8 @@ mc_status mc_risk(mc_context* ctx, const mc_model* m, const mc_portfolio* pf, ui
 }
 
 size_t mc_adjoint_ckpt_bytes(uint64_t n_paths, uint32_t n_steps, uint32_t ckpt_every) {
-  if (ckpt_every != (uint32_t)mcp::kCkpt || n_steps == 0) return 0;
+  if (ckpt_every < 2 || ckpt_every > (uint32_t)mcp::kCkptMax || (ckpt_every & 1u) || n_steps == 0)
+    return 0;
   const uint64_t n_ckpt = (n_steps + ckpt_every - 1) / ckpt_every;
   return (size_t)(2 * n_ckpt + 1) * n_paths * sizeof(float);
 }
@@ -2033,8 +2037,8 @@ mc_status mc_greeks_adjoint(mc_context* ctx, const mc_model* m, const mc_payoff*
   if (st != MC_OK) return st;
   if (f->kind != MC_EURO_CALL && f->kind != MC_ASIAN_ARITH_CALL)
     return fail(ctx, MC_ERR_UNSUPPORTED, "adjoint for the European or arithmetic-Asian call");
-  if (ckpt_every != (uint32_t)mcp::kCkpt)
-    return fail(ctx, MC_ERR_UNSUPPORTED, "checkpoint period must be %d", mcp::kCkpt);
+  if (ckpt_every < 2 || ckpt_every > (uint32_t)mcp::kCkptMax || (ckpt_every & 1u))
+    return fail(ctx, MC_ERR_UNSUPPORTED, "checkpoint period must be even, 2..%d", mcp::kCkptMax);
   if (phase != MC_ADJ_FULL && phase != MC_ADJ_FWD && phase != MC_ADJ_REV)
     return fail(ctx, MC_ERR_INVALID_ARG, "unknown phase");
   if (!std::isfinite(grad_out)) return fail(ctx, MC_ERR_INVALID_ARG, "grad_out must be finite");
@@ -2042,8 +2046,12 @@ mc_status mc_greeks_adjoint(mc_context* ctx, const mc_model* m, const mc_payoff*
   const size_t need = mc_adjoint_ckpt_bytes(n_paths, n_steps, ckpt_every);
   const int C = phase == MC_ADJ_FULL ? 3 : phase == MC_ADJ_FWD ? 1 : 2;
   const RunLayout L = layout_for(n_paths, C, o.path_values != nullptr);
-  float* ck = (float*)ckpt;
-  if (ck) {
+  const uint32_t n_ckpt = (n_steps + ckpt_every - 1) / ckpt_every;
+  // A one-launch sweep with few checkpoints keeps them in LDS.
+  const bool lds = phase == MC_ADJ_FULL && n_ckpt <= (uint32_t)mcp::kLdsCkpt;
+  float* ck = lds ? nullptr : (float*)ckpt;
+  if (lds) {
+  } else if (ck) {
     if (ckpt_bytes < need)
       return fail(ctx, MC_ERR_WORKSPACE, "checkpoint buffer has %zu bytes, %zu needed", ckpt_bytes,
                   need);
@@ -2063,7 +2071,8 @@ mc_status mc_greeks_adjoint(mc_context* ctx, const mc_model* m, const mc_payoff*
   a.asian = f->kind == MC_ASIAN_ARITH_CALL;
   a.phase = (int)phase;
   a.ckpt = ck;
-  a.n_ckpt = (n_steps + mcp::kCkpt - 1) / mcp::kCkpt;
+  a.n_ckpt = n_ckpt;
+  a.every = ckpt_every;
   a.grad_out = grad_out;
   Moments mom;
   double kms = 0.0;

@@ -11,10 +11,11 @@
 //    the block moments (Eq. 3).
 //  - heston_adjoint_kernel: pathwise delta and d/dv0 by reverse-mode
 //    differentiation of the simulation (greeks by back-propagation,
-//    Sec. I-A.3). The forward sweep stores (ln S, v) every kCkpt steps; the
-//    reverse sweep takes the segments from last to first, recomputes each
-//    from its checkpoint (regenerating the normals from Philox) with the
-//    kCkpt intermediate states in registers, and back-propagates through it.
+//    Sec. I-A.3). The forward sweep stores (ln S, v) every `every` steps
+//    (LDS when forward and reverse run in one launch, else a device buffer);
+//    the reverse sweep takes the segments from last to first, recomputes
+//    each from its checkpoint (regenerating the normals from Philox) with
+//    its intermediate states in registers, and back-propagates through it.
 #include "device/reduce.h"
 #include "device/rng.h"
 #include "mc_internal.h"
@@ -183,17 +184,33 @@ struct AdjC<1> { static constexpr int C = 1; };   // payoff
 template <>
 struct AdjC<2> { static constexpr int C = 2; };   // delta, d/dv0
 
-// Checkpoint buffer (FP32): rows [2c] = z and [2c+1] = v at step c*kCkpt,
-// then one row with the terminal statistic (A/S0 for the Asian, S_T/S0
-// otherwise). Only the FP32 kernel is built: its state is FP32, so the
-// checkpoints are exact.
-template <typename R, int PHASE, bool ASIAN>
+// Checkpoints (FP32): rows [2c] = z and [2c+1] = v at step c*every, then,
+// in the device buffer, one row with the terminal statistic (A/S0 for the
+// Asian, S_T/S0 otherwise). FULL mode with at most kLdsCkpt checkpoints
+// keeps them in LDS ([row][thread], one thread's column per path, so no
+// barrier is needed); otherwise, and for the FWD/REV split behind autograd,
+// they live in the device buffer ([row][path]). Only the FP32 kernel is
+// built: its state is FP32, so the checkpoints are exact.
+template <typename R, int PHASE, bool ASIAN, bool LDS>
 __global__ __launch_bounds__(kBlock) void heston_adjoint_kernel(const AdjointParams A) {
   constexpr int C = AdjC<PHASE>::C;
+  extern __shared__ float s_ck[];
   const HestonParams& P = A.h;
   const uint64_t pid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   const bool active = pid < P.n_paths;
   const uint64_t np = P.n_paths;
+  auto ck_store = [&](uint32_t row, R x) {
+    if constexpr (LDS)
+      s_ck[row * kBlock + threadIdx.x] = (float)x;
+    else
+      A.ckpt[(size_t)row * np + pid] = (float)x;
+  };
+  auto ck_load = [&](uint32_t row) -> R {
+    if constexpr (LDS)
+      return (R)s_ck[row * kBlock + threadIdx.x];
+    else
+      return (R)A.ckpt[(size_t)row * np + pid];
+  };
   double y[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) y[c] = 0.0;
@@ -201,25 +218,24 @@ __global__ __launch_bounds__(kBlock) void heston_adjoint_kernel(const AdjointPar
     HestonStep<R> hs;
     hs.init(P);
     const PathCounter pc = make_counter(P.path_offset + pid, P.tag, P.k0, P.k1);
-    const uint32_t n = P.n_steps;
+    const uint32_t n = P.n_steps, every = A.every;   // every: even, 2..kCkptMax
     const R S0 = (R)P.S0, K = (R)P.K, disc = (R)P.disc, inv_n = R(1) / (R)n;
     R term;  // A/S0 (Asian) or S_T/S0
     if (PHASE != 2) {
-      // Forward sweep with checkpoints.
+      // Forward sweep, storing (z, v) at the start of every segment.
       R z = R(0), v = (R)P.v0, sumE = R(0), Zs;
-      for (uint32_t j = 0; 2 * j < n; ++j) {
-        const uint32_t i = 2 * j;
-        if (i % kCkpt == 0) {
-          const uint32_t c = i / kCkpt;
-          A.ckpt[(size_t)(2 * c) * np + pid] = (float)z;
-          A.ckpt[(size_t)(2 * c + 1) * np + pid] = (float)v;
-        }
-        const Normals4<R> nz = normals4<R>(philox(j, pc));
-        hs.step(z, v, nz.z[0], nz.z[1], Zs);
-        if (ASIAN) sumE += HDom<R>::exp_(z);
-        if (i + 1 < n) {
-          hs.step(z, v, nz.z[2], nz.z[3], Zs);
+      for (uint32_t i0 = 0, seg = 0; i0 < n; i0 += every, ++seg) {
+        ck_store(2 * seg, z);
+        ck_store(2 * seg + 1, v);
+        const uint32_t len = min(every, n - i0);
+        for (uint32_t q = 0; q < len; q += 2) {
+          const Normals4<R> nz = normals4<R>(philox((i0 + q) >> 1, pc));
+          hs.step(z, v, nz.z[0], nz.z[1], Zs);
           if (ASIAN) sumE += HDom<R>::exp_(z);
+          if (q + 1 < len) {
+            hs.step(z, v, nz.z[2], nz.z[3], Zs);
+            if (ASIAN) sumE += HDom<R>::exp_(z);
+          }
         }
       }
       term = ASIAN ? sumE * inv_n : HDom<R>::exp_(z);
@@ -241,17 +257,17 @@ __global__ __launch_bounds__(kBlock) void heston_adjoint_kernel(const AdjointPar
       double xb = (!ASIAN && itm) ? (double)(disc * S0 * term) : 0.0;
       double vb = 0.0;
       const R dt = hs.dt, half_dt = R(0.5) * hs.dt, kdt = hs.kdt, xi = hs.xi;
-      const uint32_t n_seg = (n + kCkpt - 1) / kCkpt;
+      const uint32_t n_seg = (n + every - 1) / every;
       for (int seg = (int)n_seg - 1; seg >= 0; --seg) {
-        const uint32_t i0 = (uint32_t)seg * kCkpt;
-        const uint32_t len = min((uint32_t)kCkpt, n - i0);
+        const uint32_t i0 = (uint32_t)seg * every;
+        const uint32_t len = min(every, n - i0);
         // The checkpoint holds the FP32 state exactly, so the recomputed
         // segment reproduces the forward sweep bit for bit.
-        R z = (R)A.ckpt[(size_t)(2 * seg) * np + pid];
-        R v = (R)A.ckpt[(size_t)(2 * seg + 1) * np + pid];
-        R vs[kCkpt], z1s[kCkpt], zss[kCkpt], Es[kCkpt];
+        R z = ck_load(2 * seg);
+        R v = ck_load(2 * seg + 1);
+        R vs[kCkptMax], z1s[kCkptMax], zss[kCkptMax], Es[kCkptMax];
 #pragma unroll
-        for (int q = 0; q < kCkpt; q += 2) {
+        for (int q = 0; q < kCkptMax; q += 2) {
           if ((uint32_t)q < len) {
             const Normals4<R> nz = normals4<R>(philox((i0 + (uint32_t)q) >> 1, pc));
             vs[q] = v;
@@ -267,7 +283,7 @@ __global__ __launch_bounds__(kBlock) void heston_adjoint_kernel(const AdjointPar
           }
         }
 #pragma unroll
-        for (int q = kCkpt - 1; q >= 0; --q) {
+        for (int q = kCkptMax - 1; q >= 0; --q) {
           if ((uint32_t)q < len) {
             if (ASIAN) xb += abar * (double)Es[q];   // S_{i+1} enters the average
             const R vq = vs[q];
@@ -329,20 +345,32 @@ hipError_t launch_heston_tangent(const HestonParams& p, bool asian, bool fp64, h
   return hipGetLastError();
 }
 
-template <typename R, int PH, bool AS>
+template <typename R, int PH, bool AS, bool LDS>
 static hipError_t adj_one(const AdjointParams& a, hipStream_t s, uint32_t nb) {
-  hipLaunchKernelGGL((heston_adjoint_kernel<R, PH, AS>), dim3(nb), dim3(kBlock), 0, s, a);
+  const size_t lds = LDS ? (size_t)2 * a.n_ckpt * kBlock * sizeof(float) : 0;
+  hipLaunchKernelGGL((heston_adjoint_kernel<R, PH, AS, LDS>), dim3(nb), dim3(kBlock), lds, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_heston_adjoint(const AdjointParams& a, hipStream_t s, uint32_t* n_blocks) {
   const uint32_t nb = (uint32_t)((a.h.n_paths + kBlock - 1) / kBlock);
   *n_blocks = nb;
+  if (a.every < 2 || a.every > (uint32_t)kCkptMax || (a.every & 1u) ||
+      a.n_ckpt != (a.h.n_steps + a.every - 1) / a.every)
+    return hipErrorInvalidValue;
   const bool as = a.asian != 0;
+  const bool lds = a.phase == 0 && a.ckpt == nullptr;
+  if (lds && a.n_ckpt > (uint32_t)kLdsCkpt) return hipErrorInvalidValue;
+  if (!lds && a.ckpt == nullptr) return hipErrorInvalidValue;
   switch (a.phase) {
-    case 0: return as ? adj_one<float, 0, true>(a, s, nb) : adj_one<float, 0, false>(a, s, nb);
-    case 1: return as ? adj_one<float, 1, true>(a, s, nb) : adj_one<float, 1, false>(a, s, nb);
-    case 2: return as ? adj_one<float, 2, true>(a, s, nb) : adj_one<float, 2, false>(a, s, nb);
+    case 0:
+      if (lds)
+        return as ? adj_one<float, 0, true, true>(a, s, nb) : adj_one<float, 0, false, true>(a, s, nb);
+      return as ? adj_one<float, 0, true, false>(a, s, nb) : adj_one<float, 0, false, false>(a, s, nb);
+    case 1:
+      return as ? adj_one<float, 1, true, false>(a, s, nb) : adj_one<float, 1, false, false>(a, s, nb);
+    case 2:
+      return as ? adj_one<float, 2, true, false>(a, s, nb) : adj_one<float, 2, false, false>(a, s, nb);
   }
   return hipErrorInvalidValue;
 }

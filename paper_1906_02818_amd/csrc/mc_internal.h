@@ -85,14 +85,21 @@ hipError_t launch_heston(const HestonParams& p, uint32_t mask, bool fp64, hipStr
 hipError_t launch_heston_tangent(const HestonParams& p, bool asian, bool fp64, hipStream_t s,
                                  uint32_t* n_blocks);
 
-// Pathwise adjoint (reverse sweep with checkpoints every kCkpt steps).
+// Pathwise adjoint (reverse sweep with checkpoints every `every` steps:
+// even, 2..kCkptMax; kCkpt by default). A full (one-launch) sweep with at
+// most kLdsCkpt checkpoints keeps them in LDS (2 kLdsCkpt floats per path,
+// 32 KB per 256-path block) and needs no device buffer.
 constexpr int kCkpt = 16;
+constexpr int kCkptMax = 16;
+constexpr int kLdsCkpt = 16;
 struct AdjointParams {
   HestonParams h;
   int asian;            // 1: arithmetic-Asian call, 0: European call
   int phase;            // 0 full, 1 forward (write checkpoints), 2 reverse
-  float* ckpt;          // [2*n_ckpt + 1][n_paths]: (z, v) per checkpoint, then terminal
+  float* ckpt;          // [2*n_ckpt + 1][n_paths]: (z, v) per checkpoint, then terminal;
+                        // nullptr for a full sweep with checkpoints in LDS
   uint32_t n_ckpt;
+  uint32_t every;       // checkpoint period
   double grad_out;
 };
 hipError_t launch_heston_adjoint(const AdjointParams& p, hipStream_t s, uint32_t* n_blocks);

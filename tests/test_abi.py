@@ -219,10 +219,20 @@ def test_channel_names_and_sizes():
     assert names[4] == "uo_bridge" and len(names) == 9
     assert mc.mc_path_channels(HES, mc.Payoff(mc.MC_ASIAN_ARITH_CALL, 100.0),
                                mc.Options(greeks=3)) == ["asian", "asian_delta", "asian_dv0"]
-    # Checkpoints: 16 per 256 steps, (2 per checkpoint + 1) FP32 rows per path.
+    # Checkpoints: one per `every` steps, (2 per checkpoint + 1) FP32 rows per
+    # path; the period is even, 2..16.
     assert mc.mc_adjoint_ckpt_bytes(1000, 256, 16) == (2 * 16 + 1) * 1000 * 4
     assert mc.mc_adjoint_ckpt_bytes(1000, 250, 16) == (2 * 16 + 1) * 1000 * 4
-    assert mc.mc_adjoint_ckpt_bytes(1000, 256, 8) == 0
+    assert mc.mc_adjoint_ckpt_bytes(1000, 256, 8) == (2 * 32 + 1) * 1000 * 4
+    assert mc.mc_adjoint_ckpt_bytes(1000, 7, 2) == (2 * 4 + 1) * 1000 * 4
+    for bad in (0, 1, 3, 18, 32):
+        assert mc.mc_adjoint_ckpt_bytes(1000, 256, bad) == 0
+    # The one-launch adjoint keeps up to 16 checkpoints in LDS: no workspace
+    # for them at 256 steps; above that the buffer is part of the workspace.
+    hp = mc.Payoff(mc.MC_ASIAN_ARITH_CALL, 100.0)
+    assert mc.mc_workspace_bytes(HES, hp, 1 << 20, 256, mc.Options(greeks=3)) < (1 << 20)
+    assert mc.mc_workspace_bytes(HES, hp, 1 << 20, 512, mc.Options(greeks=3)) > \
+        mc.mc_adjoint_ckpt_bytes(1 << 20, 512, 16)
     ws = mc.mc_workspace_bytes(GBM, mc.Payoff(mc.MC_EURO_CALL, 100.0), 1 << 20, 64)
     assert ws >= (1 << 20) // 256 * 4 * 8     # 4 moments per block for one channel
 

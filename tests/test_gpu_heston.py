@@ -193,6 +193,38 @@ def test_fwd_rev_split_equals_full_and_autograd(ctx):
                              ckpt_ptr=ck.data_ptr(), ckpt_bytes=nbytes - 4)
 
 
+@pytest.mark.parametrize("n", [256, 250, 7])
+def test_adjoint_checkpoint_period_and_placement(ctx, n):
+    # The reverse sweep visits the steps in the same order whatever the
+    # checkpoint period, and the checkpoints hold the FP32 state exactly, so
+    # the greeks are bit for bit those of the default period (16, one-launch
+    # sweep with the checkpoints in LDS): for periods 2, 4, 8 (checkpoints in
+    # LDS when they number at most 16, else in the context workspace) and for
+    # the FWD/REV split through a device buffer.
+    import torch
+    N = 3000
+    f = mc.Payoff(mc.MC_ASIAN_ARITH_CALL, H["K"])
+    ref = mc.mc_greeks_adjoint(ctx, model(), f, N, n, SEED, mc.Options(path_values=True))
+    for every in (2, 4, 8, 16):
+        full = mc.mc_greeks_adjoint(ctx, model(), f, N, n, SEED, mc.Options(path_values=True),
+                                    ckpt_every=every)
+        say(f"  n {n} every {every}: {len(range(0, n, every))} checkpoints")
+        assert np.array_equal(full["path_values"], ref["path_values"]), every
+        nbytes = mc.mc_adjoint_ckpt_bytes(N, n, every)
+        ck = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+        fwd = mc.mc_greeks_adjoint(ctx, model(), f, N, n, SEED, phase=mc.MC_ADJ_FWD,
+                                   ckpt_every=every, ckpt_ptr=ck.data_ptr(), ckpt_bytes=nbytes)
+        rev = mc.mc_greeks_adjoint(ctx, model(), f, N, n, SEED, mc.Options(path_values=True),
+                                   phase=mc.MC_ADJ_REV, ckpt_every=every, ckpt_ptr=ck.data_ptr(),
+                                   ckpt_bytes=nbytes)
+        assert fwd["price"] == ref["price"]
+        assert np.array_equal(rev["path_values"], ref["path_values"][:, 1:]), every
+    for bad in (3, 18):
+        with pytest.raises(mc.McError) as e:
+            mc.mc_greeks_adjoint(ctx, model(), f, N, n, SEED, ckpt_every=bad)
+        assert e.value.status == mc.MC_ERR_UNSUPPORTED
+
+
 def test_adjoint_against_common_random_number_fd(ctx):
     # Central differences h = 1e-3 relative on common random numbers (same
     # seed and tags), path by path, against the adjoint.

@@ -58,6 +58,10 @@ CASES = [
     # Heston Asian with forward-mode delta and d/dv0, FP32.
     ("heston tangents fp32", heston, mc.Payoff(mc.MC_ASIAN_ARITH_CALL, 100.0),
      mc.Options(greeks=3, greeks_method=mc.MC_GREEKS_TANGENT), (1 << 20, 256), (5000, 64)),
+    # Heston Asian with adjoint delta and d/dv0 (one-launch sweep, checkpoints
+    # in LDS), FP32.
+    ("heston adjoint fp32", heston, mc.Payoff(mc.MC_ASIAN_ARITH_CALL, 100.0),
+     mc.Options(greeks=3), (1 << 20, 256), (3001, 250)),
     # Heston price, FP32.
     ("heston price fp32", heston, mc.Payoff(mc.MC_EURO_CALL, 100.0), mc.Options(),
      (1 << 22, 256), (777, 17)),
@@ -94,15 +98,15 @@ def test_noalloc_scratch_size_and_errors(ctx):
                             mc.Options(greeks=3, greeks_method=mc.MC_GREEKS_TANGENT))
     assert e.value.status == mc.MC_ERR_WORKSPACE
     bad = [
-        (heston(), f, mc.Options(greeks=3)),                       # adjoint checkpoints
-        (heston(), f, mc.Options(path_values=True)),
-        (gbm(), f, mc.Options(greeks=3, greeks_method=mc.MC_GREEKS_FD_CRN)),
+        (heston(), f, mc.Options(greeks=3), 300),          # 19 adjoint checkpoints
+        (heston(), f, mc.Options(path_values=True), 16),
+        (gbm(), f, mc.Options(greeks=3, greeks_method=mc.MC_GREEKS_FD_CRN), 16),
         (heston(), mc.Payoff(mc.MC_ASIAN_ARITH_CALL, 100.0, cv=mc.MC_CV_LEARNED),
-         mc.Options(cv_weights=synth.glorot_mlp())),
+         mc.Options(cv_weights=synth.glorot_mlp()), 16),
     ]
-    for model, payoff, o in bad:
+    for model, payoff, o, n_steps in bad:
         with pytest.raises(mc.McError) as e:
-            mc.mc_price_noalloc(ctx, model, payoff, 4096, 16, SEED, o)
+            mc.mc_price_noalloc(ctx, model, payoff, 4096, n_steps, SEED, o)
         assert e.value.status == mc.MC_ERR_UNSUPPORTED
     d = 16
     sigma, corr, _ = synth.basket_market(d)
