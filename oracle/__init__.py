@@ -56,6 +56,7 @@ def lib():
                                      _u64p, _u32p]
         L.orc_gbm.argtypes = [_dp, C.c_int, C.c_int, C.c_int, C.c_uint64,
                               C.c_uint32, C.c_uint64, C.c_uint64, _dp]
+        L.orc_gbm_payoffs.argtypes = L.orc_gbm.argtypes
         L.orc_heston.argtypes = [_dp, C.c_int, C.c_uint64, C.c_uint32, C.c_uint64,
                                  C.c_uint64, _dp]
         L.orc_cholesky.argtypes = [C.c_int, _dp, _dp]
@@ -153,10 +154,13 @@ def normals(seed: int, tag: int, path: int, k0: int, count: int) -> np.ndarray:
 # Path simulators: per-path channel rows.
 # --------------------------------------------------------------------------
 def gbm(S0, r, sigma, T, K, B, n_steps, n_paths, seed, tag=0, path0=0,
-        scheme=0, coarsen=1) -> np.ndarray:
+        scheme=0, coarsen=1, payoffs_only=False) -> np.ndarray:
+    """Per-path GBM channels; payoffs_only computes channels 0-3 and 8 only
+    (the others NaN): no tangents, Brownian-bridge stream or margins."""
     prm = np.array([S0, r, sigma, T, K, B], np.float64)
     out = np.zeros((n_paths, len(GBM_CHANNELS)), np.float64)
-    lib().orc_gbm(prm, n_steps, scheme, coarsen, seed, tag, path0, n_paths, out)
+    fn = lib().orc_gbm_payoffs if payoffs_only else lib().orc_gbm
+    fn(prm, n_steps, scheme, coarsen, seed, tag, path0, n_paths, out)
     return out
 
 

@@ -209,8 +209,11 @@ static double pos(double x) { return x > 0.0 ? x : 0.0; }
 /* ------------------------------------------------------------------------ */
 #define GBM_CH 12
 
+/* extras = 0 computes the payoff channels 0-3 and 8 only (the others are
+   NaN): no tangents, no Brownian-bridge stream, no margins. */
 static void gbm_one_path(const double *prm, int n, int scheme, int coarsen,
-                         uint64_t seed, uint32_t tag, uint64_t path, double *o)
+                         uint64_t seed, uint32_t tag, uint64_t path, int extras,
+                         double *o)
 {
     const double S0 = prm[0], r = prm[1], sig = prm[2], T = prm[3];
     const double K = prm[4], B = prm[5];
@@ -235,10 +238,12 @@ static void gbm_one_path(const double *prm, int n, int scheme, int coarsen,
         double x_prev = x;
         if (scheme == 0) {
             x = x + (r - 0.5 * sig * sig) * dt + sig * sdt * Z;
-            dx_dsig = dx_dsig - sig * dt + sdt * Z;
             S = exp(x);
-            dS_dS0 = S / S0;
-            dS_dsig = S * dx_dsig;
+            if (extras) {
+                dx_dsig = dx_dsig - sig * dt + sdt * Z;
+                dS_dS0 = S / S0;
+                dS_dsig = S * dx_dsig;
+            }
         } else {
             double f = 1.0 + r * dt + sig * sdt * Z;
             dS_dsig = dS_dsig * f + S * sdt * Z;
@@ -248,9 +253,10 @@ static void gbm_one_path(const double *prm, int n, int scheme, int coarsen,
         }
         sumS += S;
         sum_lnS += log(S);
+        if (!(S < B)) alive = 0;
+        if (!extras) continue;
         sum_dS_dS0 += dS_dS0;
         sum_dS_dsig += dS_dsig;
-        if (!(S < B)) alive = 0;
         if (log(S) - lnB > margin) margin = log(S) - lnB;
         if (scheme == 0) {
             uint32_t w[4];
@@ -269,11 +275,15 @@ static void gbm_one_path(const double *prm, int n, int scheme, int coarsen,
     o[1] = disc * pos(A - K);
     o[2] = disc * pos(G - K);
     o[3] = alive ? disc * call : 0.0;
+    o[8] = disc * S;
+    if (!extras) {
+        o[4] = o[5] = o[6] = o[7] = o[9] = o[10] = o[11] = NAN;
+        return;
+    }
     o[4] = S > K ? disc * dS_dS0 : 0.0;
     o[5] = S > K ? disc * dS_dsig : 0.0;
     o[6] = A > K ? disc * sum_dS_dS0 / n : 0.0;
     o[7] = A > K ? disc * sum_dS_dsig / n : 0.0;
-    o[8] = disc * S;
     o[9] = (scheme == 0 && alive_bb) ? disc * call : 0.0;
     o[10] = margin;
     o[11] = margin_bb;
@@ -281,7 +291,7 @@ static void gbm_one_path(const double *prm, int n, int scheme, int coarsen,
 
 int orc_gbm_channels(void) { return GBM_CH; }
 
-/* prm = {S0, r, sigma, T, K, B} */
+/* prm = {S0, r, sigma, T, K, B}; every channel. */
 void orc_gbm(const double *prm, int n_steps, int scheme, int coarsen,
              uint64_t seed, uint32_t tag, uint64_t path0, uint64_t n_paths,
              double *out)
@@ -289,7 +299,18 @@ void orc_gbm(const double *prm, int n_steps, int scheme, int coarsen,
 #pragma omp parallel for schedule(static)
     for (long long p = 0; p < (long long)n_paths; ++p)
         gbm_one_path(prm, n_steps, scheme, coarsen, seed, tag,
-                     path0 + (uint64_t)p, out + (uint64_t)p * GBM_CH);
+                     path0 + (uint64_t)p, 1, out + (uint64_t)p * GBM_CH);
+}
+
+/* The same paths with the payoff channels only (0-3 and 8; the rest NaN). */
+void orc_gbm_payoffs(const double *prm, int n_steps, int scheme, int coarsen,
+                     uint64_t seed, uint32_t tag, uint64_t path0,
+                     uint64_t n_paths, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (long long p = 0; p < (long long)n_paths; ++p)
+        gbm_one_path(prm, n_steps, scheme, coarsen, seed, tag,
+                     path0 + (uint64_t)p, 0, out + (uint64_t)p * GBM_CH);
 }
 
 /* ------------------------------------------------------------------------ */

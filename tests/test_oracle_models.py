@@ -404,3 +404,16 @@ def test_heston_without_vol_of_vol_is_black_scholes():
     assert within(e, bs_call(S0, K, r, math.sqrt(th), T), 4.0)
     d = oracle.estimate(o[:, 2])
     assert within(d, bs_delta(S0, K, r, math.sqrt(th), T), 4.0)
+
+
+def test_gbm_payoff_only_mode_equals_all_channels():
+    # The oracle's payoff-only GBM mode (used to time the CPU baseline on the
+    # channels the benchmarked step computes) gives the same payoff channels
+    # bit for bit and leaves the rest undefined.
+    for scheme in (0, 1):
+        a = oracle.gbm(100.0, 0.03, 0.25, 1.0, 100.0, 130.0, 37, 513, 5, scheme=scheme)
+        b = oracle.gbm(100.0, 0.03, 0.25, 1.0, 100.0, 130.0, 37, 513, 5, scheme=scheme,
+                       payoffs_only=True)
+        cols = [0, 1, 2, 3, 8]
+        assert np.array_equal(a[:, cols], b[:, cols])
+        assert np.isnan(b[:, [4, 5, 6, 7, 9, 10, 11]]).all()
