@@ -329,9 +329,13 @@ struct RunLayout {
   size_t off_mom, off_path, bytes;
 };
 
-RunLayout layout_for(uint64_t n_paths, int C, bool want_path, uint32_t paths_per_block = kBlock) {
+// max_blocks: the grid cap of a persistent kernel (its partials are one
+// vector per workgroup).
+RunLayout layout_for(uint64_t n_paths, int C, bool want_path, uint32_t paths_per_block = kBlock,
+                     uint32_t max_blocks = UINT32_MAX) {
   RunLayout L;
-  L.n_blocks = (uint32_t)((n_paths + paths_per_block - 1) / paths_per_block);
+  const uint64_t need = (n_paths + paths_per_block - 1) / paths_per_block;
+  L.n_blocks = (uint32_t)(need < max_blocks ? need : max_blocks);
   L.C = (uint32_t)C;
   L.n_mom = (uint32_t)n_moments(C);
   L.off_mom = align256((size_t)L.n_mom * L.n_blocks * sizeof(double));
@@ -340,31 +344,50 @@ RunLayout layout_for(uint64_t n_paths, int C, bool want_path, uint32_t paths_per
   return L;
 }
 
-// Result of one moment run: n, means and covariances of C channels.
-constexpr int kMaxChannels = 9;
+// Result of one moment run: n, means and covariances of C channels, from
+// the merged (count, means, co-moments) vector the kernels produce.
+constexpr int kMaxChannels = kMaxMomentChannels;
 struct Moments {
   int C = 0;
   double n = 0, nonfinite = 0;
-  double sum[kMaxChannels] = {};
-  double cross[kMaxChannels * (kMaxChannels + 1) / 2] = {};  // upper-triangular row order
-  double mean(int c) const { return sum[c] / n; }
+  double means[kMaxChannels] = {};
+  double co[kMaxChannels * (kMaxChannels + 1) / 2] = {};  // upper-triangular row order
+  double mean(int c) const { return means[c]; }
   double cov(int a, int b) const {
     if (a > b) std::swap(a, b);
     int idx = 0;
     for (int i = 0; i < a; ++i) idx += C - i;
     idx += b - a;
-    return (cross[idx] - sum[a] * sum[b] / n) / (n - 1.0);
+    return co[idx] / (n - 1.0);
   }
 };
+
+// Host form of the kernels' pairwise (Chan) merge of two moment vectors of
+// C channels: acc <- acc merged with b. Used to combine chunks.
+void merge_moment_vec(double* acc, const double* b, int C) {
+  const double nA = acc[0], nB = b[0], nt = nA + nB;
+  const double f = nt > 0.0 ? nB / nt : 0.0, g = nA * f;
+  acc[1] += b[1];
+  double d[kMaxChannels];
+  for (int a = 0; a < C; ++a) {
+    d[a] = b[2 + a] - acc[2 + a];
+    acc[2 + a] += d[a] * f;
+  }
+  int k = 2 + C;
+  for (int a = 0; a < C; ++a)
+    for (int c = a; c < C; ++c, ++k) acc[k] += b[k] + d[a] * d[c] * g;
+  acc[0] = nt;
+}
 
 // Launch wrapper: runs `launch` (which enqueues the path kernel), then the
 // final reduction, and brings the moments to the host.
 template <typename F>
 mc_status run_moments(mc_context* ctx, const mc_options& o, uint64_t n_paths, int C,
                       double* host_path_values, F&& launch, Moments* out, double* kernel_ms,
-                      uint32_t paths_per_block = kBlock) {
+                      uint32_t paths_per_block = kBlock, uint32_t max_blocks = UINT32_MAX) {
   if (C < 1 || C > kMaxChannels) return fail(ctx, MC_ERR_DEVICE, "channel count %d", C);
-  const RunLayout L = layout_for(n_paths, C, host_path_values != nullptr, paths_per_block);
+  const RunLayout L =
+      layout_for(n_paths, C, host_path_values != nullptr, paths_per_block, max_blocks);
   char* base = nullptr;
   mc_status st = get_ws(ctx, o, L.bytes, &base);
   if (st != MC_OK) return st;
@@ -386,7 +409,7 @@ mc_status run_moments(mc_context* ctx, const mc_options& o, uint64_t n_paths, in
   HIP_TRY(ctx, launch(partials, path_out, s, &nb));
   HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));
   if (nb == 0 || nb > L.n_blocks) return fail(ctx, MC_ERR_DEVICE, "block count mismatch");
-  HIP_TRY(ctx, launch_final_reduce(partials, nb, L.n_mom, mom, s));
+  HIP_TRY(ctx, launch_final_merge(partials, nb, (uint32_t)C, 1, mom, s));
   HIP_TRY(ctx, hipMemcpyAsync(hmom, mom, L.n_mom * sizeof(double), hipMemcpyDeviceToHost, s));
   if (host_path_values && !ctx->sink)
     HIP_TRY(ctx, hipMemcpyAsync(host_path_values, path_out, n_paths * C * sizeof(double),
@@ -398,8 +421,8 @@ mc_status run_moments(mc_context* ctx, const mc_options& o, uint64_t n_paths, in
   out->C = C;
   out->n = hmom[0];
   out->nonfinite = hmom[1];
-  std::copy(hmom + 2, hmom + 2 + C, out->sum);
-  std::copy(hmom + 2 + C, hmom + L.n_mom, out->cross);
+  std::copy(hmom + 2, hmom + 2 + C, out->means);
+  std::copy(hmom + 2 + C, hmom + L.n_mom, out->co);
   if (out->n < 2) return fail(ctx, MC_ERR_DEVICE, "fewer than two finite paths");
   return MC_OK;
 }
@@ -509,7 +532,7 @@ mc_status gbm_run(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint64
                        p.path_out = path_out;
                        return launch_gbm(p, mask, fp64, s, nb);
                      },
-                     mom, kernel_ms);
+                     mom, kernel_ms, kBlock, kGbmMaxBlocks);
 }
 
 // Fills `out` for one GBM payoff from the moments of a run.
@@ -622,7 +645,7 @@ mc_status heston_price(mc_context* ctx, const mc_model* m, const mc_payoff* f, u
                                  p.path_out = path_out;
                                  return launch_heston_tangent(p, asian, fp64, s, nb);
                                },
-                               &mom, &kms);
+                               &mom, &kms, kBlock, kHestonMaxBlocks);
     if (st != MC_OK) return st;
     mc_result r{};
     double v;
@@ -651,7 +674,7 @@ mc_status heston_price(mc_context* ctx, const mc_model* m, const mc_payoff* f, u
                                p.path_out = path_out;
                                return launch_heston(p, H_EURO | H_ASIAN, fp64, s, nb);
                              },
-                             &mom, &kms);
+                             &mom, &kms, kBlock, kHestonMaxBlocks);
   if (st != MC_OK) return st;
   mc_result r{};
   const int c = f->kind == MC_EURO_CALL ? 0 : 1;
@@ -748,7 +771,7 @@ mc_status cv_eval(mc_context* ctx, const mc_options& o, const CvParams& base, ui
                        p.path_out = path_out;
                        return launch_cv_price(p, s, nb);
                      },
-                     mom, kms, kCvPathsPerBlock);
+                     mom, kms, kCvPathsPerBlock, kCvEvalMaxBlocks);
 }
 
 mc_status heston_cv_price(mc_context* ctx, const mc_model* m, const mc_payoff* f,
@@ -761,7 +784,8 @@ mc_status heston_cv_price(mc_context* ctx, const mc_model* m, const mc_payoff* f
     if (!std::isfinite(o0.cv_weights[i])) return fail(ctx, MC_ERR_INVALID_ARG, "cv_weights not finite");
   const uint64_t n_pilot = o0.pilot_paths ? o0.pilot_paths : (1ull << 16);
   const uint64_t n_big = n_paths > n_pilot ? n_paths : n_pilot;
-  const RunLayout Lay = layout_for(n_big, 3, o0.path_values != nullptr, kCvPathsPerBlock);
+  const RunLayout Lay =
+      layout_for(n_big, 3, o0.path_values != nullptr, kCvPathsPerBlock, kCvEvalMaxBlocks);
   const size_t off = align256(Lay.bytes);
   char* base = nullptr;
   st = get_ws(ctx, o0, off + cv_extra_bytes(n_steps), &base);
@@ -929,7 +953,7 @@ mc_status cv_loss_grad_device(mc_context* ctx, hipStream_t s, const mc_model* m,
   uint32_t nb = 0;
   HIP_TRY(ctx, launch_cv_forward(p, s));
   HIP_TRY(ctx, launch_cv_values(p, s, &nb));
-  HIP_TRY(ctx, launch_final_reduce(partials, nb, Lay.n_mom, mom, s));
+  HIP_TRY(ctx, launch_final_merge(partials, nb, 3, 1, mom, s));
   p.path_out = nullptr;
   p.ybar_mom = mom;
   p.y_path = ypath;
@@ -946,9 +970,9 @@ mc_status cv_loss_grad_device(mc_context* ctx, hipStream_t s, const mc_model* m,
 }
 
 double loss_from_moments(const double* mom) {
-  // Channel 2 (Y) of a 3-channel layout: n = mom[0], sum = mom[4], sum sq = mom[10].
-  const double n = mom[0], s1 = mom[4], s2 = mom[10];
-  return (s2 - s1 * s1 / n) / n;
+  // Channel 2 (Y) of a 3-channel moment vector: n = mom[0], co-moment
+  // sum (Y - Ybar)^2 = mom[10]; the loss is the batch variance (1/B).
+  return mom[10] / mom[0];
 }
 
 // ------------------------------------------------------------- Basket ----
@@ -1324,16 +1348,16 @@ mc_status fd_greek(mc_context* ctx, const mc_model* m, const mc_payoff* f, uint6
     }
     uint32_t nb = 0;
     HIP_TRY(ctx, launch_diff_moments(A, C, ch, B, C, ch, nc, partials, s, &nb));
-    HIP_TRY(ctx, launch_final_reduce(partials, nb, M, mom, s));
+    HIP_TRY(ctx, launch_final_merge(partials, nb, 3, 1, mom, s));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, mom, M * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
-    for (uint32_t i = 0; i < M; ++i) acc[i] += ctx->pinned[i];
+    merge_moment_vec(acc, ctx->pinned, 3);
   }
-  // acc: [n, nonfinite, sum d, sum a, sum b, dd, ...]
+  // acc: [n, nonfinite, mean d, mean a, mean b, M_dd, ...]
   const double n = acc[0];
   if (n < 2) return fail(ctx, MC_ERR_DEVICE, "fewer than two finite paths in a bumped run");
-  const double var = std::max(acc[5] - acc[2] * acc[2] / n, 0.0) / (n - 1.0);
-  *g = acc[2] / n / (2.0 * h * theta);
+  const double var = acc[5] / (n - 1.0);
+  *g = acc[2] / (2.0 * h * theta);
   *se = std::sqrt(var / n) / (2.0 * h * theta);
   return MC_OK;
 }
@@ -1486,14 +1510,18 @@ size_t mc_workspace_bytes(const mc_model* m, const mc_payoff* f, uint64_t n_path
   const mc_options o = opts ? *opts : defaults();
   const uint32_t C = mc_path_channels(m, f, &o);
   if (C == 0) return 0;
-  size_t bytes = layout_for(n_paths, (int)C, o.path_values != nullptr).bytes;
+  const uint32_t cap = m->kind == MC_GBM ? kGbmMaxBlocks
+                      : m->kind == MC_HESTON && f->cv != MC_CV_LEARNED ? kHestonMaxBlocks
+                                                                       : UINT32_MAX;
+  size_t bytes = layout_for(n_paths, (int)C, o.path_values != nullptr, kBlock, cap).bytes;
   if (m->kind == MC_HESTON && o.greeks && o.greeks_method == MC_GREEKS_PATHWISE &&
       (n_steps + mcp::kCkpt - 1) / mcp::kCkpt > (uint32_t)mcp::kLdsCkpt)
     bytes = align256(bytes) + align256(mc_adjoint_ckpt_bytes(n_paths, n_steps, mcp::kCkpt));
   if (m->kind == MC_HESTON && f->cv == MC_CV_LEARNED) {
     const uint64_t n_pilot = o.pilot_paths ? o.pilot_paths : (1ull << 16);
     const uint64_t n_big = n_paths > n_pilot ? n_paths : n_pilot;
-    bytes = align256(layout_for(n_big, 3, o.path_values != nullptr, kCvPathsPerBlock).bytes) +
+    bytes = align256(layout_for(n_big, 3, o.path_values != nullptr, kCvPathsPerBlock,
+                                kCvEvalMaxBlocks).bytes) +
             cv_extra_bytes(n_steps);
   }
   if (m->kind == MC_GBM_BASKET) bytes = basket_ws_bytes(bytes, m->dim, o.prec);
@@ -1738,22 +1766,22 @@ mc_status mc_price_mlmc(mc_context* ctx, const mc_model* m, const mc_payoff* f, 
       uint32_t nb = 0;
       HIP_TRY(ctx, hipEventRecord(ctx->ev0, s));
       HIP_TRY(ctx, launch_diff_moments(A, Ca, ca, B, Cb, cb, nc, partials, s, &nb));
-      HIP_TRY(ctx, launch_final_reduce(partials, nb, M, mom, s));
+      HIP_TRY(ctx, launch_final_merge(partials, nb, 3, 1, mom, s));
       HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));
       HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, mom, M * sizeof(double), hipMemcpyDeviceToHost, s));
       HIP_TRY(ctx, hipStreamSynchronize(s));
       float ms = 0.f;
       HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
       kms += ms;
-      for (uint32_t i = 0; i < M; ++i) acc[i] += ctx->pinned[i];
+      merge_moment_vec(acc, ctx->pinned, 3);
     }
-    // acc: [n, nonfinite, sum d, sum a, sum b, dd, da, db, aa, ab, bb]
+    // acc: [n, nonfinite, mean d, mean a, mean b, M_dd, M_da, M_db, M_aa, M_ab, M_bb]
     const double n = acc[0];
     if (n < 2) return fail(ctx, MC_ERR_DEVICE, "level %u: fewer than two finite paths", l);
-    r.mean[l] = acc[2] / n;
-    r.variance[l] = (acc[5] - acc[2] * acc[2] / n) / (n - 1.0);
-    r.fine_mean[l] = acc[3] / n;
-    r.coarse_mean[l] = acc[4] / n;
+    r.mean[l] = acc[2];
+    r.variance[l] = acc[5] / (n - 1.0);
+    r.fine_mean[l] = acc[3];
+    r.coarse_mean[l] = acc[4];
     r.n_paths[l] = (uint64_t)n;
     r.kernel_ms[l] = kms;
     var_over_n += r.variance[l] / n;
@@ -1880,7 +1908,7 @@ mc_status mc_price_qmc(mc_context* ctx, const mc_model* m, const mc_payoff* f, u
     uint32_t nb = 0;
     HIP_TRY(ctx, launch_basket_qmc_batch(p, prec, n_replicates, s, &nb));
     if (nb == 0 || nb > Lay.n_blocks) return fail(ctx, MC_ERR_DEVICE, "block count mismatch");
-    HIP_TRY(ctx, launch_final_reduce_batch(parts, nb, Lay.n_mom, n_replicates, moms, s));
+    HIP_TRY(ctx, launch_final_merge(parts, nb, 3, n_replicates, moms, s));
     HIP_TRY(ctx, hipEventRecord(ctx->ev1, s));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, moms, (size_t)n_replicates * Lay.n_mom * 8,
                                 hipMemcpyDeviceToHost, s));
@@ -1889,11 +1917,11 @@ mc_status mc_price_qmc(mc_context* ctx, const mc_model* m, const mc_payoff* f, u
     HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
     r.kernel_ms = ms;
     for (uint32_t rep = 0; rep < n_replicates; ++rep) {
-      // Moments: [n_valid, n_nonfinite, sum basket, sum geometric, ...].
+      // Moments: [n_valid, n_nonfinite, mean basket, mean geometric, ...].
       const double* mr = ctx->pinned + (size_t)rep * Lay.n_mom;
       if (mr[0] < 2) return fail(ctx, MC_ERR_DEVICE, "replicate %u: fewer than two finite paths", rep);
-      r.replicate_price[rep] = mr[2] / mr[0];
-      r.replicate_geo[rep] = mr[3] / mr[0];
+      r.replicate_price[rep] = mr[2];
+      r.replicate_geo[rep] = mr[3];
     }
   }
   auto mean_se = [n_replicates](const double* x, double* mean, double* se) {
@@ -2045,7 +2073,7 @@ mc_status mc_greeks_adjoint(mc_context* ctx, const mc_model* m, const mc_payoff*
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, MC_ERR_DEVICE, "hipSetDevice");
   const size_t need = mc_adjoint_ckpt_bytes(n_paths, n_steps, ckpt_every);
   const int C = phase == MC_ADJ_FULL ? 3 : phase == MC_ADJ_FWD ? 1 : 2;
-  const RunLayout L = layout_for(n_paths, C, o.path_values != nullptr);
+  const RunLayout L = layout_for(n_paths, C, o.path_values != nullptr, kBlock, kHestonMaxBlocks);
   const uint32_t n_ckpt = (n_steps + ckpt_every - 1) / ckpt_every;
   // A one-launch sweep with few checkpoints keeps them in LDS.
   const bool lds = phase == MC_ADJ_FULL && n_ckpt <= (uint32_t)mcp::kLdsCkpt;
@@ -2082,7 +2110,7 @@ mc_status mc_greeks_adjoint(mc_context* ctx, const mc_model* m, const mc_payoff*
                      a.h.path_out = path_out;
                      return launch_heston_adjoint(a, s, nb);
                    },
-                   &mom, &kms);
+                   &mom, &kms, kBlock, kHestonMaxBlocks);
   if (st != MC_OK) return st;
   mc_result r{};
   double v;

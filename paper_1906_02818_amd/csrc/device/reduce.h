@@ -1,18 +1,162 @@
-// Block reduction of per-path values into per-block moment sums, the first
+// Block reduction of per-path values into per-block moments, the first
 // stage of the averaging reduction that ends every Monte Carlo estimate
-// (Eq. 3; the variance term of Sec. V-B needs the second moments).
+// (Eq. 3) and of its variance term (Sec. V-B).
 //
-// Each thread holds the C channel values of its path in double. The block
-// writes, for every moment m, one double to partials[m * n_blocks + block]:
-//   m = 0: number of valid paths, m = 1: number of non-finite paths,
-//   m = 2 .. C+1: sum of y_c, then sum of y_a * y_b for a <= b.
-// Wave sums use a fixed xor butterfly and the 4 wave sums are added in
-// wave order, so the result does not depend on scheduling.
+// Moments are kept as (count, means, co-moments about the means) and
+// combined by the pairwise update of Chan, Golub and LeVeque: for two parts
+// A and B with n = nA + nB and delta = mean_B - mean_A,
+//     mean = mean_A + delta nB / n,
+//     M_ab = M_ab^A + M_ab^B + delta_a delta_b nA nB / n.
+// A thread adds its own paths one at a time (Welford's update, the same
+// formula with nB = 1). No sum of squares is formed, so a variance far
+// below the square of the mean (a near-perfect control variate) keeps its
+// digits.
+//
+// A moment vector of C channels holds M = 2 + C + C (C+1)/2 doubles:
+//   [0] valid paths, [1] non-finite paths, [2 .. 2+C) means,
+//   then M_ab for a <= b in row order.
+// Block partials are block-major: block b writes partials[b M .. b M + M),
+// one contiguous vector. The wave step is a fixed xor butterfly and the
+// waves are merged in wave order, so results do not depend on scheduling.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace mcp {
+
+template <int C>
+struct Mom {
+  static constexpr int NC = C * (C + 1) / 2;
+  static constexpr int M = 2 + C + NC;
+  double n, bad, mean[C], co[NC];
+
+  __device__ __forceinline__ void zero() {
+    n = 0.0;
+    bad = 0.0;
+#pragma unroll
+    for (int a = 0; a < C; ++a) mean[a] = 0.0;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) co[k] = 0.0;
+  }
+
+  // One valid path (Welford).
+  __device__ __forceinline__ void add(const double (&y)[C]) {
+    n += 1.0;
+    const double r = 1.0 / n;
+    double d[C];
+#pragma unroll
+    for (int a = 0; a < C; ++a) {
+      d[a] = y[a] - mean[a];
+      mean[a] += d[a] * r;
+    }
+    int k = 0;
+#pragma unroll
+    for (int a = 0; a < C; ++a)
+#pragma unroll
+      for (int b = a; b < C; ++b) co[k++] += d[a] * (y[b] - mean[b]);
+  }
+
+  // A path: counted as valid (its channels enter the moments) or not, and
+  // as non-finite or not.
+  __device__ __forceinline__ void push(const double (&y)[C], bool valid, bool nonfinite) {
+    if (nonfinite) bad += 1.0;
+    if (valid) add(y);
+  }
+
+  // Chan's pairwise update; an empty part (n = 0, zero means and
+  // co-moments) leaves the other unchanged bit for bit.
+  __device__ __forceinline__ void merge(const Mom& o) {
+    bad += o.bad;
+    const double nt = n + o.n;
+    const double f = nt > 0.0 ? o.n / nt : 0.0;
+    const double g = n * f;   // nA nB / n
+    double d[C];
+#pragma unroll
+    for (int a = 0; a < C; ++a) {
+      d[a] = o.mean[a] - mean[a];
+      mean[a] += d[a] * f;
+    }
+    int k = 0;
+#pragma unroll
+    for (int a = 0; a < C; ++a)
+#pragma unroll
+      for (int b = a; b < C; ++b, ++k) co[k] += o.co[k] + d[a] * d[b] * g;
+    n = nt;
+  }
+
+  __device__ __forceinline__ void store(double* p) const {
+    p[0] = n;
+    p[1] = bad;
+#pragma unroll
+    for (int a = 0; a < C; ++a) p[2 + a] = mean[a];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) p[2 + C + k] = co[k];
+  }
+
+  __device__ __forceinline__ void load(const double* p) {
+    n = p[0];
+    bad = p[1];
+#pragma unroll
+    for (int a = 0; a < C; ++a) mean[a] = p[2 + a];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) co[k] = p[2 + C + k];
+  }
+};
+
+template <int C>
+__device__ __forceinline__ void wave_merge(Mom<C>& m) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    Mom<C> o;
+    o.n = __shfl_xor(m.n, off, 64);
+    o.bad = __shfl_xor(m.bad, off, 64);
+#pragma unroll
+    for (int a = 0; a < C; ++a) o.mean[a] = __shfl_xor(m.mean[a], off, 64);
+#pragma unroll
+    for (int k = 0; k < Mom<C>::NC; ++k) o.co[k] = __shfl_xor(m.co[k], off, 64);
+    m.merge(o);
+  }
+}
+
+// Merges the block's per-thread moments and writes the block's vector to
+// partials[block * M ...].
+template <int C, int BLOCK>
+__device__ __forceinline__ void block_reduce_moments(Mom<C>& m, double* __restrict__ partials,
+                                                     uint32_t block) {
+  constexpr int W = BLOCK / 64, M = Mom<C>::M;
+  __shared__ double red[W][M];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  wave_merge(m);
+  if (lane == 0) m.store(red[wave]);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Mom<C> t;
+    t.load(red[0]);
+#pragma unroll 1
+    for (int w = 1; w < W; ++w) {
+      Mom<C> o;
+      o.load(red[w]);
+      t.merge(o);
+    }
+    t.store(red[0]);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < M; t += BLOCK) partials[(size_t)block * M + t] = red[0][t];
+}
+
+// One path per thread (y[] ignored unless valid).
+template <int C, int BLOCK>
+__device__ __forceinline__ void block_moments(const double (&y)[C], bool valid, bool nonfinite,
+                                              double* __restrict__ partials,
+                                              uint32_t block = ~0u) {
+  Mom<C> m;
+  m.zero();
+  m.push(y, valid, nonfinite);
+  block_reduce_moments<C, BLOCK>(m, partials, block == ~0u ? blockIdx.x : block);
+}
+
+// ---- Plain sums (counts, tail sums, Gram matrices): moment-major ----------
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -20,64 +164,11 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <int C, int BLOCK>
-__device__ __forceinline__ void block_moments(const double (&y)[C], bool valid, bool nonfinite,
-                                              double* __restrict__ partials,
-                                              uint32_t n_blocks, uint32_t block = ~0u) {
-  if (block == ~0u) block = blockIdx.x;
-  constexpr int M = 2 + C + C * (C + 1) / 2;
-  constexpr int W = BLOCK / 64;
-  __shared__ double red[M][W];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  int m = 0;
-  auto push = [&](double v) {
-    v = wave_sum(v);
-    if (lane == 0) red[m][wave] = v;
-    ++m;
-  };
-  push(valid ? 1.0 : 0.0);
-  push(nonfinite ? 1.0 : 0.0);
-#pragma unroll
-  for (int a = 0; a < C; ++a) push(valid ? y[a] : 0.0);
-#pragma unroll
-  for (int a = 0; a < C; ++a)
-#pragma unroll
-    for (int b = a; b < C; ++b) push(valid ? y[a] * y[b] : 0.0);
-  __syncthreads();
-  for (int t = threadIdx.x; t < M; t += BLOCK) {
-    double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < W; ++w) s += red[t][w];
-    partials[(size_t)t * n_blocks + block] = s;
-  }
-}
-
-// Per-thread running moments over several paths (same layout as above):
-// acc[0] valid count, acc[1] non-finite count, acc[2 + c] sum y_c, then
-// sum y_a y_b for a <= b.
-template <int C>
-__device__ __forceinline__ void accumulate_moments(double (&acc)[2 + C + C * (C + 1) / 2],
-                                                   const double (&y)[C], bool valid,
-                                                   bool nonfinite) {
-  if (nonfinite) acc[1] += 1.0;
-  if (!valid) return;
-  acc[0] += 1.0;
-  int m = 2;
-#pragma unroll
-  for (int a = 0; a < C; ++a) acc[m++] += y[a];
-#pragma unroll
-  for (int a = 0; a < C; ++a)
-#pragma unroll
-    for (int b = a; b < C; ++b) acc[m++] += y[a] * y[b];
-}
-
-// Block sum of per-thread moment vectors, written to
-// partials[m * n_blocks + block] (fixed wave-butterfly and wave order).
+// Block sum of per-thread vectors, written to partials[m * n_blocks + block]
+// (fixed wave butterfly and wave order).
 template <int M, int BLOCK>
-__device__ __forceinline__ void block_reduce_moments(const double (&acc)[M],
-                                                     double* __restrict__ partials,
-                                                     uint32_t n_blocks) {
+__device__ __forceinline__ void block_sum(const double (&acc)[M], double* __restrict__ partials,
+                                          uint32_t n_blocks) {
   constexpr int W = BLOCK / 64;
   __shared__ double red[M][W];
   const int lane = threadIdx.x & 63;
@@ -96,15 +187,15 @@ __device__ __forceinline__ void block_reduce_moments(const double (&acc)[M],
   }
 }
 
-// Block sum for long moment vectors (fixed order, like the above): per
-// pass, each wave stores 16 moments of its 64 lanes in LDS; lane l adds the
-// 16 values of moment l / 4 from lanes 16 (l mod 4) .. 16 (l mod 4) + 15,
-// and two butterfly steps combine the four quarters. About a quarter of the
-// instructions of a 6-step butterfly per moment.
+// Block sum for long vectors (fixed order, like the above): per pass, each
+// wave stores 16 entries of its 64 lanes in LDS; lane l adds the 16 values
+// of entry l / 4 from lanes 16 (l mod 4) .. 16 (l mod 4) + 15, and two
+// butterfly steps combine the four quarters. About a quarter of the
+// instructions of a 6-step butterfly per entry.
 template <int M, int BLOCK>
-__device__ __forceinline__ void block_reduce_moments_wide(const double (&acc)[M],
-                                                          double* __restrict__ partials,
-                                                          uint32_t n_blocks) {
+__device__ __forceinline__ void block_sum_wide(const double (&acc)[M],
+                                               double* __restrict__ partials,
+                                               uint32_t n_blocks) {
   constexpr int W = BLOCK / 64, CH = 16;
   __shared__ double buf[W][CH][64 + 1];
   __shared__ double red[M][W];

@@ -95,14 +95,13 @@ __global__ __launch_bounds__(kThreads) void basket_kernel(const BasketParams P) 
   const int row = lane & 31;          // A row / B and D column
   const int half = lane >> 5;
   // Block blk of the launch, or of its replicate when replicates share it.
-  uint32_t blk = blockIdx.x, n_part = gridDim.x;
+  uint32_t blk = blockIdx.x;
   const uint32_t* qshift = P.qshift;
   double* partials = P.partials;
   if constexpr (QMC) {
     if (P.q_rep_blocks != 0) {
       const uint32_t rep = blockIdx.x / P.q_rep_blocks;
       blk = blockIdx.x - rep * P.q_rep_blocks;
-      n_part = P.q_rep_blocks;
       qshift += (size_t)rep * P.q_dims;
       partials += (size_t)rep * n_moments(PORT ? 1 : 3) * P.q_rep_blocks;
     }
@@ -196,7 +195,7 @@ __global__ __launch_bounds__(kThreads) void basket_kernel(const BasketParams P) 
     if (active) y[0] = (double)B - P.premium;
     const bool finite = isfinite(y[0]);
     if (active && P.path_out != nullptr) P.path_out[pid] = y[0];
-    block_moments<1, kThreads>(y, active && finite, active && !finite, partials, n_part, blk);
+    block_moments<1, kThreads>(y, active && finite, active && !finite, partials, blk);
   } else {
     double y[3] = {0.0, 0.0, 0.0};
     if (active) {
@@ -212,7 +211,7 @@ __global__ __launch_bounds__(kThreads) void basket_kernel(const BasketParams P) 
 #pragma unroll
       for (int c = 0; c < 3; ++c) P.path_out[pid * 3 + c] = y[c];
     }
-    block_moments<3, kThreads>(y, active && finite, active && !finite, partials, n_part, blk);
+    block_moments<3, kThreads>(y, active && finite, active && !finite, partials, blk);
   }
 }
 

@@ -1,5 +1,6 @@
-// Second stage of the averaging reduction (Eq. 3), the reduction of a
-// multilevel correction (difference of two runs on the same paths) and the
+// Second stage of the averaging reduction (Eq. 3) and its variance term
+// (Sec. V-B), the reduction of a multilevel correction (difference of two
+// runs on the same paths), plain sums, and the
 // diagnostic kernels that expose the device random numbers for bit-exact
 // checks.
 #include "device/reduce.h"
@@ -9,10 +10,10 @@
 namespace mcp {
 namespace {
 
-// One workgroup per moment: thread t adds blocks t, t+256, ... in order,
-// then a fixed-shape tree adds the 256 partial sums. Deterministic.
-// Moment m = blockIdx.x of batch b = blockIdx.y: partials [b][m][n_blocks],
-// out [b][n_mom].
+// Plain sums (counts, tail sums, gradients): one workgroup per entry m of
+// batch b = blockIdx.y; thread t adds blocks t, t+256, ... in order, then a
+// fixed-shape tree adds the 256 partial sums. Deterministic. partials
+// [b][m][n_blocks], out [b][n_mom].
 __global__ __launch_bounds__(256) void final_reduce_kernel(const double* __restrict__ partials,
                                                            uint32_t n_blocks,
                                                            double* __restrict__ out) {
@@ -30,6 +31,26 @@ __global__ __launch_bounds__(256) void final_reduce_kernel(const double* __restr
     __syncthreads();
   }
   if (threadIdx.x == 0) out[m] = sh[0];
+}
+
+// Moment vectors of C channels (count, means, co-moments): one workgroup per
+// batch b = blockIdx.x merges the block-major partials [b][n_blocks][M] into
+// out[b][M]: thread t merges blocks t, t+256, ... in order (Chan's update),
+// then the fixed wave butterfly and wave order of the path kernels.
+template <int C>
+__global__ __launch_bounds__(256) void final_merge_kernel(const double* __restrict__ partials,
+                                                          uint32_t n_blocks,
+                                                          double* __restrict__ out) {
+  constexpr int M = Mom<C>::M;
+  partials += (size_t)blockIdx.x * n_blocks * M;
+  Mom<C> m;
+  m.zero();
+  for (uint32_t i = threadIdx.x; i < n_blocks; i += 256) {
+    Mom<C> b;
+    b.load(partials + (size_t)i * M);
+    m.merge(b);
+  }
+  block_reduce_moments<C, 256>(m, out, blockIdx.x);
 }
 
 __global__ void philox_words_kernel(uint32_t k0, uint32_t k1, uint32_t tag, uint64_t n,
@@ -66,18 +87,16 @@ __global__ __launch_bounds__(kBlock) void diff_moments_kernel(const double* __re
                                                               const double* __restrict__ b,
                                                               uint32_t Cb, uint32_t cb, uint64_t n,
                                                               double* __restrict__ partials) {
-  constexpr int M = n_moments(3);
-  double acc[M];
-#pragma unroll
-  for (int m = 0; m < M; ++m) acc[m] = 0.0;
+  Mom<3> acc;
+  acc.zero();
   const uint64_t stride = (uint64_t)gridDim.x * kBlock;
   for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
     const double fa = a[i * Ca + ca], fb = b[i * Cb + cb];
     const double y[3] = {fa - fb, fa, fb};
     const bool finite = isfinite(y[0]) && isfinite(fa) && isfinite(fb);
-    accumulate_moments<3>(acc, y, finite, !finite);
+    acc.push(y, finite, !finite);
   }
-  block_reduce_moments<M, kBlock>(acc, partials, gridDim.x);
+  block_reduce_moments<3, kBlock>(acc, partials, blockIdx.x);
 }
 
 // Shift row of replicate replicate0 + blockIdx.y: [blockIdx.y][n_dims].
@@ -112,6 +131,31 @@ hipError_t launch_diff_moments(const double* a, uint32_t Ca, uint32_t ca, const 
   hipLaunchKernelGGL(diff_moments_kernel, dim3(nb), dim3(kBlock), 0, s, a, Ca, ca, b, Cb, cb, n,
                      partials);
   return hipGetLastError();
+}
+
+template <int C>
+static hipError_t merge_one(const double* partials, uint32_t n_blocks, uint32_t n_batch,
+                            double* out, hipStream_t s) {
+  hipLaunchKernelGGL(final_merge_kernel<C>, dim3(n_batch), dim3(256), 0, s, partials, n_blocks,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_final_merge(const double* partials, uint32_t n_blocks, uint32_t C,
+                              uint32_t n_batch, double* out, hipStream_t s) {
+  if (n_blocks == 0 || n_batch == 0 || n_batch > 65535) return hipErrorInvalidValue;
+  switch (C) {
+    case 1: return merge_one<1>(partials, n_blocks, n_batch, out, s);
+    case 2: return merge_one<2>(partials, n_blocks, n_batch, out, s);
+    case 3: return merge_one<3>(partials, n_blocks, n_batch, out, s);
+    case 4: return merge_one<4>(partials, n_blocks, n_batch, out, s);
+    case 5: return merge_one<5>(partials, n_blocks, n_batch, out, s);
+    case 6: return merge_one<6>(partials, n_blocks, n_batch, out, s);
+    case 7: return merge_one<7>(partials, n_blocks, n_batch, out, s);
+    case 8: return merge_one<8>(partials, n_blocks, n_batch, out, s);
+    case 9: return merge_one<9>(partials, n_blocks, n_batch, out, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_final_reduce(const double* partials, uint32_t n_blocks, uint32_t n_mom,

@@ -393,7 +393,7 @@ __global__ __launch_bounds__(kCvThreads) void cv_values_kernel(const CvParams P)
 #pragma unroll
     for (int q = 0; q < 3; ++q) P.path_out[pid * 3 + q] = y[q];
   }
-  block_moments<3, kCvThreads>(y, active && finite, active && !finite, P.partials, gridDim.x);
+  block_moments<3, kCvThreads>(y, active && finite, active && !finite, P.partials);
 }
 
 // Backward pass: a wave takes 32 paths of the minibatch through every hedge
@@ -445,7 +445,7 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
 
   float g = 0.f;                       // upstream factor of this path
   if (active) {
-    const double ybar = P.ybar_mom[2 + 2] / P.ybar_mom[0];
+    const double ybar = P.ybar_mom[2 + 2];   // mean of channel 2 (Y)
     g = (float)(P.g_scale * (P.y_path[pid * 3 + 2] - ybar));
   }
   f32x16 gw2[2][2], gx[2];
@@ -646,8 +646,6 @@ __global__ __launch_bounds__(kCvThreads) void cv_eval_kernel(const CvParams P) {
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int half = lane >> 5;
-  const uint64_t pid = ((uint64_t)blockIdx.x * kCvWaves + wave) * 64 + lane;
-  const bool active = pid < Hp.n_paths;
   Op8<BF16> w1a[2];
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb) {
@@ -660,54 +658,62 @@ __global__ __launch_bounds__(kCvThreads) void cv_eval_kernel(const CvParams P) {
   const HestonF c(Hp);
   const float S0 = c.S0;
   const uint32_t n = Hp.n_steps, m = P.hedge_every;
-  const PathCounter pc = make_counter(Hp.path_offset + pid, Hp.tag, Hp.k0, Hp.k1);
-
-  float z = 0.f, v = (float)Hp.v0, sumE = 0.f, H = 0.f, delta = 0.f, st_open = 0.f, Et = 1.f;
-  Normals4<float> nz;
-  for (uint32_t i = 0; i < n; ++i) {
-    if (i % m == 0) {
-      float own[4];
-      c.features(i, z, v, sumE, own);
-      float other[4];
+  Mom<3> acc;
+  acc.zero();
+  // Persistent grid: block b takes the 256-path tiles b, b + gridDim.x, ...
+  const uint64_t n_tiles = (Hp.n_paths + kCvPathsPerBlock - 1) / kCvPathsPerBlock;
+  for (uint64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const uint64_t pid = (t * kCvWaves + wave) * 64 + lane;
+    const bool active = pid < Hp.n_paths;
+    const PathCounter pc = make_counter(Hp.path_offset + pid, Hp.tag, Hp.k0, Hp.k1);
+    float z = 0.f, v = (float)Hp.v0, sumE = 0.f, H = 0.f, delta = 0.f, st_open = 0.f, Et = 1.f;
+    Normals4<float> nz;
+    for (uint32_t i = 0; i < n; ++i) {
+      if (i % m == 0) {
+        float own[4];
+        c.features(i, z, v, sumE, own);
+        float other[4];
 #pragma unroll
-      for (int f = 0; f < 4; ++f) other[f] = __shfl_xor(own[f], 32, 64);
+        for (int f = 0; f < 4; ++f) other[f] = __shfl_xor(own[f], 32, 64);
 #pragma unroll 1
-      for (int sub = 0; sub < 2; ++sub) {
-        float phi[8];
+        for (int sub = 0; sub < 2; ++sub) {
+          float phi[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) phi[j] = 0.f;
-        if (half == 0) {
+          for (int j = 0; j < 8; ++j) phi[j] = 0.f;
+          if (half == 0) {
 #pragma unroll
-          for (int f = 0; f < 4; ++f) phi[f] = sub == 0 ? own[f] : other[f];
-          phi[4] = 1.0f;
+            for (int f = 0; f < 4; ++f) phi[f] = sub == 0 ? own[f] : other[f];
+            phi[4] = 1.0f;
+          }
+          const float d = mlp_delta<BF16>(phi, w1a, s_w2f, s_lanec, lane, b3);
+          if (sub == half) delta = d;
         }
-        const float d = mlp_delta<BF16>(phi, w1a, s_w2f, s_lanec, lane, b3);
-        if (sub == half) delta = d;
+        st_open = Et;
       }
-      st_open = Et;
+      if ((i & 1) == 0) nz = normals4<float>(philox(i >> 1, pc));
+      const float Z1 = (i & 1) ? nz.z[2] : nz.z[0];
+      const float Z2 = (i & 1) ? nz.z[3] : nz.z[1];
+      c.step(z, v, Z1, Z2);
+      Et = __builtin_amdgcn_exp2f(z);
+      sumE += Et * P.dfac[i + 1];
+      if ((i + 1) % m == 0 || i + 1 == n) H = __builtin_fmaf(delta, S0 * (Et - st_open), H);
     }
-    if ((i & 1) == 0) nz = normals4<float>(philox(i >> 1, pc));
-    const float Z1 = (i & 1) ? nz.z[2] : nz.z[0];
-    const float Z2 = (i & 1) ? nz.z[3] : nz.z[1];
-    c.step(z, v, Z1, Z2);
-    Et = __builtin_amdgcn_exp2f(z);
-    sumE += Et * P.dfac[i + 1];
-    if ((i + 1) % m == 0 || i + 1 == n) H = __builtin_fmaf(delta, S0 * (Et - st_open), H);
-  }
-  double y[3] = {0.0, 0.0, 0.0};
-  if (active) {
-    const double A = (double)S0 * (double)sumE / (double)n;
-    const double pay = Hp.disc * (A > Hp.K ? A - Hp.K : 0.0);
-    y[0] = pay;
-    y[1] = (double)H;
-    y[2] = pay - (double)H;
-  }
-  const bool finite = isfinite(y[0]) && isfinite(y[1]) && isfinite(y[2]);
-  if (active && P.path_out != nullptr) {
+    double y[3] = {0.0, 0.0, 0.0};
+    if (active) {
+      const double A = (double)S0 * (double)sumE / (double)n;
+      const double pay = Hp.disc * (A > Hp.K ? A - Hp.K : 0.0);
+      y[0] = pay;
+      y[1] = (double)H;
+      y[2] = pay - (double)H;
+    }
+    const bool finite = isfinite(y[0]) && isfinite(y[1]) && isfinite(y[2]);
+    if (active && P.path_out != nullptr) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) P.path_out[pid * 3 + c] = y[c];
+      for (int q = 0; q < 3; ++q) P.path_out[pid * 3 + q] = y[q];
+    }
+    acc.push(y, active && finite, active && !finite);
   }
-  block_moments<3, kCvThreads>(y, active && finite, active && !finite, P.partials, gridDim.x);
+  block_reduce_moments<3, kCvThreads>(acc, P.partials, blockIdx.x);
 }
 
 // Builds the per-lane fragments from the flat weights (one thread per
@@ -831,7 +837,8 @@ hipError_t launch_cv_pack(const float* theta, float* w1f, float* w2f, float* w2t
 }
 
 hipError_t launch_cv_price(const CvParams& p, hipStream_t s, uint32_t* n_blocks) {
-  const uint32_t nb = (uint32_t)((p.h.n_paths + kCvPathsPerBlock - 1) / kCvPathsPerBlock);
+  const uint64_t need = (p.h.n_paths + kCvPathsPerBlock - 1) / kCvPathsPerBlock;
+  const uint32_t nb = (uint32_t)(need < kCvEvalMaxBlocks ? need : kCvEvalMaxBlocks);
   *n_blocks = nb;
   if (p.bf16)
     hipLaunchKernelGGL((cv_eval_kernel<true>), dim3(nb), dim3(kCvThreads), 0, s, p);

@@ -194,10 +194,8 @@ __device__ __forceinline__ void simulate(const GbmParams& P, uint64_t path,
 template <typename R, uint32_t MASK, bool LOGS, uint32_t CO>
 __global__ __launch_bounds__(kBlock) void gbm_path_kernel(const GbmParams P) {
   constexpr int C = gbm_channels(MASK);
-  constexpr int M = n_moments(C);
-  double acc[M];
-#pragma unroll
-  for (int m = 0; m < M; ++m) acc[m] = 0.0;
+  Mom<C> acc;
+  acc.zero();
   const uint64_t stride = (uint64_t)gridDim.x * kBlock;
   for (uint64_t pid = (uint64_t)blockIdx.x * kBlock + threadIdx.x; pid < P.n_paths;
        pid += stride) {
@@ -210,9 +208,9 @@ __global__ __launch_bounds__(kBlock) void gbm_path_kernel(const GbmParams P) {
 #pragma unroll
       for (int c = 0; c < C; ++c) P.path_out[pid * C + c] = y[c];
     }
-    accumulate_moments<C>(acc, y, finite, !finite);
+    acc.push(y, finite, !finite);
   }
-  block_reduce_moments<M, kBlock>(acc, P.partials, gridDim.x);
+  block_reduce_moments<C, kBlock>(acc, P.partials, blockIdx.x);
 }
 
 template <typename R, uint32_t MASK, bool LOGS, uint32_t CO = 1>

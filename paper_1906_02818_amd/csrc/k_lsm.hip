@@ -233,7 +233,7 @@ __global__ __launch_bounds__(256) void lsm_sim_kernel(LsmParams p) {
       }
     }
   }
-  block_reduce_moments_wide<F::NMOM, 256>(acc, p.partials, gridDim.x);
+  block_sum_wide<F::NMOM, 256>(acc, p.partials, gridDim.x);
 }
 
 __device__ __forceinline__ float lane_of(const float4& v, int u) {
@@ -313,7 +313,7 @@ __global__ __launch_bounds__(256) void lsm_update_kernel(LsmParams p, uint32_t j
     // 32-byte sector holds an exercising path at some date anyway.
     if (changed) *(float4*)(p.C + 4 * q) = make_float4(cq[0], cq[1], cq[2], cq[3]);
   }
-  block_reduce_moments_wide<F::NMOM, 256>(acc, p.partials, gridDim.x);
+  block_sum_wide<F::NMOM, 256>(acc, p.partials, gridDim.x);
 }
 
 // Solves the normal equations of date j from one stage's reduced moments
@@ -421,7 +421,7 @@ __global__ __launch_bounds__(256) void lsm_oos_kernel(LsmParams p) {
     if (p.path_value) p.path_value[i] = v;
     if (p.ex) p.ex[i] = (uint8_t)e;
   }
-  block_reduce_moments<2, 256>(acc, p.partials, gridDim.x);
+  block_sum<2, 256>(acc, p.partials, gridDim.x);
 }
 
 uint32_t grid_for(uint64_t n, uint32_t cap = kLsmMaxBlocks) {

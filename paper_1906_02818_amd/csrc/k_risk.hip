@@ -102,7 +102,7 @@ __global__ __launch_bounds__(256) void tail_sum_kernel(const double* __restrict_
       acc[1] += v;
     }
   }
-  block_reduce_moments<2, 256>(acc, partials, gridDim.x);
+  block_sum<2, 256>(acc, partials, gridDim.x);
 }
 
 uint32_t grid_for(uint64_t n) {

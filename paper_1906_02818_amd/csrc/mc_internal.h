@@ -32,8 +32,11 @@ __host__ __device__ constexpr int popcount_c(uint32_t m) {
 __host__ __device__ constexpr int gbm_channels(uint32_t mask) {
   return popcount_c(mask & 0x1Fu) + 2 * popcount_c(mask & 0x60u);
 }
-// Moments per block: [n_valid, n_nonfinite, sum y_c (C), sum y_a y_b (a<=b)].
+// Moment vector of C channels: [n_valid, n_nonfinite, mean y_c (C),
+// co-moment sum (y_a - mean_a)(y_b - mean_b) (a <= b)]; block partials are
+// block-major, [block][n_moments(C)] (device/reduce.h).
 __host__ __device__ constexpr int n_moments(int C) { return 2 + C + C * (C + 1) / 2; }
+constexpr int kMaxMomentChannels = 9;
 
 struct GbmParams {
   uint64_t n_paths, path_offset;
@@ -48,7 +51,7 @@ struct GbmParams {
   double drift_dom, vol_dom, barrier_dom, bridge_c;
   // Euler on S: increments of S/S0.
   double r_dt, vol_sdt, barrier_rel;
-  double* partials;   // [n_moments][n_blocks]
+  double* partials;   // [n_blocks][n_moments]
   double* path_out;   // [n_paths][C] or nullptr
 };
 
@@ -70,6 +73,12 @@ constexpr uint32_t kDiffMaxBlocks = 1024;
 
 // ---- Heston ----
 enum : uint32_t { H_EURO = 1u << 0, H_ASIAN = 1u << 1 };
+
+// Heston kernels run on a persistent grid of at most this many workgroups
+// (each thread prices several paths); partials are one moment vector per
+// workgroup.
+constexpr uint32_t kHestonMaxBlocks = 8192;
+uint32_t heston_blocks(uint64_t n_paths);
 
 struct HestonParams {
   uint64_t n_paths, path_offset;
@@ -125,7 +134,7 @@ struct BasketParams {
   const uint32_t* qshift; // [dims], or [replicates][dims] with q_rep_blocks
   // Replicates in one launch: block b runs replicate b / q_rep_blocks with
   // shift row q_dims * replicate, and writes its moments to that
-  // replicate's own [moment][q_rep_blocks] partials.
+  // replicate's own [q_rep_blocks][moment] partials.
   uint32_t q_rep_blocks, q_dims;
   double* partials;
   double* path_out;       // [n_paths][3] (basket) or [n_paths] (portfolio), or nullptr
@@ -240,6 +249,9 @@ struct CvParams {
   uint32_t n_seg;            // ceil(n_steps / hedge_every)
 };
 constexpr int kCvPathsPerBlock = 256;       // evaluation: 4 waves of 64 paths
+// Evaluation grid: persistent, at most four workgroups per CU of the
+// 256-CU part (its occupancy), each taking every gridDim-th 256-path tile.
+constexpr uint32_t kCvEvalMaxBlocks = 1024;
 constexpr int kCvTrainPathsPerBlock = 128;  // training: 4 waves of 32 paths
 // Fragment layout of the weights, built on the device from theta.
 constexpr int kW1fFloats = 2 * 64 * 8, kW2fFloats = 2 * 4 * 64 * 8, kLanecFloats = 2 * 64 * 32;
@@ -261,10 +273,15 @@ hipError_t launch_adam_pack(const double* partials, uint32_t n_blocks, double* g
                             hipStream_t s);
 
 // ---- reductions and diagnostics ----
+// Moment vectors of C channels (1..kMaxMomentChannels): n_batch independent
+// merges of block-major partials [batch][n_blocks][n_moments(C)] into
+// out [batch][n_moments(C)].
+hipError_t launch_final_merge(const double* partials, uint32_t n_blocks, uint32_t C,
+                              uint32_t n_batch, double* out, hipStream_t s);
+// Plain sums: partials [n_mom][n_blocks] -> out [n_mom]; the batch form takes
+// partials [batch][n_mom][n_blocks] -> out [batch][n_mom].
 hipError_t launch_final_reduce(const double* partials, uint32_t n_blocks, uint32_t n_mom,
                                double* out, hipStream_t s);
-// n_batch independent reductions: partials [batch][n_mom][n_blocks] ->
-// out [batch][n_mom].
 hipError_t launch_final_reduce_batch(const double* partials, uint32_t n_blocks, uint32_t n_mom,
                                      uint32_t n_batch, double* out, hipStream_t s);
 hipError_t launch_philox_words(uint32_t k0, uint32_t k1, uint32_t tag, uint64_t n,

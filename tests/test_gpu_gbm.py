@@ -263,3 +263,36 @@ def test_sharding_merges_exactly_and_runs_are_deterministic(ctx):
     t1 = mc.mc_price(ctx, model, f, N, n, SEED, mc.Options(stream_tag=1))
     assert t1["price"] != a["price"]
     assert abs(t1["price"] - a["price"]) < 5 * math.hypot(a["std_err"], t1["std_err"])
+
+
+def test_near_perfect_control_variate_variance(ctx):
+    # The estimator's variance from the merged (count, mean, co-moment)
+    # vectors keeps its digits when the control variate leaves almost no
+    # variance: arithmetic Asian with the geometric-Asian control variate,
+    # deep in the money (both payoffs linear in the averages), r = 0 (so the
+    # two averages agree to first order in sigma) and sigma = 0.005: they
+    # differ by O(sigma^2). FP64 paths, a fixed coefficient. Against the
+    # oracle's per-path values on the same paths with a two-pass variance:
+    # VRF above 10^6, variance within 1e-6.
+    S0, r_, sig, T, K, n, N = 100.0, 0.0, 0.005, 1.0, 90.0, 64, 1 << 18
+    model = mc.Model(kind=mc.MC_GBM, S0=S0, r=r_, T=T, sigma=sig)
+    o = oracle.gbm(S0, r_, sig, T, K, 1e300, n, N, SEED)
+    beta = oracle.cv_beta(o[:, 1], o[:, 2])
+    res = mc.mc_price(ctx, model, mc.Payoff(mc.MC_ASIAN_ARITH_CALL, K, cv=mc.MC_CV_GEO_ASIAN),
+                      N, n, SEED, mc.Options(prec=mc.MC_FP64, cv_beta=beta))
+    y = o[:, 1] - beta * o[:, 2]
+    var = float(np.sum((y - y.mean()) ** 2) / (N - 1))
+    say(f"  VRF {res['vrf']:.3e}; variance gpu {res['variance']:.12e} oracle {var:.12e}")
+    assert res["vrf"] > 1e6
+    assert abs(res["variance"] / var - 1.0) < 1e-6
+    # A payoff whose variance is 1e-10 of its squared mean (K = 0, sigma =
+    # 1e-5): a sum of squares would lose it; the co-moments keep 1e-6.
+    model = mc.Model(kind=mc.MC_GBM, S0=S0, r=r_, T=T, sigma=1e-5)
+    res = mc.mc_price(ctx, model, mc.Payoff(mc.MC_EURO_CALL, 0.0), N, n, SEED,
+                      mc.Options(prec=mc.MC_FP64))
+    e = oracle.gbm(S0, r_, 1e-5, T, 0.0, 1e300, n, N, SEED)[:, 0]
+    var = float(np.sum((e - e.mean()) ** 2) / (N - 1))
+    say(f"  tiny variance: gpu {res['variance']:.12e} oracle {var:.12e}, "
+        f"mean^2/var {e.mean() ** 2 / var:.2e}")
+    assert e.mean() ** 2 / var > 1e9
+    assert abs(res["variance"] / var - 1.0) < 1e-6
