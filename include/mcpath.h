@@ -224,12 +224,14 @@ mc_status mc_price(mc_context *ctx, const mc_model *model, const mc_payoff *payo
  * there; each run overwrites all of it that it reads, so nothing needs
  * clearing. Calls that overlap on one GPU (two host threads, or two
  * contexts' streams at once) race on the scratch: serialise them.
- * The GBM and Heston kernels run on persistent grids (at most 8192
- * workgroups), so a run needs at most 8192 moment vectors of at most 9
- * channels (3.7 MB) whatever n_paths is; the scratch holds that.
+ * The GBM kernel and the Heston price and tangent kernels run on
+ * persistent grids (at most 8192 workgroups), so those runs need at most
+ * 8192 moment vectors of at most 9 channels (3.7 MB) whatever n_paths is.
+ * The Heston adjoint takes one path per thread: one 88-byte vector per 256
+ * paths, so it fits up to about 1.2e7 paths.
  * Errors: those of mc_price; a model, payoff or option outside the list
  * above -> MC_ERR_UNSUPPORTED; a run whose moments would not fit the
- * scratch -> MC_ERR_WORKSPACE (not reachable with the kernels above). */
+ * scratch -> MC_ERR_WORKSPACE, before any launch. */
 #define MC_NOALLOC_SCRATCH_BYTES (4u << 20)
 size_t mc_noalloc_scratch_bytes(void);
 mc_status mc_price_noalloc(mc_context *ctx, const mc_model *model, const mc_payoff *payoff,

@@ -771,7 +771,7 @@ mc_status cv_eval(mc_context* ctx, const mc_options& o, const CvParams& base, ui
                        p.path_out = path_out;
                        return launch_cv_price(p, s, nb);
                      },
-                     mom, kms, kCvPathsPerBlock, kCvEvalMaxBlocks);
+                     mom, kms, kCvPathsPerBlock);
 }
 
 mc_status heston_cv_price(mc_context* ctx, const mc_model* m, const mc_payoff* f,
@@ -784,8 +784,7 @@ mc_status heston_cv_price(mc_context* ctx, const mc_model* m, const mc_payoff* f
     if (!std::isfinite(o0.cv_weights[i])) return fail(ctx, MC_ERR_INVALID_ARG, "cv_weights not finite");
   const uint64_t n_pilot = o0.pilot_paths ? o0.pilot_paths : (1ull << 16);
   const uint64_t n_big = n_paths > n_pilot ? n_paths : n_pilot;
-  const RunLayout Lay =
-      layout_for(n_big, 3, o0.path_values != nullptr, kCvPathsPerBlock, kCvEvalMaxBlocks);
+  const RunLayout Lay = layout_for(n_big, 3, o0.path_values != nullptr, kCvPathsPerBlock);
   const size_t off = align256(Lay.bytes);
   char* base = nullptr;
   st = get_ws(ctx, o0, off + cv_extra_bytes(n_steps), &base);
@@ -853,7 +852,7 @@ mc_status heston_cv_price(mc_context* ctx, const mc_model* m, const mc_payoff* f
 struct CvTrainWs {
   char* eval_base;          // moment layout with per-path values
   size_t eval_bytes;
-  double* grad_partials;    // [kMlpNParam][n_blocks]
+  double* grad_partials;    // [n_blocks][kMlpNParam]
   double* grad;             // [kMlpNParam]
   CvBuffers b;
   float *m, *v;             // Adam moments
@@ -965,7 +964,7 @@ mc_status cv_loss_grad_device(mc_context* ctx, hipStream_t s, const mc_model* m,
   if (grad_blocks)
     *grad_blocks = nb;
   else
-    HIP_TRY(ctx, launch_final_reduce(w.grad_partials, nb, kMlpNParam, w.grad, s));
+    HIP_TRY(ctx, launch_grad_sum(w.grad_partials, nb, w.grad, s));
   return MC_OK;
 }
 
@@ -1510,9 +1509,13 @@ size_t mc_workspace_bytes(const mc_model* m, const mc_payoff* f, uint64_t n_path
   const mc_options o = opts ? *opts : defaults();
   const uint32_t C = mc_path_channels(m, f, &o);
   if (C == 0) return 0;
+  // Persistent grids: GBM, and the Heston price and tangent kernels (the
+  // adjoint and the learned CV take one path per thread).
+  const bool heston_persistent = m->kind == MC_HESTON && f->cv != MC_CV_LEARNED &&
+                                 !(o.greeks && o.greeks_method != MC_GREEKS_TANGENT);
   const uint32_t cap = m->kind == MC_GBM ? kGbmMaxBlocks
-                      : m->kind == MC_HESTON && f->cv != MC_CV_LEARNED ? kHestonMaxBlocks
-                                                                       : UINT32_MAX;
+                       : heston_persistent ? kHestonMaxBlocks
+                                           : UINT32_MAX;
   size_t bytes = layout_for(n_paths, (int)C, o.path_values != nullptr, kBlock, cap).bytes;
   if (m->kind == MC_HESTON && o.greeks && o.greeks_method == MC_GREEKS_PATHWISE &&
       (n_steps + mcp::kCkpt - 1) / mcp::kCkpt > (uint32_t)mcp::kLdsCkpt)
@@ -1520,8 +1523,7 @@ size_t mc_workspace_bytes(const mc_model* m, const mc_payoff* f, uint64_t n_path
   if (m->kind == MC_HESTON && f->cv == MC_CV_LEARNED) {
     const uint64_t n_pilot = o.pilot_paths ? o.pilot_paths : (1ull << 16);
     const uint64_t n_big = n_paths > n_pilot ? n_paths : n_pilot;
-    bytes = align256(layout_for(n_big, 3, o.path_values != nullptr, kCvPathsPerBlock,
-                                kCvEvalMaxBlocks).bytes) +
+    bytes = align256(layout_for(n_big, 3, o.path_values != nullptr, kCvPathsPerBlock).bytes) +
             cv_extra_bytes(n_steps);
   }
   if (m->kind == MC_GBM_BASKET) bytes = basket_ws_bytes(bytes, m->dim, o.prec);
@@ -2073,7 +2075,7 @@ mc_status mc_greeks_adjoint(mc_context* ctx, const mc_model* m, const mc_payoff*
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, MC_ERR_DEVICE, "hipSetDevice");
   const size_t need = mc_adjoint_ckpt_bytes(n_paths, n_steps, ckpt_every);
   const int C = phase == MC_ADJ_FULL ? 3 : phase == MC_ADJ_FWD ? 1 : 2;
-  const RunLayout L = layout_for(n_paths, C, o.path_values != nullptr, kBlock, kHestonMaxBlocks);
+  const RunLayout L = layout_for(n_paths, C, o.path_values != nullptr);
   const uint32_t n_ckpt = (n_steps + ckpt_every - 1) / ckpt_every;
   // A one-launch sweep with few checkpoints keeps them in LDS.
   const bool lds = phase == MC_ADJ_FULL && n_ckpt <= (uint32_t)mcp::kLdsCkpt;
@@ -2110,7 +2112,7 @@ mc_status mc_greeks_adjoint(mc_context* ctx, const mc_model* m, const mc_payoff*
                      a.h.path_out = path_out;
                      return launch_heston_adjoint(a, s, nb);
                    },
-                   &mom, &kms, kBlock, kHestonMaxBlocks);
+                   &mom, &kms);
   if (st != MC_OK) return st;
   mc_result r{};
   double v;

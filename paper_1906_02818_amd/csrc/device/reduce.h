@@ -2,22 +2,28 @@
 // stage of the averaging reduction that ends every Monte Carlo estimate
 // (Eq. 3) and of its variance term (Sec. V-B).
 //
-// Moments are kept as (count, means, co-moments about the means) and
-// combined by the pairwise update of Chan, Golub and LeVeque: for two parts
-// A and B with n = nA + nB and delta = mean_B - mean_A,
-//     mean = mean_A + delta nB / n,
-//     M_ab = M_ab^A + M_ab^B + delta_a delta_b nA nB / n.
-// A thread adds its own paths one at a time (Welford's update, the same
-// formula with nB = 1). No sum of squares is formed, so a variance far
-// below the square of the mean (a near-perfect control variate) keeps its
-// digits.
-//
 // A moment vector of C channels holds M = 2 + C + C (C+1)/2 doubles:
 //   [0] valid paths, [1] non-finite paths, [2 .. 2+C) means,
-//   then M_ab for a <= b in row order.
+//   then the co-moments M_ab = sum (y_a - mean_a)(y_b - mean_b), a <= b, in
+//   row order.
 // Block partials are block-major: block b writes partials[b M .. b M + M),
-// one contiguous vector. The wave step is a fixed xor butterfly and the
-// waves are merged in wave order, so results do not depend on scheduling.
+// one contiguous vector; the final merge combines them the same way.
+//
+// Parts are combined by the pairwise update of Chan, Golub and LeVeque,
+// written about a shift: a part with n paths, mean m and co-moments M is
+// held as (n, c, S1 = n (m - c), S2 = M + n (m - c)(m - c)^T) for a shift c
+// that is itself one of the parts' means (a sample of the same spread).
+// About a common shift, S1 and S2 add like plain sums, so paths, lanes,
+// waves and blocks combine without a division; moving a part to another
+// shift c' is exact algebra (S1' = S1 + n e, S2' = S2 + S1 e^T + e S1^T +
+// n e e^T with e = c - c'), and the moments come back as m = c + S1 / n,
+// M = S2 - S1 S1^T / n. All deviations are of the order of the spread, so a
+// variance far below the square of the mean (a near-perfect control
+// variate) keeps its digits. A thread of a persistent kernel sums its few
+// paths about zero and enters as one part about its own mean (ThreadSums),
+// which keeps the path loop's registers and code those of plain sums.
+// Sums run in fixed orders (per-thread path order, xor butterfly, wave
+// order, block order): results do not depend on scheduling.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,124 +31,208 @@
 namespace mcp {
 
 template <int C>
-struct Mom {
+struct PartSums {
   static constexpr int NC = C * (C + 1) / 2;
-  static constexpr int M = 2 + C + NC;
-  double n, bad, mean[C], co[NC];
+  static constexpr int M = 2 + C + NC;     // doubles in a moment vector
+  double n, bad, shift[C], s1[C], s2[NC];
 
   __device__ __forceinline__ void zero() {
     n = 0.0;
     bad = 0.0;
 #pragma unroll
-    for (int a = 0; a < C; ++a) mean[a] = 0.0;
+    for (int a = 0; a < C; ++a) shift[a] = s1[a] = 0.0;
 #pragma unroll
-    for (int k = 0; k < NC; ++k) co[k] = 0.0;
+    for (int k = 0; k < NC; ++k) s2[k] = 0.0;
   }
 
-  // One valid path (Welford).
-  __device__ __forceinline__ void add(const double (&y)[C]) {
-    n += 1.0;
-    const double r = 1.0 / n;
-    double d[C];
+  // A part (nb paths, means mb, co-moments cb), in this part's shift; the
+  // first non-empty part sets the shift.
+  __device__ __forceinline__ void add(double nb, const double* mb, const double* cb) {
+    if (nb == 0.0) return;
+    if (n == 0.0) {
+#pragma unroll
+      for (int a = 0; a < C; ++a) shift[a] = mb[a];
+    }
+    double e[C];
 #pragma unroll
     for (int a = 0; a < C; ++a) {
-      d[a] = y[a] - mean[a];
-      mean[a] += d[a] * r;
+      e[a] = mb[a] - shift[a];
+      s1[a] += nb * e[a];
     }
     int k = 0;
 #pragma unroll
     for (int a = 0; a < C; ++a)
 #pragma unroll
-      for (int b = a; b < C; ++b) co[k++] += d[a] * (y[b] - mean[b]);
+      for (int b = a; b < C; ++b, ++k) s2[k] += (cb ? cb[k] : 0.0) + nb * e[a] * e[b];
+    n += nb;
   }
 
-  // A path: counted as valid (its channels enter the moments) or not, and
-  // as non-finite or not.
+  // One path: counted as valid (its channels enter the moments) or not,
+  // and as non-finite or not.
   __device__ __forceinline__ void push(const double (&y)[C], bool valid, bool nonfinite) {
     if (nonfinite) bad += 1.0;
-    if (valid) add(y);
+    if (valid) add(1.0, y, nullptr);
   }
 
-  // Chan's pairwise update; an empty part (n = 0, zero means and
-  // co-moments) leaves the other unchanged bit for bit.
-  __device__ __forceinline__ void merge(const Mom& o) {
-    bad += o.bad;
-    const double nt = n + o.n;
-    const double f = nt > 0.0 ? o.n / nt : 0.0;
-    const double g = n * f;   // nA nB / n
-    double d[C];
+  // A stored moment vector [n, bad, means, co-moments].
+  __device__ __forceinline__ void add_vector(const double* v) {
+    bad += v[1];
+    add(v[0], v + 2, v + 2 + C);
+  }
+
+  // The same part about the shift c.
+  __device__ __forceinline__ void rebase(const double (&c)[C]) {
+    double e[C];
 #pragma unroll
-    for (int a = 0; a < C; ++a) {
-      d[a] = o.mean[a] - mean[a];
-      mean[a] += d[a] * f;
-    }
+    for (int a = 0; a < C; ++a) e[a] = n > 0.0 ? shift[a] - c[a] : 0.0;
     int k = 0;
 #pragma unroll
     for (int a = 0; a < C; ++a)
 #pragma unroll
-      for (int b = a; b < C; ++b, ++k) co[k] += o.co[k] + d[a] * d[b] * g;
-    n = nt;
-  }
-
-  __device__ __forceinline__ void store(double* p) const {
-    p[0] = n;
-    p[1] = bad;
+      for (int b = a; b < C; ++b, ++k) s2[k] += s1[a] * e[b] + e[a] * s1[b] + n * e[a] * e[b];
 #pragma unroll
-    for (int a = 0; a < C; ++a) p[2 + a] = mean[a];
-#pragma unroll
-    for (int k = 0; k < NC; ++k) p[2 + C + k] = co[k];
-  }
-
-  __device__ __forceinline__ void load(const double* p) {
-    n = p[0];
-    bad = p[1];
-#pragma unroll
-    for (int a = 0; a < C; ++a) mean[a] = p[2 + a];
-#pragma unroll
-    for (int k = 0; k < NC; ++k) co[k] = p[2 + C + k];
+    for (int a = 0; a < C; ++a) {
+      s1[a] += n * e[a];
+      shift[a] = c[a];
+    }
   }
 };
 
+// Per-thread sums of a persistent kernel's paths, y and y y^T about zero:
+// a thread prices at most a few hundred paths, whose rounding errors are
+// unbiased and average out across threads; the thread's part enters the
+// reduction about its own mean (part()), and everything above the thread
+// combines about shifts.
 template <int C>
-__device__ __forceinline__ void wave_merge(Mom<C>& m) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    Mom<C> o;
-    o.n = __shfl_xor(m.n, off, 64);
-    o.bad = __shfl_xor(m.bad, off, 64);
-#pragma unroll
-    for (int a = 0; a < C; ++a) o.mean[a] = __shfl_xor(m.mean[a], off, 64);
-#pragma unroll
-    for (int k = 0; k < Mom<C>::NC; ++k) o.co[k] = __shfl_xor(m.co[k], off, 64);
-    m.merge(o);
-  }
-}
+struct ThreadSums {
+  static constexpr int NC = C * (C + 1) / 2;
+  double n, bad, s[C], ss[NC];
 
-// Merges the block's per-thread moments and writes the block's vector to
-// partials[block * M ...].
+  __device__ __forceinline__ void zero() {
+    n = 0.0;
+    bad = 0.0;
+#pragma unroll
+    for (int a = 0; a < C; ++a) s[a] = 0.0;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) ss[k] = 0.0;
+  }
+
+  __device__ __forceinline__ void push(const double (&y)[C], bool valid, bool nonfinite) {
+    if (nonfinite) bad += 1.0;
+    if (!valid) return;
+    n += 1.0;
+#pragma unroll
+    for (int a = 0; a < C; ++a) s[a] += y[a];
+    int k = 0;
+#pragma unroll
+    for (int a = 0; a < C; ++a)
+#pragma unroll
+      for (int b = a; b < C; ++b) ss[k++] += y[a] * y[b];
+  }
+
+  // (n, shift = mean, S1 = 0, S2 = co-moments).
+  __device__ __forceinline__ PartSums<C> part() const {
+    PartSums<C> p;
+    p.n = n;
+    p.bad = bad;
+    const double r = n > 0.0 ? 1.0 / n : 0.0;
+#pragma unroll
+    for (int a = 0; a < C; ++a) {
+      p.shift[a] = s[a] * r;
+      p.s1[a] = 0.0;
+    }
+    int k = 0;
+#pragma unroll
+    for (int a = 0; a < C; ++a)
+#pragma unroll
+      for (int b = a; b < C; ++b, ++k) p.s2[k] = n > 0.0 ? ss[k] - s[a] * s[b] * r : 0.0;
+    return p;
+  }
+};
+
+// The block's moment vector from its threads' parts, written to
+// out[block * M ...]: each wave moves its lanes to the shift of its first
+// lane holding a path and sums them (xor butterfly); after one barrier every
+// output component is computed by its own thread, moving the waves' sums to
+// the shift of the first wave holding a path and adding them in wave order.
 template <int C, int BLOCK>
-__device__ __forceinline__ void block_reduce_moments(Mom<C>& m, double* __restrict__ partials,
-                                                     uint32_t block) {
-  constexpr int W = BLOCK / 64, M = Mom<C>::M;
-  __shared__ double red[W][M];
+__device__ __forceinline__ void block_reduce(PartSums<C>& t, double* __restrict__ out,
+                                             uint32_t block) {
+  constexpr int W = BLOCK / 64, NC = PartSums<C>::NC, M = PartSums<C>::M;
+  constexpr int R = 2 + 2 * C + NC;        // n, bad, shift, S1, S2 of a wave
+  __shared__ double red[W][R];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  wave_merge(m);
-  if (lane == 0) m.store(red[wave]);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    Mom<C> t;
-    t.load(red[0]);
-#pragma unroll 1
-    for (int w = 1; w < W; ++w) {
-      Mom<C> o;
-      o.load(red[w]);
-      t.merge(o);
+  const unsigned long long holders = __ballot(t.n > 0.0);
+  if (holders != 0ull) {                   // wave-uniform
+    const int src = __ffsll((long long)holders) - 1;
+    double c[C];
+#pragma unroll
+    for (int a = 0; a < C; ++a) c[a] = __shfl(t.shift[a], src, 64);
+    t.rebase(c);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    t.n += __shfl_xor(t.n, off, 64);
+    t.bad += __shfl_xor(t.bad, off, 64);
+#pragma unroll
+    for (int a = 0; a < C; ++a) t.s1[a] += __shfl_xor(t.s1[a], off, 64);
+#pragma unroll
+    for (int k = 0; k < NC; ++k) t.s2[k] += __shfl_xor(t.s2[k], off, 64);
+  }
+  if (lane == 0) {
+    red[wave][0] = t.n;
+    red[wave][1] = t.bad;
+#pragma unroll
+    for (int a = 0; a < C; ++a) {
+      red[wave][2 + a] = t.shift[a];
+      red[wave][2 + C + a] = t.s1[a];
     }
-    t.store(red[0]);
+#pragma unroll
+    for (int k = 0; k < NC; ++k) red[wave][2 + 2 * C + k] = t.s2[k];
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < M; t += BLOCK) partials[(size_t)block * M + t] = red[0][t];
+  for (int q = threadIdx.x; q < M; q += BLOCK) {
+    int w0 = 0;
+    while (w0 < W - 1 && red[w0][0] == 0.0) ++w0;   // first wave holding a path
+    double n = 0.0, bad = 0.0;
+    for (int w = 0; w < W; ++w) {
+      n += red[w][0];
+      bad += red[w][1];
+    }
+    // S1 of channel a about the common shift (wave order).
+    auto S1 = [&](int a) {
+      double s = 0.0;
+      for (int w = 0; w < W; ++w)
+        s += red[w][2 + C + a] + red[w][0] * (red[w][2 + a] - red[w0][2 + a]);
+      return s;
+    };
+    double v;
+    if (q == 0) {
+      v = n;
+    } else if (q == 1) {
+      v = bad;
+    } else if (q < 2 + C) {
+      const int a = q - 2;
+      v = n > 0.0 ? red[w0][2 + a] + S1(a) / n : 0.0;
+    } else {
+      int k = q - 2 - C, a = 0;
+      while (k >= C - a) {
+        k -= C - a;
+        ++a;
+      }
+      const int b = a + k, kk = q - 2 - C;
+      double s2 = 0.0;
+      for (int w = 0; w < W; ++w) {
+        const double nw = red[w][0];
+        const double ea = red[w][2 + a] - red[w0][2 + a], eb = red[w][2 + b] - red[w0][2 + b];
+        const double sa = red[w][2 + C + a], sb = red[w][2 + C + b];
+        s2 += red[w][2 + 2 * C + kk] + sa * eb + ea * sb + nw * ea * eb;
+      }
+      v = n > 0.0 ? s2 - S1(a) * S1(b) / n : 0.0;
+    }
+    out[(size_t)block * M + q] = v;
+  }
 }
 
 // One path per thread (y[] ignored unless valid).
@@ -150,10 +240,10 @@ template <int C, int BLOCK>
 __device__ __forceinline__ void block_moments(const double (&y)[C], bool valid, bool nonfinite,
                                               double* __restrict__ partials,
                                               uint32_t block = ~0u) {
-  Mom<C> m;
+  PartSums<C> m;
   m.zero();
   m.push(y, valid, nonfinite);
-  block_reduce_moments<C, BLOCK>(m, partials, block == ~0u ? blockIdx.x : block);
+  block_reduce<C, BLOCK>(m, partials, block == ~0u ? blockIdx.x : block);
 }
 
 // ---- Plain sums (counts, tail sums, Gram matrices): moment-major ----------

@@ -33,24 +33,23 @@ __global__ __launch_bounds__(256) void final_reduce_kernel(const double* __restr
   if (threadIdx.x == 0) out[m] = sh[0];
 }
 
-// Moment vectors of C channels (count, means, co-moments): one workgroup per
-// batch b = blockIdx.x merges the block-major partials [b][n_blocks][M] into
-// out[b][M]: thread t merges blocks t, t+256, ... in order (Chan's update),
-// then the fixed wave butterfly and wave order of the path kernels.
+// Moment vectors of C channels (count, means, co-moments): one workgroup of
+// kMergeThreads per batch b = blockIdx.x merges the block-major partials
+// [b][n_blocks][M] into out[b][M]: thread t adds blocks t, t + kMergeThreads,
+// ... in order (about a shift, no division), then the block reduction of the
+// path kernels.
+constexpr int kMergeThreads = 256;
+
 template <int C>
-__global__ __launch_bounds__(256) void final_merge_kernel(const double* __restrict__ partials,
-                                                          uint32_t n_blocks,
-                                                          double* __restrict__ out) {
-  constexpr int M = Mom<C>::M;
+__global__ __launch_bounds__(kMergeThreads) void final_merge_kernel(
+    const double* __restrict__ partials, uint32_t n_blocks, double* __restrict__ out) {
+  constexpr int M = PartSums<C>::M;
   partials += (size_t)blockIdx.x * n_blocks * M;
-  Mom<C> m;
+  PartSums<C> m;
   m.zero();
-  for (uint32_t i = threadIdx.x; i < n_blocks; i += 256) {
-    Mom<C> b;
-    b.load(partials + (size_t)i * M);
-    m.merge(b);
-  }
-  block_reduce_moments<C, 256>(m, out, blockIdx.x);
+  for (uint32_t i = threadIdx.x; i < n_blocks; i += kMergeThreads)
+    m.add_vector(partials + (size_t)i * M);
+  block_reduce<C, kMergeThreads>(m, out, blockIdx.x);
 }
 
 __global__ void philox_words_kernel(uint32_t k0, uint32_t k1, uint32_t tag, uint64_t n,
@@ -87,7 +86,7 @@ __global__ __launch_bounds__(kBlock) void diff_moments_kernel(const double* __re
                                                               const double* __restrict__ b,
                                                               uint32_t Cb, uint32_t cb, uint64_t n,
                                                               double* __restrict__ partials) {
-  Mom<3> acc;
+  ThreadSums<3> acc;
   acc.zero();
   const uint64_t stride = (uint64_t)gridDim.x * kBlock;
   for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
@@ -96,7 +95,8 @@ __global__ __launch_bounds__(kBlock) void diff_moments_kernel(const double* __re
     const bool finite = isfinite(y[0]) && isfinite(fa) && isfinite(fb);
     acc.push(y, finite, !finite);
   }
-  block_reduce_moments<3, kBlock>(acc, partials, blockIdx.x);
+  PartSums<3> part = acc.part();
+  block_reduce<3, kBlock>(part, partials, blockIdx.x);
 }
 
 // Shift row of replicate replicate0 + blockIdx.y: [blockIdx.y][n_dims].
@@ -136,8 +136,8 @@ hipError_t launch_diff_moments(const double* a, uint32_t Ca, uint32_t ca, const 
 template <int C>
 static hipError_t merge_one(const double* partials, uint32_t n_blocks, uint32_t n_batch,
                             double* out, hipStream_t s) {
-  hipLaunchKernelGGL(final_merge_kernel<C>, dim3(n_batch), dim3(256), 0, s, partials, n_blocks,
-                     out);
+  hipLaunchKernelGGL(final_merge_kernel<C>, dim3(n_batch), dim3(kMergeThreads), 0, s, partials,
+                     n_blocks, out);
   return hipGetLastError();
 }
 

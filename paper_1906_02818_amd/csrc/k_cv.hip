@@ -612,8 +612,9 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
     }
     __syncthreads();
   }
+  // Block-major: the block's 4545 partials are one contiguous row.
   for (int i = threadIdx.x; i < kMlpNParam; i += kCvThreads)
-    P.grad_partials[(uint64_t)i * gridDim.x + blockIdx.x] = red[i];
+    P.grad_partials[(uint64_t)blockIdx.x * kMlpNParam + i] = red[i];
 }
 
 // The BF16 form fits two waves per SIMD (256 VGPRs, LDS for three
@@ -658,62 +659,56 @@ __global__ __launch_bounds__(kCvThreads) void cv_eval_kernel(const CvParams P) {
   const HestonF c(Hp);
   const float S0 = c.S0;
   const uint32_t n = Hp.n_steps, m = P.hedge_every;
-  Mom<3> acc;
-  acc.zero();
-  // Persistent grid: block b takes the 256-path tiles b, b + gridDim.x, ...
-  const uint64_t n_tiles = (Hp.n_paths + kCvPathsPerBlock - 1) / kCvPathsPerBlock;
-  for (uint64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-    const uint64_t pid = (t * kCvWaves + wave) * 64 + lane;
-    const bool active = pid < Hp.n_paths;
-    const PathCounter pc = make_counter(Hp.path_offset + pid, Hp.tag, Hp.k0, Hp.k1);
-    float z = 0.f, v = (float)Hp.v0, sumE = 0.f, H = 0.f, delta = 0.f, st_open = 0.f, Et = 1.f;
-    Normals4<float> nz;
-    for (uint32_t i = 0; i < n; ++i) {
-      if (i % m == 0) {
-        float own[4];
-        c.features(i, z, v, sumE, own);
-        float other[4];
+  const uint64_t pid = ((uint64_t)blockIdx.x * kCvWaves + wave) * 64 + lane;
+  const bool active = pid < Hp.n_paths;
+  const PathCounter pc = make_counter(Hp.path_offset + pid, Hp.tag, Hp.k0, Hp.k1);
+
+  float z = 0.f, v = (float)Hp.v0, sumE = 0.f, H = 0.f, delta = 0.f, st_open = 0.f, Et = 1.f;
+  Normals4<float> nz;
+  for (uint32_t i = 0; i < n; ++i) {
+    if (i % m == 0) {
+      float own[4];
+      c.features(i, z, v, sumE, own);
+      float other[4];
 #pragma unroll
-        for (int f = 0; f < 4; ++f) other[f] = __shfl_xor(own[f], 32, 64);
+      for (int f = 0; f < 4; ++f) other[f] = __shfl_xor(own[f], 32, 64);
 #pragma unroll 1
-        for (int sub = 0; sub < 2; ++sub) {
-          float phi[8];
+      for (int sub = 0; sub < 2; ++sub) {
+        float phi[8];
 #pragma unroll
-          for (int j = 0; j < 8; ++j) phi[j] = 0.f;
-          if (half == 0) {
+        for (int j = 0; j < 8; ++j) phi[j] = 0.f;
+        if (half == 0) {
 #pragma unroll
-            for (int f = 0; f < 4; ++f) phi[f] = sub == 0 ? own[f] : other[f];
-            phi[4] = 1.0f;
-          }
-          const float d = mlp_delta<BF16>(phi, w1a, s_w2f, s_lanec, lane, b3);
-          if (sub == half) delta = d;
+          for (int f = 0; f < 4; ++f) phi[f] = sub == 0 ? own[f] : other[f];
+          phi[4] = 1.0f;
         }
-        st_open = Et;
+        const float d = mlp_delta<BF16>(phi, w1a, s_w2f, s_lanec, lane, b3);
+        if (sub == half) delta = d;
       }
-      if ((i & 1) == 0) nz = normals4<float>(philox(i >> 1, pc));
-      const float Z1 = (i & 1) ? nz.z[2] : nz.z[0];
-      const float Z2 = (i & 1) ? nz.z[3] : nz.z[1];
-      c.step(z, v, Z1, Z2);
-      Et = __builtin_amdgcn_exp2f(z);
-      sumE += Et * P.dfac[i + 1];
-      if ((i + 1) % m == 0 || i + 1 == n) H = __builtin_fmaf(delta, S0 * (Et - st_open), H);
+      st_open = Et;
     }
-    double y[3] = {0.0, 0.0, 0.0};
-    if (active) {
-      const double A = (double)S0 * (double)sumE / (double)n;
-      const double pay = Hp.disc * (A > Hp.K ? A - Hp.K : 0.0);
-      y[0] = pay;
-      y[1] = (double)H;
-      y[2] = pay - (double)H;
-    }
-    const bool finite = isfinite(y[0]) && isfinite(y[1]) && isfinite(y[2]);
-    if (active && P.path_out != nullptr) {
-#pragma unroll
-      for (int q = 0; q < 3; ++q) P.path_out[pid * 3 + q] = y[q];
-    }
-    acc.push(y, active && finite, active && !finite);
+    if ((i & 1) == 0) nz = normals4<float>(philox(i >> 1, pc));
+    const float Z1 = (i & 1) ? nz.z[2] : nz.z[0];
+    const float Z2 = (i & 1) ? nz.z[3] : nz.z[1];
+    c.step(z, v, Z1, Z2);
+    Et = __builtin_amdgcn_exp2f(z);
+    sumE += Et * P.dfac[i + 1];
+    if ((i + 1) % m == 0 || i + 1 == n) H = __builtin_fmaf(delta, S0 * (Et - st_open), H);
   }
-  block_reduce_moments<3, kCvThreads>(acc, P.partials, blockIdx.x);
+  double y[3] = {0.0, 0.0, 0.0};
+  if (active) {
+    const double A = (double)S0 * (double)sumE / (double)n;
+    const double pay = Hp.disc * (A > Hp.K ? A - Hp.K : 0.0);
+    y[0] = pay;
+    y[1] = (double)H;
+    y[2] = pay - (double)H;
+  }
+  const bool finite = isfinite(y[0]) && isfinite(y[1]) && isfinite(y[2]);
+  if (active && P.path_out != nullptr) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) P.path_out[pid * 3 + q] = y[q];
+  }
+  block_moments<3, kCvThreads>(y, active && finite, active && !finite, P.partials);
 }
 
 // Builds the per-lane fragments from the flat weights (one thread per
@@ -757,65 +752,76 @@ __device__ __forceinline__ void slot_of(int u, int& mb, int& r, int& h) {
   r = 4 * (q >> 3) + (q & 3);
 }
 
-// One Adam step with the gradient reduction in front and the fragment update
-// behind, one block per parameter. The block sums its parameter's per-block
-// partials in the order of final_reduce_kernel, takes Adam's step on
-// (theta, m, v) with the bias corrections c1 = 1 - b1^t, c2 = 1 - b2^t, and
-// writes the new value into each fragment slot that cv_pack_kernel gives the
-// parameter (W1, b1: one; W2: one in each of the two layouts; b2, W3: the 32
-// lanes of a half-wave). Padding slots keep the zeros of the first pack; b3
-// lives in theta only.
-__global__ __launch_bounds__(256) void adam_pack_kernel(
+// Gradient reduction of the block-major partials [n_blocks][kMlpNParam]:
+// a block of 256 threads takes kGradCols consecutive parameters; thread
+// (slice s, column p) adds blocks s, s + kGradSlices, ... in order (reads of
+// kGradCols consecutive doubles per row), then slice 0 adds the slices in
+// order. With ADAM, the same thread then takes one Adam step on (theta, m, v)
+// with the bias corrections c1 = 1 - b1^t, c2 = 1 - b2^t, and the block
+// writes the new values into each fragment slot that cv_pack_kernel gives
+// the parameter (W1, b1: one; W2: one in each of the two layouts; b2, W3:
+// the 32 lanes of a half-wave). Padding slots keep the zeros of the first
+// pack; b3 lives in theta only.
+constexpr int kGradCols = 32, kGradSlices = 256 / kGradCols;
+
+template <bool ADAM>
+__global__ __launch_bounds__(256) void grad_adam_kernel(
     const double* __restrict__ partials, uint32_t n_blocks, double* __restrict__ grad,
     float* __restrict__ theta, float* __restrict__ m, float* __restrict__ v, float lr, float b1,
     float b2, float eps, float c1, float c2, float* __restrict__ w1f, float* __restrict__ w2f,
     float* __restrict__ w2tf, float* __restrict__ lanec) {
-  __shared__ double sh[256];
-  __shared__ float th_new;
-  const int i = blockIdx.x;
-  const double* row = partials + (size_t)i * n_blocks;
+  __shared__ double sh[kGradSlices][kGradCols];
+  __shared__ float th_new[kGradCols];
+  const int col = threadIdx.x % kGradCols, slice = threadIdx.x / kGradCols;
+  const int p0 = blockIdx.x * kGradCols;
+  const int i = p0 + col;
   double s = 0.0;
-  for (uint32_t k = threadIdx.x; k < n_blocks; k += 256) s += row[k];
-  sh[threadIdx.x] = s;
+  if (i < kMlpNParam)
+    for (uint32_t k = slice; k < n_blocks; k += kGradSlices)
+      s += partials[(size_t)k * kMlpNParam + i];
+  sh[slice][col] = s;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    const double g = sh[0];
+  if (slice == 0 && i < kMlpNParam) {
+    double g = 0.0;
+#pragma unroll
+    for (int q = 0; q < kGradSlices; ++q) g += sh[q][col];
     grad[i] = g;
-    const float gr = (float)g;
-    const float mi = b1 * m[i] + (1.0f - b1) * gr;
-    const float vi = b2 * v[i] + (1.0f - b2) * gr * gr;
-    m[i] = mi;
-    v[i] = vi;
-    const float t = theta[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-    theta[i] = t;
-    th_new = t;
+    if constexpr (ADAM) {
+      const float gr = (float)g;
+      const float mi = b1 * m[i] + (1.0f - b1) * gr;
+      const float vi = b2 * v[i] + (1.0f - b2) * gr * gr;
+      m[i] = mi;
+      v[i] = vi;
+      const float t = theta[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+      theta[i] = t;
+      th_new[col] = t;
+    }
   }
+  if constexpr (!ADAM) return;
   __syncthreads();
-  const float t = th_new;
-  const int L = threadIdx.x;
-  if (i < 320) {                       // W1 [64][4] and b1 [64]: lane = unit row, h = 0
-    if (L == 0) {
-      const int u = i < 256 ? i >> 2 : i - 256, j = i < 256 ? (i & 3) : 4;
-      w1f[(u >> 5) * 512 + (u & 31) * 8 + j] = t;
-    }
-  } else if (i < 4416) {               // W2 [64 out][64 in]
-    if (L < 2) {
-      const int e = i - 320;
-      const int a = L == 0 ? e >> 6 : e & 63;   // fragment row
-      const int k = L == 0 ? e & 63 : e >> 6;   // k-slot unit
-      int mb, r, h;
-      slot_of(k, mb, r, h);
-      const int dst = (a >> 5) * 2048 + (2 * mb + (r >> 3)) * 512 + ((a & 31) + 32 * h) * 8 + (r & 7);
-      (L == 0 ? w2f : w2tf)[dst] = t;
-    }
-  } else if (i < 4544) {               // b2 [64] (scaled) and W3 [64]
-    if (L < 32) {
-      const bool is_b2 = i < 4480;
-      const int u = is_b2 ? i - 4416 : i - 4480;
+  // Fragment slots: up to 32 per parameter (b2, W3), kGradCols parameters.
+  for (int e = threadIdx.x; e < kGradCols * 32; e += 256) {
+    const int c = e >> 5, L = e & 31, ip = p0 + c;
+    if (ip >= kMlpNParam) continue;
+    const float t = th_new[c];
+    if (ip < 320) {                       // W1 [64][4] and b1 [64]: lane = unit row, h = 0
+      if (L == 0) {
+        const int u = ip < 256 ? ip >> 2 : ip - 256, j = ip < 256 ? (ip & 3) : 4;
+        w1f[(u >> 5) * 512 + (u & 31) * 8 + j] = t;
+      }
+    } else if (ip < 4416) {               // W2 [64 out][64 in]
+      if (L < 2) {
+        const int q = ip - 320;
+        const int a = L == 0 ? q >> 6 : q & 63;   // fragment row
+        const int k = L == 0 ? q & 63 : q >> 6;   // k-slot unit
+        int mb, r, h;
+        slot_of(k, mb, r, h);
+        const int dst = (a >> 5) * 2048 + (2 * mb + (r >> 3)) * 512 + ((a & 31) + 32 * h) * 8 + (r & 7);
+        (L == 0 ? w2f : w2tf)[dst] = t;
+      }
+    } else if (ip < 4544) {               // b2 [64] (scaled) and W3 [64]
+      const bool is_b2 = ip < 4480;
+      const int u = is_b2 ? ip - 4416 : ip - 4480;
       int mb, r, h;
       slot_of(u, mb, r, h);
       const int dst = (32 * h + L) * 32 + 16 * mb + r;
@@ -837,8 +843,7 @@ hipError_t launch_cv_pack(const float* theta, float* w1f, float* w2f, float* w2t
 }
 
 hipError_t launch_cv_price(const CvParams& p, hipStream_t s, uint32_t* n_blocks) {
-  const uint64_t need = (p.h.n_paths + kCvPathsPerBlock - 1) / kCvPathsPerBlock;
-  const uint32_t nb = (uint32_t)(need < kCvEvalMaxBlocks ? need : kCvEvalMaxBlocks);
+  const uint32_t nb = (uint32_t)((p.h.n_paths + kCvPathsPerBlock - 1) / kCvPathsPerBlock);
   *n_blocks = nb;
   if (p.bf16)
     hipLaunchKernelGGL((cv_eval_kernel<true>), dim3(nb), dim3(kCvThreads), 0, s, p);
@@ -893,9 +898,20 @@ hipError_t launch_adam_pack(const double* partials, uint32_t n_blocks, double* g
                             hipStream_t s) {
   if (n_blocks == 0) return hipErrorInvalidValue;
   const float c1 = (float)(1.0 - std::pow(b1, t)), c2 = (float)(1.0 - std::pow(b2, t));
-  hipLaunchKernelGGL(adam_pack_kernel, dim3(kMlpNParam), dim3(256), 0, s, partials, n_blocks,
+  const uint32_t nb = (kMlpNParam + kGradCols - 1) / kGradCols;
+  hipLaunchKernelGGL(grad_adam_kernel<true>, dim3(nb), dim3(256), 0, s, partials, n_blocks,
                      grad, theta, m, v, (float)lr, (float)b1, (float)b2, (float)eps, c1, c2, w1f,
                      w2f, w2tf, lanec);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_sum(const double* partials, uint32_t n_blocks, double* grad,
+                           hipStream_t s) {
+  if (n_blocks == 0) return hipErrorInvalidValue;
+  const uint32_t nb = (kMlpNParam + kGradCols - 1) / kGradCols;
+  hipLaunchKernelGGL(grad_adam_kernel<false>, dim3(nb), dim3(256), 0, s, partials, n_blocks,
+                     grad, nullptr, nullptr, nullptr, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, nullptr,
+                     nullptr, nullptr, nullptr);
   return hipGetLastError();
 }
 

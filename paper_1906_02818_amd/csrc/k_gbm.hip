@@ -194,7 +194,7 @@ __device__ __forceinline__ void simulate(const GbmParams& P, uint64_t path,
 template <typename R, uint32_t MASK, bool LOGS, uint32_t CO>
 __global__ __launch_bounds__(kBlock) void gbm_path_kernel(const GbmParams P) {
   constexpr int C = gbm_channels(MASK);
-  Mom<C> acc;
+  ThreadSums<C> acc;
   acc.zero();
   const uint64_t stride = (uint64_t)gridDim.x * kBlock;
   for (uint64_t pid = (uint64_t)blockIdx.x * kBlock + threadIdx.x; pid < P.n_paths;
@@ -210,7 +210,8 @@ __global__ __launch_bounds__(kBlock) void gbm_path_kernel(const GbmParams P) {
     }
     acc.push(y, finite, !finite);
   }
-  block_reduce_moments<C, kBlock>(acc, P.partials, blockIdx.x);
+  PartSums<C> part = acc.part();
+  block_reduce<C, kBlock>(part, P.partials, blockIdx.x);
 }
 
 template <typename R, uint32_t MASK, bool LOGS, uint32_t CO = 1>

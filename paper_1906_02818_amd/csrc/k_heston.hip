@@ -78,7 +78,7 @@ __device__ __forceinline__ R posv(R x) {
 template <typename R, uint32_t MASK>
 __global__ __launch_bounds__(kBlock) void heston_price_kernel(const HestonParams P) {
   constexpr int C = popcount_c(MASK);
-  Mom<C> acc;
+  ThreadSums<C> acc;
   acc.zero();
   HestonStep<R> hs;
   hs.init(P);
@@ -111,7 +111,8 @@ __global__ __launch_bounds__(kBlock) void heston_price_kernel(const HestonParams
     }
     acc.push(y, finite, !finite);
   }
-  block_reduce_moments<C, kBlock>(acc, P.partials, blockIdx.x);
+  PartSums<C> part = acc.part();
+  block_reduce<C, kBlock>(part, P.partials, blockIdx.x);
 }
 
 // Pathwise delta and d/dv0 in forward mode: the tangents (dz, dv) of the
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(kBlock) void heston_price_kernel(const HestonParams
 // European (ASIAN = false) or arithmetic-Asian call.
 template <typename R, bool ASIAN>
 __global__ __launch_bounds__(kBlock) void heston_tangent_kernel(const HestonParams P) {
-  Mom<3> acc;
+  ThreadSums<3> acc;
   acc.zero();
   HestonStep<R> hs;
   hs.init(P);
@@ -178,7 +179,8 @@ __global__ __launch_bounds__(kBlock) void heston_tangent_kernel(const HestonPara
     }
     acc.push(y, finite, !finite);
   }
-  block_reduce_moments<3, kBlock>(acc, P.partials, blockIdx.x);
+  PartSums<3> part = acc.part();
+  block_reduce<3, kBlock>(part, P.partials, blockIdx.x);
 }
 
 // Channel sets of the adjoint phases.
@@ -203,123 +205,119 @@ __global__ __launch_bounds__(kBlock) void heston_adjoint_kernel(const AdjointPar
   constexpr int C = AdjC<PHASE>::C;
   extern __shared__ float s_ck[];
   const HestonParams& P = A.h;
+  const uint64_t pid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool active = pid < P.n_paths;
   const uint64_t np = P.n_paths;
-  Mom<C> acc;
-  acc.zero();
-  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-  for (uint64_t pid = (uint64_t)blockIdx.x * kBlock + threadIdx.x; pid < np; pid += stride) {
-    auto ck_store = [&](uint32_t row, R x) {
-      if constexpr (LDS)
-        s_ck[row * kBlock + threadIdx.x] = (float)x;
-      else
-        A.ckpt[(size_t)row * np + pid] = (float)x;
-    };
-    auto ck_load = [&](uint32_t row) -> R {
-      if constexpr (LDS)
-        return (R)s_ck[row * kBlock + threadIdx.x];
-      else
-        return (R)A.ckpt[(size_t)row * np + pid];
-    };
-    double y[C];
+  auto ck_store = [&](uint32_t row, R x) {
+    if constexpr (LDS)
+      s_ck[row * kBlock + threadIdx.x] = (float)x;
+    else
+      A.ckpt[(size_t)row * np + pid] = (float)x;
+  };
+  auto ck_load = [&](uint32_t row) -> R {
+    if constexpr (LDS)
+      return (R)s_ck[row * kBlock + threadIdx.x];
+    else
+      return (R)A.ckpt[(size_t)row * np + pid];
+  };
+  double y[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) y[c] = 0.0;
-    {
-      HestonStep<R> hs;
-      hs.init(P);
-      const PathCounter pc = make_counter(P.path_offset + pid, P.tag, P.k0, P.k1);
-      const uint32_t n = P.n_steps, every = A.every;   // every: even, 2..kCkptMax
-      const R S0 = (R)P.S0, K = (R)P.K, disc = (R)P.disc, inv_n = R(1) / (R)n;
-      R term;  // A/S0 (Asian) or S_T/S0
-      if (PHASE != 2) {
-        // Forward sweep, storing (z, v) at the start of every segment.
-        R z = R(0), v = (R)P.v0, sumE = R(0), Zs;
-        for (uint32_t i0 = 0, seg = 0; i0 < n; i0 += every, ++seg) {
-          ck_store(2 * seg, z);
-          ck_store(2 * seg + 1, v);
-          const uint32_t len = min(every, n - i0);
-          for (uint32_t q = 0; q < len; q += 2) {
-            const Normals4<R> nz = normals4<R>(philox((i0 + q) >> 1, pc));
-            hs.step(z, v, nz.z[0], nz.z[1], Zs);
+  for (int c = 0; c < C; ++c) y[c] = 0.0;
+  if (active) {
+    HestonStep<R> hs;
+    hs.init(P);
+    const PathCounter pc = make_counter(P.path_offset + pid, P.tag, P.k0, P.k1);
+    const uint32_t n = P.n_steps, every = A.every;   // every: even, 2..kCkptMax
+    const R S0 = (R)P.S0, K = (R)P.K, disc = (R)P.disc, inv_n = R(1) / (R)n;
+    R term;  // A/S0 (Asian) or S_T/S0
+    if (PHASE != 2) {
+      // Forward sweep, storing (z, v) at the start of every segment.
+      R z = R(0), v = (R)P.v0, sumE = R(0), Zs;
+      for (uint32_t i0 = 0, seg = 0; i0 < n; i0 += every, ++seg) {
+        ck_store(2 * seg, z);
+        ck_store(2 * seg + 1, v);
+        const uint32_t len = min(every, n - i0);
+        for (uint32_t q = 0; q < len; q += 2) {
+          const Normals4<R> nz = normals4<R>(philox((i0 + q) >> 1, pc));
+          hs.step(z, v, nz.z[0], nz.z[1], Zs);
+          if (ASIAN) sumE += HDom<R>::exp_(z);
+          if (q + 1 < len) {
+            hs.step(z, v, nz.z[2], nz.z[3], Zs);
             if (ASIAN) sumE += HDom<R>::exp_(z);
-            if (q + 1 < len) {
-              hs.step(z, v, nz.z[2], nz.z[3], Zs);
-              if (ASIAN) sumE += HDom<R>::exp_(z);
+          }
+        }
+      }
+      term = ASIAN ? sumE * inv_n : HDom<R>::exp_(z);
+      if (PHASE == 1) A.ckpt[(size_t)(2 * A.n_ckpt) * np + pid] = (float)term;
+      const R pay = disc * posv(S0 * term - K);
+      if (PHASE == 0) y[0] = (double)pay;
+      if (PHASE == 1) y[0] = (double)pay;
+    } else {
+      term = (R)A.ckpt[(size_t)(2 * A.n_ckpt) * np + pid];
+    }
+    if (PHASE != 1) {
+      // Reverse sweep. xb = dP/d(ln S_i), vb = dP/dv_i, natural-log units,
+      // accumulated in FP64: under a violated Feller condition the factor
+      // dv_{i+1}/dv_i = 1 - kappa dt + xi Z1 dt / (2 sqrt(v dt)) can reach
+      // 10^3 near v = 0, and products of such factors overflow FP32.
+      const bool itm = S0 * term > K;
+      // Asian: dP/d(ln S_i) = disc 1{A>K} S_i / n = abar * (S_i/S0).
+      const double abar = (ASIAN && itm) ? (double)(disc * S0 * inv_n) : 0.0;
+      double xb = (!ASIAN && itm) ? (double)(disc * S0 * term) : 0.0;
+      double vb = 0.0;
+      const R dt = hs.dt, half_dt = R(0.5) * hs.dt, kdt = hs.kdt, xi = hs.xi;
+      const uint32_t n_seg = (n + every - 1) / every;
+      for (int seg = (int)n_seg - 1; seg >= 0; --seg) {
+        const uint32_t i0 = (uint32_t)seg * every;
+        const uint32_t len = min(every, n - i0);
+        // The checkpoint holds the FP32 state exactly, so the recomputed
+        // segment reproduces the forward sweep bit for bit.
+        R z = ck_load(2 * seg);
+        R v = ck_load(2 * seg + 1);
+        R vs[kCkptMax], z1s[kCkptMax], zss[kCkptMax], Es[kCkptMax];
+#pragma unroll
+        for (int q = 0; q < kCkptMax; q += 2) {
+          if ((uint32_t)q < len) {
+            const Normals4<R> nz = normals4<R>(philox((i0 + (uint32_t)q) >> 1, pc));
+            vs[q] = v;
+            z1s[q] = nz.z[0];
+            hs.step(z, v, nz.z[0], nz.z[1], zss[q]);
+            Es[q] = HDom<R>::exp_(z);
+            if ((uint32_t)q + 1 < len) {
+              vs[q + 1] = v;
+              z1s[q + 1] = nz.z[2];
+              hs.step(z, v, nz.z[2], nz.z[3], zss[q + 1]);
+              Es[q + 1] = HDom<R>::exp_(z);
             }
           }
         }
-        term = ASIAN ? sumE * inv_n : HDom<R>::exp_(z);
-        if (PHASE == 1) A.ckpt[(size_t)(2 * A.n_ckpt) * np + pid] = (float)term;
-        const R pay = disc * posv(S0 * term - K);
-        if (PHASE == 0) y[0] = (double)pay;
-        if (PHASE == 1) y[0] = (double)pay;
-      } else {
-        term = (R)A.ckpt[(size_t)(2 * A.n_ckpt) * np + pid];
-      }
-      if (PHASE != 1) {
-        // Reverse sweep. xb = dP/d(ln S_i), vb = dP/dv_i, natural-log units,
-        // accumulated in FP64: under a violated Feller condition the factor
-        // dv_{i+1}/dv_i = 1 - kappa dt + xi Z1 dt / (2 sqrt(v dt)) can reach
-        // 10^3 near v = 0, and products of such factors overflow FP32.
-        const bool itm = S0 * term > K;
-        // Asian: dP/d(ln S_i) = disc 1{A>K} S_i / n = abar * (S_i/S0).
-        const double abar = (ASIAN && itm) ? (double)(disc * S0 * inv_n) : 0.0;
-        double xb = (!ASIAN && itm) ? (double)(disc * S0 * term) : 0.0;
-        double vb = 0.0;
-        const R dt = hs.dt, half_dt = R(0.5) * hs.dt, kdt = hs.kdt, xi = hs.xi;
-        const uint32_t n_seg = (n + every - 1) / every;
-        for (int seg = (int)n_seg - 1; seg >= 0; --seg) {
-          const uint32_t i0 = (uint32_t)seg * every;
-          const uint32_t len = min(every, n - i0);
-          // The checkpoint holds the FP32 state exactly, so the recomputed
-          // segment reproduces the forward sweep bit for bit.
-          R z = ck_load(2 * seg);
-          R v = ck_load(2 * seg + 1);
-          R vs[kCkptMax], z1s[kCkptMax], zss[kCkptMax], Es[kCkptMax];
 #pragma unroll
-          for (int q = 0; q < kCkptMax; q += 2) {
-            if ((uint32_t)q < len) {
-              const Normals4<R> nz = normals4<R>(philox((i0 + (uint32_t)q) >> 1, pc));
-              vs[q] = v;
-              z1s[q] = nz.z[0];
-              hs.step(z, v, nz.z[0], nz.z[1], zss[q]);
-              Es[q] = HDom<R>::exp_(z);
-              if ((uint32_t)q + 1 < len) {
-                vs[q + 1] = v;
-                z1s[q + 1] = nz.z[2];
-                hs.step(z, v, nz.z[2], nz.z[3], zss[q + 1]);
-                Es[q + 1] = HDom<R>::exp_(z);
-              }
-            }
-          }
-#pragma unroll
-          for (int q = kCkptMax - 1; q >= 0; --q) {
-            if ((uint32_t)q < len) {
-              if (ASIAN) xb += abar * (double)Es[q];   // S_{i+1} enters the average
-              const R vq = vs[q];
-              if (vq > R(0)) {
-                const R g = half_dt * HDom<R>::rsqrt_(vq * dt);   // d sqrt(v dt) / dv
-                const double dxdv = (double)(-half_dt + zss[q] * g);
-                const double dvdv = (double)((R(1) - kdt) + xi * z1s[q] * g);
-                vb = xb * dxdv + vb * dvdv;
-              }
+        for (int q = kCkptMax - 1; q >= 0; --q) {
+          if ((uint32_t)q < len) {
+            if (ASIAN) xb += abar * (double)Es[q];   // S_{i+1} enters the average
+            const R vq = vs[q];
+            if (vq > R(0)) {
+              const R g = half_dt * HDom<R>::rsqrt_(vq * dt);   // d sqrt(v dt) / dv
+              const double dxdv = (double)(-half_dt + zss[q] * g);
+              const double dvdv = (double)((R(1) - kdt) + xi * z1s[q] * g);
+              vb = xb * dxdv + vb * dvdv;
             }
           }
         }
-        const int c0 = PHASE == 0 ? 1 : 0;
-        y[c0] = xb / (double)P.S0;   // d/dS0 through ln S0
-        y[c0 + 1] = vb;              // d/dv0
       }
+      const int c0 = PHASE == 0 ? 1 : 0;
+      y[c0] = xb / (double)P.S0;   // d/dS0 through ln S0
+      y[c0 + 1] = vb;              // d/dv0
     }
-    bool finite = true;
-#pragma unroll
-    for (int c = 0; c < C; ++c) finite = finite && isfinite(y[c]);
-    if (P.path_out != nullptr) {
-#pragma unroll
-      for (int c = 0; c < C; ++c) P.path_out[pid * C + c] = y[c];
-    }
-    acc.push(y, finite, !finite);
   }
-  block_reduce_moments<C, kBlock>(acc, P.partials, blockIdx.x);
+  bool finite = true;
+#pragma unroll
+  for (int c = 0; c < C; ++c) finite = finite && isfinite(y[c]);
+  if (active && P.path_out != nullptr) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) P.path_out[pid * C + c] = y[c];
+  }
+  block_moments<C, kBlock>(y, active && finite, active && !finite, P.partials);
 }
 
 }  // namespace
@@ -368,8 +366,10 @@ static hipError_t adj_one(const AdjointParams& a, hipStream_t s, uint32_t nb) {
   return hipGetLastError();
 }
 
+// One path per thread: the sweep's registers leave no room for moment
+// accumulators across paths at this occupancy.
 hipError_t launch_heston_adjoint(const AdjointParams& a, hipStream_t s, uint32_t* n_blocks) {
-  const uint32_t nb = heston_blocks(a.h.n_paths);
+  const uint32_t nb = (uint32_t)((a.h.n_paths + kBlock - 1) / kBlock);
   *n_blocks = nb;
   if (a.every < 2 || a.every > (uint32_t)kCkptMax || (a.every & 1u) ||
       a.n_ckpt != (a.h.n_steps + a.every - 1) / a.every)

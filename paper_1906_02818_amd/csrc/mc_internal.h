@@ -234,7 +234,7 @@ struct CvParams {
   const double* ybar_mom;    // moments of the forward pass (Ybar = sum y2 / n)
   const double* y_path;      // per-path values of that pass, [n_paths][3] (Y is channel 2)
   double g_scale;            // -2 / B
-  double* grad_partials;     // [kMlpNParam][n_blocks] FP64
+  double* grad_partials;     // [n_blocks][kMlpNParam] FP64
   double* partials;
   double* path_out;
   // Feature cache of the training paths, one entry per hedge segment k (the
@@ -249,9 +249,6 @@ struct CvParams {
   uint32_t n_seg;            // ceil(n_steps / hedge_every)
 };
 constexpr int kCvPathsPerBlock = 256;       // evaluation: 4 waves of 64 paths
-// Evaluation grid: persistent, at most four workgroups per CU of the
-// 256-CU part (its occupancy), each taking every gridDim-th 256-path tile.
-constexpr uint32_t kCvEvalMaxBlocks = 1024;
 constexpr int kCvTrainPathsPerBlock = 128;  // training: 4 waves of 32 paths
 // Fragment layout of the weights, built on the device from theta.
 constexpr int kW1fFloats = 2 * 64 * 8, kW2fFloats = 2 * 4 * 64 * 8, kLanecFloats = 2 * 64 * 32;
@@ -265,12 +262,15 @@ hipError_t launch_cv_cache(const CvParams& p, hipStream_t s);
 hipError_t launch_cv_forward(const CvParams& p, hipStream_t s);
 hipError_t launch_cv_values(const CvParams& p, hipStream_t s, uint32_t* n_blocks);
 hipError_t launch_cv_backward(const CvParams& p, hipStream_t s, uint32_t* n_blocks);
-// Reduces the per-block gradient partials [kMlpNParam][n_blocks], takes one
-// Adam step and refreshes the packed fragments, in one launch.
+// Reduces the per-block gradient partials [n_blocks][kMlpNParam], takes one
+// Adam step and refreshes the packed fragments, in one launch; or only
+// reduces them into grad (the same fixed order).
 hipError_t launch_adam_pack(const double* partials, uint32_t n_blocks, double* grad, float* theta,
                             float* m, float* v, int t, double lr, double b1, double b2,
                             double eps, float* w1f, float* w2f, float* w2tf, float* lanec,
                             hipStream_t s);
+hipError_t launch_grad_sum(const double* partials, uint32_t n_blocks, double* grad,
+                           hipStream_t s);
 
 // ---- reductions and diagnostics ----
 // Moment vectors of C channels (1..kMaxMomentChannels): n_batch independent

@@ -1,7 +1,9 @@
 // Issue-rate microbenchmark for the VALU instructions the path kernels are
 // made of: the 32x32->64 integer product of Philox (v_mad_u64_u32, or the
 // v_mul_hi_u32 / v_mul_lo_u32 pair), 32-bit xor, FP32 and FP64 FMA, and the
-// transcendental unit (v_exp/log/sin/sqrt/rcp_f32). Each chain step is ONE
+// transcendental unit (v_exp/log/sin/sqrt/rcp_f32), and the half-precision
+// forms a cheaper activation would be built from (v_pk_fma_f16, two FMAs per
+// lane; v_exp_f16, v_rcp_f16; v_cvt_pkrtz_f16_f32). Each chain step is ONE
 // instruction of the measured kind (sign and absolute value are free source
 // modifiers), each thread runs 8 independent chains and every SIMD holds 8
 // waves, so latency is hidden. Output: wave64 instructions per clock per CU
@@ -13,6 +15,9 @@
 
 #include <cstdio>
 #include <cstdlib>
+
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+extern "C" __device__ _Float16 __ocml_exp2_f16(_Float16);
 
 #define CHECK(x)                                                              \
   do {                                                                        \
@@ -26,7 +31,7 @@
 constexpr int kIters = 2048;
 constexpr int kChains = 8;
 
-enum Op { FMA_F32, FMAC_F32, FMA_INL, BITOP3, EXP_3FMA, MAD_U64, MUL_HI, MUL_LO, XOR, EXP_F32, LOG_F32, SIN_F32, SQRT_F32, RCP_F32, FMA_F64 };
+enum Op { FMA_F32, FMAC_F32, FMA_INL, BITOP3, EXP_3FMA, MAD_U64, MUL_HI, MUL_LO, XOR, EXP_F32, LOG_F32, SIN_F32, SQRT_F32, RCP_F32, FMA_F64, PK_FMA_F16, EXP_F16, RCP_F16, CVT_PKRTZ };
 
 template <int OP>
 __global__ __launch_bounds__(256) void rate_kernel(unsigned* out, unsigned seed, float kmul) {
@@ -44,6 +49,9 @@ __global__ __launch_bounds__(256) void rate_kernel(unsigned* out, unsigned seed,
   float g[kChains];                     // second FP32 chain of the overlap probe
 #pragma unroll
   for (int c = 0; c < kChains; ++c) g[c] = 0.25f + 0.01f * c;
+  h2 hv[kChains];                       // half-precision chains
+#pragma unroll
+  for (int c = 0; c < kChains; ++c) hv[c] = (h2){(_Float16)(0.5f + 0.01f * c), (_Float16)0.25f};
   unsigned f_bits[kChains];             // per-chain third operand (VGPR, loop invariant)
 #pragma unroll
   for (int c = 0; c < kChains; ++c) f_bits[c] = t * 0x85EBCA6Bu + 31u * c;
@@ -86,6 +94,17 @@ __global__ __launch_bounds__(256) void rate_kernel(unsigned* out, unsigned seed,
         f[c] = __builtin_amdgcn_rcpf(f[c]);
       } else if constexpr (OP == FMA_F64) {
         d[c] = __builtin_fma(d[c], 0.999, 1e-3);
+      } else if constexpr (OP == PK_FMA_F16) {
+        hv[c] = __builtin_elementwise_fma(hv[c], (h2){(_Float16)-0.5f, (_Float16)-0.5f},
+                                          (h2){(_Float16)2.0f, (_Float16)2.0f});
+      } else if constexpr (OP == EXP_F16) {
+        hv[c].x = __ocml_exp2_f16(-hv[c].x);                 // v_exp_f16
+      } else if constexpr (OP == RCP_F16) {
+        hv[c].x = __builtin_amdgcn_rcph(hv[c].x + (_Float16)1.0f);
+      } else if constexpr (OP == CVT_PKRTZ) {
+        const auto p = __builtin_amdgcn_cvt_pkrtz(f[c], f[c] + 1.0f);
+        __builtin_memcpy(&hv[c], &p, 4);
+        f[c] = (float)hv[c].x;
       }
     }
   }
@@ -93,7 +112,7 @@ __global__ __launch_bounds__(256) void rate_kernel(unsigned* out, unsigned seed,
 #pragma unroll
   for (int c = 0; c < kChains; ++c)
     acc ^= a[c] ^ __float_as_uint(f[c]) ^ (unsigned)__double_as_longlong(d[c]) ^
-           __float_as_uint(g[c]);
+           __float_as_uint(g[c]) ^ __builtin_bit_cast(unsigned, hv[c]);
   out[t] = acc;
 }
 
@@ -143,6 +162,10 @@ int main() {
       {"v_sqrt_f32", run<SQRT_F32>(d_out, blocks, threads, e0, e1), 0.0},
       {"v_rcp_f32", run<RCP_F32>(d_out, blocks, threads, e0, e1), 0.0},
       {"v_fma_f64", run<FMA_F64>(d_out, blocks, threads, e0, e1), 0.0},
+      {"v_pk_fma_f16 (2 FMA/lane)", run<PK_FMA_F16>(d_out, blocks, threads, e0, e1), 0.0},
+      {"v_exp_f16", run<EXP_F16>(d_out, blocks, threads, e0, e1), 0.0},
+      {"v_rcp_f16 (+ v_add_f16)", run<RCP_F16>(d_out, blocks, threads, e0, e1), 1.0},
+      {"v_cvt_pkrtz_f16_f32 (+cvt)", run<CVT_PKRTZ>(d_out, blocks, threads, e0, e1), 2.0},
   };
   // "spec slots": issue time in units of one wave64 FMA at the FP32 vector
   // peak (128 FMA lanes per clock per CU = 2 wave64 FMAs per clock per CU).

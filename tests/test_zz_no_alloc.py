@@ -92,11 +92,17 @@ def test_noalloc_twice_in_a_row_without_mc_price_between(ctx):
 def test_noalloc_scratch_size_and_errors(ctx):
     assert mc.mc_noalloc_scratch_bytes() == 4 << 20
     f = mc.Payoff(mc.MC_ASIAN_ARITH_CALL, 100.0)
-    # The path kernels run on persistent grids, so the moments of any path
-    # count fit the scratch: 2^24 Heston paths with tangents.
+    # The GBM and Heston price and tangent kernels run on persistent grids,
+    # so the moments of any path count fit the scratch: 2^24 Heston paths
+    # with tangents.
     o = mc.Options(greeks=3, greeks_method=mc.MC_GREEKS_TANGENT)
     same(mc.mc_price_noalloc(ctx, heston(), f, 1 << 24, 16, SEED, o),
          mc.mc_price(ctx, heston(), f, 1 << 24, 16, SEED, o))
+    # The adjoint takes one path per thread: at 2^24 paths its 65536 block
+    # moment vectors exceed the scratch, refused before any launch.
+    with pytest.raises(mc.McError) as e:
+        mc.mc_price_noalloc(ctx, heston(), f, 1 << 24, 16, SEED, mc.Options(greeks=3))
+    assert e.value.status == mc.MC_ERR_WORKSPACE
     bad = [
         (heston(), f, mc.Options(greeks=3), 300),          # 19 adjoint checkpoints
         (heston(), f, mc.Options(path_values=True), 16),
