@@ -952,8 +952,10 @@ mc_status cv_loss_grad_device(mc_context* ctx, hipStream_t s, const mc_model* m,
   uint32_t nb = 0;
   HIP_TRY(ctx, launch_cv_forward(p, s));
   HIP_TRY(ctx, launch_cv_values(p, s, &nb));
-  HIP_TRY(ctx, launch_final_merge(partials, nb, 3, 1, mom, s));
+  // The backward merges the hedged values' block moments itself (Ybar) and
+  // its block 0 stores them in mom.
   p.path_out = nullptr;
+  p.val_blocks = nb;
   p.ybar_mom = mom;
   p.y_path = ypath;
   p.g_scale = -2.0 / (double)batch;

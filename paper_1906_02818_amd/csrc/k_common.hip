@@ -34,22 +34,23 @@ __global__ __launch_bounds__(256) void final_reduce_kernel(const double* __restr
 }
 
 // Moment vectors of C channels (count, means, co-moments): one workgroup of
-// kMergeThreads per batch b = blockIdx.x merges the block-major partials
-// [b][n_blocks][M] into out[b][M]: thread t adds blocks t, t + kMergeThreads,
-// ... in order (about a shift, no division), then the block reduction of the
-// path kernels.
-constexpr int kMergeThreads = 256;
+// NT threads per batch b = blockIdx.x merges the block-major partials
+// [b][n_blocks][M] into out[b][M]: thread t adds blocks t, t + NT, ... in
+// order (about a shift, no division), then the block reduction of the path
+// kernels.
+template <int C>
+constexpr int merge_threads() { return 256; }
 
 template <int C>
-__global__ __launch_bounds__(kMergeThreads) void final_merge_kernel(
+__global__ __launch_bounds__(merge_threads<C>()) void final_merge_kernel(
     const double* __restrict__ partials, uint32_t n_blocks, double* __restrict__ out) {
-  constexpr int M = PartSums<C>::M;
+  constexpr int M = PartSums<C>::M, NT = merge_threads<C>();
   partials += (size_t)blockIdx.x * n_blocks * M;
   PartSums<C> m;
   m.zero();
-  for (uint32_t i = threadIdx.x; i < n_blocks; i += kMergeThreads)
-    m.add_vector(partials + (size_t)i * M);
-  block_reduce<C, kMergeThreads>(m, out, blockIdx.x);
+#pragma unroll 4
+  for (uint32_t i = threadIdx.x; i < n_blocks; i += NT) m.add_vector(partials + (size_t)i * M);
+  block_reduce<C, NT>(m, out, blockIdx.x);
 }
 
 __global__ void philox_words_kernel(uint32_t k0, uint32_t k1, uint32_t tag, uint64_t n,
@@ -136,8 +137,8 @@ hipError_t launch_diff_moments(const double* a, uint32_t Ca, uint32_t ca, const 
 template <int C>
 static hipError_t merge_one(const double* partials, uint32_t n_blocks, uint32_t n_batch,
                             double* out, hipStream_t s) {
-  hipLaunchKernelGGL(final_merge_kernel<C>, dim3(n_batch), dim3(kMergeThreads), 0, s, partials,
-                     n_blocks, out);
+  hipLaunchKernelGGL(final_merge_kernel<C>, dim3(n_batch), dim3(merge_threads<C>()), 0, s,
+                     partials, n_blocks, out);
   return hipGetLastError();
 }
 

@@ -417,6 +417,19 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
   constexpr size_t kLds = 2 * kFragFloats * sizeof(FT) + kLaneFloats * 4 + kCvWaves * kTr * sizeof(FT);
   static_assert(kLds >= kMlpNParam * sizeof(double), "LDS too small for the gradient sum");
   __shared__ __attribute__((aligned(16))) unsigned char lds[kLds];
+  // Ybar: every block merges the hedged-value kernel's block moments itself
+  // (the same fixed-order merge, so every block gets the same value); block
+  // 0 also stores the merged vector (the minibatch's loss).
+  __shared__ double ymom[PartSums<3>::M];
+  {
+    PartSums<3> pm;
+    pm.zero();
+    for (uint32_t i = threadIdx.x; i < P.val_blocks; i += kCvThreads)
+      pm.add_vector(P.partials + (size_t)i * PartSums<3>::M);
+    block_reduce<3, kCvThreads>(pm, ymom, 0);
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x < PartSums<3>::M) P.ybar_mom[threadIdx.x] = ymom[threadIdx.x];
+  }
   FT* s_w2f = (FT*)lds;
   FT* s_w2tf = s_w2f + kFragFloats;
   float* s_lanec = (float*)(lds + 2 * kFragFloats * sizeof(FT));
@@ -445,7 +458,7 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
 
   float g = 0.f;                       // upstream factor of this path
   if (active) {
-    const double ybar = P.ybar_mom[2 + 2];   // mean of channel 2 (Y)
+    const double ybar = ymom[2 + 2];   // mean of channel 2 (Y)
     g = (float)(P.g_scale * (P.y_path[pid * 3 + 2] - ybar));
   }
   f32x16 gw2[2][2], gx[2];
@@ -762,7 +775,7 @@ __device__ __forceinline__ void slot_of(int u, int& mb, int& r, int& h) {
 // the parameter (W1, b1: one; W2: one in each of the two layouts; b2, W3:
 // the 32 lanes of a half-wave). Padding slots keep the zeros of the first
 // pack; b3 lives in theta only.
-constexpr int kGradCols = 32, kGradSlices = 256 / kGradCols;
+constexpr int kGradCols = 16, kGradSlices = 256 / kGradCols;
 
 template <bool ADAM>
 __global__ __launch_bounds__(256) void grad_adam_kernel(
@@ -776,9 +789,11 @@ __global__ __launch_bounds__(256) void grad_adam_kernel(
   const int p0 = blockIdx.x * kGradCols;
   const int i = p0 + col;
   double s = 0.0;
-  if (i < kMlpNParam)
+  if (i < kMlpNParam) {
+#pragma unroll 8
     for (uint32_t k = slice; k < n_blocks; k += kGradSlices)
       s += partials[(size_t)k * kMlpNParam + i];
+  }
   sh[slice][col] = s;
   __syncthreads();
   if (slice == 0 && i < kMlpNParam) {

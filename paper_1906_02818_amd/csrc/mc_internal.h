@@ -231,7 +231,9 @@ struct CvParams {
   const float* lanec;        // [2][64][32]: per-lane b2 * (-2 / ln 2), W3 of the lane's units
   const float* dfac;         // [n_steps + 1]: e^{r t_i}
   // training
-  const double* ybar_mom;    // moments of the forward pass (Ybar = sum y2 / n)
+  double* ybar_mom;          // out: merged moments of the hedged values (block 0 writes)
+  uint32_t val_blocks;       // blocks of the hedged-value kernel whose partials the
+                             // backward merges (in `partials`) for Ybar
   const double* y_path;      // per-path values of that pass, [n_paths][3] (Y is channel 2)
   double g_scale;            // -2 / B
   double* grad_partials;     // [n_blocks][kMlpNParam] FP64
