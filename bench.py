@@ -282,9 +282,18 @@ def _alu_roofline(slots_per_unit, units, kernel_ms, kernel):
 
 
 def _repeat(args, torch, fn):
+    """W warm-up steps, continued (up to 200 more) until 0.25 s have passed:
+    the GPU's clocks ramp up over the first few tens of ms of work, and the
+    timed steps are meant to run at steady clocks. Then the timed steps."""
+    t0 = time.perf_counter()
     for _ in range(args.warmup):
         fn()
     torch.cuda.synchronize()
+    extra = 0
+    while args.warmup > 0 and time.perf_counter() - t0 < 0.25 and extra < 200:
+        fn()
+        torch.cuda.synchronize()
+        extra += 1
     outs = []
     t0 = time.perf_counter()
     for _ in range(args.steps):

@@ -141,6 +141,14 @@ __device__ __forceinline__ void wave_lds_sync() {
 constexpr int kFragFloats = 2 * 4 * 64 * 8;   // one set of layer-2 fragments
 constexpr int kLaneFloats = 2 * 64 * 32;      // per-lane b2 (scaled) and W3
 
+// Per-lane constants (b2 scaled, then W3): 32 values per lane, one per unit
+// slot q = 16 mb + r, stored as [q / 4][lane][q mod 4] so that the four
+// consecutive slots a lane reads at once sit beside those of its neighbours
+// (a wave's 16-byte reads cover 1 KB contiguously, free of bank conflicts).
+__device__ __forceinline__ int lanec_index(int lane, int q) {
+  return (q >> 2) * 256 + lane * 4 + (q & 3);
+}
+
 // Forward pass of the hedge network for the wave's 32 paths. phi: the
 // lane's B fragment of layer 1 (half 0: features and the constant 1; half
 // 1: zeros). Returns Delta (identical in both halves); keeps h1, h2.
@@ -185,9 +193,9 @@ __device__ __forceinline__ float mlp_forward(const float (&phi)[8], const Op8<BF
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int idx = mb * 16 + r;
-      const float v = tanh_b(d2[mb][r], lanec[lane * 32 + idx]);
+      const float v = tanh_b(d2[mb][r], lanec[lanec_index(lane, idx)]);
       h2[idx] = v;
-      part = __builtin_fmaf(lanec[64 * 32 + lane * 32 + idx], v, part);
+      part = __builtin_fmaf(lanec[64 * 32 + lanec_index(lane, idx)], v, part);
     }
   return part + __shfl_xor(part, 32, 64) + b3;
 }
@@ -275,8 +283,8 @@ __device__ __forceinline__ float mlp_delta(const float (&phi)[8], const Op8<BF16
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int idx = mb * 16 + r;
-      const float v = tanh_b(d2[mb][r], lanec[lane * 32 + idx]);
-      part = __builtin_fmaf(lanec[64 * 32 + lane * 32 + idx], v, part);
+      const float v = tanh_b(d2[mb][r], lanec[lanec_index(lane, idx)]);
+      part = __builtin_fmaf(lanec[64 * 32 + lanec_index(lane, idx)], v, part);
     }
   return part + __shfl_xor(part, 32, 64) + b3;
 }
@@ -413,7 +421,11 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
   using FT = FragT<BF16>;
   // One LDS area: the weight fragments and the waves' transpose regions,
   // reused after the segment loop for the block's gradient sum.
-  constexpr int kTr = 64 * 32 + 8 * 32;
+  // Rows of kTs elements (32 paths plus padding, so that neither the
+  // lanes' 2-byte stores of a unit nor the 16-byte fragment reads of
+  // consecutive units fall on one bank group).
+  constexpr int kTs = BF16 ? 40 : 36;
+  constexpr int kTr = 64 * kTs + 8 * kTs;
   constexpr size_t kLds = 2 * kFragFloats * sizeof(FT) + kLaneFloats * 4 + kCvWaves * kTr * sizeof(FT);
   static_assert(kLds >= kMlpNParam * sizeof(double), "LDS too small for the gradient sum");
   __shared__ __attribute__((aligned(16))) unsigned char lds[kLds];
@@ -472,17 +484,17 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) gw2[a][b][r] = 0.f;
   }
-  FT* T = tr + wave * kTr;   // [64 units][32 paths]
-  FT* TP = T + 64 * 32;      // [8 columns][32 paths]
+  FT* T = tr + wave * kTr;   // [64 units][32 paths], row stride kTs
+  FT* TP = T + 64 * kTs;     // [8 columns][32 paths], row stride kTs
   // Unit-major A fragments of the region T (32 units of block mb x 8 paths).
   auto a_frag = [&](int pk, int mb) {
-    return op_lds<BF16>(&T[(32 * mb + row) * 32 + 16 * pk + 8 * half]);
+    return op_lds<BF16>(&T[(32 * mb + row) * kTs + 16 * pk + 8 * half]);
   };
   auto to_T = [&](const float (&x)[32]) {
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) T[unit_of(mb, r, half) * 32 + row] = (FT)x[mb * 16 + r];
+      for (int r = 0; r < 16; ++r) T[unit_of(mb, r, half) * kTs + row] = (FT)x[mb * 16 + r];
   };
 
   // The steps are ordered so that few path-major vectors are live at once.
@@ -498,11 +510,11 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
     if (half == 0) gb3 += gD;
     // dW3 (column 1 of gx) += H2^T gD.
     to_T(h2);
-    if (half == 0) TP[1 * 32 + row] = (FT)gD;
+    if (half == 0) TP[1 * kTs + row] = (FT)gD;
     wave_lds_sync();
 #pragma unroll
     for (int pk = 0; pk < 2; ++pk) {
-      const Op8<BF16> b = row == 1 ? op_lds<BF16>(&TP[1 * 32 + 16 * pk + 8 * half])
+      const Op8<BF16> b = row == 1 ? op_lds<BF16>(&TP[1 * kTs + 16 * pk + 8 * half])
                                    : op_zero<BF16>();
 #pragma unroll
       for (int mb = 0; mb < 2; ++mb) mma16<BF16>(gx[mb], a_frag(pk, mb), b);
@@ -513,7 +525,7 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
     float d2v[32];
 #pragma unroll
     for (int q = 0; q < 32; ++q)
-      d2v[q] = gD * s_lanec[64 * 32 + lane * 32 + q] * (1.0f - h2[q] * h2[q]);
+      d2v[q] = gD * s_lanec[64 * 32 + lanec_index(lane, q)] * (1.0f - h2[q] * h2[q]);
     to_T(d2v);
     wave_lds_sync();
     Op8<BF16> A2[2][2];
@@ -538,7 +550,7 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
     for (int pk = 0; pk < 2; ++pk)
 #pragma unroll
       for (int nb = 0; nb < 2; ++nb) {
-        const Op8<BF16> b = op_lds<BF16>(&T[(32 * nb + row) * 32 + 16 * pk + 8 * half]);
+        const Op8<BF16> b = op_lds<BF16>(&T[(32 * nb + row) * kTs + 16 * pk + 8 * half]);
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb) mma16<BF16>(gw2[mb][nb], A2[pk][mb], b);
       }
@@ -575,14 +587,14 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
       const uint64_t S = P.c_stride, c = P.c_first + pid;
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        TP[(2 + q) * 32 + row] = active ? (FT)P.c_phi[((size_t)k * 4 + q) * S + c] : (FT)0.f;
-      TP[6 * 32 + row] = active ? (FT)1.0f : (FT)0.f;
+        TP[(2 + q) * kTs + row] = active ? (FT)P.c_phi[((size_t)k * 4 + q) * S + c] : (FT)0.f;
+      TP[6 * kTs + row] = active ? (FT)1.0f : (FT)0.f;
     }
     wave_lds_sync();
 #pragma unroll
     for (int pk = 0; pk < 2; ++pk) {
       const Op8<BF16> b = (row >= 2 && row <= 6)
-                              ? op_lds<BF16>(&TP[row * 32 + 16 * pk + 8 * half])
+                              ? op_lds<BF16>(&TP[row * kTs + 16 * pk + 8 * half])
                               : op_zero<BF16>();
 #pragma unroll
       for (int mb = 0; mb < 2; ++mb) mma16<BF16>(gx[mb], a_frag(pk, mb), b);
@@ -630,8 +642,8 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
     P.grad_partials[(uint64_t)blockIdx.x * kMlpNParam + i] = red[i];
 }
 
-// The BF16 form fits two waves per SIMD (256 VGPRs, LDS for three
-// workgroups); the FP32 form's LDS allows one workgroup per CU.
+// The BF16 form fits two waves per SIMD (256 VGPRs; 55 KB of LDS, two
+// workgroups per CU); the FP32 form's 95 KB allow one workgroup per CU.
 __global__ __launch_bounds__(kCvThreads) __attribute__((amdgpu_waves_per_eu(2))) void
 cv_bwd_kernel_bf16(const CvParams P) {
   cv_bwd_body<true>(P);
@@ -749,7 +761,7 @@ __global__ void cv_pack_kernel(const float* __restrict__ th, float* __restrict__
     w2tf[t] = W2[k_unit * 64 + (32 * mb + row)];
   }
   if (t < kLanecFloats / 2) {
-    const int q = t & 31, lane = t >> 5;
+    const int q = ((t >> 8) << 2) | (t & 3), lane = (t >> 2) & 63;   // t = lanec_index(lane, q)
     const int h = lane >> 5, mb = q >> 4, r = q & 15;
     const int u = unit_of(mb, r, h);
     lanec[t] = b2[u] * kNeg2Log2e;
@@ -839,7 +851,7 @@ __global__ __launch_bounds__(256) void grad_adam_kernel(
       const int u = is_b2 ? ip - 4416 : ip - 4480;
       int mb, r, h;
       slot_of(u, mb, r, h);
-      const int dst = (32 * h + L) * 32 + 16 * mb + r;
+      const int dst = lanec_index(32 * h + L, 16 * mb + r);
       if (is_b2)
         lanec[dst] = t * kNeg2Log2e;
       else
