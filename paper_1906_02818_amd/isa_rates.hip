@@ -9,6 +9,11 @@
 // waves, so latency is hidden. Output: wave64 instructions per clock per CU
 // and the issue cost in units of a wave64 FMA at the FP32 vector peak
 // ("spec slots"), from which the path kernels' ALU roofline is derived.
+// A second table asks whether matrix-core work overlaps vector work on one
+// SIMD: the same number of v_mfma_f32_32x32x16_bf16 and of independent
+// v_fma_f32 run alone, interleaved in every wave, and split between waves
+// (even waves matrix, odd waves vector); overlap shows as a mixed time near
+// the larger of the two alone, serialisation as one near their sum.
 //   hipcc --offload-arch=gfx950 -O3 isa_rates.hip -o isa_rates && ./isa_rates
 // Memory: one store per thread into a buffer of exactly grid x block words.
 #include <hip/hip_runtime.h>
@@ -131,6 +136,80 @@ double run(unsigned* d_out, int blocks, int threads, hipEvent_t e0, hipEvent_t e
   return ms / 5.0;
 }
 
+// Matrix/vector overlap probe. MODE 0: one MFMA per iteration (four
+// accumulators in rotation, no back-to-back dependence); MODE 1: kMixFma
+// independent FMAs per iteration; MODE 2: both in every wave; MODE 3: even
+// waves run MODE 0, odd waves MODE 1 (twice the iterations each, so that
+// every SIMD issues the same totals as in MODE 2). MODES 4 and 5 repeat 0
+// and 2 with the accumulators in the accumulation registers (AGPRs) rather
+// than the vector registers (an empty asm statement that names an AGPR
+// makes the compiler choose that MFMA form).
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8_t;
+typedef __attribute__((ext_vector_type(16))) float f32x16_t;
+constexpr int kMixIters = 4096, kMixFma = 16;
+
+template <int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void mix_kernel(
+    unsigned* out, float seed) {
+  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int wave = threadIdx.x >> 6;
+  bf16x8_t a, b;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    a[j] = (__bf16)(1e-3f * (float)((t + j) & 7));
+    b[j] = (__bf16)(1e-3f * (float)((t * 3 + j) & 7));
+  }
+  f32x16_t acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[q][r] = 0.f;
+  float f[kMixFma];
+#pragma unroll
+  for (int c = 0; c < kMixFma; ++c) f[c] = seed + 0.01f * c + 1e-7f * (float)(t & 255);
+  if constexpr (MODE >= 4) {
+    float zz = seed;
+    __asm__ volatile("; accumulation register in use: %0" : "+a"(zz));
+    f[0] += zz;
+  }
+  const bool do_m = MODE == 0 || MODE == 2 || MODE >= 4 || (MODE == 3 && (wave & 1) == 0);
+  const bool do_v = MODE == 1 || MODE == 2 || MODE == 5 || (MODE == 3 && (wave & 1) == 1);
+  const int iters = MODE == 3 ? 2 * kMixIters : kMixIters;
+  for (int it = 0; it < iters; it += 4) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (do_m) acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[q], 0, 0, 0);
+      if (do_v) {
+#pragma unroll
+        for (int c = 0; c < kMixFma; ++c) f[c] = __builtin_fmaf(f[c], -0.5f, 2.0f);
+      }
+    }
+  }
+  unsigned x = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) x ^= __float_as_uint(acc[q][r]);
+#pragma unroll
+  for (int c = 0; c < kMixFma; ++c) x ^= __float_as_uint(f[c]);
+  out[t] = x;
+}
+
+template <int MODE>
+double run_mix(unsigned* d_out, int blocks, int threads, hipEvent_t e0, hipEvent_t e1) {
+  hipLaunchKernelGGL(mix_kernel<MODE>, dim3(blocks), dim3(threads), 0, 0, d_out, 0.5f);
+  CHECK(hipGetLastError());
+  CHECK(hipDeviceSynchronize());
+  CHECK(hipEventRecord(e0, 0));
+  for (int r = 0; r < 5; ++r)
+    hipLaunchKernelGGL(mix_kernel<MODE>, dim3(blocks), dim3(threads), 0, 0, d_out, 0.5f + r);
+  CHECK(hipEventRecord(e1, 0));
+  CHECK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  CHECK(hipEventElapsedTime(&ms, e0, e1));
+  return ms / 5.0;
+}
+
 int main() {
   hipDeviceProp_t prop;
   CHECK(hipGetDeviceProperties(&prop, 0));
@@ -175,6 +254,33 @@ int main() {
   for (const Row& r : rows) {
     const double rate = steps / (r.ms * 1e-3 * clk_ghz * 1e9) / cus;   // chain steps
     std::printf("%-28s %10.4f %18.4f %12.3f\n", r.name, r.ms, rate, 2.0 / rate);
+  }
+  // Overlap probe: 4 waves per SIMD (16 per CU), each SIMD issuing
+  // 4 x kMixIters MFMAs and 4 x kMixIters x kMixFma FMAs in modes 2 and 3.
+  {
+    const int mblocks = cus * 4;
+    const double m_only = run_mix<0>(d_out, mblocks, threads, e0, e1);
+    const double v_only = run_mix<1>(d_out, mblocks, threads, e0, e1);
+    const double both = run_mix<2>(d_out, mblocks, threads, e0, e1);
+    const double split = run_mix<3>(d_out, mblocks, threads, e0, e1);
+    const double m_only_a = run_mix<4>(d_out, mblocks, threads, e0, e1);
+    const double both_a = run_mix<5>(d_out, mblocks, threads, e0, e1);
+    const double cyc = clk_ghz * 1e6;   // cycles per ms
+    const double per_simd_mfma = 4.0 * kMixIters, per_simd_fma = 4.0 * kMixIters * kMixFma;
+    std::printf("\nmatrix/vector overlap (per SIMD: %.0f v_mfma_f32_32x32x16_bf16, %.0f v_fma_f32)\n",
+                per_simd_mfma, per_simd_fma);
+    std::printf("%-34s %10s %16s\n", "case", "ms", "cycles per SIMD");
+    std::printf("%-34s %10.4f %16.0f  (%.1f cycles per MFMA)\n", "MFMA alone", m_only,
+                m_only * cyc, m_only * cyc / per_simd_mfma);
+    std::printf("%-34s %10.4f %16.0f  (%.2f cycles per FMA)\n", "FMA alone", v_only, v_only * cyc,
+                v_only * cyc / per_simd_fma);
+    std::printf("%-34s %10.4f %16.0f\n", "both, interleaved in every wave", both, both * cyc);
+    std::printf("%-34s %10.4f %16.0f\n", "split: matrix waves + vector waves", split, split * cyc);
+    std::printf("%-34s %10.4f %16.0f  (%.1f cycles per MFMA)\n", "MFMA alone, AGPR accumulators",
+                m_only_a, m_only_a * cyc, m_only_a * cyc / per_simd_mfma);
+    std::printf("%-34s %10.4f %16.0f\n", "both, AGPR accumulators", both_a, both_a * cyc);
+    std::printf("sum of the two alone %.4f ms, larger of the two %.4f ms\n", m_only + v_only,
+                m_only > v_only ? m_only : v_only);
   }
   CHECK(hipFree(d_out));
   return 0;
