@@ -39,6 +39,17 @@ N_CU, CLOCK_HZ, FMA_LANES_PER_CLK = 256, 2.4e9, 128
 ALU_PEAK_SLOTS = N_CU * CLOCK_HZ * FMA_LANES_PER_CLK      # 7.86e13 slots/s
 MFMA_PEAK = {"fp32": 157.3e12, "bf16": 2.5e15, "fp16": 2.5e15, "bf16x2": 2.5e15}
 HBM_PEAK = 8.0e12                                           # bytes/s
+# One v_mfma_f32_32x32x16 (BF16/FP16) occupies a SIMD for about 35.5 cycles
+# (isa_rates.hip, matrix core alone; nominal 8 passes = 32), and on one SIMD
+# the matrix core overlaps vector issue by only ~12 % (same probe), so the
+# bound of a kernel issuing both is VALU issue time + MFMA time.
+MFMA_CYCLES_32X32X16 = 35.5
+N_SIMD = 4 * N_CU
+
+
+def _mfma_share(n_mfma, kernel_ms):
+    """Fraction of the kernel time the SIMDs spend in n_mfma 32x32x16 MFMAs."""
+    return n_mfma * MFMA_CYCLES_32X32X16 / N_SIMD / CLOCK_HZ / (kernel_ms * 1e-3)
 
 # Issue cost of each instruction class on gfx950 in "slots": wave64 FMA
 # issues at the FP32 vector peak (2 per clock per CU). Costs are 2 divided
@@ -267,8 +278,9 @@ def _line(args, metric, value, unit, ms, dtype, config, roofline, higher_is_bett
 # and launch shapes the profiles under profiles/ name; None where a kernel
 # has no such measurement.
 TRAFFIC_BYTES = {
-    "gbm_path_kernel<float, asian|geo|uo, log-Euler>": 2.984e6,   # 2^24 paths x 252 steps
-    "basket_kernel<8, bf16>": 3.395e6,                          # 2^20 paths x 100 steps
+    "gbm_path_kernel<float, asian|geo|uo, log-Euler>": 1.054e6,   # 2^24 paths x 252 steps
+    "basket_kernel<8, bf16>": 2.595e6,                          # 2^20 paths x 100 steps
+    "heston_adjoint_kernel<float, full, asian>": 2.261e6,       # 2^22 paths x 256 steps
     "lsm_update_kernel<2, 2, 1>": 3.660e8,                      # 2^24 paths, mean of 8 dates
 }
 
@@ -454,6 +466,12 @@ def run_basket(args, ctx, mc, synth, torch):
     roof = _alu_roofline(SLOTS_ASSET_STEP, N * n * d, k_ms, f"basket_kernel<8, {args.prec}>")
     roof["mfma_tflops"] = flops / (k_ms * 1e-3) / 1e12
     roof["mfma_frac"] = flops / (k_ms * 1e-3) / MFMA_PEAK[args.prec]
+    if args.prec != "fp32":
+        # VALU issue and matrix-core time add up on a SIMD: the kernel against
+        # their sum.
+        n_mfma = (N // 32) * n * blocks * (2 if args.prec == "bf16x2" else 1)
+        roof["mfma_share"] = _mfma_share(n_mfma, k_ms)
+        roof["valu_plus_mfma_frac"] = roof["frac"] + roof["mfma_share"]
     extra = {}
     if prec != mc.MC_FP32:
         # The rounding of the reduced-precision product at the full size: the
@@ -706,12 +724,15 @@ def run_learned_cv(args, ctx, mc, synth, torch):
     cv = out["learned_cv_bf16"]
     m = args.hedge_every
     per_step = SLOTS_HESTON + (128 * SLOTS_TANH + slots(fp32=64 + 8)) / m
+    roof = _alu_roofline(per_step, cv["n_paths"] * n, cv["kernel_ms"], "cv_eval_kernel<bf16>")
+    # Two network passes (2 + 8 MFMAs each) per wave of 64 paths per date.
+    n_mfma = -(-cv["n_paths"] // 64) * -(-n // m) * 20
+    roof["mfma_share"] = _mfma_share(n_mfma, cv["kernel_ms"])
+    roof["valu_plus_mfma_frac"] = roof["frac"] + roof["mfma_share"]
     return _line(args, "time to 1bp SE", cv["total_s"], "s", cv["total_s"] * 1e3, "bf16",
                  {"workload": out["workload"] + f", learned CV rebalanced every {m} steps",
                   "n_steps": n},
-                 _alu_roofline(per_step, cv["n_paths"] * n, cv["kernel_ms"],
-                               "cv_eval_kernel<bf16>"),
-                 higher_is_better=False, time_to_1bp=out)
+                 roof, higher_is_better=False, time_to_1bp=out)
 
 
 # Bermudan call on the maximum of two assets (the LSM experiment of Sec. VI-C):

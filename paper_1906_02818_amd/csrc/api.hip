@@ -44,6 +44,11 @@ struct mc_context {
   void* lsm_buf = nullptr;
   size_t lsm_bytes = 0;
   hipEvent_t ev2 = nullptr, ev3 = nullptr;
+  // The correlation matrix of the last basket call and its Cholesky factor
+  // (or that it is not positive definite): a repeated basket skips the
+  // O(d^3) factorisation, which costs milliseconds on the host at d = 256.
+  std::vector<double> chol_corr, chol_L;
+  bool chol_pd = false;
   // Event pairs around each date's update kernel (created on first use).
   std::vector<hipEvent_t> lsm_ev;
   // Allocation-free calls (mc_price_noalloc): while `noalloc` is set, every
@@ -185,10 +190,27 @@ mc_status validate_basket(mc_context* ctx, const mc_model* m, const mc_payoff* f
   if (o.greeks & MC_GREEK_VEGA) return fail(ctx, MC_ERR_UNSUPPORTED, "basket greeks: delta only");
   if ((uint64_t)n_steps * d / 4 >= (1ull << 32))
     return fail(ctx, MC_ERR_INVALID_ARG, "n_steps * dim above 2^34 normals per path");
-  std::vector<double> Lloc((size_t)d * d);
-  if (!host::cholesky((int)d, m->corr, Lloc.data()))
-    return fail(ctx, MC_ERR_NOT_PD, "correlation matrix is not positive definite");
-  if (L) *L = std::move(Lloc);
+  // The factor is cached in the context (validation without a context
+  // factorises every time).
+  const size_t dd = (size_t)d * d;
+  std::vector<double> local;
+  const std::vector<double>* Lf = &local;
+  bool pd = false;
+  if (ctx) {
+    if (ctx->chol_corr.size() != dd ||
+        std::memcmp(ctx->chol_corr.data(), m->corr, dd * sizeof(double)) != 0) {
+      ctx->chol_corr.assign(m->corr, m->corr + dd);
+      ctx->chol_L.assign(dd, 0.0);
+      ctx->chol_pd = host::cholesky((int)d, m->corr, ctx->chol_L.data());
+    }
+    Lf = &ctx->chol_L;
+    pd = ctx->chol_pd;
+  } else {
+    local.assign(dd, 0.0);
+    pd = host::cholesky((int)d, m->corr, local.data());
+  }
+  if (!pd) return fail(ctx, MC_ERR_NOT_PD, "correlation matrix is not positive definite");
+  if (L) *L = *Lf;
   return MC_OK;
 }
 

@@ -74,6 +74,32 @@ def test_basket_parity_small(ctx, d, N, n, offset, pname):
         assert abs(r["price"] - e["price"]) < 0.1 * e["std_err"]
 
 
+def test_cached_factor_follows_the_correlation_matrix(ctx):
+    # The context keeps the Cholesky factor of the last correlation matrix:
+    # a changed matrix is factorised again (paths against the oracle with its
+    # own factor), a matrix that is not positive definite is refused, and the
+    # first matrix afterwards gives bit-identical paths.
+    d, N, n = 32, 2048, 4
+    say("basket factor cache", d, N, n)
+    model, S0, sigma, corr, L, w = market(d)
+    a = run(ctx, model, 100.0, N, n, mc.MC_FP32)
+    corr2 = 0.5 * corr + 0.5 * np.eye(d)
+    model2 = mc.Model(kind=mc.MC_GBM_BASKET, S0=S0, r=0.05, T=1.0, sigma=sigma, corr=corr2)
+    b = run(ctx, model2, 100.0, N, n, mc.MC_FP32)
+    o = oracle.basket(S0, sigma, oracle.cholesky(corr2), w, 0.05, 1.0, 100.0, n, N, SEED)
+    np.testing.assert_allclose(b["path_values"][:, 0], o[:, 0], rtol=1e-4, atol=1e-4)
+    assert np.abs(b["path_values"][:, 0] - a["path_values"][:, 0]).max() > 1e-2
+    bad = corr.copy()
+    bad[0, 1] = bad[1, 0] = 1.5
+    model_bad = mc.Model(kind=mc.MC_GBM_BASKET, S0=S0, r=0.05, T=1.0, sigma=sigma, corr=bad)
+    for _ in range(2):
+        with pytest.raises(mc.McError) as e:
+            run(ctx, model_bad, 100.0, N, n, mc.MC_FP32)
+        assert e.value.status == mc.MC_ERR_NOT_PD
+    c = run(ctx, model, 100.0, N, n, mc.MC_FP32)
+    np.testing.assert_array_equal(c["path_values"], a["path_values"])
+
+
 @pytest.mark.parametrize("pname", list(PRECS))
 def test_basket_full_size_sampled_paths(ctx, pname):
     # The configured workload: d = 256, 100 steps, 2^20 paths.
