@@ -296,7 +296,20 @@ def _alu_roofline(slots_per_unit, units, kernel_ms, kernel):
 def _repeat(args, torch, fn):
     """W warm-up steps, continued (up to 200 more) until 0.25 s have passed:
     the GPU's clocks ramp up over the first few tens of ms of work, and the
-    timed steps are meant to run at steady clocks. Then the timed steps."""
+    timed steps are meant to run at steady clocks. Then the timed steps.
+    Python's garbage collector is paused meanwhile (as timeit does): a full
+    collection in a process holding torch takes tens of ms."""
+    import gc
+    gc_was_on = gc.isenabled()
+    gc.disable()
+    try:
+        return _repeat_body(args, torch, fn)
+    finally:
+        if gc_was_on:
+            gc.enable()
+
+
+def _repeat_body(args, torch, fn):
     t0 = time.perf_counter()
     for _ in range(args.warmup):
         fn()
