@@ -185,11 +185,19 @@ def _heston_model(mc, synth):
 
 
 def _timed(torch, fn):
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    r = fn()
-    torch.cuda.synchronize()
-    return r, time.perf_counter() - t0
+    """One timed call, with Python's garbage collector paused (see _repeat)."""
+    import gc
+    gc_was_on = gc.isenabled()
+    gc.disable()
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+    finally:
+        if gc_was_on:
+            gc.enable()
 
 
 def time_to_1bp(ctx, mc, synth, torch, hedge_every=16, adam_steps=2000):
