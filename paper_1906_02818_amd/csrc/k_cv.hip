@@ -19,7 +19,10 @@
 // (r mod 4). Layer 2's k-slots are ordered so that its B operand is exactly
 // the lane's layer-1 output (the host permutes W2 to match), so nothing
 // moves between layers. Layer 3 is a per-lane dot product plus one swap of
-// halves. tanh(x) = 2 / (1 + e^{-2x}) - 1 on v_exp_f32 / v_rcp_f32.
+// halves. tanh(x) = 2 / (1 + e^{-2x}) - 1 on v_exp_f32 / v_rcp_f32. Where
+// only Delta is needed, layer 3 runs on r = (1 + tanh) / 2 = 1 / (1 + e^{-2x})
+// of layer 2: Delta = sum_u (2 W3_u) r_u + (b3 - sum_u W3_u), one FMA per unit
+// fewer (the per-lane constants hold 2 W3).
 //
 // Training. The network's inputs (the features at each segment's opening
 // date) and the segment's price change do not depend on the weights, so
@@ -113,10 +116,25 @@ __device__ __forceinline__ void mma16(f32x16& acc, const Op8<BF16>& a, const Op8
   }
 }
 
-// tanh(x + b) with cb = -2 b / ln 2 folded into the exponent.
+// 1 / (1 + e^{-2(x + b)}) = (1 + tanh(x + b)) / 2, with cb = -2 b / ln 2
+// folded into the exponent.
+__device__ __forceinline__ float sigm2_b(float x, float cb) {
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(__builtin_fmaf(x, kNeg2Log2e, cb)));
+}
+
+// tanh(x + b), same folding.
 __device__ __forceinline__ float tanh_b(float x, float cb) {
-  const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(x, kNeg2Log2e, cb));
-  return __builtin_fmaf(2.0f, __builtin_amdgcn_rcpf(1.0f + e), -1.0f);
+  return __builtin_fmaf(2.0f, sigm2_b(x, cb), -1.0f);
+}
+
+// The constant of layer 3 in the sigmoid form, b3 - sum_u W3_u: the 64 W3
+// are summed by a fixed butterfly and lane 0's total is broadcast, so every
+// lane of every wave and kernel uses the same bits.
+__device__ __forceinline__ float out_const(const float* theta) {
+  float w = theta[4480 + (threadIdx.x & 63)];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off, 64);
+  return theta[4544] - __shfl(w, 0, 64);
 }
 
 __device__ __forceinline__ int unit_of(int mb, int r, int h) {
@@ -139,9 +157,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 constexpr int kFragFloats = 2 * 4 * 64 * 8;   // one set of layer-2 fragments
-constexpr int kLaneFloats = 2 * 64 * 32;      // per-lane b2 (scaled) and W3
+constexpr int kLaneFloats = 2 * 64 * 32;      // per-lane b2 (scaled) and 2 W3
 
-// Per-lane constants (b2 scaled, then W3): 32 values per lane, one per unit
+// Per-lane constants (b2 scaled, then 2 W3): 32 values per lane, one per unit
 // slot q = 16 mb + r, stored as [q / 4][lane][q mod 4] so that the four
 // consecutive slots a lane reads at once sit beside those of its neighbours
 // (a wave's 16-byte reads cover 1 KB contiguously, free of bank conflicts).
@@ -149,13 +167,13 @@ __device__ __forceinline__ int lanec_index(int lane, int q) {
   return (q >> 2) * 256 + lane * 4 + (q & 3);
 }
 
-// Forward pass of the hedge network for the wave's 32 paths. phi: the
-// lane's B fragment of layer 1 (half 0: features and the constant 1; half
-// 1: zeros). Returns Delta (identical in both halves); keeps h1, h2.
+// Forward pass of the hedge network for the wave's 32 paths, keeping the
+// activations for the backward pass. phi: the lane's B fragment of layer 1
+// (half 0: features and the constant 1; half 1: zeros). Leaves h1, h2.
 template <bool BF16>
-__device__ __forceinline__ float mlp_forward(const float (&phi)[8], const Op8<BF16> (&w1a)[2],
-                                             const FragT<BF16>* w2f, const float* lanec, int lane,
-                                             float b3, float (&h1)[32], float (&h2)[32]) {
+__device__ __forceinline__ void mlp_forward(const float (&phi)[8], const Op8<BF16> (&w1a)[2],
+                                            const FragT<BF16>* w2f, const float* lanec, int lane,
+                                            float (&h1)[32], float (&h2)[32]) {
   f32x16 d1[2];
   const Op8<BF16> phio = op_from<BF16>(phi);
 #pragma unroll
@@ -187,17 +205,13 @@ __device__ __forceinline__ float mlp_forward(const float (&phi)[8], const Op8<BF
     for (int mb = 0; mb < 2; ++mb)
       mma16<BF16>(d2[mb], op_lds<BF16>(&w2f[((mb * 4 + kb) * 64 + lane) * 8]), b);
   }
-  float part = 0.f;
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int idx = mb * 16 + r;
-      const float v = tanh_b(d2[mb][r], lanec[lanec_index(lane, idx)]);
-      h2[idx] = v;
-      part = __builtin_fmaf(lanec[64 * 32 + lanec_index(lane, idx)], v, part);
+      h2[idx] = tanh_b(d2[mb][r], lanec[lanec_index(lane, idx)]);
     }
-  return part + __shfl_xor(part, 32, 64) + b3;
 }
 
 // Constants of the Heston step on the discounted log2-price (no rate in
@@ -242,14 +256,15 @@ struct HestonF {
   }
 };
 
-// The same forward pass when only Delta is needed (evaluation): layer 1's
-// activations go straight into layer 2's B operands, so they are held in
-// the operand type (BF16 pairs) rather than as FP32 values. Same arithmetic
-// as mlp_forward.
+// The forward pass when only Delta is needed (evaluation and the training
+// forward): layer 1's activations go straight into layer 2's B operands, so
+// they are held in the operand type (BF16 pairs) rather than as FP32 values,
+// and layer 3 takes layer 2's activations in the sigmoid form. c3 =
+// out_const(theta). Returns Delta (identical in both halves).
 template <bool BF16>
 __device__ __forceinline__ float mlp_delta(const float (&phi)[8], const Op8<BF16> (&w1a)[2],
                                            const FragT<BF16>* w2f, const float* lanec, int lane,
-                                           float b3) {
+                                           float c3) {
   f32x16 d1[2];
   const Op8<BF16> phio = op_from<BF16>(phi);
 #pragma unroll
@@ -283,10 +298,10 @@ __device__ __forceinline__ float mlp_delta(const float (&phi)[8], const Op8<BF16
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int idx = mb * 16 + r;
-      const float v = tanh_b(d2[mb][r], lanec[lanec_index(lane, idx)]);
+      const float v = sigm2_b(d2[mb][r], lanec[lanec_index(lane, idx)]);
       part = __builtin_fmaf(lanec[64 * 32 + lanec_index(lane, idx)], v, part);
     }
-  return part + __shfl_xor(part, 32, 64) + b3;
+  return part + __shfl_xor(part, 32, 64) + c3;
 }
 
 // Fills the feature cache: one lane per path (h.n_paths paths from global
@@ -362,7 +377,7 @@ __global__ __launch_bounds__(kCvThreads) void cv_fwd_kernel(const CvParams P) {
     load8(&P.w1f[(mb * 64 + lane) * 8], w);
     w1a[mb] = op_from<BF16>(w);
   }
-  const float b3 = P.theta[4544];
+  const float c3 = out_const(P.theta);
   const uint64_t n = P.h.n_paths, ntiles = (n + 31) / 32;
   const uint64_t items = ntiles * P.n_seg;
   const uint64_t nw = (uint64_t)gridDim.x * kCvWaves;
@@ -370,9 +385,9 @@ __global__ __launch_bounds__(kCvThreads) void cv_fwd_kernel(const CvParams P) {
     const uint32_t k = (uint32_t)(it / ntiles);
     const uint64_t p = (it % ntiles) * 32 + row;
     const bool active = p < n;
-    float phi[8], h1[32], h2[32];
+    float phi[8];
     cached_phi(P, k, p, half, active, phi);
-    const float d = mlp_forward<BF16>(phi, w1a, s_w2f, s_lanec, lane, b3, h1, h2);
+    const float d = mlp_delta<BF16>(phi, w1a, s_w2f, s_lanec, lane, c3);
     if (half == 0 && active) P.c_delta[(size_t)k * n + p] = d;
   }
 }
@@ -465,7 +480,6 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
     load8(&P.w1f[(mb * 64 + lane) * 8], w);
     w1a[mb] = op_from<BF16>(w);
   }
-  const float b3 = P.theta[4544];
   const float col0 = row == 0 ? 1.0f : 0.0f;   // B operand entry: ones in column 0
 
   float g = 0.f;                       // upstream factor of this path
@@ -503,10 +517,11 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
     {
       float phi[8];
       cached_phi(P, k, pid, half, active, phi);
-      mlp_forward<BF16>(phi, w1a, s_w2f, s_lanec, lane, b3, h1, h2);
+      mlp_forward<BF16>(phi, w1a, s_w2f, s_lanec, lane, h1, h2);
     }
     const float dSt = active ? P.c_dst[(size_t)k * P.c_stride + P.c_first + pid] : 0.f;
     const float gD = g * dSt;                      // dL/dDelta for this segment
+    const float gDh = 0.5f * gD;                   // the constants hold 2 W3
     if (half == 0) gb3 += gD;
     // dW3 (column 1 of gx) += H2^T gD.
     to_T(h2);
@@ -525,7 +540,7 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
     float d2v[32];
 #pragma unroll
     for (int q = 0; q < 32; ++q)
-      d2v[q] = gD * s_lanec[64 * 32 + lanec_index(lane, q)] * (1.0f - h2[q] * h2[q]);
+      d2v[q] = gDh * s_lanec[64 * 32 + lanec_index(lane, q)] * (1.0f - h2[q] * h2[q]);
     to_T(d2v);
     wave_lds_sync();
     Op8<BF16> A2[2][2];
@@ -679,7 +694,7 @@ __global__ __launch_bounds__(kCvThreads) void cv_eval_kernel(const CvParams P) {
     load8(&P.w1f[(mb * 64 + lane) * 8], w);
     w1a[mb] = op_from<BF16>(w);
   }
-  const float b3 = P.theta[4544];
+  const float c3 = out_const(P.theta);
 
   const HestonF c(Hp);
   const float S0 = c.S0;
@@ -707,7 +722,7 @@ __global__ __launch_bounds__(kCvThreads) void cv_eval_kernel(const CvParams P) {
           for (int f = 0; f < 4; ++f) phi[f] = sub == 0 ? own[f] : other[f];
           phi[4] = 1.0f;
         }
-        const float d = mlp_delta<BF16>(phi, w1a, s_w2f, s_lanec, lane, b3);
+        const float d = mlp_delta<BF16>(phi, w1a, s_w2f, s_lanec, lane, c3);
         if (sub == half) delta = d;
       }
       st_open = Et;
@@ -765,7 +780,7 @@ __global__ void cv_pack_kernel(const float* __restrict__ th, float* __restrict__
     const int h = lane >> 5, mb = q >> 4, r = q & 15;
     const int u = unit_of(mb, r, h);
     lanec[t] = b2[u] * kNeg2Log2e;
-    lanec[kLanecFloats / 2 + t] = W3[u];
+    lanec[kLanecFloats / 2 + t] = 2.0f * W3[u];
   }
 }
 
@@ -855,7 +870,7 @@ __global__ __launch_bounds__(256) void grad_adam_kernel(
       if (is_b2)
         lanec[dst] = t * kNeg2Log2e;
       else
-        lanec[kLanecFloats / 2 + dst] = t;
+        lanec[kLanecFloats / 2 + dst] = 2.0f * t;
     }
   }
 }

@@ -228,7 +228,7 @@ struct CvParams {
   const float* w1f;          // [2 mb][64 lane][8]   layer-1 A fragments (W1 | b1 | 0)
   const float* w2f;          // [2 mb][4 kb][64][8]  layer-2 A fragments (permuted W2)
   const float* w2tf;         // [2 mb][4 kb][64][8]  W2^T fragments for the backward pass
-  const float* lanec;        // [2][8][64][4]: per-lane b2 * (-2 / ln 2), W3 of the lane's units
+  const float* lanec;        // [2][8][64][4]: per-lane b2 * (-2 / ln 2), 2 W3 of the lane's units
   const float* dfac;         // [n_steps + 1]: e^{r t_i}
   // training
   double* ybar_mom;          // out: merged moments of the hedged values (block 0 writes)

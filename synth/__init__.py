@@ -30,8 +30,10 @@ HESTON = dict(S0=100.0, v0=0.04, kappa=2.0, theta=0.04, xi=0.5, rho=-0.7,
               r=0.02, T=1.0, K=100.0, n_steps=256, n_paths=1 << 22)
 
 # Learned control variate on the Heston Asian: 2000 Adam steps on a fixed
-# 2^20-path training set, evaluated on 2^24 fresh paths.
-LEARNED_CV = dict(n_train=1 << 20, batch=1 << 16, adam_steps=2000, lr=1e-3,
+# 2^20-path training set, evaluated on 2^24 fresh paths. Learning rate: the
+# variance reduction after 2000 steps on 2^22 fresh paths rose from 11.65
+# (1e-3) to 12.53 (2e-3), 12.88 (4e-3), 12.92 (8e-3), 12.87 (1.6e-2).
+LEARNED_CV = dict(n_train=1 << 20, batch=1 << 16, adam_steps=2000, lr=4e-3,
                   n_eval=1 << 24)
 
 # Basket call on d = 256 correlated GBM assets, 100 steps, 2^20 paths.
