@@ -107,6 +107,9 @@ SLOTS_HESTON_REVERSE = slots(trans=2.0, fp32=6.0, fp64=3.0)
 SLOTS_ASSET_STEP = slots(**_add(NORMAL_BASKET, dict(intops=0.5)))
 #   per asset-path-step of the basket: one normal and half a 16-bit pack
 SLOTS_TANH = slots(trans=2.0, fp32=3.0)
+#   tanh(x + b): fma, exp2, add, rcp, fma
+SLOTS_SIGM = slots(trans=2.0, fp32=2.0)
+#   (1 + tanh(x + b)) / 2, the form layer 3 takes where only Delta is needed
 
 
 def _cpu_model():
@@ -744,7 +747,10 @@ def run_learned_cv(args, ctx, mc, synth, torch):
     n = synth.HESTON["n_steps"]
     cv = out["learned_cv_bf16"]
     m = args.hedge_every
-    per_step = SLOTS_HESTON + (128 * SLOTS_TANH + slots(fp32=64 + 8)) / m
+    # Per date and path (two 32-path network passes per wave of 64 paths):
+    # 64 tanh of layer 1, 64 sigmoid-form activations of layer 2, 64 FMAs of
+    # layer 3 and 8 feature operations.
+    per_step = SLOTS_HESTON + (64 * SLOTS_TANH + 64 * SLOTS_SIGM + slots(fp32=64 + 8)) / m
     roof = _alu_roofline(per_step, cv["n_paths"] * n, cv["kernel_ms"], "cv_eval_kernel<bf16>")
     # Two network passes (2 + 8 MFMAs each) per wave of 64 paths per date.
     n_mfma = -(-cv["n_paths"] // 64) * -(-n // m) * 20
