@@ -428,9 +428,11 @@ __global__ __launch_bounds__(kCvThreads) void cv_values_kernel(const CvParams P)
 //   gx  = 64 units x 32 columns holding, by column, db2 = delta2^T 1,
 //         dW3 = H2^T gD, dW1 = delta1^T phi (4 columns) and db1 = delta1^T 1,
 //         each product with a B operand that is zero outside its columns.
-// A path-major operand (delta2, H2, H1, delta1) passes through the wave's
-// LDS region to become unit-major; the column operands (gD, phi, 1) are one
-// row each of a small second region.
+// A path-major operand (delta2, H2, H1, delta1) passes through one of the
+// wave's two LDS regions to become unit-major, two operands per store ->
+// load round trip, with e1 = W2^T delta2 and delta1 computed while the
+// stores land; the column operands (gD, phi, 1) are one row each of a small
+// part of a region.
 template <bool BF16>
 __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
   using FT = FragT<BF16>;
@@ -441,7 +443,8 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
   // consecutive units fall on one bank group).
   constexpr int kTs = BF16 ? 40 : 36;
   constexpr int kTr = 64 * kTs + 8 * kTs;
-  constexpr size_t kLds = 2 * kFragFloats * sizeof(FT) + kLaneFloats * 4 + kCvWaves * kTr * sizeof(FT);
+  constexpr size_t kLds =
+      2 * kFragFloats * sizeof(FT) + kLaneFloats * 4 + kCvWaves * 2 * kTr * sizeof(FT);
   static_assert(kLds >= kMlpNParam * sizeof(double), "LDS too small for the gradient sum");
   __shared__ __attribute__((aligned(16))) unsigned char lds[kLds];
   // Ybar: every block merges the hedged-value kernel's block moments itself
@@ -498,51 +501,66 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) gw2[a][b][r] = 0.f;
   }
-  FT* T = tr + wave * kTr;   // [64 units][32 paths], row stride kTs
-  FT* TP = T + 64 * kTs;     // [8 columns][32 paths], row stride kTs
-  // Unit-major A fragments of the region T (32 units of block mb x 8 paths).
-  auto a_frag = [&](int pk, int mb) {
+  // Two regions per wave, each [64 units][32 paths] plus [8 columns][32
+  // paths], row stride kTs: two transposes share one store -> load round trip.
+  FT* const T0 = tr + wave * 2 * kTr;
+  FT* const T1 = T0 + kTr;
+  FT* const TP0 = T0 + 64 * kTs;
+  FT* const TP1 = T1 + 64 * kTs;
+  // Unit-major A fragments of a region (32 units of block mb x 8 paths).
+  auto a_frag = [&](const FT* T, int pk, int mb) {
     return op_lds<BF16>(&T[(32 * mb + row) * kTs + 16 * pk + 8 * half]);
   };
-  auto to_T = [&](const float (&x)[32]) {
+  auto to_T = [&](FT* T, const float (&x)[32]) {
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
       for (int r = 0; r < 16; ++r) T[unit_of(mb, r, half) * kTs + row] = (FT)x[mb * 16 + r];
   };
 
-  // The steps are ordered so that few path-major vectors are live at once.
   for (uint32_t k = 0; k < P.n_seg; ++k) {
-    float h1[32], h2[32];
-    {
-      float phi[8];
-      cached_phi(P, k, pid, half, active, phi);
-      mlp_forward<BF16>(phi, w1a, s_w2f, s_lanec, lane, h1, h2);
-    }
+    float h1[32], h2[32], phi[8];
+    cached_phi(P, k, pid, half, active, phi);
+    mlp_forward<BF16>(phi, w1a, s_w2f, s_lanec, lane, h1, h2);
     const float dSt = active ? P.c_dst[(size_t)k * P.c_stride + P.c_first + pid] : 0.f;
     const float gD = g * dSt;                      // dL/dDelta for this segment
     const float gDh = 0.5f * gD;                   // the constants hold 2 W3
     if (half == 0) gb3 += gD;
-    // dW3 (column 1 of gx) += H2^T gD.
-    to_T(h2);
-    if (half == 0) TP[1 * kTs + row] = (FT)gD;
-    wave_lds_sync();
-#pragma unroll
-    for (int pk = 0; pk < 2; ++pk) {
-      const Op8<BF16> b = row == 1 ? op_lds<BF16>(&TP[1 * kTs + 16 * pk + 8 * half])
-                                   : op_zero<BF16>();
-#pragma unroll
-      for (int mb = 0; mb < 2; ++mb) mma16<BF16>(gx[mb], a_frag(pk, mb), b);
-    }
-    wave_lds_sync();
-    // delta2 = gD W3 (1 - h2^2), into unit-major A fragments;
-    // db2 (column 0 of gx) += delta2^T 1.
+    // delta2 = gD W3 (1 - h2^2).
     float d2v[32];
 #pragma unroll
     for (int q = 0; q < 32; ++q)
       d2v[q] = gDh * s_lanec[64 * 32 + lanec_index(lane, q)] * (1.0f - h2[q] * h2[q]);
-    to_T(d2v);
+    // Round trip 1: H2 (with gD in column row 1) and delta2 become unit-major.
+    to_T(T0, h2);
+    if (half == 0) TP0[1 * kTs + row] = (FT)gD;
+    to_T(T1, d2v);
     wave_lds_sync();
+    // e1 = W2^T delta2 from registers while the stores land.
+    f32x16 e1[2];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) e1[mb][r] = 0.f;
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+      float bf[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) bf[j] = d2v[(kb >> 1) * 16 + 8 * (kb & 1) + j];
+      const Op8<BF16> b = op_from<BF16>(bf);
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+        mma16<BF16>(e1[mb], op_lds<BF16>(&s_w2tf[((mb * 4 + kb) * 64 + lane) * 8]), b);
+    }
+    // dW3 (column 1 of gx) += H2^T gD.
+#pragma unroll
+    for (int pk = 0; pk < 2; ++pk) {
+      const Op8<BF16> b = row == 1 ? op_lds<BF16>(&TP0[1 * kTs + 16 * pk + 8 * half])
+                                   : op_zero<BF16>();
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb) mma16<BF16>(gx[mb], a_frag(T0, pk, mb), b);
+    }
+    // db2 (column 0 of gx) += delta2^T 1; delta2's fragments stay for dW2.
     Op8<BF16> A2[2][2];
     {
       float ones[8];
@@ -553,41 +571,16 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
       for (int pk = 0; pk < 2; ++pk)
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb) {
-          A2[pk][mb] = a_frag(pk, mb);
+          A2[pk][mb] = a_frag(T1, pk, mb);
           mma16<BF16>(gx[mb], A2[pk][mb], b);
         }
     }
     wave_lds_sync();
-    // dW2 += delta2^T H1.
-    to_T(h1);
-    wave_lds_sync();
-#pragma unroll
-    for (int pk = 0; pk < 2; ++pk)
-#pragma unroll
-      for (int nb = 0; nb < 2; ++nb) {
-        const Op8<BF16> b = op_lds<BF16>(&T[(32 * nb + row) * kTs + 16 * pk + 8 * half]);
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb) mma16<BF16>(gw2[mb][nb], A2[pk][mb], b);
-      }
-    wave_lds_sync();
-    // delta1 = (W2^T delta2) (1 - h1^2)
-    float d1v[32];
+    // Round trip 2: H1 and delta1 = e1 (1 - h1^2) (with phi and the ones in
+    // column rows 2..6) become unit-major.
+    to_T(T0, h1);
     {
-      f32x16 e1[2];
-#pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) e1[mb][r] = 0.f;
-#pragma unroll
-      for (int kb = 0; kb < 4; ++kb) {
-        float bf[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) bf[j] = d2v[(kb >> 1) * 16 + 8 * (kb & 1) + j];
-        const Op8<BF16> b = op_from<BF16>(bf);
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
-          mma16<BF16>(e1[mb], op_lds<BF16>(&s_w2tf[((mb * 4 + kb) * 64 + lane) * 8]), b);
-      }
+      float d1v[32];
 #pragma unroll
       for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
@@ -595,24 +588,31 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
           const int q = mb * 16 + r;
           d1v[q] = e1[mb][r] * (1.0f - h1[q] * h1[q]);
         }
+      to_T(T1, d1v);
     }
-    // dW1 and db1 (columns 2..6 of gx) += delta1^T [phi, 1].
-    to_T(d1v);
     if (half == 0) {
-      const uint64_t S = P.c_stride, c = P.c_first + pid;
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        TP[(2 + q) * kTs + row] = active ? (FT)P.c_phi[((size_t)k * 4 + q) * S + c] : (FT)0.f;
-      TP[6 * kTs + row] = active ? (FT)1.0f : (FT)0.f;
+      for (int q = 0; q < 4; ++q) TP1[(2 + q) * kTs + row] = (FT)phi[q];
+      TP1[6 * kTs + row] = active ? (FT)1.0f : (FT)0.f;
     }
     wave_lds_sync();
+    // dW2 += delta2^T H1.
+#pragma unroll
+    for (int pk = 0; pk < 2; ++pk)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        const Op8<BF16> b = op_lds<BF16>(&T0[(32 * nb + row) * kTs + 16 * pk + 8 * half]);
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) mma16<BF16>(gw2[mb][nb], A2[pk][mb], b);
+      }
+    // dW1 and db1 (columns 2..6 of gx) += delta1^T [phi, 1].
 #pragma unroll
     for (int pk = 0; pk < 2; ++pk) {
       const Op8<BF16> b = (row >= 2 && row <= 6)
-                              ? op_lds<BF16>(&TP[row * kTs + 16 * pk + 8 * half])
+                              ? op_lds<BF16>(&TP1[row * kTs + 16 * pk + 8 * half])
                               : op_zero<BF16>();
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb) mma16<BF16>(gx[mb], a_frag(pk, mb), b);
+      for (int mb = 0; mb < 2; ++mb) mma16<BF16>(gx[mb], a_frag(T1, pk, mb), b);
     }
     wave_lds_sync();
   }
@@ -657,8 +657,8 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
     P.grad_partials[(uint64_t)blockIdx.x * kMlpNParam + i] = red[i];
 }
 
-// The BF16 form fits two waves per SIMD (256 VGPRs; 55 KB of LDS, two
-// workgroups per CU); the FP32 form's 95 KB allow one workgroup per CU.
+// The BF16 form fits two waves per SIMD (256 VGPRs; 77 KB of LDS, two
+// workgroups per CU); the FP32 form's 130 KB allow one workgroup per CU.
 __global__ __launch_bounds__(kCvThreads) __attribute__((amdgpu_waves_per_eu(2))) void
 cv_bwd_kernel_bf16(const CvParams P) {
   cv_bwd_body<true>(P);
