@@ -203,12 +203,29 @@ def _timed(torch, fn):
             gc.enable()
 
 
+def _pilot_then_run(torch, pilot_fn, run_fn, reps=3):
+    """Time to 1 bp of one estimator: a pilot sizes N*, a run of N* paths
+    follows; both are timed. One untimed pair first (the workspace grows to
+    the run's size once, as in any later pricing), then `reps` timed pairs;
+    returns the pair with the median total and every total."""
+    def pair():
+        pil, t_pil = _timed(torch, pilot_fn)
+        N = _paths_for(1e-4 * pil["price"], math.sqrt(pil["variance"]))
+        run, t_run = _timed(torch, lambda: run_fn(N))
+        return pil, t_pil, N, run, t_run
+    pair()
+    pairs = sorted((pair() for _ in range(reps)), key=lambda x: x[1] + x[4])
+    pil, t_pil, N, run, t_run = pairs[len(pairs) // 2]
+    return pil, t_pil, N, run, t_run, [x[1] + x[4] for x in pairs]
+
+
 def time_to_1bp(ctx, mc, synth, torch, hedge_every=16, adam_steps=2000):
     """Time to a Heston-Asian price whose standard error is 1 bp of the price
     (1e-4 x price), plain FP32 Monte Carlo against the learned control
     variate with BF16 matrix products. Each estimator: a 2^20-path pilot on
     stream tag 1 sizes N* = (s / (1e-4 p))^2, then one run of N* paths on
-    tag 0; both are timed. The hedge network is trained beforehand (2000
+    tag 0; both are timed (median of three pairs after an untimed one, see
+    _pilot_then_run). The hedge network is trained beforehand (2000
     Adam steps, minibatch 2^16 from a fixed 2^20-path set on tag 2); its
     training time is reported separately and added in `total_incl_train_s`.
     """
@@ -221,12 +238,12 @@ def time_to_1bp(ctx, mc, synth, torch, hedge_every=16, adam_steps=2000):
     cv_f = mc.Payoff(mc.MC_ASIAN_ARITH_CALL, H["K"], cv=mc.MC_CV_LEARNED)
     out = {"workload": f"Heston arithmetic-Asian call, {n} steps; target SE = 1e-4 x price",
            "hedge_every": hedge_every}
-    pil, t_pil = _timed(torch, lambda: mc.mc_price(ctx, model, plain_f, 1 << 20, n, synth.SEED,
-                                                   mc.Options(stream_tag=1)))
-    N_plain = _paths_for(1e-4 * pil["price"], math.sqrt(pil["variance"]))
-    run, t_run = _timed(torch, lambda: mc.mc_price(ctx, model, plain_f, N_plain, n, synth.SEED))
+    pil, t_pil, N_plain, run, t_run, totals = _pilot_then_run(
+        torch, lambda: mc.mc_price(ctx, model, plain_f, 1 << 20, n, synth.SEED,
+                                   mc.Options(stream_tag=1)),
+        lambda N: mc.mc_price(ctx, model, plain_f, N, n, synth.SEED))
     out["plain_fp32"] = {"pilot_s": t_pil, "n_paths": N_plain, "run_s": t_run,
-                         "total_s": t_pil + t_run, "price": run["price"],
+                         "total_s": t_pil + t_run, "totals_s": totals, "price": run["price"],
                          "std_err": run["std_err"], "kernel_ms": run["kernel_ms"]}
     th0 = synth.glorot_mlp()
     (w, log), t_train = _timed(torch, lambda: mc.mc_cv_train(
@@ -237,15 +254,13 @@ def time_to_1bp(ctx, mc, synth, torch, hedge_every=16, adam_steps=2000):
         return mc.Options(prec=mc.MC_BF16_GEMM, cv_weights=w, cv_hedge_every=hedge_every,
                           cv_beta=1.0, stream_tag=tag)
 
-    pil, t_pil = _timed(torch, lambda: mc.mc_price(ctx, model, cv_f, 1 << 20, n, synth.SEED,
-                                                   opts(1)))
-    N_cv = _paths_for(1e-4 * pil["price"], math.sqrt(pil["variance"]))
-    run, t_run = _timed(torch, lambda: mc.mc_price(ctx, model, cv_f, N_cv, n, synth.SEED,
-                                                   opts(0)))
+    pil, t_pil, N_cv, run, t_run, totals_cv = _pilot_then_run(
+        torch, lambda: mc.mc_price(ctx, model, cv_f, 1 << 20, n, synth.SEED, opts(1)),
+        lambda N: mc.mc_price(ctx, model, cv_f, N, n, synth.SEED, opts(0)))
     out["learned_cv_bf16"] = {"train_s": t_train, "adam_steps": adam_steps,
                               "loss_first": float(log[0]), "loss_last": float(np.mean(log[-20:])),
                               "pilot_s": t_pil, "pilot_vrf": pil["vrf"], "n_paths": N_cv,
-                              "run_s": t_run, "total_s": t_pil + t_run,
+                              "run_s": t_run, "total_s": t_pil + t_run, "totals_s": totals_cv,
                               "total_incl_train_s": t_train + t_pil + t_run,
                               "price": run["price"], "std_err": run["std_err"],
                               "vrf": run["vrf"], "plain_price_same_paths": run["plain_price"],
@@ -344,7 +359,8 @@ def gbm_time_to_1bp(ctx, mc, synth, torch):
     geometric-Asian control variate, and the up-and-out barrier. Each: a
     2^20-path pilot on stream tag 1 sizes N* = (s / (1e-4 p))^2, then one
     run of N* paths on tag 0; both are timed (the control variate's own
-    coefficient pilot is part of its run)."""
+    coefficient pilot is part of its run; median of three pairs after an
+    untimed one, see _pilot_then_run)."""
     c = synth.ASIAN_BARRIER
     n = c["n_steps"]
     model = mc.Model(kind=mc.MC_GBM, S0=c["S0"], r=c["r"], T=c["T"], sigma=c["sigma"])
@@ -353,12 +369,12 @@ def gbm_time_to_1bp(ctx, mc, synth, torch):
                                                cv=mc.MC_CV_GEO_ASIAN)),
                     ("asian_plain", mc.Payoff(mc.MC_ASIAN_ARITH_CALL, c["K"])),
                     ("uo_barrier", mc.Payoff(mc.MC_UO_BARRIER_CALL, c["K"], B=c["B"]))):
-        pil, t_pil = _timed(torch, lambda: mc.mc_price(ctx, model, f, 1 << 20, n, synth.SEED,
-                                                       mc.Options(stream_tag=1)))
-        N = _paths_for(1e-4 * pil["price"], math.sqrt(pil["variance"]))
-        run, t_run = _timed(torch, lambda: mc.mc_price(ctx, model, f, N, n, synth.SEED))
+        pil, t_pil, N, run, t_run, totals = _pilot_then_run(
+            torch, lambda: mc.mc_price(ctx, model, f, 1 << 20, n, synth.SEED,
+                                       mc.Options(stream_tag=1)),
+            lambda N: mc.mc_price(ctx, model, f, N, n, synth.SEED))
         out[name] = {"pilot_s": t_pil, "n_paths": N, "run_s": t_run, "total_s": t_pil + t_run,
-                     "price": run["price"], "std_err": run["std_err"],
+                     "totals_s": totals, "price": run["price"], "std_err": run["std_err"],
                      "kernel_ms": run["kernel_ms"]}
     out["cv_speedup"] = out["asian_plain"]["total_s"] / out["asian_geo_cv"]["total_s"]
     return out
