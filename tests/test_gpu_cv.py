@@ -200,6 +200,26 @@ def test_adam_steps_match_oracle(ctx):
 
 
 @pytest.mark.parametrize("prec", [mc.MC_FP32, mc.MC_BF16_GEMM])
+def test_training_forward_is_the_evaluation_network(ctx, prec):
+    # The training forward (32-path tiles of a minibatch, from the feature
+    # cache) and the evaluation kernel (64 paths per wave, stepping the paths
+    # itself) compute the same per-path hedge values: the loss of a minibatch
+    # equals the batch variance of the evaluation's per-path estimator on the
+    # same paths (stream tag 2, same path indices) to FP64 merge rounding.
+    th = weights(0.2, seed=9)
+    B, n, m, path0 = 1024, 40, 16, 300
+    say("train forward vs eval", prec)
+    loss, _ = mc.mc_cv_loss_grad(ctx, MODEL, PAY, n, SEED, 2, path0, B, th, hedge_every=m,
+                                 prec=prec)
+    r = mc.mc_price(ctx, MODEL, PAY, B, n, SEED,
+                    mc.Options(prec=prec, cv_weights=th, cv_hedge_every=m, cv_beta=1.0,
+                               stream_tag=2, path_offset=path0, path_values=True))
+    y = r["path_values"][:, 2]
+    say(f"  loss {loss:.12f}  eval batch variance {y.var():.12f}")
+    np.testing.assert_allclose(loss, y.var(), rtol=1e-12)
+
+
+@pytest.mark.parametrize("prec", [mc.MC_FP32, mc.MC_BF16_GEMM])
 def test_training_minibatches_are_the_cached_training_paths(ctx, prec):
     # mc_cv_train simulates its training set (stream tag 2) once and takes
     # minibatch t from paths (t mod n_batches) B onwards; its loss at step t
