@@ -197,34 +197,28 @@ struct AdjC<2> { static constexpr int C = 2; };   // delta, d/dv0
 // in the device buffer, one row with the terminal statistic (A/S0 for the
 // Asian, S_T/S0 otherwise). FULL mode with at most kLdsCkpt checkpoints
 // keeps them in LDS ([row][thread], one thread's column per path, so no
-// barrier is needed), without the first one, which is the initial state
-// (z = 0, v = v0): 2 (n_ckpt - 1) rows, 30 KB at 16 checkpoints, so five
-// workgroups share a CU. Otherwise, and for the FWD/REV split behind
-// autograd, they live in the device buffer ([row][path]). Only the FP32
-// kernel is built: its state is FP32, so the checkpoints are exact.
+// barrier is needed); otherwise, and for the FWD/REV split behind autograd,
+// they live in the device buffer ([row][path]). Only the FP32 kernel is
+// built: its state is FP32, so the checkpoints are exact.
 template <typename R, int PHASE, bool ASIAN, bool LDS>
-__device__ __forceinline__ void heston_adjoint_body(const AdjointParams& A) {
+__global__ __launch_bounds__(kBlock) void heston_adjoint_kernel(const AdjointParams A) {
   constexpr int C = AdjC<PHASE>::C;
   extern __shared__ float s_ck[];
   const HestonParams& P = A.h;
   const uint64_t pid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   const bool active = pid < P.n_paths;
   const uint64_t np = P.n_paths;
-  // Rows 0 and 1 (segment 0) are never stored in LDS mode.
   auto ck_store = [&](uint32_t row, R x) {
-    if constexpr (LDS) {
-      if (row >= 2) s_ck[(row - 2) * kBlock + threadIdx.x] = (float)x;
-    } else {
+    if constexpr (LDS)
+      s_ck[row * kBlock + threadIdx.x] = (float)x;
+    else
       A.ckpt[(size_t)row * np + pid] = (float)x;
-    }
   };
   auto ck_load = [&](uint32_t row) -> R {
-    if constexpr (LDS) {
-      if (row < 2) return row == 0 ? R(0) : (R)P.v0;
-      return (R)s_ck[(row - 2) * kBlock + threadIdx.x];
-    } else {
+    if constexpr (LDS)
+      return (R)s_ck[row * kBlock + threadIdx.x];
+    else
       return (R)A.ckpt[(size_t)row * np + pid];
-    }
   };
   double y[C];
 #pragma unroll
@@ -326,20 +320,6 @@ __device__ __forceinline__ void heston_adjoint_body(const AdjointParams& A) {
   block_moments<C, kBlock>(y, active && finite, active && !finite, P.partials);
 }
 
-// The LDS form runs five waves per SIMD (96 VGPRs; the few values the
-// compiler parks in scratch are loop invariants, stored before the reverse
-// sweep and reloaded after it); the device-buffer forms keep the default.
-template <typename R, int PHASE, bool ASIAN>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void
-heston_adjoint_lds_kernel(const AdjointParams A) {
-  heston_adjoint_body<R, PHASE, ASIAN, true>(A);
-}
-
-template <typename R, int PHASE, bool ASIAN>
-__global__ __launch_bounds__(kBlock) void heston_adjoint_kernel(const AdjointParams A) {
-  heston_adjoint_body<R, PHASE, ASIAN, false>(A);
-}
-
 }  // namespace
 
 uint32_t heston_blocks(uint64_t n_paths) {
@@ -381,12 +361,8 @@ hipError_t launch_heston_tangent(const HestonParams& p, bool asian, bool fp64, h
 
 template <typename R, int PH, bool AS, bool LDS>
 static hipError_t adj_one(const AdjointParams& a, hipStream_t s, uint32_t nb) {
-  if constexpr (LDS) {
-    const size_t lds = (size_t)2 * (a.n_ckpt - 1) * kBlock * sizeof(float);
-    hipLaunchKernelGGL((heston_adjoint_lds_kernel<R, PH, AS>), dim3(nb), dim3(kBlock), lds, s, a);
-  } else {
-    hipLaunchKernelGGL((heston_adjoint_kernel<R, PH, AS>), dim3(nb), dim3(kBlock), 0, s, a);
-  }
+  const size_t lds = LDS ? (size_t)2 * a.n_ckpt * kBlock * sizeof(float) : 0;
+  hipLaunchKernelGGL((heston_adjoint_kernel<R, PH, AS, LDS>), dim3(nb), dim3(kBlock), lds, s, a);
   return hipGetLastError();
 }
 
