@@ -35,22 +35,44 @@ __global__ __launch_bounds__(256) void final_reduce_kernel(const double* __restr
 
 // Moment vectors of C channels (count, means, co-moments): one workgroup of
 // NT threads per batch b = blockIdx.x merges the block-major partials
-// [b][n_blocks][M] into out[b][M]: thread t adds blocks t, t + NT, ... in
-// order (about a shift, no division), then the block reduction of the path
-// kernels.
+// [b][n_blocks][M], vector i at i * stride * M, into out[b][M]: thread t adds
+// vectors t, t + NT, ... in order (about a shift, no division), then the
+// block reduction of the path kernels.
 template <int C>
 constexpr int merge_threads() { return 256; }
 
 template <int C>
 __global__ __launch_bounds__(merge_threads<C>()) void final_merge_kernel(
-    const double* __restrict__ partials, uint32_t n_blocks, double* __restrict__ out) {
+    const double* __restrict__ partials, uint32_t n_blocks, uint32_t stride,
+    double* __restrict__ out) {
   constexpr int M = PartSums<C>::M, NT = merge_threads<C>();
   partials += (size_t)blockIdx.x * n_blocks * M;
   PartSums<C> m;
   m.zero();
 #pragma unroll 4
-  for (uint32_t i = threadIdx.x; i < n_blocks; i += NT) m.add_vector(partials + (size_t)i * M);
+  for (uint32_t i = threadIdx.x; i < n_blocks; i += NT)
+    m.add_vector(partials + (size_t)i * stride * M);
   block_reduce<C, NT>(m, out, blockIdx.x);
+}
+
+// First stage of a long merge (one batch): workgroup g merges the kMergeChunk
+// vectors from g * kMergeChunk (fewer in the last chunk) as above and writes
+// the result over the chunk's first vector, which no other workgroup reads;
+// the block reduction's barrier orders every thread's reads before it.
+constexpr uint32_t kMergeChunk = 2048;
+
+template <int C>
+__global__ __launch_bounds__(merge_threads<C>()) void chunk_merge_kernel(
+    double* __restrict__ partials, uint32_t n_blocks) {
+  constexpr int M = PartSums<C>::M, NT = merge_threads<C>();
+  const uint32_t first = blockIdx.x * kMergeChunk;
+  const uint32_t count = min(kMergeChunk, n_blocks - first);
+  double* head = partials + (size_t)first * M;
+  PartSums<C> m;
+  m.zero();
+#pragma unroll 4
+  for (uint32_t i = threadIdx.x; i < count; i += NT) m.add_vector(head + (size_t)i * M);
+  block_reduce<C, NT>(m, head, 0);
 }
 
 __global__ void philox_words_kernel(uint32_t k0, uint32_t k1, uint32_t tag, uint64_t n,
@@ -134,15 +156,26 @@ hipError_t launch_diff_moments(const double* a, uint32_t Ca, uint32_t ca, const 
   return hipGetLastError();
 }
 
+// One batch of more than two chunks merges in two stages: chunk heads,
+// then the heads in chunk order (a fixed order either way); the partials'
+// chunk heads are overwritten.
 template <int C>
-static hipError_t merge_one(const double* partials, uint32_t n_blocks, uint32_t n_batch,
+static hipError_t merge_one(double* partials, uint32_t n_blocks, uint32_t n_batch,
                             double* out, hipStream_t s) {
+  if (n_batch == 1 && n_blocks > 2 * kMergeChunk) {
+    const uint32_t n_chunks = (n_blocks + kMergeChunk - 1) / kMergeChunk;
+    hipLaunchKernelGGL(chunk_merge_kernel<C>, dim3(n_chunks), dim3(merge_threads<C>()), 0, s,
+                       partials, n_blocks);
+    hipLaunchKernelGGL(final_merge_kernel<C>, dim3(1), dim3(merge_threads<C>()), 0, s, partials,
+                       n_chunks, kMergeChunk, out);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(final_merge_kernel<C>, dim3(n_batch), dim3(merge_threads<C>()), 0, s,
-                     partials, n_blocks, out);
+                     partials, n_blocks, 1u, out);
   return hipGetLastError();
 }
 
-hipError_t launch_final_merge(const double* partials, uint32_t n_blocks, uint32_t C,
+hipError_t launch_final_merge(double* partials, uint32_t n_blocks, uint32_t C,
                               uint32_t n_batch, double* out, hipStream_t s) {
   if (n_blocks == 0 || n_batch == 0 || n_batch > 65535) return hipErrorInvalidValue;
   switch (C) {

@@ -277,8 +277,9 @@ hipError_t launch_grad_sum(const double* partials, uint32_t n_blocks, double* gr
 // ---- reductions and diagnostics ----
 // Moment vectors of C channels (1..kMaxMomentChannels): n_batch independent
 // merges of block-major partials [batch][n_blocks][n_moments(C)] into
-// out [batch][n_moments(C)].
-hipError_t launch_final_merge(const double* partials, uint32_t n_blocks, uint32_t C,
+// out [batch][n_moments(C)], in a fixed order. A single batch of more than
+// 4096 vectors merges in two stages and overwrites the partials' chunk heads.
+hipError_t launch_final_merge(double* partials, uint32_t n_blocks, uint32_t C,
                               uint32_t n_batch, double* out, hipStream_t s);
 // Plain sums: partials [n_mom][n_blocks] -> out [n_mom]; the batch form takes
 // partials [batch][n_mom][n_blocks] -> out [batch][n_mom].
