@@ -167,6 +167,38 @@ __device__ __forceinline__ int lanec_index(int lane, int q) {
   return (q >> 2) * 256 + lane * 4 + (q & 3);
 }
 
+// The layer-2 fragments (optionally also their transposes) and the per-lane
+// constants, global -> registers -> LDS: every thread issues all of its
+// loads before the first store, so a workgroup waits for one memory
+// latency rather than one per element.
+constexpr int kFillPer = kFragFloats / kCvThreads;
+static_assert(kFragFloats % kCvThreads == 0 && kLaneFloats == kFragFloats, "fragment split");
+struct WeightRegs {
+  float a[kFillPer], b[kFillPer], c[kFillPer];
+};
+template <bool WITH_T>
+__device__ __forceinline__ void weights_load(const float* w2f, const float* w2tf,
+                                             const float* lanec, WeightRegs& r) {
+#pragma unroll
+  for (int j = 0; j < kFillPer; ++j) {
+    const int i = threadIdx.x + j * kCvThreads;
+    r.a[j] = w2f[i];
+    if constexpr (WITH_T) r.b[j] = w2tf[i];
+    r.c[j] = lanec[i];
+  }
+}
+template <bool WITH_T, typename FT>
+__device__ __forceinline__ void weights_store(const WeightRegs& r, FT* s_w2f, FT* s_w2tf,
+                                              float* s_lanec) {
+#pragma unroll
+  for (int j = 0; j < kFillPer; ++j) {
+    const int i = threadIdx.x + j * kCvThreads;
+    s_w2f[i] = (FT)r.a[j];
+    if constexpr (WITH_T) s_w2tf[i] = (FT)r.b[j];
+    s_lanec[i] = r.c[j];
+  }
+}
+
 // Forward pass of the hedge network for the wave's 32 paths, keeping the
 // activations for the backward pass. phi: the lane's B fragment of layer 1
 // (half 0: features and the constant 1; half 1: zeros). Leaves h1, h2.
@@ -342,20 +374,6 @@ __global__ __launch_bounds__(kCvThreads) void cv_cache_kernel(const CvParams P) 
   P.c_pay[pid] = Hp.disc * (A > Hp.K ? A - Hp.K : 0.0);
 }
 
-// Layer-1 B fragment of a cached path (half 0: its features and the
-// constant 1; half 1: zeros).
-__device__ __forceinline__ void cached_phi(const CvParams& P, uint32_t k, uint64_t p, int half,
-                                           bool active, float (&phi)[8]) {
-#pragma unroll
-  for (int j = 0; j < 8; ++j) phi[j] = 0.f;
-  if (half == 0 && active) {
-    const uint64_t S = P.c_stride, c = P.c_first + p;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) phi[q] = P.c_phi[((size_t)k * 4 + q) * S + c];
-    phi[4] = 1.0f;
-  }
-}
-
 // Network forward pass over every (segment, 32-path tile) of the minibatch
 // (h.n_paths paths from cache path c_first): Delta to c_delta. Waves step
 // through the items, so a launch needs only enough of them to fill the chip.
@@ -364,8 +382,11 @@ __global__ __launch_bounds__(kCvThreads) void cv_fwd_kernel(const CvParams P) {
   using FT = FragT<BF16>;
   __shared__ __attribute__((aligned(16))) FT s_w2f[kFragFloats];
   __shared__ __attribute__((aligned(16))) float s_lanec[kLaneFloats];
-  for (int i = threadIdx.x; i < kFragFloats; i += kCvThreads) s_w2f[i] = (FT)P.w2f[i];
-  for (int i = threadIdx.x; i < kLaneFloats; i += kCvThreads) s_lanec[i] = P.lanec[i];
+  {
+    WeightRegs wr;
+    weights_load<false>(P.w2f, nullptr, P.lanec, wr);
+    weights_store<false>(wr, s_w2f, (FT*)nullptr, s_lanec);
+  }
   __syncthreads();
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -381,12 +402,31 @@ __global__ __launch_bounds__(kCvThreads) void cv_fwd_kernel(const CvParams P) {
   const uint64_t n = P.h.n_paths, ntiles = (n + 31) / 32;
   const uint64_t items = ntiles * P.n_seg;
   const uint64_t nw = (uint64_t)gridDim.x * kCvWaves;
-  for (uint64_t it = (uint64_t)blockIdx.x * kCvWaves + wave; it < items; it += nw) {
-    const uint32_t k = (uint32_t)(it / ntiles);
-    const uint64_t p = (it % ntiles) * 32 + row;
+  // An item's cached features are loaded one item ahead, so that their
+  // latency overlaps the item before.
+  uint32_t nk = 0;
+  uint64_t np = 0;
+  float nf[4];
+  auto fetch = [&](uint64_t it) {
+    nk = (uint32_t)(it / ntiles);
+    np = (it % ntiles) * 32 + row;
+    const bool act = half == 0 && np < n;
+    const uint64_t S = P.c_stride, c = P.c_first + np;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) nf[q] = act ? P.c_phi[((size_t)nk * 4 + q) * S + c] : 0.f;
+  };
+  uint64_t it = (uint64_t)blockIdx.x * kCvWaves + wave;
+  if (it < items) fetch(it);
+  for (; it < items; it += nw) {
+    const uint32_t k = nk;
+    const uint64_t p = np;
     const bool active = p < n;
     float phi[8];
-    cached_phi(P, k, p, half, active, phi);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) phi[q] = nf[q];
+    phi[4] = (half == 0 && active) ? 1.0f : 0.f;
+    phi[5] = phi[6] = phi[7] = 0.f;
+    if (it + nw < items) fetch(it + nw);
     const float d = mlp_delta<BF16>(phi, w1a, s_w2f, s_lanec, lane, c3);
     if (half == 0 && active) P.c_delta[(size_t)k * n + p] = d;
   }
@@ -445,8 +485,16 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
   constexpr int kTr = 64 * kTs + 8 * kTs;
   constexpr size_t kLds =
       2 * kFragFloats * sizeof(FT) + kLaneFloats * 4 + kCvWaves * 2 * kTr * sizeof(FT);
-  static_assert(kLds >= kMlpNParam * sizeof(double), "LDS too small for the gradient sum");
+  static_assert(kLds >= kCvWaves * kMlpNParam * sizeof(float), "LDS too small for the gradient sum");
   __shared__ __attribute__((aligned(16))) unsigned char lds[kLds];
+  FT* s_w2f = (FT*)lds;
+  FT* s_w2tf = s_w2f + kFragFloats;
+  float* s_lanec = (float*)(lds + 2 * kFragFloats * sizeof(FT));
+  FT* tr = (FT*)(lds + 2 * kFragFloats * sizeof(FT) + kLaneFloats * 4);
+  // The weight fragments and per-lane constants are loaded into registers
+  // first, so that their latency overlaps the merge below.
+  WeightRegs wr;
+  weights_load<true>(P.w2f, P.w2tf, P.lanec, wr);
   // Ybar: every block merges the hedged-value kernel's block moments itself
   // (the same fixed-order merge, so every block gets the same value); block
   // 0 also stores the merged vector (the minibatch's loss).
@@ -457,19 +505,10 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
     for (uint32_t i = threadIdx.x; i < P.val_blocks; i += kCvThreads)
       pm.add_vector(P.partials + (size_t)i * PartSums<3>::M);
     block_reduce<3, kCvThreads>(pm, ymom, 0);
-    __syncthreads();
-    if (blockIdx.x == 0 && threadIdx.x < PartSums<3>::M) P.ybar_mom[threadIdx.x] = ymom[threadIdx.x];
   }
-  FT* s_w2f = (FT*)lds;
-  FT* s_w2tf = s_w2f + kFragFloats;
-  float* s_lanec = (float*)(lds + 2 * kFragFloats * sizeof(FT));
-  FT* tr = (FT*)(lds + 2 * kFragFloats * sizeof(FT) + kLaneFloats * 4);
-  for (int i = threadIdx.x; i < kFragFloats; i += kCvThreads) {
-    s_w2f[i] = (FT)P.w2f[i];
-    s_w2tf[i] = (FT)P.w2tf[i];
-  }
-  for (int i = threadIdx.x; i < kLaneFloats; i += kCvThreads) s_lanec[i] = P.lanec[i];
+  weights_store<true>(wr, s_w2f, s_w2tf, s_lanec);
   __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x < PartSums<3>::M) P.ybar_mom[threadIdx.x] = ymom[threadIdx.x];
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int row = lane & 31, half = lane >> 5;
@@ -518,11 +557,26 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
       for (int r = 0; r < 16; ++r) T[unit_of(mb, r, half) * kTs + row] = (FT)x[mb * 16 + r];
   };
 
+  // A segment's cached features and price change are loaded one segment
+  // ahead, so that their latency overlaps the segment before.
+  float nf[4], ndst;
+  auto fetch = [&](uint32_t k) {
+    const uint64_t S = P.c_stride, c = P.c_first + pid;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      nf[q] = (half == 0 && active) ? P.c_phi[((size_t)k * 4 + q) * S + c] : 0.f;
+    ndst = active ? P.c_dst[(size_t)k * S + c] : 0.f;
+  };
+  fetch(0);
   for (uint32_t k = 0; k < P.n_seg; ++k) {
     float h1[32], h2[32], phi[8];
-    cached_phi(P, k, pid, half, active, phi);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) phi[q] = nf[q];
+    phi[4] = (half == 0 && active) ? 1.0f : 0.f;
+    phi[5] = phi[6] = phi[7] = 0.f;
+    const float dSt = ndst;
+    if (k + 1 < P.n_seg) fetch(k + 1);
     mlp_forward<BF16>(phi, w1a, s_w2f, s_lanec, lane, h1, h2);
-    const float dSt = active ? P.c_dst[(size_t)k * P.c_stride + P.c_first + pid] : 0.f;
     const float gD = g * dSt;                      // dL/dDelta for this segment
     const float gDh = 0.5f * gD;                   // the constants hold 2 W3
     if (half == 0) gb3 += gD;
@@ -618,43 +672,50 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
   }
 
   // The block's gradient in FP64, in the flat parameter layout W1[64][4],
-  // b1[64], W2[64][64], b2[64], W3[64], b3: the waves add theirs in wave
-  // order into LDS (each slot has one writer per wave), then the block
-  // writes one partial per parameter.
-  double* red = (double*)lds;
+  // b1[64], W2[64][64], b2[64], W3[64], b3: every wave stores its FP32
+  // accumulators into a row of its own (each slot has one writer per wave;
+  // b3's wave sum is FP64 and has a slot of its own), and after one barrier
+  // each thread adds the waves' values of its parameters in wave order in
+  // FP64 (the conversions are exact), so no wave waits on another's
+  // read-modify-write of LDS. The block writes one partial per parameter.
+  float* red = (float*)lds;            // [kCvWaves][kMlpNParam]
+  __shared__ double s3w[kCvWaves];
   __syncthreads();                     // every wave has left the segment loop
-  for (int w = 0; w < kCvWaves; ++w) {
-    if (wave == w) {
-      auto put = [&](int slot, double val) { red[slot] = (w == 0 ? 0.0 : red[slot]) + val; };
+  {
+    float* mine = red + wave * kMlpNParam;
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
+    for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
+      for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int out = unit_of(mb, r, half), in = 32 * nb + row;
-            put(320 + out * 64 + in, (double)gw2[mb][nb][r]);
-          }
-      // gx: lane column `row`, unit u(mb, r, half).
+        for (int r = 0; r < 16; ++r)
+          mine[320 + unit_of(mb, r, half) * 64 + 32 * nb + row] = gw2[mb][nb][r];
+    // gx: lane column `row`, unit u(mb, r, half).
+    if (row <= 6) {
 #pragma unroll
       for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int u = unit_of(mb, r, half);
-          const double x = (double)gx[mb][r];
-          if (row == 0) put(4416 + u, x);                      // b2
-          else if (row == 1) put(4480 + u, x);                 // W3
-          else if (row <= 5) put(u * 4 + (row - 2), x);        // W1
-          else if (row == 6) put(256 + u, x);                  // b1
+          const int slot = row == 0   ? 4416 + u                // b2
+                           : row == 1 ? 4480 + u                // W3
+                           : row <= 5 ? u * 4 + (row - 2)       // W1
+                                      : 256 + u;                // b1
+          mine[slot] = gx[mb][r];
         }
-      const double s3 = wave_sum((double)gb3);
-      if (lane == 0) put(4544, s3);
     }
-    __syncthreads();
+    const double s3 = wave_sum((double)gb3);
+    if (lane == 0) s3w[wave] = s3;
   }
+  __syncthreads();
   // Block-major: the block's 4545 partials are one contiguous row.
-  for (int i = threadIdx.x; i < kMlpNParam; i += kCvThreads)
-    P.grad_partials[(uint64_t)blockIdx.x * kMlpNParam + i] = red[i];
+  for (int i = threadIdx.x; i < kMlpNParam; i += kCvThreads) {
+    double acc = i == kMlpNParam - 1 ? s3w[0] : (double)red[i];
+#pragma unroll
+    for (int w = 1; w < kCvWaves; ++w)
+      acc += i == kMlpNParam - 1 ? s3w[w] : (double)red[w * kMlpNParam + i];
+    P.grad_partials[(uint64_t)blockIdx.x * kMlpNParam + i] = acc;
+  }
 }
 
 // The BF16 form fits two waves per SIMD (256 VGPRs; 77 KB of LDS, two
@@ -681,8 +742,11 @@ __global__ __launch_bounds__(kCvThreads) void cv_eval_kernel(const CvParams P) {
   __shared__ __attribute__((aligned(16))) FT s_w2f[kFragFloats];
   __shared__ __attribute__((aligned(16))) float s_lanec[kLaneFloats];
   const HestonParams& Hp = P.h;
-  for (int i = threadIdx.x; i < kFragFloats; i += kCvThreads) s_w2f[i] = (FT)P.w2f[i];
-  for (int i = threadIdx.x; i < kLaneFloats; i += kCvThreads) s_lanec[i] = P.lanec[i];
+  {
+    WeightRegs wr;
+    weights_load<false>(P.w2f, nullptr, P.lanec, wr);
+    weights_store<false>(wr, s_w2f, (FT*)nullptr, s_lanec);
+  }
   __syncthreads();
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
