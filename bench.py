@@ -219,19 +219,22 @@ def _pilot_then_run(torch, pilot_fn, run_fn, reps=3):
     return pil, t_pil, N, run, t_run, [x[1] + x[4] for x in pairs]
 
 
-def time_to_1bp(ctx, mc, synth, torch, hedge_every=16, adam_steps=2000):
+def time_to_1bp(ctx, mc, synth, torch, hedge_every=16, adam_steps=None):
     """Time to a Heston-Asian price whose standard error is 1 bp of the price
     (1e-4 x price), plain FP32 Monte Carlo against the learned control
     variate with BF16 matrix products. Each estimator: a 2^20-path pilot on
     stream tag 1 sizes N* = (s / (1e-4 p))^2, then one run of N* paths on
     tag 0; both are timed (median of three pairs after an untimed one, see
-    _pilot_then_run). The hedge network is trained beforehand (2000
-    Adam steps, minibatch 2^16 from a fixed 2^20-path set on tag 2); its
-    training time is reported separately and added in `total_incl_train_s`.
+    _pilot_then_run). The hedge network is trained beforehand (the Adam
+    recipe of synth.LEARNED_CV: 1000 steps with a stepped learning rate,
+    minibatch 2^16 from a fixed 2^20-path set on tag 2); its training time
+    is reported separately and added in `total_incl_train_s`.
     """
     import numpy as np
     H = synth.HESTON
     cv = synth.LEARNED_CV
+    if adam_steps is None:
+        adam_steps = cv["adam_steps"]
     n = H["n_steps"]
     model = _heston_model(mc, synth)
     plain_f = mc.Payoff(mc.MC_ASIAN_ARITH_CALL, H["K"])
@@ -247,8 +250,9 @@ def time_to_1bp(ctx, mc, synth, torch, hedge_every=16, adam_steps=2000):
                          "std_err": run["std_err"], "kernel_ms": run["kernel_ms"]}
     th0 = synth.glorot_mlp()
     (w, log), t_train = _timed(torch, lambda: mc.mc_cv_train(
-        ctx, model, cv_f, cv["n_train"], n, synth.SEED, th0, lr=cv["lr"], steps=adam_steps,
-        batch=cv["batch"], hedge_every=hedge_every, prec=mc.MC_BF16_GEMM))
+        ctx, model, cv_f, cv["n_train"], n, synth.SEED, th0, lr=cv["lr"], beta2=cv["beta2"],
+        steps=adam_steps, batch=cv["batch"], hedge_every=hedge_every, prec=mc.MC_BF16_GEMM,
+        decay_every=cv["decay_every"], decay=cv["decay"]))
 
     def opts(tag):
         return mc.Options(prec=mc.MC_BF16_GEMM, cv_weights=w, cv_hedge_every=hedge_every,
@@ -258,6 +262,8 @@ def time_to_1bp(ctx, mc, synth, torch, hedge_every=16, adam_steps=2000):
         torch, lambda: mc.mc_price(ctx, model, cv_f, 1 << 20, n, synth.SEED, opts(1)),
         lambda N: mc.mc_price(ctx, model, cv_f, N, n, synth.SEED, opts(0)))
     out["learned_cv_bf16"] = {"train_s": t_train, "adam_steps": adam_steps,
+                              "adam": {"lr": cv["lr"], "beta2": cv["beta2"],
+                                       "decay": cv["decay"], "decay_every": cv["decay_every"]},
                               "loss_first": float(log[0]), "loss_last": float(np.mean(log[-20:])),
                               "pilot_s": t_pil, "pilot_vrf": pil["vrf"], "n_paths": N_cv,
                               "run_s": t_run, "total_s": t_pil + t_run, "totals_s": totals_cv,
@@ -994,8 +1000,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-time-to-1bp", action="store_true")
     ap.add_argument("--hedge-every", type=int, default=16)
-    ap.add_argument("--adam-steps", type=int, default=2000,
-                    help="training steps of the hedge network in the time-to-1bp comparison")
+    ap.add_argument("--adam-steps", type=int, default=None,
+                    help="training steps of the hedge network in the time-to-1bp comparison "
+                         "(default: the recipe's 1000)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()

@@ -283,13 +283,19 @@ mc_status mc_greeks_adjoint(mc_context *ctx, const mc_model *model,
                             void *ckpt, size_t ckpt_bytes, double grad_out,
                             mc_result *out);
 
-/* Adam settings for mc_cv_train (Kingma and Ba). */
+/* Adam settings for mc_cv_train (Kingma and Ba). The step size of Adam
+ * step t (0-based) is lr * decay^floor(t / decay_every): a step decay of the
+ * learning rate, the moment estimates carried across the drops; decay_every
+ * = 0 keeps lr for every step (decay is then ignored). Zero-initialised
+ * decay fields give the constant rate. */
 typedef struct {
     double lr, beta1, beta2, eps;
     uint32_t steps;            /* Adam steps */
     uint64_t batch;            /* minibatch paths, multiple of 256 */
     uint32_t hedge_every;      /* rebalancing period m >= 1 */
     mc_precision prec;         /* MC_FP32 or MC_BF16_GEMM for the 64x64 layer */
+    uint32_t decay_every;      /* steps between learning-rate drops, 0: none */
+    double decay;              /* factor per drop, in (0, 1] when decay_every > 0 */
 } mc_adam_cfg;
 
 /* Trains the hedge network of the learned control variate on n_train paths

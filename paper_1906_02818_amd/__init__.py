@@ -526,9 +526,10 @@ def mc_greeks_adjoint(ctx: Context, model: Model, payoff: Payoff, n_paths: int, 
 
 def mc_cv_train(ctx: Context, model: Model, payoff: Payoff, n_train: int, n_steps: int, seed: int,
                 weights: np.ndarray, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, steps=2000,
-                batch=1 << 16, hedge_every=1, prec=MC_FP32):
+                batch=1 << 16, hedge_every=1, prec=MC_FP32, decay_every=0, decay=1.0):
     mm = _Marshal(model, payoff, None, n_train)
-    cfg = _abi.McAdamCfg(lr, beta1, beta2, eps, steps, batch, hedge_every, prec)
+    cfg = _abi.McAdamCfg(lr, beta1, beta2, eps, steps, batch, hedge_every, prec, decay_every,
+                         decay)
     w = np.ascontiguousarray(weights, np.float32).copy()
     log = np.zeros(steps, np.float32)
     st = _abi.load().mc_cv_train(ctx.handle, C.byref(mm.cm), C.byref(mm.cp), n_train, n_steps,

@@ -128,7 +128,8 @@ class McLsmPaths(C.Structure):
 class McAdamCfg(C.Structure):
     _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
                 ("eps", C.c_double), ("steps", C.c_uint32), ("batch", C.c_uint64),
-                ("hedge_every", C.c_uint32), ("prec", C.c_int)]
+                ("hedge_every", C.c_uint32), ("prec", C.c_int), ("decay_every", C.c_uint32),
+                ("decay", C.c_double)]
 
 
 _P = C.POINTER

@@ -879,7 +879,7 @@ struct CvTrainWs {
   CvBuffers b;
   float *m, *v;             // Adam moments
   double* log;              // [steps][n_mom] forward-pass moments
-  float *c_phi, *c_dst, *c_delta;
+  float *c_phi, *c_dst;
   double* c_pay;
 };
 
@@ -907,7 +907,6 @@ size_t cv_train_bytes(uint64_t batch, uint32_t n_steps, uint32_t steps, uint64_t
   char* cphi = take((size_t)n_seg * 4 * n_cache * 4);
   char* cdst = take((size_t)n_seg * n_cache * 4);
   char* cpay = take((size_t)n_cache * 8);
-  char* cdel = take((size_t)n_seg * batch * 4);
   if (w && base) {
     w->eval_base = e;
     w->eval_bytes = Lay.bytes;
@@ -920,7 +919,6 @@ size_t cv_train_bytes(uint64_t batch, uint32_t n_steps, uint32_t steps, uint64_t
     w->c_phi = (float*)cphi;
     w->c_dst = (float*)cdst;
     w->c_pay = (double*)cpay;
-    w->c_delta = (float*)cdel;
   }
   return off;
 }
@@ -931,7 +929,6 @@ CvParams cv_cache_params(const CvParams& base, const CvTrainWs& w, uint64_t n_ca
   p.c_phi = w.c_phi;
   p.c_dst = w.c_dst;
   p.c_pay = w.c_pay;
-  p.c_delta = w.c_delta;
   p.c_stride = n_cache;
   p.n_seg = n_seg;
   return p;
@@ -972,7 +969,6 @@ mc_status cv_loss_grad_device(mc_context* ctx, hipStream_t s, const mc_model* m,
   p.partials = partials;
   p.path_out = ypath;
   uint32_t nb = 0;
-  HIP_TRY(ctx, launch_cv_forward(p, s));
   HIP_TRY(ctx, launch_cv_values(p, s, &nb));
   // The backward merges the hedged values' block moments itself (Ybar) and
   // its block 0 stores them in mom.
@@ -2169,6 +2165,8 @@ static mc_status validate_adam(mc_context* ctx, const mc_adam_cfg* cfg, uint64_t
     return fail(ctx, MC_ERR_INVALID_ARG, "bad Adam hyper-parameters");
   if (cfg->batch < 256 || cfg->batch % 256 != 0)
     return fail(ctx, MC_ERR_INVALID_ARG, "batch must be a positive multiple of 256");
+  if (cfg->decay_every > 0 && !(cfg->decay > 0 && cfg->decay <= 1))
+    return fail(ctx, MC_ERR_INVALID_ARG, "decay must lie in (0, 1] when decay_every > 0");
   if (n_train && (n_train < cfg->batch || n_train % cfg->batch != 0))
     return fail(ctx, MC_ERR_INVALID_ARG, "n_train must be a multiple of batch");
   return MC_OK;
@@ -2257,8 +2255,12 @@ mc_status mc_cv_train(mc_context* ctx, const mc_model* m, const mc_payoff* f, ui
     st = cv_loss_grad_device(ctx, s, m, f, n_steps, first, n_train, B, cfg->hedge_every, bf16, w,
                              w.log + (size_t)t * n_mom, &nb);
     if (st != MC_OK) return st;
+    // Step decay of the learning rate; Adam's moments carry across drops.
+    const double lr =
+        cfg->decay_every > 0 ? cfg->lr * std::pow(cfg->decay, (double)(t / cfg->decay_every))
+                             : cfg->lr;
     HIP_TRY(ctx, launch_adam_pack(w.grad_partials, nb, w.grad, w.b.theta, w.m, w.v, (int)t + 1,
-                                  cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, w.b.w1f, w.b.w2f,
+                                  lr, cfg->beta1, cfg->beta2, cfg->eps, w.b.w1f, w.b.w2f,
                                   w.b.w2tf, w.b.lanec, s));
   }
   std::vector<double> log((size_t)cfg->steps * n_mom);

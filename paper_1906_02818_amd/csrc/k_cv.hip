@@ -27,9 +27,9 @@
 // Training. The network's inputs (the features at each segment's opening
 // date) and the segment's price change do not depend on the weights, so
 // the training paths are simulated once into a feature cache; an Adam step
-// then runs only the network: a forward pass over every (segment, 32-path
-// tile) of the minibatch, the per-path hedged values and their moments,
-// and the backward pass. There, for each hedge segment the upstream
+// then runs only the network: a forward pass along every 32-path tile of
+// the minibatch giving the per-path hedged values and their moments, and
+// the backward pass. There, for each hedge segment the upstream
 // derivative dL/dDelta = g_b dSt with g_b = -(2/B)(Y_b - Ybar) is pushed
 // back through the network; dW2 = delta2^T H1 and dW1 = delta1^T [phi; 1]
 // are MFMA products over the wave's 32 paths after a transpose through LDS.
@@ -374,11 +374,16 @@ __global__ __launch_bounds__(kCvThreads) void cv_cache_kernel(const CvParams P) 
   P.c_pay[pid] = Hp.disc * (A > Hp.K ? A - Hp.K : 0.0);
 }
 
-// Network forward pass over every (segment, 32-path tile) of the minibatch
-// (h.n_paths paths from cache path c_first): Delta to c_delta. Waves step
-// through the items, so a launch needs only enough of them to fill the chip.
+// Hedged values of the minibatch's paths (h.n_paths paths from cache path
+// c_first): a wave takes a 32-path tile through every hedge segment, the
+// network's Delta from the cached features, H = sum_k Delta_k dSt_k in
+// segment order and Y = payoff - H. The per-path values (channels payoff,
+// H, Y) go to path_out when it is set, their block moments to partials.
+// Lane l < 32 owns path l of the tile (lane l + 32 holds the other half of
+// the hidden units), and the next segment's inputs are loaded one segment
+// ahead, so that their latency overlaps the network.
 template <bool BF16>
-__global__ __launch_bounds__(kCvThreads) void cv_fwd_kernel(const CvParams P) {
+__global__ __launch_bounds__(kCvThreads) void cv_values_kernel(const CvParams P) {
   using FT = FragT<BF16>;
   __shared__ __attribute__((aligned(16))) FT s_w2f[kFragFloats];
   __shared__ __attribute__((aligned(16))) float s_lanec[kLaneFloats];
@@ -399,64 +404,43 @@ __global__ __launch_bounds__(kCvThreads) void cv_fwd_kernel(const CvParams P) {
     w1a[mb] = op_from<BF16>(w);
   }
   const float c3 = out_const(P.theta);
-  const uint64_t n = P.h.n_paths, ntiles = (n + 31) / 32;
-  const uint64_t items = ntiles * P.n_seg;
-  const uint64_t nw = (uint64_t)gridDim.x * kCvWaves;
-  // An item's cached features are loaded one item ahead, so that their
-  // latency overlaps the item before.
-  uint32_t nk = 0;
-  uint64_t np = 0;
-  float nf[4];
-  auto fetch = [&](uint64_t it) {
-    nk = (uint32_t)(it / ntiles);
-    np = (it % ntiles) * 32 + row;
-    const bool act = half == 0 && np < n;
-    const uint64_t S = P.c_stride, c = P.c_first + np;
+  const uint64_t n = P.h.n_paths;
+  const uint64_t pid = ((uint64_t)blockIdx.x * kCvWaves + wave) * 32 + row;
+  const bool active = pid < n;
+  const bool owner = active && half == 0;
+  const uint64_t S = P.c_stride, c = P.c_first + pid;
+  float nf[4], ndst;
+  auto fetch = [&](uint32_t k) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) nf[q] = act ? P.c_phi[((size_t)nk * 4 + q) * S + c] : 0.f;
+    for (int q = 0; q < 4; ++q) nf[q] = owner ? P.c_phi[((size_t)k * 4 + q) * S + c] : 0.f;
+    ndst = owner ? P.c_dst[(size_t)k * S + c] : 0.f;
   };
-  uint64_t it = (uint64_t)blockIdx.x * kCvWaves + wave;
-  if (it < items) fetch(it);
-  for (; it < items; it += nw) {
-    const uint32_t k = nk;
-    const uint64_t p = np;
-    const bool active = p < n;
+  fetch(0);
+  float H = 0.f;
+  for (uint32_t k = 0; k < P.n_seg; ++k) {
     float phi[8];
 #pragma unroll
     for (int q = 0; q < 4; ++q) phi[q] = nf[q];
-    phi[4] = (half == 0 && active) ? 1.0f : 0.f;
+    phi[4] = owner ? 1.0f : 0.f;
     phi[5] = phi[6] = phi[7] = 0.f;
-    if (it + nw < items) fetch(it + nw);
+    const float dst = ndst;
+    if (k + 1 < P.n_seg) fetch(k + 1);
     const float d = mlp_delta<BF16>(phi, w1a, s_w2f, s_lanec, lane, c3);
-    if (half == 0 && active) P.c_delta[(size_t)k * n + p] = d;
+    H = __builtin_fmaf(d, dst, H);
   }
-}
-
-// Hedged values of the minibatch's paths, H = sum_k Delta_k dSt_k in
-// segment order, and their moments (channels payoff, H, Y = payoff - H);
-// one path per lane.
-__global__ __launch_bounds__(kCvThreads) void cv_values_kernel(const CvParams P) {
-  const uint64_t n = P.h.n_paths;
-  const uint64_t pid = (uint64_t)blockIdx.x * kCvThreads + threadIdx.x;
-  const bool active = pid < n;
   double y[3] = {0.0, 0.0, 0.0};
-  if (active) {
-    const uint64_t S = P.c_stride, c = P.c_first + pid;
-    float H = 0.f;
-#pragma unroll 4
-    for (uint32_t k = 0; k < P.n_seg; ++k)
-      H = __builtin_fmaf(P.c_delta[(size_t)k * n + pid], P.c_dst[(size_t)k * S + c], H);
+  if (owner) {
     const double pay = P.c_pay[c];
     y[0] = pay;
     y[1] = (double)H;
     y[2] = pay - (double)H;
   }
   const bool finite = isfinite(y[0]) && isfinite(y[1]) && isfinite(y[2]);
-  if (active && P.path_out != nullptr) {
+  if (owner && P.path_out != nullptr) {
 #pragma unroll
     for (int q = 0; q < 3; ++q) P.path_out[pid * 3 + q] = y[q];
   }
-  block_moments<3, kCvThreads>(y, active && finite, active && !finite, P.partials);
+  block_moments<3, kCvThreads>(y, owner && finite, owner && !finite, P.partials);
 }
 
 // Backward pass: a wave takes 32 paths of the minibatch through every hedge
@@ -965,25 +949,14 @@ hipError_t launch_cv_cache(const CvParams& p, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Enough waves to fill the chip at the kernel's occupancy; each steps
-// through the (segment, tile) items.
-hipError_t launch_cv_forward(const CvParams& p, hipStream_t s) {
-  const uint64_t items = (p.h.n_paths + 31) / 32 * p.n_seg;
-  const uint64_t need = (items + kCvWaves - 1) / kCvWaves;
-  const uint32_t nb = (uint32_t)(need < 2048 ? need : 2048);
-  if (nb == 0 || p.c_first + p.h.n_paths > p.c_stride) return hipErrorInvalidValue;
-  if (p.bf16)
-    hipLaunchKernelGGL((cv_fwd_kernel<true>), dim3(nb), dim3(kCvThreads), 0, s, p);
-  else
-    hipLaunchKernelGGL((cv_fwd_kernel<false>), dim3(nb), dim3(kCvThreads), 0, s, p);
-  return hipGetLastError();
-}
-
 hipError_t launch_cv_values(const CvParams& p, hipStream_t s, uint32_t* n_blocks) {
-  const uint32_t nb = (uint32_t)((p.h.n_paths + kCvThreads - 1) / kCvThreads);
+  const uint32_t nb = (uint32_t)((p.h.n_paths + kCvTrainPathsPerBlock - 1) / kCvTrainPathsPerBlock);
   *n_blocks = nb;
   if (nb == 0 || p.c_first + p.h.n_paths > p.c_stride) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(cv_values_kernel, dim3(nb), dim3(kCvThreads), 0, s, p);
+  if (p.bf16)
+    hipLaunchKernelGGL((cv_values_kernel<true>), dim3(nb), dim3(kCvThreads), 0, s, p);
+  else
+    hipLaunchKernelGGL((cv_values_kernel<false>), dim3(nb), dim3(kCvThreads), 0, s, p);
   return hipGetLastError();
 }
 

@@ -245,7 +245,6 @@ struct CvParams {
   float* c_phi;              // [n_seg][4][c_stride] features at the segment's opening date
   float* c_dst;              // [n_seg][c_stride] discounted price change over the segment
   double* c_pay;             // [c_stride] discounted payoff
-  float* c_delta;            // [n_seg][n_paths] network output on the minibatch
   uint64_t c_stride;         // paths held by the cache
   uint64_t c_first;          // the minibatch's first path within the cache
   uint32_t n_seg;            // ceil(n_steps / hedge_every)
@@ -258,10 +257,9 @@ hipError_t launch_cv_pack(const float* theta, float* w1f, float* w2f, float* w2t
                           hipStream_t s);
 hipError_t launch_cv_price(const CvParams& p, hipStream_t s, uint32_t* n_blocks);
 // Training on the feature cache: fill it (h.n_paths paths from h.path_offset),
-// the network on every (segment, 32-path tile) of the minibatch, the per-path
+// the network along every 32-path tile of the minibatch with the per-path
 // hedged values and their moments, and the gradient partials.
 hipError_t launch_cv_cache(const CvParams& p, hipStream_t s);
-hipError_t launch_cv_forward(const CvParams& p, hipStream_t s);
 hipError_t launch_cv_values(const CvParams& p, hipStream_t s, uint32_t* n_blocks);
 hipError_t launch_cv_backward(const CvParams& p, hipStream_t s, uint32_t* n_blocks);
 // Reduces the per-block gradient partials [n_blocks][kMlpNParam], takes one

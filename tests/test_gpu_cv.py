@@ -176,11 +176,24 @@ def test_loss_gradient_matches_oracle(ctx, prec, tol, m_every, n):
         assert blk < 10 * tol, (a, b, blk)
 
 
-def test_adam_steps_match_oracle(ctx):
+@pytest.mark.parametrize("decay", [0.0, -0.5, 1.5, float("nan")])
+def test_adam_rejects_a_bad_decay(ctx, decay):
+    th0 = weights(0.2, seed=6)
+    with pytest.raises(mc.McError) as e:
+        mc.mc_cv_train(ctx, MODEL, PAY, 256, 8, SEED, th0, steps=1, batch=256, hedge_every=1,
+                       decay_every=10, decay=decay)
+    assert e.value.status == mc._abi.MC_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("decay_every,decay", [(0, 1.0), (2, 0.25)])
+def test_adam_steps_match_oracle(ctx, decay_every, decay):
+    # With a step decay, Adam step t (1-based) takes lr * decay^((t-1) //
+    # decay_every) and keeps its moment estimates across the drop.
     th0 = weights(0.2, seed=6)
     B, n, steps, lr = 256, 8, 4, 1e-3
     w, log = mc.mc_cv_train(ctx, MODEL, PAY, 2 * B, n, SEED, th0, lr=lr, steps=steps, batch=B,
-                            hedge_every=1, prec=mc.MC_FP32)
+                            hedge_every=1, prec=mc.MC_FP32, decay_every=decay_every,
+                            decay=decay)
     th = th0.copy()
     m = np.zeros_like(th)
     v = np.zeros_like(th)
@@ -188,7 +201,8 @@ def test_adam_steps_match_oracle(ctx):
     for t in range(1, steps + 1):
         loss, g = oracle.cv_loss_grad(H, n, th, B, SEED, tag=2, path0=((t - 1) % 2) * B)
         losses.append(loss)
-        th, m, v = oracle.adam_step(th, g, m, v, t, lr=lr)
+        lr_t = lr * decay ** ((t - 1) // decay_every) if decay_every else lr
+        th, m, v = oracle.adam_step(th, g, m, v, t, lr=lr_t)
     say("  losses gpu", log, "oracle", losses)
     np.testing.assert_allclose(log, losses, rtol=1e-4)
     d = np.abs(w - th)
