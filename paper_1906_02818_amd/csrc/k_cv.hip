@@ -45,6 +45,8 @@ namespace mcp {
 namespace {
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+typedef __attribute__((ext_vector_type(2))) float float2_t;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
 
 constexpr int kCvWaves = 4;
@@ -410,10 +412,15 @@ __global__ __launch_bounds__(kCvThreads) void cv_values_kernel(const CvParams P)
   const bool owner = active && half == 0;
   const uint64_t S = P.c_stride, c = P.c_first + pid;
   float nf[4], ndst;
+  // Row bases are uniform; the lane adds a 32-bit byte offset (the
+  // launcher keeps the minibatch below 2^30 paths).
+  const uint32_t ob = (uint32_t)pid * 4u;
+  auto at = [&](const float* rowp) { return *(const float*)((const char*)rowp + ob); };
   auto fetch = [&](uint32_t k) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) nf[q] = owner ? P.c_phi[((size_t)k * 4 + q) * S + c] : 0.f;
-    ndst = owner ? P.c_dst[(size_t)k * S + c] : 0.f;
+    for (int q = 0; q < 4; ++q)
+      nf[q] = owner ? at(P.c_phi + ((size_t)k * 4 + q) * S + P.c_first) : 0.f;
+    ndst = owner ? at(P.c_dst + (size_t)k * S + P.c_first) : 0.f;
   };
   fetch(0);
   float H = 0.f;
@@ -534,22 +541,40 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
   auto a_frag = [&](const FT* T, int pk, int mb) {
     return op_lds<BF16>(&T[(32 * mb + row) * kTs + 16 * pk + 8 * half]);
   };
+  // Units u(mb, r) and u(mb, r + 1), r even, are consecutive rows: in the
+  // BF16 form one packed conversion makes both, stored as its low and high
+  // halves.
   auto to_T = [&](FT* T, const float (&x)[32]) {
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) T[unit_of(mb, r, half) * kTs + row] = (FT)x[mb * 16 + r];
+      for (int r = 0; r < 16; r += 2) {
+        FT* t = &T[unit_of(mb, r, half) * kTs + row];
+        if constexpr (BF16) {
+          const bf16x2 p = __builtin_convertvector((float2_t){x[mb * 16 + r], x[mb * 16 + r + 1]},
+                                                   bf16x2);
+          t[0] = p[0];
+          t[kTs] = p[1];
+        } else {
+          t[0] = x[mb * 16 + r];
+          t[kTs] = x[mb * 16 + r + 1];
+        }
+      }
   };
 
   // A segment's cached features and price change are loaded one segment
   // ahead, so that their latency overlaps the segment before.
   float nf[4], ndst;
+  // Row bases are uniform; the lane adds a 32-bit byte offset (the
+  // launcher keeps the minibatch below 2^30 paths).
+  const uint32_t ob = (uint32_t)pid * 4u;
+  auto at = [&](const float* rowp) { return *(const float*)((const char*)rowp + ob); };
   auto fetch = [&](uint32_t k) {
-    const uint64_t S = P.c_stride, c = P.c_first + pid;
+    const uint64_t S = P.c_stride;
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-      nf[q] = (half == 0 && active) ? P.c_phi[((size_t)k * 4 + q) * S + c] : 0.f;
-    ndst = active ? P.c_dst[(size_t)k * S + c] : 0.f;
+      nf[q] = (half == 0 && active) ? at(P.c_phi + ((size_t)k * 4 + q) * S + P.c_first) : 0.f;
+    ndst = active ? at(P.c_dst + (size_t)k * S + P.c_first) : 0.f;
   };
   fetch(0);
   for (uint32_t k = 0; k < P.n_seg; ++k) {
@@ -674,19 +699,15 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
 #pragma unroll
         for (int r = 0; r < 16; ++r)
           mine[320 + unit_of(mb, r, half) * 64 + 32 * nb + row] = gw2[mb][nb][r];
-    // gx: lane column `row`, unit u(mb, r, half).
+    // gx: lane column `row`, unit u(mb, r, half), at slot base + u * step:
+    // b2 (column 0), W3 (1), W1 (2..5, one input each), b1 (6).
     if (row <= 6) {
+      const int base = row == 0 ? 4416 : row == 1 ? 4480 : row <= 5 ? row - 2 : 256;
+      const int step = (row >= 2 && row <= 5) ? 4 : 1;
 #pragma unroll
       for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int u = unit_of(mb, r, half);
-          const int slot = row == 0   ? 4416 + u                // b2
-                           : row == 1 ? 4480 + u                // W3
-                           : row <= 5 ? u * 4 + (row - 2)       // W1
-                                      : 256 + u;                // b1
-          mine[slot] = gx[mb][r];
-        }
+        for (int r = 0; r < 16; ++r) mine[base + unit_of(mb, r, half) * step] = gx[mb][r];
     }
     const double s3 = wave_sum((double)gb3);
     if (lane == 0) s3w[wave] = s3;
@@ -952,7 +973,8 @@ hipError_t launch_cv_cache(const CvParams& p, hipStream_t s) {
 hipError_t launch_cv_values(const CvParams& p, hipStream_t s, uint32_t* n_blocks) {
   const uint32_t nb = (uint32_t)((p.h.n_paths + kCvTrainPathsPerBlock - 1) / kCvTrainPathsPerBlock);
   *n_blocks = nb;
-  if (nb == 0 || p.c_first + p.h.n_paths > p.c_stride) return hipErrorInvalidValue;
+  if (nb == 0 || p.c_first + p.h.n_paths > p.c_stride || p.h.n_paths >= (1ull << 30))
+    return hipErrorInvalidValue;
   if (p.bf16)
     hipLaunchKernelGGL((cv_values_kernel<true>), dim3(nb), dim3(kCvThreads), 0, s, p);
   else
@@ -963,7 +985,8 @@ hipError_t launch_cv_values(const CvParams& p, hipStream_t s, uint32_t* n_blocks
 hipError_t launch_cv_backward(const CvParams& p, hipStream_t s, uint32_t* n_blocks) {
   const uint32_t nb = (uint32_t)((p.h.n_paths + kCvTrainPathsPerBlock - 1) / kCvTrainPathsPerBlock);
   *n_blocks = nb;
-  if (nb == 0 || p.c_first + p.h.n_paths > p.c_stride) return hipErrorInvalidValue;
+  if (nb == 0 || p.c_first + p.h.n_paths > p.c_stride || p.h.n_paths >= (1ull << 30))
+    return hipErrorInvalidValue;
   if (p.bf16)
     hipLaunchKernelGGL(cv_bwd_kernel_bf16, dim3(nb), dim3(kCvThreads), 0, s, p);
   else
