@@ -390,16 +390,13 @@ def run_asian_barrier(args, ctx, mc, synth, torch):
     c = synth.ASIAN_BARRIER
     N, n = c["n_paths"], c["n_steps"]
     model = mc.Model(kind=mc.MC_GBM, S0=c["S0"], r=c["r"], T=c["T"], sigma=c["sigma"])
-    # The control-variate coefficient comes from a pilot on stream tag 1,
-    # once, before timing (it is an input of the estimator, not of the step).
-    pilot = mc.mc_price(ctx, model, mc.Payoff(mc.MC_ASIAN_ARITH_CALL, c["K"],
-                                              cv=mc.MC_CV_GEO_ASIAN), N, n, synth.SEED,
-                        mc.Options(pilot_paths=1 << 20))
-    beta = pilot["cv_beta"]
+    # A step is one whole pricing: the control-variate coefficient comes from
+    # the step's own paths (in sample), so no pilot runs before or inside it.
+    insample = mc.Options(pilot_paths=mc.MC_PILOT_IN_SAMPLE)
     payoffs = [mc.Payoff(mc.MC_ASIAN_ARITH_CALL, c["K"], cv=mc.MC_CV_GEO_ASIAN),
                mc.Payoff(mc.MC_UO_BARRIER_CALL, c["K"], B=c["B"]),
                mc.Payoff(mc.MC_ASIAN_GEO_CALL, c["K"])]
-    step = mc.PreparedPriceMulti(ctx, model, payoffs, N, n, synth.SEED, mc.Options(cv_beta=beta))
+    step = mc.PreparedPriceMulti(ctx, model, payoffs, N, n, synth.SEED, insample)
     ms, outs = _repeat(args, torch, lambda: step()[0].kernel_ms)
     k_ms = sum(outs) / len(outs)
     res = step.results()
@@ -415,13 +412,13 @@ def run_asian_barrier(args, ctx, mc, synth, torch):
                          "asian_plain": res[0]["plain_price"],
                          "asian_plain_se": res[0]["plain_std_err"],
                          "uo": res[1]["price"], "uo_se": res[1]["std_err"],
-                         "geo": res[2]["price"], "geo_se": res[2]["std_err"], "cv_beta": beta,
-                         "vrf": res[0]["vrf"]})
+                         "geo": res[2]["price"], "geo_se": res[2]["std_err"],
+                         "cv_beta": res[0]["cv_beta"], "vrf": res[0]["vrf"]})
     # Outside the timed region: the same paths with FP64 state, each FP32
     # price's distance from it in standard errors, and the geometric Asian
     # against its closed form.
     r64 = mc.mc_price_multi(ctx, model, payoffs, N, n, synth.SEED,
-                            mc.Options(prec=mc.MC_FP64, cv_beta=beta))
+                            mc.Options(prec=mc.MC_FP64, pilot_paths=mc.MC_PILOT_IN_SAMPLE))
     pairs = (("asian_cv", res[0]["price"], r64[0]["price"], r64[0]["std_err"]),
              ("asian_plain", res[0]["plain_price"], r64[0]["plain_price"],
               r64[0]["plain_std_err"]),

@@ -140,6 +140,12 @@ typedef enum {
 } mc_greeks_method;
 
 #define MC_MLP_NPARAM 4545     /* 4-64-64-1 hedge network, FP32 */
+/* mc_options.pilot_paths value: the geometric-Asian control variate's
+ * coefficient beta = Cov(A, G) / Var(G) is taken from the paths it corrects
+ * (the usual in-sample estimator: no pilot run, a bias of order 1/n_paths);
+ * MC_ERR_UNSUPPORTED with the learned control variate, whose pilot decides
+ * the fallback to plain Monte Carlo. */
+#define MC_PILOT_IN_SAMPLE UINT64_MAX
 
 typedef struct {
     mc_precision prec;         /* default MC_FP32 */
@@ -156,7 +162,9 @@ typedef struct {
                                   1 with a pilot run deciding between the hedged
                                   estimator and plain MC (mc_result.cv_fallback);
                                   on fallback path_values are not written */
-    uint64_t pilot_paths;      /* pilot size (tag 1) for beta / fallback; 0 = 2^16 */
+    uint64_t pilot_paths;      /* pilot size (tag 1) for beta / fallback; 0 = 2^16;
+                                  MC_PILOT_IN_SAMPLE: the static CV's beta from the
+                                  main run's own moments (no pilot) */
     double *path_values;       /* optional host [n_paths * mc_path_channels()]
                                   per-path values (testing and diagnostics) */
     uint32_t greeks_method;    /* mc_greeks_method, default MC_GREEKS_PATHWISE */

@@ -25,6 +25,7 @@ from ._abi import (MC_ADJ_FULL, MC_ADJ_FWD, MC_ADJ_REV, MC_ASIAN_ARITH_CALL, MC_
                    MC_GREEKS_PATHWISE, MC_GREEKS_TANGENT, MC_GREEK_DELTA, MC_GREEK_VEGA,
                    MC_HESTON, MC_LOG_EULER, MC_LSM_BASKET_CALL, MC_LSM_BASKET_PUT,
                    MC_LSM_MAX_CALL, MC_LSM_MAX_DATES, MC_LSM_MAX_FEATURES, MC_MAX_STRIKES, MC_MLMC_MAX_LEVELS, MC_MLP_NPARAM, MC_OK,
+                   MC_PILOT_IN_SAMPLE,
                    MC_QMC_MAX_REPLICATES, MC_UO_BARRIER_CALL, MC_UO_BRIDGE_CALL)
 
 __all__ = [n for n in dir(_abi) if n.startswith("MC_")] + [

@@ -22,6 +22,7 @@ MC_GREEK_DELTA, MC_GREEK_VEGA = 1, 2
 MC_ADJ_FULL, MC_ADJ_FWD, MC_ADJ_REV = 0, 1, 2
 MC_GREEKS_PATHWISE, MC_GREEKS_FD_CRN, MC_GREEKS_TANGENT = 0, 1, 2
 MC_MLP_NPARAM = 4545
+MC_PILOT_IN_SAMPLE = (1 << 64) - 1
 MC_MLMC_MAX_LEVELS = 8
 MC_MAX_STRIKES = 8
 MC_QMC_MAX_REPLICATES = 64

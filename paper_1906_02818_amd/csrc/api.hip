@@ -284,6 +284,8 @@ mc_status validate_model_payoff(mc_context* ctx, const mc_model* m, const mc_pay
       if (o.prec != MC_FP32 && o.prec != MC_BF16_GEMM)
         return fail(ctx, MC_ERR_UNSUPPORTED, "learned CV runs in MC_FP32 or MC_BF16_GEMM");
       if (!o.cv_weights) return fail(ctx, MC_ERR_INVALID_ARG, "MC_CV_LEARNED needs cv_weights");
+      if (o.pilot_paths == MC_PILOT_IN_SAMPLE && !std::isfinite(o.cv_beta))
+        return fail(ctx, MC_ERR_UNSUPPORTED, "the learned CV's fallback needs a pilot run");
       return MC_OK;
     }
     if (o.prec != MC_FP32 && o.prec != MC_FP64)
@@ -588,7 +590,10 @@ mc_status gbm_result(mc_context* ctx, const mc_model* m, const mc_payoff* f, uin
       return fail(ctx, MC_ERR_UNSUPPORTED, "geometric-Asian CV needs the log-Euler scheme");
     const int a = c, gi = gbm_channel_index(mask, G_GEO);
     double beta = o.cv_beta;
-    if (!std::isfinite(beta)) {
+    if (!std::isfinite(beta) && o.pilot_paths == MC_PILOT_IN_SAMPLE) {
+      // In sample: the coefficient from the main paths' own moments.
+      beta = mom.cov(a, gi) / mom.cov(gi, gi);
+    } else if (!std::isfinite(beta)) {
       // Pilot on stream tag+1 (independent of the main paths).
       Moments pm;
       uint32_t pmask;
@@ -1541,7 +1546,9 @@ size_t mc_workspace_bytes(const mc_model* m, const mc_payoff* f, uint64_t n_path
       (n_steps + mcp::kCkpt - 1) / mcp::kCkpt > (uint32_t)mcp::kLdsCkpt)
     bytes = align256(bytes) + align256(mc_adjoint_ckpt_bytes(n_paths, n_steps, mcp::kCkpt));
   if (m->kind == MC_HESTON && f->cv == MC_CV_LEARNED) {
-    const uint64_t n_pilot = o.pilot_paths ? o.pilot_paths : (1ull << 16);
+    const uint64_t n_pilot = o.pilot_paths == MC_PILOT_IN_SAMPLE ? 0
+                             : o.pilot_paths                     ? o.pilot_paths
+                                                                 : (1ull << 16);
     const uint64_t n_big = n_paths > n_pilot ? n_paths : n_pilot;
     bytes = align256(layout_for(n_big, 3, o.path_values != nullptr, kCvPathsPerBlock).bytes) +
             cv_extra_bytes(n_steps);

@@ -194,6 +194,12 @@ HES = mc.Model(kind=mc.MC_HESTON, S0=100.0, r=0.02, T=1.0, v0=0.04, kappa=2.0, t
      mc._abi.MC_ERR_UNSUPPORTED),
     (HES, mc.Payoff(mc.MC_ASIAN_ARITH_CALL, 100.0), 16, 4,
      mc.Options(greeks=3, prec=mc.MC_FP64), mc._abi.MC_ERR_UNSUPPORTED),
+    (HES, mc.Payoff(mc.MC_ASIAN_ARITH_CALL, 100.0, cv=mc.MC_CV_LEARNED), 256, 16,
+     mc.Options(cv_weights=np.zeros(mc.MC_MLP_NPARAM, np.float32),
+                pilot_paths=mc.MC_PILOT_IN_SAMPLE), mc._abi.MC_ERR_UNSUPPORTED),
+    (HES, mc.Payoff(mc.MC_ASIAN_ARITH_CALL, 100.0, cv=mc.MC_CV_LEARNED), 256, 16,
+     mc.Options(cv_weights=np.zeros(mc.MC_MLP_NPARAM, np.float32), cv_beta=1.0,
+                pilot_paths=mc.MC_PILOT_IN_SAMPLE), mc.MC_OK),
 ])
 def test_validation_without_device(model, payoff, n_paths, n_steps, opts, want):
     assert mc.mc_validate(model, payoff, n_paths, n_steps, opts) == want

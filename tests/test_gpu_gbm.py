@@ -205,6 +205,26 @@ def test_geometric_control_variate_with_pilot(ctx):
     assert abs(r["price"] - r["plain_price"]) < 3 * r["plain_std_err"]
 
 
+
+def test_geometric_control_variate_in_sample(ctx):
+    # MC_PILOT_IN_SAMPLE: beta = Cov(A, G) / Var(G) from the priced paths
+    # themselves and the price A - beta (G - C_G) on the same paths, both
+    # against the oracle's per-path values (FP64 paths, ragged path count).
+    c = synth.ASIAN_BARRIER
+    N, n = (1 << 16) + 37, 64
+    model = gbm_model(c)
+    f = mc.Payoff(mc.MC_ASIAN_ARITH_CALL, c["K"], cv=mc.MC_CV_GEO_ASIAN)
+    r = mc.mc_price(ctx, model, f, N, n, SEED,
+                    mc.Options(prec=mc.MC_FP64, pilot_paths=mc.MC_PILOT_IN_SAMPLE))
+    o = oracle.gbm(c["S0"], c["r"], c["sigma"], c["T"], c["K"], 1e300, n, N, SEED)
+    beta = oracle.cv_beta(o[:, 1], o[:, 2])
+    est = oracle.cv_estimate(o[:, 1], o[:, 2],
+                             geo_asian_call(c["S0"], c["K"], c["r"], c["sigma"], c["T"], n), beta)
+    say("  beta gpu", r["cv_beta"], "oracle", beta, "price", r["price"], est["price"])
+    assert abs(r["cv_beta"] / beta - 1.0) < 1e-9
+    assert abs(r["price"] - est["price"]) < 1e-10 * est["price"]
+    assert abs(r["std_err"] / est["std_err"] - 1.0) < 1e-6
+
 # ----------------------------------------------------------- edge cases --
 @pytest.mark.parametrize("N,n,offset,scheme,prec", [
     (1000, 7, 0, mc.MC_LOG_EULER, mc.MC_FP32),
