@@ -295,7 +295,9 @@ mc_status mc_greeks_adjoint(mc_context *ctx, const mc_model *model,
  * step t (0-based) is lr * decay^floor(t / decay_every): a step decay of the
  * learning rate, the moment estimates carried across the drops; decay_every
  * = 0 keeps lr for every step (decay is then ignored). Zero-initialised
- * decay fields give the constant rate. */
+ * decay fields give the constant rate. MC_ERR_INVALID_ARG: lr, eps not
+ * positive, beta1 or beta2 outside [0, 1), batch not a positive multiple of
+ * 256, decay outside (0, 1] while decay_every > 0. */
 typedef struct {
     double lr, beta1, beta2, eps;
     uint32_t steps;            /* Adam steps */
