@@ -33,7 +33,7 @@
 // derivative dL/dDelta = g_b dSt with g_b = -(2/B)(Y_b - Ybar) is pushed
 // back through the network; dW2 = delta2^T H1 and dW1 = delta1^T [phi; 1]
 // are MFMA products over the wave's 32 paths after a transpose through LDS.
-// Each wave writes its partial gradient in FP64; a fixed-order reduction
+// Each block writes its partial gradient in FP64; a fixed-order reduction
 // and the Adam kernel follow.
 #include <type_traits>
 
