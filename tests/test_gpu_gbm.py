@@ -190,7 +190,13 @@ def test_asian_barrier_full_size_sampled_paths(ctx):
     say("  geo", geo, "+-", se, "closed form", cg)
     assert abs(geo - cg) < 4 * se
     assert np.all(pv[:, 0] >= pv[:, 1] - 1e-3)
+    # The estimate and its standard error from the block moments (8192
+    # blocks: merged in two stages, chunks of 2048 blocks, then the chunk
+    # heads) against the per-path values.
     assert abs(r["price"] - pv[:, 2].mean()) < 1e-9 * r["price"]
+    se_path = pv[:, 2].std(ddof=1) / math.sqrt(N)
+    say("  se merged", r["std_err"], "per-path", se_path)
+    assert abs(r["std_err"] / se_path - 1.0) < 1e-9
 
 
 def test_geometric_control_variate_with_pilot(ctx):
