@@ -226,7 +226,7 @@ def time_to_1bp(ctx, mc, synth, torch, hedge_every=16, adam_steps=None):
     stream tag 1 sizes N* = (s / (1e-4 p))^2, then one run of N* paths on
     tag 0; both are timed (median of three pairs after an untimed one, see
     _pilot_then_run). The hedge network is trained beforehand (the Adam
-    recipe of synth.LEARNED_CV: 1000 steps with a stepped learning rate,
+    recipe of synth.LEARNED_CV: 2000 steps with a stepped learning rate,
     minibatch 2^16 from a fixed 2^20-path set on tag 2); its training time
     is reported separately and added in `total_incl_train_s`.
     """
@@ -999,7 +999,7 @@ def main():
     ap.add_argument("--hedge-every", type=int, default=16)
     ap.add_argument("--adam-steps", type=int, default=None,
                     help="training steps of the hedge network in the time-to-1bp comparison "
-                         "(default: the recipe's 1000)")
+                         "(default: the recipe's 2000)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
