@@ -9,10 +9,11 @@ one step at a time). This module only marshals numpy arrays through ctypes
 and adds the estimator formulas of Eq. (3) and the bias-variance split of
 Sec. V-B, plus the Adam update used to train the learned control variate.
 
-Parity unpinned: the arithmetic-Asian call price with volatility (no closed
-form); its K = 0 mean, its zero-volatility value at any K, its ordering
-against the geometric Asian and its pathwise tangents are pinned by the
-tests.
+The arithmetic-Asian call price has no closed form for many fixings; the
+tests pin its K = 0 mean, its zero-volatility value at any K, its ordering
+against the geometric Asian, its pathwise tangents, its one-fixing case (the
+European call) and its two-fixing price at K > 0 with volatility (a
+one-dimensional quadrature of a Black-Scholes inner expectation).
 """
 from __future__ import annotations
 

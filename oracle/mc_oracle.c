@@ -17,11 +17,12 @@
  *
  * Per-path outputs are written row-major: out[p * n_channels + c].
  *
- * Parity unpinned: the arithmetic-Asian call price (GBM channel "asian",
- * Heston channel "asian") has no closed form. Its K = 0 mean (exact), its
- * zero-volatility value at any K (exact), its ordering against the
- * geometric Asian and its pathwise tangents are pinned; the price at K > 0
- * with volatility is not.
+ * The arithmetic-Asian call price (GBM channel "asian", Heston channel
+ * "asian") has no closed form for many fixings. It is pinned by its K = 0
+ * mean (exact), its zero-volatility value at any K (exact), its ordering
+ * against the geometric Asian, its pathwise tangents, its one-fixing case
+ * (the European call) and, at K > 0 with volatility, the two-fixing price
+ * (a one-dimensional quadrature of a Black-Scholes inner expectation).
  */
 #include <math.h>
 #include <stdint.h>

@@ -52,6 +52,35 @@ def geo_asian_call(S0, K, r, sigma, T, n):
 
 # Continuously monitored up-and-out call, barrier H above the strike
 # (Merton 1973; Reiner-Rubinstein 1991), no rebate.
+def arith_asian2_call(S0, K, r, sigma, T):
+    """Arithmetic-average Asian call on two fixings, S(T/2) and S(T), under
+    GBM: e^{-rT} E[((S_1 + S_2)/2 - K)^+]. Given S_1 the inner expectation
+    is a Black-Scholes call on S_2 / 2 over the second half with strike
+    K - S_1 / 2 (or a forward when that strike is not positive); the outer
+    expectation over the first half's normal is an adaptive quadrature."""
+    dt = 0.5 * T
+    sd = sigma * math.sqrt(dt)
+    mu = (r - 0.5 * sigma * sigma) * dt
+
+    def inner(z):
+        a = 0.5 * S0 * math.exp(mu + sd * z)          # S_1 / 2
+        fwd = a * math.exp(r * dt)                     # E[S_2 / 2 | S_1]
+        kp = K - a
+        if kp <= 0.0:
+            v = a + fwd - K
+        else:
+            d1 = (math.log(a / kp) + (r + 0.5 * sigma * sigma) * dt) / sd
+            v = fwd * norm.cdf(d1) - kp * norm.cdf(d1 - sd)
+        return v * norm.pdf(z)
+
+    # The integrand has a kink where K - S_1 / 2 changes sign.
+    zk = (math.log(2.0 * K / S0) - mu) / sd
+    lo, hi = -14.0, 14.0
+    pts = [zk] if lo < zk < hi else None
+    val, _ = integrate.quad(inner, lo, hi, points=pts, epsabs=1e-13, epsrel=1e-12, limit=400)
+    return math.exp(-r * T) * val
+
+
 def up_out_call(S, K, H, r, sigma, T):
     if S >= H:
         return 0.0

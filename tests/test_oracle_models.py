@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 import synth
-from closed_forms import (bs_call, bs_delta, bs_vega, geo_asian_call, up_out_call,
+from closed_forms import (arith_asian2_call, bs_call, bs_delta, bs_vega, geo_asian_call, up_out_call,
                           bgk_discrete_up_out_call, heston_call, geo_basket_call)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -390,6 +390,30 @@ def test_asian_price_at_zero_volatility_is_the_deterministic_payoff(K):
     geo = math.exp(-r * T) * max(math.exp(sum(math.log(S0) + r * i * T / n
                                                for i in range(1, n + 1)) / n) - K, 0.0)
     np.testing.assert_allclose(o[:, 2], geo, rtol=0, atol=1e-11)
+
+
+@pytest.mark.parametrize("K", [90.0, 100.0, 115.0])
+def test_arithmetic_asian_two_fixings_semi_closed_form(K):
+    # The arithmetic-Asian price at K > 0 with volatility on two fixings,
+    # S(T/2) and S(T): against the semi-closed form (inner Black-Scholes
+    # given S(T/2), outer quadrature), for GBM and for Heston without
+    # vol-of-vol (v0 = theta: GBM with sigma = sqrt(theta), exact in law under
+    # the log-Euler step). Averaging S0 in, a wrong divisor, shifted fixings
+    # or a half-period discount would each move the price by many standard
+    # errors; so would the European or the geometric Asian in its place.
+    S0, r, T, th = H["S0"], H["r"], H["T"], 0.0625
+    sig = math.sqrt(th)
+    ref = arith_asian2_call(S0, K, r, sig, T)
+    o = oracle.gbm(S0, r, sig, T, K, 1e30, 2, 1 << 20, 41)
+    e = oracle.estimate(o[:, 1])
+    assert within(e, ref)
+    assert not within(e, bs_call(S0, K, r, sig, T))
+    assert not within(e, geo_asian_call(S0, K, r, sig, T, 2))
+    oh = _heston(2, 1 << 20, 43, xi=0.0, v0=th, theta=th, K=K)
+    assert within(oracle.estimate(oh[:, 1]), ref)
+    # One fixing: the Asian channel is the European call.
+    o1 = oracle.gbm(S0, r, sig, T, K, 1e30, 1, 4096, 47)
+    np.testing.assert_allclose(o1[:, 1], o1[:, 0], rtol=1e-14, atol=1e-13)
 
 
 def test_heston_without_vol_of_vol_is_black_scholes():
