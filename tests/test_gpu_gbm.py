@@ -10,7 +10,7 @@ import pytest
 import oracle
 import paper_1906_02818_amd as mc
 import synth
-from closed_forms import bs_call, bs_delta, bs_vega, geo_asian_call
+from closed_forms import arith_asian2_call, bs_call, bs_delta, bs_vega, geo_asian_call
 
 pytestmark = pytest.mark.gpu
 
@@ -230,6 +230,19 @@ def test_geometric_control_variate_in_sample(ctx):
     assert abs(r["cv_beta"] / beta - 1.0) < 1e-9
     assert abs(r["price"] - est["price"]) < 1e-10 * est["price"]
     assert abs(r["std_err"] / est["std_err"] - 1.0) < 1e-6
+
+
+@pytest.mark.parametrize("K", [90.0, 115.0])
+def test_arithmetic_asian_two_fixings_against_semi_closed_form(ctx, K):
+    # The GPU's arithmetic Asian at K > 0 with volatility, two fixings, FP32
+    # paths: within 4 standard errors of the semi-closed form (inner
+    # Black-Scholes given S(T/2), quadrature over the first half).
+    c = synth.ASIAN_BARRIER
+    model = gbm_model(c)
+    r = mc.mc_price(ctx, model, mc.Payoff(mc.MC_ASIAN_ARITH_CALL, K), 1 << 22, 2, SEED)
+    ref = arith_asian2_call(c["S0"], K, c["r"], c["sigma"], c["T"])
+    say("  asian n=2", r["price"], "+-", r["std_err"], "semi-closed form", ref)
+    assert abs(r["price"] - ref) < 4 * r["std_err"]
 
 # ----------------------------------------------------------- edge cases --
 @pytest.mark.parametrize("N,n,offset,scheme,prec", [
