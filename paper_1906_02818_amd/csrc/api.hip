@@ -809,7 +809,11 @@ mc_status heston_cv_price(mc_context* ctx, const mc_model* m, const mc_payoff* f
   if (!o0.cv_weights) return fail(ctx, MC_ERR_INVALID_ARG, "MC_CV_LEARNED needs cv_weights");
   for (int i = 0; i < kMlpNParam; ++i)
     if (!std::isfinite(o0.cv_weights[i])) return fail(ctx, MC_ERR_INVALID_ARG, "cv_weights not finite");
-  const uint64_t n_pilot = o0.pilot_paths ? o0.pilot_paths : (1ull << 16);
+  // The pilot runs only when beta is left to it (NaN).
+  const bool pilot = !std::isfinite(o0.cv_beta);
+  if (pilot && o0.pilot_paths == MC_PILOT_IN_SAMPLE)
+    return fail(ctx, MC_ERR_UNSUPPORTED, "the learned CV's fallback needs a pilot run");
+  const uint64_t n_pilot = !pilot ? 0 : o0.pilot_paths ? o0.pilot_paths : (1ull << 16);
   const uint64_t n_big = n_paths > n_pilot ? n_paths : n_pilot;
   const RunLayout Lay = layout_for(n_big, 3, o0.path_values != nullptr, kCvPathsPerBlock);
   const size_t off = align256(Lay.bytes);
@@ -1546,9 +1550,9 @@ size_t mc_workspace_bytes(const mc_model* m, const mc_payoff* f, uint64_t n_path
       (n_steps + mcp::kCkpt - 1) / mcp::kCkpt > (uint32_t)mcp::kLdsCkpt)
     bytes = align256(bytes) + align256(mc_adjoint_ckpt_bytes(n_paths, n_steps, mcp::kCkpt));
   if (m->kind == MC_HESTON && f->cv == MC_CV_LEARNED) {
-    const uint64_t n_pilot = o.pilot_paths == MC_PILOT_IN_SAMPLE ? 0
-                             : o.pilot_paths                     ? o.pilot_paths
-                                                                 : (1ull << 16);
+    const uint64_t n_pilot = std::isfinite(o.cv_beta) || o.pilot_paths == MC_PILOT_IN_SAMPLE ? 0
+                             : o.pilot_paths ? o.pilot_paths
+                                             : (1ull << 16);
     const uint64_t n_big = n_paths > n_pilot ? n_paths : n_pilot;
     bytes = align256(layout_for(n_big, 3, o.path_values != nullptr, kCvPathsPerBlock).bytes) +
             cv_extra_bytes(n_steps);

@@ -270,6 +270,22 @@ def test_trained_hedge_reduces_variance_on_fresh_paths(ctx):
         assert abs(r["price"] - r["plain_price"]) < 3 * r["plain_std_err"]
 
 
+def test_fixed_beta_ignores_the_pilot_setting(ctx):
+    # With a finite cv_beta no pilot runs: MC_PILOT_IN_SAMPLE (or any pilot
+    # size) leaves the estimate unchanged to the bit; with beta left to the
+    # pilot (NaN), MC_PILOT_IN_SAMPLE is refused.
+    th = weights(0.2, seed=5)
+    base = dict(cv_weights=th, cv_beta=1.0)
+    a = mc.mc_price(ctx, MODEL, PAY, 1 << 12, 32, SEED, mc.Options(**base))
+    b = mc.mc_price(ctx, MODEL, PAY, 1 << 12, 32, SEED,
+                    mc.Options(pilot_paths=mc.MC_PILOT_IN_SAMPLE, **base))
+    assert a["price"] == b["price"] and a["std_err"] == b["std_err"]
+    with pytest.raises(mc.McError) as e:
+        mc.mc_price(ctx, MODEL, PAY, 1 << 12, 32, SEED,
+                    mc.Options(cv_weights=th, pilot_paths=mc.MC_PILOT_IN_SAMPLE))
+    assert e.value.status == mc._abi.MC_ERR_UNSUPPORTED
+
+
 def test_fallback_to_plain_when_hedge_hurts(ctx):
     # Very large weights make the hedge P&L noise: the pilot sees VRF < 1 and
     # the call returns the plain Monte Carlo estimate.
