@@ -227,7 +227,7 @@ def time_to_1bp(ctx, mc, synth, torch, hedge_every=16, adam_steps=None):
     tag 0; both are timed (median of three pairs after an untimed one, see
     _pilot_then_run). The hedge network is trained beforehand (the Adam
     recipe of synth.LEARNED_CV: 2000 steps with a stepped learning rate,
-    minibatch 2^16 from a fixed 2^20-path set on tag 2); its training time
+    minibatch 2^15 from a fixed 2^20-path set on tag 2); its training time
     is reported separately and added in `total_incl_train_s`.
     """
     import numpy as np
@@ -262,7 +262,7 @@ def time_to_1bp(ctx, mc, synth, torch, hedge_every=16, adam_steps=None):
         torch, lambda: mc.mc_price(ctx, model, cv_f, 1 << 20, n, synth.SEED, opts(1)),
         lambda N: mc.mc_price(ctx, model, cv_f, N, n, synth.SEED, opts(0)))
     out["learned_cv_bf16"] = {"train_s": t_train, "adam_steps": adam_steps,
-                              "adam": {"lr": cv["lr"], "beta2": cv["beta2"],
+                              "adam": {"lr": cv["lr"], "beta2": cv["beta2"], "batch": cv["batch"],
                                        "decay": cv["decay"], "decay_every": cv["decay_every"]},
                               "loss_first": float(log[0]), "loss_last": float(np.mean(log[-20:])),
                               "pilot_s": t_pil, "pilot_vrf": pil["vrf"], "n_paths": N_cv,

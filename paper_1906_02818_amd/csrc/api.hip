@@ -896,10 +896,17 @@ uint32_t cv_segments(uint32_t n_steps, uint32_t hedge_every) {
   return (n_steps + hedge_every - 1) / hedge_every;
 }
 
+// Block moments and per-path values of the hedged-value kernel.
+RunLayout cv_values_layout(uint64_t batch, uint32_t n_seg) {
+  uint32_t split = 1;
+  cv_values_blocks(batch, n_seg, &split);
+  return layout_for(batch, 3, true, (uint32_t)kCvTrainPathsPerBlock / split);
+}
+
 size_t cv_train_bytes(uint64_t batch, uint32_t n_steps, uint32_t steps, uint64_t n_cache,
                       uint32_t n_seg, CvTrainWs* w, char* base) {
-  const RunLayout Lay = layout_for(batch, 3, true, kCvTrainPathsPerBlock);
-  const uint64_t n_blocks = (batch + kCvTrainPathsPerBlock - 1) / kCvTrainPathsPerBlock;
+  const RunLayout Lay = cv_values_layout(batch, n_seg);
+  const uint64_t n_blocks = cv_bwd_blocks(batch, n_seg, nullptr);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     char* p = base ? base + off : nullptr;
@@ -968,7 +975,7 @@ mc_status cv_loss_grad_device(mc_context* ctx, hipStream_t s, const mc_model* m,
                               uint32_t* grad_blocks = nullptr) {
   mc_options o = defaults();
   o.hip_stream = s;
-  const RunLayout Lay = layout_for(batch, 3, true, kCvTrainPathsPerBlock);
+  const RunLayout Lay = cv_values_layout(batch, cv_segments(n_steps, hedge_every));
   double* partials = (double*)w.eval_base;
   double* mom = log_row ? log_row : (double*)(w.eval_base + Lay.off_mom);
   double* ypath = (double*)(w.eval_base + Lay.off_path);

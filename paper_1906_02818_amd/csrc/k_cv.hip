@@ -377,18 +377,23 @@ __global__ __launch_bounds__(kCvThreads) void cv_cache_kernel(const CvParams P) 
 }
 
 // Hedged values of the minibatch's paths (h.n_paths paths from cache path
-// c_first): a wave takes a 32-path tile through every hedge segment, the
-// network's Delta from the cached features, H = sum_k Delta_k dSt_k in
-// segment order and Y = payoff - H. The per-path values (channels payoff,
-// H, Y) go to path_out when it is set, their block moments to partials.
-// Lane l < 32 owns path l of the tile (lane l + 32 holds the other half of
-// the hidden units), and the next segment's inputs are loaded one segment
-// ahead, so that their latency overlaps the network.
+// c_first): a 32-path tile goes through every hedge segment, the network's
+// Delta from the cached features, H = sum_k Delta_k dSt_k in segment order
+// and Y = payoff - H. The per-path values (channels payoff, H, Y) go to
+// path_out when it is set, their block moments to partials. Lane l < 32
+// owns path l of the tile (lane l + 32 holds the other half of the hidden
+// units), and the next segment's inputs are loaded one segment ahead, so
+// that their latency overlaps the network. With seg_split > 1 the tile's
+// waves evaluate the network on their own ranges of segments, and its first
+// wave forms H from their (Delta, dSt) pairs in segment order: the same
+// FMAs in the same order as one wave taking every segment.
 template <bool BF16>
 __global__ __launch_bounds__(kCvThreads) void cv_values_kernel(const CvParams P) {
   using FT = FragT<BF16>;
   __shared__ __attribute__((aligned(16))) FT s_w2f[kFragFloats];
   __shared__ __attribute__((aligned(16))) float s_lanec[kLaneFloats];
+  // (Delta, dSt) of each segment a wave of a split tile takes.
+  __shared__ float2 s_dd[kCvWaves][kCvValSlab][32];
   {
     WeightRegs wr;
     weights_load<false>(P.w2f, nullptr, P.lanec, wr);
@@ -407,9 +412,15 @@ __global__ __launch_bounds__(kCvThreads) void cv_values_kernel(const CvParams P)
   }
   const float c3 = out_const(P.theta);
   const uint64_t n = P.h.n_paths;
-  const uint64_t pid = ((uint64_t)blockIdx.x * kCvWaves + wave) * 32 + row;
+  // seg_split waves share a tile, wave `part` taking segments [k0, k1).
+  const uint32_t split = P.seg_split, part = (uint32_t)wave % split;
+  const uint64_t tile = (uint64_t)blockIdx.x * (kCvWaves / split) + (uint32_t)wave / split;
+  const uint32_t k0 = (uint32_t)((uint64_t)P.n_seg * part / split);
+  const uint32_t k1 = (uint32_t)((uint64_t)P.n_seg * (part + 1) / split);
+  const uint64_t pid = tile * 32 + row;
   const bool active = pid < n;
-  const bool owner = active && half == 0;
+  const bool lead = active && half == 0;     // lanes holding a path's inputs
+  const bool owner = lead && part == 0;      // ... and summing its hedge
   const uint64_t S = P.c_stride, c = P.c_first + pid;
   float nf[4], ndst;
   // Row bases are uniform; the lane adds a 32-bit byte offset (the
@@ -419,21 +430,39 @@ __global__ __launch_bounds__(kCvThreads) void cv_values_kernel(const CvParams P)
   auto fetch = [&](uint32_t k) {
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-      nf[q] = owner ? at(P.c_phi + ((size_t)k * 4 + q) * S + P.c_first) : 0.f;
-    ndst = owner ? at(P.c_dst + (size_t)k * S + P.c_first) : 0.f;
+      nf[q] = lead ? at(P.c_phi + ((size_t)k * 4 + q) * S + P.c_first) : 0.f;
+    ndst = lead ? at(P.c_dst + (size_t)k * S + P.c_first) : 0.f;
   };
-  fetch(0);
+  if (k0 < k1) fetch(k0);
   float H = 0.f;
-  for (uint32_t k = 0; k < P.n_seg; ++k) {
+  for (uint32_t k = k0; k < k1; ++k) {
     float phi[8];
 #pragma unroll
     for (int q = 0; q < 4; ++q) phi[q] = nf[q];
-    phi[4] = owner ? 1.0f : 0.f;
+    phi[4] = lead ? 1.0f : 0.f;
     phi[5] = phi[6] = phi[7] = 0.f;
     const float dst = ndst;
-    if (k + 1 < P.n_seg) fetch(k + 1);
+    if (k + 1 < k1) fetch(k + 1);
     const float d = mlp_delta<BF16>(phi, w1a, s_w2f, s_lanec, lane, c3);
-    H = __builtin_fmaf(d, dst, H);
+    if (split == 1)
+      H = __builtin_fmaf(d, dst, H);
+    else if (half == 0)
+      s_dd[wave][k - k0][row] = make_float2(d, dst);
+  }
+  if (split > 1) {
+    // The tile's first wave sums the hedge in segment order, as one wave
+    // taking every segment does.
+    __syncthreads();
+    if (part == 0 && half == 0) {
+      for (uint32_t p = 0; p < split; ++p) {
+        const uint32_t a = (uint32_t)((uint64_t)P.n_seg * p / split);
+        const uint32_t b = (uint32_t)((uint64_t)P.n_seg * (p + 1) / split);
+        for (uint32_t k = a; k < b; ++k) {
+          const float2 e = s_dd[wave + p][k - a][row];
+          H = __builtin_fmaf(e.x, e.y, H);
+        }
+      }
+    }
   }
   double y[3] = {0.0, 0.0, 0.0};
   if (owner) {
@@ -451,7 +480,8 @@ __global__ __launch_bounds__(kCvThreads) void cv_values_kernel(const CvParams P)
 }
 
 // Backward pass: a wave takes 32 paths of the minibatch through every hedge
-// segment, re-running the forward pass from the cached features.
+// segment (or, with seg_split > 1, through its range of them), re-running
+// the forward pass from the cached features.
 //
 // Every weight gradient is a product over the wave's 32 paths on the
 // matrix cores, accumulated in two register sets:
@@ -503,7 +533,13 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int row = lane & 31, half = lane >> 5;
-  const uint64_t tile = (uint64_t)blockIdx.x * kCvWaves + wave;
+  // seg_split waves share a tile, wave `part` taking segments [k0, k1): the
+  // gradient is a sum over (path, segment) items, so any split of the
+  // segments gives the same sum up to rounding.
+  const uint32_t split = P.seg_split, part = (uint32_t)wave % split;
+  const uint64_t tile = (uint64_t)blockIdx.x * (kCvWaves / split) + (uint32_t)wave / split;
+  const uint32_t k0 = (uint32_t)((uint64_t)P.n_seg * part / split);
+  const uint32_t k1 = (uint32_t)((uint64_t)P.n_seg * (part + 1) / split);
   const uint64_t pid = tile * 32 + row;
   const bool active = pid < P.h.n_paths;
   Op8<BF16> w1a[2];
@@ -576,15 +612,15 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
       nf[q] = (half == 0 && active) ? at(P.c_phi + ((size_t)k * 4 + q) * S + P.c_first) : 0.f;
     ndst = active ? at(P.c_dst + (size_t)k * S + P.c_first) : 0.f;
   };
-  fetch(0);
-  for (uint32_t k = 0; k < P.n_seg; ++k) {
+  if (k0 < k1) fetch(k0);
+  for (uint32_t k = k0; k < k1; ++k) {
     float h1[32], h2[32], phi[8];
 #pragma unroll
     for (int q = 0; q < 4; ++q) phi[q] = nf[q];
     phi[4] = (half == 0 && active) ? 1.0f : 0.f;
     phi[5] = phi[6] = phi[7] = 0.f;
     const float dSt = ndst;
-    if (k + 1 < P.n_seg) fetch(k + 1);
+    if (k + 1 < k1) fetch(k + 1);
     mlp_forward<BF16>(phi, w1a, s_w2f, s_lanec, lane, h1, h2);
     const float gD = g * dSt;                      // dL/dDelta for this segment
     const float gDh = 0.5f * gD;                   // the constants hold 2 W3
@@ -971,26 +1007,61 @@ hipError_t launch_cv_cache(const CvParams& p, hipStream_t s) {
 }
 
 hipError_t launch_cv_values(const CvParams& p, hipStream_t s, uint32_t* n_blocks) {
-  const uint32_t nb = (uint32_t)((p.h.n_paths + kCvTrainPathsPerBlock - 1) / kCvTrainPathsPerBlock);
+  CvParams q = p;
+  const uint32_t nb = cv_values_blocks(p.h.n_paths, p.n_seg, &q.seg_split);
   *n_blocks = nb;
-  if (nb == 0 || p.c_first + p.h.n_paths > p.c_stride || p.h.n_paths >= (1ull << 30))
+  if (nb == 0 || p.n_seg == 0 || p.c_first + p.h.n_paths > p.c_stride ||
+      p.h.n_paths >= (1ull << 30))
     return hipErrorInvalidValue;
   if (p.bf16)
-    hipLaunchKernelGGL((cv_values_kernel<true>), dim3(nb), dim3(kCvThreads), 0, s, p);
+    hipLaunchKernelGGL((cv_values_kernel<true>), dim3(nb), dim3(kCvThreads), 0, s, q);
   else
-    hipLaunchKernelGGL((cv_values_kernel<false>), dim3(nb), dim3(kCvThreads), 0, s, p);
+    hipLaunchKernelGGL((cv_values_kernel<false>), dim3(nb), dim3(kCvThreads), 0, s, q);
   return hipGetLastError();
 }
 
+// A small minibatch has too few 32-path tiles to keep every SIMD busy; its
+// tiles' segments are then split over two or four waves, which run side by
+// side. Each extra workgroup adds its own prologue (weights, Ybar) and
+// gradient row, so the backward splits less than the hedged values do
+// (measured, 2^14 to 2^16 paths: per Adam step, two waves per tile beat
+// four at 512 tiles and one at 1024).
+static uint32_t tile_split(uint64_t tiles, uint32_t n_seg, uint64_t four_upto) {
+  uint32_t sp = tiles <= four_upto ? 4 : tiles <= 1024 ? 2 : 1;
+  while (sp > 1 && sp > n_seg) sp >>= 1;
+  return sp;
+}
+
+uint32_t cv_bwd_blocks(uint64_t n_paths, uint32_t n_seg, uint32_t* split) {
+  const uint64_t tiles = (n_paths + 31) / 32;
+  const uint32_t sp = tile_split(tiles, n_seg, 256);
+  if (split) *split = sp;
+  const uint32_t tiles_per_block = kCvWaves / sp;
+  return (uint32_t)((tiles + tiles_per_block - 1) / tiles_per_block);
+}
+
+// The hedged values split a tile's segments while each wave's share fits
+// its LDS slab (the tile's first wave then sums them in order).
+uint32_t cv_values_blocks(uint64_t n_paths, uint32_t n_seg, uint32_t* split) {
+  const uint64_t tiles = (n_paths + 31) / 32;
+  uint32_t sp = tile_split(tiles, n_seg, 512);
+  if (sp > 1 && (n_seg + sp - 1) / sp > (uint32_t)kCvValSlab) sp = 1;
+  if (split) *split = sp;
+  const uint32_t tiles_per_block = kCvWaves / sp;
+  return (uint32_t)((tiles + tiles_per_block - 1) / tiles_per_block);
+}
+
 hipError_t launch_cv_backward(const CvParams& p, hipStream_t s, uint32_t* n_blocks) {
-  const uint32_t nb = (uint32_t)((p.h.n_paths + kCvTrainPathsPerBlock - 1) / kCvTrainPathsPerBlock);
+  CvParams q = p;
+  const uint32_t nb = cv_bwd_blocks(p.h.n_paths, p.n_seg, &q.seg_split);
   *n_blocks = nb;
-  if (nb == 0 || p.c_first + p.h.n_paths > p.c_stride || p.h.n_paths >= (1ull << 30))
+  if (nb == 0 || p.n_seg == 0 || p.c_first + p.h.n_paths > p.c_stride ||
+      p.h.n_paths >= (1ull << 30))
     return hipErrorInvalidValue;
   if (p.bf16)
-    hipLaunchKernelGGL(cv_bwd_kernel_bf16, dim3(nb), dim3(kCvThreads), 0, s, p);
+    hipLaunchKernelGGL(cv_bwd_kernel_bf16, dim3(nb), dim3(kCvThreads), 0, s, q);
   else
-    hipLaunchKernelGGL(cv_bwd_kernel_fp32, dim3(nb), dim3(kCvThreads), 0, s, p);
+    hipLaunchKernelGGL(cv_bwd_kernel_fp32, dim3(nb), dim3(kCvThreads), 0, s, q);
   return hipGetLastError();
 }
 

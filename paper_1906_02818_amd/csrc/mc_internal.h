@@ -248,9 +248,11 @@ struct CvParams {
   uint64_t c_stride;         // paths held by the cache
   uint64_t c_first;          // the minibatch's first path within the cache
   uint32_t n_seg;            // ceil(n_steps / hedge_every)
+  uint32_t seg_split;        // backward: waves per 32-path tile, each taking a
+                             // contiguous range of segments (set by its launcher)
 };
 constexpr int kCvPathsPerBlock = 256;       // evaluation: 4 waves of 64 paths
-constexpr int kCvTrainPathsPerBlock = 128;  // training: 4 waves of 32 paths
+constexpr int kCvTrainPathsPerBlock = 128;  // training: 4 waves of 32 paths (/ split)
 // Fragment layout of the weights, built on the device from theta.
 constexpr int kW1fFloats = 2 * 64 * 8, kW2fFloats = 2 * 4 * 64 * 8, kLanecFloats = 2 * 64 * 32;
 hipError_t launch_cv_pack(const float* theta, float* w1f, float* w2f, float* w2tf, float* lanec,
@@ -262,6 +264,13 @@ hipError_t launch_cv_price(const CvParams& p, hipStream_t s, uint32_t* n_blocks)
 hipError_t launch_cv_cache(const CvParams& p, hipStream_t s);
 hipError_t launch_cv_values(const CvParams& p, hipStream_t s, uint32_t* n_blocks);
 hipError_t launch_cv_backward(const CvParams& p, hipStream_t s, uint32_t* n_blocks);
+// Workgroups of the backward (the rows of its gradient partials) and of the
+// hedged-value kernel (the rows of its block moments) for a minibatch of
+// n_paths with n_seg hedge segments; *split (if given) receives the waves
+// per 32-path tile.
+uint32_t cv_bwd_blocks(uint64_t n_paths, uint32_t n_seg, uint32_t* split);
+uint32_t cv_values_blocks(uint64_t n_paths, uint32_t n_seg, uint32_t* split);
+constexpr int kCvValSlab = 16;  // segments a wave of a split tile holds (values)
 // Reduces the per-block gradient partials [n_blocks][kMlpNParam], takes one
 // Adam step and refreshes the packed fragments, in one launch; or only
 // reduces them into grad (the same fixed order).

@@ -176,6 +176,27 @@ def test_loss_gradient_matches_oracle(ctx, prec, tol, m_every, n):
         assert blk < 10 * tol, (a, b, blk)
 
 
+@pytest.mark.parametrize("prec,tol", [(mc.MC_FP32, 1e-4), (mc.MC_BF16_GEMM, 2e-2)])
+@pytest.mark.parametrize("B,n,m_every", [(512, 3, 1), (512, 4, 4), (16640, 9, 1), (33024, 9, 1)])
+def test_loss_gradient_across_segment_splits(ctx, prec, tol, B, n, m_every):
+    # The backward gives a small minibatch's 32-path tiles to two or four
+    # waves, each taking a contiguous range of the hedge segments: 3 segments
+    # over two waves, one segment (no split), 520 tiles with 9 segments over
+    # two waves (4 + 5), 1032 tiles with one wave per tile.
+    th = weights(0.2, seed=7)
+    say("grad split", prec, B, n, m_every)
+    loss, g = mc.mc_cv_loss_grad(ctx, MODEL, PAY, n, SEED, 2, 64, B, th, hedge_every=m_every,
+                                 prec=prec)
+    lo, go = oracle.cv_loss_grad(H, n, th, B, SEED, tag=2, path0=64, m_every=m_every)
+    rel = np.linalg.norm(g - go) / np.linalg.norm(go)
+    say(f"  loss gpu {loss:.6f} oracle {lo:.6f}; grad rel-L2 {rel:.2e}")
+    assert abs(loss - lo) < (1e-5 if prec == mc.MC_FP32 else 1e-2) * lo
+    assert rel < tol
+    for a, b in ((0, 256), (256, 320), (320, 4416), (4416, 4480), (4480, 4544), (4544, 4545)):
+        blk = np.linalg.norm(g[a:b] - go[a:b]) / max(np.linalg.norm(go[a:b]), 1e-30)
+        assert blk < 10 * tol, (a, b, blk)
+
+
 @pytest.mark.parametrize("decay", [0.0, -0.5, 1.5, float("nan")])
 def test_adam_rejects_a_bad_decay(ctx, decay):
     th0 = weights(0.2, seed=6)
@@ -214,15 +235,19 @@ def test_adam_steps_match_oracle(ctx, decay_every, decay):
 
 
 @pytest.mark.parametrize("prec", [mc.MC_FP32, mc.MC_BF16_GEMM])
-def test_training_forward_is_the_evaluation_network(ctx, prec):
+@pytest.mark.parametrize("B,n,m", [(1024, 40, 16), (1024, 64, 4), (40192, 20, 4)])
+def test_training_forward_is_the_evaluation_network(ctx, prec, B, n, m):
     # The training forward (32-path tiles of a minibatch, from the feature
     # cache) and the evaluation kernel (64 paths per wave, stepping the paths
     # itself) compute the same per-path hedge values: the loss of a minibatch
     # equals the batch variance of the evaluation's per-path estimator on the
     # same paths (stream tag 2, same path indices) to FP64 merge rounding.
+    # A small minibatch's tiles split their segments over waves and sum the
+    # hedge in segment order all the same: 3 segments over two waves, 16 over
+    # four; 1256 tiles take one wave each.
     th = weights(0.2, seed=9)
-    B, n, m, path0 = 1024, 40, 16, 300
-    say("train forward vs eval", prec)
+    path0 = 300
+    say("train forward vs eval", prec, B, n, m)
     loss, _ = mc.mc_cv_loss_grad(ctx, MODEL, PAY, n, SEED, 2, path0, B, th, hedge_every=m,
                                  prec=prec)
     r = mc.mc_price(ctx, MODEL, PAY, B, n, SEED,
