@@ -972,7 +972,7 @@ mc_status cv_loss_grad_device(mc_context* ctx, hipStream_t s, const mc_model* m,
                               const mc_payoff* f, uint32_t n_steps, uint64_t first,
                               uint64_t n_cache, uint64_t batch, uint32_t hedge_every, bool bf16,
                               const CvTrainWs& w, double* log_row,
-                              uint32_t* grad_blocks = nullptr) {
+                              uint32_t* grad_blocks = nullptr, CvValMoments* vm_out = nullptr) {
   mc_options o = defaults();
   o.hip_stream = s;
   const RunLayout Lay = cv_values_layout(batch, cv_segments(n_steps, hedge_every));
@@ -986,21 +986,23 @@ mc_status cv_loss_grad_device(mc_context* ctx, hipStream_t s, const mc_model* m,
   p.path_out = ypath;
   uint32_t nb = 0;
   HIP_TRY(ctx, launch_cv_values(p, s, &nb));
-  // The backward merges the hedged values' block moments itself (Ybar) and
-  // its block 0 stores them in mom.
+  // The backward sums the hedged values' block moments itself (Ybar); the
+  // gradient reduction's launch merges them into mom.
+  const CvValMoments vm{partials, nb, mom};
   p.path_out = nullptr;
   p.val_blocks = nb;
-  p.ybar_mom = mom;
   p.y_path = ypath;
   p.g_scale = -2.0 / (double)batch;
   p.grad_partials = w.grad_partials;
   HIP_TRY(ctx, launch_cv_backward(p, s, &nb));   // one partial per block
-  // With grad_blocks the caller reduces the partials itself (the training
-  // loop does it inside its Adam step).
-  if (grad_blocks)
+  // With grad_blocks the caller reduces the partials and merges the moments
+  // itself (the training loop does it inside its Adam step).
+  if (grad_blocks) {
     *grad_blocks = nb;
-  else
-    HIP_TRY(ctx, launch_grad_sum(w.grad_partials, nb, w.grad, s));
+    if (vm_out) *vm_out = vm;
+  } else {
+    HIP_TRY(ctx, launch_grad_sum(w.grad_partials, nb, vm, w.grad, s));
+  }
   return MC_OK;
 }
 
@@ -2270,16 +2272,17 @@ mc_status mc_cv_train(mc_context* ctx, const mc_model* m, const mc_payoff* f, ui
     // Minibatches cycle through the training set.
     const uint64_t first = (t % n_batches) * B;
     uint32_t nb = 0;
+    CvValMoments vm{};
     st = cv_loss_grad_device(ctx, s, m, f, n_steps, first, n_train, B, cfg->hedge_every, bf16, w,
-                             w.log + (size_t)t * n_mom, &nb);
+                             w.log + (size_t)t * n_mom, &nb, &vm);
     if (st != MC_OK) return st;
     // Step decay of the learning rate; Adam's moments carry across drops.
     const double lr =
         cfg->decay_every > 0 ? cfg->lr * std::pow(cfg->decay, (double)(t / cfg->decay_every))
                              : cfg->lr;
-    HIP_TRY(ctx, launch_adam_pack(w.grad_partials, nb, w.grad, w.b.theta, w.m, w.v, (int)t + 1,
-                                  lr, cfg->beta1, cfg->beta2, cfg->eps, w.b.w1f, w.b.w2f,
-                                  w.b.w2tf, w.b.lanec, s));
+    HIP_TRY(ctx, launch_adam_pack(w.grad_partials, nb, vm, w.grad, w.b.theta, w.m, w.v,
+                                  (int)t + 1, lr, cfg->beta1, cfg->beta2, cfg->eps, w.b.w1f,
+                                  w.b.w2f, w.b.w2tf, w.b.lanec, s));
   }
   std::vector<double> log((size_t)cfg->steps * n_mom);
   HIP_TRY(ctx, hipMemcpyAsync(weights_inout, w.b.theta, kMlpNParam * 4, hipMemcpyDeviceToHost, s));

@@ -513,23 +513,36 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
   float* s_lanec = (float*)(lds + 2 * kFragFloats * sizeof(FT));
   FT* tr = (FT*)(lds + 2 * kFragFloats * sizeof(FT) + kLaneFloats * 4);
   // The weight fragments and per-lane constants are loaded into registers
-  // first, so that their latency overlaps the merge below.
+  // first, so that their latency overlaps the sum below.
   WeightRegs wr;
   weights_load<true>(P.w2f, P.w2tf, P.lanec, wr);
-  // Ybar: every block merges the hedged-value kernel's block moments itself
-  // (the same fixed-order merge, so every block gets the same value); block
-  // 0 also stores the merged vector (the minibatch's loss).
-  __shared__ double ymom[PartSums<3>::M];
+  // Ybar = sum n_b mean_b / sum n_b over the hedged-value kernel's block
+  // moment vectors, summed in the same fixed order by every block (the full
+  // merge of those vectors, the minibatch's loss, runs in the gradient
+  // reduction's launch).
+  __shared__ double s_ys[kCvWaves][2];
   {
-    PartSums<3> pm;
-    pm.zero();
-    for (uint32_t i = threadIdx.x; i < P.val_blocks; i += kCvThreads)
-      pm.add_vector(P.partials + (size_t)i * PartSums<3>::M);
-    block_reduce<3, kCvThreads>(pm, ymom, 0);
+    double sn = 0.0, sy = 0.0;
+    for (uint32_t i = threadIdx.x; i < P.val_blocks; i += kCvThreads) {
+      const double* v = P.partials + (size_t)i * PartSums<3>::M;
+      sn += v[0];
+      sy += v[0] * v[2 + 2];             // n and mean of channel 2 (Y)
+    }
+    // A shuffle-down tree into lane 0 (a butterfly here would share its
+    // lane addresses with the epilogue's and keep them live across the
+    // segment loop).
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      sn += __shfl_down(sn, off, 64);
+      sy += __shfl_down(sy, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      s_ys[threadIdx.x >> 6][0] = sn;
+      s_ys[threadIdx.x >> 6][1] = sy;
+    }
   }
   weights_store<true>(wr, s_w2f, s_w2tf, s_lanec);
   __syncthreads();
-  if (blockIdx.x == 0 && threadIdx.x < PartSums<3>::M) P.ybar_mom[threadIdx.x] = ymom[threadIdx.x];
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int row = lane & 31, half = lane >> 5;
@@ -542,6 +555,17 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
   const uint32_t k1 = (uint32_t)((uint64_t)P.n_seg * (part + 1) / split);
   const uint64_t pid = tile * 32 + row;
   const bool active = pid < P.h.n_paths;
+  float g = 0.f;                       // upstream factor of this path
+  if (active) {
+    double n = 0.0, sy = 0.0;
+#pragma unroll
+    for (int w = 0; w < kCvWaves; ++w) {
+      n += s_ys[w][0];
+      sy += s_ys[w][1];
+    }
+    const double ybar = n > 0.0 ? sy / n : 0.0;
+    g = (float)(P.g_scale * (P.y_path[pid * 3 + 2] - ybar));
+  }
   Op8<BF16> w1a[2];
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb) {
@@ -551,11 +575,6 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
   }
   const float col0 = row == 0 ? 1.0f : 0.0f;   // B operand entry: ones in column 0
 
-  float g = 0.f;                       // upstream factor of this path
-  if (active) {
-    const double ybar = ymom[2 + 2];   // mean of channel 2 (Y)
-    g = (float)(P.g_scale * (P.y_path[pid * 3 + 2] - ybar));
-  }
   f32x16 gw2[2][2], gx[2];
   float gb3 = 0.f;
 #pragma unroll
@@ -908,13 +927,25 @@ __device__ __forceinline__ void slot_of(int u, int& mb, int& r, int& h) {
 // the 32 lanes of a half-wave). Padding slots keep the zeros of the first
 // pack; b3 lives in theta only.
 constexpr int kGradCols = 16, kGradSlices = 256 / kGradCols;
+constexpr int kGradBlocks = (kMlpNParam + kGradCols - 1) / kGradCols;
 
 template <bool ADAM>
 __global__ __launch_bounds__(256) void grad_adam_kernel(
     const double* __restrict__ partials, uint32_t n_blocks, double* __restrict__ grad,
     float* __restrict__ theta, float* __restrict__ m, float* __restrict__ v, float lr, float b1,
     float b2, float eps, float c1, float c2, float* __restrict__ w1f, float* __restrict__ w2f,
-    float* __restrict__ w2tf, float* __restrict__ lanec) {
+    float* __restrict__ w2tf, float* __restrict__ lanec, const double* __restrict__ vpart,
+    uint32_t vblocks, double* __restrict__ vmom) {
+  if (blockIdx.x == kGradBlocks) {
+    // The extra workgroup: the fixed-order merge of the hedged values'
+    // block moments (the minibatch's loss), beside the reduction.
+    PartSums<3> pm;
+    pm.zero();
+    for (uint32_t i = threadIdx.x; i < vblocks; i += 256)
+      pm.add_vector(vpart + (size_t)i * PartSums<3>::M);
+    block_reduce<3, 256>(pm, vmom, 0);
+    return;
+  }
   __shared__ double sh[kGradSlices][kGradCols];
   __shared__ float th_new[kGradCols];
   const int col = threadIdx.x % kGradCols, slice = threadIdx.x / kGradCols;
@@ -1065,26 +1096,26 @@ hipError_t launch_cv_backward(const CvParams& p, hipStream_t s, uint32_t* n_bloc
   return hipGetLastError();
 }
 
-hipError_t launch_adam_pack(const double* partials, uint32_t n_blocks, double* grad, float* theta,
-                            float* m, float* v, int t, double lr, double b1, double b2,
-                            double eps, float* w1f, float* w2f, float* w2tf, float* lanec,
-                            hipStream_t s) {
-  if (n_blocks == 0) return hipErrorInvalidValue;
+hipError_t launch_adam_pack(const double* partials, uint32_t n_blocks, const CvValMoments& vm,
+                            double* grad, float* theta, float* m, float* v, int t, double lr,
+                            double b1, double b2, double eps, float* w1f, float* w2f, float* w2tf,
+                            float* lanec, hipStream_t s) {
+  if (n_blocks == 0 || vm.n_blocks == 0 || vm.partials == nullptr || vm.out == nullptr)
+    return hipErrorInvalidValue;
   const float c1 = (float)(1.0 - std::pow(b1, t)), c2 = (float)(1.0 - std::pow(b2, t));
-  const uint32_t nb = (kMlpNParam + kGradCols - 1) / kGradCols;
-  hipLaunchKernelGGL(grad_adam_kernel<true>, dim3(nb), dim3(256), 0, s, partials, n_blocks,
-                     grad, theta, m, v, (float)lr, (float)b1, (float)b2, (float)eps, c1, c2, w1f,
-                     w2f, w2tf, lanec);
+  hipLaunchKernelGGL(grad_adam_kernel<true>, dim3(kGradBlocks + 1), dim3(256), 0, s, partials,
+                     n_blocks, grad, theta, m, v, (float)lr, (float)b1, (float)b2, (float)eps, c1,
+                     c2, w1f, w2f, w2tf, lanec, vm.partials, vm.n_blocks, vm.out);
   return hipGetLastError();
 }
 
-hipError_t launch_grad_sum(const double* partials, uint32_t n_blocks, double* grad,
-                           hipStream_t s) {
-  if (n_blocks == 0) return hipErrorInvalidValue;
-  const uint32_t nb = (kMlpNParam + kGradCols - 1) / kGradCols;
-  hipLaunchKernelGGL(grad_adam_kernel<false>, dim3(nb), dim3(256), 0, s, partials, n_blocks,
-                     grad, nullptr, nullptr, nullptr, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, nullptr,
-                     nullptr, nullptr, nullptr);
+hipError_t launch_grad_sum(const double* partials, uint32_t n_blocks, const CvValMoments& vm,
+                           double* grad, hipStream_t s) {
+  if (n_blocks == 0 || vm.n_blocks == 0 || vm.partials == nullptr || vm.out == nullptr)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(grad_adam_kernel<false>, dim3(kGradBlocks + 1), dim3(256), 0, s, partials,
+                     n_blocks, grad, nullptr, nullptr, nullptr, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
+                     nullptr, nullptr, nullptr, nullptr, vm.partials, vm.n_blocks, vm.out);
   return hipGetLastError();
 }
 

@@ -231,9 +231,8 @@ struct CvParams {
   const float* lanec;        // [2][8][64][4]: per-lane b2 * (-2 / ln 2), 2 W3 of the lane's units
   const float* dfac;         // [n_steps + 1]: e^{r t_i}
   // training
-  double* ybar_mom;          // out: merged moments of the hedged values (block 0 writes)
-  uint32_t val_blocks;       // blocks of the hedged-value kernel whose partials the
-                             // backward merges (in `partials`) for Ybar
+  uint32_t val_blocks;       // blocks of the hedged-value kernel whose moment vectors
+                             // (in `partials`) the backward sums for Ybar
   const double* y_path;      // per-path values of that pass, [n_paths][3] (Y is channel 2)
   double g_scale;            // -2 / B
   double* grad_partials;     // [n_blocks][kMlpNParam] FP64
@@ -271,15 +270,23 @@ hipError_t launch_cv_backward(const CvParams& p, hipStream_t s, uint32_t* n_bloc
 uint32_t cv_bwd_blocks(uint64_t n_paths, uint32_t n_seg, uint32_t* split);
 uint32_t cv_values_blocks(uint64_t n_paths, uint32_t n_seg, uint32_t* split);
 constexpr int kCvValSlab = 16;  // segments a wave of a split tile holds (values)
+// The hedged-value kernel's moment vectors (one per workgroup) and where
+// their fixed-order merge (the minibatch's loss) goes.
+struct CvValMoments {
+  const double* partials;
+  uint32_t n_blocks;
+  double* out;
+};
 // Reduces the per-block gradient partials [n_blocks][kMlpNParam], takes one
 // Adam step and refreshes the packed fragments, in one launch; or only
-// reduces them into grad (the same fixed order).
-hipError_t launch_adam_pack(const double* partials, uint32_t n_blocks, double* grad, float* theta,
-                            float* m, float* v, int t, double lr, double b1, double b2,
-                            double eps, float* w1f, float* w2f, float* w2tf, float* lanec,
-                            hipStream_t s);
-hipError_t launch_grad_sum(const double* partials, uint32_t n_blocks, double* grad,
-                           hipStream_t s);
+// reduces them into grad (the same fixed order). A workgroup of its own in
+// the same launch merges the hedged values' moments into vm.out.
+hipError_t launch_adam_pack(const double* partials, uint32_t n_blocks, const CvValMoments& vm,
+                            double* grad, float* theta, float* m, float* v, int t, double lr,
+                            double b1, double b2, double eps, float* w1f, float* w2f, float* w2tf,
+                            float* lanec, hipStream_t s);
+hipError_t launch_grad_sum(const double* partials, uint32_t n_blocks, const CvValMoments& vm,
+                           double* grad, hipStream_t s);
 
 // ---- reductions and diagnostics ----
 // Moment vectors of C channels (1..kMaxMomentChannels): n_batch independent
