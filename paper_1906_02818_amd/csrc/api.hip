@@ -883,7 +883,7 @@ mc_status heston_cv_price(mc_context* ctx, const mc_model* m, const mc_payoff* f
 struct CvTrainWs {
   char* eval_base;          // moment layout with per-path values
   size_t eval_bytes;
-  double* grad_partials;    // [n_blocks][kMlpNParam]
+  float* grad_partials;     // [n_blocks][kMlpNParam]
   double* grad;             // [kMlpNParam]
   CvBuffers b;
   float *m, *v;             // Adam moments
@@ -914,7 +914,7 @@ size_t cv_train_bytes(uint64_t batch, uint32_t n_steps, uint32_t steps, uint64_t
     return p;
   };
   char* e = take(Lay.bytes);
-  char* gp = take((size_t)kMlpNParam * n_blocks * 8);
+  char* gp = take((size_t)kMlpNParam * n_blocks * 4);
   char* g = take((size_t)kMlpNParam * 8);
   char* cv = take(cv_extra_bytes(n_steps));
   char* mm = take((size_t)kMlpNParam * 4);
@@ -926,7 +926,7 @@ size_t cv_train_bytes(uint64_t batch, uint32_t n_steps, uint32_t steps, uint64_t
   if (w && base) {
     w->eval_base = e;
     w->eval_bytes = Lay.bytes;
-    w->grad_partials = (double*)gp;
+    w->grad_partials = (float*)gp;
     w->grad = (double*)g;
     w->b = cv_carve(cv);
     w->m = (float*)mm;

@@ -33,8 +33,9 @@
 // derivative dL/dDelta = g_b dSt with g_b = -(2/B)(Y_b - Ybar) is pushed
 // back through the network; dW2 = delta2^T H1 and dW1 = delta1^T [phi; 1]
 // are MFMA products over the wave's 32 paths after a transpose through LDS.
-// Each block writes its partial gradient in FP64; a fixed-order reduction
-// and the Adam kernel follow.
+// Each block writes its partial gradient (its waves summed in FP64, stored
+// in FP32); a fixed-order FP64 reduction and the Adam step follow in one
+// launch.
 #include <type_traits>
 
 #include "device/reduce.h"
@@ -735,13 +736,14 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
     wave_lds_sync();
   }
 
-  // The block's gradient in FP64, in the flat parameter layout W1[64][4],
-  // b1[64], W2[64][64], b2[64], W3[64], b3: every wave stores its FP32
-  // accumulators into a row of its own (each slot has one writer per wave;
-  // b3's wave sum is FP64 and has a slot of its own), and after one barrier
-  // each thread adds the waves' values of its parameters in wave order in
-  // FP64 (the conversions are exact), so no wave waits on another's
-  // read-modify-write of LDS. The block writes one partial per parameter.
+  // The block's gradient, in the flat parameter layout W1[64][4], b1[64],
+  // W2[64][64], b2[64], W3[64], b3: every wave stores its FP32 accumulators
+  // into a row of its own (each slot has one writer per wave; b3's wave sum
+  // is FP64 and has a slot of its own), and after one barrier each thread
+  // adds the waves' values of its parameters in wave order in FP64 (the
+  // conversions are exact), so no wave waits on another's read-modify-write
+  // of LDS. The block writes one partial per parameter, rounded to FP32 (the
+  // precision of the accumulators it sums; the cross-block sum is FP64).
   float* red = (float*)lds;            // [kCvWaves][kMlpNParam]
   __shared__ double s3w[kCvWaves];
   __syncthreads();                     // every wave has left the segment loop
@@ -774,7 +776,7 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
 #pragma unroll
     for (int w = 1; w < kCvWaves; ++w)
       acc += i == kMlpNParam - 1 ? s3w[w] : (double)red[w * kMlpNParam + i];
-    P.grad_partials[(uint64_t)blockIdx.x * kMlpNParam + i] = acc;
+    P.grad_partials[(uint64_t)blockIdx.x * kMlpNParam + i] = (float)acc;
   }
 }
 
@@ -931,7 +933,7 @@ constexpr int kGradBlocks = (kMlpNParam + kGradCols - 1) / kGradCols;
 
 template <bool ADAM>
 __global__ __launch_bounds__(256) void grad_adam_kernel(
-    const double* __restrict__ partials, uint32_t n_blocks, double* __restrict__ grad,
+    const float* __restrict__ partials, uint32_t n_blocks, double* __restrict__ grad,
     float* __restrict__ theta, float* __restrict__ m, float* __restrict__ v, float lr, float b1,
     float b2, float eps, float c1, float c2, float* __restrict__ w1f, float* __restrict__ w2f,
     float* __restrict__ w2tf, float* __restrict__ lanec, const double* __restrict__ vpart,
@@ -1096,7 +1098,7 @@ hipError_t launch_cv_backward(const CvParams& p, hipStream_t s, uint32_t* n_bloc
   return hipGetLastError();
 }
 
-hipError_t launch_adam_pack(const double* partials, uint32_t n_blocks, const CvValMoments& vm,
+hipError_t launch_adam_pack(const float* partials, uint32_t n_blocks, const CvValMoments& vm,
                             double* grad, float* theta, float* m, float* v, int t, double lr,
                             double b1, double b2, double eps, float* w1f, float* w2f, float* w2tf,
                             float* lanec, hipStream_t s) {
@@ -1109,7 +1111,7 @@ hipError_t launch_adam_pack(const double* partials, uint32_t n_blocks, const CvV
   return hipGetLastError();
 }
 
-hipError_t launch_grad_sum(const double* partials, uint32_t n_blocks, const CvValMoments& vm,
+hipError_t launch_grad_sum(const float* partials, uint32_t n_blocks, const CvValMoments& vm,
                            double* grad, hipStream_t s) {
   if (n_blocks == 0 || vm.n_blocks == 0 || vm.partials == nullptr || vm.out == nullptr)
     return hipErrorInvalidValue;

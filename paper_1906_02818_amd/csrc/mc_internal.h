@@ -235,7 +235,7 @@ struct CvParams {
                              // (in `partials`) the backward sums for Ybar
   const double* y_path;      // per-path values of that pass, [n_paths][3] (Y is channel 2)
   double g_scale;            // -2 / B
-  double* grad_partials;     // [n_blocks][kMlpNParam] FP64
+  float* grad_partials;      // [n_blocks][kMlpNParam]: FP64 wave sums rounded to FP32
   double* partials;
   double* path_out;
   // Feature cache of the training paths, one entry per hedge segment k (the
@@ -281,11 +281,11 @@ struct CvValMoments {
 // Adam step and refreshes the packed fragments, in one launch; or only
 // reduces them into grad (the same fixed order). A workgroup of its own in
 // the same launch merges the hedged values' moments into vm.out.
-hipError_t launch_adam_pack(const double* partials, uint32_t n_blocks, const CvValMoments& vm,
+hipError_t launch_adam_pack(const float* partials, uint32_t n_blocks, const CvValMoments& vm,
                             double* grad, float* theta, float* m, float* v, int t, double lr,
                             double b1, double b2, double eps, float* w1f, float* w2f, float* w2tf,
                             float* lanec, hipStream_t s);
-hipError_t launch_grad_sum(const double* partials, uint32_t n_blocks, const CvValMoments& vm,
+hipError_t launch_grad_sum(const float* partials, uint32_t n_blocks, const CvValMoments& vm,
                            double* grad, hipStream_t s);
 
 // ---- reductions and diagnostics ----
