@@ -919,20 +919,20 @@ __device__ __forceinline__ void slot_of(int u, int& mb, int& r, int& h) {
 }
 
 // Gradient reduction of the block-major partials [n_blocks][kMlpNParam]:
-// a block of 256 threads takes kGradCols consecutive parameters; thread
-// (slice s, column p) adds blocks s, s + kGradSlices, ... in order (reads of
-// kGradCols consecutive doubles per row), then slice 0 adds the slices in
-// order. With ADAM, the same thread then takes one Adam step on (theta, m, v)
-// with the bias corrections c1 = 1 - b1^t, c2 = 1 - b2^t, and the block
-// writes the new values into each fragment slot that cv_pack_kernel gives
-// the parameter (W1, b1: one; W2: one in each of the two layouts; b2, W3:
-// the 32 lanes of a half-wave). Padding slots keep the zeros of the first
-// pack; b3 lives in theta only.
-constexpr int kGradCols = 16, kGradSlices = 256 / kGradCols;
+// a block of kGradThreads threads takes kGradCols consecutive parameters
+// (32 FP32 partials of a row are one 128-byte line); thread (slice s,
+// column p) adds blocks s, s + kGradSlices, ... in order in FP64, then
+// slice 0 adds the slices in order. With ADAM, the same thread then takes
+// one Adam step on (theta, m, v) with the bias corrections c1 = 1 - b1^t,
+// c2 = 1 - b2^t, and the block writes the new values into each fragment
+// slot that cv_pack_kernel gives the parameter (W1, b1: one; W2: one in
+// each of the two layouts; b2, W3: the 32 lanes of a half-wave). Padding
+// slots keep the zeros of the first pack; b3 lives in theta only.
+constexpr int kGradThreads = 512, kGradCols = 32, kGradSlices = kGradThreads / kGradCols;
 constexpr int kGradBlocks = (kMlpNParam + kGradCols - 1) / kGradCols;
 
 template <bool ADAM>
-__global__ __launch_bounds__(256) void grad_adam_kernel(
+__global__ __launch_bounds__(kGradThreads) void grad_adam_kernel(
     const float* __restrict__ partials, uint32_t n_blocks, double* __restrict__ grad,
     float* __restrict__ theta, float* __restrict__ m, float* __restrict__ v, float lr, float b1,
     float b2, float eps, float c1, float c2, float* __restrict__ w1f, float* __restrict__ w2f,
@@ -943,9 +943,9 @@ __global__ __launch_bounds__(256) void grad_adam_kernel(
     // block moments (the minibatch's loss), beside the reduction.
     PartSums<3> pm;
     pm.zero();
-    for (uint32_t i = threadIdx.x; i < vblocks; i += 256)
+    for (uint32_t i = threadIdx.x; i < vblocks; i += kGradThreads)
       pm.add_vector(vpart + (size_t)i * PartSums<3>::M);
-    block_reduce<3, 256>(pm, vmom, 0);
+    block_reduce<3, kGradThreads>(pm, vmom, 0);
     return;
   }
   __shared__ double sh[kGradSlices][kGradCols];
@@ -980,7 +980,7 @@ __global__ __launch_bounds__(256) void grad_adam_kernel(
   if constexpr (!ADAM) return;
   __syncthreads();
   // Fragment slots: up to 32 per parameter (b2, W3), kGradCols parameters.
-  for (int e = threadIdx.x; e < kGradCols * 32; e += 256) {
+  for (int e = threadIdx.x; e < kGradCols * 32; e += kGradThreads) {
     const int c = e >> 5, L = e & 31, ip = p0 + c;
     if (ip >= kMlpNParam) continue;
     const float t = th_new[c];
@@ -1105,7 +1105,7 @@ hipError_t launch_adam_pack(const float* partials, uint32_t n_blocks, const CvVa
   if (n_blocks == 0 || vm.n_blocks == 0 || vm.partials == nullptr || vm.out == nullptr)
     return hipErrorInvalidValue;
   const float c1 = (float)(1.0 - std::pow(b1, t)), c2 = (float)(1.0 - std::pow(b2, t));
-  hipLaunchKernelGGL(grad_adam_kernel<true>, dim3(kGradBlocks + 1), dim3(256), 0, s, partials,
+  hipLaunchKernelGGL(grad_adam_kernel<true>, dim3(kGradBlocks + 1), dim3(kGradThreads), 0, s, partials,
                      n_blocks, grad, theta, m, v, (float)lr, (float)b1, (float)b2, (float)eps, c1,
                      c2, w1f, w2f, w2tf, lanec, vm.partials, vm.n_blocks, vm.out);
   return hipGetLastError();
@@ -1115,7 +1115,7 @@ hipError_t launch_grad_sum(const float* partials, uint32_t n_blocks, const CvVal
                            double* grad, hipStream_t s) {
   if (n_blocks == 0 || vm.n_blocks == 0 || vm.partials == nullptr || vm.out == nullptr)
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL(grad_adam_kernel<false>, dim3(kGradBlocks + 1), dim3(256), 0, s, partials,
+  hipLaunchKernelGGL(grad_adam_kernel<false>, dim3(kGradBlocks + 1), dim3(kGradThreads), 0, s, partials,
                      n_blocks, grad, nullptr, nullptr, nullptr, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
                      nullptr, nullptr, nullptr, nullptr, vm.partials, vm.n_blocks, vm.out);
   return hipGetLastError();
