@@ -883,7 +883,7 @@ mc_status heston_cv_price(mc_context* ctx, const mc_model* m, const mc_payoff* f
 struct CvTrainWs {
   char* eval_base;          // moment layout with per-path values
   size_t eval_bytes;
-  float* grad_partials;     // [n_blocks][kMlpNParam]
+  float* grad_partials;     // [n_blocks][kGradStride]
   double* grad;             // [kMlpNParam]
   CvBuffers b;
   float *m, *v;             // Adam moments
@@ -914,7 +914,7 @@ size_t cv_train_bytes(uint64_t batch, uint32_t n_steps, uint32_t steps, uint64_t
     return p;
   };
   char* e = take(Lay.bytes);
-  char* gp = take((size_t)kMlpNParam * n_blocks * 4);
+  char* gp = take((size_t)kGradStride * n_blocks * 4);
   char* g = take((size_t)kMlpNParam * 8);
   char* cv = take(cv_extra_bytes(n_steps));
   char* mm = take((size_t)kMlpNParam * 4);

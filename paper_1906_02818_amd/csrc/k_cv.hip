@@ -770,13 +770,14 @@ __device__ __forceinline__ void cv_bwd_body(const CvParams& P) {
     if (lane == 0) s3w[wave] = s3;
   }
   __syncthreads();
-  // Block-major: the block's 4545 partials are one contiguous row.
+  // Block-major: the block's 4545 partials are one row (padded to whole
+  // 128-byte lines).
   for (int i = threadIdx.x; i < kMlpNParam; i += kCvThreads) {
     double acc = i == kMlpNParam - 1 ? s3w[0] : (double)red[i];
 #pragma unroll
     for (int w = 1; w < kCvWaves; ++w)
       acc += i == kMlpNParam - 1 ? s3w[w] : (double)red[w * kMlpNParam + i];
-    P.grad_partials[(uint64_t)blockIdx.x * kMlpNParam + i] = (float)acc;
+    P.grad_partials[(uint64_t)blockIdx.x * kGradStride + i] = (float)acc;
   }
 }
 
@@ -918,7 +919,7 @@ __device__ __forceinline__ void slot_of(int u, int& mb, int& r, int& h) {
   r = 4 * (q >> 3) + (q & 3);
 }
 
-// Gradient reduction of the block-major partials [n_blocks][kMlpNParam]:
+// Gradient reduction of the block-major partials [n_blocks][kGradStride]:
 // a block of kGradThreads threads takes kGradCols consecutive parameters
 // (32 FP32 partials of a row are one 128-byte line); thread (slice s,
 // column p) adds blocks s, s + kGradSlices, ... in order in FP64, then
@@ -957,7 +958,7 @@ __global__ __launch_bounds__(kGradThreads) void grad_adam_kernel(
   if (i < kMlpNParam) {
 #pragma unroll 8
     for (uint32_t k = slice; k < n_blocks; k += kGradSlices)
-      s += partials[(size_t)k * kMlpNParam + i];
+      s += partials[(size_t)k * kGradStride + i];
   }
   sh[slice][col] = s;
   __syncthreads();

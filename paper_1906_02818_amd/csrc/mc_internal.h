@@ -220,6 +220,8 @@ hipError_t launch_lsm_oos(const LsmParams& p, hipStream_t s, uint32_t* n_blocks)
 // wave. Host-packed per-lane fragments (see api.hip, pack_mlp):
 constexpr int kMlpH = 64;
 constexpr int kMlpNParam = 4545;
+// Row stride of the per-block gradient partials: whole 128-byte lines.
+constexpr int kGradStride = (kMlpNParam + 31) / 32 * 32;
 struct CvParams {
   HestonParams h;
   uint32_t hedge_every;      // rebalancing period m
@@ -235,7 +237,7 @@ struct CvParams {
                              // (in `partials`) the backward sums for Ybar
   const double* y_path;      // per-path values of that pass, [n_paths][3] (Y is channel 2)
   double g_scale;            // -2 / B
-  float* grad_partials;      // [n_blocks][kMlpNParam]: FP64 wave sums rounded to FP32
+  float* grad_partials;      // [n_blocks][kGradStride]: FP64 wave sums rounded to FP32
   double* partials;
   double* path_out;
   // Feature cache of the training paths, one entry per hedge segment k (the
