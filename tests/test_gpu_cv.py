@@ -177,12 +177,15 @@ def test_loss_gradient_matches_oracle(ctx, prec, tol, m_every, n):
 
 
 @pytest.mark.parametrize("prec,tol", [(mc.MC_FP32, 1e-4), (mc.MC_BF16_GEMM, 2e-2)])
-@pytest.mark.parametrize("B,n,m_every", [(512, 3, 1), (512, 4, 4), (16640, 9, 1), (33024, 9, 1)])
+@pytest.mark.parametrize("B,n,m_every", [(512, 3, 1), (512, 4, 4), (512, 100, 1), (16640, 9, 1),
+                                         (33024, 9, 1)])
 def test_loss_gradient_across_segment_splits(ctx, prec, tol, B, n, m_every):
     # The backward gives a small minibatch's 32-path tiles to two or four
     # waves, each taking a contiguous range of the hedge segments: 3 segments
-    # over two waves, one segment (no split), 520 tiles with 9 segments over
-    # two waves (4 + 5), 1032 tiles with one wave per tile.
+    # over two waves, one segment (no split), 100 segments over four waves in
+    # the backward (the hedged values keep one wave per tile: 25 segments
+    # would not fit a wave's LDS slab), 520 tiles with 9 segments over two
+    # waves (4 + 5), 1032 tiles with one wave per tile.
     th = weights(0.2, seed=7)
     say("grad split", prec, B, n, m_every)
     loss, g = mc.mc_cv_loss_grad(ctx, MODEL, PAY, n, SEED, 2, 64, B, th, hedge_every=m_every,
@@ -235,7 +238,7 @@ def test_adam_steps_match_oracle(ctx, decay_every, decay):
 
 
 @pytest.mark.parametrize("prec", [mc.MC_FP32, mc.MC_BF16_GEMM])
-@pytest.mark.parametrize("B,n,m", [(1024, 40, 16), (1024, 64, 4), (40192, 20, 4)])
+@pytest.mark.parametrize("B,n,m", [(1024, 40, 16), (1024, 64, 4), (1024, 100, 1), (40192, 20, 4)])
 def test_training_forward_is_the_evaluation_network(ctx, prec, B, n, m):
     # The training forward (32-path tiles of a minibatch, from the feature
     # cache) and the evaluation kernel (64 paths per wave, stepping the paths
@@ -244,7 +247,8 @@ def test_training_forward_is_the_evaluation_network(ctx, prec, B, n, m):
     # same paths (stream tag 2, same path indices) to FP64 merge rounding.
     # A small minibatch's tiles split their segments over waves and sum the
     # hedge in segment order all the same: 3 segments over two waves, 16 over
-    # four; 1256 tiles take one wave each.
+    # four; 100 segments stay on one wave per tile (a quarter would not fit a
+    # wave's LDS slab); 1256 tiles take one wave each.
     th = weights(0.2, seed=9)
     path0 = 300
     say("train forward vs eval", prec, B, n, m)
